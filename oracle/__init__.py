@@ -1,0 +1,300 @@
+"""FP64 CPU oracle for the Deep Scattering radiance-prediction path.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg.  The GPU library never imports, links or runs it,
+and it shares no code with the library (`oracle.c` is compiled on its own with
+gcc).  Inputs are host numpy arrays; results are float64.
+
+What each part follows in the paper and what pins it (tests/test_oracle_*.py):
+  normalize       Sec. 4.2 / Sec. 5 scale normalisation     closed form on constructed grids
+  pyramid         Sec. 6 Gaussian mipmap, sigma_i = 2^i     brute-force 3-D sum, constant/affine
+                                                            fields, impulse response, unit mass
+  frame           Sec. 4.2 local frame, gamma               closed form (0, sin g, cos g), det +1
+  gather          Sec. 4.2 / Fig. 5 hierarchical stencil    affine-field exactness, constant grid,
+                                                            cube-rotation invariance, axial symmetry
+  forward         Sec. 4.3 / Fig. 6 progressive residual    numpy matmul, bias-only closed form,
+                  blocks + trailing layers                  hand-computed K=1, W=2 case
+  loss_grad       Sec. 5.2 loss and its gradient            central finite differences
+  adam            Sec. 5.2 (Kingma and Ba, Alg. 1)          first-step closed form, 1-D recursion
+  philox          Salmon et al. 2011                        published known-answer vectors
+  trace_li etc.   Sec. 3.2 Eq. 1, Sec. 4, Sec. 4.4, 5.1     slab transmittance, furnace, sphere
+                                                            closed form, single-scatter quadrature,
+                                                            HG moments and CDF
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+FLAG_INVALID, FLAG_OUTSIDE, FLAG_FALLBACK = 1, 2, 4
+STENCIL_N = 225
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (FP64, OpenMP, no fast-math, no FMA contraction)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-D_GNU_SOURCE",
+               "-ffp-contract=off", "-Wall", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        P, I, D, I64, U64 = C.c_void_p, C.c_int, C.c_double, C.c_int64, C.c_uint64
+        sig = {
+            "dso_num_threads": (I, []),
+            "dso_set_threads": (None, [I]),
+            "dso_normalize": (I, [P, I, I, I, I, D, P, P]),
+            "dso_pyramid_layout": (I64, [I, I, I, I, P, P]),
+            "dso_gauss_norm": (D, [I]),
+            "dso_pyramid": (I, [P, I, I, I, I, D, D, I, P]),
+            "dso_default_mips": (None, [D, D, I, I, P]),
+            "dso_frame": (I, [P, P, P, P, P, P]),
+            "dso_stencil_offset": (None, [I, P]),
+            "dso_gather": (I, [P, P, P, I, P, D, I, I, I, D, I, P, P, P, P, I64, P, P]),
+            "dso_param_count": (I64, [I, I, I]),
+            "dso_forward": (I, [P, I, I, I, P, I64, P, P]),
+            "dso_loss_grad": (I, [P, I, I, I, P, P, I64, P, P]),
+            "dso_adam": (None, [P, P, P, P, I64, I64, D, D, D, D]),
+            "dso_philox4x32_10": (None, [P, P, P]),
+            "dso_hg": (D, [D, D]),
+            "dso_hg_sample_cos": (D, [D, D]),
+            "dso_trace_li": (I, [P, I, I, I, I, D, P, D, D, D, D, I, I, I, U64, P, P, P, I64, P, P]),
+            "dso_transmittance": (I, [P, I, I, I, I, D, P, D, P, P, I64, I, U64, P, P]),
+            "dso_sample_records": (I, [P, I, I, I, I, D, P, D, I64, U64, P, P, P, P]),
+            "dso_render_pixels": (I, [P, I, I, I, I, D, P, D, D, D, D, I, I, P, P, P, I64, I, U64,
+                                      P, P]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError(f"oracle {what} failed with status {rc}")
+
+
+def threads() -> int:
+    return lib().dso_num_threads()
+
+
+def set_threads(n: int) -> None:
+    lib().dso_set_threads(int(n))
+
+
+# --------------------------------------------------------------------------------------
+class Grid:
+    """A density grid on the host: float32 or bf16 bit patterns (uint16), [z][y][x]."""
+
+    def __init__(self, d, sigma_max: float, aabb_min, h0: float):
+        d = np.ascontiguousarray(d)
+        if d.dtype == np.float32:
+            self.dtype = 0
+        elif d.dtype == np.uint16:
+            self.dtype = 1
+        else:
+            raise TypeError("density must be float32 or bf16 bit patterns as uint16")
+        self.d = d
+        self.nz, self.ny, self.nx = d.shape
+        self.sigma_max = float(sigma_max)
+        self.aabb_min = np.ascontiguousarray(np.asarray(aabb_min, np.float64))
+        self.h0 = float(h0)
+
+    def args(self):
+        return (_p(self.d), self.dtype, self.nx, self.ny, self.nz, self.sigma_max)
+
+
+def normalize(grid: Grid):
+    """(mean extinction over non-zero voxels, number of such voxels)."""
+    m = np.zeros(1, np.float64)
+    c = np.zeros(1, np.int64)
+    _check(lib().dso_normalize(*grid.args(), _p(m), _p(c)), "normalize")
+    return float(m[0]), int(c[0])
+
+
+def pyramid_layout(nx, ny, nz, L):
+    dims = np.zeros((L, 3), np.int32)
+    offs = np.zeros(L, np.int64)
+    total = lib().dso_pyramid_layout(nx, ny, nz, L, _p(dims), _p(offs))
+    return dims, offs, int(total)
+
+
+def gauss_norm(level: int) -> float:
+    return lib().dso_gauss_norm(int(level))
+
+
+def pyramid(grid: Grid, mean_mu_t: float, L: int):
+    """Concatenated float64 levels plus (dims[L][3] as (nx, ny, nz), offsets[L])."""
+    dims, offs, total = pyramid_layout(grid.nx, grid.ny, grid.nz, L)
+    out = np.zeros(total, np.float64)
+    _check(lib().dso_pyramid(*grid.args(), float(mean_mu_t), int(L), _p(out)), "pyramid")
+    return out, dims, offs
+
+
+def level(pyr, dims, offs, i):
+    nx, ny, nz = (int(v) for v in dims[i])
+    return pyr[offs[i]:offs[i] + nx * ny * nz].reshape(nz, ny, nx)
+
+
+def default_mips(mean_mu_t: float, h0: float, K: int, L: int) -> np.ndarray:
+    out = np.zeros(K, np.int32)
+    lib().dso_default_mips(float(mean_mu_t), float(h0), int(K), int(L), _p(out))
+    return out
+
+
+def frame(view, light):
+    v = np.ascontiguousarray(np.asarray(view, np.float64))
+    l_ = np.ascontiguousarray(np.asarray(light, np.float64))
+    X, Y, Z = (np.zeros(3, np.float64) for _ in range(3))
+    g = np.zeros(1, np.float64)
+    ok = lib().dso_frame(_p(v), _p(l_), _p(X), _p(Y), _p(Z), _p(g))
+    if not ok:
+        return None
+    return X, Y, Z, float(g[0])
+
+
+def stencil_offset(n: int) -> np.ndarray:
+    o = np.zeros(3, np.float64)
+    lib().dso_stencil_offset(int(n), _p(o))
+    return o
+
+
+def gather(grid: Grid, pyr, dims, offs, mean_mu_t, K, mips, pos, view, light):
+    """Descriptor rows [Sigma^1 .. Sigma^K, gamma] (P, 225K+1) and per-point flags."""
+    pos = np.ascontiguousarray(pos, np.float32)
+    view = np.ascontiguousarray(view, np.float32)
+    light = np.ascontiguousarray(light, np.float32)
+    mips = np.ascontiguousarray(mips, np.int32)
+    P = pos.shape[0]
+    z = np.zeros((P, STENCIL_N * K + 1), np.float64)
+    flags = np.zeros(P, np.uint8)
+    dims = np.ascontiguousarray(dims, np.int32)
+    offs = np.ascontiguousarray(offs, np.int64)
+    _check(lib().dso_gather(_p(pyr), _p(dims), _p(offs), int(dims.shape[0]), _p(grid.aabb_min),
+                            grid.h0, grid.nx, grid.ny, grid.nz, float(mean_mu_t), int(K), _p(mips),
+                            _p(pos), _p(view), _p(light), P, _p(z), _p(flags)), "gather")
+    return z, flags
+
+
+def param_count(K, W, H=3) -> int:
+    return int(lib().dso_param_count(K, W, H))
+
+
+def forward(theta, K, W, H, z):
+    """Network output g and the final layer's pre-activation, both (P,)."""
+    th = np.ascontiguousarray(theta, np.float64)
+    if th.size != param_count(K, W, H):
+        raise ValueError("parameter vector has the wrong length")
+    z = np.ascontiguousarray(z, np.float64)
+    P = z.shape[0]
+    g = np.zeros(P, np.float64)
+    pre = np.zeros(P, np.float64)
+    _check(lib().dso_forward(_p(th), K, W, H, _p(z), P, _p(g), _p(pre)), "forward")
+    return g, pre
+
+
+def loss_grad(theta, K, W, H, z, target_log1p, want_grad=True):
+    th = np.ascontiguousarray(theta, np.float64)
+    z = np.ascontiguousarray(z, np.float64)
+    t = np.ascontiguousarray(target_log1p, np.float64)
+    B = z.shape[0]
+    loss = np.zeros(1, np.float64)
+    grad = np.zeros(th.size, np.float64) if want_grad else None
+    _check(lib().dso_loss_grad(_p(th), K, W, H, _p(z), _p(t), B, _p(loss), _p(grad)), "loss_grad")
+    return float(loss[0]), grad
+
+
+def adam(theta, m, v, grad, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In-place Adam step on float64 arrays; t is the 1-based step number."""
+    for a in (theta, m, v, grad):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    lib().dso_adam(_p(theta), _p(m), _p(v), _p(grad), theta.size, int(t), lr, b1, b2, eps)
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(np.asarray(ctr, np.uint32))
+    k = np.ascontiguousarray(np.asarray(key, np.uint32))
+    out = np.zeros(4, np.uint32)
+    lib().dso_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def hg(g, mu):
+    return lib().dso_hg(float(g), float(mu))
+
+
+def hg_sample_cos(g, u):
+    return lib().dso_hg_sample_cos(float(g), float(u))
+
+
+def trace_li(grid: Grid, pos, view, light, albedo=0.999, g=0.85, irradiance=1.0, light_mode=0,
+             max_interactions=0, spp=64, seed=1):
+    """Per record: mean of spp path estimates of L_i and the variance of that mean."""
+    pos = np.ascontiguousarray(pos, np.float32)
+    view = np.ascontiguousarray(view, np.float32)
+    light = np.ascontiguousarray(light, np.float32)
+    P = pos.shape[0]
+    mean = np.zeros(P, np.float64)
+    var = np.zeros(P, np.float64)
+    _check(lib().dso_trace_li(*grid.args(), _p(grid.aabb_min), grid.h0, albedo, g, irradiance,
+                              light_mode, max_interactions, spp, seed, _p(pos), _p(view),
+                              _p(light), P, _p(mean), _p(var)), "trace_li")
+    return mean, var
+
+
+def transmittance(grid: Grid, orig, dirs, spp=256, seed=1):
+    o = np.ascontiguousarray(orig, np.float64)
+    d = np.ascontiguousarray(dirs, np.float64)
+    R = o.shape[0]
+    rm = np.zeros(R, np.float64)
+    ef = np.zeros(R, np.float64)
+    _check(lib().dso_transmittance(*grid.args(), _p(grid.aabb_min), grid.h0, _p(o), _p(d), R, spp,
+                                   seed, _p(rm), _p(ef)), "transmittance")
+    return rm, ef
+
+
+def sample_records(grid: Grid, N, seed):
+    pos = np.zeros((N, 3), np.float32)
+    view = np.zeros((N, 3), np.float32)
+    light = np.zeros((N, 3), np.float32)
+    att = np.zeros(N, np.int32)
+    _check(lib().dso_sample_records(*grid.args(), _p(grid.aabb_min), grid.h0, N, seed, _p(pos),
+                                    _p(view), _p(light), _p(att)), "sample_records")
+    return pos, view, light, att
+
+
+def render_pixels(grid: Grid, ray_o, ray_d, light_dir, albedo=0.999, g=0.85, irradiance=1.0,
+                  light_mode=0, max_interactions=0, spp=16, seed=1):
+    o = np.ascontiguousarray(ray_o, np.float32)
+    d = np.ascontiguousarray(ray_d, np.float32)
+    ld = np.ascontiguousarray(np.asarray(light_dir, np.float64))
+    N = o.shape[0]
+    mean = np.zeros(N, np.float64)
+    var = np.zeros(N, np.float64)
+    _check(lib().dso_render_pixels(*grid.args(), _p(grid.aabb_min), grid.h0, albedo, g, irradiance,
+                                   light_mode, max_interactions, _p(ld), _p(o), _p(d), N, spp,
+                                   seed, _p(mean), _p(var)), "render_pixels")
+    return mean, var
