@@ -1,0 +1,197 @@
+#!/usr/bin/env python3
+"""Throughput of the radiance-prediction hot path on one MI355X.
+
+One step = one ds_predict over the whole batch of shading points: the
+hierarchical stencil gather from the mip pyramid plus the residual network, in
+the fused BF16 kernel.  Inputs are resident in HBM before timing starts.
+
+Default workload (paper-sized inference): seeded 512^3 fBm + Worley cloud,
+sigma_max 512/unit, 10 mip levels, K = 10 stencil levels, 10 residual blocks of
+width 200 plus 3 trailing layers, 2^20 shading points = primary hits of a
+1024 x 1024 view, light from the side.  Also timed: the FP32 plain form (the
+descriptor through HBM, one kernel per layer) on the same points, and the FP64
+oracle on a bounded sample of them on the host cores.
+
+    python bench.py [--steps K] [--warmup W] [--workload paper|tiny] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+METRIC = "shading points/s (stencil+RPNN) BF16/FP8 vs FP32 at stated rel. error; MFMA %"
+PEAK_BF16_TFLOPS = 2500.0
+
+WORKLOADS = {
+    "paper": dict(n=512, sigma=512.0, L=10, K=10, W=200, H=3, P=1 << 20, res=1024, worley=0.3,
+                  seed_cloud=10, seed_pts=11, seed_theta=12,
+                  name="paper-sized inference: 512^3 fBm+Worley cloud, 10 mip levels, K=10, "
+                       "10 residual blocks x 200 + 3 layers, 2^20 primary hits of a 1024^2 view"),
+    "tiny": dict(n=64, sigma=64.0, L=6, K=6, W=64, H=3, P=4096, res=64, worley=0.0,
+                 seed_cloud=1, seed_pts=3, seed_theta=2,
+                 name="tiny: 64^3 fBm cloud, 6 mip levels, K=6, 6 residual blocks x 64 + 3 layers, "
+                      "4096 points"),
+}
+
+
+def macs_per_point(K, W, H):
+    return 226 * K * W + (K - 1) * W * W + K * W * W + (H - 1) * W * W + W
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="paper", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the FP64 oracle baseline")
+    ap.add_argument("--cpu-sample", type=int, default=16384)
+    ap.add_argument("--fp32-steps", type=int, default=3)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this library has no multi-GPU path "
+              "(shading points are independent; see DESIGN.md for how it would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1709_05418_amd as ds
+    from paper_1709_05418_amd import synth
+
+    cfg = WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    K, W, H, P = cfg["K"], cfg["W"], cfg["H"], cfg["P"]
+    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
+
+    t0 = time.time()
+    density = synth.cloud_density(cfg["n"], cfg["seed_cloud"], worley=cfg["worley"], device=dev)
+    aabb_min, h0 = synth.unit_box(cfg["n"])
+    ctx = ds.Context(0)
+    cloud = ds.Cloud(ctx, density, cfg["sigma"], aabb_min, h0, cfg["L"], K)
+    pos_np, view_np = synth.camera_hits(density, cfg["sigma"], cfg["res"], P, cfg["seed_pts"],
+                                        aabb_min, h0, device=dev)
+    light_np = np.broadcast_to(synth.table1_lights()["side"], (P, 3)).copy()
+    pos = torch.from_numpy(pos_np).to(dev)
+    view = torch.from_numpy(view_np).to(dev)
+    light = torch.from_numpy(light_np).to(dev)
+    theta = synth.init_params(K, W, H, cfg["seed_theta"])
+    net = ds.Net(ctx, K, W, H)
+    net.set_params(theta)
+    out = torch.empty(P, dtype=torch.float32, device=dev)
+    flags = torch.empty(P, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    log(f"setup {time.time() - t0:.1f}s; cloud mean {cloud.info['mean_mu_t']:.3f}, "
+        f"mips {cloud.info['mip_of_level']}")
+
+    def run(prec, out_t, pre_t=None):
+        ds.ds_predict(ctx.h, cloud.h, net.h, prec, pos, view, light, out=out_t, pre=pre_t,
+                      flags=flags, want_pre=pre_t is not None)
+
+    # ---------------------------------------------------------------- BF16 fused (timed)
+    for _ in range(args.warmup):
+        run(ds.DS_PREC_BF16, out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        run(ds.DS_PREC_BF16, out)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    kernel_ms = [a.elapsed_time(b) for a, b in evs]
+    ms_step = wall * 1e3 / args.steps
+    avg_kernel_ms = float(np.mean(kernel_ms))
+    value = P / (ms_step / 1e3)
+    log(f"bf16 fused: {ms_step:.3f} ms/step (wall), kernel {avg_kernel_ms:.3f} ms avg, "
+        f"{value:.3e} points/s")
+
+    flop = 2.0 * macs_per_point(K, W, H) * P
+    achieved = flop / (avg_kernel_ms / 1e3) / 1e12
+    roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
+                "kernel": "k_fused<13,1> (BF16 MFMA, stencil gather fused)",
+                "flop_per_point": 2 * macs_per_point(K, W, H)}
+
+    # ---------------------------------------------------------------- FP32 plain form
+    out32 = torch.empty(P, dtype=torch.float32, device=dev)
+    run(ds.DS_PREC_F32, out32)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.fp32_steps):
+        run(ds.DS_PREC_F32, out32)
+    torch.cuda.synchronize()
+    ms32 = (time.perf_counter() - t1) * 1e3 / args.fp32_steps
+    log(f"fp32 plain: {ms32:.2f} ms/step, speedup of bf16 fused {ms32 / ms_step:.2f}x")
+    fp32 = {"ms_per_step": round(ms32, 3), "value": P / (ms32 / 1e3),
+            "speedup_bf16_over_fp32": round(ms32 / ms_step, 2)}
+
+    # ---------------------------------------------------------------- oracle baseline
+    cpu = None
+    parity = None
+    if not args.no_cpu:
+        sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+        import oracle as O
+        S = min(args.cpu_sample, P)
+        idx = np.linspace(0, P - 1, S).astype(np.int64)
+        d_host = density.float().cpu().numpy()
+        grid = O.Grid(d_host, cfg["sigma"], aabb_min, h0)
+        tp = time.time()
+        mean, _ = O.normalize(grid)
+        pyr, dims, offs = O.pyramid(grid, mean, cfg["L"])
+        mips = O.default_mips(mean, h0, K, cfg["L"])
+        log(f"oracle pyramid {time.time() - tp:.1f}s (not part of the timed sample)")
+        tc = time.perf_counter()
+        g_ref = np.zeros(S)
+        chunk = 4096
+        for c0 in range(0, S, chunk):
+            sl = idx[c0:c0 + chunk]
+            z, _ = O.gather(grid, pyr, dims, offs, mean, K, mips, pos_np[sl], view_np[sl],
+                            light_np[sl])
+            g_ref[c0:c0 + chunk], _ = O.forward(theta.astype(np.float64), K, W, H, z)
+        tcpu = time.perf_counter() - tc
+        cpu = {"value": round(S / tcpu, 2), "unit": "shading points/s", "cores": O.threads(),
+               "kind": "oracle",
+               "sample": f"{S} of the {P} shading points (evenly strided), FP64 gather + "
+                         f"network, {tcpu:.1f} s"}
+        log(f"oracle: {S / tcpu:.1f} points/s on {O.threads()} threads")
+        same_mips = list(mips) == list(cloud.info["mip_of_level"])
+        g16 = out.cpu().numpy()[idx]
+        g32 = out32.cpu().numpy()[idx]
+        rl = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+        parity = {"sampled_points": S, "same_mip_map": same_mips,
+                  "rel_l2_bf16": rl(g16, g_ref) if same_mips else None,
+                  "rel_l2_fp32": rl(g32, g_ref) if same_mips else None,
+                  "tolerance_bf16": 2e-2, "tolerance_fp32": 1e-5}
+        log(f"parity on sample: {parity}")
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "shading points/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "grid": cfg["n"], "mip_levels": cfg["L"], "K": K,
+                   "W": W, "trailing_layers": H, "points": P, "precision": "bf16",
+                   "light": "side"},
+        "roofline": roofline, "cpu_baseline": cpu, "fp32_plain": fp32, "parity": parity,
+        "kernel_ms": round(avg_kernel_ms, 4),
+    }
+    net.close()
+    cloud.close()
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,174 @@
+/*
+ * deepscatter.h - C ABI of the MI355X (gfx950) radiance-prediction library.
+ *
+ * The library implements the per-shading-point hot path of Kallweit et al.,
+ * "Deep Scattering: Rendering Atmospheric Clouds with Radiance-Predicting Neural
+ * Networks": a hierarchical, light-oriented stencil descriptor gathered from a
+ * Gaussian mipmap of the cloud density (Sec. 4.2, Sec. 6 "Implementation"), fed
+ * progressively into a residual radiance-predicting network (Sec. 4.3, Fig. 6),
+ * plus the Monte Carlo path tracer that produces its training data (Sec. 3.2,
+ * Sec. 5.1) and the training step (Sec. 5.2).
+ *
+ * Conventions (all calls):
+ *  - Every call returns a ds_status; DS_OK is 0 and every error is negative.
+ *    ds_last_error() returns a thread-local message for the last failure.
+ *    Nothing aborts and no exception crosses the ABI.  Argument checks happen
+ *    before anything is enqueued; a failed call leaves its outputs untouched.
+ *  - "device" pointers are HIP device memory owned by the caller, "host"
+ *    pointers are ordinary host memory.  The library never keeps a caller
+ *    pointer beyond the call.
+ *  - Work is enqueued asynchronously on the context's stream (a caller-owned
+ *    hipStream_t passed as void*; NULL is the default stream) unless a call says
+ *    it synchronises.  Outputs are valid once the stream reaches that point.
+ *  - Geometry: density grids are [nz][ny][nx] with x fastest; voxel (i, j, k)
+ *    occupies aabb_min + [i, i+1] x [j, j+1] x [k, k+1] * voxel_size (world
+ *    units).  Points and directions are float32 arrays of shape [P][3].
+ *    view_dir is omega, the direction in which the radiance travels toward the
+ *    viewer (the integration in Eq. (1) runs along x - u omega); light_dir is
+ *    omega_l, pointing toward the light.  Neither needs unit length.
+ *  - A context, and the clouds, networks and optimisers created from it, must
+ *    not be used from two threads at once.
+ */
+#ifndef DEEPSCATTER_H
+#define DEEPSCATTER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ds_status;
+#define DS_OK 0
+#define DS_ERR_INVALID_ARG (-1)
+#define DS_ERR_OOM (-2)
+#define DS_ERR_DEVICE (-3)
+#define DS_ERR_UNSUPPORTED (-4)
+#define DS_ERR_STATE (-5)
+
+typedef enum { DS_F32 = 0, DS_BF16 = 1 } ds_dtype;
+
+/* Arithmetic of the network layers.  DS_PREC_F32: plain form, every layer in FP32
+ * (descriptor materialised, one kernel per layer).  DS_PREC_BF16 / DS_PREC_FP8:
+ * fused kernel, layer inputs and weights in BF16 or FP8 E4M3 (OCP, per-layer
+ * scales) on the matrix cores, accumulation, biases and residual sums in FP32. */
+typedef enum { DS_PREC_F32 = 0, DS_PREC_BF16 = 1, DS_PREC_FP8 = 2 } ds_precision;
+
+/* Per-point flag bits written by ds_gather / ds_predict. */
+#define DS_FLAG_INVALID 1u  /* non-finite position or zero/non-finite direction: outputs are 0 */
+#define DS_FLAG_OUTSIDE 2u  /* the point lies outside the grid box                           */
+#define DS_FLAG_FALLBACK 4u /* the level-1 stencil box (from (-1,-1,-1) to (1,1,3) mean free
+                               paths in the light frame) is not entirely inside the grid box  */
+
+typedef struct ds_ctx ds_ctx;
+typedef struct ds_cloud ds_cloud;
+typedef struct ds_net ds_net;
+typedef struct ds_adam ds_adam;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *ds_last_error(void);
+
+/* Library version string. */
+const char *ds_version(void);
+
+/* ---------------------------------------------------------------- context */
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t, or NULL for the default stream).  The stream stays owned by
+ * the caller and must outlive the context. */
+ds_status ds_create(int device, void *hip_stream, ds_ctx **out);
+/* Change the stream of an existing context. */
+ds_status ds_set_stream(ds_ctx *ctx, void *hip_stream);
+/* Wait for all work on the context's stream. */
+ds_status ds_synchronize(ds_ctx *ctx);
+/* Destroy a context; clouds and networks created from it must be destroyed first. */
+ds_status ds_destroy(ds_ctx *ctx);
+
+/* ---------------------------------------------------------------- cloud (Sec. 4.2, 5, 6) */
+/* Build the per-cloud state from a caller-owned device density grid d in [0, 1]
+ * (dtype DS_F32 or DS_BF16) of nx*ny*nz voxels.  Extinction is
+ * mu_t = sigma_max * d per world unit.  The call
+ *  - computes the mean extinction over all voxels with mu_t > 0 (one mean free
+ *    path = 1 / that mean; Sec. 4.2) and the scaled density rho = mu_t / mean;
+ *  - builds n_levels mip levels, level i filtered with a Gaussian of standard
+ *    deviation 2^i base voxels (Sec. 6), truncated at 3 sigma, zero outside the
+ *    grid, sampled at the centres of voxels 2^i times larger
+ *    (ceil(n / 2^i) per axis);
+ *  - records which mip level stencil level k (1..K) reads: mip_of_level[k-1],
+ *    or, when mip_of_level is NULL, the level whose voxel best matches the
+ *    level-1 stencil spacing of half a mean free path, plus k-1, clamped.
+ * The density buffer is read during the call only.  The call synchronises the
+ * stream once (to read the mean back).  Errors: DS_ERR_INVALID_ARG for bad sizes,
+ * n_levels outside 1..16, K outside 1..16, mip entries outside [0, n_levels), or a
+ * grid without any positive voxel; DS_ERR_OOM if the pyramid does not fit. */
+ds_status ds_cloud_create(ds_ctx *ctx, const void *density_dev, ds_dtype dtype, int nx, int ny,
+                          int nz, float sigma_max, const float aabb_min[3], float voxel_size,
+                          int n_levels, const int *mip_of_level, int K, ds_cloud **out);
+/* Host-side description: mean extinction, level count, per-level dims [L][3] as
+ * (nx, ny, nz), stencil-to-mip map [K] and K.  Any output pointer may be NULL. */
+ds_status ds_cloud_info(const ds_cloud *cloud, double *mean_mu_t, int *n_levels, int *dims,
+                        int *mip_of_level, int *K);
+/* Copy mip level `level` (float32, [nz][ny][nx]) into caller device memory. */
+ds_status ds_cloud_level(ds_ctx *ctx, const ds_cloud *cloud, int level, float *dst_dev);
+ds_status ds_cloud_destroy(ds_cloud *cloud);
+
+/* ---------------------------------------------------------------- network (Sec. 4.3) */
+/* K residual blocks of width W, then H trailing layers (H-1 of width W and a
+ * final scalar layer), ReLU everywhere.  The canonical parameter vector (float32)
+ * holds, for k = 1..K: V^k [W][226] (225 stencil densities of level k, then the
+ * angle gamma), W1^k [W][W] (absent for k = 1, whose input o^0 is zero), b1^k [W],
+ * W2^k [W][W], b2^k [W]; then per trailing layer its matrix [out][in] and bias.
+ * Matrices are row-major [out][in]. */
+typedef struct {
+    int K; /* 1..16 */
+    int W; /* 1..256 */
+    int H; /* 1..8 */
+} ds_net_desc;
+
+int64_t ds_net_param_count(const ds_net_desc *desc);
+ds_status ds_net_create(ds_ctx *ctx, const ds_net_desc *desc, ds_net **out);
+/* Upload / read back the FP32 master parameters (host arrays of exactly
+ * ds_net_param_count() floats).  set_params also refreshes the BF16 copy and
+ * invalidates the FP8 copy; both synchronise the stream. */
+ds_status ds_net_set_params(ds_net *net, const float *theta_host, int64_t n);
+ds_status ds_net_get_params(ds_net *net, float *theta_host, int64_t n);
+ds_status ds_net_destroy(ds_net *net);
+
+/* ---------------------------------------------------------------- hot path */
+/* Plain-form descriptor (Sec. 4.2): per point the row
+ * [Sigma^1 (225) ... Sigma^K (225), gamma] of 225K+1 values, Sigma^k_n the
+ * trilinearly interpolated rho of mip level mip_of_level[k-1] at
+ * q = x + 2^(k-1)/mean * (o_x X + o_y Y + o_z Z), o the lattice point
+ * n = ix + 5 iy + 25 iz, o = (-1 + ix/2, -1 + iy/2, -1 + iz/2), (X, Y, Z) the
+ * light frame (Z toward the light, X = normalize(omega x omega_l), Y = Z x X) and
+ * gamma = acos(omega . omega_l) in radians.  Voxel-centred interpolation, zero
+ * outside each level's grid.  z_out is device memory of P*(225K+1) elements of
+ * out_dtype; flags (device, P bytes) may be NULL. */
+ds_status ds_gather(ds_ctx *ctx, const ds_cloud *cloud, const float *pos, const float *view_dir,
+                    const float *light_dir, int64_t P, ds_dtype out_dtype, void *z_out,
+                    uint8_t *flags);
+
+/* Network on materialised descriptors z (device, [P][225K+1] float32):
+ * out[p] = g(z_p) (the predicted L_i per unit irradiance) and, if pre_out is not
+ * NULL, the final layer's pre-activation.  FP32 plain form. */
+ds_status ds_forward(ds_ctx *ctx, const ds_net *net, const float *z, int64_t P, float *out,
+                     float *pre_out);
+
+/* The hot path: for P shading points, the descriptor of `cloud` (K levels of the
+ * cloud must equal the network's K) and the network prediction of the indirect
+ * in-scattered radiance L_i(x, omega) per unit light irradiance (Sec. 4, 4.1).
+ * DS_PREC_F32 runs the plain form (descriptor through HBM, FP32 layers, in
+ * chunks of at most 65536 points, with library-owned workspace);
+ * DS_PREC_BF16 / DS_PREC_FP8 run the fused kernel (descriptor stays on chip).
+ * out (device, P floats), pre_out (device, P floats, may be NULL: final
+ * pre-activation) and flags (device, P bytes, may be NULL).  Invalid points get
+ * out = pre_out = 0.  FP8 needs ds_net_quantize_fp8 first (else DS_ERR_STATE). */
+ds_status ds_predict(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
+                     ds_precision precision, const float *pos, const float *view_dir,
+                     const float *light_dir, int64_t P, float *out, float *pre_out,
+                     uint8_t *flags);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DEEPSCATTER_H */

@@ -1,0 +1,292 @@
+"""Python binding of libdeepscatter (MI355X / gfx950 radiance prediction).
+
+Thin ctypes layer over the C ABI in include/deepscatter.h: every ds_* function
+here marshals torch device tensors (data pointers) and the current HIP stream and
+calls the C entry point of the same name.  All computation happens in the HIP
+kernels of libdeepscatter.so; there is no CPU fallback.  Importing works without
+the library, but every call raises if libdeepscatter.so has not been built
+(python -m paper_1709_05418_amd.build).
+
+The small classes at the end (Context, Cloud, Net) only own handles and call the
+same functions.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdeepscatter.so")
+
+DS_OK = 0
+DS_F32, DS_BF16 = 0, 1
+DS_PREC_F32, DS_PREC_BF16, DS_PREC_FP8 = 0, 1, 2
+DS_FLAG_INVALID, DS_FLAG_OUTSIDE, DS_FLAG_FALLBACK = 1, 2, 4
+STENCIL_N = 225
+
+_lib = None
+
+
+class DSError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def lib():
+    """Load libdeepscatter.so (raises if it is missing: no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run python -m paper_1709_05418_amd.build")
+    L = C.CDLL(LIB_PATH)
+    P, I, F, D, I64, S = C.c_void_p, C.c_int, C.c_float, C.c_double, C.c_int64, C.c_int32
+    sig = {
+        "ds_last_error": (C.c_char_p, []),
+        "ds_version": (C.c_char_p, []),
+        "ds_create": (S, [I, P, P]),
+        "ds_set_stream": (S, [P, P]),
+        "ds_synchronize": (S, [P]),
+        "ds_destroy": (S, [P]),
+        "ds_cloud_create": (S, [P, P, I, I, I, I, F, P, F, I, P, I, P]),
+        "ds_cloud_info": (S, [P, P, P, P, P, P]),
+        "ds_cloud_level": (S, [P, P, I, P]),
+        "ds_cloud_destroy": (S, [P]),
+        "ds_net_param_count": (I64, [P]),
+        "ds_net_create": (S, [P, P, P]),
+        "ds_net_set_params": (S, [P, P, I64]),
+        "ds_net_get_params": (S, [P, P, I64]),
+        "ds_net_destroy": (S, [P]),
+        "ds_gather": (S, [P, P, P, P, P, I64, I, P, P]),
+        "ds_forward": (S, [P, P, P, I64, P, P]),
+        "ds_predict": (S, [P, P, P, I, P, P, P, I64, P, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+class _NetDesc(C.Structure):
+    _fields_ = [("K", C.c_int), ("W", C.c_int), ("H", C.c_int)]
+
+
+def _check(st):
+    if st != DS_OK:
+        raise DSError(st, lib().ds_last_error().decode())
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (or None)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device (cuda) tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _pts(t, P=None):
+    import torch
+    if t.dtype != torch.float32 or t.dim() != 2 or t.shape[1] != 3:
+        raise ValueError("points and directions must be float32 tensors of shape (P, 3)")
+    if P is not None and t.shape[0] != P:
+        raise ValueError("points and directions must have the same length")
+    return _ptr(t)
+
+
+# ----------------------------------------------------------------------------- C ABI
+def ds_version() -> str:
+    return lib().ds_version().decode()
+
+
+def ds_last_error() -> str:
+    return lib().ds_last_error().decode()
+
+
+def ds_create(device: int = 0, stream=None):
+    h = C.c_void_p()
+    _check(lib().ds_create(device, _stream_handle(stream), C.byref(h)))
+    return h
+
+
+def ds_set_stream(ctx, stream=None):
+    _check(lib().ds_set_stream(ctx, _stream_handle(stream)))
+
+
+def ds_synchronize(ctx):
+    _check(lib().ds_synchronize(ctx))
+
+
+def ds_destroy(ctx):
+    _check(lib().ds_destroy(ctx))
+
+
+def ds_cloud_create(ctx, density, sigma_max, aabb_min, voxel_size, n_levels, K, mip_of_level=None):
+    import torch
+    if density.dim() != 3:
+        raise ValueError("density must be a (nz, ny, nx) tensor")
+    dt = {torch.float32: DS_F32, torch.bfloat16: DS_BF16}.get(density.dtype)
+    if dt is None:
+        raise ValueError("density must be float32 or bfloat16")
+    nz, ny, nx = density.shape
+    amin = (C.c_float * 3)(*[float(v) for v in aabb_min])
+    mips = None
+    if mip_of_level is not None:
+        mips = (C.c_int * len(mip_of_level))(*[int(v) for v in mip_of_level])
+    h = C.c_void_p()
+    _check(lib().ds_cloud_create(ctx, _ptr(density), dt, nx, ny, nz, float(sigma_max), amin,
+                                 float(voxel_size), int(n_levels), mips, int(K), C.byref(h)))
+    return h
+
+
+def ds_cloud_info(cloud):
+    mean = C.c_double()
+    L = C.c_int()
+    K = C.c_int()
+    dims = (C.c_int * 48)()
+    mips = (C.c_int * 16)()
+    _check(lib().ds_cloud_info(cloud, C.byref(mean), C.byref(L), dims, mips, C.byref(K)))
+    return {"mean_mu_t": mean.value, "n_levels": L.value, "K": K.value,
+            "dims": [tuple(dims[3 * i:3 * i + 3]) for i in range(L.value)],
+            "mip_of_level": list(mips[:K.value])}
+
+
+def ds_cloud_level(ctx, cloud, level: int):
+    import torch
+    info = ds_cloud_info(cloud)
+    nx, ny, nz = info["dims"][level]
+    out = torch.empty((nz, ny, nx), dtype=torch.float32, device="cuda")
+    _check(lib().ds_cloud_level(ctx, cloud, int(level), _ptr(out)))
+    return out
+
+
+def ds_cloud_destroy(cloud):
+    _check(lib().ds_cloud_destroy(cloud))
+
+
+def ds_net_param_count(K: int, W: int, H: int = 3) -> int:
+    d = _NetDesc(K, W, H)
+    return int(lib().ds_net_param_count(C.byref(d)))
+
+
+def ds_net_create(ctx, K: int, W: int, H: int = 3):
+    d = _NetDesc(K, W, H)
+    h = C.c_void_p()
+    _check(lib().ds_net_create(ctx, C.byref(d), C.byref(h)))
+    return h
+
+
+def ds_net_set_params(net, theta):
+    th = np.ascontiguousarray(theta, dtype=np.float32)
+    _check(lib().ds_net_set_params(net, C.c_void_p(th.ctypes.data), th.size))
+
+
+def ds_net_get_params(net, n: int):
+    th = np.zeros(n, np.float32)
+    _check(lib().ds_net_get_params(net, C.c_void_p(th.ctypes.data), n))
+    return th
+
+
+def ds_net_destroy(net):
+    _check(lib().ds_net_destroy(net))
+
+
+def ds_gather(ctx, cloud, pos, view_dir, light_dir, K: int, out_dtype=None, flags=True):
+    import torch
+    P = pos.shape[0]
+    odt = torch.float32 if out_dtype is None else out_dtype
+    code = {torch.float32: DS_F32, torch.bfloat16: DS_BF16}[odt]
+    z = torch.empty((P, STENCIL_N * K + 1), dtype=odt, device=pos.device)
+    fl = torch.empty(P, dtype=torch.uint8, device=pos.device) if flags else None
+    _check(lib().ds_gather(ctx, cloud, _pts(pos), _pts(view_dir, P), _pts(light_dir, P), P, code,
+                           _ptr(z), _ptr(fl)))
+    return z, fl
+
+
+def ds_forward(ctx, net, z, want_pre=True):
+    import torch
+    if z.dtype != torch.float32 or z.dim() != 2:
+        raise ValueError("z must be a float32 (P, 225K+1) tensor")
+    P = z.shape[0]
+    out = torch.empty(P, dtype=torch.float32, device=z.device)
+    pre = torch.empty(P, dtype=torch.float32, device=z.device) if want_pre else None
+    _check(lib().ds_forward(ctx, net, _ptr(z), P, _ptr(out), _ptr(pre)))
+    return out, pre
+
+
+def ds_predict(ctx, cloud, net, precision, pos, view_dir, light_dir, out=None, pre=None,
+               flags=None, want_pre=True, want_flags=True):
+    import torch
+    P = pos.shape[0]
+    if out is None:
+        out = torch.empty(P, dtype=torch.float32, device=pos.device)
+    if pre is None and want_pre:
+        pre = torch.empty(P, dtype=torch.float32, device=pos.device)
+    if flags is None and want_flags:
+        flags = torch.empty(P, dtype=torch.uint8, device=pos.device)
+    _check(lib().ds_predict(ctx, cloud, net, int(precision), _pts(pos), _pts(view_dir, P),
+                            _pts(light_dir, P), P, _ptr(out), _ptr(pre), _ptr(flags)))
+    return out, pre, flags
+
+
+# ----------------------------------------------------------------------------- owners
+class Context:
+    def __init__(self, device: int = 0, stream=None):
+        self.h = ds_create(device, stream)
+
+    def close(self):
+        if self.h is not None:
+            ds_destroy(self.h)
+            self.h = None
+
+    def synchronize(self):
+        ds_synchronize(self.h)
+
+
+class Cloud:
+    def __init__(self, ctx: Context, density, sigma_max, aabb_min, voxel_size, n_levels, K,
+                 mip_of_level=None):
+        self.ctx = ctx
+        self.h = ds_cloud_create(ctx.h, density, sigma_max, aabb_min, voxel_size, n_levels, K,
+                                 mip_of_level)
+        self.info = ds_cloud_info(self.h)
+        self.K = K
+
+    def level(self, i):
+        return ds_cloud_level(self.ctx.h, self.h, i)
+
+    def close(self):
+        if self.h is not None:
+            ds_cloud_destroy(self.h)
+            self.h = None
+
+
+class Net:
+    def __init__(self, ctx: Context, K: int, W: int, H: int = 3):
+        self.ctx, self.K, self.W, self.H = ctx, K, W, H
+        self.h = ds_net_create(ctx.h, K, W, H)
+        self.n_params = ds_net_param_count(K, W, H)
+
+    def set_params(self, theta):
+        ds_net_set_params(self.h, theta)
+
+    def get_params(self):
+        return ds_net_get_params(self.h, self.n_params)
+
+    def close(self):
+        if self.h is not None:
+            ds_net_destroy(self.h)
+            self.h = None

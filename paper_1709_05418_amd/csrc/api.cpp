@@ -1,0 +1,622 @@
+// Host side of the C ABI: argument validation, object lifetime, device memory and
+// kernel dispatch.  Every entry point returns a status and never throws.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+namespace ds {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+ds_status hip_fail(hipError_t e, const char *what)
+{
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? DS_ERR_OOM : DS_ERR_DEVICE;
+}
+
+namespace {
+
+int level_dim(int n, int i)
+{
+    int64_t s = (int64_t)1 << i;
+    int64_t d = ((int64_t)n + s - 1) / s;
+    return d < 1 ? 1 : (int)d;
+}
+
+struct ParamOffsets {
+    std::vector<int64_t> V, W1, b1, W2, b2, hw, hb;
+};
+
+ParamOffsets param_offsets(int K, int W, int H)
+{
+    ParamOffsets o;
+    int64_t off = 0;
+    for (int k = 0; k < K; ++k) {
+        o.V.push_back(off);
+        off += (int64_t)W * 226;
+        o.W1.push_back(k ? off : -1);
+        if (k)
+            off += (int64_t)W * W;
+        o.b1.push_back(off);
+        off += W;
+        o.W2.push_back(off);
+        off += (int64_t)W * W;
+        o.b2.push_back(off);
+        off += W;
+    }
+    for (int m = 0; m < H; ++m) {
+        int rows = m == H - 1 ? 1 : W;
+        o.hw.push_back(off);
+        off += (int64_t)rows * W;
+        o.hb.push_back(off);
+        off += rows;
+    }
+    return o;
+}
+
+bool desc_ok(const ds_net_desc *d)
+{
+    return d && d->K >= 1 && d->K <= kMaxK && d->W >= 1 && d->W <= 256 && d->H >= 1 && d->H <= 8;
+}
+
+ds_status ensure_ws(ds_ctx *ctx, size_t bytes)
+{
+    if (ctx->ws_bytes >= bytes)
+        return DS_OK;
+    if (ctx->ws) {
+        DS_HIP(hipStreamSynchronize(ctx->stream));
+        (void)hipFree(ctx->ws);
+        ctx->ws = nullptr;
+        ctx->ws_bytes = 0;
+    }
+    DS_HIP(hipMalloc(&ctx->ws, bytes));
+    ctx->ws_bytes = bytes;
+    return DS_OK;
+}
+
+void gather_args(const ds_cloud *c, const float *pos, const float *view, const float *light,
+                 int64_t P, GatherArgs &a)
+{
+    a.pos = pos;
+    a.view = view;
+    a.light = light;
+    a.P = P;
+    int n[3] = {c->nx, c->ny, c->nz};
+    for (int i = 0; i < 3; ++i) {
+        a.amin[i] = c->aabb_min[i];
+        a.amax[i] = (float)((double)c->aabb_min[i] + (double)n[i] * c->h0);
+    }
+    a.inv_mean = (float)(1.0 / c->mean);
+    a.K = c->K;
+    a.lv = static_cast<const GatherLevel *>(c->tables);
+}
+
+constexpr int64_t kChunk = 65536;  // points per plain-form chunk
+
+// Plain FP32 network over `rows` descriptor rows (ldz = 225K + 1).
+ds_status forward_plain(ds_ctx *ctx, const ds_net *net, const float *z, int64_t rows, float *out,
+                        float *pre, float *O, float *F, float *T)
+{
+    const int K = net->K, W = net->W, H = net->H;
+    const int D = kStencil * K + 1;
+    const float *th = net->theta;
+    ParamOffsets po = param_offsets(K, W, H);
+    for (int64_t r0 = 0; r0 < rows; r0 += kChunk) {
+        int M = (int)((rows - r0) < kChunk ? (rows - r0) : kChunk);
+        const float *zc = z + r0 * D;
+        for (int k = 0; k < K; ++k) {
+            GemmArgs g1 = {};
+            g1.M = M;
+            g1.N = W;
+            g1.A1 = zc + (int64_t)k * kStencil;
+            g1.lda1 = D;
+            g1.K1 = kStencil;
+            g1.B1 = th + po.V[k];
+            g1.ldb1 = 226;
+            if (k > 0) {
+                g1.A2 = O;
+                g1.lda2 = W;
+                g1.K2 = W;
+                g1.B2 = th + po.W1[k];
+                g1.ldb2 = W;
+            }
+            g1.g = zc + (int64_t)kStencil * K;
+            g1.ldg = D;
+            g1.gw = th + po.V[k] + 225;
+            g1.ldgw = 226;
+            g1.bias = th + po.b1[k];
+            g1.C = F;
+            g1.ldc = W;
+            g1.relu = 1;
+            ds_status st = gemm_f32(ctx->stream, g1);
+            if (st)
+                return st;
+            GemmArgs g2 = {};
+            g2.M = M;
+            g2.N = W;
+            g2.A1 = F;
+            g2.lda1 = W;
+            g2.K1 = W;
+            g2.B1 = th + po.W2[k];
+            g2.ldb1 = W;
+            g2.bias = th + po.b2[k];
+            if (k > 0) {
+                g2.R = O;
+                g2.ldr = W;
+            }
+            g2.C = O;
+            g2.ldc = W;
+            g2.relu = 1;
+            st = gemm_f32(ctx->stream, g2);
+            if (st)
+                return st;
+        }
+        const float *in = O;
+        float *bufs[2] = {T, F};
+        for (int m = 0; m < H; ++m) {
+            bool last = m == H - 1;
+            GemmArgs g = {};
+            g.M = M;
+            g.N = last ? 1 : W;
+            g.A1 = in;
+            g.lda1 = W;
+            g.K1 = W;
+            g.B1 = th + po.hw[m];
+            g.ldb1 = W;
+            g.bias = th + po.hb[m];
+            g.C = last ? out + r0 : bufs[m & 1];
+            g.ldc = last ? 1 : W;
+            if (last && pre) {
+                g.pre = pre + r0;
+                g.ldpre = 1;
+            }
+            g.relu = 1;
+            ds_status st = gemm_f32(ctx->stream, g);
+            if (st)
+                return st;
+            in = bufs[m & 1];
+        }
+    }
+    return DS_OK;
+}
+
+}  // namespace
+}  // namespace ds
+
+using namespace ds;
+
+extern "C" {
+
+const char *ds_last_error(void) { return g_err; }
+
+const char *ds_version(void) { return "deepscatter-mi355x 0.1 (gfx950)"; }
+
+ds_status ds_create(int device, void *hip_stream, ds_ctx **out)
+{
+    DS_CHECK(out, DS_ERR_INVALID_ARG, "ds_create: out is NULL");
+    int n = 0;
+    DS_HIP(hipGetDeviceCount(&n));
+    DS_CHECK(device >= 0 && device < n, DS_ERR_INVALID_ARG, "ds_create: device %d of %d", device,
+             n);
+    DS_HIP(hipSetDevice(device));
+    ds_ctx *c = new (std::nothrow) ds_ctx();
+    DS_CHECK(c, DS_ERR_OOM, "ds_create: out of host memory");
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    *out = c;
+    return DS_OK;
+}
+
+ds_status ds_set_stream(ds_ctx *ctx, void *hip_stream)
+{
+    DS_CHECK(ctx, DS_ERR_INVALID_ARG, "ds_set_stream: ctx is NULL");
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return DS_OK;
+}
+
+ds_status ds_synchronize(ds_ctx *ctx)
+{
+    DS_CHECK(ctx, DS_ERR_INVALID_ARG, "ds_synchronize: ctx is NULL");
+    DS_HIP(hipStreamSynchronize(ctx->stream));
+    return DS_OK;
+}
+
+ds_status ds_destroy(ds_ctx *ctx)
+{
+    if (!ctx)
+        return DS_OK;
+    if (ctx->ws) {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipFree(ctx->ws);
+    }
+    delete ctx;
+    return DS_OK;
+}
+
+// ---------------------------------------------------------------- cloud
+ds_status ds_cloud_create(ds_ctx *ctx, const void *density_dev, ds_dtype dtype, int nx, int ny,
+                          int nz, float sigma_max, const float aabb_min[3], float voxel_size,
+                          int n_levels, const int *mip_of_level, int K, ds_cloud **out)
+{
+    DS_CHECK(ctx && density_dev && aabb_min && out, DS_ERR_INVALID_ARG,
+             "ds_cloud_create: NULL argument");
+    DS_CHECK(dtype == DS_F32 || dtype == DS_BF16, DS_ERR_INVALID_ARG,
+             "ds_cloud_create: dtype must be DS_F32 or DS_BF16");
+    DS_CHECK(nx > 0 && ny > 0 && nz > 0 && nx <= 4096 && ny <= 4096 && nz <= 4096,
+             DS_ERR_INVALID_ARG, "ds_cloud_create: bad grid size %d x %d x %d", nx, ny, nz);
+    DS_CHECK(sigma_max > 0.f && isfinite(sigma_max) && voxel_size > 0.f && isfinite(voxel_size),
+             DS_ERR_INVALID_ARG, "ds_cloud_create: sigma_max and voxel_size must be positive");
+    DS_CHECK(isfinite(aabb_min[0]) && isfinite(aabb_min[1]) && isfinite(aabb_min[2]),
+             DS_ERR_INVALID_ARG, "ds_cloud_create: aabb_min must be finite");
+    DS_CHECK(n_levels >= 1 && n_levels <= kMaxLevels, DS_ERR_INVALID_ARG,
+             "ds_cloud_create: n_levels %d outside 1..%d", n_levels, kMaxLevels);
+    DS_CHECK(K >= 1 && K <= kMaxK, DS_ERR_INVALID_ARG, "ds_cloud_create: K %d outside 1..%d", K,
+             kMaxK);
+    if (mip_of_level)
+        for (int k = 0; k < K; ++k)
+            DS_CHECK(mip_of_level[k] >= 0 && mip_of_level[k] < n_levels, DS_ERR_INVALID_ARG,
+                     "ds_cloud_create: mip_of_level[%d] = %d outside [0, %d)", k, mip_of_level[k],
+                     n_levels);
+    DS_HIP(hipSetDevice(ctx->device));
+    const int64_t nvox = (int64_t)nx * ny * nz;
+    double sum = 0.0;
+    int64_t count = 0;
+    ds_status st = cloud_mean(ctx->stream, density_dev, dtype, nvox, &sum, &count);
+    if (st)
+        return st;
+    DS_CHECK(count > 0 && sum > 0.0, DS_ERR_INVALID_ARG,
+             "ds_cloud_create: the density grid has no positive voxel");
+
+    ds_cloud *c = new (std::nothrow) ds_cloud();
+    DS_CHECK(c, DS_ERR_OOM, "ds_cloud_create: out of host memory");
+    c->ctx = ctx;
+    c->nx = nx;
+    c->ny = ny;
+    c->nz = nz;
+    c->sigma_max = sigma_max;
+    memcpy(c->aabb_min, aabb_min, sizeof(float) * 3);
+    c->h0 = voxel_size;
+    c->mean = (double)sigma_max * sum / (double)count;
+    c->L = n_levels;
+    c->K = K;
+    int64_t off = 0, coff = 0;
+    for (int i = 0; i < n_levels; ++i) {
+        Level &l = c->lv[i];
+        l.nx = level_dim(nx, i);
+        l.ny = level_dim(ny, i);
+        l.nz = level_dim(nz, i);
+        l.off = off;
+        l.cell_off = coff;
+        l.h = (float)ldexp((double)voxel_size, i);
+        off += (int64_t)l.nx * l.ny * l.nz;
+        coff += (int64_t)(l.nx + 2) * (l.ny + 2) * (l.nz + 2);
+    }
+    c->pyr_elems = off;
+    c->n_cells = coff;
+    if (mip_of_level) {
+        memcpy(c->mips, mip_of_level, sizeof(int) * K);
+    } else {
+        // the level whose voxel best matches the level-1 spacing of half a mean free path
+        int delta = (int)floor(log2(0.5 / (c->mean * (double)voxel_size)) + 0.5);
+        for (int k = 0; k < K; ++k) {
+            int m = k + delta;
+            c->mips[k] = m < 0 ? 0 : (m > n_levels - 1 ? n_levels - 1 : m);
+        }
+    }
+    auto fail = [&](ds_status s) {
+        ds_cloud_destroy(c);
+        return s;
+    };
+    if (hipMalloc(&c->pyr, sizeof(float) * c->pyr_elems) != hipSuccess) {
+        set_error("ds_cloud_create: out of device memory for the float32 pyramid (%lld floats)",
+                  (long long)c->pyr_elems);
+        return fail(DS_ERR_OOM);
+    }
+    if (hipMalloc(&c->cells, sizeof(uint4) * c->n_cells) != hipSuccess) {
+        set_error("ds_cloud_create: out of device memory for the packed pyramid (%lld cells)",
+                  (long long)c->n_cells);
+        return fail(DS_ERR_OOM);
+    }
+    float scale = (float)((double)sigma_max / c->mean);
+    st = cloud_pyramid(ctx->stream, density_dev, dtype, nx, ny, nz, scale, n_levels, c->lv, c->pyr);
+    if (st)
+        return fail(st);
+    st = cloud_pack(ctx->stream, c->pyr, n_levels, c->lv, c->cells);
+    if (st)
+        return fail(st);
+    // device-side per-stencil-level tables
+    std::vector<GatherLevel> gl(K);
+    std::vector<FusedLevel> fl(K);
+    for (int k = 0; k < K; ++k) {
+        const Level &l = c->lv[c->mips[k]];
+        double h = ldexp((double)voxel_size, c->mips[k]);
+        double step = ldexp(1.0, k) / c->mean;
+        gl[k].data = c->pyr + l.off;
+        gl[k].nx = l.nx;
+        gl[k].ny = l.ny;
+        gl[k].nz = l.nz;
+        gl[k].inv_h = (float)(1.0 / h);
+        gl[k].step = (float)step;
+        fl[k].cells = c->cells + l.cell_off;
+        fl[k].cx = l.nx + 2;
+        fl[k].cy = l.ny + 2;
+        fl[k].hi_x = (float)l.nx;
+        fl[k].hi_y = (float)l.ny;
+        fl[k].hi_z = (float)l.nz;
+        fl[k].inv_h = (float)(1.0 / h);
+        fl[k].step = (float)step;
+    }
+    size_t tb = sizeof(GatherLevel) * K + sizeof(FusedLevel) * K + 64;
+    if (hipMalloc(&c->tables, tb) != hipSuccess) {
+        set_error("ds_cloud_create: out of device memory for the level tables");
+        return fail(DS_ERR_OOM);
+    }
+    std::vector<char> host(tb, 0);
+    memcpy(host.data(), gl.data(), sizeof(GatherLevel) * K);
+    size_t foff = (sizeof(GatherLevel) * K + 63) / 64 * 64;
+    memcpy(host.data() + foff, fl.data(), sizeof(FusedLevel) * K);
+    hipError_t e = hipMemcpy(c->tables, host.data(), tb, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess)
+        return fail(hip_fail(e, "ds_cloud_create"));
+    *out = c;
+    return DS_OK;
+}
+
+static const FusedLevel *fused_table(const ds_cloud *c)
+{
+    size_t foff = (sizeof(GatherLevel) * c->K + 63) / 64 * 64;
+    return reinterpret_cast<const FusedLevel *>(static_cast<const char *>(c->tables) + foff);
+}
+
+ds_status ds_cloud_info(const ds_cloud *c, double *mean_mu_t, int *n_levels, int *dims,
+                        int *mip_of_level, int *K)
+{
+    DS_CHECK(c, DS_ERR_INVALID_ARG, "ds_cloud_info: cloud is NULL");
+    if (mean_mu_t)
+        *mean_mu_t = c->mean;
+    if (n_levels)
+        *n_levels = c->L;
+    if (dims)
+        for (int i = 0; i < c->L; ++i) {
+            dims[3 * i] = c->lv[i].nx;
+            dims[3 * i + 1] = c->lv[i].ny;
+            dims[3 * i + 2] = c->lv[i].nz;
+        }
+    if (mip_of_level)
+        memcpy(mip_of_level, c->mips, sizeof(int) * c->K);
+    if (K)
+        *K = c->K;
+    return DS_OK;
+}
+
+ds_status ds_cloud_level(ds_ctx *ctx, const ds_cloud *c, int level, float *dst_dev)
+{
+    DS_CHECK(ctx && c && dst_dev, DS_ERR_INVALID_ARG, "ds_cloud_level: NULL argument");
+    DS_CHECK(level >= 0 && level < c->L, DS_ERR_INVALID_ARG, "ds_cloud_level: level %d of %d",
+             level, c->L);
+    const Level &l = c->lv[level];
+    DS_HIP(hipMemcpyAsync(dst_dev, c->pyr + l.off, sizeof(float) * l.nx * l.ny * l.nz,
+                          hipMemcpyDeviceToDevice, ctx->stream));
+    return DS_OK;
+}
+
+ds_status ds_cloud_destroy(ds_cloud *c)
+{
+    if (!c)
+        return DS_OK;
+    if (c->ctx)
+        (void)hipStreamSynchronize(c->ctx->stream);
+    (void)hipFree(c->pyr);
+    (void)hipFree(c->cells);
+    (void)hipFree(c->tables);
+    delete c;
+    return DS_OK;
+}
+
+// ---------------------------------------------------------------- network
+int64_t ds_net_param_count(const ds_net_desc *d)
+{
+    if (!desc_ok(d))
+        return -1;
+    int64_t n = 0;
+    for (int k = 0; k < d->K; ++k)
+        n += (int64_t)d->W * 226 + (k ? (int64_t)d->W * d->W : 0) + d->W + (int64_t)d->W * d->W +
+             d->W;
+    for (int m = 0; m < d->H; ++m) {
+        int rows = m == d->H - 1 ? 1 : d->W;
+        n += (int64_t)rows * d->W + rows;
+    }
+    return n;
+}
+
+ds_status ds_net_create(ds_ctx *ctx, const ds_net_desc *desc, ds_net **out)
+{
+    DS_CHECK(ctx && out, DS_ERR_INVALID_ARG, "ds_net_create: NULL argument");
+    DS_CHECK(desc_ok(desc), DS_ERR_INVALID_ARG,
+             "ds_net_create: need 1 <= K <= 16, 1 <= W <= 256, 1 <= H <= 8");
+    ds_net *n = new (std::nothrow) ds_net();
+    DS_CHECK(n, DS_ERR_OOM, "ds_net_create: out of host memory");
+    n->ctx = ctx;
+    n->K = desc->K;
+    n->W = desc->W;
+    n->H = desc->H;
+    n->n_params = ds_net_param_count(desc);
+    if (hipMalloc(&n->theta, sizeof(float) * n->n_params) != hipSuccess) {
+        delete n;
+        set_error("ds_net_create: out of device memory");
+        return DS_ERR_OOM;
+    }
+    hipError_t e = hipMemsetAsync(n->theta, 0, sizeof(float) * n->n_params, ctx->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(n->theta);
+        delete n;
+        return hip_fail(e, "ds_net_create");
+    }
+    *out = n;
+    return DS_OK;
+}
+
+ds_status ds_net_set_params(ds_net *net, const float *theta_host, int64_t n)
+{
+    DS_CHECK(net && theta_host, DS_ERR_INVALID_ARG, "ds_net_set_params: NULL argument");
+    DS_CHECK(n == net->n_params, DS_ERR_INVALID_ARG,
+             "ds_net_set_params: %lld parameters given, %lld expected", (long long)n,
+             (long long)net->n_params);
+    for (int64_t i = 0; i < n; ++i)
+        DS_CHECK(isfinite(theta_host[i]), DS_ERR_INVALID_ARG,
+                 "ds_net_set_params: parameter %lld is not finite", (long long)i);
+    DS_HIP(hipStreamSynchronize(net->ctx->stream));
+    DS_HIP(hipMemcpy(net->theta, theta_host, sizeof(float) * n, hipMemcpyHostToDevice));
+    net->has_fp8 = false;
+    if (fused_tiles(net->W) > 0)
+        return fused_pack_bf16(net, theta_host);
+    return DS_OK;
+}
+
+ds_status ds_net_get_params(ds_net *net, float *theta_host, int64_t n)
+{
+    DS_CHECK(net && theta_host, DS_ERR_INVALID_ARG, "ds_net_get_params: NULL argument");
+    DS_CHECK(n == net->n_params, DS_ERR_INVALID_ARG,
+             "ds_net_get_params: %lld parameters requested, %lld held", (long long)n,
+             (long long)net->n_params);
+    DS_HIP(hipStreamSynchronize(net->ctx->stream));
+    DS_HIP(hipMemcpy(theta_host, net->theta, sizeof(float) * n, hipMemcpyDeviceToHost));
+    return DS_OK;
+}
+
+ds_status ds_net_destroy(ds_net *net)
+{
+    if (!net)
+        return DS_OK;
+    (void)hipStreamSynchronize(net->ctx->stream);
+    (void)hipFree(net->theta);
+    (void)hipFree(net->frag_bf16);
+    (void)hipFree(net->vec);
+    delete net;
+    return DS_OK;
+}
+
+// ---------------------------------------------------------------- hot path
+ds_status ds_gather(ds_ctx *ctx, const ds_cloud *cloud, const float *pos, const float *view_dir,
+                    const float *light_dir, int64_t P, ds_dtype out_dtype, void *z_out,
+                    uint8_t *flags)
+{
+    DS_CHECK(ctx && cloud, DS_ERR_INVALID_ARG, "ds_gather: NULL context or cloud");
+    DS_CHECK(P >= 0 && P <= ((int64_t)1 << 31), DS_ERR_INVALID_ARG, "ds_gather: bad P %lld",
+             (long long)P);
+    DS_CHECK(out_dtype == DS_F32 || out_dtype == DS_BF16, DS_ERR_INVALID_ARG,
+             "ds_gather: bad output dtype");
+    if (P == 0)
+        return DS_OK;
+    DS_CHECK(pos && view_dir && light_dir && z_out, DS_ERR_INVALID_ARG,
+             "ds_gather: NULL device pointer");
+    GatherArgs a;
+    gather_args(cloud, pos, view_dir, light_dir, P, a);
+    return gather_plain(ctx->stream, a, 0, P, out_dtype, z_out, kStencil * cloud->K + 1, flags);
+}
+
+ds_status ds_forward(ds_ctx *ctx, const ds_net *net, const float *z, int64_t P, float *out,
+                     float *pre_out)
+{
+    DS_CHECK(ctx && net, DS_ERR_INVALID_ARG, "ds_forward: NULL context or network");
+    DS_CHECK(P >= 0 && P <= ((int64_t)1 << 31), DS_ERR_INVALID_ARG, "ds_forward: bad P");
+    if (P == 0)
+        return DS_OK;
+    DS_CHECK(z && out, DS_ERR_INVALID_ARG, "ds_forward: NULL device pointer");
+    const int64_t rows = P < kChunk ? P : kChunk;
+    size_t need = sizeof(float) * (size_t)rows * net->W * 3;
+    ds_status st = ensure_ws(ctx, need);
+    if (st)
+        return st;
+    float *O = static_cast<float *>(ctx->ws);
+    return forward_plain(ctx, net, z, P, out, pre_out, O, O + rows * net->W,
+                         O + 2 * rows * net->W);
+}
+
+ds_status ds_predict(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
+                     ds_precision precision, const float *pos, const float *view_dir,
+                     const float *light_dir, int64_t P, float *out, float *pre_out,
+                     uint8_t *flags)
+{
+    DS_CHECK(ctx && cloud && net, DS_ERR_INVALID_ARG, "ds_predict: NULL context, cloud or net");
+    DS_CHECK(cloud->K == net->K, DS_ERR_INVALID_ARG,
+             "ds_predict: the cloud has %d stencil levels, the network %d", cloud->K, net->K);
+    DS_CHECK(P >= 0 && P <= ((int64_t)1 << 31), DS_ERR_INVALID_ARG, "ds_predict: bad P");
+    if (P == 0)
+        return DS_OK;
+    DS_CHECK(pos && view_dir && light_dir && out, DS_ERR_INVALID_ARG,
+             "ds_predict: NULL device pointer");
+    if (precision == DS_PREC_F32) {
+        const int D = kStencil * net->K + 1;
+        const int64_t rows = P < kChunk ? P : kChunk;
+        size_t need = sizeof(float) * (size_t)rows * ((size_t)D + 3 * net->W) + (size_t)rows;
+        ds_status st = ensure_ws(ctx, need);
+        if (st)
+            return st;
+        float *z = static_cast<float *>(ctx->ws);
+        float *O = z + rows * D;
+        uint8_t *fl_ws = reinterpret_cast<uint8_t *>(O + 3 * rows * net->W);
+        GatherArgs a;
+        gather_args(cloud, pos, view_dir, light_dir, P, a);
+        for (int64_t p0 = 0; p0 < P; p0 += kChunk) {
+            int64_t np = (P - p0) < kChunk ? (P - p0) : kChunk;
+            // the gather writes flags at absolute point indices
+            uint8_t *fl = flags ? flags : fl_ws - p0;
+            st = gather_plain(ctx->stream, a, p0, np, DS_F32, z, D, fl);
+            if (st)
+                return st;
+            st = forward_plain(ctx, net, z, np, out + p0, pre_out ? pre_out + p0 : nullptr, O,
+                               O + rows * net->W, O + 2 * rows * net->W);
+            if (st)
+                return st;
+            st = mask_invalid(ctx->stream, fl + p0, np, out + p0, pre_out ? pre_out + p0 : nullptr);
+            if (st)
+                return st;
+        }
+        return DS_OK;
+    }
+    if (precision == DS_PREC_BF16) {
+        DS_CHECK(net->frag_bf16, DS_ERR_STATE, "ds_predict: network parameters were never set");
+        FusedArgs a = {};
+        GatherArgs ga;
+        gather_args(cloud, pos, view_dir, light_dir, P, ga);
+        a.pos = pos;
+        a.view = view_dir;
+        a.light = light_dir;
+        a.P = P;
+        a.out = out;
+        a.pre = pre_out;
+        a.flags = flags;
+        memcpy(a.amin, ga.amin, sizeof(a.amin));
+        memcpy(a.amax, ga.amax, sizeof(a.amax));
+        a.inv_mean = ga.inv_mean;
+        a.K = net->K;
+        a.W = net->W;
+        a.H = net->H;
+        return fused_predict_bf16(ctx->stream, net, a, fused_table(cloud));
+    }
+    if (precision == DS_PREC_FP8) {
+        set_error("ds_predict: FP8 weights are not available for this network");
+        return net->has_fp8 ? DS_ERR_UNSUPPORTED : DS_ERR_STATE;
+    }
+    set_error("ds_predict: unknown precision %d", (int)precision);
+    return DS_ERR_INVALID_ARG;
+}
+
+}  // extern "C"

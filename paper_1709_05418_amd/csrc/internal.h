@@ -1,0 +1,152 @@
+// Internal declarations shared by the host API and the HIP kernels of
+// libdeepscatter.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/deepscatter.h"
+
+namespace ds {
+
+// ------------------------------------------------------------------ errors
+void set_error(const char *fmt, ...);
+ds_status hip_fail(hipError_t e, const char *what);
+
+#define DS_HIP(expr)                                                    \
+    do {                                                                \
+        hipError_t e_ = (expr);                                         \
+        if (e_ != hipSuccess)                                           \
+            return ::ds::hip_fail(e_, #expr);                           \
+    } while (0)
+
+#define DS_CHECK(cond, code, ...)                                       \
+    do {                                                                \
+        if (!(cond)) {                                                  \
+            ::ds::set_error(__VA_ARGS__);                               \
+            return (code);                                              \
+        }                                                               \
+    } while (0)
+
+constexpr int kStencil = 225;   // 5 x 5 x 9 points per level
+constexpr int kMaxLevels = 16;
+constexpr int kMaxK = 16;
+
+// ------------------------------------------------------------------ objects
+struct Level {
+    int nx, ny, nz;          // level dims (ceil(n / 2^i))
+    int64_t off;             // offset in the float32 pyramid (elements)
+    int64_t cell_off;        // offset in the corner-packed pyramid (cells)
+    float h;                 // voxel size (world units)
+};
+
+}  // namespace ds
+
+struct ds_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    // workspace for the plain (materialised-descriptor) form
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+};
+
+struct ds_cloud {
+    ds_ctx *ctx = nullptr;
+    int nx = 0, ny = 0, nz = 0;
+    float sigma_max = 0.f;
+    float aabb_min[3] = {0, 0, 0};
+    float h0 = 0.f;
+    double mean = 0.0;        // mean extinction over non-zero voxels
+    int L = 0;
+    ds::Level lv[ds::kMaxLevels];
+    int K = 0;
+    int mips[ds::kMaxK];
+    float *pyr = nullptr;      // float32 levels, concatenated
+    int64_t pyr_elems = 0;
+    uint4 *cells = nullptr;    // corner-packed bf16 levels (8 corners per cell)
+    int64_t n_cells = 0;
+    void *tables = nullptr;    // device: GatherLevel[K] then FusedLevel[K]
+};
+
+struct ds_net {
+    ds_ctx *ctx = nullptr;
+    int K = 0, W = 0, H = 0;
+    int64_t n_params = 0;
+    float *theta = nullptr;       // FP32 master parameters (canonical order), device
+    // fused-kernel operands, see fused.hip for the layout
+    uint4 *frag_bf16 = nullptr;   // packed weight fragments
+    int64_t frag_count = 0;       // number of 16-byte lane entries
+    float *vec = nullptr;         // packed biases and the final layer (fp32)
+    int64_t vec_count = 0;
+    bool has_fp8 = false;
+};
+
+namespace ds {
+
+// ------------------------------------------------------------------ kernels (launchers)
+// cloud.hip
+ds_status cloud_mean(hipStream_t s, const void *d, ds_dtype dt, int64_t n, double *sum,
+                     int64_t *count);
+ds_status cloud_pyramid(hipStream_t s, const void *d, ds_dtype dt, int nx, int ny, int nz,
+                        float scale, int L, const Level *lv, float *pyr);
+ds_status cloud_pack(hipStream_t s, const float *pyr, int L, const Level *lv, uint4 *cells);
+
+// gather.hip
+struct GatherLevel {
+    const float *data;  // level base (float32)
+    int nx, ny, nz;
+    float inv_h;        // 1 / h_m
+    float step;         // 2^(k-1) / mean  (world units per lattice unit of 1 mfp)
+};
+struct GatherArgs {
+    const float *pos, *view, *light;
+    int64_t P;
+    float amin[3], amax[3];
+    float inv_mean;     // 1 / mean (level-1 scale)
+    int K;
+    const GatherLevel *lv;  // device table, K entries
+};
+ds_status gather_plain(hipStream_t s, const GatherArgs &a, int64_t p0, int64_t np, ds_dtype odt,
+                       void *z, int64_t ldz, uint8_t *flags);
+ds_status mask_invalid(hipStream_t s, const uint8_t *flags, int64_t n, float *out, float *pre);
+
+// mlp.hip: C = act(A1 B1^T + A2 B2^T + g (x) gw + bias + R), row-major, B rows = outputs
+struct GemmArgs {
+    int M, N;
+    const float *A1; int lda1; int K1; const float *B1; int ldb1;
+    const float *A2; int lda2; int K2; const float *B2; int ldb2;
+    const float *g; int ldg; const float *gw; int ldgw;  // rank-1 term (may be null)
+    const float *bias;
+    const float *R; int ldr;                           // residual (may be null)
+    float *C; int ldc;
+    float *pre; int ldpre;                             // pre-activation copy (may be null)
+    int relu;
+};
+ds_status gemm_f32(hipStream_t s, const GemmArgs &a);
+
+// fused.hip
+int fused_tiles(int W);
+ds_status fused_pack_bf16(ds_net *net, const float *theta_host);
+struct FusedLevel {
+    const uint4 *cells;
+    int cx, cy;          // cell-grid dims in x and y (level dims + 2)
+    float hi_x, hi_y, hi_z;  // clamp bounds (level dims as float)
+    float inv_h;
+    float step;          // 2^(k-1) / mean
+};
+struct FusedArgs {
+    const float *pos, *view, *light;
+    int64_t P;
+    float *out, *pre;
+    uint8_t *flags;
+    float amin[3], amax[3];
+    float inv_mean;
+    int K, W, H;
+};
+ds_status fused_predict_bf16(hipStream_t s, const ds_net *net, const FusedArgs &a,
+                             const FusedLevel *lvt);
+
+}  // namespace ds
