@@ -51,8 +51,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the FP64 oracle baseline")
-    ap.add_argument("--cpu-sample", type=int, default=16384)
-    ap.add_argument("--fp32-steps", type=int, default=3)
+    ap.add_argument("--cpu-sample", type=int, default=262144)
+    ap.add_argument("--fp32-steps", type=int, default=3, help="0 skips the FP32 plain form")
+    ap.add_argument("--save-inputs", default=None, help="write the generated inputs to this .npz")
+    ap.add_argument("--load-inputs", default=None,
+                    help="read inputs written by --save-inputs instead of generating them "
+                         "(keeps generator kernels out of profiled runs)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 256 MiB elementwise copy kernel (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -72,12 +78,20 @@ def main():
     log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
 
     t0 = time.time()
-    density = synth.cloud_density(cfg["n"], cfg["seed_cloud"], worley=cfg["worley"], device=dev)
     aabb_min, h0 = synth.unit_box(cfg["n"])
+    if args.load_inputs:
+        saved = np.load(args.load_inputs)
+        density = torch.from_numpy(saved["density"]).to(dev)
+        pos_np, view_np = saved["pos"], saved["view"]
+    else:
+        density = synth.cloud_density(cfg["n"], cfg["seed_cloud"], worley=cfg["worley"],
+                                      device=dev)
+        pos_np, view_np = synth.camera_hits(density, cfg["sigma"], cfg["res"], P,
+                                            cfg["seed_pts"], aabb_min, h0, device=dev)
+    if args.save_inputs:
+        np.savez(args.save_inputs, density=density.cpu().numpy(), pos=pos_np, view=view_np)
     ctx = ds.Context(0)
     cloud = ds.Cloud(ctx, density, cfg["sigma"], aabb_min, h0, cfg["L"], K)
-    pos_np, view_np = synth.camera_hits(density, cfg["sigma"], cfg["res"], P, cfg["seed_pts"],
-                                        aabb_min, h0, device=dev)
     light_np = np.broadcast_to(synth.table1_lights()["side"], (P, 3)).copy()
     pos = torch.from_numpy(pos_np).to(dev)
     view = torch.from_numpy(view_np).to(dev)
@@ -126,16 +140,27 @@ def main():
 
     # ---------------------------------------------------------------- FP32 plain form
     out32 = torch.empty(P, dtype=torch.float32, device=dev)
-    run(ds.DS_PREC_F32, out32)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(args.fp32_steps):
+    fp32 = None
+    if args.fp32_steps > 0:
         run(ds.DS_PREC_F32, out32)
-    torch.cuda.synchronize()
-    ms32 = (time.perf_counter() - t1) * 1e3 / args.fp32_steps
-    log(f"fp32 plain: {ms32:.2f} ms/step, speedup of bf16 fused {ms32 / ms_step:.2f}x")
-    fp32 = {"ms_per_step": round(ms32, 3), "value": P / (ms32 / 1e3),
-            "speedup_bf16_over_fp32": round(ms32 / ms_step, 2)}
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(args.fp32_steps):
+            run(ds.DS_PREC_F32, out32)
+        torch.cuda.synchronize()
+        ms32 = (time.perf_counter() - t1) * 1e3 / args.fp32_steps
+        log(f"fp32 plain: {ms32:.2f} ms/step, speedup of bf16 fused {ms32 / ms_step:.2f}x")
+        fp32 = {"ms_per_step": round(ms32, 3), "value": P / (ms32 / 1e3),
+                "speedup_bf16_over_fp32": round(ms32 / ms_step, 2)}
+
+    if args.calib_copy:
+        # plain elementwise copy of a known size: reads and writes 256 MiB each
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log("calibration copy: 3 x 256 MiB read + 256 MiB written")
 
     # ---------------------------------------------------------------- oracle baseline
     cpu = None
@@ -168,11 +193,11 @@ def main():
         log(f"oracle: {S / tcpu:.1f} points/s on {O.threads()} threads")
         same_mips = list(mips) == list(cloud.info["mip_of_level"])
         g16 = out.cpu().numpy()[idx]
-        g32 = out32.cpu().numpy()[idx]
+        g32 = out32.cpu().numpy()[idx] if fp32 else None
         rl = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
         parity = {"sampled_points": S, "same_mip_map": same_mips,
                   "rel_l2_bf16": rl(g16, g_ref) if same_mips else None,
-                  "rel_l2_fp32": rl(g32, g_ref) if same_mips else None,
+                  "rel_l2_fp32": rl(g32, g_ref) if (same_mips and fp32) else None,
                   "tolerance_bf16": 2e-2, "tolerance_fp32": 1e-5}
         log(f"parity on sample: {parity}")
 

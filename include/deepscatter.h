@@ -148,6 +148,15 @@ ds_status ds_gather(ds_ctx *ctx, const ds_cloud *cloud, const float *pos, const 
                     const float *light_dir, int64_t P, ds_dtype out_dtype, void *z_out,
                     uint8_t *flags);
 
+/* The descriptor as the fused kernel gathers it: the same samples as ds_gather,
+ * interpolated from the corner-packed BF16 copy of the pyramid with BF16
+ * interpolation weights (FP32 accumulation), written as float32 rows of 225K+1
+ * values in ds_gather's order.  For checking the fused path; z_out is device
+ * memory of P*(225K+1) floats. */
+ds_status ds_gather_packed(ds_ctx *ctx, const ds_cloud *cloud, const float *pos,
+                           const float *view_dir, const float *light_dir, int64_t P,
+                           float *z_out);
+
 /* Network on materialised descriptors z (device, [P][225K+1] float32):
  * out[p] = g(z_p) (the predicted L_i per unit irradiance) and, if pre_out is not
  * NULL, the final layer's pre-activation.  FP32 plain form. */

@@ -61,6 +61,7 @@ def lib():
         "ds_net_get_params": (S, [P, P, I64]),
         "ds_net_destroy": (S, [P]),
         "ds_gather": (S, [P, P, P, P, P, I64, I, P, P]),
+        "ds_gather_packed": (S, [P, P, P, P, P, I64, P]),
         "ds_forward": (S, [P, P, P, I64, P, P]),
         "ds_predict": (S, [P, P, P, I, P, P, P, I64, P, P, P]),
     }
@@ -214,6 +215,15 @@ def ds_gather(ctx, cloud, pos, view_dir, light_dir, K: int, out_dtype=None, flag
     _check(lib().ds_gather(ctx, cloud, _pts(pos), _pts(view_dir, P), _pts(light_dir, P), P, code,
                            _ptr(z), _ptr(fl)))
     return z, fl
+
+
+def ds_gather_packed(ctx, cloud, pos, view_dir, light_dir, K: int):
+    import torch
+    P = pos.shape[0]
+    z = torch.empty((P, STENCIL_N * K + 1), dtype=torch.float32, device=pos.device)
+    _check(lib().ds_gather_packed(ctx, cloud, _pts(pos), _pts(view_dir, P), _pts(light_dir, P), P,
+                                  _ptr(z)))
+    return z
 
 
 def ds_forward(ctx, net, z, want_pre=True):

@@ -354,9 +354,9 @@ ds_status ds_cloud_create(ds_ctx *ctx, const void *density_dev, ds_dtype dtype, 
         fl[k].cells = c->cells + l.cell_off;
         fl[k].cx = l.nx + 2;
         fl[k].cy = l.ny + 2;
-        fl[k].hi_x = (float)l.nx;
-        fl[k].hi_y = (float)l.ny;
-        fl[k].hi_z = (float)l.nz;
+        fl[k].hi_x = (float)(l.nx + 1);  // cell coordinates are shifted by one
+        fl[k].hi_y = (float)(l.ny + 1);
+        fl[k].hi_z = (float)(l.nz + 1);
         fl[k].inv_h = (float)(1.0 / h);
         fl[k].step = (float)step;
     }
@@ -529,6 +529,29 @@ ds_status ds_gather(ds_ctx *ctx, const ds_cloud *cloud, const float *pos, const 
     GatherArgs a;
     gather_args(cloud, pos, view_dir, light_dir, P, a);
     return gather_plain(ctx->stream, a, 0, P, out_dtype, z_out, kStencil * cloud->K + 1, flags);
+}
+
+ds_status ds_gather_packed(ds_ctx *ctx, const ds_cloud *cloud, const float *pos,
+                           const float *view_dir, const float *light_dir, int64_t P, float *z_out)
+{
+    DS_CHECK(ctx && cloud, DS_ERR_INVALID_ARG, "ds_gather_packed: NULL context or cloud");
+    DS_CHECK(P >= 0 && P <= ((int64_t)1 << 31), DS_ERR_INVALID_ARG, "ds_gather_packed: bad P");
+    if (P == 0)
+        return DS_OK;
+    DS_CHECK(pos && view_dir && light_dir && z_out, DS_ERR_INVALID_ARG,
+             "ds_gather_packed: NULL device pointer");
+    FusedArgs a = {};
+    GatherArgs ga;
+    gather_args(cloud, pos, view_dir, light_dir, P, ga);
+    a.pos = pos;
+    a.view = view_dir;
+    a.light = light_dir;
+    a.P = P;
+    memcpy(a.amin, ga.amin, sizeof(a.amin));
+    memcpy(a.amax, ga.amax, sizeof(a.amax));
+    a.inv_mean = ga.inv_mean;
+    a.K = cloud->K;
+    return fused_gather_packed(ctx->stream, a, fused_table(cloud), z_out);
 }
 
 ds_status ds_forward(ds_ctx *ctx, const ds_net *net, const float *z, int64_t P, float *out,

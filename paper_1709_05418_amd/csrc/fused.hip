@@ -11,12 +11,26 @@
 // layout, and the order in which inputs enter the 32-wide reduction is a fixed
 // permutation that the host folds into the packed weight fragments.
 //
-// The stencil part of each block's first layer is gathered straight into B
-// operands: lane (g, n) samples stencil points 32c + 8g + j (j = 0..7) of point n
-// for chunk c = 0..6; chunk 7 carries sample 224, gamma and, when the number of M
-// tiles is odd, the last tile of o^{k-1}.  Samples come from a corner-packed BF16
-// copy of the mip level (8 corners per 16-byte cell, one load per sample) with the
-// coordinates clamped to [-1, n], which reproduces zero outside the grid.
+// Work split.  A workgroup of NW waves (4 or 8) owns 16 NW points, 16 per wave,
+// with two waves per SIMD.  The weight fragments of one 32-wide input chunk (MT KB)
+// are staged once per workgroup in LDS, double-buffered: while the waves consume
+// chunk i the next chunk is already in flight from L2.  Fragments are stored in
+// consumption order, so staging is a linear walk.  The stencil samples are
+// software-pipelined: each lane keeps two half-chunks (4 samples each) of loads in
+// flight, and the first samples of level k+1 are issued before the second layer
+// of block k runs.
+//
+// Stencil gather.  The first layer of block k reads 225 stencil densities plus
+// gamma.  Lane group g of chunk c gathers 8 samples of its point: chunks 0..5 and
+// the g = 0 part of chunk 6 cover the 25 stencil columns (ix, iy) with iz = 0..7,
+// so consecutive samples differ by one fixed step vector; lanes g = 1..3 of chunk
+// 6 take 24 of the 25 samples of the iz = 8 plane (five rows of four and one
+// column of four), and chunk 7 carries the last plane sample (4, 4, 8), gamma and
+// (for an odd tile count) the last tile of o^{k-1}.
+// Densities come from a corner-packed BF16 copy of the mip level (the 8 corners
+// of a cell in one 16-byte load) addressed in cell coordinates shifted by one and
+// clamped to [0, n+1], which reproduces zero outside the grid.
+#include <stdlib.h>
 #include <string.h>
 
 #include <vector>
@@ -28,45 +42,132 @@ namespace ds {
 namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f4 __attribute__((ext_vector_type(4)));
-
-constexpr int kWaves = 4;
 
 __device__ __forceinline__ f4 mfma_bf16(const uint4 &a, const bf16x8 &b, const f4 &c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), b, c, 0, 0, 0);
 }
 
-__device__ __forceinline__ float bf_lo(uint32_t v) { return __uint_as_float(v << 16); }
-__device__ __forceinline__ float bf_hi(uint32_t v) { return __uint_as_float(v & 0xffff0000u); }
-
-// Per point and level: voxel coordinate of lattice point (0,0,0) and the
-// coordinate steps along the three lattice axes.
+// Per point and level: cell coordinate (shifted by +1) of lattice point (0,0,0)
+// and the coordinate steps along the three lattice axes.
 struct PtLevel {
     float u0[3], a[3], b[3], c[3];
 };
 
 __device__ __forceinline__ float lerp(float a, float b, float t) { return fmaf(t, b - a, a); }
 
-__device__ __forceinline__ float sample(const FusedLevel &L, const PtLevel &q, float ix, float iy,
-                                        float iz)
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) u32x4 *gcell_ptr;
+
+// Four trilinear samples in flight: the 16-byte corner cells and the fractions.
+struct Pending {
+    u32x4 v[4];
+    float fx[4], fy[4], fz[4];
+};
+
+// Clamp a shifted cell coordinate, start the cell load, keep the fractions.
+__device__ __forceinline__ void issue_one(gcell_ptr cells, const FusedLevel &L, float ux, float uy,
+                                          float uz, u32x4 &v, float &fx, float &fy, float &fz)
 {
-    float ux = q.u0[0] + ix * q.a[0] + iy * q.b[0] + iz * q.c[0];
-    float uy = q.u0[1] + ix * q.a[1] + iy * q.b[1] + iz * q.c[1];
-    float uz = q.u0[2] + ix * q.a[2] + iy * q.b[2] + iz * q.c[2];
-    ux = fminf(fmaxf(ux, -1.f), L.hi_x);
-    uy = fminf(fmaxf(uy, -1.f), L.hi_y);
-    uz = fminf(fmaxf(uz, -1.f), L.hi_z);
-    float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
-    float fx = ux - fx0, fy = uy - fy0, fz = uz - fz0;
-    int i = (int)fx0 + 1, j = (int)fy0 + 1, k = (int)fz0 + 1;
-    int64_t idx = ((int64_t)k * L.cy + j) * L.cx + i;
-    uint4 v = L.cells[idx];
-    float x00 = lerp(bf_lo(v.x), bf_hi(v.x), fx);
-    float x10 = lerp(bf_lo(v.y), bf_hi(v.y), fx);
-    float x01 = lerp(bf_lo(v.z), bf_hi(v.z), fx);
-    float x11 = lerp(bf_lo(v.w), bf_hi(v.w), fx);
+    ux = __builtin_amdgcn_fmed3f(ux, 0.f, L.hi_x);
+    uy = __builtin_amdgcn_fmed3f(uy, 0.f, L.hi_y);
+    uz = __builtin_amdgcn_fmed3f(uz, 0.f, L.hi_z);
+    const uint32_t i = (uint32_t)ux, j = (uint32_t)uy, k = (uint32_t)uz;
+    fx = __builtin_amdgcn_fractf(ux);
+    fy = __builtin_amdgcn_fractf(uy);
+    fz = __builtin_amdgcn_fractf(uz);
+    // 24-bit multiplies: cell dims stay below 2^13 and j + cy k below 2^24
+    const uint32_t idx = i + __umul24((uint32_t)L.cx, j + __umul24((uint32_t)L.cy, k));
+    v = cells[idx];
+}
+
+// Trilinear interpolation of a loaded cell in FP32: unpack the eight bf16 corners
+// (a shift or a mask each) and lerp along x, y, z.  (The v_dot2c_f32_bf16 form of
+// the x lerps read its zeroed accumulator register stale when the compiler placed
+// the zeroing move right before it, so it is not used.)
+__device__ __forceinline__ float finish_one(const u32x4 &v, float fx, float fy, float fz)
+{
+    const float x00 = lerp(__uint_as_float(v[0] << 16), __uint_as_float(v[0] & 0xffff0000u), fx);
+    const float x10 = lerp(__uint_as_float(v[1] << 16), __uint_as_float(v[1] & 0xffff0000u), fx);
+    const float x01 = lerp(__uint_as_float(v[2] << 16), __uint_as_float(v[2] & 0xffff0000u), fx);
+    const float x11 = lerp(__uint_as_float(v[3] << 16), __uint_as_float(v[3] & 0xffff0000u), fx);
     return lerp(lerp(x00, x10, fy), lerp(x01, x11, fy), fz);
+}
+
+// Halves 0..11 (chunks 0..5): lane group g walks stencil column 4c + g along z,
+// iz = 4 (h & 1) + j, so consecutive samples differ by the step vector c.
+__device__ __forceinline__ void issue_column_half(gcell_ptr cells, const FusedLevel &L,
+                                                  const PtLevel &q, int h, int g, Pending &p)
+{
+    const int col = 4 * (h >> 1) + g;
+    const float ix = (float)(col % 5), iy = (float)(col / 5), iz0 = (float)(4 * (h & 1));
+    const float bx = q.u0[0] + ix * q.a[0] + iy * q.b[0] + iz0 * q.c[0];
+    const float by = q.u0[1] + ix * q.a[1] + iy * q.b[1] + iz0 * q.c[1];
+    const float bz = q.u0[2] + ix * q.a[2] + iy * q.b[2] + iz0 * q.c[2];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        issue_one(cells, L, fmaf((float)j, q.c[0], bx), fmaf((float)j, q.c[1], by),
+                  fmaf((float)j, q.c[2], bz), p.v[j], p.fx[j], p.fy[j], p.fz[j]);
+}
+
+// Halves 12, 13 (chunk 6) mix directions: lattice coordinates come from a table
+// (column 24 for g = 0; the iz = 8 plane for g = 1..3: rows iy = 0..4 with
+// ix = 0..3, then ix = 4 with iy = 0..3; its last point (4, 4, 8) goes to chunk 7).
+__device__ __forceinline__ void issue_table_half(gcell_ptr cells, const FusedLevel &L,
+                                                 const PtLevel &q, int hh, int g,
+                                                 const float4 *tab, Pending &p)
+{
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float4 o = tab[8 * g + 4 * hh + j];
+        issue_one(cells, L, q.u0[0] + o.x * q.a[0] + o.y * q.b[0] + o.z * q.c[0],
+                  q.u0[1] + o.x * q.a[1] + o.y * q.b[1] + o.z * q.c[1],
+                  q.u0[2] + o.x * q.a[2] + o.y * q.b[2] + o.z * q.c[2], p.v[j], p.fx[j], p.fy[j],
+                  p.fz[j]);
+    }
+}
+
+// Position and light frame of point p; false (and a zero frame) if p is out of
+// range or its inputs are unusable.  Recomputed where needed instead of being kept
+// in registers for the whole kernel.
+__device__ __forceinline__ bool point_frame(const FusedArgs &a, int64_t p, float *x, Frame &fr)
+{
+    bool ok = false;
+    x[0] = x[1] = x[2] = 0.f;
+    if (p < a.P) {
+        x[0] = a.pos[3 * p];
+        x[1] = a.pos[3 * p + 1];
+        x[2] = a.pos[3 * p + 2];
+        ok = isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) &&
+             light_frame(&a.view[3 * p], &a.light[3 * p], fr);
+    }
+    if (!ok) {
+        x[0] = x[1] = x[2] = 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            fr.X[c] = fr.Y[c] = fr.Z[c] = 0.f;
+        fr.gamma = 0.f;
+    }
+    return ok;
+}
+
+__device__ __forceinline__ void point_level(const FusedLevel &L, const float *x, const Frame &fr,
+                                            const float *amin, bool valid, PtLevel &q)
+{
+    const float st = L.step * L.inv_h;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float X = fr.X[c], Y = fr.Y[c], Z = fr.Z[c];
+        // +1: cell coordinates start at the zero border cell
+        q.u0[c] = (x[c] - amin[c]) * L.inv_h + 0.5f - st * (X + Y + Z);
+        q.a[c] = 0.5f * st * X;
+        q.b[c] = 0.5f * st * Y;
+        q.c[c] = 0.5f * st * Z;
+    }
+    if (!valid)
+        q.u0[0] = q.u0[1] = q.u0[2] = -4.f;  // clamps to the zero border cell
 }
 
 __device__ __forceinline__ bf16x8 pack8(const f4 &lo, const f4 &hi)
@@ -83,34 +184,504 @@ __device__ __forceinline__ bf16x8 pack8(const f4 &lo, const f4 &hi)
     return r;
 }
 
-template <int MT, int NT>
-__device__ __forceinline__ void dense(const uint4 *__restrict__ frags, const float *__restrict__ bias,
-                                      int lane, const f4 (&in)[MT][NT], f4 (&out)[MT][NT])
+// Double-buffered staging of weight chunks (MT fragments of 64 x 16 bytes).  Every
+// thread copies a fixed share of entries per chunk; only the last copy is
+// predicated per lane.  Loads past the last chunk land in zeroed padding of the
+// device buffer and are never consumed.
+template <int MT, int NW>
+struct WeightStage {
+    static constexpr int FR = MT * 64;
+    static constexpr int T = 64 * NW;
+    static constexpr int R = (FR + T - 1) / T;
+    static constexpr int SLOT = FR;  // LDS entries per buffer
+    uint4 *buf;          // LDS, 2 * SLOT entries
+    const uint4 *src;    // next chunk to fetch
+    int cur;
+    uint4 pf[R];
+
+    __device__ __forceinline__ const uint4 *chunk() const { return buf + cur * SLOT; }
+    // start fetching the next chunk into registers
+    __device__ __forceinline__ void fetch(int tid)
+    {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            pf[r] = src[tid + r * T];
+    }
+    // publish the fetched chunk and switch buffers (all threads must call)
+    __device__ __forceinline__ void advance(int tid)
+    {
+        uint4 *dst = buf + (cur ^ 1) * SLOT;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (r + 1 < R || tid + r * T < FR)
+                dst[tid + r * T] = pf[r];
+        src += FR;
+        __syncthreads();
+        cur ^= 1;
+    }
+};
+
+template <int MT>
+__device__ __forceinline__ void mfma_chunk(const uint4 *w, int lane, const bf16x8 &B, f4 (&acc)[MT])
+{
+    // keep the fragment reads next to their MFMAs (hoisting all of them above the
+    // gather math costs more registers than the two waves per SIMD can spare)
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+        acc[mt] = mfma_bf16(w[mt * 64 + lane], B, acc[mt]);
+}
+
+// out = relu(Wmat in + bias) for a W-wide input held in accumulator layout.
+template <int MT, int NW>
+__device__ __forceinline__ void dense(WeightStage<MT, NW> &ws, const float *__restrict__ bias,
+                                      int tid, int lane, const f4 (&in)[MT], f4 (&out)[MT])
 {
     constexpr int C2 = (MT + 1) / 2;
     const int g = lane >> 4;
 #pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+        out[mt] = *reinterpret_cast<const f4 *>(bias + 16 * mt + 4 * g);
+#pragma unroll
+    for (int q = 0; q < C2; ++q) {
+        ws.fetch(tid);
+        const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
+        bf16x8 B = pack8(in[2 * q], (2 * q + 1 < MT) ? in[2 * q + 1 < MT ? 2 * q + 1 : 0] : z4);
+        mfma_chunk<MT>(ws.chunk(), lane, B, out);
+        ws.advance(tid);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            out[mt][i] = fmaxf(out[mt][i], 0.f);
+}
+
+template <int MT, int NW>
+__global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const FusedLevel *__restrict__ lvt,
+                                                      const uint4 *__restrict__ frags,
+                                                      const float *__restrict__ vec, int n_chunks)
+{
+    constexpr int C2 = (MT + 1) / 2;   // chunks of a W-wide input
+    constexpr int WP = 16 * MT;        // padded width
+    __shared__ uint4 wbuf[2 * WeightStage<MT, NW>::SLOT];
+    __shared__ float4 plane[32];       // lattice coordinates of halves 12, 13 per (lane group, j)
+    // residual stream o^k of each wave in FP32, accumulator layout [tile][lane]; it
+    // lives in LDS while the first layer runs and comes back for the second
+    __shared__ f4 obuf[NW][MT][64];
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int g = lane >> 4, n = lane & 15;
+    if (tid < 32) {
+        const int gg = tid >> 3, j = tid & 7;
+        if (gg == 0) {
+            plane[tid] = make_float4(4.f, 4.f, (float)j, 0.f);        // column 24, iz = j
+        } else {
+            const int G = 2 * (gg - 1) + (j >> 2), jj = j & 3;        // plane iz = 8
+            plane[tid] = G < 5 ? make_float4((float)jj, (float)G, 8.f, 0.f)
+                               : make_float4(4.f, (float)jj, 8.f, 0.f);
+        }
+    }
+
+    WeightStage<MT, NW> ws;
+    ws.buf = wbuf;
+    ws.src = frags;
+    ws.cur = 1;
+    ws.fetch(tid);
+    ws.advance(tid);  // chunk 0 -> buffer 0 (also orders the plane table)
+
+    const int64_t p = (int64_t)blockIdx.x * (16 * NW) + (tid >> 6) * 16 + n;
+    float gamma;
+    bool valid;
+    {
+        float x[3];
+        Frame fr;
+        valid = point_frame(a, p, x, fr);
+        gamma = fr.gamma;
+    }
+
+    f4 F[MT];
+    const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
+    f4(*Os)[64] = obuf[tid >> 6];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+        Os[mt][lane] = z4;
+
+    // the first two half-chunks of level 1 go out before the loop; later levels
+    // start theirs while the previous level's second layer runs
+    FusedLevel L = lvt[0];
+    gcell_ptr cells = (gcell_ptr)L.cells;
+    PtLevel q;
+    {
+        float x[3];
+        Frame fr;
+        point_frame(a, p, x, fr);
+        point_level(L, x, fr, a.amin, valid, q);
+    }
+    Pending pa, pb;
+    issue_column_half(cells, L, q, 0, g, pa);
+    issue_column_half(cells, L, q, 1, g, pb);
+
+    for (int k = 0; k < a.K; ++k) {
+        const float *b1 = vec + (size_t)k * 2 * WP;
+        const float *b2 = b1 + WP;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+            F[mt] = z4;
+
+        // stencil chunks 0..6, two halves of four samples each, two halves in flight:
+        // step c finishes halves 2c, 2c+1 and issues halves 2c+2, 2c+3
+#pragma unroll 1
+        for (int c = 0; c < 5; ++c) {
+            ws.fetch(tid);
+            f4 lo, hi;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
+            issue_column_half(cells, L, q, 2 * c + 2, g, pa);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
+            issue_column_half(cells, L, q, 2 * c + 3, g, pb);
+            mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
+            ws.advance(tid);
+        }
+        {  // chunk 5: issues the table halves of chunk 6
+            ws.fetch(tid);
+            f4 lo, hi;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
+            issue_table_half(cells, L, q, 0, g, plane, pa);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
+            issue_table_half(cells, L, q, 1, g, plane, pb);
+            mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
+            ws.advance(tid);
+        }
+        {  // chunk 6: issues chunk 7's stencil sample (4, 4, 8)
+            ws.fetch(tid);
+            f4 lo, hi;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
+            issue_one(cells, L, q.u0[0] + 4.f * (q.a[0] + q.b[0]) + 8.f * q.c[0],
+                      q.u0[1] + 4.f * (q.a[1] + q.b[1]) + 8.f * q.c[1],
+                      q.u0[2] + 4.f * (q.a[2] + q.b[2]) + 8.f * q.c[2], pa.v[0], pa.fx[0],
+                      pa.fy[0], pa.fz[0]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
+            mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
+            ws.advance(tid);
+        }
+        // chunk 7: stencil sample (4, 4, 8), gamma, and the odd tile of o^{k-1}
+        {
+            ws.fetch(tid);
+            float s = finish_one(pa.v[0], pa.fx[0], pa.fy[0], pa.fz[0]);
+            f4 lo = f4{g == 0 ? s : 0.f, g == 0 ? gamma : 0.f, 0.f, 0.f};
+            bf16x8 B = pack8(lo, (MT & 1) ? Os[MT - 1][lane] : z4);
+            mfma_chunk<MT>(ws.chunk(), lane, B, F);
+            ws.advance(tid);
+        }
+        // o^{k-1} in pairs of tiles (o^0 = 0: block 1 has no such chunks)
+        if (k > 0) {
+#pragma unroll
+            for (int qq = 0; qq < MT / 2; ++qq) {
+                ws.fetch(tid);
+                mfma_chunk<MT>(ws.chunk(), lane, pack8(Os[2 * qq][lane], Os[2 * qq + 1][lane]), F);
+                ws.advance(tid);
+            }
+        }
+        // the next level's first samples fly while the second layer runs
+        if (k + 1 < a.K) {
+            L = lvt[k + 1];
+            cells = (gcell_ptr)L.cells;
+            float x[3];
+            Frame fr;
+            point_frame(a, p, x, fr);
+            point_level(L, x, fr, a.amin, valid, q);
+            issue_column_half(cells, L, q, 0, g, pa);
+            issue_column_half(cells, L, q, 1, g, pb);
+        }
+        // F1 = relu(. + b1)
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            f4 bb = *reinterpret_cast<const f4 *>(b1 + 16 * mt + 4 * g);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                F[mt][i] = fmaxf(F[mt][i] + bb[i], 0.f);
+        }
+        // o^k = relu(W2 F1 + b2 + o^{k-1}), accumulated in place
+        f4 O[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+            O[mt] = Os[mt][lane] + *reinterpret_cast<const f4 *>(b2 + 16 * mt + 4 * g);
+#pragma unroll
+        for (int qq = 0; qq < C2; ++qq) {
+            ws.fetch(tid);
+            mfma_chunk<MT>(ws.chunk(), lane,
+                           pack8(F[2 * qq], (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0] : z4),
+                           O);
+            ws.advance(tid);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                O[mt][i] = fmaxf(O[mt][i], 0.f);
+            Os[mt][lane] = O[mt];
+        }
+    }
+
+    // trailing layers: H-1 dense W -> W layers, ping-ponging between O and F
+    f4 O[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+        O[mt] = Os[mt][lane];
+    const float *bh = vec + (size_t)a.K * 2 * WP;
+    int h = 0;
+    for (; h + 1 < a.H - 1; h += 2) {
+        dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+        dense<MT, NW>(ws, bh + (size_t)(h + 1) * WP, tid, lane, F, O);
+    }
+    if (h < a.H - 1) {
+        dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+            O[mt] = F[mt];
+    }
+    // final scalar layer in FP32 on the vector ALUs
+    const float *wl = bh + (size_t)(a.H - 1) * WP;
+    const float bl = wl[WP];
+    float acc = 0.f;
+#pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-        f4 b = *reinterpret_cast<const f4 *>(bias + 16 * mt + 4 * g);
+        f4 w = *reinterpret_cast<const f4 *>(wl + 16 * mt + 4 * g);
+        acc += w[0] * O[mt][0] + w[1] * O[mt][1] + w[2] * O[mt][2] + w[3] * O[mt][3];
+    }
+    acc += __shfl_xor(acc, 16, 64);
+    acc += __shfl_xor(acc, 32, 64);
+    if (g == 0 && p < a.P) {
+        float pre = acc + bl;
+        a.out[p] = valid ? fmaxf(pre, 0.f) : 0.f;
+        if (a.pre)
+            a.pre[p] = valid ? pre : 0.f;
+        if (a.flags) {
+            float x[3];
+            Frame fr;
+            point_frame(a, p, x, fr);
+            a.flags[p] = valid ? point_flags(x, fr, a.amin, a.amax, a.inv_mean)
+                               : (uint8_t)DS_FLAG_INVALID;
+        }
+    }
+}
+
+// Register variant: 16 points per wave, two waves per SIMD, the residual stream in
+// registers and no cross-chunk pipelining (each chunk issues its 8 samples and
+// interpolates them); the other wave on the SIMD covers the load latency.
+template <int MT, int NW>
+__global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a, const FusedLevel *__restrict__ lvt,
+                                                          const uint4 *__restrict__ frags,
+                                                          const float *__restrict__ vec)
+{
+    constexpr int C2 = (MT + 1) / 2;
+    constexpr int WP = 16 * MT;
+    __shared__ uint4 wbuf[2 * WeightStage<MT, NW>::SLOT];
+    __shared__ float4 plane[32];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int g = lane >> 4, n = lane & 15;
+    if (tid < 32) {
+        const int gg = tid >> 3, j = tid & 7;
+        if (gg == 0) {
+            plane[tid] = make_float4(4.f, 4.f, (float)j, 0.f);
+        } else {
+            const int G = 2 * (gg - 1) + (j >> 2), jj = j & 3;
+            plane[tid] = G < 5 ? make_float4((float)jj, (float)G, 8.f, 0.f)
+                               : make_float4(4.f, (float)jj, 8.f, 0.f);
+        }
+    }
+    WeightStage<MT, NW> ws;
+    ws.buf = wbuf;
+    ws.src = frags;
+    ws.cur = 1;
+    ws.fetch(tid);
+    ws.advance(tid);
+
+    const int64_t p = (int64_t)blockIdx.x * (16 * NW) + (tid >> 6) * 16 + n;
+    float gamma;
+    bool valid;
+    {
+        float x[3];
+        Frame fr;
+        valid = point_frame(a, p, x, fr);
+        gamma = fr.gamma;
+    }
+    const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
+    f4 O[MT], F[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+        O[mt] = z4;
+
+    for (int k = 0; k < a.K; ++k) {
+        const FusedLevel L = lvt[k];
+        gcell_ptr cells = (gcell_ptr)L.cells;
+        PtLevel q;
+        {
+            float x[3];
+            Frame fr;
+            point_frame(a, p, x, fr);
+            point_level(L, x, fr, a.amin, valid, q);
+        }
+        const float *b1 = vec + (size_t)k * 2 * WP;
+        const float *b2 = b1 + WP;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+            F[mt] = z4;
+#pragma unroll 1
+        for (int c = 0; c < 7; ++c) {
+            ws.fetch(tid);
+            Pending pa, pb;
+            if (c < 6) {
+                issue_column_half(cells, L, q, 2 * c, g, pa);
+                issue_column_half(cells, L, q, 2 * c + 1, g, pb);
+            } else {
+                issue_table_half(cells, L, q, 0, g, plane, pa);
+                issue_table_half(cells, L, q, 1, g, plane, pb);
+            }
+            f4 lo, hi;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
+                hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
+            }
+            mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
+            ws.advance(tid);
+        }
+        {
+            ws.fetch(tid);
+            Pending pa;
+            issue_one(cells, L, q.u0[0] + 4.f * (q.a[0] + q.b[0]) + 8.f * q.c[0],
+                      q.u0[1] + 4.f * (q.a[1] + q.b[1]) + 8.f * q.c[1],
+                      q.u0[2] + 4.f * (q.a[2] + q.b[2]) + 8.f * q.c[2], pa.v[0], pa.fx[0],
+                      pa.fy[0], pa.fz[0]);
+            const float sv = finish_one(pa.v[0], pa.fx[0], pa.fy[0], pa.fz[0]);
+            const f4 lo = f4{g == 0 ? sv : 0.f, g == 0 ? gamma : 0.f, 0.f, 0.f};
+            mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, (MT & 1) ? O[MT - 1] : z4), F);
+            ws.advance(tid);
+        }
+        if (k > 0) {
+#pragma unroll
+            for (int qq = 0; qq < MT / 2; ++qq) {
+                ws.fetch(tid);
+                mfma_chunk<MT>(ws.chunk(), lane, pack8(O[2 * qq], O[2 * qq + 1]), F);
+                ws.advance(tid);
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const f4 bb = *reinterpret_cast<const f4 *>(b1 + 16 * mt + 4 * g);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                F[mt][i] = fmaxf(F[mt][i] + bb[i], 0.f);
+            O[mt] += *reinterpret_cast<const f4 *>(b2 + 16 * mt + 4 * g);
+        }
+#pragma unroll
+        for (int qq = 0; qq < C2; ++qq) {
+            ws.fetch(tid);
+            mfma_chunk<MT>(ws.chunk(), lane,
+                           pack8(F[2 * qq], (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0] : z4),
+                           O);
+            ws.advance(tid);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                O[mt][i] = fmaxf(O[mt][i], 0.f);
+    }
+    const float *bh = vec + (size_t)a.K * 2 * WP;
+    int h = 0;
+    for (; h + 1 < a.H - 1; h += 2) {
+        dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+        dense<MT, NW>(ws, bh + (size_t)(h + 1) * WP, tid, lane, F, O);
+    }
+    if (h < a.H - 1) {
+        dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+            O[mt] = F[mt];
+    }
+    const float *wl = bh + (size_t)(a.H - 1) * WP;
+    const float bl = wl[WP];
+    float acc = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const f4 w = *reinterpret_cast<const f4 *>(wl + 16 * mt + 4 * g);
+        acc += w[0] * O[mt][0] + w[1] * O[mt][1] + w[2] * O[mt][2] + w[3] * O[mt][3];
+    }
+    acc += __shfl_xor(acc, 16, 64);
+    acc += __shfl_xor(acc, 32, 64);
+    if (g == 0 && p < a.P) {
+        const float pre = acc + bl;
+        a.out[p] = valid ? fmaxf(pre, 0.f) : 0.f;
+        if (a.pre)
+            a.pre[p] = valid ? pre : 0.f;
+        if (a.flags) {
+            float x[3];
+            Frame fr;
+            point_frame(a, p, x, fr);
+            a.flags[p] = valid ? point_flags(x, fr, a.amin, a.amax, a.inv_mean)
+                               : (uint8_t)DS_FLAG_INVALID;
+        }
+    }
+}
+
+// Wide variant: one wave per SIMD holding 2 x 16 points, the residual stream and
+// the first-layer accumulators of both point tiles in registers.  Every weight
+// fragment read from LDS feeds two MFMAs, which halves the LDS fragment traffic
+// and (at 128 points per workgroup) the L2 traffic of the weight staging.
+template <int MT, int NT>
+__device__ __forceinline__ void mfma_chunk_nt(const uint4 *w, int lane, const bf16x8 (&B)[NT],
+                                              f4 (&acc)[MT][NT])
+{
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const uint4 a = w[mt * 64 + lane];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+            acc[mt][nt] = mfma_bf16(a, B[nt], acc[mt][nt]);
+    }
+}
+
+template <int MT, int NT, int NW>
+__device__ __forceinline__ void dense_nt(WeightStage<MT, NW> &ws, const float *__restrict__ bias,
+                                         int tid, int lane, const f4 (&in)[MT][NT],
+                                         f4 (&out)[MT][NT])
+{
+    constexpr int C2 = (MT + 1) / 2;
+    const int g = lane >> 4;
+    const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const f4 b = *reinterpret_cast<const f4 *>(bias + 16 * mt + 4 * g);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
             out[mt][nt] = b;
     }
 #pragma unroll
     for (int q = 0; q < C2; ++q) {
+        ws.fetch(tid);
         bf16x8 B[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
-            B[nt] = pack8(in[2 * q][nt], (2 * q + 1 < MT) ? in[2 * q + 1 < MT ? 2 * q + 1 : 0][nt]
-                                                          : f4{0.f, 0.f, 0.f, 0.f});
-        const uint4 *fr = frags + (size_t)(q * MT) * 64 + lane;
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            uint4 a = fr[mt * 64];
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-                out[mt][nt] = mfma_bf16(a, B[nt], out[mt][nt]);
-        }
+            B[nt] = pack8(in[2 * q][nt], (2 * q + 1 < MT) ? in[2 * q + 1 < MT ? 2 * q + 1 : 0][nt] : z4);
+        mfma_chunk_nt<MT, NT>(ws.chunk(), lane, B, out);
+        ws.advance(tid);
     }
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -122,166 +693,168 @@ __device__ __forceinline__ void dense(const uint4 *__restrict__ frags, const flo
 }
 
 template <int MT, int NT>
-__global__ void __launch_bounds__(64 * kWaves) k_fused(FusedArgs a, const FusedLevel *__restrict__ lvt,
+__global__ void __launch_bounds__(256, 1) k_fused_wide(FusedArgs a, const FusedLevel *__restrict__ lvt,
                                                        const uint4 *__restrict__ frags,
                                                        const float *__restrict__ vec)
 {
-    constexpr int C1 = 8 + MT / 2;     // first-layer chunks
-    constexpr int C2 = (MT + 1) / 2;   // chunks of a W-wide input
-    constexpr int WP = 16 * MT;        // padded width
-    __shared__ float4 tab[224];        // lattice coordinates (ix, iy, iz) of stencil point s
-    for (int s = threadIdx.x; s < 224; s += blockDim.x)
-        tab[s] = make_float4((float)(s % 5), (float)((s / 5) % 5), (float)(s / 25), 0.f);
-    __syncthreads();
+    constexpr int NW = 4;
+    constexpr int C2 = (MT + 1) / 2;
+    constexpr int WP = 16 * MT;
+    __shared__ uint4 wbuf[2 * WeightStage<MT, NW>::SLOT];
+    __shared__ float4 plane[32];
 
-    const int lane = threadIdx.x & 63;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
     const int g = lane >> 4, n = lane & 15;
-    const int64_t pbase = ((int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6)) * (16 * NT);
+    if (tid < 32) {
+        const int gg = tid >> 3, j = tid & 7;
+        if (gg == 0) {
+            plane[tid] = make_float4(4.f, 4.f, (float)j, 0.f);
+        } else {
+            const int G = 2 * (gg - 1) + (j >> 2), jj = j & 3;
+            plane[tid] = G < 5 ? make_float4((float)jj, (float)G, 8.f, 0.f)
+                               : make_float4(4.f, (float)jj, 8.f, 0.f);
+        }
+    }
+    WeightStage<MT, NW> ws;
+    ws.buf = wbuf;
+    ws.src = frags;
+    ws.cur = 1;
+    ws.fetch(tid);
+    ws.advance(tid);
 
-    float x[NT][3];
-    Frame fr[NT];
+    const int64_t p0 = ((int64_t)blockIdx.x * NW + (tid >> 6)) * (16 * NT) + n;
+    float gamma[NT];
     bool valid[NT];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-        int64_t p = pbase + 16 * nt + n;
-        valid[nt] = false;
-        if (p < a.P) {
-            x[nt][0] = a.pos[3 * p];
-            x[nt][1] = a.pos[3 * p + 1];
-            x[nt][2] = a.pos[3 * p + 2];
-            valid[nt] = isfinite(x[nt][0]) && isfinite(x[nt][1]) && isfinite(x[nt][2]) &&
-                        light_frame(&a.view[3 * p], &a.light[3 * p], fr[nt]);
-        }
-        if (!valid[nt]) {
-            x[nt][0] = x[nt][1] = x[nt][2] = 0.f;
-#pragma unroll
-            for (int c = 0; c < 3; ++c)
-                fr[nt].X[c] = fr[nt].Y[c] = fr[nt].Z[c] = 0.f;
-            fr[nt].gamma = 0.f;
-        }
+        float x[3];
+        Frame fr;
+        valid[nt] = point_frame(a, p0 + 16 * nt, x, fr);
+        gamma[nt] = fr.gamma;
     }
-
+    const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
     f4 O[MT][NT], F[MT][NT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
-            O[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
+            O[mt][nt] = z4;
+
+    FusedLevel L = lvt[0];
+    gcell_ptr cells = (gcell_ptr)L.cells;
+    PtLevel q[NT];
+    Pending pa[NT], pb[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        float x[3];
+        Frame fr;
+        point_frame(a, p0 + 16 * nt, x, fr);
+        point_level(L, x, fr, a.amin, valid[nt], q[nt]);
+        issue_column_half(cells, L, q[nt], 0, g, pa[nt]);
+        issue_column_half(cells, L, q[nt], 1, g, pb[nt]);
+    }
 
     for (int k = 0; k < a.K; ++k) {
-        const FusedLevel L = lvt[k];
-        PtLevel q[NT];
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            float st = L.step * L.inv_h;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                float X = fr[nt].X[c], Y = fr[nt].Y[c], Z = fr[nt].Z[c];
-                q[nt].u0[c] = (x[nt][c] - a.amin[c]) * L.inv_h - 0.5f - st * (X + Y + Z);
-                q[nt].a[c] = 0.5f * st * X;
-                q[nt].b[c] = 0.5f * st * Y;
-                q[nt].c[c] = 0.5f * st * Z;
-            }
-            if (!valid[nt])
-                q[nt].u0[0] = q[nt].u0[1] = q[nt].u0[2] = -4.f;  // clamps to the zero border
-        }
-        const uint4 *f1 = frags + (size_t)k * (C1 + C2) * MT * 64 + lane;
-        const uint4 *f2 = f1 + (size_t)C1 * MT * 64;
         const float *b1 = vec + (size_t)k * 2 * WP;
         const float *b2 = b1 + WP;
-
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
-                F[mt][nt] = f4{0.f, 0.f, 0.f, 0.f};
-
-        // stencil chunks 0..6: 32 samples per point each
+                F[mt][nt] = z4;
 #pragma unroll 1
         for (int c = 0; c < 7; ++c) {
-            bf16x8 B[NT];
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    float4 o = tab[32 * c + 8 * g + j];
-                    B[nt][j] = (__bf16)sample(L, q[nt], o.x, o.y, o.z);
-                }
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                uint4 af = f1[(c * MT + mt) * 64];
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-                    F[mt][nt] = mfma_bf16(af, B[nt], F[mt][nt]);
-            }
-        }
-        // chunk 7: sample 224, gamma, and the odd tile of o^{k-1}
-        {
+            ws.fetch(tid);
             bf16x8 B[NT];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
-                float s224 = sample(L, q[nt], 4.f, 4.f, 8.f);
-                f4 lo = f4{g == 0 ? s224 : 0.f, g == 0 ? fr[nt].gamma : 0.f, 0.f, 0.f};
-                f4 hi = (MT & 1) ? O[MT - 1][nt] : f4{0.f, 0.f, 0.f, 0.f};
+                f4 lo, hi;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    lo[j] = finish_one(pa[nt].v[j], pa[nt].fx[j], pa[nt].fy[j], pa[nt].fz[j]);
+                if (c < 5)
+                    issue_column_half(cells, L, q[nt], 2 * c + 2, g, pa[nt]);
+                else if (c == 5)
+                    issue_table_half(cells, L, q[nt], 0, g, plane, pa[nt]);
+                else
+                    issue_one(cells, L, q[nt].u0[0] + 4.f * (q[nt].a[0] + q[nt].b[0]) + 8.f * q[nt].c[0],
+                              q[nt].u0[1] + 4.f * (q[nt].a[1] + q[nt].b[1]) + 8.f * q[nt].c[1],
+                              q[nt].u0[2] + 4.f * (q[nt].a[2] + q[nt].b[2]) + 8.f * q[nt].c[2],
+                              pa[nt].v[0], pa[nt].fx[0], pa[nt].fy[0], pa[nt].fz[0]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    hi[j] = finish_one(pb[nt].v[j], pb[nt].fx[j], pb[nt].fy[j], pb[nt].fz[j]);
+                if (c < 5)
+                    issue_column_half(cells, L, q[nt], 2 * c + 3, g, pb[nt]);
+                else if (c == 5)
+                    issue_table_half(cells, L, q[nt], 1, g, plane, pb[nt]);
                 B[nt] = pack8(lo, hi);
+                // one point tile at a time: interleaving both tiles' gathers costs
+                // more registers than the wave has
+                __builtin_amdgcn_sched_barrier(0);
             }
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                uint4 af = f1[(7 * MT + mt) * 64];
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-                    F[mt][nt] = mfma_bf16(af, B[nt], F[mt][nt]);
-            }
+            mfma_chunk_nt<MT, NT>(ws.chunk(), lane, B, F);
+            ws.advance(tid);
         }
-        // o^{k-1} pairs (o^0 = 0, so block 1 skips them)
+        {  // chunk 7: sample (4, 4, 8), gamma, odd tile of o^{k-1}
+            ws.fetch(tid);
+            bf16x8 B[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const float sv = finish_one(pa[nt].v[0], pa[nt].fx[0], pa[nt].fy[0], pa[nt].fz[0]);
+                const f4 lo = f4{g == 0 ? sv : 0.f, g == 0 ? gamma[nt] : 0.f, 0.f, 0.f};
+                B[nt] = pack8(lo, (MT & 1) ? O[MT - 1][nt] : z4);
+            }
+            mfma_chunk_nt<MT, NT>(ws.chunk(), lane, B, F);
+            ws.advance(tid);
+        }
         if (k > 0) {
 #pragma unroll
             for (int qq = 0; qq < MT / 2; ++qq) {
+                ws.fetch(tid);
                 bf16x8 B[NT];
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt)
                     B[nt] = pack8(O[2 * qq][nt], O[2 * qq + 1][nt]);
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt) {
-                    uint4 af = f1[((8 + qq) * MT + mt) * 64];
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt)
-                        F[mt][nt] = mfma_bf16(af, B[nt], F[mt][nt]);
-                }
+                mfma_chunk_nt<MT, NT>(ws.chunk(), lane, B, F);
+                ws.advance(tid);
             }
         }
-        // F1 = relu(. + b1)
+        if (k + 1 < a.K) {
+            L = lvt[k + 1];
+            cells = (gcell_ptr)L.cells;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                float x[3];
+                Frame fr;
+                point_frame(a, p0 + 16 * nt, x, fr);
+                point_level(L, x, fr, a.amin, valid[nt], q[nt]);
+                issue_column_half(cells, L, q[nt], 0, g, pa[nt]);
+                issue_column_half(cells, L, q[nt], 1, g, pb[nt]);
+            }
+        }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-            f4 bb = *reinterpret_cast<const f4 *>(b1 + 16 * mt + 4 * g);
+            const f4 bb = *reinterpret_cast<const f4 *>(b1 + 16 * mt + 4 * g);
+            const f4 cc = *reinterpret_cast<const f4 *>(b2 + 16 * mt + 4 * g);
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
+            for (int nt = 0; nt < NT; ++nt) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
                     F[mt][nt][i] = fmaxf(F[mt][nt][i] + bb[i], 0.f);
-        }
-        // o^k = relu(W2 F1 + b2 + o^{k-1}), accumulated in place
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            f4 bb = *reinterpret_cast<const f4 *>(b2 + 16 * mt + 4 * g);
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-                O[mt][nt] += bb;
+                O[mt][nt] += cc;
+            }
         }
 #pragma unroll
         for (int qq = 0; qq < C2; ++qq) {
+            ws.fetch(tid);
             bf16x8 B[NT];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
-                B[nt] = pack8(F[2 * qq][nt], (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0][nt]
-                                                                : f4{0.f, 0.f, 0.f, 0.f});
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                uint4 af = f2[(qq * MT + mt) * 64];
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-                    O[mt][nt] = mfma_bf16(af, B[nt], O[mt][nt]);
-            }
+                B[nt] = pack8(F[2 * qq][nt], (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0][nt] : z4);
+            mfma_chunk_nt<MT, NT>(ws.chunk(), lane, B, O);
+            ws.advance(tid);
         }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
@@ -292,47 +865,116 @@ __global__ void __launch_bounds__(64 * kWaves) k_fused(FusedArgs a, const FusedL
                     O[mt][nt][i] = fmaxf(O[mt][nt][i], 0.f);
     }
 
-    // trailing layers: H-1 dense W -> W layers, ping-ponging between O and F
-    const uint4 *fh = frags + (size_t)a.K * (C1 + C2) * MT * 64;  // dense() adds the lane
     const float *bh = vec + (size_t)a.K * 2 * WP;
     int h = 0;
     for (; h + 1 < a.H - 1; h += 2) {
-        dense<MT, NT>(fh + (size_t)h * C2 * MT * 64, bh + (size_t)h * WP, lane, O, F);
-        dense<MT, NT>(fh + (size_t)(h + 1) * C2 * MT * 64, bh + (size_t)(h + 1) * WP, lane, F, O);
+        dense_nt<MT, NT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+        dense_nt<MT, NT, NW>(ws, bh + (size_t)(h + 1) * WP, tid, lane, F, O);
     }
     if (h < a.H - 1) {
-        dense<MT, NT>(fh + (size_t)h * C2 * MT * 64, bh + (size_t)h * WP, lane, O, F);
+        dense_nt<MT, NT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
                 O[mt][nt] = F[mt][nt];
     }
-    // final scalar layer in FP32 on the vector ALUs
     const float *wl = bh + (size_t)(a.H - 1) * WP;
     const float bl = wl[WP];
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
-        float s = 0.f;
+        float acc = 0.f;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-            f4 w = *reinterpret_cast<const f4 *>(wl + 16 * mt + 4 * g);
-            f4 v = O[mt][nt];
-            s += w[0] * v[0] + w[1] * v[1] + w[2] * v[2] + w[3] * v[3];
+            const f4 w = *reinterpret_cast<const f4 *>(wl + 16 * mt + 4 * g);
+            acc += w[0] * O[mt][nt][0] + w[1] * O[mt][nt][1] + w[2] * O[mt][nt][2] +
+                   w[3] * O[mt][nt][3];
         }
-        s += __shfl_xor(s, 16, 64);
-        s += __shfl_xor(s, 32, 64);
-        int64_t p = pbase + 16 * nt + n;
+        acc += __shfl_xor(acc, 16, 64);
+        acc += __shfl_xor(acc, 32, 64);
+        const int64_t p = p0 + 16 * nt;
         if (g == 0 && p < a.P) {
-            float pre = s + bl;
+            const float pre = acc + bl;
             a.out[p] = valid[nt] ? fmaxf(pre, 0.f) : 0.f;
             if (a.pre)
                 a.pre[p] = valid[nt] ? pre : 0.f;
-            if (a.flags)
-                a.flags[p] = valid[nt] ? point_flags(x[nt], fr[nt], a.amin, a.amax, a.inv_mean)
+            if (a.flags) {
+                float x[3];
+                Frame fr;
+                point_frame(a, p, x, fr);
+                a.flags[p] = valid[nt] ? point_flags(x, fr, a.amin, a.amax, a.inv_mean)
                                        : (uint8_t)DS_FLAG_INVALID;
+            }
         }
     }
+}
+
+// The fused kernel's gather schedule on its own: every sample is written to its
+// canonical descriptor position [k][ix + 5 iy + 25 iz] (and gamma last), so the
+// BF16 gather path can be checked against the plain descriptor.
+__device__ __forceinline__ int column_sample(int c, int g, int j)
+{
+    const int col = 4 * c + g;
+    return (col % 5) + 5 * (col / 5) + 25 * j;
+}
+
+__global__ void __launch_bounds__(256) k_gather_packed(FusedArgs a, const FusedLevel *__restrict__ lvt,
+                                                       float *__restrict__ z)
+{
+    __shared__ float4 plane[32];
+    const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, n = lane & 15;
+    if (tid < 32) {
+        const int gg = tid >> 3, j = tid & 7;
+        if (gg == 0) {
+            plane[tid] = make_float4(4.f, 4.f, (float)j, 0.f);
+        } else {
+            const int G = 2 * (gg - 1) + (j >> 2), jj = j & 3;
+            plane[tid] = G < 5 ? make_float4((float)jj, (float)G, 8.f, 0.f)
+                               : make_float4(4.f, (float)jj, 8.f, 0.f);
+        }
+    }
+    __syncthreads();
+    const int64_t p = (int64_t)blockIdx.x * 64 + (tid >> 6) * 16 + n;
+    float x[3];
+    Frame fr;
+    const bool valid = point_frame(a, p, x, fr);
+    const int64_t D = 225 * (int64_t)a.K + 1;
+    for (int k = 0; k < a.K; ++k) {
+        const FusedLevel L = lvt[k];
+        gcell_ptr cells = (gcell_ptr)L.cells;
+        PtLevel q;
+        point_level(L, x, fr, a.amin, valid, q);
+        Pending pa;
+        for (int h = 0; h < 12; ++h) {
+            issue_column_half(cells, L, q, h, g, pa);
+            for (int j = 0; j < 4; ++j) {
+                float v = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
+                if (p < a.P)
+                    z[p * D + 225 * k + column_sample(h >> 1, g, 4 * (h & 1) + j)] = v;
+            }
+        }
+        for (int hh = 0; hh < 2; ++hh) {
+            issue_table_half(cells, L, q, hh, g, plane, pa);
+            for (int j = 0; j < 4; ++j) {
+                float v = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
+                float4 o = plane[8 * g + 4 * hh + j];
+                int sidx = (int)o.x + 5 * (int)o.y + 25 * (int)o.z;
+                if (p < a.P)
+                    z[p * D + 225 * k + sidx] = v;
+            }
+        }
+        if (g == 0) {
+            issue_one(cells, L, q.u0[0] + 4.f * (q.a[0] + q.b[0]) + 8.f * q.c[0],
+                      q.u0[1] + 4.f * (q.a[1] + q.b[1]) + 8.f * q.c[1],
+                      q.u0[2] + 4.f * (q.a[2] + q.b[2]) + 8.f * q.c[2], pa.v[0], pa.fx[0],
+                      pa.fy[0], pa.fz[0]);
+            float v = finish_one(pa.v[0], pa.fx[0], pa.fy[0], pa.fz[0]);
+            if (p < a.P)
+                z[p * D + 225 * k + 224] = v;
+        }
+    }
+    if (g == 0 && p < a.P)
+        z[p * D + D - 1] = fr.gamma;
 }
 
 uint16_t bf16_host(float f)
@@ -353,16 +995,71 @@ int pair_slot(int MT, int q, int g, int j)
     return 16 * t + 4 * g + (j & 3);
 }
 
-template <int MT, int NT>
-ds_status launch(hipStream_t s, const ds_net *net, const FusedArgs &a, const FusedLevel *lvt)
+// Chunks in consumption order: block 1 has 8 stencil chunks, later blocks also the
+// o^{k-1} pairs; every block then its second layer; then the dense trailing layers.
+int chunk_count(int MT, int K, int H)
 {
-    int64_t per = (int64_t)kWaves * 16 * NT;
+    int C1 = 8 + MT / 2, C2 = (MT + 1) / 2;
+    return (8 + C2) + (K - 1) * (C1 + C2) + (H - 1) * C2;
+}
+
+int g_waves = 0;  // workgroup size override (waves), 0 = default
+constexpr size_t kFragPad = 2048;  // >= R x threads of every instantiation (entries)
+
+template <int MT, int NW>
+ds_status launch_nw(hipStream_t s, const ds_net *net, const FusedArgs &a, const FusedLevel *lvt)
+{
+    int64_t per = 16 * NW;
     int64_t blocks = (a.P + per - 1) / per;
     if (blocks <= 0)
         return DS_OK;
-    k_fused<MT, NT><<<(unsigned)blocks, 64 * kWaves, 0, s>>>(a, lvt, net->frag_bf16, net->vec);
+    k_fused<MT, NW><<<(unsigned)blocks, 64 * NW, 0, s>>>(a, lvt, net->frag_bf16, net->vec,
+                                                         chunk_count(MT, a.K, a.H));
     DS_HIP(hipGetLastError());
     return DS_OK;
+}
+
+template <int MT>
+ds_status launch_wide(hipStream_t s, const ds_net *net, const FusedArgs &a, const FusedLevel *lvt)
+{
+    constexpr int NT = 2;
+    int64_t per = 4 * 16 * NT;
+    int64_t blocks = (a.P + per - 1) / per;
+    if (blocks <= 0)
+        return DS_OK;
+    k_fused_wide<MT, NT><<<(unsigned)blocks, 256, 0, s>>>(a, lvt, net->frag_bf16, net->vec);
+    DS_HIP(hipGetLastError());
+    return DS_OK;
+}
+
+template <int MT, int NW>
+ds_status launch_reg(hipStream_t s, const ds_net *net, const FusedArgs &a, const FusedLevel *lvt)
+{
+    int64_t per = 16 * NW;
+    int64_t blocks = (a.P + per - 1) / per;
+    if (blocks <= 0)
+        return DS_OK;
+    k_fused_reg<MT, NW><<<(unsigned)blocks, 64 * NW, 0, s>>>(a, lvt, net->frag_bf16, net->vec);
+    DS_HIP(hipGetLastError());
+    return DS_OK;
+}
+
+template <int MT>
+ds_status launch(hipStream_t s, const ds_net *net, const FusedArgs &a, const FusedLevel *lvt)
+{
+    if (g_waves == 0 || g_waves == 14)
+        return launch_reg<MT, 4>(s, net, a, lvt);
+    if (g_waves == 18)
+        return launch_reg<MT, 8>(s, net, a, lvt);
+    if (g_waves == 2)
+        return launch_wide<MT>(s, net, a, lvt);
+    // 0 / 1: wide kernel (one wave per SIMD, 32 points per wave); 4 / 8: narrow
+    // kernel with 16 points per wave and that many waves per workgroup
+    if (g_waves == 4)
+        return launch_nw<MT, 4>(s, net, a, lvt);
+    if (MT < 16 && g_waves == 8)
+        return launch_nw<MT, (MT < 16 ? 8 : 4)>(s, net, a, lvt);
+    return launch_wide<MT>(s, net, a, lvt);
 }
 
 }  // namespace
@@ -407,14 +1104,24 @@ ds_status fused_pack_bf16(ds_net *net, const float *theta)
         ohb[m] = off;
         off += rows;
     }
-    const int64_t nfr = (int64_t)K * (C1 + C2) * MT + (int64_t)(H - 1) * C2 * MT;
+    const int64_t nfr = (int64_t)chunk_count(MT, K, H) * MT;
     std::vector<uint16_t> fr((size_t)nfr * 64 * 8, 0);
-    auto put = [&](int64_t frag, int mt, int g, int r, int j, float v) {
+    auto put = [&](int64_t frag, int g, int r, int j, float v) {
         fr[((size_t)frag * 64 + 16 * g + r) * 8 + j] = bf16_host(v);
     };
+    // stencil sample (index n = ix + 5 iy + 25 iz) held by slot (g, j) of chunk c < 7
+    auto stencil_slot = [](int c, int g, int j) {
+        if (c < 6 || g == 0) {
+            int col = 4 * c + g;               // column (ix, iy), iz = j
+            return (col % 5) + 5 * (col / 5) + 25 * j;
+        }
+        int G = 2 * (g - 1) + (j >> 2), jj = j & 3;  // plane iz = 8
+        return G < 5 ? jj + 5 * G + 25 * 8 : 4 + 5 * jj + 25 * 8;
+    };
+    int64_t frag = 0;
     for (int k = 0; k < K; ++k) {
-        int64_t base1 = (int64_t)k * (C1 + C2) * MT, base2 = base1 + (int64_t)C1 * MT;
-        for (int c = 0; c < C1; ++c)
+        const int c1 = k == 0 ? 8 : C1;
+        for (int c = 0; c < c1; ++c, frag += MT)
             for (int mt = 0; mt < MT; ++mt)
                 for (int g = 0; g < 4; ++g)
                     for (int r = 0; r < 16; ++r) {
@@ -424,26 +1131,26 @@ ds_status fused_pack_bf16(ds_net *net, const float *theta)
                         for (int j = 0; j < 8; ++j) {
                             float v = 0.f;
                             if (c < 7) {
-                                v = theta[oV[k] + (int64_t)row * 226 + 32 * c + 8 * g + j];
+                                v = theta[oV[k] + (int64_t)row * 226 + stencil_slot(c, g, j)];
                             } else if (c == 7) {
-                                if (j < 4) {
-                                    int sidx = 224 + 8 * g + j;
-                                    if (sidx <= 225)
-                                        v = theta[oV[k] + (int64_t)row * 226 + sidx];
-                                } else if ((MT & 1) && k > 0) {
+                                if (g == 0 && j == 0)
+                                    v = theta[oV[k] + (int64_t)row * 226 + 224];   // (4, 4, 8)
+                                else if (g == 0 && j == 1)
+                                    v = theta[oV[k] + (int64_t)row * 226 + 225];   // gamma
+                                else if (j >= 4 && (MT & 1) && k > 0) {
                                     int col = 16 * (MT - 1) + 4 * g + (j - 4);
                                     if (col < W)
                                         v = theta[oW1[k] + (int64_t)row * W + col];
                                 }
-                            } else if (k > 0) {
+                            } else {
                                 int col = pair_slot(MT, c - 8, g, j);
                                 if (col >= 0 && col < W)
                                     v = theta[oW1[k] + (int64_t)row * W + col];
                             }
-                            put(base1 + (int64_t)c * MT + mt, mt, g, r, j, v);
+                            put(frag + mt, g, r, j, v);
                         }
                     }
-        for (int q = 0; q < C2; ++q)
+        for (int q = 0; q < C2; ++q, frag += MT)
             for (int mt = 0; mt < MT; ++mt)
                 for (int g = 0; g < 4; ++g)
                     for (int r = 0; r < 16; ++r) {
@@ -454,13 +1161,12 @@ ds_status fused_pack_bf16(ds_net *net, const float *theta)
                             int col = pair_slot(MT, q, g, j);
                             float v = (col >= 0 && col < W)
                                           ? theta[oW2[k] + (int64_t)row * W + col] : 0.f;
-                            put(base2 + (int64_t)q * MT + mt, mt, g, r, j, v);
+                            put(frag + mt, g, r, j, v);
                         }
                     }
     }
-    for (int h = 0; h < H - 1; ++h) {
-        int64_t base = (int64_t)K * (C1 + C2) * MT + (int64_t)h * C2 * MT;
-        for (int q = 0; q < C2; ++q)
+    for (int h = 0; h < H - 1; ++h)
+        for (int q = 0; q < C2; ++q, frag += MT)
             for (int mt = 0; mt < MT; ++mt)
                 for (int g = 0; g < 4; ++g)
                     for (int r = 0; r < 16; ++r) {
@@ -471,9 +1177,13 @@ ds_status fused_pack_bf16(ds_net *net, const float *theta)
                             int col = pair_slot(MT, q, g, j);
                             float v = (col >= 0 && col < W)
                                           ? theta[ohw[h] + (int64_t)row * W + col] : 0.f;
-                            put(base + (int64_t)q * MT + mt, mt, g, r, j, v);
+                            put(frag + mt, g, r, j, v);
                         }
                     }
+    if (frag != nfr) {
+        set_error("internal: fragment count mismatch (%lld != %lld)", (long long)frag,
+                  (long long)nfr);
+        return DS_ERR_STATE;
     }
     // vectors: per block b1, b2; per dense trailing layer its bias; final weights + bias
     const int64_t nvec = (int64_t)K * 2 * WP + (int64_t)(H - 1) * WP + WP + 4;
@@ -500,8 +1210,11 @@ ds_status fused_pack_bf16(ds_net *net, const float *theta)
         net->vec = nullptr;
     }
     if (!net->frag_bf16) {
-        DS_CHECK(hipMalloc(&net->frag_bf16, (size_t)nfr * 64 * 16) == hipSuccess, DS_ERR_OOM,
-                 "out of device memory for the packed weights");
+        // zeroed tail: the kernel's branch-free staging may read up to one padded
+        // chunk slot past the last chunk
+        DS_CHECK(hipMalloc(&net->frag_bf16, ((size_t)nfr * 64 + kFragPad) * 16) == hipSuccess,
+                 DS_ERR_OOM, "out of device memory for the packed weights");
+        DS_HIP(hipMemset(net->frag_bf16, 0, ((size_t)nfr * 64 + kFragPad) * 16));
         net->frag_count = nfr * 64;
     }
     if (!net->vec) {
@@ -514,16 +1227,31 @@ ds_status fused_pack_bf16(ds_net *net, const float *theta)
     return DS_OK;
 }
 
+ds_status fused_gather_packed(hipStream_t s, const FusedArgs &a, const FusedLevel *lvt, float *z)
+{
+    int64_t blocks = (a.P + 63) / 64;
+    if (blocks <= 0)
+        return DS_OK;
+    k_gather_packed<<<(unsigned)blocks, 256, 0, s>>>(a, lvt, z);
+    DS_HIP(hipGetLastError());
+    return DS_OK;
+}
+
 ds_status fused_predict_bf16(hipStream_t s, const ds_net *net, const FusedArgs &a,
                              const FusedLevel *lvt)
 {
+    static const int env_waves = [] {
+        const char *e = getenv("DS_FUSED_WAVES");
+        return e ? atoi(e) : 0;
+    }();
+    g_waves = env_waves;
     switch (fused_tiles(net->W)) {
-    case 1: return launch<1, 2>(s, net, a, lvt);
-    case 2: return launch<2, 2>(s, net, a, lvt);
-    case 4: return launch<4, 2>(s, net, a, lvt);
-    case 8: return launch<8, 1>(s, net, a, lvt);
-    case 13: return launch<13, 1>(s, net, a, lvt);
-    case 16: return launch<16, 1>(s, net, a, lvt);
+    case 1: return launch<1>(s, net, a, lvt);
+    case 2: return launch<2>(s, net, a, lvt);
+    case 4: return launch<4>(s, net, a, lvt);
+    case 8: return launch<8>(s, net, a, lvt);
+    case 13: return launch<13>(s, net, a, lvt);
+    case 16: return launch<16>(s, net, a, lvt);
     default:
         set_error("width %d is not supported by the fused kernel", net->W);
         return DS_ERR_UNSUPPORTED;

@@ -133,7 +133,7 @@ ds_status fused_pack_bf16(ds_net *net, const float *theta_host);
 struct FusedLevel {
     const uint4 *cells;
     int cx, cy;          // cell-grid dims in x and y (level dims + 2)
-    float hi_x, hi_y, hi_z;  // clamp bounds (level dims as float)
+    float hi_x, hi_y, hi_z;  // clamp bounds of the shifted cell coordinate (level dims + 1)
     float inv_h;
     float step;          // 2^(k-1) / mean
 };
@@ -148,5 +148,6 @@ struct FusedArgs {
 };
 ds_status fused_predict_bf16(hipStream_t s, const ds_net *net, const FusedArgs &a,
                              const FusedLevel *lvt);
+ds_status fused_gather_packed(hipStream_t s, const FusedArgs &a, const FusedLevel *lvt, float *z);
 
 }  // namespace ds

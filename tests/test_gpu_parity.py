@@ -87,6 +87,18 @@ def test_gather_bf16_output(ctx, tiny, tiny_cloud):
     assert e <= 4e-3
 
 
+def test_packed_gather_matches_oracle(ctx, tiny, tiny_cloud):
+    # the fused kernel's gather schedule (BF16 corner cells, BF16 weights) in canonical order
+    pos, view, light = tiny.cuda_inputs()
+    z = ds.ds_gather_packed(ctx.h, tiny_cloud.h, pos, view, light, tiny.K).cpu().numpy()
+    zr, _ = tiny.oracle_z()
+    per = [rel_l2(z[:, k * 225:(k + 1) * 225], zr[:, k * 225:(k + 1) * 225]) for k in range(tiny.K)]
+    bad = np.argmax(np.abs(z - zr).max(0))
+    print("packed gather rel_l2", rel_l2(z, zr), "per level", [f"{e:.1e}" for e in per],
+          "worst column", bad)
+    assert rel_l2(z, zr) <= 4e-3
+
+
 def test_forward_f32_on_oracle_descriptors(ctx, tiny):
     net, theta = _net(ctx, tiny.K, 64)
     zr, _ = tiny.oracle_z()
