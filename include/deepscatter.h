@@ -177,6 +177,32 @@ ds_status ds_predict(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
                      const float *light_dir, int64_t P, float *out, float *pre_out,
                      uint8_t *flags);
 
+/* ---------------------------------------------------------------- training (Sec. 5.2) */
+/* Adam (Kingma and Ba; the paper uses the default learning rate and decay rates:
+ * lr 1e-3, beta1 0.9, beta2 0.999, eps 1e-8) on the network's FP32 master
+ * parameters.  The optimiser owns its moment buffers (FP32, zero-initialised). */
+ds_status ds_adam_create(ds_net *net, float lr, float beta1, float beta2, float eps,
+                         ds_adam **out);
+ds_status ds_adam_destroy(ds_adam *opt);
+/* Number of updates applied so far (host read, no synchronisation). */
+ds_status ds_adam_steps(const ds_adam *opt, int64_t *t);
+
+/* Minibatch loss (1/B) sum_b (log(1 + g(z_b)) - t_b)^2 with t_b = log(1 + L_i) and,
+ * if grad_dev is not NULL, its gradient with respect to every parameter in
+ * canonical order (FP32, device, ds_net_param_count floats).  z is device memory
+ * [B][225K+1] float32 (as ds_gather writes it), target_log1p device [B];
+ * loss_dev (device, 1 float) may be NULL.  Reductions over the batch run in a
+ * fixed order, so results are bitwise reproducible.  1 <= B <= 2^20. */
+ds_status ds_loss_grad(ds_net *net, const float *z, const float *target_log1p, int B,
+                       float *loss_dev, float *grad_dev);
+/* One training step: loss and gradient as ds_loss_grad, one Adam update of the
+ * FP32 master parameters (step count t + 1, bias-corrected moments), then the
+ * matrix-core copy of the weights is refreshed on the device.  Asynchronous;
+ * capturable in a stream graph once the workspace exists (after the first call
+ * with the same B). */
+ds_status ds_train_step(ds_net *net, ds_adam *opt, const float *z, const float *target_log1p,
+                        int B, float *loss_dev);
+
 #ifdef __cplusplus
 }
 #endif

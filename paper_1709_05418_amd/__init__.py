@@ -64,6 +64,11 @@ def lib():
         "ds_gather_packed": (S, [P, P, P, P, P, I64, P]),
         "ds_forward": (S, [P, P, P, I64, P, P]),
         "ds_predict": (S, [P, P, P, I, P, P, P, I64, P, P, P]),
+        "ds_adam_create": (S, [P, F, F, F, F, P]),
+        "ds_adam_destroy": (S, [P]),
+        "ds_adam_steps": (S, [P, P]),
+        "ds_loss_grad": (S, [P, P, P, I, P, P]),
+        "ds_train_step": (S, [P, P, P, P, I, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -250,6 +255,50 @@ def ds_predict(ctx, cloud, net, precision, pos, view_dir, light_dir, out=None, p
     _check(lib().ds_predict(ctx, cloud, net, int(precision), _pts(pos), _pts(view_dir, P),
                             _pts(light_dir, P), P, _ptr(out), _ptr(pre), _ptr(flags)))
     return out, pre, flags
+
+
+def ds_adam_create(net, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    h = C.c_void_p()
+    _check(lib().ds_adam_create(net, float(lr), float(beta1), float(beta2), float(eps),
+                                C.byref(h)))
+    return h
+
+
+def ds_adam_destroy(opt):
+    _check(lib().ds_adam_destroy(opt))
+
+
+def ds_adam_steps(opt) -> int:
+    t = C.c_int64()
+    _check(lib().ds_adam_steps(opt, C.byref(t)))
+    return t.value
+
+
+def _batch(z, target):
+    import torch
+    if z.dtype != torch.float32 or z.dim() != 2 or target.dtype != torch.float32:
+        raise ValueError("z must be float32 (B, 225K+1) and target float32 (B,)")
+    if target.shape[0] != z.shape[0]:
+        raise ValueError("z and target have different batch sizes")
+    return z.shape[0]
+
+
+def ds_loss_grad(net, z, target_log1p, n_params, want_grad=True):
+    import torch
+    B = _batch(z, target_log1p)
+    loss = torch.empty(1, dtype=torch.float32, device=z.device)
+    grad = torch.empty(n_params, dtype=torch.float32, device=z.device) if want_grad else None
+    _check(lib().ds_loss_grad(net, _ptr(z), _ptr(target_log1p), B, _ptr(loss), _ptr(grad)))
+    return loss, grad
+
+
+def ds_train_step(net, opt, z, target_log1p, loss=None):
+    import torch
+    B = _batch(z, target_log1p)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=z.device)
+    _check(lib().ds_train_step(net, opt, _ptr(z), _ptr(target_log1p), B, _ptr(loss)))
+    return loss
 
 
 # ----------------------------------------------------------------------------- owners

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "internal.h"
@@ -189,6 +190,191 @@ ds_status forward_plain(ds_ctx *ctx, const ds_net *net, const float *z, int64_t 
             if (st)
                 return st;
             in = bufs[m & 1];
+        }
+    }
+    return DS_OK;
+}
+
+// Workspace of one minibatch: per block the first-layer pre-activations H, their
+// ReLU F1, the second-layer pre-activations A and the block outputs O; per
+// trailing layer its pre-activations and outputs; gradient scratch.
+struct TrainWs {
+    float *H, *F1, *A, *O, *HA, *HO, *dcur, *dnext, *dh, *dpre, *sq;
+};
+
+ds_status train_ws(ds_net *net, int B, TrainWs &w)
+{
+    const size_t BW = (size_t)B * net->W, K = net->K, Hh = net->H;
+    const size_t need = 4 * K * BW + 2 * Hh * BW + 3 * BW + 2 * (size_t)B;
+    if (net->tws_floats < need) {
+        if (net->tws) {
+            DS_HIP(hipStreamSynchronize(net->ctx->stream));
+            (void)hipFree(net->tws);
+            net->tws = nullptr;
+            net->tws_floats = 0;
+        }
+        DS_HIP(hipMalloc(&net->tws, need * sizeof(float)));
+        net->tws_floats = need;
+    }
+    float *p = net->tws;
+    w.H = p;
+    p += K * BW;
+    w.F1 = p;
+    p += K * BW;
+    w.A = p;
+    p += K * BW;
+    w.O = p;
+    p += K * BW;
+    w.HA = p;
+    p += Hh * BW;
+    w.HO = p;
+    p += Hh * BW;
+    w.dcur = p;
+    p += BW;
+    w.dnext = p;
+    p += BW;
+    w.dh = p;
+    p += BW;
+    w.dpre = p;
+    p += B;
+    w.sq = p;
+    return DS_OK;
+}
+
+#define DS_TRY(expr)          \
+    do {                      \
+        ds_status s_ = (expr); \
+        if (s_)               \
+            return s_;        \
+    } while (0)
+
+// Loss and gradient of a minibatch (FP32): forward keeping pre-activations, then
+// backpropagation layer by layer; every parameter gradient is written exactly once.
+ds_status loss_grad_f32(ds_net *net, const float *z, const float *target, int B, float *loss,
+                        float *grad)
+{
+    hipStream_t s = net->ctx->stream;
+    const int K = net->K, W = net->W, Hn = net->H, D = kStencil * K + 1;
+    const float *th = net->theta;
+    ParamOffsets po = param_offsets(K, W, Hn);
+    TrainWs w;
+    DS_TRY(train_ws(net, B, w));
+    const size_t BW = (size_t)B * W;
+    auto H = [&](int k) { return w.H + k * BW; };
+    auto F1 = [&](int k) { return w.F1 + k * BW; };
+    auto A = [&](int k) { return w.A + k * BW; };
+    auto O = [&](int k) { return w.O + k * BW; };  // output of block k
+    auto HA = [&](int m) { return w.HA + m * BW; };
+    auto HO = [&](int m) { return w.HO + m * BW; };
+    // ---- forward
+    for (int k = 0; k < K; ++k) {
+        GemmArgs g1 = {};
+        g1.M = B;
+        g1.N = W;
+        g1.A1 = z + (int64_t)k * kStencil;
+        g1.lda1 = D;
+        g1.K1 = kStencil;
+        g1.B1 = th + po.V[k];
+        g1.ldb1 = 226;
+        if (k > 0) {
+            g1.A2 = O(k - 1);
+            g1.lda2 = W;
+            g1.K2 = W;
+            g1.B2 = th + po.W1[k];
+            g1.ldb2 = W;
+        }
+        g1.g = z + (int64_t)kStencil * K;
+        g1.ldg = D;
+        g1.gw = th + po.V[k] + 225;
+        g1.ldgw = 226;
+        g1.bias = th + po.b1[k];
+        g1.C = F1(k);
+        g1.ldc = W;
+        g1.pre = H(k);
+        g1.ldpre = W;
+        g1.relu = 1;
+        DS_TRY(gemm_f32(s, g1));
+        GemmArgs g2 = {};
+        g2.M = B;
+        g2.N = W;
+        g2.A1 = F1(k);
+        g2.lda1 = W;
+        g2.K1 = W;
+        g2.B1 = th + po.W2[k];
+        g2.ldb1 = W;
+        g2.bias = th + po.b2[k];
+        if (k > 0) {
+            g2.R = O(k - 1);
+            g2.ldr = W;
+        }
+        g2.C = O(k);
+        g2.ldc = W;
+        g2.pre = A(k);
+        g2.ldpre = W;
+        g2.relu = 1;
+        DS_TRY(gemm_f32(s, g2));
+    }
+    for (int m = 0; m < Hn; ++m) {
+        const bool last = m == Hn - 1;
+        GemmArgs g = {};
+        g.M = B;
+        g.N = last ? 1 : W;
+        g.A1 = m == 0 ? O(K - 1) : HO(m - 1);
+        g.lda1 = W;
+        g.K1 = W;
+        g.B1 = th + po.hw[m];
+        g.ldb1 = W;
+        g.bias = th + po.hb[m];
+        g.C = HO(m);
+        g.ldc = last ? 1 : W;
+        g.pre = HA(m);
+        g.ldpre = last ? 1 : W;
+        g.relu = 1;
+        DS_TRY(gemm_f32(s, g));
+    }
+    // ---- loss and d loss / d (final pre-activation)
+    DS_TRY(loss_head(s, HA(Hn - 1), target, B, w.dpre, w.sq, loss));
+    if (!grad)
+        return DS_OK;
+    // ---- trailing layers, last first; dcur = d loss / d (layer pre-activation)
+    const float *dY = w.dpre;
+    int ldy = 1;
+    for (int m = Hn - 1; m >= 0; --m) {
+        const int rows = m == Hn - 1 ? 1 : W;
+        const float *in = m == 0 ? O(K - 1) : HO(m - 1);
+        if (m < Hn - 1) {
+            DS_TRY(relu_mask(s, w.dcur, W, HA(m), W, B, W));
+            dY = w.dcur;
+            ldy = W;
+        }
+        // dW = dY^T in, db = column sums of dY
+        DS_TRY(gemm_strided(s, {rows, W, B, dY, 1, ldy, in, W, 1, grad + po.hw[m], W, 0}));
+        DS_TRY(colsum(s, dY, ldy, B, rows, grad + po.hb[m]));
+        // d in = dY W
+        DS_TRY(gemm_strided(s, {B, W, rows, dY, ldy, 1, th + po.hw[m], W, 1, w.dnext, W, 0}));
+        std::swap(w.dcur, w.dnext);
+    }
+    // ---- blocks, last first; dcur = d loss / d o^k
+    for (int k = K - 1; k >= 0; --k) {
+        float *da = w.dcur;
+        DS_TRY(relu_mask(s, da, W, A(k), W, B, W));
+        DS_TRY(gemm_strided(s, {W, W, B, da, 1, W, F1(k), W, 1, grad + po.W2[k], W, 0}));
+        DS_TRY(colsum(s, da, W, B, W, grad + po.b2[k]));
+        // dh = (da W2) masked by h > 0
+        DS_TRY(gemm_strided(s, {B, W, W, da, W, 1, th + po.W2[k], W, 1, w.dh, W, 0}));
+        DS_TRY(relu_mask(s, w.dh, W, H(k), W, B, W));
+        // dV over the 225 stencil columns and the gamma column
+        DS_TRY(gemm_strided(s, {W, kStencil, B, w.dh, 1, W, z + (int64_t)k * kStencil, D, 1,
+                                grad + po.V[k], 226, 0}));
+        DS_TRY(gemm_strided(s, {W, 1, B, w.dh, 1, W, z + (int64_t)kStencil * K, D, 1,
+                                grad + po.V[k] + 225, 226, 0}));
+        DS_TRY(colsum(s, w.dh, W, B, W, grad + po.b1[k]));
+        if (k > 0) {
+            DS_TRY(gemm_strided(s, {W, W, B, w.dh, 1, W, O(k - 1), W, 1, grad + po.W1[k], W, 0}));
+            // d o^{k-1} = da + dh W1
+            DS_HIP(hipMemcpyAsync(w.dnext, da, BW * sizeof(float), hipMemcpyDeviceToDevice, s));
+            DS_TRY(gemm_strided(s, {B, W, W, w.dh, W, 1, th + po.W1[k], W, 1, w.dnext, W, 1}));
+            std::swap(w.dcur, w.dnext);
         }
     }
     return DS_OK;
@@ -484,8 +670,12 @@ ds_status ds_net_set_params(ds_net *net, const float *theta_host, int64_t n)
     DS_HIP(hipStreamSynchronize(net->ctx->stream));
     DS_HIP(hipMemcpy(net->theta, theta_host, sizeof(float) * n, hipMemcpyHostToDevice));
     net->has_fp8 = false;
-    if (fused_tiles(net->W) > 0)
-        return fused_pack_bf16(net, theta_host);
+    if (fused_tiles(net->W) > 0) {
+        ds_status st = fused_pack_bf16(net->ctx->stream, net);
+        if (st)
+            return st;
+        DS_HIP(hipStreamSynchronize(net->ctx->stream));
+    }
     return DS_OK;
 }
 
@@ -508,6 +698,9 @@ ds_status ds_net_destroy(ds_net *net)
     (void)hipFree(net->theta);
     (void)hipFree(net->frag_bf16);
     (void)hipFree(net->vec);
+    (void)hipFree(net->fmap);
+    (void)hipFree(net->vmap);
+    (void)hipFree(net->tws);
     delete net;
     return DS_OK;
 }
@@ -640,6 +833,91 @@ ds_status ds_predict(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
     }
     set_error("ds_predict: unknown precision %d", (int)precision);
     return DS_ERR_INVALID_ARG;
+}
+
+// ---------------------------------------------------------------- training (Sec. 5.2)
+ds_status ds_adam_create(ds_net *net, float lr, float beta1, float beta2, float eps, ds_adam **out)
+{
+    DS_CHECK(net && out, DS_ERR_INVALID_ARG, "ds_adam_create: NULL argument");
+    DS_CHECK(lr > 0.f && beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f && eps > 0.f,
+             DS_ERR_INVALID_ARG, "ds_adam_create: bad hyper-parameters");
+    ds_adam *a = new (std::nothrow) ds_adam();
+    DS_CHECK(a, DS_ERR_OOM, "ds_adam_create: out of host memory");
+    a->net = net;
+    a->lr = lr;
+    a->b1 = beta1;
+    a->b2 = beta2;
+    a->eps = eps;
+    const size_t n = (size_t)net->n_params;
+    if (hipMalloc(&a->m, n * 4) != hipSuccess || hipMalloc(&a->v, n * 4) != hipSuccess ||
+        hipMalloc(&a->grad, n * 4) != hipSuccess) {
+        (void)hipFree(a->m);
+        (void)hipFree(a->v);
+        (void)hipFree(a->grad);
+        delete a;
+        set_error("ds_adam_create: out of device memory");
+        return DS_ERR_OOM;
+    }
+    hipStream_t s = net->ctx->stream;
+    if (hipMemsetAsync(a->m, 0, n * 4, s) != hipSuccess ||
+        hipMemsetAsync(a->v, 0, n * 4, s) != hipSuccess) {
+        ds_adam_destroy(a);
+        set_error("ds_adam_create: clearing the moments failed");
+        return DS_ERR_DEVICE;
+    }
+    *out = a;
+    return DS_OK;
+}
+
+ds_status ds_adam_destroy(ds_adam *a)
+{
+    if (!a)
+        return DS_OK;
+    (void)hipStreamSynchronize(a->net->ctx->stream);
+    (void)hipFree(a->m);
+    (void)hipFree(a->v);
+    (void)hipFree(a->grad);
+    delete a;
+    return DS_OK;
+}
+
+ds_status ds_adam_steps(const ds_adam *a, int64_t *t)
+{
+    DS_CHECK(a && t, DS_ERR_INVALID_ARG, "ds_adam_steps: NULL argument");
+    *t = a->t;
+    return DS_OK;
+}
+
+ds_status ds_loss_grad(ds_net *net, const float *z, const float *target_log1p, int B,
+                       float *loss_dev, float *grad_dev)
+{
+    DS_CHECK(net && z && target_log1p, DS_ERR_INVALID_ARG, "ds_loss_grad: NULL argument");
+    DS_CHECK(B >= 1 && B <= (1 << 20), DS_ERR_INVALID_ARG, "ds_loss_grad: batch %d outside 1..2^20",
+             B);
+    return loss_grad_f32(net, z, target_log1p, B, loss_dev, grad_dev);
+}
+
+ds_status ds_train_step(ds_net *net, ds_adam *opt, const float *z, const float *target_log1p,
+                        int B, float *loss_dev)
+{
+    DS_CHECK(net && opt && z && target_log1p, DS_ERR_INVALID_ARG, "ds_train_step: NULL argument");
+    DS_CHECK(opt->net == net, DS_ERR_INVALID_ARG, "ds_train_step: optimiser of another network");
+    DS_CHECK(B >= 1 && B <= (1 << 20), DS_ERR_INVALID_ARG,
+             "ds_train_step: batch %d outside 1..2^20", B);
+    ds_status st = loss_grad_f32(net, z, target_log1p, B, loss_dev, opt->grad);
+    if (st)
+        return st;
+    opt->t += 1;
+    const double c1 = 1.0 - pow((double)opt->b1, (double)opt->t);
+    const double c2 = 1.0 - pow((double)opt->b2, (double)opt->t);
+    st = adam_update(net->ctx->stream, net->theta, opt->m, opt->v, opt->grad, net->n_params,
+                     opt->lr, opt->b1, opt->b2, opt->eps, (float)c1, (float)c2);
+    if (st)
+        return st;
+    net->has_fp8 = false;
+    if (fused_tiles(net->W) > 0)
+        return fused_pack_bf16(net->ctx->stream, net);
+    return DS_OK;
 }
 
 }  // extern "C"

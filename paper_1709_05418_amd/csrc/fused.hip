@@ -977,14 +977,6 @@ __global__ void __launch_bounds__(256) k_gather_packed(FusedArgs a, const FusedL
         z[p * D + D - 1] = fr.gamma;
 }
 
-uint16_t bf16_host(float f)
-{
-    uint32_t u;
-    memcpy(&u, &f, 4);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
 // Input index feeding slot (g, j) of chunk q of a W-wide layer: tiles 2q and 2q+1
 // of the previous output, 4 features per lane group each; -1 if padding.
 int pair_slot(int MT, int q, int g, int j)
@@ -1074,14 +1066,14 @@ int fused_tiles(int W)
     return -1;
 }
 
-// Host packing of the BF16 weight fragments and FP32 vectors in kernel order.
-ds_status fused_pack_bf16(ds_net *net, const float *theta)
+// Packing maps: for every bf16 element of the weight fragments (in kernel order)
+// and every FP32 entry of the bias / final-layer vector, the index of the
+// canonical parameter it holds, or -1 for padding.
+static void build_pack_maps(int K, int W, int H, std::vector<int32_t> &fmap,
+                            std::vector<int32_t> &vmap)
 {
-    const int K = net->K, W = net->W, H = net->H;
     const int MT = fused_tiles(W);
-    DS_CHECK(MT > 0, DS_ERR_UNSUPPORTED, "width %d is not supported by the fused kernel", W);
     const int C1 = 8 + MT / 2, C2 = (MT + 1) / 2, WP = 16 * MT;
-    // parameter offsets (canonical order)
     std::vector<int64_t> oV(K), oW1(K), ob1(K), oW2(K), ob2(K), ohw(H), ohb(H);
     int64_t off = 0;
     for (int k = 0; k < K; ++k) {
@@ -1105,9 +1097,9 @@ ds_status fused_pack_bf16(ds_net *net, const float *theta)
         off += rows;
     }
     const int64_t nfr = (int64_t)chunk_count(MT, K, H) * MT;
-    std::vector<uint16_t> fr((size_t)nfr * 64 * 8, 0);
-    auto put = [&](int64_t frag, int g, int r, int j, float v) {
-        fr[((size_t)frag * 64 + 16 * g + r) * 8 + j] = bf16_host(v);
+    fmap.assign((size_t)nfr * 64 * 8, -1);
+    auto put = [&](int64_t frag, int g, int r, int j, int64_t idx) {
+        fmap[((size_t)frag * 64 + 16 * g + r) * 8 + j] = (int32_t)idx;
     };
     // stencil sample (index n = ix + 5 iy + 25 iz) held by slot (g, j) of chunk c < 7
     auto stencil_slot = [](int c, int g, int j) {
@@ -1125,43 +1117,42 @@ ds_status fused_pack_bf16(ds_net *net, const float *theta)
             for (int mt = 0; mt < MT; ++mt)
                 for (int g = 0; g < 4; ++g)
                     for (int r = 0; r < 16; ++r) {
-                        int row = 16 * mt + r;
+                        const int row = 16 * mt + r;
                         if (row >= W)
                             continue;
                         for (int j = 0; j < 8; ++j) {
-                            float v = 0.f;
+                            int64_t idx = -1;
                             if (c < 7) {
-                                v = theta[oV[k] + (int64_t)row * 226 + stencil_slot(c, g, j)];
+                                idx = oV[k] + (int64_t)row * 226 + stencil_slot(c, g, j);
                             } else if (c == 7) {
                                 if (g == 0 && j == 0)
-                                    v = theta[oV[k] + (int64_t)row * 226 + 224];   // (4, 4, 8)
+                                    idx = oV[k] + (int64_t)row * 226 + 224;  // (4, 4, 8)
                                 else if (g == 0 && j == 1)
-                                    v = theta[oV[k] + (int64_t)row * 226 + 225];   // gamma
+                                    idx = oV[k] + (int64_t)row * 226 + 225;  // gamma
                                 else if (j >= 4 && (MT & 1) && k > 0) {
-                                    int col = 16 * (MT - 1) + 4 * g + (j - 4);
+                                    const int col = 16 * (MT - 1) + 4 * g + (j - 4);
                                     if (col < W)
-                                        v = theta[oW1[k] + (int64_t)row * W + col];
+                                        idx = oW1[k] + (int64_t)row * W + col;
                                 }
                             } else {
-                                int col = pair_slot(MT, c - 8, g, j);
+                                const int col = pair_slot(MT, c - 8, g, j);
                                 if (col >= 0 && col < W)
-                                    v = theta[oW1[k] + (int64_t)row * W + col];
+                                    idx = oW1[k] + (int64_t)row * W + col;
                             }
-                            put(frag + mt, g, r, j, v);
+                            put(frag + mt, g, r, j, idx);
                         }
                     }
         for (int q = 0; q < C2; ++q, frag += MT)
             for (int mt = 0; mt < MT; ++mt)
                 for (int g = 0; g < 4; ++g)
                     for (int r = 0; r < 16; ++r) {
-                        int row = 16 * mt + r;
+                        const int row = 16 * mt + r;
                         if (row >= W)
                             continue;
                         for (int j = 0; j < 8; ++j) {
-                            int col = pair_slot(MT, q, g, j);
-                            float v = (col >= 0 && col < W)
-                                          ? theta[oW2[k] + (int64_t)row * W + col] : 0.f;
-                            put(frag + mt, g, r, j, v);
+                            const int col = pair_slot(MT, q, g, j);
+                            put(frag + mt, g, r, j,
+                                (col >= 0 && col < W) ? oW2[k] + (int64_t)row * W + col : -1);
                         }
                     }
     }
@@ -1170,60 +1161,96 @@ ds_status fused_pack_bf16(ds_net *net, const float *theta)
             for (int mt = 0; mt < MT; ++mt)
                 for (int g = 0; g < 4; ++g)
                     for (int r = 0; r < 16; ++r) {
-                        int row = 16 * mt + r;
+                        const int row = 16 * mt + r;
                         if (row >= W)
                             continue;
                         for (int j = 0; j < 8; ++j) {
-                            int col = pair_slot(MT, q, g, j);
-                            float v = (col >= 0 && col < W)
-                                          ? theta[ohw[h] + (int64_t)row * W + col] : 0.f;
-                            put(frag + mt, g, r, j, v);
+                            const int col = pair_slot(MT, q, g, j);
+                            put(frag + mt, g, r, j,
+                                (col >= 0 && col < W) ? ohw[h] + (int64_t)row * W + col : -1);
                         }
                     }
-    if (frag != nfr) {
-        set_error("internal: fragment count mismatch (%lld != %lld)", (long long)frag,
-                  (long long)nfr);
-        return DS_ERR_STATE;
-    }
     // vectors: per block b1, b2; per dense trailing layer its bias; final weights + bias
     const int64_t nvec = (int64_t)K * 2 * WP + (int64_t)(H - 1) * WP + WP + 4;
-    std::vector<float> vec((size_t)nvec, 0.f);
+    vmap.assign((size_t)nvec, -1);
     for (int k = 0; k < K; ++k)
         for (int r = 0; r < W; ++r) {
-            vec[(size_t)k * 2 * WP + r] = theta[ob1[k] + r];
-            vec[(size_t)k * 2 * WP + WP + r] = theta[ob2[k] + r];
+            vmap[(size_t)k * 2 * WP + r] = (int32_t)(ob1[k] + r);
+            vmap[(size_t)k * 2 * WP + WP + r] = (int32_t)(ob2[k] + r);
         }
     for (int h = 0; h < H - 1; ++h)
         for (int r = 0; r < W; ++r)
-            vec[(size_t)K * 2 * WP + (size_t)h * WP + r] = theta[ohb[h] + r];
-    size_t wl = (size_t)K * 2 * WP + (size_t)(H - 1) * WP;
+            vmap[(size_t)K * 2 * WP + (size_t)h * WP + r] = (int32_t)(ohb[h] + r);
+    const size_t wl = (size_t)K * 2 * WP + (size_t)(H - 1) * WP;
     for (int c = 0; c < W; ++c)
-        vec[wl + c] = theta[ohw[H - 1] + c];
-    vec[wl + WP] = theta[ohb[H - 1]];
+        vmap[wl + c] = (int32_t)(ohw[H - 1] + c);
+    vmap[wl + WP] = (int32_t)ohb[H - 1];
+}
 
-    if (net->frag_bf16 && net->frag_count != nfr * 64) {
-        (void)hipFree(net->frag_bf16);
-        net->frag_bf16 = nullptr;
+namespace {
+__global__ void __launch_bounds__(256) k_pack_frags(const float *__restrict__ theta,
+                                                    const int32_t *__restrict__ map, int64_t n,
+                                                    uint16_t *__restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t idx = map[i];
+        uint32_t u = idx >= 0 ? __float_as_uint(theta[idx]) : 0u;
+        u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+        out[i] = (uint16_t)(u >> 16);
     }
-    if (net->vec && net->vec_count != nvec) {
-        (void)hipFree(net->vec);
-        net->vec = nullptr;
+}
+__global__ void __launch_bounds__(256) k_pack_vec(const float *__restrict__ theta,
+                                                  const int32_t *__restrict__ map, int64_t n,
+                                                  float *__restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t idx = map[i];
+        out[i] = idx >= 0 ? theta[idx] : 0.f;
     }
-    if (!net->frag_bf16) {
-        // zeroed tail: the kernel's branch-free staging may read up to one padded
-        // chunk slot past the last chunk
-        DS_CHECK(hipMalloc(&net->frag_bf16, ((size_t)nfr * 64 + kFragPad) * 16) == hipSuccess,
-                 DS_ERR_OOM, "out of device memory for the packed weights");
-        DS_HIP(hipMemset(net->frag_bf16, 0, ((size_t)nfr * 64 + kFragPad) * 16));
-        net->frag_count = nfr * 64;
-    }
-    if (!net->vec) {
-        DS_CHECK(hipMalloc(&net->vec, (size_t)nvec * 4) == hipSuccess, DS_ERR_OOM,
-                 "out of device memory for the packed biases");
-        net->vec_count = nvec;
-    }
-    DS_HIP(hipMemcpy(net->frag_bf16, fr.data(), fr.size() * 2, hipMemcpyHostToDevice));
-    DS_HIP(hipMemcpy(net->vec, vec.data(), vec.size() * 4, hipMemcpyHostToDevice));
+}
+}  // namespace
+
+// Allocate the fused-kernel operands and their index maps (once per network).
+ds_status fused_prepare(ds_net *net)
+{
+    if (net->frag_bf16)
+        return DS_OK;
+    DS_CHECK(fused_tiles(net->W) > 0, DS_ERR_UNSUPPORTED,
+             "width %d is not supported by the fused kernel", net->W);
+    std::vector<int32_t> fmap, vmap;
+    build_pack_maps(net->K, net->W, net->H, fmap, vmap);
+    const int64_t nf = (int64_t)fmap.size(), nv = (int64_t)vmap.size();
+    // zeroed tail: the kernel's branch-free staging may read past the last chunk
+    const size_t fbytes = (size_t)nf * 2 + kFragPad * 16;
+    DS_CHECK(hipMalloc(&net->frag_bf16, fbytes) == hipSuccess, DS_ERR_OOM,
+             "out of device memory for the packed weights");
+    DS_HIP(hipMemset(net->frag_bf16, 0, fbytes));
+    net->frag_count = nf / 8;
+    DS_CHECK(hipMalloc(&net->vec, (size_t)nv * 4) == hipSuccess, DS_ERR_OOM,
+             "out of device memory for the packed biases");
+    net->vec_count = nv;
+    DS_CHECK(hipMalloc(&net->fmap, (size_t)nf * 4) == hipSuccess, DS_ERR_OOM,
+             "out of device memory for the packing map");
+    DS_CHECK(hipMalloc(&net->vmap, (size_t)nv * 4) == hipSuccess, DS_ERR_OOM,
+             "out of device memory for the packing map");
+    DS_HIP(hipMemcpy(net->fmap, fmap.data(), (size_t)nf * 4, hipMemcpyHostToDevice));
+    DS_HIP(hipMemcpy(net->vmap, vmap.data(), (size_t)nv * 4, hipMemcpyHostToDevice));
+    return DS_OK;
+}
+
+// Refresh the BF16 fragments and the FP32 vectors from the device master parameters.
+ds_status fused_pack_bf16(hipStream_t s, ds_net *net)
+{
+    ds_status st = fused_prepare(net);
+    if (st)
+        return st;
+    const int64_t nf = net->frag_count * 8, nv = net->vec_count;
+    k_pack_frags<<<(unsigned)((nf + 255) / 256 < 8192 ? (nf + 255) / 256 : 8192), 256, 0, s>>>(
+        net->theta, net->fmap, nf, reinterpret_cast<uint16_t *>(net->frag_bf16));
+    k_pack_vec<<<(unsigned)((nv + 255) / 256), 256, 0, s>>>(net->theta, net->vmap, nv, net->vec);
+    DS_HIP(hipGetLastError());
     return DS_OK;
 }
 

@@ -81,7 +81,21 @@ struct ds_net {
     int64_t frag_count = 0;       // number of 16-byte lane entries
     float *vec = nullptr;         // packed biases and the final layer (fp32)
     int64_t vec_count = 0;
+    int32_t *fmap = nullptr;      // parameter index of every fragment element (-1: zero)
+    int32_t *vmap = nullptr;      // parameter index of every vector entry
     bool has_fp8 = false;
+    // training workspace (activations and gradients of one minibatch)
+    float *tws = nullptr;
+    size_t tws_floats = 0;
+};
+
+struct ds_adam {
+    ds_net *net = nullptr;
+    float lr = 1e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    int64_t t = 0;       // steps taken
+    float *m = nullptr;  // first and second moments, FP32
+    float *v = nullptr;
+    float *grad = nullptr;
 };
 
 namespace ds {
@@ -127,9 +141,26 @@ struct GemmArgs {
 };
 ds_status gemm_f32(hipStream_t s, const GemmArgs &a);
 
+// train.hip: C (+)= A B with A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn]
+struct StridedGemm {
+    int M, N, K;
+    const float *A; int64_t sam, sak;
+    const float *B; int64_t sbk, sbn;
+    float *C; int64_t ldc;
+    int accumulate;
+};
+ds_status gemm_strided(hipStream_t s, const StridedGemm &g);
+ds_status relu_mask(hipStream_t s, float *x, int ldx, const float *pre, int ldp, int R, int C);
+ds_status colsum(hipStream_t s, const float *d, int ldd, int R, int C, float *db);
+ds_status loss_head(hipStream_t s, const float *pre, const float *t, int B, float *dpre, float *sq,
+                    float *loss);
+ds_status adam_update(hipStream_t s, float *theta, float *m, float *v, const float *grad,
+                      int64_t n, float lr, float b1, float b2, float eps, float c1, float c2);
+
 // fused.hip
 int fused_tiles(int W);
-ds_status fused_pack_bf16(ds_net *net, const float *theta_host);
+ds_status fused_prepare(ds_net *net);
+ds_status fused_pack_bf16(hipStream_t s, ds_net *net);
 struct FusedLevel {
     const uint4 *cells;
     int cx, cy;          // cell-grid dims in x and y (level dims + 2)

@@ -1,0 +1,111 @@
+"""GPU parity of the training path (Sec. 5.2): loss and gradients against the
+FP64 oracle (itself pinned by central finite differences), one Adam update against
+the oracle's update, and the matrix-core weight copy refreshed after a step."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1709_05418_amd as ds
+from paper_1709_05418_amd import synth
+from _util import Workload, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = ds.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def batch():
+    # descriptors of a 64^3 cloud at K = 6 (the oracle's), targets log(1 + L) in [0, 1]
+    w = Workload(64, 64.0, L=6, K=6, P=300, seed_cloud=2, seed_pts=40)
+    z, _ = w.oracle_z()
+    t = np.log1p(np.random.default_rng(5).random(w.P) * 1.5)
+    return w, z, t
+
+
+def _net(ctx, K, W, seed, z=None, out_bias=0.3):
+    theta = synth.init_params(K, W, 3, seed)
+    theta[-1] = out_bias
+    if z is not None:
+        # shift the output bias so that most samples keep a live output ReLU
+        _, pre = O.forward(theta.astype(np.float64), K, W, 3, z)
+        theta[-1] += np.float32(1.0 - np.percentile(pre, 30))
+    net = ds.Net(ctx, K, W, 3)
+    net.set_params(theta)
+    return net, theta
+
+
+@pytest.mark.parametrize("K,W,B", [(2, 16, 64), (6, 64, 300)])
+def test_loss_and_gradient_match_oracle(ctx, batch, K, W, B):
+    w, z, t = batch
+    zk = np.ascontiguousarray(np.concatenate([z[:B, :225 * K], z[:B, -1:]], axis=1))
+    net, theta = _net(ctx, K, W, seed=K + W)
+    zt = torch.from_numpy(zk.astype(np.float32)).cuda()
+    tt = torch.from_numpy(t[:B].astype(np.float32)).cuda()
+    loss, grad = ds.ds_loss_grad(net.h, zt, tt, net.n_params)
+    lref, gref = O.loss_grad(theta.astype(np.float64), K, W, 3, zk.astype(np.float32).astype(np.float64),
+                             t[:B].astype(np.float32).astype(np.float64))
+    e = rel_l2(grad.cpu().numpy(), gref)
+    print(f"K={K} W={W} B={B}: loss {loss.item():.6f} ref {lref:.6f} grad rel_l2 {e:.2e}")
+    assert loss.item() == pytest.approx(lref, rel=1e-5)
+    assert e <= 1e-5
+    # bitwise reproducible
+    loss2, grad2 = ds.ds_loss_grad(net.h, zt, tt, net.n_params)
+    assert torch.equal(grad, grad2) and torch.equal(loss, loss2)
+    net.close()
+
+
+def test_adam_step_matches_oracle_and_refreshes_bf16(ctx, batch):
+    w, z, t = batch
+    K, W, B = 6, 64, 256
+    zk = z[:B].astype(np.float32)
+    net, theta = _net(ctx, K, W, seed=77, z=z[:B])
+    opt = ds.ds_adam_create(net.h)
+    zt = torch.from_numpy(zk).cuda()
+    tt = torch.from_numpy(t[:B].astype(np.float32)).cuda()
+    ds.ds_train_step(net.h, opt, zt, tt)
+    assert ds.ds_adam_steps(opt) == 1
+    th1 = net.get_params().astype(np.float64)
+    _, gref = O.loss_grad(theta.astype(np.float64), K, W, 3, zk.astype(np.float64),
+                          t[:B].astype(np.float32).astype(np.float64))
+    ref = theta.astype(np.float64).copy()
+    m, v = np.zeros_like(ref), np.zeros_like(ref)
+    O.adam(ref, m, v, gref.copy(), 1)
+    d_gpu, d_ref = th1 - theta, ref - theta
+    # where |g| >> eps (1e-8) the first step is -lr * sign(g) to within rounding; closer
+    # to eps the step depends on |g| itself, which FP32 and FP64 resolve differently
+    big = np.abs(gref) > max(1e-3 * np.abs(gref).max(), 1e-5)
+    assert big.sum() > 1000
+    # the master parameters are FP32: theta - step rounds to the spacing of theta
+    ulp = np.spacing(np.abs(theta).astype(np.float32)).astype(np.float64)
+    assert np.all(np.abs(d_gpu[big] - d_ref[big]) <= 1e-8 + ulp[big])
+    assert np.max(np.abs(d_gpu)) <= 1e-3 * (1 + 1e-5)
+    # the fused BF16 path now predicts with the updated parameters
+    pos, view, light = w.cuda_inputs()
+    cloud = ds.Cloud(ctx, w.density.cuda(), w.sigma_max, w.aabb_min, w.h0, w.L, w.K, w.mips)
+    g, pre, _ = ds.ds_predict(ctx.h, cloud.h, net.h, ds.DS_PREC_BF16, pos, view, light)
+    gr, prer = O.forward(th1, K, W, 3, z)
+    assert rel_l2(pre.cpu().numpy(), prer) <= 2e-2
+    cloud.close()
+    ds.ds_adam_destroy(opt)
+    net.close()
+
+
+def test_training_reduces_the_loss(ctx, batch):
+    w, z, t = batch
+    K, W, B = 6, 64, 256
+    net, theta = _net(ctx, K, W, seed=5, z=z[:B])
+    opt = ds.ds_adam_create(net.h, lr=1e-3)
+    zt = torch.from_numpy(z[:B].astype(np.float32)).cuda()
+    tt = torch.from_numpy(t[:B].astype(np.float32)).cuda()
+    losses = [ds.ds_train_step(net.h, opt, zt, tt).item() for _ in range(60)]
+    print("loss first/last", losses[0], losses[-1])
+    assert losses[-1] < 0.5 * losses[0]
+    ds.ds_adam_destroy(opt)
+    net.close()
