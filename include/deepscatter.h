@@ -20,6 +20,8 @@
  *  - Work is enqueued asynchronously on the context's stream (a caller-owned
  *    hipStream_t passed as void*; NULL is the default stream) unless a call says
  *    it synchronises.  Outputs are valid once the stream reaches that point.
+ *  - A call with an item count of 0 does nothing after its argument checks;
+ *    its per-item arrays may then be NULL.
  *  - Geometry: density grids are [nz][ny][nx] with x fastest; voxel (i, j, k)
  *    occupies aabb_min + [i, i+1] x [j, j+1] x [k, k+1] * voxel_size (world
  *    units).  Points and directions are float32 arrays of shape [P][3].
@@ -202,6 +204,84 @@ ds_status ds_loss_grad(ds_net *net, const float *z, const float *target_log1p, i
  * with the same B). */
 ds_status ds_train_step(ds_net *net, ds_adam *opt, const float *z, const float *target_log1p,
                         int B, float *loss_dev);
+
+/* ---------------------------------------------------------------- Monte Carlo (Sec. 3.2, 4, 5.1) */
+/* The medium of every tracer call is the cloud's base grid: extinction
+ * mu_t = sigma_max * d, trilinear between voxel centres, zero outside the grid,
+ * vacuum outside its box.  Free flights are delta-tracked against the global
+ * majorant sigma_max * max(d); transmittance toward the light is ratio-tracked;
+ * scattering follows Henyey-Greenstein; at each collision the path survives
+ * with probability albedo (absorption by Russian roulette).  Randomness:
+ * Philox4x32-10 with key = seed and counter = (stream id low, high, block, 0),
+ * uniforms are the top 24 bits of each word times 2^-24; stream ids are stated
+ * per call.  Path estimates are FP32; per-record sums are FP64 and reduced in a
+ * fixed order, so every result is bitwise reproducible for a given seed. */
+#define DS_LIGHT_DIRECTIONAL 0 /* a directional light of irradiance E, next-event estimation */
+#define DS_LIGHT_ENVIRONMENT 1 /* a uniform environment of radiance E, counted on escape     */
+
+typedef struct ds_tracer_params {
+    float albedo;         /* survival probability per collision, in [0, 1]              */
+    float g;              /* HG mean cosine, in (-1, 1)                                   */
+    float irradiance;     /* E of the light (DS_LIGHT_DIRECTIONAL) or of the environment */
+    int32_t light_mode;   /* DS_LIGHT_DIRECTIONAL or DS_LIGHT_ENVIRONMENT                 */
+    int32_t max_interactions; /* path length cap in collisions; 0 = unlimited          */
+} ds_tracer_params;
+
+/* The cloud's majorant sigma_max * max(d) (host write). */
+ds_status ds_cloud_majorant(const ds_cloud *cloud, float *majorant);
+
+/* Reference estimates of the indirect in-scattered radiance L_i(x, omega) of
+ * Sec. 4 (light that reaches x after at least one collision, folded with the
+ * phase function; Eq. (1) without its single-scattering term) for P records:
+ * per record the mean of spp path estimates (mean_out, device, P doubles) and
+ * the variance of that mean (var_out, device, P doubles, may be NULL).  Path s
+ * of record i uses stream id i * 2^20 + s.  Records with an unusable direction
+ * get 0.  In DS_LIGHT_DIRECTIONAL mode light_dir is omega_l per record; in
+ * DS_LIGHT_ENVIRONMENT mode it is ignored but must still be a valid pointer.
+ * 1 <= spp <= 2^20, P < 2^40.  Library-owned workspace: 16 * P * ceil(spp/256) bytes. */
+ds_status ds_trace_li(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params *params,
+                      const float *pos, const float *view_dir, const float *light_dir, int64_t P,
+                      int spp, uint64_t seed, double *mean_out, double *var_out);
+
+/* Training-record configurations (Sec. 5.1): per record a direction d uniform on
+ * the sphere, a ray origin uniform over the disc of the box's bounding sphere
+ * orthogonal to d, and a delta-tracked free flight along d into the cloud,
+ * retried from scratch on escape (at most 10^6 tries; a record that never
+ * collides gets NaN positions).  Writes pos (the collision), view_dir = -d and
+ * a light direction uniform on the sphere (device, [N][3] float32 each) and,
+ * if not NULL, the number of tries (device, N int32).  Record i uses stream id i. */
+ds_status ds_sample_records(ds_ctx *ctx, const ds_cloud *cloud, int64_t N, uint64_t seed,
+                            float *pos, float *view_dir, float *light_dir, int32_t *attempts);
+
+/* Path-traced pixels (Sec. 4.4 with the network replaced by path estimates):
+ * along each camera ray o + t d (device, [N][3] float32 each) a delta-tracked
+ * first collision x (escaping rays see 0, or E in DS_LIGHT_ENVIRONMENT mode),
+ * then albedo times the in-scattered radiance at x toward -d: direct single
+ * scattering by next-event estimation plus L_i for the directional light
+ * light_dir (host, 3 floats); all in-scattered environment light in the other
+ * mode.  Per pixel the mean of spp samples and the variance of the mean
+ * (device doubles; var_out may be NULL).  Sample s of pixel i uses stream id
+ * i * 2^20 + s.  Same limits and workspace as ds_trace_li. */
+ds_status ds_render_mc(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params *params,
+                       const float light_dir[3], const float *ray_o, const float *ray_d,
+                       int64_t N, int spp, uint64_t seed, double *mean_out, double *var_out);
+
+/* One camera sample per ray for the network renderer (Sec. 4.4): the
+ * delta-tracked first collision along o + t d (pos, device [N][3]), the view
+ * direction there (view_dir = -d), the direct single scattering albedo * p *
+ * T * E from the directional light light_dir (host, 3 floats) by one
+ * ratio-tracking estimate (direct, device N floats), and hit (device N bytes,
+ * 1 where the ray collided).  Rays that escape get hit = 0 and zero outputs.
+ * Ray i uses stream id i * 2^20 + sample. */
+ds_status ds_first_hits(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params *params,
+                        const float light_dir[3], const float *ray_o, const float *ray_d,
+                        int64_t N, uint64_t seed, uint64_t sample, float *pos, float *view_dir,
+                        float *direct, uint8_t *hit);
+
+/* The tracer's random generator itself: for n (counter, key) pairs
+ * ctr_key (device, [n][6] uint32: c0 c1 c2 c3 k0 k1) the Philox4x32-10 block
+ * (device out, [n][4] uint32), as defined by Salmon et al., SC'11. */
+ds_status ds_philox4x32_10(ds_ctx *ctx, const uint32_t *ctr_key, int64_t n, uint32_t *out);
 
 #ifdef __cplusplus
 }

@@ -24,6 +24,7 @@ DS_OK = 0
 DS_F32, DS_BF16 = 0, 1
 DS_PREC_F32, DS_PREC_BF16, DS_PREC_FP8 = 0, 1, 2
 DS_FLAG_INVALID, DS_FLAG_OUTSIDE, DS_FLAG_FALLBACK = 1, 2, 4
+DS_LIGHT_DIRECTIONAL, DS_LIGHT_ENVIRONMENT = 0, 1
 STENCIL_N = 225
 
 _lib = None
@@ -69,6 +70,12 @@ def lib():
         "ds_adam_steps": (S, [P, P]),
         "ds_loss_grad": (S, [P, P, P, I, P, P]),
         "ds_train_step": (S, [P, P, P, P, I, P]),
+        "ds_cloud_majorant": (S, [P, P]),
+        "ds_trace_li": (S, [P, P, P, P, P, P, I64, I, C.c_uint64, P, P]),
+        "ds_sample_records": (S, [P, P, I64, C.c_uint64, P, P, P, P]),
+        "ds_render_mc": (S, [P, P, P, P, P, P, I64, I, C.c_uint64, P, P]),
+        "ds_first_hits": (S, [P, P, P, P, P, P, I64, C.c_uint64, C.c_uint64, P, P, P, P]),
+        "ds_philox4x32_10": (S, [P, P, I64, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -80,6 +87,17 @@ def lib():
 
 class _NetDesc(C.Structure):
     _fields_ = [("K", C.c_int), ("W", C.c_int), ("H", C.c_int)]
+
+
+class TracerParams(C.Structure):
+    """ds_tracer_params: albedo, HG g, light irradiance (or environment radiance),
+    light_mode (DS_LIGHT_DIRECTIONAL / DS_LIGHT_ENVIRONMENT), max_interactions (0: none)."""
+    _fields_ = [("albedo", C.c_float), ("g", C.c_float), ("irradiance", C.c_float),
+                ("light_mode", C.c_int32), ("max_interactions", C.c_int32)]
+
+    def __init__(self, albedo=0.999, g=0.85, irradiance=1.0, light_mode=0, max_interactions=0):
+        super().__init__(float(albedo), float(g), float(irradiance), int(light_mode),
+                         int(max_interactions))
 
 
 def _check(st):
@@ -299,6 +317,77 @@ def ds_train_step(net, opt, z, target_log1p, loss=None):
         loss = torch.empty(1, dtype=torch.float32, device=z.device)
     _check(lib().ds_train_step(net, opt, _ptr(z), _ptr(target_log1p), B, _ptr(loss)))
     return loss
+
+
+def ds_cloud_majorant(cloud) -> float:
+    m = C.c_float()
+    _check(lib().ds_cloud_majorant(cloud, C.byref(m)))
+    return m.value
+
+
+def _f64(n, device):
+    import torch
+    return torch.empty(n, dtype=torch.float64, device=device)
+
+
+def ds_trace_li(ctx, cloud, params: TracerParams, pos, view_dir, light_dir, spp, seed,
+                want_var=True):
+    """Per record: (mean of spp path estimates of L_i, variance of that mean), FP64."""
+    P = pos.shape[0]
+    mean = _f64(P, pos.device)
+    var = _f64(P, pos.device) if want_var else None
+    _check(lib().ds_trace_li(ctx, cloud, C.byref(params), _pts(pos), _pts(view_dir, P),
+                             _pts(light_dir, P), P, int(spp), int(seed), _ptr(mean), _ptr(var)))
+    return mean, var
+
+
+def ds_sample_records(ctx, cloud, N, seed, device="cuda", want_attempts=True):
+    import torch
+    pos = torch.empty((N, 3), dtype=torch.float32, device=device)
+    view = torch.empty((N, 3), dtype=torch.float32, device=device)
+    light = torch.empty((N, 3), dtype=torch.float32, device=device)
+    att = torch.empty(N, dtype=torch.int32, device=device) if want_attempts else None
+    _check(lib().ds_sample_records(ctx, cloud, int(N), int(seed), _ptr(pos), _ptr(view),
+                                   _ptr(light), _ptr(att)))
+    return pos, view, light, att
+
+
+def ds_render_mc(ctx, cloud, params: TracerParams, light_dir, ray_o, ray_d, spp, seed,
+                 want_var=True):
+    N = ray_o.shape[0]
+    ld = (C.c_float * 3)(*[float(v) for v in light_dir])
+    mean = _f64(N, ray_o.device)
+    var = _f64(N, ray_o.device) if want_var else None
+    _check(lib().ds_render_mc(ctx, cloud, C.byref(params), ld, _pts(ray_o), _pts(ray_d, N), N,
+                              int(spp), int(seed), _ptr(mean), _ptr(var)))
+    return mean, var
+
+
+def ds_first_hits(ctx, cloud, params: TracerParams, light_dir, ray_o, ray_d, seed, sample=0):
+    import torch
+    N = ray_o.shape[0]
+    ld = (C.c_float * 3)(*[float(v) for v in light_dir])
+    dev = ray_o.device
+    pos = torch.empty((N, 3), dtype=torch.float32, device=dev)
+    view = torch.empty((N, 3), dtype=torch.float32, device=dev)
+    direct = torch.empty(N, dtype=torch.float32, device=dev)
+    hit = torch.empty(N, dtype=torch.uint8, device=dev)
+    _check(lib().ds_first_hits(ctx, cloud, C.byref(params), ld, _pts(ray_o), _pts(ray_d, N), N,
+                               int(seed), int(sample), _ptr(pos), _ptr(view), _ptr(direct),
+                               _ptr(hit)))
+    return pos, view, direct, hit
+
+
+def ds_philox4x32_10(ctx, ctr_key):
+    """ctr_key: int32/uint32 device tensor (n, 6) = c0 c1 c2 c3 k0 k1; returns (n, 4) words
+    (as int32 bit patterns)."""
+    import torch
+    if ctr_key.dim() != 2 or ctr_key.shape[1] != 6 or ctr_key.element_size() != 4:
+        raise ValueError("ctr_key must be a 32-bit (n, 6) tensor")
+    n = ctr_key.shape[0]
+    out = torch.empty((n, 4), dtype=torch.int32, device=ctr_key.device)
+    _check(lib().ds_philox4x32_10(ctx, _ptr(ctr_key), n, _ptr(out)))
+    return out
 
 
 # ----------------------------------------------------------------------------- owners

@@ -1,6 +1,8 @@
 // Host side of the C ABI: argument validation, object lifetime, device memory and
 // kernel dispatch.  Every entry point returns a status and never throws.
 #include <math.h>
+
+#include <cmath>
 #include <stdarg.h>
 #include <stdio.h>
 #include <string.h>
@@ -27,6 +29,20 @@ ds_status hip_fail(hipError_t e, const char *what)
 {
     set_error("%s: %s", what, hipGetErrorString(e));
     return e == hipErrorOutOfMemory ? DS_ERR_OOM : DS_ERR_DEVICE;
+}
+
+bool unit_host(const float *v, float *u)
+{
+    double a = v[0], b = v[1], c = v[2];
+    if (!(std::isfinite(a) && std::isfinite(b) && std::isfinite(c)))
+        return false;
+    const double l = std::sqrt(a * a + b * b + c * c);
+    if (!(l > 0.0))
+        return false;
+    u[0] = (float)(a / l);
+    u[1] = (float)(b / l);
+    u[2] = (float)(c / l);
+    return true;
 }
 
 namespace {
@@ -524,6 +540,9 @@ ds_status ds_cloud_create(ds_ctx *ctx, const void *density_dev, ds_dtype dtype, 
     st = cloud_pack(ctx->stream, c->pyr, n_levels, c->lv, c->cells);
     if (st)
         return fail(st);
+    st = tracer_prepare(c, density_dev, dtype);
+    if (st)
+        return fail(st);
     // device-side per-stencil-level tables
     std::vector<GatherLevel> gl(K);
     std::vector<FusedLevel> fl(K);
@@ -611,6 +630,7 @@ ds_status ds_cloud_destroy(ds_cloud *c)
     (void)hipFree(c->pyr);
     (void)hipFree(c->cells);
     (void)hipFree(c->tables);
+    (void)hipFree(c->mu);
     delete c;
     return DS_OK;
 }
@@ -918,6 +938,129 @@ ds_status ds_train_step(ds_net *net, ds_adam *opt, const float *z, const float *
     if (fused_tiles(net->W) > 0)
         return fused_pack_bf16(net->ctx->stream, net);
     return DS_OK;
+}
+
+// ---------------------------------------------------------------- Monte Carlo
+static ds_status tracer_params(const ds_tracer_params *p, TracerParams &tp, const char *fn)
+{
+    DS_CHECK(p, DS_ERR_INVALID_ARG, "%s: params is NULL", fn);
+    DS_CHECK(p->albedo >= 0.f && p->albedo <= 1.f, DS_ERR_INVALID_ARG,
+             "%s: albedo %g outside [0, 1]", fn, (double)p->albedo);
+    DS_CHECK(p->g > -1.f && p->g < 1.f, DS_ERR_INVALID_ARG, "%s: g %g outside (-1, 1)", fn,
+             (double)p->g);
+    DS_CHECK(std::isfinite(p->irradiance), DS_ERR_INVALID_ARG, "%s: irradiance not finite", fn);
+    DS_CHECK(p->light_mode == DS_LIGHT_DIRECTIONAL || p->light_mode == DS_LIGHT_ENVIRONMENT,
+             DS_ERR_INVALID_ARG, "%s: unknown light_mode %d", fn, p->light_mode);
+    DS_CHECK(p->max_interactions >= 0, DS_ERR_INVALID_ARG, "%s: max_interactions < 0", fn);
+    tp.albedo = p->albedo;
+    tp.g = p->g;
+    tp.irradiance = p->irradiance;
+    tp.light_mode = p->light_mode;
+    tp.max_interactions = p->max_interactions;
+    return DS_OK;
+}
+
+ds_status ds_cloud_majorant(const ds_cloud *c, float *majorant)
+{
+    DS_CHECK(c && majorant, DS_ERR_INVALID_ARG, "ds_cloud_majorant: NULL argument");
+    *majorant = c->majorant;
+    return DS_OK;
+}
+
+ds_status ds_trace_li(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params *params,
+                      const float *pos, const float *view_dir, const float *light_dir, int64_t P,
+                      int spp, uint64_t seed, double *mean_out, double *var_out)
+{
+    DS_CHECK(ctx && cloud && (P == 0 || (pos && view_dir && light_dir && mean_out)),
+             DS_ERR_INVALID_ARG, "ds_trace_li: NULL argument");
+    DS_CHECK(P >= 0 && P < (int64_t(1) << 40), DS_ERR_INVALID_ARG, "ds_trace_li: P out of range");
+    DS_CHECK(spp >= 1 && spp <= (1 << 20), DS_ERR_INVALID_ARG,
+             "ds_trace_li: spp %d outside [1, 2^20]", spp);
+    TracerParams tp;
+    ds_status st = tracer_params(params, tp, "ds_trace_li");
+    if (st || P == 0)
+        return st;
+    DS_HIP(hipSetDevice(ctx->device));
+    st = ensure_ws(ctx, sizeof(double) * 2 * (size_t)P * tracer_blocks(spp));
+    if (st)
+        return st;
+    return tracer_li(ctx->stream, cloud, tp, pos, view_dir, light_dir, P, spp, seed,
+                     static_cast<double *>(ctx->ws), mean_out, var_out);
+}
+
+ds_status ds_sample_records(ds_ctx *ctx, const ds_cloud *cloud, int64_t N, uint64_t seed,
+                            float *pos, float *view_dir, float *light_dir, int32_t *attempts)
+{
+    DS_CHECK(ctx && cloud && (N == 0 || (pos && view_dir && light_dir)), DS_ERR_INVALID_ARG,
+             "ds_sample_records: NULL argument");
+    DS_CHECK(N >= 0 && N < (int64_t(1) << 40), DS_ERR_INVALID_ARG,
+             "ds_sample_records: N out of range");
+    if (N == 0)
+        return DS_OK;
+    DS_HIP(hipSetDevice(ctx->device));
+    return tracer_records(ctx->stream, cloud, N, seed, pos, view_dir, light_dir, attempts);
+}
+
+ds_status ds_render_mc(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params *params,
+                       const float light_dir[3], const float *ray_o, const float *ray_d,
+                       int64_t N, int spp, uint64_t seed, double *mean_out, double *var_out)
+{
+    DS_CHECK(ctx && cloud && light_dir && (N == 0 || (ray_o && ray_d && mean_out)),
+             DS_ERR_INVALID_ARG, "ds_render_mc: NULL argument");
+    DS_CHECK(N >= 0 && N < (int64_t(1) << 40), DS_ERR_INVALID_ARG, "ds_render_mc: N out of range");
+    DS_CHECK(spp >= 1 && spp <= (1 << 20), DS_ERR_INVALID_ARG,
+             "ds_render_mc: spp %d outside [1, 2^20]", spp);
+    TracerParams tp;
+    ds_status st = tracer_params(params, tp, "ds_render_mc");
+    if (st)
+        return st;
+    float l[3];
+    DS_CHECK(unit_host(light_dir, l), DS_ERR_INVALID_ARG, "ds_render_mc: unusable light_dir");
+    if (N == 0)
+        return DS_OK;
+    DS_HIP(hipSetDevice(ctx->device));
+    st = ensure_ws(ctx, sizeof(double) * 2 * (size_t)N * tracer_blocks(spp));
+    if (st)
+        return st;
+    return tracer_render(ctx->stream, cloud, tp, light_dir, ray_o, ray_d, N, spp, seed,
+                         static_cast<double *>(ctx->ws), mean_out, var_out);
+}
+
+ds_status ds_first_hits(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params *params,
+                        const float light_dir[3], const float *ray_o, const float *ray_d,
+                        int64_t N, uint64_t seed, uint64_t sample, float *pos, float *view_dir,
+                        float *direct, uint8_t *hit)
+{
+    DS_CHECK(ctx && cloud && light_dir &&
+                 (N == 0 || (ray_o && ray_d && pos && view_dir && direct && hit)),
+             DS_ERR_INVALID_ARG, "ds_first_hits: NULL argument");
+    DS_CHECK(N >= 0 && N < (int64_t(1) << 40), DS_ERR_INVALID_ARG,
+             "ds_first_hits: N out of range");
+    DS_CHECK(sample < (uint64_t(1) << 20), DS_ERR_INVALID_ARG,
+             "ds_first_hits: sample index must be below 2^20");
+    TracerParams tp;
+    ds_status st = tracer_params(params, tp, "ds_first_hits");
+    if (st)
+        return st;
+    float l[3];
+    DS_CHECK(unit_host(light_dir, l), DS_ERR_INVALID_ARG, "ds_first_hits: unusable light_dir");
+    if (N == 0)
+        return DS_OK;
+    DS_HIP(hipSetDevice(ctx->device));
+    return tracer_first_hits(ctx->stream, cloud, tp, light_dir, ray_o, ray_d, N, seed, sample, pos,
+                             view_dir, direct, hit);
+}
+
+ds_status ds_philox4x32_10(ds_ctx *ctx, const uint32_t *ctr_key, int64_t n, uint32_t *out)
+{
+    DS_CHECK(ctx && (n == 0 || (ctr_key && out)), DS_ERR_INVALID_ARG,
+             "ds_philox4x32_10: NULL argument");
+    DS_CHECK(n >= 0 && n < (int64_t(1) << 40), DS_ERR_INVALID_ARG,
+             "ds_philox4x32_10: n out of range");
+    if (n == 0)
+        return DS_OK;
+    DS_HIP(hipSetDevice(ctx->device));
+    return philox_blocks(ctx->stream, ctr_key, n, out);
 }
 
 }  // extern "C"

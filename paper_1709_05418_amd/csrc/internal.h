@@ -69,6 +69,8 @@ struct ds_cloud {
     uint4 *cells = nullptr;    // corner-packed bf16 levels (8 corners per cell)
     int64_t n_cells = 0;
     void *tables = nullptr;    // device: GatherLevel[K] then FusedLevel[K]
+    float *mu = nullptr;       // extinction sigma_max * d on the base grid (tracer medium)
+    float majorant = 0.f;      // sigma_max * max(d)
 };
 
 struct ds_net {
@@ -180,5 +182,27 @@ struct FusedArgs {
 ds_status fused_predict_bf16(hipStream_t s, const ds_net *net, const FusedArgs &a,
                              const FusedLevel *lvt);
 ds_status fused_gather_packed(hipStream_t s, const FusedArgs &a, const FusedLevel *lvt, float *z);
+
+// tracer.hip
+struct TracerParams {
+    float albedo, g, irradiance;
+    int light_mode, max_interactions;
+};
+bool unit_host(const float *v, float *u);  // normalise a host 3-vector; false if unusable
+ds_status tracer_prepare(ds_cloud *c, const void *density, ds_dtype dt);
+int tracer_blocks(int spp);  // partial sums per record
+ds_status tracer_li(hipStream_t s, const ds_cloud *c, const TracerParams &tp, const float *pos,
+                    const float *view, const float *light, int64_t P, int spp, uint64_t seed,
+                    double *partial, double *mean, double *var);
+ds_status tracer_records(hipStream_t s, const ds_cloud *c, int64_t N, uint64_t seed, float *pos,
+                         float *view, float *light, int32_t *attempts);
+ds_status tracer_render(hipStream_t s, const ds_cloud *c, const TracerParams &tp,
+                        const float *light_dir, const float *ray_o, const float *ray_d, int64_t N,
+                        int spp, uint64_t seed, double *partial, double *mean, double *var);
+ds_status tracer_first_hits(hipStream_t s, const ds_cloud *c, const TracerParams &tp,
+                            const float *light_dir, const float *ray_o, const float *ray_d,
+                            int64_t N, uint64_t seed, uint64_t sample, float *pos, float *view,
+                            float *direct, uint8_t *hit);
+ds_status philox_blocks(hipStream_t s, const uint32_t *ctr_key, int64_t n, uint32_t *out);
 
 }  // namespace ds

@@ -1,0 +1,626 @@
+// Monte Carlo transport in the cloud (Sec. 3.2 Eq. (1), Sec. 4, Sec. 4.4, Sec. 5.1):
+// delta tracking against a global majorant, ratio-tracked transmittance toward the
+// light, Henyey-Greenstein scattering, absorption by Russian roulette.  One thread
+// per path; per-record sums of the path estimates are accumulated in FP64 and
+// reduced in a fixed order, so results are reproducible bit for bit.
+#include <math.h>
+
+#include "internal.h"
+
+namespace ds {
+namespace {
+
+constexpr int kPaths = 256;                 // paths per block
+constexpr int64_t kMaxSteps = 1ll << 26;    // hard bound on tentative collisions per path
+
+// ------------------------------------------------------------------ Philox4x32-10
+// Counter-based generator of Salmon et al. (SC'11): 10 rounds of two 32x32->64-bit
+// multiplications mixing the four counter words, with a Weyl-sequence key schedule.
+struct Rng {
+    uint32_t k0, k1;        // key = seed
+    uint32_t c0, c1, c2, c3; // counter = (stream id lo, hi, block, 0)
+    uint32_t buf[4];
+    int used;
+
+    __device__ void init(uint64_t seed, uint64_t id)
+    {
+        k0 = (uint32_t)seed;
+        k1 = (uint32_t)(seed >> 32);
+        c0 = (uint32_t)id;
+        c1 = (uint32_t)(id >> 32);
+        c2 = 0;
+        c3 = 0;
+        used = 4;
+    }
+    __device__ void refill()
+    {
+        uint32_t x0 = c0, x1 = c1, x2 = c2, x3 = c3, a = k0, b = k1;
+#pragma unroll
+        for (int r = 0; r < 10; ++r) {
+            const uint32_t lo0 = 0xD2511F53u * x0, hi0 = __umulhi(0xD2511F53u, x0);
+            const uint32_t lo1 = 0xCD9E8D57u * x2, hi1 = __umulhi(0xCD9E8D57u, x2);
+            const uint32_t y0 = hi1 ^ x1 ^ a, y2 = hi0 ^ x3 ^ b;
+            x0 = y0;
+            x1 = lo1;
+            x2 = y2;
+            x3 = lo0;
+            a += 0x9E3779B9u;
+            b += 0xBB67AE85u;
+        }
+        buf[0] = x0;
+        buf[1] = x1;
+        buf[2] = x2;
+        buf[3] = x3;
+        if (++c2 == 0)
+            ++c3;
+        used = 0;
+    }
+    // uniform in [0, 1) on the 2^-24 grid
+    __device__ float u()
+    {
+        if (used == 4)
+            refill();
+        return (float)(buf[used++] >> 8) * (1.f / 16777216.f);
+    }
+};
+
+// ------------------------------------------------------------------ geometry helpers
+struct V3 {
+    float x, y, z;
+};
+__host__ __device__ __forceinline__ V3 v3(float x, float y, float z) { return V3{x, y, z}; }
+__device__ __forceinline__ float dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ V3 neg(V3 a) { return v3(-a.x, -a.y, -a.z); }
+__device__ __forceinline__ V3 madd(V3 a, float t, V3 d) { return v3(a.x + t * d.x, a.y + t * d.y, a.z + t * d.z); }
+
+__device__ __forceinline__ bool unit(const float *v, V3 &u)
+{
+    float a = v[0], b = v[1], c = v[2];
+    if (!(isfinite(a) && isfinite(b) && isfinite(c)))
+        return false;
+    float m = fmaxf(fabsf(a), fmaxf(fabsf(b), fabsf(c)));
+    if (m == 0.f)
+        return false;
+    a /= m;
+    b /= m;
+    c /= m;
+    float l = sqrtf(a * a + b * b + c * c);
+    u = v3(a / l, b / l, c / l);
+    return true;
+}
+
+// Orthonormal pair around unit n (branchless construction of Duff et al. 2017).
+__device__ __forceinline__ void basis(V3 n, V3 &t1, V3 &t2)
+{
+    const float sg = copysignf(1.f, n.z);
+    const float a = -1.f / (sg + n.z);
+    const float b = n.x * n.y * a;
+    t1 = v3(1.f + sg * n.x * n.x * a, sg * b, -sg * n.x);
+    t2 = v3(b, sg + n.y * n.y * a, -n.y);
+}
+
+// ------------------------------------------------------------------ medium
+struct Medium {
+    const float *mu;   // extinction sigma_max * d, [nz][ny][nx]
+    int nx, ny, nz;
+    V3 amin, amax;
+    float inv_h, maj;
+};
+
+// Voxel-centred trilinear extinction, zero outside the grid.
+__device__ float mu_at(const Medium &M, V3 p)
+{
+    const float ux = (p.x - M.amin.x) * M.inv_h - 0.5f;
+    const float uy = (p.y - M.amin.y) * M.inv_h - 0.5f;
+    const float uz = (p.z - M.amin.z) * M.inv_h - 0.5f;
+    const float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
+    const float fx = ux - fx0, fy = uy - fy0, fz = uz - fz0;
+    const int ix = (int)fx0, iy = (int)fy0, iz = (int)fz0;
+    float acc = 0.f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
+        const int a = ix + dx, b = iy + dy, e = iz + dz;
+        if (a >= 0 && b >= 0 && e >= 0 && a < M.nx && b < M.ny && e < M.nz) {
+            const float w = (dx ? fx : 1.f - fx) * (dy ? fy : 1.f - fy) * (dz ? fz : 1.f - fz);
+            acc += w * M.mu[((int64_t)e * M.ny + b) * M.nx + a];
+        }
+    }
+    return acc;
+}
+
+// Parametric interval [t0, t1] of o + t d inside the grid box, t >= 0.
+__device__ bool clip(const Medium &M, V3 o, V3 d, float &t0, float &t1)
+{
+    float lo = 0.f, hi = INFINITY;
+    const float oo[3] = {o.x, o.y, o.z}, dd[3] = {d.x, d.y, d.z};
+    const float mn[3] = {M.amin.x, M.amin.y, M.amin.z}, mx[3] = {M.amax.x, M.amax.y, M.amax.z};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (dd[a] != 0.f) {
+            float ta = (mn[a] - oo[a]) / dd[a], tb = (mx[a] - oo[a]) / dd[a];
+            if (ta > tb) {
+                const float s = ta;
+                ta = tb;
+                tb = s;
+            }
+            lo = fmaxf(lo, ta);
+            hi = fminf(hi, tb);
+        } else if (oo[a] < mn[a] || oo[a] > mx[a]) {
+            return false;
+        }
+    }
+    t0 = lo;
+    t1 = hi;
+    return hi > lo;
+}
+
+// Free flight from o along unit d: true and the collision point, false on escape.
+__device__ bool delta_track(const Medium &M, V3 o, V3 d, Rng &r, V3 &x, int64_t &steps)
+{
+    float t0, t1;
+    if (!clip(M, o, d, t0, t1) || !(M.maj > 0.f))
+        return false;
+    float t = t0;
+    const float inv = 1.f / M.maj;
+    while (steps < kMaxSteps) {
+        ++steps;
+        t += -logf(1.f - r.u()) * inv;
+        if (t >= t1)
+            return false;
+        const V3 p = madd(o, t, d);
+        if (r.u() * M.maj < mu_at(M, p)) {
+            x = p;
+            return true;
+        }
+    }
+    return false;
+}
+
+// Ratio-tracking estimate of the transmittance from o along unit d to the box exit.
+__device__ float ratio_track(const Medium &M, V3 o, V3 d, Rng &r, int64_t &steps)
+{
+    float t0, t1;
+    if (!clip(M, o, d, t0, t1) || !(M.maj > 0.f))
+        return 1.f;
+    float T = 1.f, t = t0;
+    const float inv = 1.f / M.maj;
+    while (steps < kMaxSteps) {
+        ++steps;
+        t += -logf(1.f - r.u()) * inv;
+        if (t >= t1)
+            break;
+        T *= 1.f - mu_at(M, madd(o, t, d)) * inv;
+    }
+    return T;
+}
+
+__device__ __forceinline__ float hg(float g, float mu)
+{
+    const float den = 1.f + g * g - 2.f * g * mu;
+    return (1.f - g * g) / (4.f * (float)M_PI * den * sqrtf(den));
+}
+
+// Inverse-CDF sample of the Henyey-Greenstein cosine (isotropic for |g| < 1e-3).
+__device__ __forceinline__ float hg_cos(float g, float u)
+{
+    if (fabsf(g) < 1e-3f)
+        return 2.f * u - 1.f;
+    const float s = (1.f - g * g) / (1.f - g + 2.f * g * u);
+    return fminf(1.f, fmaxf(-1.f, (1.f + g * g - s * s) / (2.f * g)));
+}
+
+__device__ V3 around(V3 w, float c, float u)
+{
+    V3 t1, t2;
+    basis(w, t1, t2);
+    const float s = sqrtf(fmaxf(0.f, 1.f - c * c));
+    float sp, cp;
+    sincosf(2.f * (float)M_PI * u, &sp, &cp);
+    V3 o = v3(s * cp * t1.x + s * sp * t2.x + c * w.x, s * cp * t1.y + s * sp * t2.y + c * w.y,
+              s * cp * t1.z + s * sp * t2.z + c * w.z);
+    const float l = sqrtf(dot(o, o));
+    return v3(o.x / l, o.y / l, o.z / l);
+}
+
+// One path estimate of the indirect in-scattered radiance at x toward w
+// (directional light: next-event estimation at every collision; uniform
+// environment: the radiance of escaping paths after at least one collision, or
+// any escape when count_uncollided).
+__device__ float li_path(const Medium &M, const TracerParams &tp, V3 x, V3 w, V3 wl,
+                         bool count_uncollided, Rng &r)
+{
+    V3 wprev = w, p = x;
+    float sum = 0.f;
+    int64_t steps = 0;
+    for (int j = 1;; ++j) {
+        if ((tp.max_interactions > 0 && j > tp.max_interactions) || steps >= kMaxSteps)
+            break;
+        const float c = hg_cos(tp.g, r.u());
+        const V3 wh = around(wprev, c, r.u());
+        V3 xn;
+        if (!delta_track(M, p, neg(wh), r, xn, steps)) {
+            if (tp.light_mode == 1 && (j > 1 || count_uncollided))
+                sum += tp.irradiance;
+            break;
+        }
+        p = xn;
+        if (r.u() >= tp.albedo)
+            break;
+        if (tp.light_mode == 0)
+            sum += hg(tp.g, -dot(wh, wl)) * ratio_track(M, p, wl, r, steps) * tp.irradiance;
+        wprev = wh;
+    }
+    return sum;
+}
+
+// Launch geometry of the per-record estimators: a block holds kPaths / seg
+// records, each owning seg consecutive threads (seg a power of two); records with
+// more than kPaths samples are split over nblk blocks (then seg = kPaths).
+struct Split {
+    int seg, nblk;
+};
+
+// Deterministic segmented reduction of (sum, sum of squares) in FP64: thread
+// t of each segment ends holding nothing; the segment leader writes the totals.
+__device__ void segment_sums(double s1, double s2, int seg, bool write, double *out)
+{
+    __shared__ double a[kPaths], b[kPaths];
+    const int t = threadIdx.x;
+    a[t] = s1;
+    b[t] = s2;
+    __syncthreads();
+    for (int w = seg >> 1; w > 0; w >>= 1) {
+        if ((t & (seg - 1)) < w) {
+            a[t] += a[t + w];
+            b[t] += b[t + w];
+        }
+        __syncthreads();
+    }
+    if (write && (t & (seg - 1)) == 0) {
+        out[0] = a[t];
+        out[1] = b[t];
+    }
+}
+
+__global__ void __launch_bounds__(kPaths) k_trace_li(Medium M, TracerParams tp, const float *pos,
+                                                     const float *view, const float *light,
+                                                     int64_t P, int spp, Split sp, uint64_t seed,
+                                                     double *partial)
+{
+    const int64_t group = blockIdx.x / sp.nblk;
+    const int blk = blockIdx.x % sp.nblk;
+    const int64_t rec = group * (kPaths / sp.seg) + threadIdx.x / sp.seg;
+    const int s = blk * sp.seg + (threadIdx.x & (sp.seg - 1));
+    double e = 0.0;
+    V3 w, wl;
+    if (rec < P && s < spp && unit(view + 3 * rec, w) && unit(light + 3 * rec, wl)) {
+        const V3 x = v3(pos[3 * rec], pos[3 * rec + 1], pos[3 * rec + 2]);
+        Rng r;
+        r.init(seed, ((uint64_t)rec << 20) + (uint64_t)s);
+        e = (double)li_path(M, tp, x, w, wl, false, r);
+    }
+    segment_sums(e, e * e, sp.seg, rec < P, partial + 2 * ((size_t)rec * sp.nblk + blk));
+}
+
+__global__ void __launch_bounds__(256) k_finish_sums(const double *partial, int64_t P, int nblk,
+                                                     int spp, double *mean, double *var)
+{
+    const int64_t rec = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (rec >= P)
+        return;
+    double s1 = 0.0, s2 = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        s1 += partial[2 * (rec * nblk + b)];
+        s2 += partial[2 * (rec * nblk + b) + 1];
+    }
+    const double m = s1 / spp;
+    mean[rec] = m;
+    if (var)
+        var[rec] = spp > 1 ? fmax(0.0, (s2 - spp * m * m) / (spp - 1)) / spp : 0.0;
+}
+
+// Record configurations (Sec. 5.1): direction d uniform on the sphere, origin
+// uniform over the bounding sphere's cross-section orthogonal to d, a free flight
+// along d into the cloud, retried on escape; view = -d, light uniform.
+__global__ void __launch_bounds__(256) k_sample_records(Medium M, int64_t N, uint64_t seed,
+                                                        float *pos, float *view, float *light,
+                                                        int32_t *attempts)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N)
+        return;
+    const V3 c = v3(0.5f * (M.amin.x + M.amax.x), 0.5f * (M.amin.y + M.amax.y),
+                    0.5f * (M.amin.z + M.amax.z));
+    const V3 e = v3(0.5f * (M.amax.x - M.amin.x), 0.5f * (M.amax.y - M.amin.y),
+                    0.5f * (M.amax.z - M.amin.z));
+    const float R = sqrtf(dot(e, e));
+    Rng r;
+    r.init(seed, (uint64_t)i);
+    V3 d = v3(0, 0, 1), x = v3(NAN, NAN, NAN);
+    int tries = 0;
+    int64_t steps = 0;
+    while (tries < 1000000) {
+        ++tries;
+        const float u0 = r.u(), u1 = r.u();
+        const float zc = 1.f - 2.f * u0, rr = sqrtf(fmaxf(0.f, 1.f - zc * zc));
+        float sp, cp;
+        sincosf(2.f * (float)M_PI * u1, &sp, &cp);
+        d = v3(rr * cp, rr * sp, zc);
+        V3 t1, t2;
+        basis(d, t1, t2);
+        const float rad = R * sqrtf(r.u());
+        sincosf(2.f * (float)M_PI * r.u(), &sp, &cp);
+        const V3 o = v3(c.x - R * d.x + rad * (cp * t1.x + sp * t2.x),
+                        c.y - R * d.y + rad * (cp * t1.y + sp * t2.y),
+                        c.z - R * d.z + rad * (cp * t1.z + sp * t2.z));
+        steps = 0;
+        if (delta_track(M, o, d, r, x, steps))
+            break;
+        x = v3(NAN, NAN, NAN);
+    }
+    const float u0 = r.u(), u1 = r.u();
+    const float zc = 1.f - 2.f * u0, rr = sqrtf(fmaxf(0.f, 1.f - zc * zc));
+    float sp, cp;
+    sincosf(2.f * (float)M_PI * u1, &sp, &cp);
+    pos[3 * i] = x.x;
+    pos[3 * i + 1] = x.y;
+    pos[3 * i + 2] = x.z;
+    view[3 * i] = -d.x;
+    view[3 * i + 1] = -d.y;
+    view[3 * i + 2] = -d.z;
+    light[3 * i] = rr * cp;
+    light[3 * i + 1] = rr * sp;
+    light[3 * i + 2] = zc;
+    if (attempts)
+        attempts[i] = tries;
+}
+
+// Path-traced pixels: first collision along each camera ray, then albedo times the
+// in-scattered radiance there (direct by next-event estimation plus the indirect
+// path estimate for a directional light; all in-scattered environment light in mode 1).
+__global__ void __launch_bounds__(kPaths) k_render_mc(Medium M, TracerParams tp, V3 wl,
+                                                      const float *ray_o, const float *ray_d,
+                                                      int64_t N, int spp, Split sp, uint64_t seed,
+                                                      double *partial)
+{
+    const int64_t group = blockIdx.x / sp.nblk;
+    const int blk = blockIdx.x % sp.nblk;
+    const int64_t px = group * (kPaths / sp.seg) + threadIdx.x / sp.seg;
+    const int s = blk * sp.seg + (threadIdx.x & (sp.seg - 1));
+    double e = 0.0;
+    V3 d;
+    if (px < N && s < spp && unit(ray_d + 3 * px, d)) {
+        const V3 o = v3(ray_o[3 * px], ray_o[3 * px + 1], ray_o[3 * px + 2]);
+        Rng r;
+        r.init(seed, ((uint64_t)px << 20) + (uint64_t)s);
+        V3 x;
+        int64_t steps = 0;
+        if (!delta_track(M, o, d, r, x, steps)) {
+            e = tp.light_mode == 1 ? tp.irradiance : 0.0;
+        } else {
+            const V3 w = neg(d);
+            if (tp.light_mode == 0) {
+                const float direct = hg(tp.g, -dot(w, wl)) * ratio_track(M, x, wl, r, steps) * tp.irradiance;
+                e = (double)tp.albedo * (double)(direct + li_path(M, tp, x, w, wl, false, r));
+            } else {
+                e = (double)tp.albedo * (double)li_path(M, tp, x, w, wl, true, r);
+            }
+        }
+    }
+    segment_sums(e, e * e, sp.seg, px < N, partial + 2 * ((size_t)px * sp.nblk + blk));
+}
+
+// One camera sample per ray for the network renderer: the delta-tracked first
+// collision, the view direction there, and the direct single scattering from the
+// directional light (next-event estimation, times the albedo).  Rays that escape
+// get hit = 0 and zero outputs.
+__global__ void __launch_bounds__(256) k_first_hits(Medium M, TracerParams tp, V3 wl,
+                                                    const float *ray_o, const float *ray_d,
+                                                    int64_t N, uint64_t seed, uint64_t sample,
+                                                    float *pos, float *view, float *direct,
+                                                    uint8_t *hit)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N)
+        return;
+    V3 d;
+    bool h = false;
+    float dir = 0.f;
+    V3 x = v3(0, 0, 0);
+    if (unit(ray_d + 3 * i, d)) {
+        const V3 o = v3(ray_o[3 * i], ray_o[3 * i + 1], ray_o[3 * i + 2]);
+        Rng r;
+        r.init(seed, ((uint64_t)i << 20) + sample);
+        int64_t steps = 0;
+        h = delta_track(M, o, d, r, x, steps);
+        if (h)
+            dir = tp.albedo * hg(tp.g, dot(d, wl)) * ratio_track(M, x, wl, r, steps) * tp.irradiance;
+    }
+    pos[3 * i] = x.x;
+    pos[3 * i + 1] = x.y;
+    pos[3 * i + 2] = x.z;
+    view[3 * i] = -d.x;
+    view[3 * i + 1] = -d.y;
+    view[3 * i + 2] = -d.z;
+    direct[i] = dir;
+    hit[i] = h ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(256) k_mu(const void *d, ds_dtype dt, int64_t n, float sigma,
+                                            float *mu)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float v;
+        if (dt == DS_F32)
+            v = static_cast<const float *>(d)[i];
+        else
+            v = __uint_as_float((uint32_t) static_cast<const uint16_t *>(d)[i] << 16);
+        mu[i] = sigma * v;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_max(const float *x, int64_t n, float *out)
+{
+    __shared__ float s[256];
+    float m = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, x[i]);
+    s[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+            s[threadIdx.x] = fmaxf(s[threadIdx.x], s[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        out[blockIdx.x] = s[0];
+}
+
+__global__ void __launch_bounds__(256) k_philox(const uint32_t *ck, int64_t n, uint32_t *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n)
+        return;
+    Rng r;
+    r.c0 = ck[6 * i];
+    r.c1 = ck[6 * i + 1];
+    r.c2 = ck[6 * i + 2];
+    r.c3 = ck[6 * i + 3];
+    r.k0 = ck[6 * i + 4];
+    r.k1 = ck[6 * i + 5];
+    r.refill();
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        out[4 * i + j] = r.buf[j];
+}
+
+Medium medium(const ds_cloud *c)
+{
+    Medium M;
+    M.mu = c->mu;
+    M.nx = c->nx;
+    M.ny = c->ny;
+    M.nz = c->nz;
+    M.amin = v3(c->aabb_min[0], c->aabb_min[1], c->aabb_min[2]);
+    M.amax = v3((float)((double)c->aabb_min[0] + (double)c->nx * c->h0),
+                (float)((double)c->aabb_min[1] + (double)c->ny * c->h0),
+                (float)((double)c->aabb_min[2] + (double)c->nz * c->h0));
+    M.inv_h = (float)(1.0 / (double)c->h0);
+    M.maj = c->majorant;
+    return M;
+}
+
+Split split(int spp)
+{
+    Split sp;
+    sp.nblk = (spp + kPaths - 1) / kPaths;
+    sp.seg = 1;
+    while (sp.seg < spp && sp.seg < kPaths)
+        sp.seg <<= 1;
+    return sp;
+}
+
+unsigned grid_of(int64_t n, Split sp)
+{
+    const int64_t rpb = kPaths / sp.seg;
+    return (unsigned)(((n + rpb - 1) / rpb) * sp.nblk);
+}
+
+ds_status reduce_records(hipStream_t s, const double *partial, int64_t P, int nblk, int spp,
+                         double *mean, double *var)
+{
+    k_finish_sums<<<(unsigned)((P + 255) / 256), 256, 0, s>>>(partial, P, nblk, spp, mean, var);
+    DS_HIP(hipGetLastError());
+    return DS_OK;
+}
+
+}  // namespace
+
+ds_status tracer_prepare(ds_cloud *c, const void *density, ds_dtype dt)
+{
+    const int64_t n = (int64_t)c->nx * c->ny * c->nz;
+    DS_CHECK(hipMalloc(&c->mu, (size_t)n * sizeof(float)) == hipSuccess, DS_ERR_OOM,
+             "out of device memory for the extinction grid");
+    hipStream_t s = c->ctx->stream;
+    int grid = (int)((n + 255) / 256 < 16384 ? (n + 255) / 256 : 16384);
+    k_mu<<<grid, 256, 0, s>>>(density, dt, n, c->sigma_max, c->mu);
+    float *part = nullptr;
+    DS_HIP(hipMalloc(&part, 1024 * sizeof(float)));
+    k_max<<<1024, 256, 0, s>>>(c->mu, n, part);
+    k_max<<<1, 256, 0, s>>>(part, 1024, part);
+    float mx = 0.f;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&mx, part, sizeof(float), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(s);
+    (void)hipFree(part);
+    if (e != hipSuccess)
+        return hip_fail(e, "majorant");
+    c->majorant = mx;
+    return DS_OK;
+}
+
+ds_status tracer_li(hipStream_t s, const ds_cloud *c, const TracerParams &tp, const float *pos,
+                    const float *view, const float *light, int64_t P, int spp, uint64_t seed,
+                    double *partial, double *mean, double *var)
+{
+    const Split sp = split(spp);
+    k_trace_li<<<grid_of(P, sp), kPaths, 0, s>>>(medium(c), tp, pos, view, light, P, spp, sp,
+                                                  seed, partial);
+    DS_HIP(hipGetLastError());
+    return reduce_records(s, partial, P, sp.nblk, spp, mean, var);
+}
+
+ds_status tracer_records(hipStream_t s, const ds_cloud *c, int64_t N, uint64_t seed, float *pos,
+                         float *view, float *light, int32_t *attempts)
+{
+    k_sample_records<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(medium(c), N, seed, pos, view,
+                                                                 light, attempts);
+    DS_HIP(hipGetLastError());
+    return DS_OK;
+}
+
+ds_status tracer_render(hipStream_t s, const ds_cloud *c, const TracerParams &tp,
+                        const float *light_dir, const float *ray_o, const float *ray_d, int64_t N,
+                        int spp, uint64_t seed, double *partial, double *mean, double *var)
+{
+    float l[3];
+    DS_CHECK(light_dir && unit_host(light_dir, l), DS_ERR_INVALID_ARG,
+             "the light direction is not a usable vector");
+    const V3 wl = v3(l[0], l[1], l[2]);
+    const Split sp = split(spp);
+    k_render_mc<<<grid_of(N, sp), kPaths, 0, s>>>(medium(c), tp, wl, ray_o, ray_d, N, spp, sp,
+                                                   seed, partial);
+    DS_HIP(hipGetLastError());
+    return reduce_records(s, partial, N, sp.nblk, spp, mean, var);
+}
+
+ds_status tracer_first_hits(hipStream_t s, const ds_cloud *c, const TracerParams &tp,
+                            const float *light_dir, const float *ray_o, const float *ray_d,
+                            int64_t N, uint64_t seed, uint64_t sample, float *pos, float *view,
+                            float *direct, uint8_t *hit)
+{
+    float l[3];
+    DS_CHECK(light_dir && unit_host(light_dir, l), DS_ERR_INVALID_ARG,
+             "the light direction is not a usable vector");
+    const V3 wl = v3(l[0], l[1], l[2]);
+    k_first_hits<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(medium(c), tp, wl, ray_o, ray_d, N,
+                                                             seed, sample, pos, view, direct, hit);
+    DS_HIP(hipGetLastError());
+    return DS_OK;
+}
+
+ds_status philox_blocks(hipStream_t s, const uint32_t *ctr_key, int64_t n, uint32_t *out)
+{
+    k_philox<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(ctr_key, n, out);
+    DS_HIP(hipGetLastError());
+    return DS_OK;
+}
+
+int tracer_blocks(int spp) { return split(spp).nblk; }
+
+}  // namespace ds
