@@ -20,6 +20,9 @@ What each part follows in the paper and what pins it (tests/test_oracle_*.py):
   trace_li etc.   Sec. 3.2 Eq. 1, Sec. 4, Sec. 4.4, 5.1     slab transmittance, furnace, sphere
                                                             closed form, single-scatter quadrature,
                                                             HG moments and CDF
+  first_hits      Sec. 4.4 camera sample: first collision   homogeneous box: hit fraction
+                  and direct single scattering              1 - exp(-sigma L), direct term against
+                                                            albedo p exp(-sigma s) E
 """
 from __future__ import annotations
 
@@ -79,6 +82,8 @@ def lib():
             "dso_sample_records": (I, [P, I, I, I, I, D, P, D, I64, U64, P, P, P, P]),
             "dso_render_pixels": (I, [P, I, I, I, I, D, P, D, D, D, D, I, I, P, P, P, I64, I, U64,
                                       P, P]),
+            "dso_first_hits": (I, [P, I, I, I, I, D, P, D, D, D, D, P, P, P, I64, U64, U64, P, P,
+                                   P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -284,6 +289,23 @@ def sample_records(grid: Grid, N, seed):
     _check(lib().dso_sample_records(*grid.args(), _p(grid.aabb_min), grid.h0, N, seed, _p(pos),
                                     _p(view), _p(light), _p(att)), "sample_records")
     return pos, view, light, att
+
+
+def first_hits(grid: Grid, ray_o, ray_d, light_dir, albedo=0.999, g=0.85, irradiance=1.0, seed=1,
+               sample=0):
+    """First collision, view direction and NEE direct term per ray (one sample)."""
+    o = np.ascontiguousarray(ray_o, np.float32)
+    d = np.ascontiguousarray(ray_d, np.float32)
+    ld = np.ascontiguousarray(np.asarray(light_dir, np.float64))
+    N = o.shape[0]
+    pos = np.zeros((N, 3))
+    view = np.zeros((N, 3))
+    direct = np.zeros(N)
+    hit = np.zeros(N, np.uint8)
+    _check(lib().dso_first_hits(*grid.args(), _p(grid.aabb_min), grid.h0, albedo, g, irradiance,
+                                _p(ld), _p(o), _p(d), N, seed, sample, _p(pos), _p(view),
+                                _p(direct), _p(hit)), "first_hits")
+    return pos, view, direct, hit
 
 
 def render_pixels(grid: Grid, ray_o, ray_d, light_dir, albedo=0.999, g=0.85, irradiance=1.0,

@@ -1132,6 +1132,47 @@ int dso_sample_records(const void *dens, int dtype, int nx, int ny, int nz, doub
     return DSO_OK;
 }
 
+/* One camera sample per ray (Sec. 4.4): the delta-tracked first collision x along
+ * o + t d, the view direction there (-d), and the direct single scattering
+ * albedo * p(d . w_l) * T(x -> light) * E with T one ratio-tracking estimate;
+ * hit = 0 and zeros for rays that escape.  Ray i, sample s uses stream id
+ * i * 2^20 + s under key `seed`: the same streams, consumed in the same order, as
+ * the first stage of dso_render_pixels in mode 0. */
+int dso_first_hits(const void *dens, int dtype, int nx, int ny, int nz, double sigma_max,
+                   const double *aabb_min, double h0, double albedo, double g, double irradiance,
+                   const double *light_dir, const float *ray_o, const float *ray_d, int64_t N,
+                   uint64_t seed, uint64_t sample, double *pos, double *view, double *direct,
+                   uint8_t *hit)
+{
+    medium_t M;
+    if (!medium_init(&M, dens, dtype, nx, ny, nz, sigma_max, aabb_min, h0) || sample >= (1u << 20))
+        return DSO_ERR_INVALID;
+    double wl[3];
+    if (!unit3(light_dir, wl))
+        return DSO_ERR_INVALID;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < N; ++i) {
+        double o[3] = {ray_o[3 * i], ray_o[3 * i + 1], ray_o[3 * i + 2]};
+        double dv[3] = {ray_d[3 * i], ray_d[3 * i + 1], ray_d[3 * i + 2]}, d[3], x[3];
+        int h = 0;
+        double e = 0.0;
+        if (unit3(dv, d)) {
+            rng_t r;
+            rng_init(&r, seed, ((uint64_t)i << 20) + sample);
+            h = delta_track(&M, o, d, &r, x);
+            if (h)
+                e = albedo * dso_hg(g, dot3(d, wl)) * ratio_track(&M, x, wl, &r) * irradiance;
+        }
+        for (int a = 0; a < 3; ++a) {
+            pos[3 * i + a] = h ? x[a] : 0.0;
+            view[3 * i + a] = h ? -d[a] : 0.0;
+        }
+        direct[i] = e;
+        hit[i] = (uint8_t)h;
+    }
+    return DSO_OK;
+}
+
 /* Path-traced pixels (Sec. 4.4 with the network replaced by the path estimate):
  * a delta-tracked first collision x along each camera ray o + t d (background 0,
  * or the environment radiance in mode 1), then albedo times the in-scattered

@@ -221,3 +221,40 @@ def test_record_sampler_places_points_in_the_medium():
     # the same seed reproduces the same records
     pos2, _, _, _ = O.sample_records(g, 50, seed=5)
     np.testing.assert_array_equal(pos2, pos[:50])
+
+
+# ---------------------------------------------------------------- camera samples
+def test_first_hits_homogeneous_box_closed_forms():
+    # rays along +x through a homogeneous box, light along +z: a ray collides with
+    # probability 1 - exp(-tau) and, given a collision, the direct term has mean
+    # albedo * p(0) * exp(-sigma * depth toward the light) * E, the same for every
+    # collision of that ray because the depth depends on z only
+    n = 12
+    h = 1.0 / n
+    d = np.ones((n, n, n), np.float32)
+    sigma, albedo, gg, E = 1.7, 0.9, 0.6, 2.5
+    grid = O.Grid(d, sigma, [-0.5] * 3, h)
+    R, S = 6, 3000
+    zs = np.linspace(-0.35, 0.35, R)
+    o = np.stack([np.full(R, -0.9), np.full(R, 0.05), zs], 1).astype(np.float32)
+    dirs = np.tile(np.array([[1.0, 0, 0]], np.float32), (R, 1))
+    hits = np.zeros(R)
+    dsum = np.zeros(R)
+    for s in range(S):
+        pos, view, direct, hit = O.first_hits(grid, o, dirs, [0, 0, 1], albedo=albedo, g=gg,
+                                              irradiance=E, seed=4, sample=s)
+        h1 = hit == 1
+        assert np.all(np.abs(pos[h1, 1:] - o[h1, 1:]) < 1e-6)   # on the ray
+        assert np.all(view[h1] == [-1, 0, 0]) and np.all(direct[~h1] == 0)
+        hits += h1
+        dsum += direct
+    T_ray = math.exp(-sigma * (1.0 - h / 4))
+    p_hit = 1 - T_ray
+    sd = math.sqrt(p_hit * (1 - p_hit) / S)
+    assert np.all(np.abs(hits / S - p_hit) < 5 * sd)
+    depth = np.array([ramp_int(z + 0.5, 1.0, n, h) for z in zs])  # optical depth / sigma to the top
+    T_up = np.exp(-sigma * depth)
+    want = albedo * O.hg(gg, 0.0) * T_up * E
+    mean = dsum / hits
+    sd_d = albedo * O.hg(gg, 0.0) * E * np.sqrt(T_up * (1 - T_up) / hits) + 1e-12
+    assert np.all(np.abs(mean - want) < 5 * sd_d), (mean, want)
