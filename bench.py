@@ -40,6 +40,39 @@ WORKLOADS = {
 }
 
 
+HERE = os.path.dirname(os.path.abspath(__file__))
+FUSED_KERNEL = "k_fused_reg<13,4>"
+TRAFFIC_FILE = os.path.join(HERE, "profiles", "k_fused_reg_bf16_512cube_1M_points_hbm_traffic.txt")
+KERNEL_SOURCES = ["fused.hip", "frame.h", "internal.h"]
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "paper_1709_05418_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the fused kernel from the committed counter summary,
+    or None when the kernel sources changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for ln in open(TRAFFIC_FILE):
+        if ":" in ln and not ln.startswith("#"):
+            k, v = ln.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return None
+    try:
+        return int(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def macs_per_point(K, W, H):
     return 226 * K * W + (K - 1) * W * W + K * W * W + (H - 1) * W * W + W
 
@@ -133,10 +166,12 @@ def main():
 
     flop = 2.0 * macs_per_point(K, W, H) * P
     achieved = flop / (avg_kernel_ms / 1e3) / 1e12
+    traffic = measured_traffic() if args.workload == "paper" else None
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4), "traffic": None,
-                "kernel": "k_fused<13,1> (BF16 MFMA, stencil gather fused)",
-                "flop_per_point": 2 * macs_per_point(K, W, H)}
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
+                "traffic": traffic,
+                "kernel": FUSED_KERNEL + " (BF16 MFMA, stencil gather fused)",
+                "flop_per_point": 2 * macs_per_point(K, W, H), "points_per_launch": P}
 
     # ---------------------------------------------------------------- FP32 plain form
     out32 = torch.empty(P, dtype=torch.float32, device=dev)

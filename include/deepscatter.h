@@ -278,6 +278,42 @@ ds_status ds_first_hits(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_para
                         int64_t N, uint64_t seed, uint64_t sample, float *pos, float *view_dir,
                         float *direct, uint8_t *hit);
 
+/* Training pairs (Sec. 5.1, 5.2): N records of `cloud` as ds_sample_records
+ * draws them (key seed), their reference L_i per unit irradiance as
+ * ds_trace_li estimates it with spp paths (DS_LIGHT_DIRECTIONAL only; its key
+ * is derived from seed by a SplitMix64 finaliser, so record and path streams
+ * never coincide), the plain FP32 descriptor of each record and the target
+ * log(1 + L_i) in FP32.  Record i goes to row i * stride of z (device, rows of
+ * 225K+1 floats) and to target_log1p[i * stride] (device), so several calls with
+ * offsets 0..stride-1 interleave clouds.  pos / view_dir / light_dir (device
+ * [N][3]) and li_mean / li_var (device N doubles: the estimate and the variance
+ * of that mean) are written when not NULL.  Records that never collide get a
+ * zero row and target 0.  Library-owned workspace as ds_trace_li plus 52 B per
+ * record. */
+ds_status ds_make_records(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params *params,
+                          int64_t N, int spp, uint64_t seed, int64_t stride, float *z,
+                          float *target_log1p, float *pos, float *view_dir, float *light_dir,
+                          double *li_mean, double *li_var);
+
+/* Image formation with the network (Sec. 4.4): for each camera ray o + t d
+ * (device [N][3] each) and each of spp samples s, a delta-tracked first
+ * collision and its direct single scattering as ds_first_hits computes them
+ * (sample index s), then radiance = direct + albedo * E * L_i with L_i the
+ * network's prediction at `precision` for the directional light light_dir (host,
+ * 3 floats).  Where the level-1 stencil leaves the grid (DS_FLAG_FALLBACK) and
+ * fallback_spp > 0, L_i comes from fallback_spp path-traced estimates instead
+ * (ds_trace_li, key derived from seed and s).  Escaping rays give 0.  Per pixel:
+ * the mean over samples (mean_out, device N doubles), the variance of that mean
+ * (var_out, may be NULL) and the mean of the direct term alone (direct_out, may
+ * be NULL: the renderer without the network).  n_fallback (host, may be NULL)
+ * receives the number of (pixel, sample) collisions that used the fallback; it
+ * makes the call synchronise.  The cloud's K must equal the network's. */
+ds_status ds_render_rpnn(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
+                         ds_precision precision, const ds_tracer_params *params,
+                         const float light_dir[3], const float *ray_o, const float *ray_d,
+                         int64_t N, int spp, uint64_t seed, int fallback_spp, double *mean_out,
+                         double *var_out, double *direct_out, int64_t *n_fallback);
+
 /* The tracer's random generator itself: for n (counter, key) pairs
  * ctr_key (device, [n][6] uint32: c0 c1 c2 c3 k0 k1) the Philox4x32-10 block
  * (device out, [n][4] uint32), as defined by Salmon et al., SC'11. */

@@ -76,6 +76,8 @@ def lib():
         "ds_render_mc": (S, [P, P, P, P, P, P, I64, I, C.c_uint64, P, P]),
         "ds_first_hits": (S, [P, P, P, P, P, P, I64, C.c_uint64, C.c_uint64, P, P, P, P]),
         "ds_philox4x32_10": (S, [P, P, I64, P]),
+        "ds_make_records": (S, [P, P, P, I64, I, C.c_uint64, I64, P, P, P, P, P, P, P]),
+        "ds_render_rpnn": (S, [P, P, P, I, P, P, P, P, I64, I, C.c_uint64, I, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -376,6 +378,48 @@ def ds_first_hits(ctx, cloud, params: TracerParams, light_dir, ray_o, ray_d, see
                                int(seed), int(sample), _ptr(pos), _ptr(view), _ptr(direct),
                                _ptr(hit)))
     return pos, view, direct, hit
+
+
+def ds_make_records(ctx, cloud, params: TracerParams, N, spp, seed, z, target, offset=0,
+                    stride=1, want_records=False, want_li=False):
+    """Training pairs into rows offset + i * stride of z ((M, 225K+1) float32) and
+    target ((M,) float32, log(1 + L_i)).  Optionally returns (pos, view, light) and
+    (li_mean, li_var) of the N records."""
+    import torch
+    D = z.shape[1]
+    if z.dtype != torch.float32 or target.dtype != torch.float32 or z.dim() != 2:
+        raise ValueError("z must be float32 (M, 225K+1), target float32 (M,)")
+    if N > 0 and (offset + (N - 1) * stride >= z.shape[0] or
+                  offset + (N - 1) * stride >= target.shape[0]):
+        raise ValueError("z / target too small for N records at this offset and stride")
+    dev = z.device
+    rec = [torch.empty((N, 3), dtype=torch.float32, device=dev) for _ in range(3)] \
+        if want_records else [None, None, None]
+    li = [torch.empty(N, dtype=torch.float64, device=dev) for _ in range(2)] \
+        if want_li else [None, None]
+    zp = C.c_void_p(z.data_ptr() + 4 * D * offset) if N > 0 else None
+    tp = C.c_void_p(target.data_ptr() + 4 * offset) if N > 0 else None
+    _check(lib().ds_make_records(ctx, cloud, C.byref(params), int(N), int(spp), int(seed),
+                                 int(stride), zp, tp, *[_ptr(t) for t in rec],
+                                 *[_ptr(t) for t in li]))
+    return (tuple(rec) if want_records else None), (tuple(li) if want_li else None)
+
+
+def ds_render_rpnn(ctx, cloud, net, precision, params: TracerParams, light_dir, ray_o, ray_d,
+                   spp, seed, fallback_spp=0, want_var=True, want_direct=True,
+                   count_fallback=False):
+    """Per pixel: (mean, variance of the mean, mean of the direct term, fallback count)."""
+    N = ray_o.shape[0]
+    ld = (C.c_float * 3)(*[float(v) for v in light_dir])
+    mean = _f64(N, ray_o.device)
+    var = _f64(N, ray_o.device) if want_var else None
+    direct = _f64(N, ray_o.device) if want_direct else None
+    nfb = C.c_int64(0)
+    _check(lib().ds_render_rpnn(ctx, cloud, net, int(precision), C.byref(params), ld,
+                                _pts(ray_o), _pts(ray_d, N), N, int(spp), int(seed),
+                                int(fallback_spp), _ptr(mean), _ptr(var), _ptr(direct),
+                                C.byref(nfb) if count_fallback else None))
+    return mean, var, direct, (nfb.value if count_fallback else None)
 
 
 def ds_philox4x32_10(ctx, ctr_key):

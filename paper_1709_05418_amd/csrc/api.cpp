@@ -105,6 +105,45 @@ ds_status ensure_ws(ds_ctx *ctx, size_t bytes)
     return DS_OK;
 }
 
+ds_status ensure_ws2(ds_ctx *ctx, size_t bytes)
+{
+    if (ctx->ws2_bytes >= bytes)
+        return DS_OK;
+    if (ctx->ws2) {
+        DS_HIP(hipStreamSynchronize(ctx->stream));
+        (void)hipFree(ctx->ws2);
+        ctx->ws2 = nullptr;
+        ctx->ws2_bytes = 0;
+    }
+    DS_HIP(hipMalloc(&ctx->ws2, bytes));
+    ctx->ws2_bytes = bytes;
+    return DS_OK;
+}
+
+// Carves aligned sub-buffers out of one workspace.
+struct Carve {
+    char *base;
+    size_t off = 0;
+    explicit Carve(void *b) : base(static_cast<char *>(b)) {}
+    template <class T> T *take(size_t n)
+    {
+        off = (off + 255) & ~size_t(255);
+        T *p = reinterpret_cast<T *>(base + off);
+        off += n * sizeof(T);
+        return p;
+    }
+};
+
+// Philox key of the path-tracing streams derived from a caller seed, kept apart from
+// the key of the record and camera streams.
+uint64_t derived_key(uint64_t seed, uint64_t which)
+{
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (which + 1);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
 void gather_args(const ds_cloud *c, const float *pos, const float *view, const float *light,
                  int64_t P, GatherArgs &a)
 {
@@ -441,10 +480,10 @@ ds_status ds_destroy(ds_ctx *ctx)
 {
     if (!ctx)
         return DS_OK;
-    if (ctx->ws) {
+    if (ctx->ws || ctx->ws2)
         (void)hipStreamSynchronize(ctx->stream);
-        (void)hipFree(ctx->ws);
-    }
+    (void)hipFree(ctx->ws);
+    (void)hipFree(ctx->ws2);
     delete ctx;
     return DS_OK;
 }
@@ -1049,6 +1088,145 @@ ds_status ds_first_hits(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_para
     DS_HIP(hipSetDevice(ctx->device));
     return tracer_first_hits(ctx->stream, cloud, tp, light_dir, ray_o, ray_d, N, seed, sample, pos,
                              view_dir, direct, hit);
+}
+
+ds_status ds_make_records(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params *params,
+                          int64_t N, int spp, uint64_t seed, int64_t stride, float *z,
+                          float *target_log1p, float *pos, float *view_dir, float *light_dir,
+                          double *li_mean, double *li_var)
+{
+    DS_CHECK(ctx && cloud && (N == 0 || (z && target_log1p)), DS_ERR_INVALID_ARG,
+             "ds_make_records: NULL argument");
+    DS_CHECK(N >= 0 && N <= ((int64_t)1 << 31) - 1, DS_ERR_INVALID_ARG,
+             "ds_make_records: N out of range");
+    DS_CHECK(stride >= 1, DS_ERR_INVALID_ARG, "ds_make_records: stride must be >= 1");
+    DS_CHECK(spp >= 1 && spp <= (1 << 20), DS_ERR_INVALID_ARG,
+             "ds_make_records: spp %d outside [1, 2^20]", spp);
+    TracerParams tp;
+    ds_status st = tracer_params(params, tp, "ds_make_records");
+    if (st)
+        return st;
+    DS_CHECK(tp.light_mode == DS_LIGHT_DIRECTIONAL, DS_ERR_INVALID_ARG,
+             "ds_make_records: records need a directional light");
+    if (N == 0)
+        return DS_OK;
+    DS_HIP(hipSetDevice(ctx->device));
+    st = ensure_ws2(ctx, 3 * 3 * sizeof(float) * (size_t)N + 2 * sizeof(double) * (size_t)N +
+                             5 * 256);
+    if (st)
+        return st;
+    Carve cv(ctx->ws2);
+    float *p = pos ? pos : cv.take<float>(3 * (size_t)N);
+    float *v = view_dir ? view_dir : cv.take<float>(3 * (size_t)N);
+    float *l = light_dir ? light_dir : cv.take<float>(3 * (size_t)N);
+    double *m = li_mean ? li_mean : cv.take<double>((size_t)N);
+    hipStream_t s = ctx->stream;
+    st = tracer_records(s, cloud, N, seed, p, v, l, nullptr);
+    if (st)
+        return st;
+    st = ensure_ws(ctx, sizeof(double) * 2 * (size_t)N * tracer_blocks(spp));
+    if (st)
+        return st;
+    st = tracer_li(s, cloud, tp, p, v, l, N, spp, derived_key(seed, 0),
+                   static_cast<double *>(ctx->ws), m, li_var);
+    if (st)
+        return st;
+    GatherArgs ga;
+    gather_args(cloud, p, v, l, N, ga);
+    st = gather_plain(s, ga, 0, N, DS_F32, z, (int64_t)(kStencil * cloud->K + 1) * stride,
+                      nullptr);
+    if (st)
+        return st;
+    return tracer_targets(s, m, N, stride, target_log1p);
+}
+
+ds_status ds_render_rpnn(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
+                         ds_precision precision, const ds_tracer_params *params,
+                         const float light_dir[3], const float *ray_o, const float *ray_d,
+                         int64_t N, int spp, uint64_t seed, int fallback_spp, double *mean_out,
+                         double *var_out, double *direct_out, int64_t *n_fallback)
+{
+    DS_CHECK(ctx && cloud && net && light_dir && (N == 0 || (ray_o && ray_d && mean_out)),
+             DS_ERR_INVALID_ARG, "ds_render_rpnn: NULL argument");
+    DS_CHECK(N >= 0 && N <= ((int64_t)1 << 31), DS_ERR_INVALID_ARG,
+             "ds_render_rpnn: N out of range");
+    DS_CHECK(spp >= 1 && spp <= (1 << 20), DS_ERR_INVALID_ARG,
+             "ds_render_rpnn: spp %d outside [1, 2^20]", spp);
+    DS_CHECK(fallback_spp >= 0 && fallback_spp <= (1 << 20), DS_ERR_INVALID_ARG,
+             "ds_render_rpnn: fallback_spp %d outside [0, 2^20]", fallback_spp);
+    DS_CHECK(cloud->K == net->K, DS_ERR_INVALID_ARG,
+             "ds_render_rpnn: the cloud has %d stencil levels, the network %d", cloud->K, net->K);
+    TracerParams tp;
+    ds_status st = tracer_params(params, tp, "ds_render_rpnn");
+    if (st)
+        return st;
+    DS_CHECK(tp.light_mode == DS_LIGHT_DIRECTIONAL, DS_ERR_INVALID_ARG,
+             "ds_render_rpnn: the network predicts radiance from a directional light");
+    float l[3];
+    DS_CHECK(unit_host(light_dir, l), DS_ERR_INVALID_ARG, "ds_render_rpnn: unusable light_dir");
+    if (n_fallback)
+        *n_fallback = 0;
+    if (N == 0)
+        return DS_OK;
+    DS_HIP(hipSetDevice(ctx->device));
+    const size_t n = (size_t)N;
+    st = ensure_ws2(ctx, n * (9 * sizeof(float) + 2 * sizeof(float) + 2 + 5 * sizeof(double)) +
+                             16 * 256);
+    if (st)
+        return st;
+    Carve cv(ctx->ws2);
+    float *pos = cv.take<float>(3 * n), *view = cv.take<float>(3 * n);
+    float *light = cv.take<float>(3 * n);
+    float *direct = cv.take<float>(n), *li = cv.take<float>(n);
+    uint8_t *hit = cv.take<uint8_t>(n), *flags = cv.take<uint8_t>(n);
+    double *li_mc = cv.take<double>(n), *sums = cv.take<double>(2 * n);
+    double *dsum = direct_out ? cv.take<double>(2 * n) : nullptr;
+    unsigned long long *cnt = cv.take<unsigned long long>(1);
+    hipStream_t s = ctx->stream;
+    if ((st = tracer_fill3(s, light, N, l)) || (st = tracer_zero(s, sums, 2 * N)) ||
+        (dsum && (st = tracer_zero(s, dsum, 2 * N))) ||
+        (st = tracer_zero(s, reinterpret_cast<double *>(cnt), 1)))
+        return st;
+    for (int smp = 0; smp < spp; ++smp) {
+        st = tracer_first_hits(s, cloud, tp, l, ray_o, ray_d, N, seed, (uint64_t)smp, pos, view,
+                               direct, hit);
+        if (st)
+            return st;
+        st = ds_predict(ctx, cloud, net, precision, pos, view, light, N, li, nullptr, flags);
+        if (st)
+            return st;
+        const double *mc = nullptr;
+        if (fallback_spp > 0) {
+            st = ensure_ws(ctx, sizeof(double) * 2 * n * tracer_blocks(fallback_spp));
+            if (st)
+                return st;
+            st = tracer_li(s, cloud, tp, pos, view, light, N, fallback_spp,
+                           derived_key(seed, 1 + (uint64_t)smp), static_cast<double *>(ctx->ws),
+                           li_mc, nullptr, flags, DS_FLAG_FALLBACK);
+            if (st)
+                return st;
+            mc = li_mc;
+        }
+        st = tracer_accumulate(s, N, hit, direct, li, flags, mc, tp.albedo, tp.irradiance, sums,
+                               dsum, n_fallback ? cnt : nullptr);
+        if (st)
+            return st;
+    }
+    st = tracer_finish(s, sums, N, spp, mean_out, var_out);
+    if (st)
+        return st;
+    if (direct_out) {
+        st = tracer_finish(s, dsum, N, spp, direct_out, nullptr);
+        if (st)
+            return st;
+    }
+    if (n_fallback) {
+        unsigned long long h = 0;
+        DS_HIP(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, s));
+        DS_HIP(hipStreamSynchronize(s));
+        *n_fallback = (int64_t)h;
+    }
+    return DS_OK;
 }
 
 ds_status ds_philox4x32_10(ds_ctx *ctx, const uint32_t *ctr_key, int64_t n, uint32_t *out)

@@ -51,6 +51,9 @@ struct ds_ctx {
     // workspace for the plain (materialised-descriptor) form
     void *ws = nullptr;
     size_t ws_bytes = 0;
+    // second workspace for calls that chain other calls using the first
+    void *ws2 = nullptr;
+    size_t ws2_bytes = 0;
 };
 
 struct ds_cloud {
@@ -191,9 +194,21 @@ struct TracerParams {
 bool unit_host(const float *v, float *u);  // normalise a host 3-vector; false if unusable
 ds_status tracer_prepare(ds_cloud *c, const void *density, ds_dtype dt);
 int tracer_blocks(int spp);  // partial sums per record
+// mask: when not NULL, only records with (mask[i] & mask_bits) == mask_bits are traced
+// (the others get 0)
 ds_status tracer_li(hipStream_t s, const ds_cloud *c, const TracerParams &tp, const float *pos,
                     const float *view, const float *light, int64_t P, int spp, uint64_t seed,
-                    double *partial, double *mean, double *var);
+                    double *partial, double *mean, double *var, const uint8_t *mask = nullptr,
+                    uint8_t mask_bits = 0);
+ds_status tracer_targets(hipStream_t s, const double *li, int64_t N, int64_t stride, float *t);
+ds_status tracer_accumulate(hipStream_t s, int64_t N, const uint8_t *hit, const float *direct,
+                            const float *li_net, const uint8_t *flags, const double *li_mc,
+                            float albedo, float E, double *sums, double *dsum,
+                            unsigned long long *n_fb);
+ds_status tracer_fill3(hipStream_t s, float *v, int64_t N, const float *xyz);
+ds_status tracer_zero(hipStream_t s, double *v, int64_t n);
+ds_status tracer_finish(hipStream_t s, const double *sums, int64_t N, int spp, double *mean,
+                        double *var);
 ds_status tracer_records(hipStream_t s, const ds_cloud *c, int64_t N, uint64_t seed, float *pos,
                          float *view, float *light, int32_t *attempts);
 ds_status tracer_render(hipStream_t s, const ds_cloud *c, const TracerParams &tp,

@@ -286,6 +286,7 @@ __device__ void segment_sums(double s1, double s2, int seg, bool write, double *
 __global__ void __launch_bounds__(kPaths) k_trace_li(Medium M, TracerParams tp, const float *pos,
                                                      const float *view, const float *light,
                                                      int64_t P, int spp, Split sp, uint64_t seed,
+                                                     const uint8_t *mask, uint8_t mask_bits,
                                                      double *partial)
 {
     const int64_t group = blockIdx.x / sp.nblk;
@@ -294,7 +295,8 @@ __global__ void __launch_bounds__(kPaths) k_trace_li(Medium M, TracerParams tp, 
     const int s = blk * sp.seg + (threadIdx.x & (sp.seg - 1));
     double e = 0.0;
     V3 w, wl;
-    if (rec < P && s < spp && unit(view + 3 * rec, w) && unit(light + 3 * rec, wl)) {
+    const bool wanted = rec < P && (!mask || (mask[rec] & mask_bits) == mask_bits);
+    if (wanted && s < spp && unit(view + 3 * rec, w) && unit(light + 3 * rec, wl)) {
         const V3 x = v3(pos[3 * rec], pos[3 * rec + 1], pos[3 * rec + 2]);
         Rng r;
         r.init(seed, ((uint64_t)rec << 20) + (uint64_t)s);
@@ -440,9 +442,9 @@ __global__ void __launch_bounds__(256) k_first_hits(Medium M, TracerParams tp, V
     pos[3 * i] = x.x;
     pos[3 * i + 1] = x.y;
     pos[3 * i + 2] = x.z;
-    view[3 * i] = -d.x;
-    view[3 * i + 1] = -d.y;
-    view[3 * i + 2] = -d.z;
+    view[3 * i] = h ? -d.x : 0.f;
+    view[3 * i + 1] = h ? -d.y : 0.f;
+    view[3 * i + 2] = h ? -d.z : 0.f;
     direct[i] = dir;
     hit[i] = h ? 1 : 0;
 }
@@ -495,6 +497,61 @@ __global__ void __launch_bounds__(256) k_philox(const uint32_t *ck, int64_t n, u
 #pragma unroll
     for (int j = 0; j < 4; ++j)
         out[4 * i + j] = r.buf[j];
+}
+
+// Training targets: t = log(1 + L_i) in FP32 at record stride `stride`.
+__global__ void __launch_bounds__(256) k_targets(const double *li, int64_t N, int64_t stride,
+                                                 float *t)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N)
+        t[i * stride] = log1pf((float)li[i]);
+}
+
+// One camera sample per pixel added to the pixel sums (Sec. 4.4): radiance
+// direct + albedo * E * L_i at a collision, with L_i from the network or, where
+// the stencil leaves the grid (fallback flag), from the path-traced estimate; 0 for
+// rays that escape.  sums holds (sum, sum of squares) per pixel in FP64; dsum the
+// sum of the direct term alone.
+__global__ void __launch_bounds__(256) k_accumulate(int64_t N, const uint8_t *hit,
+                                                    const float *direct, const float *li_net,
+                                                    const uint8_t *flags, const double *li_mc,
+                                                    float albedo, float E, double *sums,
+                                                    double *dsum, unsigned long long *n_fb)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N)
+        return;
+    double e = 0.0, d = 0.0;
+    if (hit[i]) {
+        const bool fb = li_mc && (flags[i] & DS_FLAG_FALLBACK);
+        const double li = fb ? li_mc[i] : (double)E * (double)li_net[i];
+        d = (double)direct[i];
+        e = d + (double)albedo * li;
+        if (fb && n_fb)
+            atomicAdd(n_fb, 1ull);
+    }
+    sums[2 * i] += e;
+    sums[2 * i + 1] += e * e;
+    if (dsum)
+        dsum[2 * i] += d;
+}
+
+__global__ void __launch_bounds__(256) k_fill3(float *v, int64_t N, float x, float y, float z)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) {
+        v[3 * i] = x;
+        v[3 * i + 1] = y;
+        v[3 * i + 2] = z;
+    }
+}
+
+__global__ void __launch_bounds__(256) k_zero64(double *v, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        v[i] = 0.0;
 }
 
 Medium medium(const ds_cloud *c)
@@ -566,11 +623,12 @@ ds_status tracer_prepare(ds_cloud *c, const void *density, ds_dtype dt)
 
 ds_status tracer_li(hipStream_t s, const ds_cloud *c, const TracerParams &tp, const float *pos,
                     const float *view, const float *light, int64_t P, int spp, uint64_t seed,
-                    double *partial, double *mean, double *var)
+                    double *partial, double *mean, double *var, const uint8_t *mask,
+                    uint8_t mask_bits)
 {
     const Split sp = split(spp);
     k_trace_li<<<grid_of(P, sp), kPaths, 0, s>>>(medium(c), tp, pos, view, light, P, spp, sp,
-                                                  seed, partial);
+                                                  seed, mask, mask_bits, partial);
     DS_HIP(hipGetLastError());
     return reduce_records(s, partial, P, sp.nblk, spp, mean, var);
 }
@@ -619,6 +677,45 @@ ds_status philox_blocks(hipStream_t s, const uint32_t *ctr_key, int64_t n, uint3
     k_philox<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(ctr_key, n, out);
     DS_HIP(hipGetLastError());
     return DS_OK;
+}
+
+ds_status tracer_targets(hipStream_t s, const double *li, int64_t N, int64_t stride, float *t)
+{
+    k_targets<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(li, N, stride, t);
+    DS_HIP(hipGetLastError());
+    return DS_OK;
+}
+
+ds_status tracer_accumulate(hipStream_t s, int64_t N, const uint8_t *hit, const float *direct,
+                            const float *li_net, const uint8_t *flags, const double *li_mc,
+                            float albedo, float E, double *sums, double *dsum,
+                            unsigned long long *n_fb)
+{
+    k_accumulate<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(N, hit, direct, li_net, flags, li_mc,
+                                                             albedo, E, sums, dsum, n_fb);
+    DS_HIP(hipGetLastError());
+    return DS_OK;
+}
+
+ds_status tracer_fill3(hipStream_t s, float *v, int64_t N, const float *xyz)
+{
+    k_fill3<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(v, N, xyz[0], xyz[1], xyz[2]);
+    DS_HIP(hipGetLastError());
+    return DS_OK;
+}
+
+ds_status tracer_zero(hipStream_t s, double *v, int64_t n)
+{
+    int64_t b = (n + 255) / 256;
+    k_zero64<<<(unsigned)(b > 4096 ? 4096 : (b < 1 ? 1 : b)), 256, 0, s>>>(v, n);
+    DS_HIP(hipGetLastError());
+    return DS_OK;
+}
+
+ds_status tracer_finish(hipStream_t s, const double *sums, int64_t N, int spp, double *mean,
+                        double *var)
+{
+    return reduce_records(s, sums, N, 1, spp, mean, var);
 }
 
 int tracer_blocks(int spp) { return split(spp).nblk; }

@@ -209,16 +209,27 @@ def n_params(K: int, W: int, H: int = 3) -> int:
     return sum(r * (c if c else 1) for _, r, c in layer_shapes(K, W, H))
 
 
-def init_params(K: int, W: int, H: int, seed: int, bias: float = 0.0) -> np.ndarray:
-    """He-uniform weights (bound sqrt(6 / fan_in)), constant biases; float32 vector."""
+def init_params(K: int, W: int, H: int, seed: int, bias: float = 0.0, branch_scale: float = 1.0,
+                out_scale: float = 1.0, out_bias: float | None = None) -> np.ndarray:
+    """He-uniform weights (bound sqrt(6 / fan_in)), constant biases; float32 vector.
+    For training runs: branch_scale multiplies the second matrix of every residual
+    block (keeps the residual stream from growing with depth), out_scale the final
+    layer's weights, and out_bias sets the final bias (a starting prediction that
+    keeps the output unit alive)."""
     rng = np.random.default_rng(seed)
     parts = []
     for name, r, c in layer_shapes(K, W, H):
         if c == 0:
-            parts.append(np.full(r, bias, dtype=np.float64))
+            v = out_bias if (name == f"bh{H - 1}" and out_bias is not None) else bias
+            parts.append(np.full(r, v, dtype=np.float64))
         else:
             b = math.sqrt(6.0 / c)
-            parts.append(rng.uniform(-b, b, size=r * c))
+            w = rng.uniform(-b, b, size=r * c)
+            if name.startswith("W2_"):
+                w = w * branch_scale
+            if name == f"Wh{H - 1}":
+                w = w * out_scale
+            parts.append(w)
     return np.concatenate(parts).astype(np.float32)
 
 

@@ -1,0 +1,232 @@
+"""The learned part on the GPU (Sec. 4.4, 5.1, 5.2): training pairs, the network
+renderer and its fallback against the FP64 oracle, then a short training run whose
+network must beat the renderer without it (direct light only) against a path-traced
+reference on a cloud it never saw."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1709_05418_amd as ds
+from paper_1709_05418_amd import learn, synth
+from _util import Workload, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+M64 = (1 << 64) - 1
+
+
+def derived_key(seed, which):
+    """The path-tracing key ds_make_records / ds_render_rpnn derive from a seed
+    (SplitMix64 finaliser of seed + golden-ratio increment * (which + 1))."""
+    z = (seed + 0x9E3779B97F4A7C15 * (which + 1)) & M64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+    return z ^ (z >> 31)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = ds.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def small():
+    return Workload(32, 32.0, L=5, K=5, P=8, seed_cloud=4, seed_pts=21)
+
+
+@pytest.fixture(scope="module")
+def small_cloud(ctx, small):
+    c = ds.Cloud(ctx, small.density.cuda(), small.sigma_max, small.aabb_min, small.h0, small.L,
+                 small.K, small.mips)
+    yield c
+    c.close()
+
+
+def _cuda(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _rays(res, seed, crop=False):
+    rng = np.random.default_rng(seed)
+    px, py = np.meshgrid(np.arange(res), np.arange(res))
+    px, py = px.reshape(-1), py.reshape(-1)
+    cam = np.array([0.0, 0.12, 2.3])
+    full = 2 * res if crop else res
+    off = res // 2 if crop else 0
+    d = synth.camera_rays(full, cam, (0, 0, 0), 42.0, px + off, py + off, rng.random(px.size),
+                          rng.random(px.size))
+    return np.broadcast_to(cam, d.shape).astype(np.float32).copy(), d.astype(np.float32)
+
+
+def test_first_hits_follow_the_oracle_streams(ctx, small_cloud, small):
+    o, d = _rays(20, 3)
+    ld = synth.table1_lights()["side"]
+    prm = ds.TracerParams(0.95, 0.85, 2.0, 0, 0)
+    for s in (0, 5):
+        pos, view, direct, hit = (t.cpu().numpy() for t in ds.ds_first_hits(
+            ctx.h, small_cloud.h, prm, ld, _cuda(o), _cuda(d), seed=12, sample=s))
+        po, vo, do, ho = O.first_hits(small.grid, o, d, ld, albedo=0.95, g=0.85, irradiance=2.0,
+                                      seed=12, sample=s)
+        same = (hit == ho) & (np.linalg.norm(pos - po, axis=1) < 1e-4)
+        assert same.mean() > 0.97, same.mean()
+        h = same & (ho == 1)
+        assert np.abs(view[h] - vo[h]).max() < 1e-6
+        assert np.all(view[hit == 0] == 0) and np.all(direct[hit == 0] == 0)
+        # the same ratio-tracking steps: direct terms agree to rounding on most rays
+        rel = np.abs(direct[h] - do[h]) / np.maximum(do[h], 1e-6)
+        assert np.median(rel) < 1e-4
+
+
+def test_make_records_match_oracle(ctx, small_cloud, small):
+    N, spp, seed, stride, off = 600 + 7, 32, 41, 3, 1
+    prm = ds.TracerParams(0.95, 0.85, 1.0, 0, 0)
+    D = 225 * small.K + 1
+    z = torch.full((off + (N - 1) * stride + 1, D), -7.0, dtype=torch.float32, device="cuda")
+    t = torch.full((z.shape[0],), -7.0, dtype=torch.float32, device="cuda")
+    (pos, view, light), (m, v) = ds.ds_make_records(ctx.h, small_cloud.h, prm, N, spp, seed, z, t,
+                                                   offset=off, stride=stride, want_records=True,
+                                                   want_li=True)
+    zc, tc = z.cpu().numpy(), t.cpu().numpy()
+    pos, view, light, m, v = (a.cpu().numpy() for a in (pos, view, light, m, v))
+    rows = off + stride * np.arange(N)
+    untouched = np.setdiff1d(np.arange(z.shape[0]), rows)
+    assert np.all(zc[untouched] == -7.0) and np.all(tc[untouched] == -7.0)
+    # the stored target is log(1 + L_i) of the stored estimate
+    assert np.allclose(tc[rows], np.log1p(m.astype(np.float32)), rtol=1e-6, atol=1e-7)
+    # records and estimates against the oracle on the same streams
+    po, vo, lo, _ = O.sample_records(small.grid, N, seed)
+    mo, vo2 = O.trace_li(small.grid, po, vo, lo, albedo=0.95, g=0.85, spp=spp,
+                         seed=derived_key(seed, 0))
+    same = np.linalg.norm(pos - po, axis=1) < 1e-4
+    assert same.mean() > 0.97
+    tol = 5 * np.sqrt(v + vo2) + 1e-7
+    assert np.all(np.abs(m - mo)[same] <= tol[same])
+    assert np.median(np.abs(m - mo)[same] / np.maximum(mo[same], 1e-6)) < 1e-3
+    # descriptors of matching records against the oracle's gather at its own records
+    pyr, dims, offs = small.pyr
+    zo, _ = O.gather(small.grid, pyr, dims, offs, small.mean, small.K, small.mips, po[same],
+                     vo[same], lo[same])
+    assert rel_l2(zc[rows][same], zo) < 1e-4
+
+
+def _net(ctx, K, W, seed=5):
+    net = ds.Net(ctx, K, W, 3)
+    theta = synth.init_params(K, W, 3, seed, branch_scale=0.3, out_scale=0.05, out_bias=0.1)
+    net.set_params(theta)
+    return net, theta
+
+
+@pytest.mark.parametrize("prec,tol", [(ds.DS_PREC_F32, 1e-4), (ds.DS_PREC_BF16, 2e-2)])
+def test_render_rpnn_matches_oracle_composition(ctx, small_cloud, small, prec, tol):
+    o, d = _rays(14, 8)
+    ld = synth.table1_lights()["back"]
+    prm = ds.TracerParams(0.9, 0.85, 1.5, 0, 0)
+    S, seed = 3, 19
+    net, theta = _net(ctx, small.K, 32)
+    try:
+        img, var, direct, _ = ds.ds_render_rpnn(ctx.h, small_cloud.h, net.h, prec, prm, ld,
+                                                _cuda(o), _cuda(d), S, seed, fallback_spp=0)
+        img, direct = img.cpu().numpy(), direct.cpu().numpy()
+    finally:
+        net.close()
+    # oracle: the same camera samples, then direct + albedo * E * g(descriptor).
+    # A camera sample whose FP32 path left the FP64 one (a collision decided by
+    # rounding) changes its pixel; such pixels are compared only statistically.
+    N = o.shape[0]
+    acc = np.zeros(N)
+    dacc = np.zeros(N)
+    same = np.ones(N, bool)
+    pyr, dims, offs = small.pyr
+    for s in range(S):
+        po, vo, do, ho = O.first_hits(small.grid, o, d, ld, albedo=0.9, g=0.85, irradiance=1.5,
+                                      seed=seed, sample=s)
+        pg, _, _, hg = (t.cpu().numpy() for t in ds.ds_first_hits(
+            ctx.h, small_cloud.h, prm, ld, _cuda(o), _cuda(d), seed=seed, sample=s))
+        same &= (hg == ho) & (np.linalg.norm(pg - po, axis=1) < 1e-4)
+        h = ho == 1
+        li = np.zeros(N)
+        if h.any():
+            lt = np.broadcast_to(np.asarray(ld, np.float64), (h.sum(), 3))
+            z, _ = O.gather(small.grid, pyr, dims, offs, small.mean, small.K, small.mips, po[h],
+                            vo[h], lt)
+            li[h], _ = O.forward(theta.astype(np.float64), small.K, 32, 3, z)
+        acc += np.where(h, do + 0.9 * 1.5 * li, 0.0)
+        dacc += np.where(h, do, 0.0)
+    ref, dref = acc / S, dacc / S
+    assert same.mean() > 0.9, same.mean()
+    assert rel_l2(direct[same], dref[same]) < 1e-3
+    assert rel_l2(img[same], ref[same]) < tol
+
+
+def test_render_rpnn_fallback(ctx):
+    # a cloud that fills its box: many first collisions near the faces have stencils
+    # leaving the grid and take path-traced L_i
+    w = Workload(32, 32.0, L=5, K=5, P=1, seed_cloud=9)
+    d = 0.6 + 0.4 * w.density
+    cloud = ds.Cloud(ctx, d.cuda(), 32.0, w.aabb_min, w.h0, 5, 5)
+    net, _ = _net(ctx, 5, 32)
+    try:
+        o, dd = _rays(16, 2)
+        ld = synth.table1_lights()["side"]
+        prm = ds.TracerParams(0.95, 0.85, 1.0, 0, 0)
+        a, _, _, nfb = ds.ds_render_rpnn(ctx.h, cloud.h, net.h, ds.DS_PREC_BF16, prm, ld,
+                                         _cuda(o), _cuda(dd), 4, 3, fallback_spp=16,
+                                         count_fallback=True)
+        b, _, _, nfb0 = ds.ds_render_rpnn(ctx.h, cloud.h, net.h, ds.DS_PREC_BF16, prm, ld,
+                                          _cuda(o), _cuda(dd), 4, 3, fallback_spp=0,
+                                          count_fallback=True)
+        # the fallback count is the number of colliding samples whose flag says so
+        want = 0
+        for s in range(4):
+            pos, view, _, hit = ds.ds_first_hits(ctx.h, cloud.h, prm, ld, _cuda(o), _cuda(dd),
+                                                 seed=3, sample=s)
+            lt = torch.from_numpy(np.broadcast_to(np.float32(ld), (o.shape[0], 3)).copy()).cuda()
+            _, _, fl = ds.ds_predict(ctx.h, cloud.h, net.h, ds.DS_PREC_BF16, pos, view, lt)
+            want += int(((fl & ds.DS_FLAG_FALLBACK) != 0)[hit == 1].sum())
+        assert nfb == want and nfb > 0 and nfb0 == 0
+        assert not torch.equal(a, b)
+    finally:
+        net.close()
+        cloud.close()
+
+
+def test_trained_network_beats_direct_light_only(ctx):
+    # training pairs from four seeded clouds, a short run of Adam, and a view of a
+    # fifth cloud: the network image must be far closer to the path-traced one than
+    # the same renderer without the network
+    n, sig, L, K, W = 48, 48.0, 6, 6, 64
+    prm = ds.TracerParams(0.999, 0.85, 1.0, 0, 0)
+    clouds = []
+    try:
+        for c in range(5):
+            d = synth.cloud_density(n, 500 + c, worley=0.3, device="cuda")
+            amin, h0 = synth.unit_box(n)
+            clouds.append(ds.Cloud(ctx, d, sig, amin, h0, L, K))
+        print("clouds built", flush=True)
+        z, t = learn.make_dataset(ctx, clouds[:4], 32768, 128, 1000, prm)
+        li_mean = float(torch.expm1(t).mean())
+        net = ds.Net(ctx, K, W, 3)
+        net.set_params(synth.init_params(K, W, 3, 3, branch_scale=1 / np.sqrt(K), out_scale=0.01,
+                                         out_bias=li_mean))
+        opt = ds.ds_adam_create(net.h, 1e-3)
+        try:
+            res = learn.train(net, opt, z, t, 2000, 1024, 0.25, eval_every=1000,
+                              log=lambda m: print(m, flush=True))
+            v0, v1 = res["held_out"][0][1], res["held_out"][-1][1]
+            assert v1 < 0.25 * v0, res["held_out"]
+            o, dd = _rays(40, 1, crop=True)
+            ld = synth.table1_lights()["side"]
+            j = learn.judge(ctx, clouds[4], net, ds.DS_PREC_BF16, prm, ld, _cuda(o), _cuda(dd),
+                            16, 512, 77, fallback_spp=32)
+            print({k: v for k, v in j.items() if not hasattr(v, "shape")}, flush=True)
+            assert j["ref_noise_rel"] < 0.02
+            assert j["rel_l1"] < 0.4 and j["rel_l1"] < 0.5 * j["rel_l1_direct_only"]
+        finally:
+            ds.ds_adam_destroy(opt)
+            net.close()
+    finally:
+        for c in clouds:
+            c.close()
