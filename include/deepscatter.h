@@ -179,6 +179,53 @@ ds_status ds_predict(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
                      const float *light_dir, int64_t P, float *out, float *pre_out,
                      uint8_t *flags);
 
+/* ---------------------------------------------------------------- batched prediction */
+/* Uneven sets of shading points from several clouds (each with its own pyramid,
+ * all with the network's K) in one persistent launch of the fused kernel: the
+ * points of every cloud are cut into tiles of 16 * waves points, a tile never
+ * spans two clouds, and the workgroups walk the tiles of all clouds.  A batch
+ * plan fixes the clouds and the per-cloud point ranges; the arrays are given per
+ * call.  Kernel variants: */
+#define DS_KERNEL_REGISTER 0  /* residual stream in registers, one chunk of samples in flight */
+#define DS_KERNEL_PIPELINED 1 /* residual stream in LDS, the next chunk's samples in flight  */
+typedef struct ds_batch ds_batch;
+
+/* n_clouds (1..16) clouds; the points of cloud c are rows offsets[c] ..
+ * offsets[c+1]-1 of the concatenated point arrays (offsets: host, n_clouds + 1
+ * non-decreasing values, offsets[0] = 0).  The plan keeps the cloud and network
+ * handles (they must outlive it) and starts with the variant ds_predict uses
+ * (DS_KERNEL_REGISTER, 4 waves, one workgroup per tile). */
+ds_status ds_batch_create(ds_ctx *ctx, const ds_net *net, int n_clouds,
+                          const ds_cloud *const *clouds, const int64_t *offsets, ds_batch **out);
+ds_status ds_batch_destroy(ds_batch *batch);
+/* Kernel variant of the plan: kernel DS_KERNEL_*, waves 4 or 8 (8 needs W <= 240),
+ * grid 0 (one workgroup per tile) or the number of persistent workgroups.
+ * Setting a variant drops a captured graph. */
+ds_status ds_batch_set_config(ds_batch *batch, int32_t kernel, int32_t waves, int32_t grid);
+/* Current variant and, after ds_batch_autotune, its measured time in ms (else -1). */
+ds_status ds_batch_get_config(const ds_batch *batch, int32_t *kernel, int32_t *waves,
+                              int32_t *grid, float *ms);
+/* Prediction for all clouds of the plan: as ds_predict per cloud, on the
+ * concatenated arrays (device, offsets[n] points).  DS_PREC_BF16 (and DS_PREC_FP8
+ * once quantised) runs one launch; DS_PREC_F32 runs the plain form per cloud. */
+ds_status ds_batch_predict(ds_batch *batch, ds_precision precision, const float *pos,
+                           const float *view_dir, const float *light_dir, float *out,
+                           float *pre_out, uint8_t *flags);
+/* Times every available variant (kernel x waves x grid in {one per tile, 1, 2, 4
+ * workgroups per compute unit}) on these arrays, `reps` launches each after one
+ * warm-up, keeps the fastest and drops a captured graph.  Synchronises; writes
+ * out.  Results depend on the arrays' contents only through timing. */
+ds_status ds_batch_autotune(ds_batch *batch, ds_precision precision, const float *pos,
+                            const float *view_dir, const float *light_dir, float *out, int reps);
+/* Records the plan's launch for these arrays into a HIP graph (captured on a
+ * stream of the plan's own) and instantiates it; ds_batch_replay enqueues the
+ * graph on the context's stream.  The arrays must stay valid while the graph is
+ * replayed.  Fused precisions only (DS_ERR_UNSUPPORTED for DS_PREC_F32). */
+ds_status ds_batch_capture(ds_batch *batch, ds_precision precision, const float *pos,
+                           const float *view_dir, const float *light_dir, float *out,
+                           float *pre_out, uint8_t *flags);
+ds_status ds_batch_replay(ds_batch *batch);
+
 /* ---------------------------------------------------------------- training (Sec. 5.2) */
 /* Adam (Kingma and Ba; the paper uses the default learning rate and decay rates:
  * lr 1e-3, beta1 0.9, beta2 0.999, eps 1e-8) on the network's FP32 master

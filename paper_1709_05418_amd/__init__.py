@@ -25,6 +25,7 @@ DS_F32, DS_BF16 = 0, 1
 DS_PREC_F32, DS_PREC_BF16, DS_PREC_FP8 = 0, 1, 2
 DS_FLAG_INVALID, DS_FLAG_OUTSIDE, DS_FLAG_FALLBACK = 1, 2, 4
 DS_LIGHT_DIRECTIONAL, DS_LIGHT_ENVIRONMENT = 0, 1
+DS_KERNEL_REGISTER, DS_KERNEL_PIPELINED = 0, 1
 STENCIL_N = 225
 
 _lib = None
@@ -76,6 +77,14 @@ def lib():
         "ds_render_mc": (S, [P, P, P, P, P, P, I64, I, C.c_uint64, P, P]),
         "ds_first_hits": (S, [P, P, P, P, P, P, I64, C.c_uint64, C.c_uint64, P, P, P, P]),
         "ds_philox4x32_10": (S, [P, P, I64, P]),
+        "ds_batch_create": (S, [P, P, I, P, P, P]),
+        "ds_batch_destroy": (S, [P]),
+        "ds_batch_set_config": (S, [P, S, S, S]),
+        "ds_batch_get_config": (S, [P, P, P, P, P]),
+        "ds_batch_predict": (S, [P, I, P, P, P, P, P, P]),
+        "ds_batch_autotune": (S, [P, I, P, P, P, P, I]),
+        "ds_batch_capture": (S, [P, I, P, P, P, P, P, P]),
+        "ds_batch_replay": (S, [P]),
         "ds_make_records": (S, [P, P, P, I64, I, C.c_uint64, I64, P, P, P, P, P, P, P]),
         "ds_render_rpnn": (S, [P, P, P, I, P, P, P, P, I64, I, C.c_uint64, I, P, P, P, P]),
     }
@@ -378,6 +387,54 @@ def ds_first_hits(ctx, cloud, params: TracerParams, light_dir, ray_o, ray_d, see
                                int(seed), int(sample), _ptr(pos), _ptr(view), _ptr(direct),
                                _ptr(hit)))
     return pos, view, direct, hit
+
+
+def ds_batch_create(ctx, net, clouds, offsets):
+    """clouds: list of cloud handles; offsets: n + 1 row offsets into the concatenated
+    point arrays."""
+    n = len(clouds)
+    arr = (C.c_void_p * n)(*[c.value if isinstance(c, C.c_void_p) else c for c in clouds])
+    off = (C.c_int64 * (n + 1))(*[int(v) for v in offsets])
+    h = C.c_void_p()
+    _check(lib().ds_batch_create(ctx, net, n, arr, off, C.byref(h)))
+    return h
+
+
+def ds_batch_destroy(batch):
+    _check(lib().ds_batch_destroy(batch))
+
+
+def ds_batch_set_config(batch, kernel, waves, grid):
+    _check(lib().ds_batch_set_config(batch, int(kernel), int(waves), int(grid)))
+
+
+def ds_batch_get_config(batch):
+    k, w, g, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_float()
+    _check(lib().ds_batch_get_config(batch, C.byref(k), C.byref(w), C.byref(g), C.byref(ms)))
+    return {"kernel": k.value, "waves": w.value, "grid": g.value, "ms": ms.value}
+
+
+def ds_batch_predict(batch, precision, pos, view_dir, light_dir, out, pre=None, flags=None):
+    P = pos.shape[0]
+    _check(lib().ds_batch_predict(batch, int(precision), _pts(pos), _pts(view_dir, P),
+                                  _pts(light_dir, P), _ptr(out), _ptr(pre), _ptr(flags)))
+
+
+def ds_batch_autotune(batch, precision, pos, view_dir, light_dir, out, reps=3):
+    P = pos.shape[0]
+    _check(lib().ds_batch_autotune(batch, int(precision), _pts(pos), _pts(view_dir, P),
+                                   _pts(light_dir, P), _ptr(out), int(reps)))
+    return ds_batch_get_config(batch)
+
+
+def ds_batch_capture(batch, precision, pos, view_dir, light_dir, out, pre=None, flags=None):
+    P = pos.shape[0]
+    _check(lib().ds_batch_capture(batch, int(precision), _pts(pos), _pts(view_dir, P),
+                                  _pts(light_dir, P), _ptr(out), _ptr(pre), _ptr(flags)))
+
+
+def ds_batch_replay(batch):
+    _check(lib().ds_batch_replay(batch))
 
 
 def ds_make_records(ctx, cloud, params: TracerParams, N, spp, seed, z, target, offset=0,

@@ -628,6 +628,40 @@ static const FusedLevel *fused_table(const ds_cloud *c)
     return reinterpret_cast<const FusedLevel *>(static_cast<const char *>(c->tables) + foff);
 }
 
+static const FusedVariant kDefaultVariant = {DS_KERNEL_REGISTER, 4, 0};
+
+static void fused_args(const float *pos, const float *view, const float *light, float *out,
+                       float *pre, uint8_t *flags, int K, int W, int H, FusedArgs &a)
+{
+    a.pos = pos;
+    a.view = view;
+    a.light = light;
+    a.out = out;
+    a.pre = pre;
+    a.flags = flags;
+    a.K = K;
+    a.W = W;
+    a.H = H;
+    a.n_clouds = 0;
+    a.n_tiles = 0;
+}
+
+// Appends a cloud whose points are rows [p_begin, p_begin + P) of the point arrays.
+static void add_cloud(FusedArgs &a, const ds_cloud *c, int64_t p_begin, int64_t P)
+{
+    FusedCloud &f = a.cl[a.n_clouds++];
+    GatherArgs ga;
+    gather_args(c, nullptr, nullptr, nullptr, 0, ga);
+    f.lvt = fused_table(c);
+    memcpy(f.amin, ga.amin, sizeof(f.amin));
+    memcpy(f.amax, ga.amax, sizeof(f.amax));
+    f.inv_mean = ga.inv_mean;
+    f.pad_ = 0;
+    f.p_begin = p_begin;
+    f.P = P;
+    f.tile_begin = 0;
+}
+
 ds_status ds_cloud_info(const ds_cloud *c, double *mean_mu_t, int *n_levels, int *dims,
                         int *mip_of_level, int *K)
 {
@@ -793,17 +827,9 @@ ds_status ds_gather_packed(ds_ctx *ctx, const ds_cloud *cloud, const float *pos,
     DS_CHECK(pos && view_dir && light_dir && z_out, DS_ERR_INVALID_ARG,
              "ds_gather_packed: NULL device pointer");
     FusedArgs a = {};
-    GatherArgs ga;
-    gather_args(cloud, pos, view_dir, light_dir, P, ga);
-    a.pos = pos;
-    a.view = view_dir;
-    a.light = light_dir;
-    a.P = P;
-    memcpy(a.amin, ga.amin, sizeof(a.amin));
-    memcpy(a.amax, ga.amax, sizeof(a.amax));
-    a.inv_mean = ga.inv_mean;
-    a.K = cloud->K;
-    return fused_gather_packed(ctx->stream, a, fused_table(cloud), z_out);
+    fused_args(pos, view_dir, light_dir, nullptr, nullptr, nullptr, cloud->K, 0, 0, a);
+    add_cloud(a, cloud, 0, P);
+    return fused_gather_packed(ctx->stream, a, z_out);
 }
 
 ds_status ds_forward(ds_ctx *ctx, const ds_net *net, const float *z, int64_t P, float *out,
@@ -869,22 +895,9 @@ ds_status ds_predict(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
     if (precision == DS_PREC_BF16) {
         DS_CHECK(net->frag_bf16, DS_ERR_STATE, "ds_predict: network parameters were never set");
         FusedArgs a = {};
-        GatherArgs ga;
-        gather_args(cloud, pos, view_dir, light_dir, P, ga);
-        a.pos = pos;
-        a.view = view_dir;
-        a.light = light_dir;
-        a.P = P;
-        a.out = out;
-        a.pre = pre_out;
-        a.flags = flags;
-        memcpy(a.amin, ga.amin, sizeof(a.amin));
-        memcpy(a.amax, ga.amax, sizeof(a.amax));
-        a.inv_mean = ga.inv_mean;
-        a.K = net->K;
-        a.W = net->W;
-        a.H = net->H;
-        return fused_predict_bf16(ctx->stream, net, a, fused_table(cloud));
+        fused_args(pos, view_dir, light_dir, out, pre_out, flags, net->K, net->W, net->H, a);
+        add_cloud(a, cloud, 0, P);
+        return fused_predict_bf16(ctx->stream, net, a, kDefaultVariant);
     }
     if (precision == DS_PREC_FP8) {
         set_error("ds_predict: FP8 weights are not available for this network");
@@ -892,6 +905,251 @@ ds_status ds_predict(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
     }
     set_error("ds_predict: unknown precision %d", (int)precision);
     return DS_ERR_INVALID_ARG;
+}
+
+// ---------------------------------------------------------------- batched prediction
+static void batch_args(const ds_batch *b, const float *pos, const float *view, const float *light,
+                       float *out, float *pre, uint8_t *flags, FusedArgs &a)
+{
+    fused_args(pos, view, light, out, pre, flags, b->net->K, b->net->W, b->net->H, a);
+    for (int c = 0; c < b->n; ++c)
+        add_cloud(a, b->clouds[c], b->offsets[c], b->offsets[c + 1] - b->offsets[c]);
+}
+
+static void batch_drop_graph(ds_batch *b)
+{
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+}
+
+static ds_status batch_fused(ds_batch *b, hipStream_t s, ds_precision prec, const float *pos,
+                             const float *view, const float *light, float *out, float *pre,
+                             uint8_t *flags, const FusedVariant &v)
+{
+    DS_CHECK(prec == DS_PREC_BF16, prec == DS_PREC_FP8 ? DS_ERR_STATE : DS_ERR_INVALID_ARG,
+             "batched launch: precision %d is not available for this network", (int)prec);
+    DS_CHECK(b->net->frag_bf16, DS_ERR_STATE, "batched launch: network parameters never set");
+    FusedArgs a = {};
+    batch_args(b, pos, view, light, out, pre, flags, a);
+    return fused_predict_bf16(s, b->net, a, v);
+}
+
+ds_status ds_batch_create(ds_ctx *ctx, const ds_net *net, int n_clouds,
+                          const ds_cloud *const *clouds, const int64_t *offsets, ds_batch **out)
+{
+    DS_CHECK(ctx && net && clouds && offsets && out, DS_ERR_INVALID_ARG,
+             "ds_batch_create: NULL argument");
+    DS_CHECK(n_clouds >= 1 && n_clouds <= kMaxBatch, DS_ERR_INVALID_ARG,
+             "ds_batch_create: n_clouds %d outside 1..%d", n_clouds, kMaxBatch);
+    DS_CHECK(offsets[0] == 0, DS_ERR_INVALID_ARG, "ds_batch_create: offsets[0] must be 0");
+    for (int c = 0; c < n_clouds; ++c) {
+        DS_CHECK(clouds[c], DS_ERR_INVALID_ARG, "ds_batch_create: cloud %d is NULL", c);
+        DS_CHECK(clouds[c]->K == net->K, DS_ERR_INVALID_ARG,
+                 "ds_batch_create: cloud %d has %d stencil levels, the network %d", c,
+                 clouds[c]->K, net->K);
+        DS_CHECK(offsets[c + 1] >= offsets[c], DS_ERR_INVALID_ARG,
+                 "ds_batch_create: offsets must not decrease");
+    }
+    DS_CHECK(offsets[n_clouds] <= ((int64_t)1 << 31), DS_ERR_INVALID_ARG,
+             "ds_batch_create: more than 2^31 points");
+    ds_batch *b = new (std::nothrow) ds_batch();
+    DS_CHECK(b, DS_ERR_OOM, "ds_batch_create: out of host memory");
+    b->ctx = ctx;
+    b->net = net;
+    b->n = n_clouds;
+    for (int c = 0; c < n_clouds; ++c)
+        b->clouds[c] = clouds[c];
+    memcpy(b->offsets, offsets, sizeof(int64_t) * (n_clouds + 1));
+    b->kind = kDefaultVariant.kind;
+    b->waves = kDefaultVariant.waves;
+    b->grid = kDefaultVariant.grid;
+    *out = b;
+    return DS_OK;
+}
+
+ds_status ds_batch_destroy(ds_batch *b)
+{
+    if (!b)
+        return DS_OK;
+    batch_drop_graph(b);
+    if (b->cap_stream)
+        (void)hipStreamDestroy(b->cap_stream);
+    delete b;
+    return DS_OK;
+}
+
+ds_status ds_batch_set_config(ds_batch *b, int32_t kernel, int32_t waves, int32_t grid)
+{
+    DS_CHECK(b, DS_ERR_INVALID_ARG, "ds_batch_set_config: batch is NULL");
+    FusedVariant v = {kernel, waves, grid};
+    DS_CHECK(fused_variant_ok(b->net, v), DS_ERR_INVALID_ARG,
+             "ds_batch_set_config: variant (kernel %d, %d waves, grid %d) not available", kernel,
+             waves, grid);
+    b->kind = kernel;
+    b->waves = waves;
+    b->grid = grid;
+    b->tuned_ms = -1.f;
+    batch_drop_graph(b);
+    return DS_OK;
+}
+
+ds_status ds_batch_get_config(const ds_batch *b, int32_t *kernel, int32_t *waves, int32_t *grid,
+                              float *ms)
+{
+    DS_CHECK(b, DS_ERR_INVALID_ARG, "ds_batch_get_config: batch is NULL");
+    if (kernel)
+        *kernel = b->kind;
+    if (waves)
+        *waves = b->waves;
+    if (grid)
+        *grid = b->grid;
+    if (ms)
+        *ms = b->tuned_ms;
+    return DS_OK;
+}
+
+ds_status ds_batch_predict(ds_batch *b, ds_precision precision, const float *pos,
+                           const float *view_dir, const float *light_dir, float *out,
+                           float *pre_out, uint8_t *flags)
+{
+    DS_CHECK(b, DS_ERR_INVALID_ARG, "ds_batch_predict: batch is NULL");
+    const int64_t total = b->offsets[b->n];
+    if (total == 0)
+        return DS_OK;
+    DS_CHECK(pos && view_dir && light_dir && out, DS_ERR_INVALID_ARG,
+             "ds_batch_predict: NULL device pointer");
+    DS_HIP(hipSetDevice(b->ctx->device));
+    if (precision == DS_PREC_F32) {
+        for (int c = 0; c < b->n; ++c) {
+            const int64_t o = b->offsets[c], P = b->offsets[c + 1] - o;
+            ds_status st = ds_predict(b->ctx, b->clouds[c], b->net, DS_PREC_F32, pos + 3 * o,
+                                      view_dir + 3 * o, light_dir + 3 * o, P, out + o,
+                                      pre_out ? pre_out + o : nullptr, flags ? flags + o : nullptr);
+            if (st)
+                return st;
+        }
+        return DS_OK;
+    }
+    return batch_fused(b, b->ctx->stream, precision, pos, view_dir, light_dir, out, pre_out, flags,
+                       FusedVariant{b->kind, b->waves, b->grid});
+}
+
+ds_status ds_batch_autotune(ds_batch *b, ds_precision precision, const float *pos,
+                            const float *view_dir, const float *light_dir, float *out, int reps)
+{
+    DS_CHECK(b, DS_ERR_INVALID_ARG, "ds_batch_autotune: batch is NULL");
+    DS_CHECK(reps >= 1 && reps <= 1000, DS_ERR_INVALID_ARG, "ds_batch_autotune: reps 1..1000");
+    DS_CHECK(precision != DS_PREC_F32, DS_ERR_UNSUPPORTED,
+             "ds_batch_autotune: only the fused precisions have variants");
+    if (b->offsets[b->n] == 0)
+        return DS_OK;
+    DS_CHECK(pos && view_dir && light_dir && out, DS_ERR_INVALID_ARG,
+             "ds_batch_autotune: NULL device pointer");
+    DS_HIP(hipSetDevice(b->ctx->device));
+    int cus = 0;
+    DS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->ctx->device));
+    hipStream_t s = b->ctx->stream;
+    hipEvent_t e0, e1;
+    DS_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return hip_fail(hipErrorOutOfMemory, "ds_batch_autotune: event");
+    }
+    ds_status st = DS_OK;
+    float best = -1.f;
+    FusedVariant bestv = {b->kind, b->waves, b->grid};
+    const int grids[4] = {0, cus, 2 * cus, 4 * cus};
+    for (int kind = 0; kind < 2 && !st; ++kind)
+        for (int waves = 4; waves <= 8 && !st; waves += 4)
+            for (int gi = 0; gi < 4 && !st; ++gi) {
+                FusedVariant v = {kind, waves, grids[gi]};
+                if (!fused_variant_ok(b->net, v))
+                    continue;
+                st = batch_fused(b, s, precision, pos, view_dir, light_dir, out, nullptr, nullptr,
+                                 v);
+                if (st)
+                    break;
+                hipError_t e = hipEventRecord(e0, s);
+                for (int r = 0; r < reps && !st && e == hipSuccess; ++r)
+                    st = batch_fused(b, s, precision, pos, view_dir, light_dir, out, nullptr,
+                                     nullptr, v);
+                if (e == hipSuccess)
+                    e = hipEventRecord(e1, s);
+                if (e == hipSuccess)
+                    e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess)
+                    e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess && !st)
+                    st = hip_fail(e, "ds_batch_autotune");
+                if (!st && (best < 0.f || ms / reps < best)) {
+                    best = ms / reps;
+                    bestv = v;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st)
+        return st;
+    b->kind = bestv.kind;
+    b->waves = bestv.waves;
+    b->grid = bestv.grid;
+    b->tuned_ms = best;
+    batch_drop_graph(b);
+    return DS_OK;
+}
+
+ds_status ds_batch_capture(ds_batch *b, ds_precision precision, const float *pos,
+                           const float *view_dir, const float *light_dir, float *out,
+                           float *pre_out, uint8_t *flags)
+{
+    DS_CHECK(b, DS_ERR_INVALID_ARG, "ds_batch_capture: batch is NULL");
+    DS_CHECK(precision != DS_PREC_F32, DS_ERR_UNSUPPORTED,
+             "ds_batch_capture: the plain FP32 form is not captured");
+    DS_CHECK(b->offsets[b->n] == 0 || (pos && view_dir && light_dir && out), DS_ERR_INVALID_ARG,
+             "ds_batch_capture: NULL device pointer");
+    DS_CHECK(precision == DS_PREC_BF16, precision == DS_PREC_FP8 ? DS_ERR_STATE
+                                                                 : DS_ERR_INVALID_ARG,
+             "ds_batch_capture: precision %d is not available", (int)precision);
+    DS_CHECK(b->net->frag_bf16, DS_ERR_STATE, "ds_batch_capture: network parameters never set");
+    DS_HIP(hipSetDevice(b->ctx->device));
+    batch_drop_graph(b);
+    if (!b->cap_stream)
+        DS_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+    // the capture stream starts after the context stream's pending work
+    DS_HIP(hipStreamSynchronize(b->ctx->stream));
+    DS_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+    ds_status st = b->offsets[b->n] == 0
+                       ? DS_OK
+                       : batch_fused(b, b->cap_stream, precision, pos, view_dir, light_dir, out,
+                                     pre_out, flags, FusedVariant{b->kind, b->waves, b->grid});
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    if (st) {
+        if (g)
+            (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess)
+        return hip_fail(e, "ds_batch_capture: end of capture");
+    e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        b->exec = nullptr;
+        return hip_fail(e, "ds_batch_capture: instantiate");
+    }
+    return DS_OK;
+}
+
+ds_status ds_batch_replay(ds_batch *b)
+{
+    DS_CHECK(b, DS_ERR_INVALID_ARG, "ds_batch_replay: batch is NULL");
+    DS_CHECK(b->exec, DS_ERR_STATE, "ds_batch_replay: nothing captured");
+    DS_HIP(hipSetDevice(b->ctx->device));
+    DS_HIP(hipGraphLaunch(b->exec, b->ctx->stream));
+    return DS_OK;
 }
 
 // ---------------------------------------------------------------- training (Sec. 5.2)

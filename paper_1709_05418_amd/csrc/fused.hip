@@ -129,14 +129,15 @@ __device__ __forceinline__ void issue_table_half(gcell_ptr cells, const FusedLev
     }
 }
 
-// Position and light frame of point p; false (and a zero frame) if p is out of
-// range or its inputs are unusable.  Recomputed where needed instead of being kept
+// Position and light frame of point p; false (and a zero frame) if the lane has
+// no point (in = false) or its inputs are unusable.  Recomputed where needed instead of being kept
 // in registers for the whole kernel.
-__device__ __forceinline__ bool point_frame(const FusedArgs &a, int64_t p, float *x, Frame &fr)
+__device__ __forceinline__ bool point_frame(const FusedArgs &a, int64_t p, bool in, float *x,
+                                            Frame &fr)
 {
     bool ok = false;
     x[0] = x[1] = x[2] = 0.f;
-    if (p < a.P) {
+    if (in) {
         x[0] = a.pos[3 * p];
         x[1] = a.pos[3 * p + 1];
         x[2] = a.pos[3 * p + 2];
@@ -151,6 +152,17 @@ __device__ __forceinline__ bool point_frame(const FusedArgs &a, int64_t p, float
         fr.gamma = 0.f;
     }
     return ok;
+}
+
+// Cloud of tile t: the last cloud whose first tile is not after t (clouds without
+// points own no tiles).  Uniform across the workgroup.
+__device__ __forceinline__ int tile_cloud(const FusedArgs &a, int64_t t)
+{
+    int c = 0;
+    for (int i = 1; i < a.n_clouds; ++i)
+        if (t >= a.cl[i].tile_begin)
+            c = i;
+    return __builtin_amdgcn_readfirstlane(c);
 }
 
 __device__ __forceinline__ void point_level(const FusedLevel &L, const float *x, const Frame &fr,
@@ -258,9 +270,8 @@ __device__ __forceinline__ void dense(WeightStage<MT, NW> &ws, const float *__re
 }
 
 template <int MT, int NW>
-__global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const FusedLevel *__restrict__ lvt,
-                                                      const uint4 *__restrict__ frags,
-                                                      const float *__restrict__ vec, int n_chunks)
+__global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *__restrict__ frags,
+                                                      const float *__restrict__ vec)
 {
     constexpr int C2 = (MT + 1) / 2;   // chunks of a W-wide input
     constexpr int WP = 16 * MT;        // padded width
@@ -286,195 +297,205 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const FusedLe
 
     WeightStage<MT, NW> ws;
     ws.buf = wbuf;
-    ws.src = frags;
-    ws.cur = 1;
-    ws.fetch(tid);
-    ws.advance(tid);  // chunk 0 -> buffer 0 (also orders the plane table)
-
-    const int64_t p = (int64_t)blockIdx.x * (16 * NW) + (tid >> 6) * 16 + n;
-    float gamma;
-    bool valid;
-    {
-        float x[3];
-        Frame fr;
-        valid = point_frame(a, p, x, fr);
-        gamma = fr.gamma;
-    }
-
-    f4 F[MT];
-    const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
-    f4(*Os)[64] = obuf[tid >> 6];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-        Os[mt][lane] = z4;
-
-    // the first two half-chunks of level 1 go out before the loop; later levels
-    // start theirs while the previous level's second layer runs
-    FusedLevel L = lvt[0];
-    gcell_ptr cells = (gcell_ptr)L.cells;
-    PtLevel q;
-    {
-        float x[3];
-        Frame fr;
-        point_frame(a, p, x, fr);
-        point_level(L, x, fr, a.amin, valid, q);
-    }
-    Pending pa, pb;
-    issue_column_half(cells, L, q, 0, g, pa);
-    issue_column_half(cells, L, q, 1, g, pb);
-
-    for (int k = 0; k < a.K; ++k) {
-        const float *b1 = vec + (size_t)k * 2 * WP;
-        const float *b2 = b1 + WP;
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-            F[mt] = z4;
-
-        // stencil chunks 0..6, two halves of four samples each, two halves in flight:
-        // step c finishes halves 2c, 2c+1 and issues halves 2c+2, 2c+3
+    // persistent loop over tiles of 16 NW points; a tile never spans two clouds
 #pragma unroll 1
-        for (int c = 0; c < 5; ++c) {
-            ws.fetch(tid);
-            f4 lo, hi;
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
-            issue_column_half(cells, L, q, 2 * c + 2, g, pa);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
-            issue_column_half(cells, L, q, 2 * c + 3, g, pb);
-            mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
-            ws.advance(tid);
-        }
-        {  // chunk 5: issues the table halves of chunk 6
-            ws.fetch(tid);
-            f4 lo, hi;
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
-            issue_table_half(cells, L, q, 0, g, plane, pa);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
-            issue_table_half(cells, L, q, 1, g, plane, pb);
-            mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
-            ws.advance(tid);
-        }
-        {  // chunk 6: issues chunk 7's stencil sample (4, 4, 8)
-            ws.fetch(tid);
-            f4 lo, hi;
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
-            issue_one(cells, L, q.u0[0] + 4.f * (q.a[0] + q.b[0]) + 8.f * q.c[0],
-                      q.u0[1] + 4.f * (q.a[1] + q.b[1]) + 8.f * q.c[1],
-                      q.u0[2] + 4.f * (q.a[2] + q.b[2]) + 8.f * q.c[2], pa.v[0], pa.fx[0],
-                      pa.fy[0], pa.fz[0]);
-#pragma unroll
-            for (int j = 0; j < 4; ++j)
-                hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
-            mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
-            ws.advance(tid);
-        }
-        // chunk 7: stencil sample (4, 4, 8), gamma, and the odd tile of o^{k-1}
+    for (int64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
+        // keeps tile-invariant LDS reads (the plane table) inside the loop: hoisted,
+        // they would hold registers across the whole tile and force spills
+        asm volatile("" ::: "memory");
+        const FusedCloud &cl = a.cl[tile_cloud(a, t)];
+        ws.src = frags;
+        ws.cur = 1;
+        ws.fetch(tid);
+        ws.advance(tid);  // chunk 0 -> buffer 0 (also orders the plane table)
+
+        const int64_t pl = (t - cl.tile_begin) * (16 * NW) + (tid >> 6) * 16 + n;
+        const bool in = pl < cl.P;
+        const int64_t p = cl.p_begin + pl;
+        float gamma;
+        bool valid;
         {
-            ws.fetch(tid);
-            float s = finish_one(pa.v[0], pa.fx[0], pa.fy[0], pa.fz[0]);
-            f4 lo = f4{g == 0 ? s : 0.f, g == 0 ? gamma : 0.f, 0.f, 0.f};
-            bf16x8 B = pack8(lo, (MT & 1) ? Os[MT - 1][lane] : z4);
-            mfma_chunk<MT>(ws.chunk(), lane, B, F);
-            ws.advance(tid);
+            float x[3];
+            Frame fr;
+            valid = point_frame(a, p, in, x, fr);
+            gamma = fr.gamma;
         }
-        // o^{k-1} in pairs of tiles (o^0 = 0: block 1 has no such chunks)
-        if (k > 0) {
-#pragma unroll
-            for (int qq = 0; qq < MT / 2; ++qq) {
+
+        f4 F[MT];
+        const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
+        f4(*Os)[64] = obuf[tid >> 6];
+    #pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+            Os[mt][lane] = z4;
+
+        // the first two half-chunks of level 1 go out before the loop; later levels
+        // start theirs while the previous level's second layer runs
+        FusedLevel L = cl.lvt[0];
+        gcell_ptr cells = (gcell_ptr)L.cells;
+        PtLevel q;
+        {
+            float x[3];
+            Frame fr;
+            point_frame(a, p, in, x, fr);
+            point_level(L, x, fr, cl.amin, valid, q);
+        }
+        Pending pa, pb;
+        issue_column_half(cells, L, q, 0, g, pa);
+        issue_column_half(cells, L, q, 1, g, pb);
+
+        for (int k = 0; k < a.K; ++k) {
+            const float *b1 = vec + (size_t)k * 2 * WP;
+            const float *b2 = b1 + WP;
+    #pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                F[mt] = z4;
+
+            // stencil chunks 0..6, two halves of four samples each, two halves in flight:
+            // step c finishes halves 2c, 2c+1 and issues halves 2c+2, 2c+3
+    #pragma unroll 1
+            for (int c = 0; c < 5; ++c) {
                 ws.fetch(tid);
-                mfma_chunk<MT>(ws.chunk(), lane, pack8(Os[2 * qq][lane], Os[2 * qq + 1][lane]), F);
+                f4 lo, hi;
+    #pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
+                issue_column_half(cells, L, q, 2 * c + 2, g, pa);
+    #pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
+                issue_column_half(cells, L, q, 2 * c + 3, g, pb);
+                mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
                 ws.advance(tid);
             }
+            {  // chunk 5: issues the table halves of chunk 6
+                ws.fetch(tid);
+                f4 lo, hi;
+    #pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
+                issue_table_half(cells, L, q, 0, g, plane, pa);
+    #pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
+                issue_table_half(cells, L, q, 1, g, plane, pb);
+                mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
+                ws.advance(tid);
+            }
+            {  // chunk 6: issues chunk 7's stencil sample (4, 4, 8)
+                ws.fetch(tid);
+                f4 lo, hi;
+    #pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
+                issue_one(cells, L, q.u0[0] + 4.f * (q.a[0] + q.b[0]) + 8.f * q.c[0],
+                          q.u0[1] + 4.f * (q.a[1] + q.b[1]) + 8.f * q.c[1],
+                          q.u0[2] + 4.f * (q.a[2] + q.b[2]) + 8.f * q.c[2], pa.v[0], pa.fx[0],
+                          pa.fy[0], pa.fz[0]);
+    #pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
+                mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
+                ws.advance(tid);
+            }
+            // chunk 7: stencil sample (4, 4, 8), gamma, and the odd tile of o^{k-1}
+            {
+                ws.fetch(tid);
+                float s = finish_one(pa.v[0], pa.fx[0], pa.fy[0], pa.fz[0]);
+                f4 lo = f4{g == 0 ? s : 0.f, g == 0 ? gamma : 0.f, 0.f, 0.f};
+                bf16x8 B = pack8(lo, (MT & 1) ? Os[MT - 1][lane] : z4);
+                mfma_chunk<MT>(ws.chunk(), lane, B, F);
+                ws.advance(tid);
+            }
+            // o^{k-1} in pairs of tiles (o^0 = 0: block 1 has no such chunks)
+            if (k > 0) {
+    #pragma unroll
+                for (int qq = 0; qq < MT / 2; ++qq) {
+                    ws.fetch(tid);
+                    mfma_chunk<MT>(ws.chunk(), lane, pack8(Os[2 * qq][lane], Os[2 * qq + 1][lane]), F);
+                    ws.advance(tid);
+                }
+            }
+            // the next level's first samples fly while the second layer runs
+            if (k + 1 < a.K) {
+                L = cl.lvt[k + 1];
+                cells = (gcell_ptr)L.cells;
+                float x[3];
+                Frame fr;
+                point_frame(a, p, in, x, fr);
+                point_level(L, x, fr, cl.amin, valid, q);
+                issue_column_half(cells, L, q, 0, g, pa);
+                issue_column_half(cells, L, q, 1, g, pb);
+            }
+            // F1 = relu(. + b1)
+    #pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                f4 bb = *reinterpret_cast<const f4 *>(b1 + 16 * mt + 4 * g);
+    #pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    F[mt][i] = fmaxf(F[mt][i] + bb[i], 0.f);
+            }
+            // o^k = relu(W2 F1 + b2 + o^{k-1}), accumulated in place
+            f4 O[MT];
+    #pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                O[mt] = Os[mt][lane] + *reinterpret_cast<const f4 *>(b2 + 16 * mt + 4 * g);
+    #pragma unroll
+            for (int qq = 0; qq < C2; ++qq) {
+                ws.fetch(tid);
+                mfma_chunk<MT>(ws.chunk(), lane,
+                               pack8(F[2 * qq], (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0] : z4),
+                               O);
+                ws.advance(tid);
+            }
+    #pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+    #pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    O[mt][i] = fmaxf(O[mt][i], 0.f);
+                Os[mt][lane] = O[mt];
+            }
         }
-        // the next level's first samples fly while the second layer runs
-        if (k + 1 < a.K) {
-            L = lvt[k + 1];
-            cells = (gcell_ptr)L.cells;
-            float x[3];
-            Frame fr;
-            point_frame(a, p, x, fr);
-            point_level(L, x, fr, a.amin, valid, q);
-            issue_column_half(cells, L, q, 0, g, pa);
-            issue_column_half(cells, L, q, 1, g, pb);
-        }
-        // F1 = relu(. + b1)
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            f4 bb = *reinterpret_cast<const f4 *>(b1 + 16 * mt + 4 * g);
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                F[mt][i] = fmaxf(F[mt][i] + bb[i], 0.f);
-        }
-        // o^k = relu(W2 F1 + b2 + o^{k-1}), accumulated in place
-        f4 O[MT];
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-            O[mt] = Os[mt][lane] + *reinterpret_cast<const f4 *>(b2 + 16 * mt + 4 * g);
-#pragma unroll
-        for (int qq = 0; qq < C2; ++qq) {
-            ws.fetch(tid);
-            mfma_chunk<MT>(ws.chunk(), lane,
-                           pack8(F[2 * qq], (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0] : z4),
-                           O);
-            ws.advance(tid);
-        }
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                O[mt][i] = fmaxf(O[mt][i], 0.f);
-            Os[mt][lane] = O[mt];
-        }
-    }
 
-    // trailing layers: H-1 dense W -> W layers, ping-ponging between O and F
-    f4 O[MT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-        O[mt] = Os[mt][lane];
-    const float *bh = vec + (size_t)a.K * 2 * WP;
-    int h = 0;
-    for (; h + 1 < a.H - 1; h += 2) {
-        dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
-        dense<MT, NW>(ws, bh + (size_t)(h + 1) * WP, tid, lane, F, O);
-    }
-    if (h < a.H - 1) {
-        dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
-#pragma unroll
+        // trailing layers: H-1 dense W -> W layers, ping-ponging between O and F
+        f4 O[MT];
+    #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
-            O[mt] = F[mt];
-    }
-    // final scalar layer in FP32 on the vector ALUs
-    const float *wl = bh + (size_t)(a.H - 1) * WP;
-    const float bl = wl[WP];
-    float acc = 0.f;
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-        f4 w = *reinterpret_cast<const f4 *>(wl + 16 * mt + 4 * g);
-        acc += w[0] * O[mt][0] + w[1] * O[mt][1] + w[2] * O[mt][2] + w[3] * O[mt][3];
-    }
-    acc += __shfl_xor(acc, 16, 64);
-    acc += __shfl_xor(acc, 32, 64);
-    if (g == 0 && p < a.P) {
-        float pre = acc + bl;
-        a.out[p] = valid ? fmaxf(pre, 0.f) : 0.f;
-        if (a.pre)
-            a.pre[p] = valid ? pre : 0.f;
-        if (a.flags) {
-            float x[3];
-            Frame fr;
-            point_frame(a, p, x, fr);
-            a.flags[p] = valid ? point_flags(x, fr, a.amin, a.amax, a.inv_mean)
-                               : (uint8_t)DS_FLAG_INVALID;
+            O[mt] = Os[mt][lane];
+        const float *bh = vec + (size_t)a.K * 2 * WP;
+        int h = 0;
+        for (; h + 1 < a.H - 1; h += 2) {
+            dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+            dense<MT, NW>(ws, bh + (size_t)(h + 1) * WP, tid, lane, F, O);
+        }
+        if (h < a.H - 1) {
+            dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+    #pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                O[mt] = F[mt];
+        }
+        // final scalar layer in FP32 on the vector ALUs
+        const float *wl = bh + (size_t)(a.H - 1) * WP;
+        const float bl = wl[WP];
+        float acc = 0.f;
+    #pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            f4 w = *reinterpret_cast<const f4 *>(wl + 16 * mt + 4 * g);
+            acc += w[0] * O[mt][0] + w[1] * O[mt][1] + w[2] * O[mt][2] + w[3] * O[mt][3];
+        }
+        acc += __shfl_xor(acc, 16, 64);
+        acc += __shfl_xor(acc, 32, 64);
+        if (g == 0 && in) {
+            float pre = acc + bl;
+            a.out[p] = valid ? fmaxf(pre, 0.f) : 0.f;
+            if (a.pre)
+                a.pre[p] = valid ? pre : 0.f;
+            if (a.flags) {
+                float x[3];
+                Frame fr;
+                point_frame(a, p, in, x, fr);
+                a.flags[p] = valid ? point_flags(x, fr, cl.amin, cl.amax, cl.inv_mean)
+                                   : (uint8_t)DS_FLAG_INVALID;
+            }
         }
     }
 }
@@ -483,7 +504,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const FusedLe
 // registers and no cross-chunk pipelining (each chunk issues its 8 samples and
 // interpolates them); the other wave on the SIMD covers the load latency.
 template <int MT, int NW>
-__global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a, const FusedLevel *__restrict__ lvt,
+__global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
                                                           const uint4 *__restrict__ frags,
                                                           const float *__restrict__ vec)
 {
@@ -506,404 +527,145 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a, const Fus
     }
     WeightStage<MT, NW> ws;
     ws.buf = wbuf;
-    ws.src = frags;
-    ws.cur = 1;
-    ws.fetch(tid);
-    ws.advance(tid);
-
-    const int64_t p = (int64_t)blockIdx.x * (16 * NW) + (tid >> 6) * 16 + n;
-    float gamma;
-    bool valid;
-    {
-        float x[3];
-        Frame fr;
-        valid = point_frame(a, p, x, fr);
-        gamma = fr.gamma;
-    }
-    const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
-    f4 O[MT], F[MT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-        O[mt] = z4;
-
-    for (int k = 0; k < a.K; ++k) {
-        const FusedLevel L = lvt[k];
-        gcell_ptr cells = (gcell_ptr)L.cells;
-        PtLevel q;
-        {
-            float x[3];
-            Frame fr;
-            point_frame(a, p, x, fr);
-            point_level(L, x, fr, a.amin, valid, q);
-        }
-        const float *b1 = vec + (size_t)k * 2 * WP;
-        const float *b2 = b1 + WP;
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-            F[mt] = z4;
+    // persistent loop over tiles of 16 NW points; a tile never spans two clouds
 #pragma unroll 1
-        for (int c = 0; c < 7; ++c) {
-            ws.fetch(tid);
-            Pending pa, pb;
-            if (c < 6) {
-                issue_column_half(cells, L, q, 2 * c, g, pa);
-                issue_column_half(cells, L, q, 2 * c + 1, g, pb);
-            } else {
-                issue_table_half(cells, L, q, 0, g, plane, pa);
-                issue_table_half(cells, L, q, 1, g, plane, pb);
-            }
-            f4 lo, hi;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
-                hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
-            }
-            mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
-            ws.advance(tid);
-        }
-        {
-            ws.fetch(tid);
-            Pending pa;
-            issue_one(cells, L, q.u0[0] + 4.f * (q.a[0] + q.b[0]) + 8.f * q.c[0],
-                      q.u0[1] + 4.f * (q.a[1] + q.b[1]) + 8.f * q.c[1],
-                      q.u0[2] + 4.f * (q.a[2] + q.b[2]) + 8.f * q.c[2], pa.v[0], pa.fx[0],
-                      pa.fy[0], pa.fz[0]);
-            const float sv = finish_one(pa.v[0], pa.fx[0], pa.fy[0], pa.fz[0]);
-            const f4 lo = f4{g == 0 ? sv : 0.f, g == 0 ? gamma : 0.f, 0.f, 0.f};
-            mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, (MT & 1) ? O[MT - 1] : z4), F);
-            ws.advance(tid);
-        }
-        if (k > 0) {
-#pragma unroll
-            for (int qq = 0; qq < MT / 2; ++qq) {
-                ws.fetch(tid);
-                mfma_chunk<MT>(ws.chunk(), lane, pack8(O[2 * qq], O[2 * qq + 1]), F);
-                ws.advance(tid);
-            }
-        }
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            const f4 bb = *reinterpret_cast<const f4 *>(b1 + 16 * mt + 4 * g);
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                F[mt][i] = fmaxf(F[mt][i] + bb[i], 0.f);
-            O[mt] += *reinterpret_cast<const f4 *>(b2 + 16 * mt + 4 * g);
-        }
-#pragma unroll
-        for (int qq = 0; qq < C2; ++qq) {
-            ws.fetch(tid);
-            mfma_chunk<MT>(ws.chunk(), lane,
-                           pack8(F[2 * qq], (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0] : z4),
-                           O);
-            ws.advance(tid);
-        }
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                O[mt][i] = fmaxf(O[mt][i], 0.f);
-    }
-    const float *bh = vec + (size_t)a.K * 2 * WP;
-    int h = 0;
-    for (; h + 1 < a.H - 1; h += 2) {
-        dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
-        dense<MT, NW>(ws, bh + (size_t)(h + 1) * WP, tid, lane, F, O);
-    }
-    if (h < a.H - 1) {
-        dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-            O[mt] = F[mt];
-    }
-    const float *wl = bh + (size_t)(a.H - 1) * WP;
-    const float bl = wl[WP];
-    float acc = 0.f;
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-        const f4 w = *reinterpret_cast<const f4 *>(wl + 16 * mt + 4 * g);
-        acc += w[0] * O[mt][0] + w[1] * O[mt][1] + w[2] * O[mt][2] + w[3] * O[mt][3];
-    }
-    acc += __shfl_xor(acc, 16, 64);
-    acc += __shfl_xor(acc, 32, 64);
-    if (g == 0 && p < a.P) {
-        const float pre = acc + bl;
-        a.out[p] = valid ? fmaxf(pre, 0.f) : 0.f;
-        if (a.pre)
-            a.pre[p] = valid ? pre : 0.f;
-        if (a.flags) {
-            float x[3];
-            Frame fr;
-            point_frame(a, p, x, fr);
-            a.flags[p] = valid ? point_flags(x, fr, a.amin, a.amax, a.inv_mean)
-                               : (uint8_t)DS_FLAG_INVALID;
-        }
-    }
-}
-
-// Wide variant: one wave per SIMD holding 2 x 16 points, the residual stream and
-// the first-layer accumulators of both point tiles in registers.  Every weight
-// fragment read from LDS feeds two MFMAs, which halves the LDS fragment traffic
-// and (at 128 points per workgroup) the L2 traffic of the weight staging.
-template <int MT, int NT>
-__device__ __forceinline__ void mfma_chunk_nt(const uint4 *w, int lane, const bf16x8 (&B)[NT],
-                                              f4 (&acc)[MT][NT])
-{
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-        const uint4 a = w[mt * 64 + lane];
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-            acc[mt][nt] = mfma_bf16(a, B[nt], acc[mt][nt]);
-    }
-}
-
-template <int MT, int NT, int NW>
-__device__ __forceinline__ void dense_nt(WeightStage<MT, NW> &ws, const float *__restrict__ bias,
-                                         int tid, int lane, const f4 (&in)[MT][NT],
-                                         f4 (&out)[MT][NT])
-{
-    constexpr int C2 = (MT + 1) / 2;
-    const int g = lane >> 4;
-    const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-        const f4 b = *reinterpret_cast<const f4 *>(bias + 16 * mt + 4 * g);
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-            out[mt][nt] = b;
-    }
-#pragma unroll
-    for (int q = 0; q < C2; ++q) {
+    for (int64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
+        // keeps tile-invariant LDS reads (the plane table) inside the loop: hoisted,
+        // they would hold registers across the whole tile and force spills
+        asm volatile("" ::: "memory");
+        const FusedCloud &cl = a.cl[tile_cloud(a, t)];
+        ws.src = frags;
+        ws.cur = 1;
         ws.fetch(tid);
-        bf16x8 B[NT];
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-            B[nt] = pack8(in[2 * q][nt], (2 * q + 1 < MT) ? in[2 * q + 1 < MT ? 2 * q + 1 : 0][nt] : z4);
-        mfma_chunk_nt<MT, NT>(ws.chunk(), lane, B, out);
         ws.advance(tid);
-    }
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                out[mt][nt][i] = fmaxf(out[mt][nt][i], 0.f);
-}
 
-template <int MT, int NT>
-__global__ void __launch_bounds__(256, 1) k_fused_wide(FusedArgs a, const FusedLevel *__restrict__ lvt,
-                                                       const uint4 *__restrict__ frags,
-                                                       const float *__restrict__ vec)
-{
-    constexpr int NW = 4;
-    constexpr int C2 = (MT + 1) / 2;
-    constexpr int WP = 16 * MT;
-    __shared__ uint4 wbuf[2 * WeightStage<MT, NW>::SLOT];
-    __shared__ float4 plane[32];
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int g = lane >> 4, n = lane & 15;
-    if (tid < 32) {
-        const int gg = tid >> 3, j = tid & 7;
-        if (gg == 0) {
-            plane[tid] = make_float4(4.f, 4.f, (float)j, 0.f);
-        } else {
-            const int G = 2 * (gg - 1) + (j >> 2), jj = j & 3;
-            plane[tid] = G < 5 ? make_float4((float)jj, (float)G, 8.f, 0.f)
-                               : make_float4(4.f, (float)jj, 8.f, 0.f);
+        const int64_t pl = (t - cl.tile_begin) * (16 * NW) + (tid >> 6) * 16 + n;
+        const bool in = pl < cl.P;
+        const int64_t p = cl.p_begin + pl;
+        float gamma;
+        bool valid;
+        {
+            float x[3];
+            Frame fr;
+            valid = point_frame(a, p, in, x, fr);
+            gamma = fr.gamma;
         }
-    }
-    WeightStage<MT, NW> ws;
-    ws.buf = wbuf;
-    ws.src = frags;
-    ws.cur = 1;
-    ws.fetch(tid);
-    ws.advance(tid);
-
-    const int64_t p0 = ((int64_t)blockIdx.x * NW + (tid >> 6)) * (16 * NT) + n;
-    float gamma[NT];
-    bool valid[NT];
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        float x[3];
-        Frame fr;
-        valid[nt] = point_frame(a, p0 + 16 * nt, x, fr);
-        gamma[nt] = fr.gamma;
-    }
-    const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
-    f4 O[MT][NT], F[MT][NT];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < NT; ++nt)
-            O[mt][nt] = z4;
-
-    FusedLevel L = lvt[0];
-    gcell_ptr cells = (gcell_ptr)L.cells;
-    PtLevel q[NT];
-    Pending pa[NT], pb[NT];
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        float x[3];
-        Frame fr;
-        point_frame(a, p0 + 16 * nt, x, fr);
-        point_level(L, x, fr, a.amin, valid[nt], q[nt]);
-        issue_column_half(cells, L, q[nt], 0, g, pa[nt]);
-        issue_column_half(cells, L, q[nt], 1, g, pb[nt]);
-    }
-
-    for (int k = 0; k < a.K; ++k) {
-        const float *b1 = vec + (size_t)k * 2 * WP;
-        const float *b2 = b1 + WP;
-#pragma unroll
+        const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
+        f4 O[MT], F[MT];
+    #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-                F[mt][nt] = z4;
-#pragma unroll 1
-        for (int c = 0; c < 7; ++c) {
-            ws.fetch(tid);
-            bf16x8 B[NT];
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                f4 lo, hi;
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    lo[j] = finish_one(pa[nt].v[j], pa[nt].fx[j], pa[nt].fy[j], pa[nt].fz[j]);
-                if (c < 5)
-                    issue_column_half(cells, L, q[nt], 2 * c + 2, g, pa[nt]);
-                else if (c == 5)
-                    issue_table_half(cells, L, q[nt], 0, g, plane, pa[nt]);
-                else
-                    issue_one(cells, L, q[nt].u0[0] + 4.f * (q[nt].a[0] + q[nt].b[0]) + 8.f * q[nt].c[0],
-                              q[nt].u0[1] + 4.f * (q[nt].a[1] + q[nt].b[1]) + 8.f * q[nt].c[1],
-                              q[nt].u0[2] + 4.f * (q[nt].a[2] + q[nt].b[2]) + 8.f * q[nt].c[2],
-                              pa[nt].v[0], pa[nt].fx[0], pa[nt].fy[0], pa[nt].fz[0]);
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    hi[j] = finish_one(pb[nt].v[j], pb[nt].fx[j], pb[nt].fy[j], pb[nt].fz[j]);
-                if (c < 5)
-                    issue_column_half(cells, L, q[nt], 2 * c + 3, g, pb[nt]);
-                else if (c == 5)
-                    issue_table_half(cells, L, q[nt], 1, g, plane, pb[nt]);
-                B[nt] = pack8(lo, hi);
-                // one point tile at a time: interleaving both tiles' gathers costs
-                // more registers than the wave has
-                __builtin_amdgcn_sched_barrier(0);
-            }
-            mfma_chunk_nt<MT, NT>(ws.chunk(), lane, B, F);
-            ws.advance(tid);
-        }
-        {  // chunk 7: sample (4, 4, 8), gamma, odd tile of o^{k-1}
-            ws.fetch(tid);
-            bf16x8 B[NT];
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const float sv = finish_one(pa[nt].v[0], pa[nt].fx[0], pa[nt].fy[0], pa[nt].fz[0]);
-                const f4 lo = f4{g == 0 ? sv : 0.f, g == 0 ? gamma[nt] : 0.f, 0.f, 0.f};
-                B[nt] = pack8(lo, (MT & 1) ? O[MT - 1][nt] : z4);
-            }
-            mfma_chunk_nt<MT, NT>(ws.chunk(), lane, B, F);
-            ws.advance(tid);
-        }
-        if (k > 0) {
-#pragma unroll
-            for (int qq = 0; qq < MT / 2; ++qq) {
-                ws.fetch(tid);
-                bf16x8 B[NT];
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt)
-                    B[nt] = pack8(O[2 * qq][nt], O[2 * qq + 1][nt]);
-                mfma_chunk_nt<MT, NT>(ws.chunk(), lane, B, F);
-                ws.advance(tid);
-            }
-        }
-        if (k + 1 < a.K) {
-            L = lvt[k + 1];
-            cells = (gcell_ptr)L.cells;
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
+            O[mt] = z4;
+
+        for (int k = 0; k < a.K; ++k) {
+            const FusedLevel L = cl.lvt[k];
+            gcell_ptr cells = (gcell_ptr)L.cells;
+            PtLevel q;
+            {
                 float x[3];
                 Frame fr;
-                point_frame(a, p0 + 16 * nt, x, fr);
-                point_level(L, x, fr, a.amin, valid[nt], q[nt]);
-                issue_column_half(cells, L, q[nt], 0, g, pa[nt]);
-                issue_column_half(cells, L, q[nt], 1, g, pb[nt]);
+                point_frame(a, p, in, x, fr);
+                point_level(L, x, fr, cl.amin, valid, q);
             }
-        }
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            const f4 bb = *reinterpret_cast<const f4 *>(b1 + 16 * mt + 4 * g);
-            const f4 cc = *reinterpret_cast<const f4 *>(b2 + 16 * mt + 4 * g);
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    F[mt][nt][i] = fmaxf(F[mt][nt][i] + bb[i], 0.f);
-                O[mt][nt] += cc;
+            const float *b1 = vec + (size_t)k * 2 * WP;
+            const float *b2 = b1 + WP;
+    #pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                F[mt] = z4;
+    #pragma unroll 1
+            for (int c = 0; c < 7; ++c) {
+                ws.fetch(tid);
+                Pending pa, pb;
+                if (c < 6) {
+                    issue_column_half(cells, L, q, 2 * c, g, pa);
+                    issue_column_half(cells, L, q, 2 * c + 1, g, pb);
+                } else {
+                    issue_table_half(cells, L, q, 0, g, plane, pa);
+                    issue_table_half(cells, L, q, 1, g, plane, pb);
+                }
+                f4 lo, hi;
+    #pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
+                    hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
+                }
+                mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
+                ws.advance(tid);
             }
-        }
-#pragma unroll
-        for (int qq = 0; qq < C2; ++qq) {
-            ws.fetch(tid);
-            bf16x8 B[NT];
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-                B[nt] = pack8(F[2 * qq][nt], (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0][nt] : z4);
-            mfma_chunk_nt<MT, NT>(ws.chunk(), lane, B, O);
-            ws.advance(tid);
-        }
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
+            {
+                ws.fetch(tid);
+                Pending pa;
+                issue_one(cells, L, q.u0[0] + 4.f * (q.a[0] + q.b[0]) + 8.f * q.c[0],
+                          q.u0[1] + 4.f * (q.a[1] + q.b[1]) + 8.f * q.c[1],
+                          q.u0[2] + 4.f * (q.a[2] + q.b[2]) + 8.f * q.c[2], pa.v[0], pa.fx[0],
+                          pa.fy[0], pa.fz[0]);
+                const float sv = finish_one(pa.v[0], pa.fx[0], pa.fy[0], pa.fz[0]);
+                const f4 lo = f4{g == 0 ? sv : 0.f, g == 0 ? gamma : 0.f, 0.f, 0.f};
+                mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, (MT & 1) ? O[MT - 1] : z4), F);
+                ws.advance(tid);
+            }
+            if (k > 0) {
+    #pragma unroll
+                for (int qq = 0; qq < MT / 2; ++qq) {
+                    ws.fetch(tid);
+                    mfma_chunk<MT>(ws.chunk(), lane, pack8(O[2 * qq], O[2 * qq + 1]), F);
+                    ws.advance(tid);
+                }
+            }
+    #pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const f4 bb = *reinterpret_cast<const f4 *>(b1 + 16 * mt + 4 * g);
+    #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    O[mt][nt][i] = fmaxf(O[mt][nt][i], 0.f);
-    }
-
-    const float *bh = vec + (size_t)a.K * 2 * WP;
-    int h = 0;
-    for (; h + 1 < a.H - 1; h += 2) {
-        dense_nt<MT, NT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
-        dense_nt<MT, NT, NW>(ws, bh + (size_t)(h + 1) * WP, tid, lane, F, O);
-    }
-    if (h < a.H - 1) {
-        dense_nt<MT, NT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-            for (int nt = 0; nt < NT; ++nt)
-                O[mt][nt] = F[mt][nt];
-    }
-    const float *wl = bh + (size_t)(a.H - 1) * WP;
-    const float bl = wl[WP];
-#pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
+                    F[mt][i] = fmaxf(F[mt][i] + bb[i], 0.f);
+                O[mt] += *reinterpret_cast<const f4 *>(b2 + 16 * mt + 4 * g);
+            }
+    #pragma unroll
+            for (int qq = 0; qq < C2; ++qq) {
+                ws.fetch(tid);
+                mfma_chunk<MT>(ws.chunk(), lane,
+                               pack8(F[2 * qq], (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0] : z4),
+                               O);
+                ws.advance(tid);
+            }
+    #pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+    #pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    O[mt][i] = fmaxf(O[mt][i], 0.f);
+        }
+        const float *bh = vec + (size_t)a.K * 2 * WP;
+        int h = 0;
+        for (; h + 1 < a.H - 1; h += 2) {
+            dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+            dense<MT, NW>(ws, bh + (size_t)(h + 1) * WP, tid, lane, F, O);
+        }
+        if (h < a.H - 1) {
+            dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+    #pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                O[mt] = F[mt];
+        }
+        const float *wl = bh + (size_t)(a.H - 1) * WP;
+        const float bl = wl[WP];
         float acc = 0.f;
-#pragma unroll
+    #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
             const f4 w = *reinterpret_cast<const f4 *>(wl + 16 * mt + 4 * g);
-            acc += w[0] * O[mt][nt][0] + w[1] * O[mt][nt][1] + w[2] * O[mt][nt][2] +
-                   w[3] * O[mt][nt][3];
+            acc += w[0] * O[mt][0] + w[1] * O[mt][1] + w[2] * O[mt][2] + w[3] * O[mt][3];
         }
         acc += __shfl_xor(acc, 16, 64);
         acc += __shfl_xor(acc, 32, 64);
-        const int64_t p = p0 + 16 * nt;
-        if (g == 0 && p < a.P) {
+        if (g == 0 && in) {
             const float pre = acc + bl;
-            a.out[p] = valid[nt] ? fmaxf(pre, 0.f) : 0.f;
+            a.out[p] = valid ? fmaxf(pre, 0.f) : 0.f;
             if (a.pre)
-                a.pre[p] = valid[nt] ? pre : 0.f;
+                a.pre[p] = valid ? pre : 0.f;
             if (a.flags) {
                 float x[3];
                 Frame fr;
-                point_frame(a, p, x, fr);
-                a.flags[p] = valid[nt] ? point_flags(x, fr, a.amin, a.amax, a.inv_mean)
-                                       : (uint8_t)DS_FLAG_INVALID;
+                point_frame(a, p, in, x, fr);
+                a.flags[p] = valid ? point_flags(x, fr, cl.amin, cl.amax, cl.inv_mean)
+                                   : (uint8_t)DS_FLAG_INVALID;
             }
         }
     }
@@ -918,8 +680,7 @@ __device__ __forceinline__ int column_sample(int c, int g, int j)
     return (col % 5) + 5 * (col / 5) + 25 * j;
 }
 
-__global__ void __launch_bounds__(256) k_gather_packed(FusedArgs a, const FusedLevel *__restrict__ lvt,
-                                                       float *__restrict__ z)
+__global__ void __launch_bounds__(256) k_gather_packed(FusedArgs a, float *__restrict__ z)
 {
     __shared__ float4 plane[32];
     const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, n = lane & 15;
@@ -934,22 +695,24 @@ __global__ void __launch_bounds__(256) k_gather_packed(FusedArgs a, const FusedL
         }
     }
     __syncthreads();
+    const FusedCloud &cl = a.cl[0];
     const int64_t p = (int64_t)blockIdx.x * 64 + (tid >> 6) * 16 + n;
+    const bool in = p < cl.P;
     float x[3];
     Frame fr;
-    const bool valid = point_frame(a, p, x, fr);
+    const bool valid = point_frame(a, p, in, x, fr);
     const int64_t D = 225 * (int64_t)a.K + 1;
     for (int k = 0; k < a.K; ++k) {
-        const FusedLevel L = lvt[k];
+        const FusedLevel L = cl.lvt[k];
         gcell_ptr cells = (gcell_ptr)L.cells;
         PtLevel q;
-        point_level(L, x, fr, a.amin, valid, q);
+        point_level(L, x, fr, cl.amin, valid, q);
         Pending pa;
         for (int h = 0; h < 12; ++h) {
             issue_column_half(cells, L, q, h, g, pa);
             for (int j = 0; j < 4; ++j) {
                 float v = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
-                if (p < a.P)
+                if (in)
                     z[p * D + 225 * k + column_sample(h >> 1, g, 4 * (h & 1) + j)] = v;
             }
         }
@@ -959,7 +722,7 @@ __global__ void __launch_bounds__(256) k_gather_packed(FusedArgs a, const FusedL
                 float v = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
                 float4 o = plane[8 * g + 4 * hh + j];
                 int sidx = (int)o.x + 5 * (int)o.y + 25 * (int)o.z;
-                if (p < a.P)
+                if (in)
                     z[p * D + 225 * k + sidx] = v;
             }
         }
@@ -969,11 +732,11 @@ __global__ void __launch_bounds__(256) k_gather_packed(FusedArgs a, const FusedL
                       q.u0[2] + 4.f * (q.a[2] + q.b[2]) + 8.f * q.c[2], pa.v[0], pa.fx[0],
                       pa.fy[0], pa.fz[0]);
             float v = finish_one(pa.v[0], pa.fx[0], pa.fy[0], pa.fz[0]);
-            if (p < a.P)
+            if (in)
                 z[p * D + 225 * k + 224] = v;
         }
     }
-    if (g == 0 && p < a.P)
+    if (g == 0 && in)
         z[p * D + D - 1] = fr.gamma;
 }
 
@@ -995,63 +758,46 @@ int chunk_count(int MT, int K, int H)
     return (8 + C2) + (K - 1) * (C1 + C2) + (H - 1) * C2;
 }
 
-int g_waves = 0;  // workgroup size override (waves), 0 = default
 constexpr size_t kFragPad = 2048;  // >= R x threads of every instantiation (entries)
 
-template <int MT, int NW>
-ds_status launch_nw(hipStream_t s, const ds_net *net, const FusedArgs &a, const FusedLevel *lvt)
+// Tile partition of the clouds for tiles of `per` points; returns the tile count.
+int64_t assign_tiles(FusedArgs &a, int64_t per)
 {
-    int64_t per = 16 * NW;
-    int64_t blocks = (a.P + per - 1) / per;
-    if (blocks <= 0)
+    int64_t t = 0;
+    for (int c = 0; c < a.n_clouds; ++c) {
+        a.cl[c].tile_begin = t;
+        t += (a.cl[c].P + per - 1) / per;
+    }
+    a.n_tiles = t;
+    return t;
+}
+
+template <int MT, int NW>
+ds_status launch_kind(hipStream_t s, const ds_net *net, FusedArgs a, int kind, int grid)
+{
+    const int64_t tiles = assign_tiles(a, 16 * NW);
+    if (tiles <= 0)
         return DS_OK;
-    k_fused<MT, NW><<<(unsigned)blocks, 64 * NW, 0, s>>>(a, lvt, net->frag_bf16, net->vec,
-                                                         chunk_count(MT, a.K, a.H));
+    const int64_t g = grid > 0 && grid < tiles ? grid : tiles;
+    DS_CHECK(g < ((int64_t)1 << 31), DS_ERR_INVALID_ARG, "too many tiles for one launch");
+    if (kind == DS_KERNEL_PIPELINED)
+        k_fused<MT, NW><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_bf16, net->vec);
+    else
+        k_fused_reg<MT, NW><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_bf16, net->vec);
     DS_HIP(hipGetLastError());
     return DS_OK;
 }
 
 template <int MT>
-ds_status launch_wide(hipStream_t s, const ds_net *net, const FusedArgs &a, const FusedLevel *lvt)
+ds_status launch(hipStream_t s, const ds_net *net, const FusedArgs &a, const FusedVariant &v)
 {
-    constexpr int NT = 2;
-    int64_t per = 4 * 16 * NT;
-    int64_t blocks = (a.P + per - 1) / per;
-    if (blocks <= 0)
-        return DS_OK;
-    k_fused_wide<MT, NT><<<(unsigned)blocks, 256, 0, s>>>(a, lvt, net->frag_bf16, net->vec);
-    DS_HIP(hipGetLastError());
-    return DS_OK;
-}
-
-template <int MT, int NW>
-ds_status launch_reg(hipStream_t s, const ds_net *net, const FusedArgs &a, const FusedLevel *lvt)
-{
-    int64_t per = 16 * NW;
-    int64_t blocks = (a.P + per - 1) / per;
-    if (blocks <= 0)
-        return DS_OK;
-    k_fused_reg<MT, NW><<<(unsigned)blocks, 64 * NW, 0, s>>>(a, lvt, net->frag_bf16, net->vec);
-    DS_HIP(hipGetLastError());
-    return DS_OK;
-}
-
-template <int MT>
-ds_status launch(hipStream_t s, const ds_net *net, const FusedArgs &a, const FusedLevel *lvt)
-{
-    if (g_waves == 0 || g_waves == 14)
-        return launch_reg<MT, 4>(s, net, a, lvt);
-    if (g_waves == 18)
-        return launch_reg<MT, 8>(s, net, a, lvt);
-    if (g_waves == 2)
-        return launch_wide<MT>(s, net, a, lvt);
-    // 0 / 1: wide kernel (one wave per SIMD, 32 points per wave); 4 / 8: narrow
-    // kernel with 16 points per wave and that many waves per workgroup
-    if (g_waves == 4)
-        return launch_nw<MT, 4>(s, net, a, lvt);
-    if (MT < 16 && g_waves == 8)
-        return launch_nw<MT, (MT < 16 ? 8 : 4)>(s, net, a, lvt);
-    return launch_wide<MT>(s, net, a, lvt);
+    if (v.waves == 8) {
+        if constexpr (MT < 16)
+            return launch_kind<MT, 8>(s, net, a, v.kind, v.grid);
+        set_error("eight waves per workgroup do not fit the LDS at width %d", net->W);
+        return DS_ERR_UNSUPPORTED;
+    }
+    return launch_kind<MT, 4>(s, net, a, v.kind, v.grid);
 }
 
 }  // namespace
@@ -1254,31 +1000,42 @@ ds_status fused_pack_bf16(hipStream_t s, ds_net *net)
     return DS_OK;
 }
 
-ds_status fused_gather_packed(hipStream_t s, const FusedArgs &a, const FusedLevel *lvt, float *z)
+ds_status fused_gather_packed(hipStream_t s, const FusedArgs &a, float *z)
 {
-    int64_t blocks = (a.P + 63) / 64;
+    int64_t blocks = (a.cl[0].P + 63) / 64;
     if (blocks <= 0)
         return DS_OK;
-    k_gather_packed<<<(unsigned)blocks, 256, 0, s>>>(a, lvt, z);
+    k_gather_packed<<<(unsigned)blocks, 256, 0, s>>>(a, z);
     DS_HIP(hipGetLastError());
     return DS_OK;
 }
 
-ds_status fused_predict_bf16(hipStream_t s, const ds_net *net, const FusedArgs &a,
-                             const FusedLevel *lvt)
+bool fused_variant_ok(const ds_net *net, const FusedVariant &v)
 {
-    static const int env_waves = [] {
-        const char *e = getenv("DS_FUSED_WAVES");
-        return e ? atoi(e) : 0;
-    }();
-    g_waves = env_waves;
+    if (v.kind != DS_KERNEL_REGISTER && v.kind != DS_KERNEL_PIPELINED)
+        return false;
+    if (v.waves != 4 && v.waves != 8)
+        return false;
+    if (v.waves == 8 && fused_tiles(net->W) >= 16)
+        return false;
+    return v.grid >= 0;
+}
+
+ds_status fused_predict_bf16(hipStream_t s, const ds_net *net, const FusedArgs &a,
+                             const FusedVariant &v)
+{
+    DS_CHECK(a.n_clouds >= 1 && a.n_clouds <= kMaxBatch, DS_ERR_INVALID_ARG,
+             "between 1 and %d clouds per launch", kMaxBatch);
+    DS_CHECK(fused_variant_ok(net, v), DS_ERR_INVALID_ARG,
+             "kernel variant (kind %d, %d waves, grid %d) is not available at width %d", v.kind,
+             v.waves, v.grid, net->W);
     switch (fused_tiles(net->W)) {
-    case 1: return launch<1>(s, net, a, lvt);
-    case 2: return launch<2>(s, net, a, lvt);
-    case 4: return launch<4>(s, net, a, lvt);
-    case 8: return launch<8>(s, net, a, lvt);
-    case 13: return launch<13>(s, net, a, lvt);
-    case 16: return launch<16>(s, net, a, lvt);
+    case 1: return launch<1>(s, net, a, v);
+    case 2: return launch<2>(s, net, a, v);
+    case 4: return launch<4>(s, net, a, v);
+    case 8: return launch<8>(s, net, a, v);
+    case 13: return launch<13>(s, net, a, v);
+    case 16: return launch<16>(s, net, a, v);
     default:
         set_error("width %d is not supported by the fused kernel", net->W);
         return DS_ERR_UNSUPPORTED;

@@ -94,6 +94,18 @@ struct ds_net {
     size_t tws_floats = 0;
 };
 
+struct ds_batch {
+    ds_ctx *ctx = nullptr;
+    const ds_net *net = nullptr;
+    int n = 0;
+    const ds_cloud *clouds[16] = {};
+    int64_t offsets[17] = {};
+    int kind = 0, waves = 4, grid = 0;
+    float tuned_ms = -1.f;
+    hipStream_t cap_stream = nullptr;  // capture stream (created on first capture)
+    hipGraphExec_t exec = nullptr;
+};
+
 struct ds_adam {
     ds_net *net = nullptr;
     float lr = 1e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
@@ -173,18 +185,37 @@ struct FusedLevel {
     float inv_h;
     float step;          // 2^(k-1) / mean
 };
-struct FusedArgs {
-    const float *pos, *view, *light;
-    int64_t P;
-    float *out, *pre;
-    uint8_t *flags;
+constexpr int kMaxBatch = 16;  // clouds per fused launch
+struct FusedCloud {
+    const FusedLevel *lvt;   // device table, K entries
     float amin[3], amax[3];
     float inv_mean;
-    int K, W, H;
+    int32_t pad_;
+    int64_t p_begin;         // first point of this cloud in the point arrays
+    int64_t P;               // its point count
+    int64_t tile_begin;      // first tile (set by the launcher for its tile size)
 };
+// Kernel arguments: the per-cloud records travel in the argument block, so the
+// kernel reads them with scalar loads.
+struct FusedArgs {
+    const float *pos, *view, *light;
+    float *out, *pre;
+    uint8_t *flags;
+    int K, W, H;
+    int n_clouds;
+    int64_t n_tiles;
+    FusedCloud cl[kMaxBatch];
+};
+// Kernel variant of the fused prediction: kind (register-resident residual stream,
+// or LDS-resident with cross-chunk pipelining), waves per workgroup (16 points each)
+// and grid (0: one workgroup per tile; else that many persistent workgroups).
+struct FusedVariant {
+    int kind, waves, grid;
+};
+bool fused_variant_ok(const ds_net *net, const FusedVariant &v);
 ds_status fused_predict_bf16(hipStream_t s, const ds_net *net, const FusedArgs &a,
-                             const FusedLevel *lvt);
-ds_status fused_gather_packed(hipStream_t s, const FusedArgs &a, const FusedLevel *lvt, float *z);
+                             const FusedVariant &v);
+ds_status fused_gather_packed(hipStream_t s, const FusedArgs &a, float *z);
 
 // tracer.hip
 struct TracerParams {

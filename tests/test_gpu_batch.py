@@ -1,0 +1,175 @@
+"""Batched uneven prediction: several clouds of different sizes and uneven point
+counts in one launch of the fused kernel, every kernel variant, the autotuner and
+graph capture/replay, against per-cloud prediction and the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1709_05418_amd as ds
+from paper_1709_05418_amd import synth
+from _util import Workload, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+K, W, H = 5, 64, 3
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = ds.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def setup(ctx):
+    # four clouds (24^3 .. 48^3, one BF16 grid), uneven ragged point counts, one empty
+    sizes = [24, 40, 32, 48]
+    counts = [1000 + 3, 0, 4096 + 77, 257]
+    ws, clouds = [], []
+    for i, (n, P) in enumerate(zip(sizes, counts)):
+        dens = synth.cloud_density(n, 60 + i)
+        if i == 2:
+            dens = dens.to(torch.bfloat16)
+        w = Workload(n, float(n), L=5, K=K, P=max(P, 1), seed_cloud=60 + i, seed_pts=70 + i,
+                     density=dens)
+        ws.append(w)
+        clouds.append(ds.Cloud(ctx, dens.cuda(), w.sigma_max, w.aabb_min, w.h0, w.L, K, w.mips))
+    offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    pos = np.concatenate([w.pos[:P] for w, P in zip(ws, counts)])
+    view = np.concatenate([w.view[:P] for w, P in zip(ws, counts)])
+    light = np.concatenate([w.light[:P] for w, P in zip(ws, counts)])
+    net = ds.Net(ctx, K, W, H)
+    theta = synth.init_params(K, W, H, 9, branch_scale=0.5, out_scale=0.2, out_bias=0.5)
+    net.set_params(theta)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    yield dict(ws=ws, clouds=clouds, counts=counts, offsets=offsets, pos=t(pos), view=t(view),
+               light=t(light), net=net, theta=theta)
+    net.close()
+    for c in clouds:
+        c.close()
+
+
+def _batch(ctx, s):
+    return ds.ds_batch_create(ctx.h, s["net"].h, [c.h for c in s["clouds"]], s["offsets"])
+
+
+def _per_cloud(ctx, s, prec):
+    outs = []
+    for c, (a, b) in zip(s["clouds"], zip(s["offsets"][:-1], s["offsets"][1:])):
+        if b == a:
+            continue
+        o, _, _ = ds.ds_predict(ctx.h, c.h, s["net"].h, prec, s["pos"][a:b], s["view"][a:b],
+                                s["light"][a:b], want_pre=False, want_flags=False)
+        outs.append(o)
+    return torch.cat(outs)
+
+
+def test_batched_equals_per_cloud_and_oracle(ctx, setup):
+    s = setup
+    N = int(s["offsets"][-1])
+    b = _batch(ctx, s)
+    try:
+        out = torch.empty(N, dtype=torch.float32, device="cuda")
+        pre = torch.empty(N, dtype=torch.float32, device="cuda")
+        fl = torch.empty(N, dtype=torch.uint8, device="cuda")
+        ds.ds_batch_predict(b, ds.DS_PREC_BF16, s["pos"], s["view"], s["light"], out, pre, fl)
+        ref = _per_cloud(ctx, s, ds.DS_PREC_BF16)
+        # each point's arithmetic does not depend on which tile carries it
+        assert torch.equal(out, ref)
+        out32 = torch.empty_like(out)
+        ds.ds_batch_predict(b, ds.DS_PREC_F32, s["pos"], s["view"], s["light"], out32)
+        assert torch.equal(out32, _per_cloud(ctx, s, ds.DS_PREC_F32))
+        # against the oracle, cloud by cloud
+        got, got32, want = [], [], []
+        for w, P, a in zip(s["ws"], s["counts"], s["offsets"]):
+            if P == 0:
+                continue
+            idx = np.arange(0, P, 7)
+            z, _ = w.oracle_z(idx)
+            g, _ = O.forward(s["theta"].astype(np.float64), K, W, H, z)
+            want.append(g)
+            got.append(out.cpu().numpy()[a + idx])
+            got32.append(out32.cpu().numpy()[a + idx])
+        want = np.concatenate(want)
+        assert rel_l2(np.concatenate(got32), want) < 1e-5
+        assert rel_l2(np.concatenate(got), want) < 2e-2
+    finally:
+        ds.ds_batch_destroy(b)
+
+
+def test_every_variant_and_grid_agrees(ctx, setup):
+    s = setup
+    N = int(s["offsets"][-1])
+    b = _batch(ctx, s)
+    try:
+        base = torch.empty(N, dtype=torch.float32, device="cuda")
+        ds.ds_batch_predict(b, ds.DS_PREC_BF16, s["pos"], s["view"], s["light"], base)
+        for kind in (ds.DS_KERNEL_REGISTER, ds.DS_KERNEL_PIPELINED):
+            for waves in (4, 8):
+                for grid in (0, 1, 3, 64):
+                    print("variant", kind, waves, grid, flush=True)
+                    ds.ds_batch_set_config(b, kind, waves, grid)
+                    out = torch.full((N,), -1.0, device="cuda")
+                    ds.ds_batch_predict(b, ds.DS_PREC_BF16, s["pos"], s["view"], s["light"], out)
+                    assert torch.equal(out, base), (kind, waves, grid)
+        with pytest.raises(ds.DSError):
+            ds.ds_batch_set_config(b, 2, 4, 0)
+        with pytest.raises(ds.DSError):
+            ds.ds_batch_set_config(b, 0, 6, 0)
+    finally:
+        ds.ds_batch_destroy(b)
+
+
+def test_autotune_then_graph_replay(ctx, setup):
+    s = setup
+    N = int(s["offsets"][-1])
+    b = _batch(ctx, s)
+    try:
+        eager = torch.empty(N, dtype=torch.float32, device="cuda")
+        ds.ds_batch_predict(b, ds.DS_PREC_BF16, s["pos"], s["view"], s["light"], eager)
+        cfg = ds.ds_batch_autotune(b, ds.DS_PREC_BF16, s["pos"], s["view"], s["light"], eager, 2)
+        assert cfg["ms"] > 0 and cfg["waves"] in (4, 8) and cfg["kernel"] in (0, 1)
+        out = torch.full((N,), -1.0, device="cuda")
+        pos = s["pos"].clone()
+        ds.ds_batch_capture(b, ds.DS_PREC_BF16, pos, s["view"], s["light"], out)
+        for r in range(3):
+            out.fill_(-1.0)
+            ds.ds_batch_replay(b)
+            torch.cuda.synchronize()
+            assert torch.equal(out, eager), r
+            _ = (pos * 2).sum()  # unrelated eager work between replays
+        # the graph reads the arrays it was captured with: new contents, new results
+        pos[: s["counts"][0]] += 0.01
+        ds.ds_batch_replay(b)
+        torch.cuda.synchronize()
+        moved = torch.empty_like(out)
+        ds.ds_batch_predict(b, ds.DS_PREC_BF16, pos, s["view"], s["light"], moved)
+        assert torch.equal(out, moved) and not torch.equal(out, eager)
+        with pytest.raises(ds.DSError):
+            ds.ds_batch_capture(b, ds.DS_PREC_F32, pos, s["view"], s["light"], out)
+    finally:
+        ds.ds_batch_destroy(b)
+
+
+def test_batch_argument_checks(ctx, setup):
+    s = setup
+    with pytest.raises(ds.DSError):
+        ds.ds_batch_create(ctx.h, s["net"].h, [s["clouds"][0].h] * 17, list(range(18)))
+    with pytest.raises(ds.DSError):
+        ds.ds_batch_create(ctx.h, s["net"].h, [c.h for c in s["clouds"][:2]], [0, 5, 3])
+    with pytest.raises(ds.DSError):
+        ds.ds_batch_create(ctx.h, s["net"].h, [c.h for c in s["clouds"][:2]], [1, 5, 6])
+    other = ds.Net(ctx, K + 1, W, H)
+    try:
+        with pytest.raises(ds.DSError):
+            ds.ds_batch_create(ctx.h, other.h, [c.h for c in s["clouds"][:2]], [0, 5, 6])
+    finally:
+        other.close()
+    b = _batch(ctx, s)
+    try:
+        with pytest.raises(ds.DSError):
+            ds.ds_batch_replay(b)
+    finally:
+        ds.ds_batch_destroy(b)
