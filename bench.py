@@ -77,12 +77,111 @@ def macs_per_point(K, W, H):
     return 226 * K * W + (K - 1) * W * W + K * W * W + (H - 1) * W * W + W
 
 
+BATCHED = dict(sizes=[128, 192, 256, 384, 512, 640, 768, 1024], seeds=list(range(100, 108)),
+               point_seed=200, pts_seeds=list(range(300, 308)), K=10, W=200, H=3, seed_theta=12,
+               name="batched uneven inference: 8 BF16 clouds 128^3..1024^3 (sigma_max = n/unit, "
+                    "fBm+Worley), 10^4..2x10^6 points each (log-uniform), K=10, W=200, one "
+                    "persistent launch replayed from a HIP graph, autotuned variant")
+
+
+def run_batched(args, log):
+    """Batched uneven workload: one autotuned persistent launch over 8 clouds,
+    captured in a HIP graph and replayed; compared with one ds_predict per cloud."""
+    import torch
+    import paper_1709_05418_amd as ds
+    from paper_1709_05418_amd import synth
+    cfg = BATCHED
+    dev = torch.device("cuda:0")
+    K, W, H = cfg["K"], cfg["W"], cfg["H"]
+    rng = np.random.default_rng(cfg["point_seed"])
+    counts = np.exp(rng.uniform(np.log(1e4), np.log(2e6), len(cfg["sizes"]))).astype(np.int64)
+    ctx = ds.Context(0)
+    clouds, pos, view, light = [], [], [], []
+    t0 = time.time()
+    for n, sd, ps, P in zip(cfg["sizes"], cfg["seeds"], cfg["pts_seeds"], counts):
+        d = synth.cloud_density(n, sd, worley=0.3, device=dev, dtype=torch.bfloat16)
+        amin, h0 = synth.unit_box(n)
+        L = min(16, int(math.ceil(math.log2(n))) + 1)
+        clouds.append(ds.Cloud(ctx, d, float(n), amin, h0, L, K))
+        pos.append(synth.points_in_density_device(d, int(P), ps, amin, h0))
+        view.append(torch.from_numpy(synth.uniform_dirs(int(P), ps + 1000)).to(dev))
+        light.append(torch.from_numpy(synth.uniform_dirs(int(P), ps + 2000)).to(dev))
+        del d
+        torch.cuda.synchronize()
+        log(f"cloud {n}^3: {int(P)} points, {L} levels, mean {clouds[-1].info['mean_mu_t']:.1f} "
+            f"({time.time() - t0:.1f}s)")
+    pos, view, light = torch.cat(pos), torch.cat(view), torch.cat(light)
+    offsets = np.concatenate([[0], np.cumsum(counts)])
+    N = int(offsets[-1])
+    net = ds.Net(ctx, K, W, H)
+    net.set_params(synth.init_params(K, W, H, cfg["seed_theta"]))
+    out = torch.empty(N, dtype=torch.float32, device=dev)
+    b = ds.ds_batch_create(ctx.h, net.h, [c.h for c in clouds], offsets)
+    ta = time.time()
+    tuned = ds.ds_batch_autotune(b, ds.DS_PREC_BF16, pos, view, light, out, 2)
+    log(f"autotune {time.time() - ta:.1f}s: {tuned}")
+    ds.ds_batch_capture(b, ds.DS_PREC_BF16, pos, view, light, out)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        ds.ds_batch_replay(b)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    tw = time.perf_counter()
+    for a, e in evs:
+        a.record(stream)
+        ds.ds_batch_replay(b)
+        e.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - tw
+    ms_step = wall * 1e3 / args.steps
+    kernel_ms = float(np.mean([a.elapsed_time(e) for a, e in evs]))
+    # the same points, one default ds_predict per cloud
+    seq = torch.empty_like(out)
+    def per_cloud():
+        for c, (a, e) in zip(clouds, zip(offsets[:-1], offsets[1:])):
+            ds.ds_predict(ctx.h, c.h, net.h, ds.DS_PREC_BF16, pos[a:e], view[a:e], light[a:e],
+                          out=seq[a:e], want_pre=False, want_flags=False)
+    per_cloud()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(args.steps):
+        per_cloud()
+    torch.cuda.synchronize()
+    ms_seq = (time.perf_counter() - ts) * 1e3 / args.steps
+    same = bool(torch.equal(seq, out))
+    flop = 2.0 * macs_per_point(K, W, H) * N
+    achieved = flop / (kernel_ms / 1e3) / 1e12
+    log(f"batched graph replay {ms_step:.3f} ms ({kernel_ms:.3f} ms events), per-cloud "
+        f"launches {ms_seq:.3f} ms, identical outputs {same}")
+    line = {
+        "metric": METRIC, "value": round(N / (ms_step / 1e3), 1), "unit": "shading points/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": cfg["name"], "points": N, "points_per_cloud": counts.tolist(),
+                   "autotuned": tuned, "per_cloud_launches_ms": round(ms_seq, 4),
+                   "batched_equals_per_cloud": same},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
+                     "traffic": None, "kernel": "fused prediction, autotuned variant",
+                     "flop_per_point": 2 * macs_per_point(K, W, H), "points_per_launch": N},
+        "cpu_baseline": None,
+    }
+    ds.ds_batch_destroy(b)
+    net.close()
+    for c in clouds:
+        c.close()
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="paper", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="paper", choices=sorted(WORKLOADS) + ["batched"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the FP64 oracle baseline")
     ap.add_argument("--cpu-sample", type=int, default=262144)
     ap.add_argument("--fp32-steps", type=int, default=3, help="0 skips the FP32 plain form")
@@ -100,6 +199,10 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
+    if args.workload == "batched":
+        return run_batched(args, log)
+
     import torch
     import paper_1709_05418_amd as ds
     from paper_1709_05418_amd import synth
@@ -108,7 +211,6 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     K, W, H, P = cfg["K"], cfg["W"], cfg["H"], cfg["P"]
-    log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
 
     t0 = time.time()
     aabb_min, h0 = synth.unit_box(cfg["n"])

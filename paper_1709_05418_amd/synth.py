@@ -186,6 +186,33 @@ def points_in_density(d, P: int, seed: int, aabb_min, h0: float) -> np.ndarray:
     return pos.astype(np.float32)
 
 
+def points_in_density_device(d: torch.Tensor, P: int, seed: int, aabb_min, h0: float):
+    """Same distribution as points_in_density for grids too large to scan on the
+    host: voxels drawn uniformly on the device, kept where d > 0 (rejection),
+    jittered inside the voxel.  Returns a (P, 3) float32 device tensor."""
+    nz, ny, nx = d.shape
+    g = torch.Generator(device=d.device).manual_seed(seed)
+    flat = d.reshape(-1)
+    got = []
+    have = 0
+    while have < P:
+        m = max(4 * (P - have), 4096)
+        cand = torch.randint(0, flat.numel(), (m,), generator=g, device=d.device)
+        cand = cand[flat[cand] > 0][: P - have]
+        got.append(cand)
+        have += cand.numel()
+        if have == 0 and m > 64 * P + 4096:
+            raise ValueError("density grid looks empty")
+    pick = torch.cat(got)
+    iz = pick // (ny * nx)
+    rem = pick % (ny * nx)
+    iy, ix = rem // nx, rem % nx
+    jit = torch.rand((P, 3), generator=g, device=d.device, dtype=torch.float64)
+    lo = torch.as_tensor(np.asarray(aabb_min, np.float64), device=d.device)
+    idx = torch.stack([ix, iy, iz], 1).to(torch.float64)
+    return (lo + (idx + jit) * h0).to(torch.float32)
+
+
 def layer_shapes(K: int, W: int, H: int = 3, n_in: int = 226):
     """(name, rows, cols) of every weight matrix / bias vector in canonical order:
     per block k: V[W][226], W1[W][W] (k > 1 only), b1[W], W2[W][W], b2[W];
