@@ -71,9 +71,8 @@ def train(net, opt, z, t, steps, batch=1024, val_frac=0.25, eval_every=500, seed
     val.append((0, v0))
     for i in range(steps):
         j = i % per_epoch
-        if j == 0:
-            start = int(torch.randint(0, batch, (1,), generator=g).item()) \
-                if n_tr - per_epoch * batch >= batch else 0
+        if j == 0:  # each pass starts at a random offset within the leftover rows
+            start = int(torch.randint(0, n_tr - per_epoch * batch + 1, (1,), generator=g).item())
         a = start + j * batch
         ds.ds_train_step(net.h, opt, zt[a:a + batch], tt[a:a + batch], loss=losses[i:i + 1])
         if eval_every and (i + 1) % eval_every == 0:
@@ -117,3 +116,150 @@ def judge(ctx, cloud, net, precision, params, light_dir, ray_o, ray_d, spp, ref_
             "ref_noise_rel": float(math.sqrt(float(ref_var.sum())) / max(float(ref.sum()), 1e-300)),
             "fallback_samples": nfb, "seconds_network": t_net, "seconds_reference": t_ref,
             "image": img, "reference": ref, "direct": direct}
+
+
+def camera(width, height, cam_pos=(0.0, 0.12, 2.3), look_at=(0.0, 0.0, 0.0), fov_deg=42.0,
+           crop=None, seed=0, device="cuda"):
+    """Jittered pinhole rays of a width x height view (fov over the larger side), as
+    device tensors (origins, directions); crop = (x0, y0, w, h) keeps a window."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(seed)
+    x0, y0, w, h = crop if crop else (0, 0, width, height)
+    px, py = np.meshgrid(np.arange(x0, x0 + w), np.arange(y0, y0 + h))
+    px, py = px.reshape(-1).astype(np.float64), py.reshape(-1).astype(np.float64)
+    cam = np.asarray(cam_pos, np.float64)
+    fwd = np.asarray(look_at, np.float64) - cam
+    fwd /= np.linalg.norm(fwd)
+    right = np.cross(fwd, [0.0, 1.0, 0.0])
+    right /= np.linalg.norm(right)
+    up = np.cross(right, fwd)
+    t = math.tan(math.radians(fov_deg) / 2)
+    s = max(width, height)
+    u = ((px + rng.random(px.size)) / s * 2 - width / s) * t
+    v = (height / s - (py + rng.random(py.size)) / s * 2) * t
+    d = fwd[None] + u[:, None] * right[None] + v[:, None] * up[None]
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    o = np.broadcast_to(cam, d.shape)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
+    return T(o), T(d)
+
+
+def main(argv=None):
+    """Training pairs from procedural clouds, paper-width training, then a frame of
+    a larger held-out cloud rendered with the network and judged against path
+    tracing on a crop.  Prints progress and one JSON summary line."""
+    import argparse
+    import json
+    import numpy as np
+    import torch
+    from paper_1709_05418_amd import synth
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--clouds", type=int, default=32)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--records", type=int, default=1 << 19, help="total training pairs")
+    ap.add_argument("--spp", type=int, default=256, help="paths per training pair")
+    ap.add_argument("--K", type=int, default=10)
+    ap.add_argument("--W", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--judge-n", type=int, default=1024)
+    ap.add_argument("--width", type=int, default=1920)
+    ap.add_argument("--height", type=int, default=1080)
+    ap.add_argument("--crop", type=int, default=128)
+    ap.add_argument("--frame-spp", type=int, default=4)
+    ap.add_argument("--crop-spp", type=int, default=64)
+    ap.add_argument("--ref-spp", type=int, default=512)
+    ap.add_argument("--fallback-spp", type=int, default=64)
+    ap.add_argument("--seed", type=int, default=1000)
+    ap.add_argument("--save-theta", default=None)
+    args = ap.parse_args(argv)
+    log = lambda *a: print("[learn]", *a, flush=True)
+    dev = "cuda"
+    ctx = ds.Context(0)
+    prm = ds.TracerParams(0.999, 0.85, 1.0, ds.DS_LIGHT_DIRECTIONAL, 0)
+    K, W = args.K, args.W
+    L = int(math.ceil(math.log2(args.n))) + 1
+    per = args.records // args.clouds
+    D = ds.STENCIL_N * K + 1
+    z = torch.empty((per * args.clouds, D), dtype=torch.float32, device=dev)
+    t = torch.empty(per * args.clouds, dtype=torch.float32, device=dev)
+    t0 = time.time()
+    for c in range(args.clouds):
+        d = synth.cloud_density(args.n, args.seed + c, worley=0.3, device=dev)
+        amin, h0 = synth.unit_box(args.n)
+        cl = ds.Cloud(ctx, d, float(args.n), amin, h0, L, K)
+        ds.ds_make_records(ctx.h, cl.h, prm, per, args.spp, args.seed + 7919 * c, z, t,
+                           offset=c, stride=args.clouds)
+        torch.cuda.synchronize()
+        cl.close()
+        del d
+        log(f"cloud {c + 1}/{args.clouds}: {per} pairs x {args.spp} paths "
+            f"({time.time() - t0:.1f}s)")
+    t_data = time.time() - t0
+    paths = per * args.clouds * args.spp
+    li = torch.expm1(t)
+    log(f"data: {z.shape[0]} pairs, {paths:.3e} paths in {t_data:.1f}s "
+        f"({paths / t_data:.3e} paths/s); mean L_i {float(li.mean()):.4f}")
+    net = ds.Net(ctx, K, W, 3)
+    net.set_params(synth.init_params(K, W, 3, args.seed + 1, branch_scale=1 / math.sqrt(K),
+                                     out_scale=0.01, out_bias=float(li.mean())))
+    opt = ds.ds_adam_create(net.h, args.lr)
+    res = train(net, opt, z, t, args.steps, args.batch, 0.25, eval_every=max(1, args.steps // 10),
+                log=log)
+    log(f"training {res['seconds']:.1f}s ({args.steps / res['seconds']:.1f} steps/s)")
+    if args.save_theta:
+        np.save(args.save_theta, net.get_params())
+    del z, t
+    torch.cuda.empty_cache()
+    # held-out cloud, larger grid, same optical size in mean free paths per unit
+    d = synth.cloud_density(args.judge_n, args.seed + 5000, worley=0.3, device=dev,
+                            dtype=torch.bfloat16)
+    amin, h0 = synth.unit_box(args.judge_n)
+    Lj = min(16, int(math.ceil(math.log2(args.judge_n))) + 1)
+    jc = ds.Cloud(ctx, d, float(args.n), amin, h0, Lj, K)
+    del d
+    log(f"judge cloud {args.judge_n}^3 built ({time.time() - t0:.1f}s)")
+    light = synth.table1_lights()["side"]
+    o, dd = camera(args.width, args.height, seed=1)
+    summary = {}
+    for name, prec in (("bf16", ds.DS_PREC_BF16), ("fp32", ds.DS_PREC_F32)):
+        torch.cuda.synchronize()
+        tf = time.time()
+        img, _, direct, nfb = ds.ds_render_rpnn(ctx.h, jc.h, net.h, prec, prm, light, o, dd,
+                                                args.frame_spp, 5, args.fallback_spp,
+                                                count_fallback=True)
+        torch.cuda.synchronize()
+        summary[f"frame_ms_{name}"] = (time.time() - tf) * 1e3
+        summary[f"frame_fallback_samples_{name}"] = nfb
+        log(f"{args.width}x{args.height} frame {name}, {args.frame_spp} spp: "
+            f"{summary[f'frame_ms_{name}']:.1f} ms, fallback samples {nfb}")
+    cx0 = (args.width - args.crop) // 2
+    cy0 = (args.height - args.crop) // 2
+    co, cd = camera(args.width, args.height, crop=(cx0, cy0, args.crop, args.crop), seed=2)
+    for name, prec in (("bf16", ds.DS_PREC_BF16), ("fp32", ds.DS_PREC_F32)):
+        j = judge(ctx, jc, net, prec, prm, light, co, cd, args.crop_spp, args.ref_spp, 11,
+                  args.fallback_spp)
+        for k in ("rel_l1", "rmse", "rel_l1_direct_only", "rmse_direct_only", "ref_noise_rel",
+                  "seconds_network", "seconds_reference", "fallback_samples"):
+            summary[f"crop_{k}_{name}"] = j[k]
+        log(f"crop {args.crop}^2 {name}: rel L1 {j['rel_l1']:.4f} (direct only "
+            f"{j['rel_l1_direct_only']:.4f}), RMSE {j['rmse']:.5f}; reference noise "
+            f"{j['ref_noise_rel']:.4f}; network {j['seconds_network']:.2f}s vs reference "
+            f"{j['seconds_reference']:.2f}s")
+    summary.update({"clouds": args.clouds, "n": args.n, "pairs": per * args.clouds,
+                    "spp": args.spp, "K": K, "W": W, "steps": args.steps, "batch": args.batch,
+                    "data_seconds": t_data, "paths_per_second": paths / t_data,
+                    "train_seconds": res["seconds"], "held_out": res["held_out"],
+                    "judge_n": args.judge_n, "frame": [args.width, args.height],
+                    "crop": args.crop, "crop_spp": args.crop_spp, "ref_spp": args.ref_spp})
+    print(json.dumps(summary), flush=True)
+    ds.ds_adam_destroy(opt)
+    net.close()
+    jc.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()
