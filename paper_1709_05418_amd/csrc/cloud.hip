@@ -1,6 +1,6 @@
 // Per-cloud precompute: mean extinction over non-zero voxels (Sec. 4.2, 5) and the
 // Gaussian density mipmap with sigma_i = 2^i base voxels (Sec. 6), plus the
-// corner-packed BF16 copy of every level read by the fused prediction kernel.
+// corner-packed FP16 copy of every level read by the fused prediction kernel.
 #include <math.h>
 
 #include <vector>
@@ -148,16 +148,17 @@ __global__ void __launch_bounds__(256) k_blur(const void *in, ds_dtype dt, float
     }
 }
 
-__device__ __forceinline__ uint32_t bf16_rne(float f)
+// FP16 bits of f, round to nearest even, saturated at the largest finite value.
+__device__ __forceinline__ uint32_t f16_sat(float f)
 {
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return u >> 16;
+    const _Float16 h = (_Float16)fminf(f, 65504.f);
+    return (uint32_t)__builtin_bit_cast(uint16_t, h);
 }
 
 // Corner-packed level: cell (cx, cy, cz) holds the 8 values around lower corner
-// (cx-1, cy-1, cz-1) as bf16, zero outside the level grid:
-// word 0 = (v000, v100), 1 = (v010, v110), 2 = (v001, v101), 3 = (v011, v111).
+// (cx-1, cy-1, cz-1) as FP16, zero outside the level grid:
+// word 0 = (v000, v100), 1 = (v010, v110), 2 = (v001, v101), 3 = (v011, v111),
+// the first value of each pair in the low half.
 __global__ void __launch_bounds__(256) k_pack(const float *__restrict__ lv, int nx, int ny, int nz,
                                               uint4 *__restrict__ cells)
 {
@@ -174,7 +175,7 @@ __global__ void __launch_bounds__(256) k_pack(const float *__restrict__ lv, int 
         for (int c = 0; c < 8; ++c) {
             int64_t a = i + (c & 1), b = j + ((c >> 1) & 1), e = k + ((c >> 2) & 1);
             bool in = a >= 0 && b >= 0 && e >= 0 && a < nx && b < ny && e < nz;
-            v[c] = in ? bf16_rne(lv[(e * ny + b) * nx + a]) : 0u;
+            v[c] = in ? f16_sat(lv[(e * ny + b) * nx + a]) : 0u;
         }
         cells[idx] = make_uint4(v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16),
                                 v[6] | (v[7] << 16));

@@ -27,7 +27,7 @@
 // 6 take 24 of the 25 samples of the iz = 8 plane (five rows of four and one
 // column of four), and chunk 7 carries the last plane sample (4, 4, 8), gamma and
 // (for an odd tile count) the last tile of o^{k-1}.
-// Densities come from a corner-packed BF16 copy of the mip level (the 8 corners
+// Densities come from a corner-packed FP16 copy of the mip level (the 8 corners
 // of a cell in one 16-byte load) addressed in cell coordinates shifted by one and
 // clamped to [0, n+1], which reproduces zero outside the grid.
 #include <stdlib.h>
@@ -83,16 +83,27 @@ __device__ __forceinline__ void issue_one(gcell_ptr cells, const FusedLevel &L, 
     v = cells[idx];
 }
 
-// Trilinear interpolation of a loaded cell in FP32: unpack the eight bf16 corners
-// (a shift or a mask each) and lerp along x, y, z.  (The v_dot2c_f32_bf16 form of
-// the x lerps read its zeroed accumulator register stale when the compiler placed
-// the zeroing move right before it, so it is not used.)
+// Trilinear interpolation of a loaded cell in FP32.  (Corners stored as BF16 pairs
+// would need a shift or a mask per corner before the lerps; a v_dot2c_f32_bf16
+// form of the x lerps read its zeroed accumulator register stale when the
+// compiler placed the zeroing move right before it.)
+// x-lerp of the FP16 pair (lo, hi) of word w with weights (gx, fx): the mixed-
+// precision FMAs read the halves in place, so no unpacking instructions.
+__device__ __forceinline__ float lerp_pair(uint32_t w, float fx, float gx)
+{
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    const h2 v = __builtin_bit_cast(h2, w);
+    return fmaf((float)v[1], fx, fmaf((float)v[0], gx, 0.f));
+}
+
+// Trilinear value of a sample from its 8 corners (FP16) in FP32.
 __device__ __forceinline__ float finish_one(const u32x4 &v, float fx, float fy, float fz)
 {
-    const float x00 = lerp(__uint_as_float(v[0] << 16), __uint_as_float(v[0] & 0xffff0000u), fx);
-    const float x10 = lerp(__uint_as_float(v[1] << 16), __uint_as_float(v[1] & 0xffff0000u), fx);
-    const float x01 = lerp(__uint_as_float(v[2] << 16), __uint_as_float(v[2] & 0xffff0000u), fx);
-    const float x11 = lerp(__uint_as_float(v[3] << 16), __uint_as_float(v[3] & 0xffff0000u), fx);
+    const float gx = 1.f - fx;
+    const float x00 = lerp_pair(v[0], fx, gx);
+    const float x10 = lerp_pair(v[1], fx, gx);
+    const float x01 = lerp_pair(v[2], fx, gx);
+    const float x11 = lerp_pair(v[3], fx, gx);
     return lerp(lerp(x00, x10, fy), lerp(x01, x11, fy), fz);
 }
 
@@ -106,8 +117,9 @@ __device__ __forceinline__ void issue_column_half(gcell_ptr cells, const FusedLe
     const float bx = q.u0[0] + ix * q.a[0] + iy * q.b[0] + iz0 * q.c[0];
     const float by = q.u0[1] + ix * q.a[1] + iy * q.b[1] + iz0 * q.c[1];
     const float bz = q.u0[2] + ix * q.a[2] + iy * q.b[2] + iz0 * q.c[2];
+    issue_one(cells, L, bx, by, bz, p.v[0], p.fx[0], p.fy[0], p.fz[0]);
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 1; j < 4; ++j)
         issue_one(cells, L, fmaf((float)j, q.c[0], bx), fmaf((float)j, q.c[1], by),
                   fmaf((float)j, q.c[2], bz), p.v[j], p.fx[j], p.fy[j], p.fz[j]);
 }
@@ -165,20 +177,44 @@ __device__ __forceinline__ int tile_cloud(const FusedArgs &a, int64_t t)
     return __builtin_amdgcn_readfirstlane(c);
 }
 
-__device__ __forceinline__ void point_level(const FusedLevel &L, const float *x, const Frame &fr,
-                                            const float *amin, bool valid, PtLevel &q)
+// Per-point geometry that every stencil level needs: the position relative to the
+// grid corner (x'), the frame axes X, Y, Z and their sum S (the lattice origin sits
+// at -S half steps), and whether the point is valid.  Computed once per tile and
+// kept in LDS; layout [x'0 x'1 x'2 S0] [S1 S2 X0 X1] [X2 Y0 Y1 Y2] [Z0 Z1 Z2 ok].
+struct PtGeom {
+    float4 a, b, c, d;
+};
+
+__device__ __forceinline__ PtGeom make_geom(const float *x, const Frame &fr, const float *amin,
+                                            bool valid)
 {
-    const float st = L.step * L.inv_h;
+    PtGeom G;
+    const float S0 = fr.X[0] + fr.Y[0] + fr.Z[0];
+    const float S1 = fr.X[1] + fr.Y[1] + fr.Z[1];
+    const float S2 = fr.X[2] + fr.Y[2] + fr.Z[2];
+    G.a = make_float4(x[0] - amin[0], x[1] - amin[1], x[2] - amin[2], S0);
+    G.b = make_float4(S1, S2, fr.X[0], fr.X[1]);
+    G.c = make_float4(fr.X[2], fr.Y[0], fr.Y[1], fr.Y[2]);
+    G.d = make_float4(fr.Z[0], fr.Z[1], fr.Z[2], valid ? 1.f : 0.f);
+    return G;
+}
+
+// Stencil origin and lattice steps of one level, in cell coordinates shifted by +1
+// (cell coordinates start at the zero border cell).
+__device__ __forceinline__ void level_from_geom(const FusedLevel &L, const PtGeom &G, PtLevel &q)
+{
+    const float st = L.step * L.inv_h, hs = 0.5f * st;
+    const float xr[3] = {G.a.x, G.a.y, G.a.z}, S[3] = {G.a.w, G.b.x, G.b.y};
+    const float X[3] = {G.b.z, G.b.w, G.c.x}, Y[3] = {G.c.y, G.c.z, G.c.w};
+    const float Z[3] = {G.d.x, G.d.y, G.d.z};
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const float X = fr.X[c], Y = fr.Y[c], Z = fr.Z[c];
-        // +1: cell coordinates start at the zero border cell
-        q.u0[c] = (x[c] - amin[c]) * L.inv_h + 0.5f - st * (X + Y + Z);
-        q.a[c] = 0.5f * st * X;
-        q.b[c] = 0.5f * st * Y;
-        q.c[c] = 0.5f * st * Z;
+        q.u0[c] = fmaf(-st, S[c], fmaf(xr[c], L.inv_h, 0.5f));
+        q.a[c] = hs * X[c];
+        q.b[c] = hs * Y[c];
+        q.c[c] = hs * Z[c];
     }
-    if (!valid)
+    if (!(G.d.w > 0.f))
         q.u0[0] = q.u0[1] = q.u0[2] = -4.f;  // clamps to the zero border cell
 }
 
@@ -196,10 +232,14 @@ __device__ __forceinline__ bf16x8 pack8(const f4 &lo, const f4 &hi)
     return r;
 }
 
-// Double-buffered staging of weight chunks (MT fragments of 64 x 16 bytes).  Every
-// thread copies a fixed share of entries per chunk; only the last copy is
-// predicated per lane.  Loads past the last chunk land in zeroed padding of the
-// device buffer and are never consumed.
+// Double-buffered staging of weight chunks (MT fragments of 64 x 16 bytes).  The
+// next chunk is copied from global memory straight into the idle LDS buffer
+// (global_load_lds, 16 bytes per lane, lane l of a wave writing base + 16 l), so
+// the copy holds no registers; advance() waits for the copy and publishes it.
+// FR is a multiple of 64, so each wave copies whole 1 KB rows or none.
+typedef __attribute__((address_space(1))) void gvoid;
+typedef __attribute__((address_space(3))) void lvoid;
+
 template <int MT, int NW>
 struct WeightStage {
     static constexpr int FR = MT * 64;
@@ -209,24 +249,27 @@ struct WeightStage {
     uint4 *buf;          // LDS, 2 * SLOT entries
     const uint4 *src;    // next chunk to fetch
     int cur;
-    uint4 pf[R];
 
     __device__ __forceinline__ const uint4 *chunk() const { return buf + cur * SLOT; }
-    // start fetching the next chunk into registers
+    // start copying the next chunk into the buffer not being read: wave w copies the
+    // 64-entry rows w, w + NW, ... (scalar bases, one lane offset for every row)
     __device__ __forceinline__ void fetch(int tid)
     {
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-            pf[r] = src[tid + r * T];
-    }
-    // publish the fetched chunk and switch buffers (all threads must call)
-    __device__ __forceinline__ void advance(int tid)
-    {
+        const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const int lane = tid & 63;
         uint4 *dst = buf + (cur ^ 1) * SLOT;
 #pragma unroll
-        for (int r = 0; r < R; ++r)
-            if (r + 1 < R || tid + r * T < FR)
-                dst[tid + r * T] = pf[r];
+        for (int r = 0; r < R; ++r) {
+            const int row = w + r * NW;
+            if (r + 1 < R || row < MT)
+                __builtin_amdgcn_global_load_lds((gvoid *)(src + row * 64 + lane),
+                                                 (lvoid *)(dst + row * 64), 16, 0, 0);
+        }
+    }
+    // wait for the copy, publish it and switch buffers (all threads must call)
+    __device__ __forceinline__ void advance(int)
+    {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         src += FR;
         __syncthreads();
         cur ^= 1;
@@ -280,6 +323,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
     // residual stream o^k of each wave in FP32, accumulator layout [tile][lane]; it
     // lives in LDS while the first layer runs and comes back for the second
     __shared__ f4 obuf[NW][MT][64];
+    __shared__ PtGeom geom[16 * NW];   // per point of the tile, see make_geom
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -319,6 +363,8 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
             Frame fr;
             valid = point_frame(a, p, in, x, fr);
             gamma = fr.gamma;
+            // the four lanes of a point write the same slot; each reads its own write
+            geom[(tid >> 6) * 16 + n] = make_geom(x, fr, cl.amin, valid);
         }
 
         f4 F[MT];
@@ -334,10 +380,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
         gcell_ptr cells = (gcell_ptr)L.cells;
         PtLevel q;
         {
-            float x[3];
-            Frame fr;
-            point_frame(a, p, in, x, fr);
-            point_level(L, x, fr, cl.amin, valid, q);
+            level_from_geom(L, geom[(tid >> 6) * 16 + n], q);
         }
         Pending pa, pb;
         issue_column_half(cells, L, q, 0, g, pa);
@@ -419,10 +462,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
             if (k + 1 < a.K) {
                 L = cl.lvt[k + 1];
                 cells = (gcell_ptr)L.cells;
-                float x[3];
-                Frame fr;
-                point_frame(a, p, in, x, fr);
-                point_level(L, x, fr, cl.amin, valid, q);
+                level_from_geom(L, geom[(tid >> 6) * 16 + n], q);
                 issue_column_half(cells, L, q, 0, g, pa);
                 issue_column_half(cells, L, q, 1, g, pb);
             }
@@ -512,6 +552,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
     constexpr int WP = 16 * MT;
     __shared__ uint4 wbuf[2 * WeightStage<MT, NW>::SLOT];
     __shared__ float4 plane[32];
+    __shared__ PtGeom geom[16 * NW];   // per point of the tile, see make_geom
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int g = lane >> 4, n = lane & 15;
@@ -549,6 +590,8 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
             Frame fr;
             valid = point_frame(a, p, in, x, fr);
             gamma = fr.gamma;
+            // the four lanes of a point write the same slot; each reads its own write
+            geom[(tid >> 6) * 16 + n] = make_geom(x, fr, cl.amin, valid);
         }
         const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
         f4 O[MT], F[MT];
@@ -561,10 +604,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
             gcell_ptr cells = (gcell_ptr)L.cells;
             PtLevel q;
             {
-                float x[3];
-                Frame fr;
-                point_frame(a, p, in, x, fr);
-                point_level(L, x, fr, cl.amin, valid, q);
+                level_from_geom(L, geom[(tid >> 6) * 16 + n], q);
             }
             const float *b1 = vec + (size_t)k * 2 * WP;
             const float *b2 = b1 + WP;
@@ -573,7 +613,6 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
                 F[mt] = z4;
     #pragma unroll 1
             for (int c = 0; c < 7; ++c) {
-                ws.fetch(tid);
                 Pending pa, pb;
                 if (c < 6) {
                     issue_column_half(cells, L, q, 2 * c, g, pa);
@@ -582,6 +621,8 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
                     issue_table_half(cells, L, q, 0, g, plane, pa);
                     issue_table_half(cells, L, q, 1, g, plane, pb);
                 }
+                // after the samples, so waiting for them does not wait for the weights
+                ws.fetch(tid);
                 f4 lo, hi;
     #pragma unroll
                 for (int j = 0; j < 4; ++j) {
@@ -592,12 +633,12 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
                 ws.advance(tid);
             }
             {
-                ws.fetch(tid);
                 Pending pa;
                 issue_one(cells, L, q.u0[0] + 4.f * (q.a[0] + q.b[0]) + 8.f * q.c[0],
                           q.u0[1] + 4.f * (q.a[1] + q.b[1]) + 8.f * q.c[1],
                           q.u0[2] + 4.f * (q.a[2] + q.b[2]) + 8.f * q.c[2], pa.v[0], pa.fx[0],
                           pa.fy[0], pa.fz[0]);
+                ws.fetch(tid);
                 const float sv = finish_one(pa.v[0], pa.fx[0], pa.fy[0], pa.fz[0]);
                 const f4 lo = f4{g == 0 ? sv : 0.f, g == 0 ? gamma : 0.f, 0.f, 0.f};
                 mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, (MT & 1) ? O[MT - 1] : z4), F);
@@ -706,7 +747,7 @@ __global__ void __launch_bounds__(256) k_gather_packed(FusedArgs a, float *__res
         const FusedLevel L = cl.lvt[k];
         gcell_ptr cells = (gcell_ptr)L.cells;
         PtLevel q;
-        point_level(L, x, fr, cl.amin, valid, q);
+        level_from_geom(L, make_geom(x, fr, cl.amin, valid), q);
         Pending pa;
         for (int h = 0; h < 12; ++h) {
             issue_column_half(cells, L, q, h, g, pa);

@@ -69,7 +69,7 @@ struct ds_cloud {
     int mips[ds::kMaxK];
     float *pyr = nullptr;      // float32 levels, concatenated
     int64_t pyr_elems = 0;
-    uint4 *cells = nullptr;    // corner-packed bf16 levels (8 corners per cell)
+    uint4 *cells = nullptr;    // corner-packed FP16 levels (8 corners per cell)
     int64_t n_cells = 0;
     void *tables = nullptr;    // device: GatherLevel[K] then FusedLevel[K]
     float *mu = nullptr;       // extinction sigma_max * d on the base grid (tracer medium)
