@@ -232,47 +232,75 @@ __device__ __forceinline__ bf16x8 pack8(const f4 &lo, const f4 &hi)
     return r;
 }
 
-// Double-buffered staging of weight chunks (MT fragments of 64 x 16 bytes).  The
-// next chunk is copied from global memory straight into the idle LDS buffer
-// (global_load_lds, 16 bytes per lane, lane l of a wave writing base + 16 l), so
-// the copy holds no registers; advance() waits for the copy and publishes it.
+// Double-buffered staging of weight chunks (MT fragments of 64 x 16 bytes), G chunks
+// per buffer.  The next group of chunks is copied from global memory straight into
+// the idle LDS buffer (global_load_lds, 16 bytes per lane, lane l of a wave writing
+// base + 16 l), so the copy holds no registers; one barrier per group publishes it.
 // FR is a multiple of 64, so each wave copies whole 1 KB rows or none.
+//   begin()  at the start of a tile: group 0 resident, group 1 pending
+//   fetch()  issue the pending group's copy (call after the chunk's sample loads, so
+//            waiting for a sample never waits for weights)
+//   next()   after consuming a chunk; at the end of a group: wait, barrier, switch
 typedef __attribute__((address_space(1))) void gvoid;
 typedef __attribute__((address_space(3))) void lvoid;
 
 template <int MT, int NW>
 struct WeightStage {
+    static constexpr int G = 2;
     static constexpr int FR = MT * 64;
     static constexpr int T = 64 * NW;
-    static constexpr int R = (FR + T - 1) / T;
-    static constexpr int SLOT = FR;  // LDS entries per buffer
-    uint4 *buf;          // LDS, 2 * SLOT entries
-    const uint4 *src;    // next chunk to fetch
-    int cur;
+    static constexpr int SLOT = FR;            // LDS entries per chunk
+    static constexpr int BUF = G * SLOT;       // entries per buffer
+    static constexpr int ROWS = G * MT;        // 1 KB rows per group
+    uint4 *buf;          // LDS, 2 * BUF entries
+    const uint4 *src;    // first chunk of the next group to copy
+    int cur, j;
+    bool pending;
 
-    __device__ __forceinline__ const uint4 *chunk() const { return buf + cur * SLOT; }
-    // start copying the next chunk into the buffer not being read: wave w copies the
-    // 64-entry rows w, w + NW, ... (scalar bases, one lane offset for every row)
-    __device__ __forceinline__ void fetch(int tid)
+    __device__ __forceinline__ const uint4 *chunk() const { return buf + cur * BUF + j * SLOT; }
+    __device__ __forceinline__ void copy_group(int tid, uint4 *dst)
     {
         const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
         const int lane = tid & 63;
-        uint4 *dst = buf + (cur ^ 1) * SLOT;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
+        for (int r = 0; r < (ROWS + NW - 1) / NW; ++r) {
             const int row = w + r * NW;
-            if (r + 1 < R || row < MT)
+            if ((r + 1) * NW <= ROWS || row < ROWS)
                 __builtin_amdgcn_global_load_lds((gvoid *)(src + row * 64 + lane),
                                                  (lvoid *)(dst + row * 64), 16, 0, 0);
         }
+        src += BUF;
     }
-    // wait for the copy, publish it and switch buffers (all threads must call)
-    __device__ __forceinline__ void advance(int)
+    __device__ __forceinline__ void begin(const uint4 *frags, int tid)
     {
+        // drain a copy still in flight from the previous tile before reusing the buffers
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        src += FR;
         __syncthreads();
-        cur ^= 1;
+        src = frags;
+        copy_group(tid, buf);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        cur = 0;
+        j = 0;
+        pending = true;
+    }
+    __device__ __forceinline__ void fetch(int tid)
+    {
+        if (pending) {
+            copy_group(tid, buf + (cur ^ 1) * BUF);
+            pending = false;
+        }
+    }
+    __device__ __forceinline__ void next(int tid)
+    {
+        if (++j == G) {
+            fetch(tid);  // a group without sample loads has not issued its copy yet
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            cur ^= 1;
+            j = 0;
+            pending = true;
+        }
     }
 };
 
@@ -303,7 +331,7 @@ __device__ __forceinline__ void dense(WeightStage<MT, NW> &ws, const float *__re
         const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
         bf16x8 B = pack8(in[2 * q], (2 * q + 1 < MT) ? in[2 * q + 1 < MT ? 2 * q + 1 : 0] : z4);
         mfma_chunk<MT>(ws.chunk(), lane, B, out);
-        ws.advance(tid);
+        ws.next(tid);
     }
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -318,7 +346,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
 {
     constexpr int C2 = (MT + 1) / 2;   // chunks of a W-wide input
     constexpr int WP = 16 * MT;        // padded width
-    __shared__ uint4 wbuf[2 * WeightStage<MT, NW>::SLOT];
+    __shared__ uint4 wbuf[2 * WeightStage<MT, NW>::BUF];
     __shared__ float4 plane[32];       // lattice coordinates of halves 12, 13 per (lane group, j)
     // residual stream o^k of each wave in FP32, accumulator layout [tile][lane]; it
     // lives in LDS while the first layer runs and comes back for the second
@@ -348,10 +376,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
         // they would hold registers across the whole tile and force spills
         asm volatile("" ::: "memory");
         const FusedCloud &cl = a.cl[tile_cloud(a, t)];
-        ws.src = frags;
-        ws.cur = 1;
-        ws.fetch(tid);
-        ws.advance(tid);  // chunk 0 -> buffer 0 (also orders the plane table)
+        ws.begin(frags, tid);  // also orders the plane table
 
         const int64_t pl = (t - cl.tile_begin) * (16 * NW) + (tid >> 6) * 16 + n;
         const bool in = pl < cl.P;
@@ -408,7 +433,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
                     hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
                 issue_column_half(cells, L, q, 2 * c + 3, g, pb);
                 mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
-                ws.advance(tid);
+                ws.next(tid);
             }
             {  // chunk 5: issues the table halves of chunk 6
                 ws.fetch(tid);
@@ -422,7 +447,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
                     hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
                 issue_table_half(cells, L, q, 1, g, plane, pb);
                 mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
-                ws.advance(tid);
+                ws.next(tid);
             }
             {  // chunk 6: issues chunk 7's stencil sample (4, 4, 8)
                 ws.fetch(tid);
@@ -438,7 +463,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
                 for (int j = 0; j < 4; ++j)
                     hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
                 mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
-                ws.advance(tid);
+                ws.next(tid);
             }
             // chunk 7: stencil sample (4, 4, 8), gamma, and the odd tile of o^{k-1}
             {
@@ -447,7 +472,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
                 f4 lo = f4{g == 0 ? s : 0.f, g == 0 ? gamma : 0.f, 0.f, 0.f};
                 bf16x8 B = pack8(lo, (MT & 1) ? Os[MT - 1][lane] : z4);
                 mfma_chunk<MT>(ws.chunk(), lane, B, F);
-                ws.advance(tid);
+                ws.next(tid);
             }
             // o^{k-1} in pairs of tiles (o^0 = 0: block 1 has no such chunks)
             if (k > 0) {
@@ -455,7 +480,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
                 for (int qq = 0; qq < MT / 2; ++qq) {
                     ws.fetch(tid);
                     mfma_chunk<MT>(ws.chunk(), lane, pack8(Os[2 * qq][lane], Os[2 * qq + 1][lane]), F);
-                    ws.advance(tid);
+                    ws.next(tid);
                 }
             }
             // the next level's first samples fly while the second layer runs
@@ -485,7 +510,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
                 mfma_chunk<MT>(ws.chunk(), lane,
                                pack8(F[2 * qq], (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0] : z4),
                                O);
-                ws.advance(tid);
+                ws.next(tid);
             }
     #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
@@ -550,7 +575,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
 {
     constexpr int C2 = (MT + 1) / 2;
     constexpr int WP = 16 * MT;
-    __shared__ uint4 wbuf[2 * WeightStage<MT, NW>::SLOT];
+    __shared__ uint4 wbuf[2 * WeightStage<MT, NW>::BUF];
     __shared__ float4 plane[32];
     __shared__ PtGeom geom[16 * NW];   // per point of the tile, see make_geom
     const int tid = threadIdx.x;
@@ -575,10 +600,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
         // they would hold registers across the whole tile and force spills
         asm volatile("" ::: "memory");
         const FusedCloud &cl = a.cl[tile_cloud(a, t)];
-        ws.src = frags;
-        ws.cur = 1;
-        ws.fetch(tid);
-        ws.advance(tid);
+        ws.begin(frags, tid);
 
         const int64_t pl = (t - cl.tile_begin) * (16 * NW) + (tid >> 6) * 16 + n;
         const bool in = pl < cl.P;
@@ -630,7 +652,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
                     hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
                 }
                 mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
-                ws.advance(tid);
+                ws.next(tid);
             }
             {
                 Pending pa;
@@ -642,14 +664,14 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
                 const float sv = finish_one(pa.v[0], pa.fx[0], pa.fy[0], pa.fz[0]);
                 const f4 lo = f4{g == 0 ? sv : 0.f, g == 0 ? gamma : 0.f, 0.f, 0.f};
                 mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, (MT & 1) ? O[MT - 1] : z4), F);
-                ws.advance(tid);
+                ws.next(tid);
             }
             if (k > 0) {
     #pragma unroll
                 for (int qq = 0; qq < MT / 2; ++qq) {
                     ws.fetch(tid);
                     mfma_chunk<MT>(ws.chunk(), lane, pack8(O[2 * qq], O[2 * qq + 1]), F);
-                    ws.advance(tid);
+                    ws.next(tid);
                 }
             }
     #pragma unroll
@@ -666,7 +688,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
                 mfma_chunk<MT>(ws.chunk(), lane,
                                pack8(F[2 * qq], (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0] : z4),
                                O);
-                ws.advance(tid);
+                ws.next(tid);
             }
     #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
@@ -799,7 +821,9 @@ int chunk_count(int MT, int K, int H)
     return (8 + C2) + (K - 1) * (C1 + C2) + (H - 1) * C2;
 }
 
-constexpr size_t kFragPad = 2048;  // >= R x threads of every instantiation (entries)
+// zeroed entries after the last chunk: the copies run up to two groups (2 x 2 chunks of
+// at most 16 x 64 entries) past the chunk being consumed
+constexpr size_t kFragPad = 4096;
 
 // Tile partition of the clouds for tiles of `per` points; returns the tile count.
 int64_t assign_tiles(FusedArgs &a, int64_t per)
@@ -813,15 +837,15 @@ int64_t assign_tiles(FusedArgs &a, int64_t per)
     return t;
 }
 
-template <int MT, int NW>
-ds_status launch_kind(hipStream_t s, const ds_net *net, FusedArgs a, int kind, int grid)
+template <int MT, int NW, bool PIPE>
+ds_status launch_kind(hipStream_t s, const ds_net *net, FusedArgs a, int grid)
 {
     const int64_t tiles = assign_tiles(a, 16 * NW);
     if (tiles <= 0)
         return DS_OK;
     const int64_t g = grid > 0 && grid < tiles ? grid : tiles;
     DS_CHECK(g < ((int64_t)1 << 31), DS_ERR_INVALID_ARG, "too many tiles for one launch");
-    if (kind == DS_KERNEL_PIPELINED)
+    if constexpr (PIPE)
         k_fused<MT, NW><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_bf16, net->vec);
     else
         k_fused_reg<MT, NW><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_bf16, net->vec);
@@ -829,16 +853,31 @@ ds_status launch_kind(hipStream_t s, const ds_net *net, FusedArgs a, int kind, i
     return DS_OK;
 }
 
+// Eight waves need LDS for twice the points: the register kernel fits below 16
+// tiles, the pipelined one (residual stream in LDS) below 13.
+constexpr bool fits(int MT, int waves, int kind)
+{
+    return waves == 4 || (kind == DS_KERNEL_REGISTER ? MT < 16 : MT < 13);
+}
+
 template <int MT>
 ds_status launch(hipStream_t s, const ds_net *net, const FusedArgs &a, const FusedVariant &v)
 {
+    const bool pipe = v.kind == DS_KERNEL_PIPELINED;
     if (v.waves == 8) {
-        if constexpr (MT < 16)
-            return launch_kind<MT, 8>(s, net, a, v.kind, v.grid);
+        if constexpr (fits(MT, 8, DS_KERNEL_PIPELINED)) {
+            if (pipe)
+                return launch_kind<MT, 8, true>(s, net, a, v.grid);
+        }
+        if constexpr (fits(MT, 8, DS_KERNEL_REGISTER)) {
+            if (!pipe)
+                return launch_kind<MT, 8, false>(s, net, a, v.grid);
+        }
         set_error("eight waves per workgroup do not fit the LDS at width %d", net->W);
         return DS_ERR_UNSUPPORTED;
     }
-    return launch_kind<MT, 4>(s, net, a, v.kind, v.grid);
+    return pipe ? launch_kind<MT, 4, true>(s, net, a, v.grid)
+                : launch_kind<MT, 4, false>(s, net, a, v.grid);
 }
 
 }  // namespace
@@ -1057,7 +1096,7 @@ bool fused_variant_ok(const ds_net *net, const FusedVariant &v)
         return false;
     if (v.waves != 4 && v.waves != 8)
         return false;
-    if (v.waves == 8 && fused_tiles(net->W) >= 16)
+    if (!fits(fused_tiles(net->W), v.waves, v.kind))
         return false;
     return v.grid >= 0;
 }
