@@ -1,0 +1,77 @@
+"""Parity at the full benchmark size: the seeded 512^3 fBm+Worley cloud (sigma_max
+512/unit, 10 levels, K = 10), the 10 x 200 network and 2^20 primary hits of a 1024^2
+view, run in the launch the benchmark times (autotuned batch plan replayed from a
+HIP graph) and in the plain FP32 form; checked against the FP64 oracle on an evenly
+strided sample of points, with the final pre-activations compared as well."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1709_05418_amd as ds
+from paper_1709_05418_amd import synth
+from _util import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+N, SIGMA, L, K, W, H, P = 512, 512.0, 10, 10, 200, 3, 1 << 20
+
+
+@pytest.fixture(scope="module")
+def full():
+    dev = torch.device("cuda:0")
+    d = synth.cloud_density(N, 10, worley=0.3, device=dev)
+    aabb_min, h0 = synth.unit_box(N)
+    pos, view = synth.camera_hits(d, SIGMA, 1024, P, 11, aabb_min, h0, device=dev)
+    light = np.broadcast_to(synth.table1_lights()["side"], (P, 3)).astype(np.float32).copy()
+    theta = synth.init_params(K, W, H, 12)
+    dh = d.cpu().numpy()
+    grid = O.Grid(dh, SIGMA, aabb_min, h0)
+    mean, _ = O.normalize(grid)
+    pyr = O.pyramid(grid, mean, L)
+    mips = O.default_mips(mean, h0, K, L)
+    return dict(d=d, aabb_min=aabb_min, h0=h0, pos=pos, view=view, light=light, theta=theta,
+                grid=grid, mean=mean, pyr=pyr, mips=mips)
+
+
+def test_full_size_bench_launch_matches_oracle(full):
+    f = full
+    ctx = ds.Context(0)
+    cloud = ds.Cloud(ctx, f["d"], SIGMA, f["aabb_min"], f["h0"], L, K)
+    net = ds.Net(ctx, K, W, H)
+    try:
+        assert cloud.info["mip_of_level"] == list(f["mips"])
+        net.set_params(f["theta"])
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        pos, view, light = t(f["pos"]), t(f["view"]), t(f["light"])
+        out = torch.empty(P, device="cuda")
+        pre = torch.empty(P, device="cuda")
+        fl = torch.empty(P, dtype=torch.uint8, device="cuda")
+        b = ds.ds_batch_create(ctx.h, net.h, [cloud.h], [0, P])
+        try:
+            ds.ds_batch_autotune(b, ds.DS_PREC_BF16, pos, view, light, out, 1)
+            ds.ds_batch_capture(b, ds.DS_PREC_BF16, pos, view, light, out, pre, fl)
+            out.fill_(-1.0)
+            ds.ds_batch_replay(b)
+            torch.cuda.synchronize()
+        finally:
+            ds.ds_batch_destroy(b)
+        g32, pre32, _ = ds.ds_predict(ctx.h, cloud.h, net.h, ds.DS_PREC_F32, pos, view, light)
+        idx = np.linspace(0, P - 1, 3000).astype(np.int64)
+        pyr, dims, offs = f["pyr"]
+        z, flr = O.gather(f["grid"], pyr, dims, offs, f["mean"], K, f["mips"], f["pos"][idx],
+                          f["view"][idx], f["light"][idx])
+        gr, prer = O.forward(f["theta"].astype(np.float64), K, W, H, z)
+        g16, p16 = out.cpu().numpy()[idx], pre.cpu().numpy()[idx]
+        e16 = (rel_l2(g16, gr), rel_l2(p16, prer))
+        e32 = (rel_l2(g32.cpu().numpy()[idx], gr), rel_l2(pre32.cpu().numpy()[idx], prer))
+        print(f"full size: bf16 g {e16[0]:.2e} pre {e16[1]:.2e}; fp32 g {e32[0]:.2e} "
+              f"pre {e32[1]:.2e}; alive {(gr > 0).mean():.2f}", flush=True)
+        assert max(e16) <= 2e-2 and max(e32) <= 1e-5
+        # flags decided by FP32 vs FP64 box tests may differ right at a box face
+        assert int((fl.cpu().numpy()[idx] != flr).sum()) <= 2
+        assert bool(torch.isfinite(out).all()) and float(out.min()) >= 0.0
+    finally:
+        net.close()
+        cloud.close()
+        ctx.close()
