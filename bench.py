@@ -282,8 +282,8 @@ def main():
     achieved = flop / (avg_kernel_ms / 1e3) / 1e12
     mt = (W + 15) // 16
     mt = next(v for v in (1, 2, 4, 8, 13, 16) if v >= mt)
-    kname = ("k_fused_reg" if tuned["kernel"] == ds.DS_KERNEL_REGISTER else "k_fused") + \
-        f"<{mt},{tuned['waves']}>"
+    kname = {ds.DS_KERNEL_REGISTER: "k_fused_reg", ds.DS_KERNEL_PIPELINED: "k_fused",
+             ds.DS_KERNEL_WIDE: "k_fused_wide"}[tuned["kernel"]] + f"<{mt},{tuned['waves']}>"
     traffic = measured_traffic() if (args.workload == "paper" and kname == FUSED_KERNEL and
                                      tuned["grid"] == 0) else None
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,

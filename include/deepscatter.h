@@ -189,6 +189,7 @@ ds_status ds_predict(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
  * call.  Kernel variants: */
 #define DS_KERNEL_REGISTER 0  /* residual stream in registers, one chunk of samples in flight */
 #define DS_KERNEL_PIPELINED 1 /* residual stream in LDS, the next chunk's samples in flight  */
+#define DS_KERNEL_WIDE 2      /* one wave per SIMD with two 16-point tiles (4 waves only)     */
 typedef struct ds_batch ds_batch;
 
 /* n_clouds (1..16) clouds; the points of cloud c are rows offsets[c] ..
@@ -199,7 +200,9 @@ typedef struct ds_batch ds_batch;
 ds_status ds_batch_create(ds_ctx *ctx, const ds_net *net, int n_clouds,
                           const ds_cloud *const *clouds, const int64_t *offsets, ds_batch **out);
 ds_status ds_batch_destroy(ds_batch *batch);
-/* Kernel variant of the plan: kernel DS_KERNEL_*, waves 4 or 8 (8 needs W <= 240),
+/* Kernel variant of the plan: kernel DS_KERNEL_*, waves 4 or 8 (8 needs W <= 240 for
+ * DS_KERNEL_REGISTER, W <= 192 for DS_KERNEL_PIPELINED and is not available for
+ * DS_KERNEL_WIDE),
  * grid 0 (one workgroup per tile) or the number of persistent workgroups.
  * Setting a variant drops a captured graph. */
 ds_status ds_batch_set_config(ds_batch *batch, int32_t kernel, int32_t waves, int32_t grid);

@@ -734,6 +734,262 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
     }
 }
 
+// Wide variant: one wave per SIMD holding two 16-point tiles, so every weight
+// fragment read from LDS feeds two MFMAs and a workgroup covers 128 points (half the
+// LDS fragment reads, weight copies and barriers per point).  With one wave per
+// SIMD the accumulators of both tiles live in the accumulation registers; the two
+// tiles' samples of a chunk are in flight together.
+template <int MT, int NT>
+__device__ __forceinline__ void mfma_chunk_nt(const uint4 *w, int lane, const bf16x8 (&B)[NT],
+                                              f4 (&acc)[MT][NT])
+{
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const uint4 wa = w[mt * 64 + lane];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+            acc[mt][nt] = mfma_bf16(wa, B[nt], acc[mt][nt]);
+    }
+}
+
+template <int MT, int NW, int NT>
+__device__ __forceinline__ void dense_nt(WeightStage<MT, NW> &ws, const float *__restrict__ bias,
+                                         int tid, int lane, const f4 (&in)[MT][NT],
+                                         f4 (&out)[MT][NT])
+{
+    constexpr int C2 = (MT + 1) / 2;
+    const int g = lane >> 4;
+    const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const f4 b = *reinterpret_cast<const f4 *>(bias + 16 * mt + 4 * g);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+            out[mt][nt] = b;
+    }
+#pragma unroll
+    for (int q = 0; q < C2; ++q) {
+        ws.fetch(tid);
+        bf16x8 B[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+            B[nt] = pack8(in[2 * q][nt], (2 * q + 1 < MT) ? in[2 * q + 1 < MT ? 2 * q + 1 : 0][nt] : z4);
+        mfma_chunk_nt<MT, NT>(ws.chunk(), lane, B, out);
+        ws.next(tid);
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                out[mt][nt][i] = fmaxf(out[mt][nt][i], 0.f);
+}
+
+template <int MT, int NW>
+__global__ void __launch_bounds__(64 * NW, 1) k_fused_wide(FusedArgs a,
+                                                           const uint4 *__restrict__ frags,
+                                                           const float *__restrict__ vec)
+{
+    constexpr int NT = 2;
+    constexpr int C2 = (MT + 1) / 2;
+    constexpr int WP = 16 * MT;
+    constexpr int TP = 16 * NW * NT;   // points per tile
+    __shared__ uint4 wbuf[2 * WeightStage<MT, NW>::BUF];
+    __shared__ float4 plane[32];
+    __shared__ PtGeom geom[TP];        // per point of the tile, see make_geom
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int g = lane >> 4, n = lane & 15;
+    const int wv = tid >> 6;
+    if (tid < 32) {
+        const int gg = tid >> 3, j = tid & 7;
+        if (gg == 0) {
+            plane[tid] = make_float4(4.f, 4.f, (float)j, 0.f);
+        } else {
+            const int G = 2 * (gg - 1) + (j >> 2), jj = j & 3;
+            plane[tid] = G < 5 ? make_float4((float)jj, (float)G, 8.f, 0.f)
+                               : make_float4(4.f, (float)jj, 8.f, 0.f);
+        }
+    }
+    WeightStage<MT, NW> ws;
+    ws.buf = wbuf;
+#pragma unroll 1
+    for (int64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
+        asm volatile("" ::: "memory");
+        const FusedCloud &cl = a.cl[tile_cloud(a, t)];
+        ws.begin(frags, tid);
+        bool in[NT], valid[NT];
+        float gamma[NT];
+        int64_t p[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int64_t pl = (t - cl.tile_begin) * TP + (wv * NT + nt) * 16 + n;
+            in[nt] = pl < cl.P;
+            p[nt] = cl.p_begin + pl;
+            float x[3];
+            Frame fr;
+            valid[nt] = point_frame(a, p[nt], in[nt], x, fr);
+            gamma[nt] = fr.gamma;
+            geom[(wv * NT + nt) * 16 + n] = make_geom(x, fr, cl.amin, valid[nt]);
+        }
+        const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
+        f4 O[MT][NT], F[MT][NT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                O[mt][nt] = z4;
+
+        for (int k = 0; k < a.K; ++k) {
+            const FusedLevel L = cl.lvt[k];
+            gcell_ptr cells = (gcell_ptr)L.cells;
+            PtLevel q[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+                level_from_geom(L, geom[(wv * NT + nt) * 16 + n], q[nt]);
+            const float *b1 = vec + (size_t)k * 2 * WP;
+            const float *b2 = b1 + WP;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    F[mt][nt] = z4;
+#pragma unroll 1
+            for (int c = 0; c < 7; ++c) {
+                Pending pa[NT], pb[NT];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    if (c < 6) {
+                        issue_column_half(cells, L, q[nt], 2 * c, g, pa[nt]);
+                        issue_column_half(cells, L, q[nt], 2 * c + 1, g, pb[nt]);
+                    } else {
+                        issue_table_half(cells, L, q[nt], 0, g, plane, pa[nt]);
+                        issue_table_half(cells, L, q[nt], 1, g, plane, pb[nt]);
+                    }
+                }
+                ws.fetch(tid);
+                bf16x8 B[NT];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    f4 lo, hi;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        lo[j] = finish_one(pa[nt].v[j], pa[nt].fx[j], pa[nt].fy[j], pa[nt].fz[j]);
+                        hi[j] = finish_one(pb[nt].v[j], pb[nt].fx[j], pb[nt].fy[j], pb[nt].fz[j]);
+                    }
+                    B[nt] = pack8(lo, hi);
+                }
+                mfma_chunk_nt<MT, NT>(ws.chunk(), lane, B, F);
+                ws.next(tid);
+            }
+            {
+                Pending pa[NT];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    issue_one(cells, L, q[nt].u0[0] + 4.f * (q[nt].a[0] + q[nt].b[0]) + 8.f * q[nt].c[0],
+                              q[nt].u0[1] + 4.f * (q[nt].a[1] + q[nt].b[1]) + 8.f * q[nt].c[1],
+                              q[nt].u0[2] + 4.f * (q[nt].a[2] + q[nt].b[2]) + 8.f * q[nt].c[2],
+                              pa[nt].v[0], pa[nt].fx[0], pa[nt].fy[0], pa[nt].fz[0]);
+                ws.fetch(tid);
+                bf16x8 B[NT];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    const float sv = finish_one(pa[nt].v[0], pa[nt].fx[0], pa[nt].fy[0], pa[nt].fz[0]);
+                    const f4 lo = f4{g == 0 ? sv : 0.f, g == 0 ? gamma[nt] : 0.f, 0.f, 0.f};
+                    B[nt] = pack8(lo, (MT & 1) ? O[MT - 1][nt] : z4);
+                }
+                mfma_chunk_nt<MT, NT>(ws.chunk(), lane, B, F);
+                ws.next(tid);
+            }
+            if (k > 0) {
+#pragma unroll
+                for (int qq = 0; qq < MT / 2; ++qq) {
+                    ws.fetch(tid);
+                    bf16x8 B[NT];
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+                        B[nt] = pack8(O[2 * qq][nt], O[2 * qq + 1][nt]);
+                    mfma_chunk_nt<MT, NT>(ws.chunk(), lane, B, F);
+                    ws.next(tid);
+                }
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const f4 bb = *reinterpret_cast<const f4 *>(b1 + 16 * mt + 4 * g);
+                const f4 cc = *reinterpret_cast<const f4 *>(b2 + 16 * mt + 4 * g);
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        F[mt][nt][i] = fmaxf(F[mt][nt][i] + bb[i], 0.f);
+                    O[mt][nt] += cc;
+                }
+            }
+#pragma unroll
+            for (int qq = 0; qq < C2; ++qq) {
+                ws.fetch(tid);
+                bf16x8 B[NT];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    B[nt] = pack8(F[2 * qq][nt],
+                                  (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0][nt] : z4);
+                mfma_chunk_nt<MT, NT>(ws.chunk(), lane, B, O);
+                ws.next(tid);
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        O[mt][nt][i] = fmaxf(O[mt][nt][i], 0.f);
+        }
+        const float *bh = vec + (size_t)a.K * 2 * WP;
+        int h = 0;
+        for (; h + 1 < a.H - 1; h += 2) {
+            dense_nt<MT, NW, NT>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+            dense_nt<MT, NW, NT>(ws, bh + (size_t)(h + 1) * WP, tid, lane, F, O);
+        }
+        if (h < a.H - 1) {
+            dense_nt<MT, NW, NT>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    O[mt][nt] = F[mt][nt];
+        }
+        const float *wl = bh + (size_t)(a.H - 1) * WP;
+        const float bl = wl[WP];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            float acc = 0.f;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const f4 w = *reinterpret_cast<const f4 *>(wl + 16 * mt + 4 * g);
+                acc += w[0] * O[mt][nt][0] + w[1] * O[mt][nt][1] + w[2] * O[mt][nt][2] +
+                       w[3] * O[mt][nt][3];
+            }
+            acc += __shfl_xor(acc, 16, 64);
+            acc += __shfl_xor(acc, 32, 64);
+            if (g == 0 && in[nt]) {
+                const float pre = acc + bl;
+                a.out[p[nt]] = valid[nt] ? fmaxf(pre, 0.f) : 0.f;
+                if (a.pre)
+                    a.pre[p[nt]] = valid[nt] ? pre : 0.f;
+                if (a.flags) {
+                    float x[3];
+                    Frame fr;
+                    point_frame(a, p[nt], in[nt], x, fr);
+                    a.flags[p[nt]] = valid[nt] ? point_flags(x, fr, cl.amin, cl.amax, cl.inv_mean)
+                                               : (uint8_t)DS_FLAG_INVALID;
+                }
+            }
+        }
+    }
+}
+
 // The fused kernel's gather schedule on its own: every sample is written to its
 // canonical descriptor position [k][ix + 5 iy + 25 iz] (and gamma last), so the
 // BF16 gather path can be checked against the plain descriptor.
@@ -837,16 +1093,18 @@ int64_t assign_tiles(FusedArgs &a, int64_t per)
     return t;
 }
 
-template <int MT, int NW, bool PIPE>
+template <int MT, int NW, int KIND>
 ds_status launch_kind(hipStream_t s, const ds_net *net, FusedArgs a, int grid)
 {
-    const int64_t tiles = assign_tiles(a, 16 * NW);
+    const int64_t tiles = assign_tiles(a, 16 * NW * (KIND == DS_KERNEL_WIDE ? 2 : 1));
     if (tiles <= 0)
         return DS_OK;
     const int64_t g = grid > 0 && grid < tiles ? grid : tiles;
     DS_CHECK(g < ((int64_t)1 << 31), DS_ERR_INVALID_ARG, "too many tiles for one launch");
-    if constexpr (PIPE)
+    if constexpr (KIND == DS_KERNEL_PIPELINED)
         k_fused<MT, NW><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_bf16, net->vec);
+    else if constexpr (KIND == DS_KERNEL_WIDE)
+        k_fused_wide<MT, NW><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_bf16, net->vec);
     else
         k_fused_reg<MT, NW><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_bf16, net->vec);
     DS_HIP(hipGetLastError());
@@ -854,30 +1112,35 @@ ds_status launch_kind(hipStream_t s, const ds_net *net, FusedArgs a, int grid)
 }
 
 // Eight waves need LDS for twice the points: the register kernel fits below 16
-// tiles, the pipelined one (residual stream in LDS) below 13.
+// tiles, the pipelined one (residual stream in LDS) below 13; the wide kernel runs
+// one wave per SIMD, so four waves only.
 constexpr bool fits(int MT, int waves, int kind)
 {
+    if (kind == DS_KERNEL_WIDE)
+        return waves == 4;
     return waves == 4 || (kind == DS_KERNEL_REGISTER ? MT < 16 : MT < 13);
 }
 
 template <int MT>
 ds_status launch(hipStream_t s, const ds_net *net, const FusedArgs &a, const FusedVariant &v)
 {
-    const bool pipe = v.kind == DS_KERNEL_PIPELINED;
     if (v.waves == 8) {
         if constexpr (fits(MT, 8, DS_KERNEL_PIPELINED)) {
-            if (pipe)
-                return launch_kind<MT, 8, true>(s, net, a, v.grid);
+            if (v.kind == DS_KERNEL_PIPELINED)
+                return launch_kind<MT, 8, DS_KERNEL_PIPELINED>(s, net, a, v.grid);
         }
         if constexpr (fits(MT, 8, DS_KERNEL_REGISTER)) {
-            if (!pipe)
-                return launch_kind<MT, 8, false>(s, net, a, v.grid);
+            if (v.kind == DS_KERNEL_REGISTER)
+                return launch_kind<MT, 8, DS_KERNEL_REGISTER>(s, net, a, v.grid);
         }
-        set_error("eight waves per workgroup do not fit the LDS at width %d", net->W);
+        set_error("eight waves per workgroup do not fit this kernel at width %d", net->W);
         return DS_ERR_UNSUPPORTED;
     }
-    return pipe ? launch_kind<MT, 4, true>(s, net, a, v.grid)
-                : launch_kind<MT, 4, false>(s, net, a, v.grid);
+    if (v.kind == DS_KERNEL_PIPELINED)
+        return launch_kind<MT, 4, DS_KERNEL_PIPELINED>(s, net, a, v.grid);
+    if (v.kind == DS_KERNEL_WIDE)
+        return launch_kind<MT, 4, DS_KERNEL_WIDE>(s, net, a, v.grid);
+    return launch_kind<MT, 4, DS_KERNEL_REGISTER>(s, net, a, v.grid);
 }
 
 }  // namespace
@@ -1092,7 +1355,7 @@ ds_status fused_gather_packed(hipStream_t s, const FusedArgs &a, float *z)
 
 bool fused_variant_ok(const ds_net *net, const FusedVariant &v)
 {
-    if (v.kind != DS_KERNEL_REGISTER && v.kind != DS_KERNEL_PIPELINED)
+    if (v.kind != DS_KERNEL_REGISTER && v.kind != DS_KERNEL_PIPELINED && v.kind != DS_KERNEL_WIDE)
         return false;
     if (v.waves != 4 && v.waves != 8)
         return false;

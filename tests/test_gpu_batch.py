@@ -106,8 +106,8 @@ def test_every_variant_and_grid_agrees(ctx, setup):
     try:
         base = torch.empty(N, dtype=torch.float32, device="cuda")
         ds.ds_batch_predict(b, ds.DS_PREC_BF16, s["pos"], s["view"], s["light"], base)
-        for kind in (ds.DS_KERNEL_REGISTER, ds.DS_KERNEL_PIPELINED):
-            for waves in (4, 8):
+        for kind in (ds.DS_KERNEL_REGISTER, ds.DS_KERNEL_PIPELINED, ds.DS_KERNEL_WIDE):
+            for waves in ((4,) if kind == ds.DS_KERNEL_WIDE else (4, 8)):
                 for grid in (0, 1, 3, 64):
                     print("variant", kind, waves, grid, flush=True)
                     ds.ds_batch_set_config(b, kind, waves, grid)
@@ -115,7 +115,9 @@ def test_every_variant_and_grid_agrees(ctx, setup):
                     ds.ds_batch_predict(b, ds.DS_PREC_BF16, s["pos"], s["view"], s["light"], out)
                     assert torch.equal(out, base), (kind, waves, grid)
         with pytest.raises(ds.DSError):
-            ds.ds_batch_set_config(b, 2, 4, 0)
+            ds.ds_batch_set_config(b, 3, 4, 0)
+        with pytest.raises(ds.DSError):
+            ds.ds_batch_set_config(b, ds.DS_KERNEL_WIDE, 8, 0)
         with pytest.raises(ds.DSError):
             ds.ds_batch_set_config(b, 0, 6, 0)
     finally:
@@ -130,7 +132,7 @@ def test_autotune_then_graph_replay(ctx, setup):
         eager = torch.empty(N, dtype=torch.float32, device="cuda")
         ds.ds_batch_predict(b, ds.DS_PREC_BF16, s["pos"], s["view"], s["light"], eager)
         cfg = ds.ds_batch_autotune(b, ds.DS_PREC_BF16, s["pos"], s["view"], s["light"], eager, 2)
-        assert cfg["ms"] > 0 and cfg["waves"] in (4, 8) and cfg["kernel"] in (0, 1)
+        assert cfg["ms"] > 0 and cfg["waves"] in (4, 8) and cfg["kernel"] in (0, 1, 2)
         out = torch.full((N,), -1.0, device="cuda")
         pos = s["pos"].clone()
         ds.ds_batch_capture(b, ds.DS_PREC_BF16, pos, s["view"], s["light"], out)
