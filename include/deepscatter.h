@@ -240,6 +240,13 @@ ds_status ds_adam_destroy(ds_adam *opt);
 /* Number of updates applied so far (host read, no synchronisation). */
 ds_status ds_adam_steps(const ds_adam *opt, int64_t *t);
 
+/* Arithmetic of ds_loss_grad and ds_train_step: DS_PREC_F32 (default; every GEMM in
+ * FP32) or DS_PREC_BF16 (every GEMM operand - descriptors, activations, weights and
+ * back-propagated gradients - rounded to BF16 with FP32 accumulation on the matrix
+ * cores; bias, residual, ReLU, loss and batch reductions in FP32; the master
+ * parameters and Adam stay FP32).  DS_PREC_FP8 gives DS_ERR_UNSUPPORTED. */
+ds_status ds_net_set_train_precision(ds_net *net, ds_precision precision);
+
 /* Minibatch loss (1/B) sum_b (log(1 + g(z_b)) - t_b)^2 with t_b = log(1 + L_i) and,
  * if grad_dev is not NULL, its gradient with respect to every parameter in
  * canonical order (FP32, device, ds_net_param_count floats).  z is device memory

@@ -71,6 +71,7 @@ def lib():
         "ds_adam_steps": (S, [P, P]),
         "ds_loss_grad": (S, [P, P, P, I, P, P]),
         "ds_train_step": (S, [P, P, P, P, I, P]),
+        "ds_net_set_train_precision": (S, [P, I]),
         "ds_cloud_majorant": (S, [P, P]),
         "ds_trace_li": (S, [P, P, P, P, P, P, I64, I, C.c_uint64, P, P]),
         "ds_sample_records": (S, [P, P, I64, C.c_uint64, P, P, P, P]),
@@ -284,6 +285,10 @@ def ds_predict(ctx, cloud, net, precision, pos, view_dir, light_dir, out=None, p
     _check(lib().ds_predict(ctx, cloud, net, int(precision), _pts(pos), _pts(view_dir, P),
                             _pts(light_dir, P), P, _ptr(out), _ptr(pre), _ptr(flags)))
     return out, pre, flags
+
+
+def ds_net_set_train_precision(net, precision):
+    _check(lib().ds_net_set_train_precision(net, int(precision)))
 
 
 def ds_adam_create(net, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -255,12 +255,15 @@ ds_status forward_plain(ds_ctx *ctx, const ds_net *net, const float *z, int64_t 
 // trailing layer its pre-activations and outputs; gradient scratch.
 struct TrainWs {
     float *H, *F1, *A, *O, *HA, *HO, *dcur, *dnext, *dh, *dpre, *sq;
+    float *split;          // split-K partial products (BF16 training)
+    size_t split_floats;
 };
 
 ds_status train_ws(ds_net *net, int B, TrainWs &w)
 {
     const size_t BW = (size_t)B * net->W, K = net->K, Hh = net->H;
-    const size_t need = 4 * K * BW + 2 * Hh * BW + 3 * BW + 2 * (size_t)B;
+    const size_t split = (size_t)16 * net->W * 226;
+    const size_t need = 4 * K * BW + 2 * Hh * BW + 3 * BW + 2 * (size_t)B + split;
     if (net->tws_floats < need) {
         if (net->tws) {
             DS_HIP(hipStreamSynchronize(net->ctx->stream));
@@ -293,6 +296,9 @@ ds_status train_ws(ds_net *net, int B, TrainWs &w)
     w.dpre = p;
     p += B;
     w.sq = p;
+    p += B;
+    w.split = p;
+    w.split_floats = split;
     return DS_OK;
 }
 
@@ -303,17 +309,23 @@ ds_status train_ws(ds_net *net, int B, TrainWs &w)
             return s_;        \
     } while (0)
 
-// Loss and gradient of a minibatch (FP32): forward keeping pre-activations, then
+// Loss and gradient of a minibatch: forward keeping pre-activations, then
 // backpropagation layer by layer; every parameter gradient is written exactly once.
-ds_status loss_grad_f32(ds_net *net, const float *z, const float *target, int B, float *loss,
-                        float *grad)
+// FP32 arithmetic, or (train_prec BF16) every GEMM operand rounded to BF16 with FP32
+// accumulation on the matrix cores; epilogues, reductions and the loss stay FP32.
+ds_status loss_grad(ds_net *net, const float *z, const float *target, int B, float *loss,
+                    float *grad)
 {
     hipStream_t s = net->ctx->stream;
+    const bool bf = net->train_prec == DS_PREC_BF16;
     const int K = net->K, W = net->W, Hn = net->H, D = kStencil * K + 1;
     const float *th = net->theta;
     ParamOffsets po = param_offsets(K, W, Hn);
     TrainWs w;
     DS_TRY(train_ws(net, B, w));
+    auto mm = [&](const StridedGemm &g) {
+        return bf ? gemm_bf16(s, g, w.split, w.split_floats) : gemm_strided(s, g);
+    };
     const size_t BW = (size_t)B * W;
     auto H = [&](int k) { return w.H + k * BW; };
     auto F1 = [&](int k) { return w.F1 + k * BW; };
@@ -348,7 +360,16 @@ ds_status loss_grad_f32(ds_net *net, const float *z, const float *target, int B,
         g1.pre = H(k);
         g1.ldpre = W;
         g1.relu = 1;
-        DS_TRY(gemm_f32(s, g1));
+        if (bf) {
+            DS_TRY(mm({B, W, kStencil, z + (int64_t)k * kStencil, D, 1, th + po.V[k], 1, 226, H(k), W,
+                       0}));
+            if (k > 0)
+                DS_TRY(mm({B, W, W, O(k - 1), W, 1, th + po.W1[k], 1, W, H(k), W, 1}));
+            DS_TRY(layer_epilogue(s, B, W, H(k), W, z + (int64_t)kStencil * K, D,
+                                  th + po.V[k] + 225, 226, th + po.b1[k], nullptr, 0, F1(k), W));
+        } else {
+            DS_TRY(gemm_f32(s, g1));
+        }
         GemmArgs g2 = {};
         g2.M = B;
         g2.N = W;
@@ -367,7 +388,13 @@ ds_status loss_grad_f32(ds_net *net, const float *z, const float *target, int B,
         g2.pre = A(k);
         g2.ldpre = W;
         g2.relu = 1;
-        DS_TRY(gemm_f32(s, g2));
+        if (bf) {
+            DS_TRY(mm({B, W, W, F1(k), W, 1, th + po.W2[k], 1, W, A(k), W, 0}));
+            DS_TRY(layer_epilogue(s, B, W, A(k), W, nullptr, 0, nullptr, 0, th + po.b2[k],
+                                  k > 0 ? O(k - 1) : nullptr, W, O(k), W));
+        } else {
+            DS_TRY(gemm_f32(s, g2));
+        }
     }
     for (int m = 0; m < Hn; ++m) {
         const bool last = m == Hn - 1;
@@ -385,7 +412,14 @@ ds_status loss_grad_f32(ds_net *net, const float *z, const float *target, int B,
         g.pre = HA(m);
         g.ldpre = last ? 1 : W;
         g.relu = 1;
-        DS_TRY(gemm_f32(s, g));
+        if (bf) {
+            const int N = last ? 1 : W;
+            DS_TRY(mm({B, N, W, g.A1, W, 1, th + po.hw[m], 1, W, HA(m), N, 0}));
+            DS_TRY(layer_epilogue(s, B, N, HA(m), N, nullptr, 0, nullptr, 0, th + po.hb[m], nullptr,
+                                  0, HO(m), N));
+        } else {
+            DS_TRY(gemm_f32(s, g));
+        }
     }
     // ---- loss and d loss / d (final pre-activation)
     DS_TRY(loss_head(s, HA(Hn - 1), target, B, w.dpre, w.sq, loss));
@@ -403,32 +437,32 @@ ds_status loss_grad_f32(ds_net *net, const float *z, const float *target, int B,
             ldy = W;
         }
         // dW = dY^T in, db = column sums of dY
-        DS_TRY(gemm_strided(s, {rows, W, B, dY, 1, ldy, in, W, 1, grad + po.hw[m], W, 0}));
+        DS_TRY(mm({rows, W, B, dY, 1, ldy, in, W, 1, grad + po.hw[m], W, 0}));
         DS_TRY(colsum(s, dY, ldy, B, rows, grad + po.hb[m]));
         // d in = dY W
-        DS_TRY(gemm_strided(s, {B, W, rows, dY, ldy, 1, th + po.hw[m], W, 1, w.dnext, W, 0}));
+        DS_TRY(mm({B, W, rows, dY, ldy, 1, th + po.hw[m], W, 1, w.dnext, W, 0}));
         std::swap(w.dcur, w.dnext);
     }
     // ---- blocks, last first; dcur = d loss / d o^k
     for (int k = K - 1; k >= 0; --k) {
         float *da = w.dcur;
         DS_TRY(relu_mask(s, da, W, A(k), W, B, W));
-        DS_TRY(gemm_strided(s, {W, W, B, da, 1, W, F1(k), W, 1, grad + po.W2[k], W, 0}));
+        DS_TRY(mm({W, W, B, da, 1, W, F1(k), W, 1, grad + po.W2[k], W, 0}));
         DS_TRY(colsum(s, da, W, B, W, grad + po.b2[k]));
         // dh = (da W2) masked by h > 0
-        DS_TRY(gemm_strided(s, {B, W, W, da, W, 1, th + po.W2[k], W, 1, w.dh, W, 0}));
+        DS_TRY(mm({B, W, W, da, W, 1, th + po.W2[k], W, 1, w.dh, W, 0}));
         DS_TRY(relu_mask(s, w.dh, W, H(k), W, B, W));
         // dV over the 225 stencil columns and the gamma column
-        DS_TRY(gemm_strided(s, {W, kStencil, B, w.dh, 1, W, z + (int64_t)k * kStencil, D, 1,
+        DS_TRY(mm({W, kStencil, B, w.dh, 1, W, z + (int64_t)k * kStencil, D, 1,
                                 grad + po.V[k], 226, 0}));
-        DS_TRY(gemm_strided(s, {W, 1, B, w.dh, 1, W, z + (int64_t)kStencil * K, D, 1,
+        DS_TRY(mm({W, 1, B, w.dh, 1, W, z + (int64_t)kStencil * K, D, 1,
                                 grad + po.V[k] + 225, 226, 0}));
         DS_TRY(colsum(s, w.dh, W, B, W, grad + po.b1[k]));
         if (k > 0) {
-            DS_TRY(gemm_strided(s, {W, W, B, w.dh, 1, W, O(k - 1), W, 1, grad + po.W1[k], W, 0}));
+            DS_TRY(mm({W, W, B, w.dh, 1, W, O(k - 1), W, 1, grad + po.W1[k], W, 0}));
             // d o^{k-1} = da + dh W1
             DS_HIP(hipMemcpyAsync(w.dnext, da, BW * sizeof(float), hipMemcpyDeviceToDevice, s));
-            DS_TRY(gemm_strided(s, {B, W, W, w.dh, W, 1, th + po.W1[k], W, 1, w.dnext, W, 1}));
+            DS_TRY(mm({B, W, W, w.dh, W, 1, th + po.W1[k], W, 1, w.dnext, W, 1}));
             std::swap(w.dcur, w.dnext);
         }
     }
@@ -1153,6 +1187,16 @@ ds_status ds_batch_replay(ds_batch *b)
 }
 
 // ---------------------------------------------------------------- training (Sec. 5.2)
+ds_status ds_net_set_train_precision(ds_net *net, ds_precision precision)
+{
+    DS_CHECK(net, DS_ERR_INVALID_ARG, "ds_net_set_train_precision: net is NULL");
+    DS_CHECK(precision == DS_PREC_F32 || precision == DS_PREC_BF16,
+             precision == DS_PREC_FP8 ? DS_ERR_UNSUPPORTED : DS_ERR_INVALID_ARG,
+             "ds_net_set_train_precision: training runs in FP32 or BF16");
+    net->train_prec = precision;
+    return DS_OK;
+}
+
 ds_status ds_adam_create(ds_net *net, float lr, float beta1, float beta2, float eps, ds_adam **out)
 {
     DS_CHECK(net && out, DS_ERR_INVALID_ARG, "ds_adam_create: NULL argument");
@@ -1211,7 +1255,7 @@ ds_status ds_loss_grad(ds_net *net, const float *z, const float *target_log1p, i
     DS_CHECK(net && z && target_log1p, DS_ERR_INVALID_ARG, "ds_loss_grad: NULL argument");
     DS_CHECK(B >= 1 && B <= (1 << 20), DS_ERR_INVALID_ARG, "ds_loss_grad: batch %d outside 1..2^20",
              B);
-    return loss_grad_f32(net, z, target_log1p, B, loss_dev, grad_dev);
+    return loss_grad(net, z, target_log1p, B, loss_dev, grad_dev);
 }
 
 ds_status ds_train_step(ds_net *net, ds_adam *opt, const float *z, const float *target_log1p,
@@ -1221,7 +1265,7 @@ ds_status ds_train_step(ds_net *net, ds_adam *opt, const float *z, const float *
     DS_CHECK(opt->net == net, DS_ERR_INVALID_ARG, "ds_train_step: optimiser of another network");
     DS_CHECK(B >= 1 && B <= (1 << 20), DS_ERR_INVALID_ARG,
              "ds_train_step: batch %d outside 1..2^20", B);
-    ds_status st = loss_grad_f32(net, z, target_log1p, B, loss_dev, opt->grad);
+    ds_status st = loss_grad(net, z, target_log1p, B, loss_dev, opt->grad);
     if (st)
         return st;
     opt->t += 1;

@@ -92,6 +92,7 @@ struct ds_net {
     // training workspace (activations and gradients of one minibatch)
     float *tws = nullptr;
     size_t tws_floats = 0;
+    ds_precision train_prec = DS_PREC_F32;  // arithmetic of ds_loss_grad / ds_train_step
 };
 
 struct ds_batch {
@@ -167,6 +168,13 @@ struct StridedGemm {
     int accumulate;
 };
 ds_status gemm_strided(hipStream_t s, const StridedGemm &g);
+// same product with operands rounded to BF16 and FP32 accumulation on the matrix
+// cores; split_ws (ws_floats floats, may be NULL) enables deterministic split-K
+ds_status gemm_bf16(hipStream_t s, const StridedGemm &g, float *split_ws, size_t ws_floats);
+int splitk_count(const StridedGemm &g);
+ds_status layer_epilogue(hipStream_t s, int M, int N, float *pre, int ldp, const float *gv, int ldg,
+                         const float *gw, int ldgw, const float *bias, const float *R, int ldr,
+                         float *out, int ldo);
 ds_status relu_mask(hipStream_t s, float *x, int ldx, const float *pre, int ldp, int R, int C);
 ds_status colsum(hipStream_t s, const float *d, int ldd, int R, int C, float *db);
 ds_status loss_head(hipStream_t s, const float *pre, const float *t, int B, float *dpre, float *sq,

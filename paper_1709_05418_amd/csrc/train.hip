@@ -141,6 +141,120 @@ __global__ void __launch_bounds__(256) k_adam(float *theta, float *m, float *v, 
     }
 }
 
+// ---------------------------------------------------------------- BF16 MFMA GEMM
+// C (+)= A B with the strided operands of StridedGemm, every operand rounded to BF16
+// (nearest even) as it is staged into LDS, products accumulated in FP32 by
+// v_mfma_f32_16x16x32_bf16.  A 256-thread block computes a 64 x 64 tile of C, each
+// wave a 32 x 32 quarter (2 x 2 MFMA tiles).  Split s (blockIdx.z) covers
+// k in [s kc, (s+1) kc); with several splits the partial tiles go to P[s][M][N] and
+// k_splitk_sum adds them in split order, so results do not depend on timing.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+constexpr int TM = 64, TN = 64, TK = 32, TKP = TK + 8;
+
+__global__ void __launch_bounds__(256) k_gemm_bf16(StridedGemm g, int kc, float *P)
+{
+    __shared__ __bf16 As[TM][TKP];  // [row][k]
+    __shared__ __bf16 Bt[TN][TKP];  // [col][k]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int g4 = lane >> 4, n16 = lane & 15;
+    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+    const int kbeg = blockIdx.z * kc;
+    const int kend = min(g.K, kbeg + kc);
+    const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
+    const bool a_kc = g.sak == 1;  // consecutive threads walk the contiguous index
+    const bool b_nc = g.sbn == 1;
+    f4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = kbeg; k0 < kend; k0 += TK) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int e = tid + 256 * i;
+            const int r = a_kc ? e >> 5 : e & 63, ka = a_kc ? e & 31 : e >> 6;
+            float v = 0.f;
+            if (m0 + r < g.M && k0 + ka < kend)
+                v = g.A[(int64_t)(m0 + r) * g.sam + (int64_t)(k0 + ka) * g.sak];
+            As[r][ka] = (__bf16)v;
+            const int c = b_nc ? e & 63 : e >> 5, kb = b_nc ? e >> 6 : e & 31;
+            float u = 0.f;
+            if (n0 + c < g.N && k0 + kb < kend)
+                u = g.B[(int64_t)(k0 + kb) * g.sbk + (int64_t)(n0 + c) * g.sbn];
+            Bt[c][kb] = (__bf16)u;
+        }
+        __syncthreads();
+        bf16x8 a[2], b[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            a[t] = *reinterpret_cast<const bf16x8 *>(&As[wr + 16 * t + n16][8 * g4]);
+            b[t] = *reinterpret_cast<const bf16x8 *>(&Bt[wc + 16 * t + n16][8 * g4]);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        __syncthreads();
+    }
+    // lane 16 g4 + n16 holds rows 4 g4 .. 4 g4 + 3, column n16 of each 16 x 16 tile
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = m0 + wr + 16 * i + 4 * g4 + q, col = n0 + wc + 16 * j + n16;
+                if (row >= g.M || col >= g.N)
+                    continue;
+                const float v = acc[i][j][q];
+                if (P) {
+                    P[((int64_t)blockIdx.z * g.M + row) * g.N + col] = v;
+                } else {
+                    float *c = g.C + (int64_t)row * g.ldc + col;
+                    *c = g.accumulate ? *c + v : v;
+                }
+            }
+}
+
+__global__ void __launch_bounds__(256) k_splitk_sum(const float *P, int S, StridedGemm g)
+{
+    const int64_t n = (int64_t)g.M * g.N;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        float v = 0.f;
+        for (int z = 0; z < S; ++z)
+            v += P[z * n + i];
+        const int64_t row = i / g.N, col = i % g.N;
+        float *c = g.C + row * g.ldc + col;
+        *c = g.accumulate ? *c + v : v;
+    }
+}
+
+// Forward epilogue of a layer whose GEMM part is already in pre:
+// pre += g[m] gw[n] + bias[n] + R[m][n]; out = relu(pre).
+__global__ void __launch_bounds__(256) k_epilogue(int M, int N, float *pre, int ldp,
+                                                  const float *gv, int ldg, const float *gw,
+                                                  int ldgw, const float *bias, const float *R,
+                                                  int ldr, float *out, int ldo)
+{
+    const int64_t n = (int64_t)M * N;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t m = i / N, c = i % N;
+        float v = pre[m * ldp + c];
+        if (gv)
+            v += gv[m * ldg] * gw[c * ldgw];
+        v += bias[c];
+        if (R)
+            v += R[m * ldr + c];
+        pre[m * ldp + c] = v;
+        out[m * ldo + c] = fmaxf(v, 0.f);
+    }
+}
+
 int grid1(int64_t n)
 {
     int64_t b = (n + 255) / 256;
@@ -155,6 +269,42 @@ ds_status gemm_strided(hipStream_t s, const StridedGemm &g)
         return DS_OK;
     dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM);
     k_gemm_strided<<<grid, 256, 0, s>>>(g);
+    DS_HIP(hipGetLastError());
+    return DS_OK;
+}
+
+int splitk_count(const StridedGemm &g)
+{
+    const int64_t tiles = (int64_t)((g.N + TN - 1) / TN) * ((g.M + TM - 1) / TM);
+    const int ksteps = (g.K + TK - 1) / TK;
+    int S = 1;
+    while (S < 16 && tiles * S < 256 && ksteps >= 8 * S)
+        S *= 2;
+    return S;
+}
+
+ds_status gemm_bf16(hipStream_t s, const StridedGemm &g, float *split_ws, size_t ws_floats)
+{
+    if (g.M <= 0 || g.N <= 0)
+        return DS_OK;
+    const int S = split_ws ? splitk_count(g) : 1;
+    const int ksteps = (g.K + TK - 1) / TK;
+    const int kc = ((ksteps + S - 1) / S) * TK;
+    const bool split = S > 1 && (size_t)S * g.M * g.N <= ws_floats;
+    dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM, split ? S : 1);
+    k_gemm_bf16<<<grid, 256, 0, s>>>(g, split ? kc : ksteps * TK, split ? split_ws : nullptr);
+    if (split)
+        k_splitk_sum<<<grid1((int64_t)g.M * g.N), 256, 0, s>>>(split_ws, S, g);
+    DS_HIP(hipGetLastError());
+    return DS_OK;
+}
+
+ds_status layer_epilogue(hipStream_t s, int M, int N, float *pre, int ldp, const float *gv, int ldg,
+                         const float *gw, int ldgw, const float *bias, const float *R, int ldr,
+                         float *out, int ldo)
+{
+    k_epilogue<<<grid1((int64_t)M * N), 256, 0, s>>>(M, N, pre, ldp, gv, ldg, gw, ldgw, bias, R, ldr,
+                                                     out, ldo);
     DS_HIP(hipGetLastError());
     return DS_OK;
 }

@@ -164,6 +164,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--train-precision", default="bf16", choices=["bf16", "fp32"],
+                    help="GEMM arithmetic of the training step (FP32 masters either way)")
     ap.add_argument("--judge-n", type=int, default=1024)
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
@@ -205,6 +207,8 @@ def main(argv=None):
     net = ds.Net(ctx, K, W, 3)
     net.set_params(synth.init_params(K, W, 3, args.seed + 1, branch_scale=1 / math.sqrt(K),
                                      out_scale=0.01, out_bias=float(li.mean())))
+    ds.ds_net_set_train_precision(net.h, ds.DS_PREC_BF16 if args.train_precision == "bf16"
+                                  else ds.DS_PREC_F32)
     opt = ds.ds_adam_create(net.h, args.lr)
     res = train(net, opt, z, t, args.steps, args.batch, 0.25, eval_every=max(1, args.steps // 10),
                 log=log)
@@ -248,7 +252,8 @@ def main(argv=None):
             f"{j['rel_l1_direct_only']:.4f}), RMSE {j['rmse']:.5f}; reference noise "
             f"{j['ref_noise_rel']:.4f}; network {j['seconds_network']:.2f}s vs reference "
             f"{j['seconds_reference']:.2f}s")
-    summary.update({"clouds": args.clouds, "n": args.n, "pairs": per * args.clouds,
+    summary.update({"train_precision": args.train_precision,
+                    "clouds": args.clouds, "n": args.n, "pairs": per * args.clouds,
                     "spp": args.spp, "K": K, "W": W, "steps": args.steps, "batch": args.batch,
                     "data_seconds": t_data, "paths_per_second": paths / t_data,
                     "train_seconds": res["seconds"], "held_out": res["held_out"],

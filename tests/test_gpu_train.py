@@ -109,3 +109,76 @@ def test_training_reduces_the_loss(ctx, batch):
     assert losses[-1] < 0.5 * losses[0]
     ds.ds_adam_destroy(opt)
     net.close()
+
+
+@pytest.fixture(scope="module")
+def wide_batch():
+    # paper-width network on descriptors of a 64^3 cloud at K = 10
+    w = Workload(64, 64.0, L=7, K=10, P=256, seed_cloud=3, seed_pts=41)
+    z, _ = w.oracle_z()
+    t = np.log1p(np.random.default_rng(6).random(w.P) * 1.5)
+    return w, z, t
+
+
+@pytest.mark.parametrize("case", ["small", "K6W64", "paper"])
+def test_bf16_training_arithmetic_matches_oracle(ctx, batch, wide_batch, case):
+    # BF16 operands with FP32 accumulation: the loss and the whole gradient agree
+    # with the FP64 oracle to the BF16 tolerance, and the step stays reproducible
+    if case == "paper":
+        w, z, t = wide_batch
+        K, W, B = 10, 200, 256
+    else:
+        w, z, t = batch
+        K, W, B = (2, 16, 64) if case == "small" else (6, 64, 300)
+    zk = np.ascontiguousarray(np.concatenate([z[:B, :225 * K], z[:B, -1:]], axis=1))
+    net, theta = _net(ctx, K, W, seed=K + W + 1, z=zk.astype(np.float64))
+    ds.ds_net_set_train_precision(net.h, ds.DS_PREC_BF16)
+    zt = torch.from_numpy(zk.astype(np.float32)).cuda()
+    tt = torch.from_numpy(t[:B].astype(np.float32)).cuda()
+    loss, grad = ds.ds_loss_grad(net.h, zt, tt, net.n_params)
+    lref, gref = O.loss_grad(theta.astype(np.float64), K, W, 3,
+                             zk.astype(np.float32).astype(np.float64),
+                             t[:B].astype(np.float32).astype(np.float64))
+    g = grad.cpu().numpy().astype(np.float64)
+    e = rel_l2(g, gref)
+    cos = float(g @ gref / (np.linalg.norm(g) * np.linalg.norm(gref)))
+    print(f"bf16 {case}: loss {loss.item():.6f} ref {lref:.6f} grad rel_l2 {e:.2e} cos {cos:.6f}")
+    assert loss.item() == pytest.approx(lref, rel=2e-2)
+    assert e <= 5e-2 and cos >= 0.998
+    loss2, grad2 = ds.ds_loss_grad(net.h, zt, tt, net.n_params)
+    assert torch.equal(grad, grad2) and torch.equal(loss, loss2)
+    with pytest.raises(ds.DSError):
+        ds.ds_net_set_train_precision(net.h, ds.DS_PREC_FP8)
+    net.close()
+
+
+def test_bf16_training_steps_reduce_loss_and_run_faster(ctx):
+    # paper width, minibatch 1024 of random descriptors with a learnable target
+    K, W, B = 10, 200, 1024
+    rng = np.random.default_rng(8)
+    z = rng.random((B, 225 * K + 1)).astype(np.float32)
+    z[:, -1] *= np.pi
+    t = np.log1p(z[:, :225].mean(1) * 2.0).astype(np.float32)
+    zt, tt = torch.from_numpy(z).cuda(), torch.from_numpy(t).cuda()
+    rates = {}
+    for prec in (ds.DS_PREC_F32, ds.DS_PREC_BF16):
+        net = ds.Net(ctx, K, W, 3)
+        net.set_params(synth.init_params(K, W, 3, 4, branch_scale=1 / np.sqrt(K), out_scale=0.01,
+                                         out_bias=float(np.expm1(t).mean())))
+        ds.ds_net_set_train_precision(net.h, prec)
+        opt = ds.ds_adam_create(net.h, 1e-3)
+        losses = torch.zeros(60, device="cuda")
+        ds.ds_train_step(net.h, opt, zt, tt, loss=losses[0:1])
+        torch.cuda.synchronize()
+        import time
+        t0 = time.perf_counter()
+        for i in range(1, 60):
+            ds.ds_train_step(net.h, opt, zt, tt, loss=losses[i:i + 1])
+        torch.cuda.synchronize()
+        rates[prec] = 59 / (time.perf_counter() - t0)
+        l = losses.cpu().numpy()
+        print(f"precision {prec}: loss {l[0]:.5f} -> {l[-1]:.5f}, {rates[prec]:.1f} steps/s")
+        assert l[-1] < 0.5 * l[0]
+        ds.ds_adam_destroy(opt)
+        net.close()
+    assert rates[ds.DS_PREC_BF16] > rates[ds.DS_PREC_F32]
