@@ -237,6 +237,8 @@ ds_status ds_batch_replay(ds_batch *batch);
 ds_status ds_adam_create(ds_net *net, float lr, float beta1, float beta2, float eps,
                          ds_adam **out);
 ds_status ds_adam_destroy(ds_adam *opt);
+/* Learning rate of the following updates (moments and step count are kept). */
+ds_status ds_adam_set_lr(ds_adam *opt, float lr);
 /* Number of updates applied so far (host read, no synchronisation). */
 ds_status ds_adam_steps(const ds_adam *opt, int64_t *t);
 

@@ -68,6 +68,7 @@ def lib():
         "ds_predict": (S, [P, P, P, I, P, P, P, I64, P, P, P]),
         "ds_adam_create": (S, [P, F, F, F, F, P]),
         "ds_adam_destroy": (S, [P]),
+        "ds_adam_set_lr": (S, [P, F]),
         "ds_adam_steps": (S, [P, P]),
         "ds_loss_grad": (S, [P, P, P, I, P, P]),
         "ds_train_step": (S, [P, P, P, P, I, P]),
@@ -300,6 +301,10 @@ def ds_adam_create(net, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
 
 def ds_adam_destroy(opt):
     _check(lib().ds_adam_destroy(opt))
+
+
+def ds_adam_set_lr(opt, lr):
+    _check(lib().ds_adam_set_lr(opt, float(lr)))
 
 
 def ds_adam_steps(opt) -> int:

@@ -1230,6 +1230,15 @@ ds_status ds_adam_create(ds_net *net, float lr, float beta1, float beta2, float 
     return DS_OK;
 }
 
+ds_status ds_adam_set_lr(ds_adam *a, float lr)
+{
+    DS_CHECK(a, DS_ERR_INVALID_ARG, "ds_adam_set_lr: optimiser is NULL");
+    DS_CHECK(lr > 0.f && std::isfinite(lr), DS_ERR_INVALID_ARG,
+             "ds_adam_set_lr: learning rate must be positive and finite");
+    a->lr = lr;
+    return DS_OK;
+}
+
 ds_status ds_adam_destroy(ds_adam *a)
 {
     if (!a)

@@ -38,10 +38,13 @@ def make_dataset(ctx, clouds, n_per_cloud, spp, seed, params=None, device="cuda"
     return z, t
 
 
-def train(net, opt, z, t, steps, batch=1024, val_frac=0.25, eval_every=500, seed=0, log=None):
+def train(net, opt, z, t, steps, batch=1024, val_frac=0.25, eval_every=500, seed=0, log=None,
+          lr=None, decay_at=(), decay=0.1):
     """Adam steps on contiguous minibatches of the first (1 - val_frac) rows; each
-    pass over the data starts at a different offset.  Returns a dict with the
-    per-step training losses and the held-out losses at each evaluation."""
+    pass over the data starts at a different offset.  With lr given, the learning
+    rate is multiplied by `decay` at each fraction of the run listed in decay_at.
+    Returns a dict with the per-step training losses and the held-out losses at each
+    evaluation."""
     import torch
     M = z.shape[0]
     n_val = int(M * val_frac)
@@ -69,7 +72,12 @@ def train(net, opt, z, t, steps, batch=1024, val_frac=0.25, eval_every=500, seed
     t0 = time.time()
     v0 = held_out()
     val.append((0, v0))
+    cuts = sorted(int(f * steps) for f in decay_at)
     for i in range(steps):
+        if lr is not None and cuts and i == cuts[0]:
+            cuts.pop(0)
+            lr *= decay
+            ds.ds_adam_set_lr(opt, lr)
         j = i % per_epoch
         if j == 0:  # each pass starts at a random offset within the leftover rows
             start = int(torch.randint(0, n_tr - per_epoch * batch + 1, (1,), generator=g).item())
@@ -164,6 +172,8 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--decay-at", type=float, nargs="*", default=[0.6, 0.85],
+                    help="fractions of the run at which the learning rate drops tenfold")
     ap.add_argument("--train-precision", default="bf16", choices=["bf16", "fp32"],
                     help="GEMM arithmetic of the training step (FP32 masters either way)")
     ap.add_argument("--judge-n", type=int, default=1024)
@@ -211,7 +221,7 @@ def main(argv=None):
                                   else ds.DS_PREC_F32)
     opt = ds.ds_adam_create(net.h, args.lr)
     res = train(net, opt, z, t, args.steps, args.batch, 0.25, eval_every=max(1, args.steps // 10),
-                log=log)
+                log=log, lr=args.lr, decay_at=tuple(args.decay_at))
     log(f"training {res['seconds']:.1f}s ({args.steps / res['seconds']:.1f} steps/s)")
     if args.save_theta:
         np.save(args.save_theta, net.get_params())
