@@ -107,13 +107,34 @@ __device__ __forceinline__ float finish_one(const u32x4 &v, float fx, float fy, 
     return lerp(lerp(x00, x10, fy), lerp(x01, x11, fy), fz);
 }
 
+// Lattice tables shared by a workgroup: (ix, iy) of stencil columns 0..23 (the
+// column walk of chunks 0..5) and the coordinates of halves 12, 13 (column 24 for
+// lane group 0; the iz = 8 plane for lane groups 1..3, see issue_table_half).
+__device__ __forceinline__ void init_tables(int tid, float4 *plane, float2 *cols)
+{
+    if (tid < 32) {
+        const int gg = tid >> 3, j = tid & 7;
+        if (gg == 0) {
+            plane[tid] = make_float4(4.f, 4.f, (float)j, 0.f);
+        } else {
+            const int G = 2 * (gg - 1) + (j >> 2), jj = j & 3;
+            plane[tid] = G < 5 ? make_float4((float)jj, (float)G, 8.f, 0.f)
+                               : make_float4(4.f, (float)jj, 8.f, 0.f);
+        }
+    }
+    if (tid < 24)
+        cols[tid] = make_float2((float)(tid % 5), (float)(tid / 5));
+}
+
 // Halves 0..11 (chunks 0..5): lane group g walks stencil column 4c + g along z,
 // iz = 4 (h & 1) + j, so consecutive samples differ by the step vector c.
 __device__ __forceinline__ void issue_column_half(gcell_ptr cells, const FusedLevel &L,
-                                                  const PtLevel &q, int h, int g, Pending &p)
+                                                  const PtLevel &q, int h, int g,
+                                                  const float2 *cols, Pending &p)
 {
-    const int col = 4 * (h >> 1) + g;
-    const float ix = (float)(col % 5), iy = (float)(col / 5), iz0 = (float)(4 * (h & 1));
+    // (ix, iy) of column 4 (h >> 1) + g from the table (see init_tables)
+    const float2 xy = cols[4 * (h >> 1) + g];
+    const float ix = xy.x, iy = xy.y, iz0 = (float)(4 * (h & 1));
     const float bx = q.u0[0] + ix * q.a[0] + iy * q.b[0] + iz0 * q.c[0];
     const float by = q.u0[1] + ix * q.a[1] + iy * q.b[1] + iz0 * q.c[1];
     const float bz = q.u0[2] + ix * q.a[2] + iy * q.b[2] + iz0 * q.c[2];
@@ -244,6 +265,16 @@ __device__ __forceinline__ bf16x8 pack8(const f4 &lo, const f4 &hi)
 typedef __attribute__((address_space(1))) void gvoid;
 typedef __attribute__((address_space(3))) void lvoid;
 
+// s_waitcnt vmcnt(N) with the other counters left alone (gfx9 encoding: vmcnt in
+// bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
+template <int N>
+__device__ __forceinline__ void vm_wait()
+{
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | (15 << 8) | ((N >> 4) << 14));
+    asm volatile("" ::: "memory");
+}
+
 template <int MT, int NW>
 struct WeightStage {
     static constexpr int G = 2;
@@ -274,11 +305,11 @@ struct WeightStage {
     __device__ __forceinline__ void begin(const uint4 *frags, int tid)
     {
         // drain a copy still in flight from the previous tile before reusing the buffers
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        vm_wait<0>();
         __syncthreads();
         src = frags;
         copy_group(tid, buf);
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        vm_wait<0>();
         __syncthreads();
         cur = 0;
         j = 0;
@@ -291,11 +322,19 @@ struct WeightStage {
             pending = false;
         }
     }
+    // N: vector-memory loads this chunk issued after its fetch() that may stay in
+    // flight across the barrier (the copy is older, so waiting until at most N loads
+    // are outstanding completes it)
+    template <int N = 0>
     __device__ __forceinline__ void next(int tid)
     {
         if (++j == G) {
-            fetch(tid);  // a group without sample loads has not issued its copy yet
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            if (pending) {  // a group whose chunks never fetched: copy now, wait for all
+                fetch(tid);
+                vm_wait<0>();
+            } else {
+                vm_wait<N>();
+            }
             __syncthreads();
             cur ^= 1;
             j = 0;
@@ -331,7 +370,7 @@ __device__ __forceinline__ void dense(WeightStage<MT, NW> &ws, const float *__re
         const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
         bf16x8 B = pack8(in[2 * q], (2 * q + 1 < MT) ? in[2 * q + 1 < MT ? 2 * q + 1 : 0] : z4);
         mfma_chunk<MT>(ws.chunk(), lane, B, out);
-        ws.next(tid);
+        ws.template next<0>(tid);
     }
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -348,6 +387,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
     constexpr int WP = 16 * MT;        // padded width
     __shared__ uint4 wbuf[2 * WeightStage<MT, NW>::BUF];
     __shared__ float4 plane[32];       // lattice coordinates of halves 12, 13 per (lane group, j)
+    __shared__ float2 cols[24];
     // residual stream o^k of each wave in FP32, accumulator layout [tile][lane]; it
     // lives in LDS while the first layer runs and comes back for the second
     __shared__ f4 obuf[NW][MT][64];
@@ -356,16 +396,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int g = lane >> 4, n = lane & 15;
-    if (tid < 32) {
-        const int gg = tid >> 3, j = tid & 7;
-        if (gg == 0) {
-            plane[tid] = make_float4(4.f, 4.f, (float)j, 0.f);        // column 24, iz = j
-        } else {
-            const int G = 2 * (gg - 1) + (j >> 2), jj = j & 3;        // plane iz = 8
-            plane[tid] = G < 5 ? make_float4((float)jj, (float)G, 8.f, 0.f)
-                               : make_float4(4.f, (float)jj, 8.f, 0.f);
-        }
-    }
+    init_tables(tid, plane, cols);
 
     WeightStage<MT, NW> ws;
     ws.buf = wbuf;
@@ -408,8 +439,8 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
             level_from_geom(L, geom[(tid >> 6) * 16 + n], q);
         }
         Pending pa, pb;
-        issue_column_half(cells, L, q, 0, g, pa);
-        issue_column_half(cells, L, q, 1, g, pb);
+        issue_column_half(cells, L, q, 0, g, cols, pa);
+        issue_column_half(cells, L, q, 1, g, cols, pb);
 
         for (int k = 0; k < a.K; ++k) {
             const float *b1 = vec + (size_t)k * 2 * WP;
@@ -427,13 +458,13 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
     #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
-                issue_column_half(cells, L, q, 2 * c + 2, g, pa);
+                issue_column_half(cells, L, q, 2 * c + 2, g, cols, pa);
     #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
-                issue_column_half(cells, L, q, 2 * c + 3, g, pb);
+                issue_column_half(cells, L, q, 2 * c + 3, g, cols, pb);
                 mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
-                ws.next(tid);
+                ws.template next<0>(tid);
             }
             {  // chunk 5: issues the table halves of chunk 6
                 ws.fetch(tid);
@@ -447,7 +478,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
                     hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
                 issue_table_half(cells, L, q, 1, g, plane, pb);
                 mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
-                ws.next(tid);
+                ws.template next<0>(tid);
             }
             {  // chunk 6: issues chunk 7's stencil sample (4, 4, 8)
                 ws.fetch(tid);
@@ -463,7 +494,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
                 for (int j = 0; j < 4; ++j)
                     hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
                 mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
-                ws.next(tid);
+                ws.template next<0>(tid);
             }
             // chunk 7: stencil sample (4, 4, 8), gamma, and the odd tile of o^{k-1}
             {
@@ -472,7 +503,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
                 f4 lo = f4{g == 0 ? s : 0.f, g == 0 ? gamma : 0.f, 0.f, 0.f};
                 bf16x8 B = pack8(lo, (MT & 1) ? Os[MT - 1][lane] : z4);
                 mfma_chunk<MT>(ws.chunk(), lane, B, F);
-                ws.next(tid);
+                ws.template next<0>(tid);
             }
             // o^{k-1} in pairs of tiles (o^0 = 0: block 1 has no such chunks)
             if (k > 0) {
@@ -480,7 +511,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
                 for (int qq = 0; qq < MT / 2; ++qq) {
                     ws.fetch(tid);
                     mfma_chunk<MT>(ws.chunk(), lane, pack8(Os[2 * qq][lane], Os[2 * qq + 1][lane]), F);
-                    ws.next(tid);
+                    ws.template next<0>(tid);
                 }
             }
             // the next level's first samples fly while the second layer runs
@@ -488,8 +519,8 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
                 L = cl.lvt[k + 1];
                 cells = (gcell_ptr)L.cells;
                 level_from_geom(L, geom[(tid >> 6) * 16 + n], q);
-                issue_column_half(cells, L, q, 0, g, pa);
-                issue_column_half(cells, L, q, 1, g, pb);
+                issue_column_half(cells, L, q, 0, g, cols, pa);
+                issue_column_half(cells, L, q, 1, g, cols, pb);
             }
             // F1 = relu(. + b1)
     #pragma unroll
@@ -510,7 +541,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
                 mfma_chunk<MT>(ws.chunk(), lane,
                                pack8(F[2 * qq], (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0] : z4),
                                O);
-                ws.next(tid);
+                ws.template next<0>(tid);
             }
     #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
@@ -577,27 +608,19 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
     constexpr int WP = 16 * MT;
     __shared__ uint4 wbuf[2 * WeightStage<MT, NW>::BUF];
     __shared__ float4 plane[32];
+    __shared__ float2 cols[24];
     __shared__ PtGeom geom[16 * NW];   // per point of the tile, see make_geom
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int g = lane >> 4, n = lane & 15;
-    if (tid < 32) {
-        const int gg = tid >> 3, j = tid & 7;
-        if (gg == 0) {
-            plane[tid] = make_float4(4.f, 4.f, (float)j, 0.f);
-        } else {
-            const int G = 2 * (gg - 1) + (j >> 2), jj = j & 3;
-            plane[tid] = G < 5 ? make_float4((float)jj, (float)G, 8.f, 0.f)
-                               : make_float4(4.f, (float)jj, 8.f, 0.f);
-        }
-    }
+    init_tables(tid, plane, cols);
     WeightStage<MT, NW> ws;
     ws.buf = wbuf;
     // persistent loop over tiles of 16 NW points; a tile never spans two clouds
 #pragma unroll 1
     for (int64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
-        // keeps tile-invariant LDS reads (the plane table) inside the loop: hoisted,
-        // they would hold registers across the whole tile and force spills
+        // keeps tile-invariant LDS reads (the tables) inside the loop: hoisted, they
+        // would hold registers across the whole tile and force spills
         asm volatile("" ::: "memory");
         const FusedCloud &cl = a.cl[tile_cloud(a, t)];
         ws.begin(frags, tid);
@@ -617,82 +640,106 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
         }
         const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
         f4 O[MT], F[MT];
-    #pragma unroll
+#pragma unroll
         for (int mt = 0; mt < MT; ++mt)
             O[mt] = z4;
 
+        // Samples are software-pipelined within a level: each stencil chunk finishes
+        // the samples the previous chunk issued and issues the next chunk's.  (Issuing
+        // the next level's first samples before the second layer would keep them live
+        // next to both accumulator sets, which costs more registers than there are.)
         for (int k = 0; k < a.K; ++k) {
             const FusedLevel L = cl.lvt[k];
             gcell_ptr cells = (gcell_ptr)L.cells;
             PtLevel q;
-            {
-                level_from_geom(L, geom[(tid >> 6) * 16 + n], q);
-            }
+            level_from_geom(L, geom[(tid >> 6) * 16 + n], q);
+            Pending pa, pb;
+            issue_column_half(cells, L, q, 0, g, cols, pa);
+            issue_column_half(cells, L, q, 1, g, cols, pb);
             const float *b1 = vec + (size_t)k * 2 * WP;
             const float *b2 = b1 + WP;
-    #pragma unroll
+            // the first layer accumulates onto its bias
+#pragma unroll
             for (int mt = 0; mt < MT; ++mt)
-                F[mt] = z4;
-    #pragma unroll 1
-            for (int c = 0; c < 7; ++c) {
-                Pending pa, pb;
-                if (c < 6) {
-                    issue_column_half(cells, L, q, 2 * c, g, pa);
-                    issue_column_half(cells, L, q, 2 * c + 1, g, pb);
-                } else {
-                    issue_table_half(cells, L, q, 0, g, plane, pa);
-                    issue_table_half(cells, L, q, 1, g, plane, pb);
-                }
-                // after the samples, so waiting for them does not wait for the weights
+                F[mt] = *reinterpret_cast<const f4 *>(b1 + 16 * mt + 4 * g);
+#pragma unroll 1
+            for (int c = 0; c < 5; ++c) {  // chunks 0..4: halves 2c, 2c+1 in, 2c+2, 2c+3 out
                 ws.fetch(tid);
                 f4 lo, hi;
-    #pragma unroll
-                for (int j = 0; j < 4; ++j) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
                     lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
+                issue_column_half(cells, L, q, 2 * c + 2, g, cols, pa);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
                     hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
-                }
+                issue_column_half(cells, L, q, 2 * c + 3, g, cols, pb);
                 mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
-                ws.next(tid);
+                ws.template next<8>(tid);
             }
-            {
-                Pending pa;
+            {  // chunk 5: issues the table halves of chunk 6
+                ws.fetch(tid);
+                f4 lo, hi;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
+                issue_table_half(cells, L, q, 0, g, plane, pa);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
+                issue_table_half(cells, L, q, 1, g, plane, pb);
+                mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
+                ws.template next<8>(tid);
+            }
+            {  // chunk 6: issues chunk 7's stencil sample (4, 4, 8)
+                ws.fetch(tid);
+                f4 lo, hi;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
                 issue_one(cells, L, q.u0[0] + 4.f * (q.a[0] + q.b[0]) + 8.f * q.c[0],
                           q.u0[1] + 4.f * (q.a[1] + q.b[1]) + 8.f * q.c[1],
                           q.u0[2] + 4.f * (q.a[2] + q.b[2]) + 8.f * q.c[2], pa.v[0], pa.fx[0],
                           pa.fy[0], pa.fz[0]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
+                mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
+                ws.template next<1>(tid);
+            }
+            {  // chunk 7: stencil sample (4, 4, 8), gamma, and the odd tile of o^{k-1}
                 ws.fetch(tid);
                 const float sv = finish_one(pa.v[0], pa.fx[0], pa.fy[0], pa.fz[0]);
                 const f4 lo = f4{g == 0 ? sv : 0.f, g == 0 ? gamma : 0.f, 0.f, 0.f};
                 mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, (MT & 1) ? O[MT - 1] : z4), F);
-                ws.next(tid);
+                ws.template next<0>(tid);
             }
             if (k > 0) {
-    #pragma unroll
+#pragma unroll
                 for (int qq = 0; qq < MT / 2; ++qq) {
                     ws.fetch(tid);
                     mfma_chunk<MT>(ws.chunk(), lane, pack8(O[2 * qq], O[2 * qq + 1]), F);
-                    ws.next(tid);
+                    ws.template next<0>(tid);
                 }
             }
-    #pragma unroll
+#pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
-                const f4 bb = *reinterpret_cast<const f4 *>(b1 + 16 * mt + 4 * g);
-    #pragma unroll
+#pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    F[mt][i] = fmaxf(F[mt][i] + bb[i], 0.f);
+                    F[mt][i] = fmaxf(F[mt][i], 0.f);
                 O[mt] += *reinterpret_cast<const f4 *>(b2 + 16 * mt + 4 * g);
             }
-    #pragma unroll
+#pragma unroll
             for (int qq = 0; qq < C2; ++qq) {
                 ws.fetch(tid);
                 mfma_chunk<MT>(ws.chunk(), lane,
                                pack8(F[2 * qq], (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0] : z4),
                                O);
-                ws.next(tid);
+                ws.template next<0>(tid);
             }
-    #pragma unroll
+#pragma unroll
             for (int mt = 0; mt < MT; ++mt)
-    #pragma unroll
+#pragma unroll
                 for (int i = 0; i < 4; ++i)
                     O[mt][i] = fmaxf(O[mt][i], 0.f);
         }
@@ -704,14 +751,14 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
         }
         if (h < a.H - 1) {
             dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
-    #pragma unroll
+#pragma unroll
             for (int mt = 0; mt < MT; ++mt)
                 O[mt] = F[mt];
         }
         const float *wl = bh + (size_t)(a.H - 1) * WP;
         const float bl = wl[WP];
         float acc = 0.f;
-    #pragma unroll
+#pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
             const f4 w = *reinterpret_cast<const f4 *>(wl + 16 * mt + 4 * g);
             acc += w[0] * O[mt][0] + w[1] * O[mt][1] + w[2] * O[mt][2] + w[3] * O[mt][3];
@@ -776,7 +823,7 @@ __device__ __forceinline__ void dense_nt(WeightStage<MT, NW> &ws, const float *_
         for (int nt = 0; nt < NT; ++nt)
             B[nt] = pack8(in[2 * q][nt], (2 * q + 1 < MT) ? in[2 * q + 1 < MT ? 2 * q + 1 : 0][nt] : z4);
         mfma_chunk_nt<MT, NT>(ws.chunk(), lane, B, out);
-        ws.next(tid);
+        ws.template next<0>(tid);
     }
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
@@ -798,21 +845,13 @@ __global__ void __launch_bounds__(64 * NW, 1) k_fused_wide(FusedArgs a,
     constexpr int TP = 16 * NW * NT;   // points per tile
     __shared__ uint4 wbuf[2 * WeightStage<MT, NW>::BUF];
     __shared__ float4 plane[32];
+    __shared__ float2 cols[24];
     __shared__ PtGeom geom[TP];        // per point of the tile, see make_geom
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int g = lane >> 4, n = lane & 15;
     const int wv = tid >> 6;
-    if (tid < 32) {
-        const int gg = tid >> 3, j = tid & 7;
-        if (gg == 0) {
-            plane[tid] = make_float4(4.f, 4.f, (float)j, 0.f);
-        } else {
-            const int G = 2 * (gg - 1) + (j >> 2), jj = j & 3;
-            plane[tid] = G < 5 ? make_float4((float)jj, (float)G, 8.f, 0.f)
-                               : make_float4(4.f, (float)jj, 8.f, 0.f);
-        }
-    }
+    init_tables(tid, plane, cols);
     WeightStage<MT, NW> ws;
     ws.buf = wbuf;
 #pragma unroll 1
@@ -852,18 +891,20 @@ __global__ void __launch_bounds__(64 * NW, 1) k_fused_wide(FusedArgs a,
             const float *b1 = vec + (size_t)k * 2 * WP;
             const float *b2 = b1 + WP;
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
+            for (int mt = 0; mt < MT; ++mt) {
+                const f4 bb = *reinterpret_cast<const f4 *>(b1 + 16 * mt + 4 * g);
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt)
-                    F[mt][nt] = z4;
+                    F[mt][nt] = bb;
+            }
 #pragma unroll 1
             for (int c = 0; c < 7; ++c) {
                 Pending pa[NT], pb[NT];
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) {
                     if (c < 6) {
-                        issue_column_half(cells, L, q[nt], 2 * c, g, pa[nt]);
-                        issue_column_half(cells, L, q[nt], 2 * c + 1, g, pb[nt]);
+                        issue_column_half(cells, L, q[nt], 2 * c, g, cols, pa[nt]);
+                        issue_column_half(cells, L, q[nt], 2 * c + 1, g, cols, pb[nt]);
                     } else {
                         issue_table_half(cells, L, q[nt], 0, g, plane, pa[nt]);
                         issue_table_half(cells, L, q[nt], 1, g, plane, pb[nt]);
@@ -882,7 +923,7 @@ __global__ void __launch_bounds__(64 * NW, 1) k_fused_wide(FusedArgs a,
                     B[nt] = pack8(lo, hi);
                 }
                 mfma_chunk_nt<MT, NT>(ws.chunk(), lane, B, F);
-                ws.next(tid);
+                ws.template next<0>(tid);
             }
             {
                 Pending pa[NT];
@@ -901,7 +942,7 @@ __global__ void __launch_bounds__(64 * NW, 1) k_fused_wide(FusedArgs a,
                     B[nt] = pack8(lo, (MT & 1) ? O[MT - 1][nt] : z4);
                 }
                 mfma_chunk_nt<MT, NT>(ws.chunk(), lane, B, F);
-                ws.next(tid);
+                ws.template next<0>(tid);
             }
             if (k > 0) {
 #pragma unroll
@@ -912,18 +953,17 @@ __global__ void __launch_bounds__(64 * NW, 1) k_fused_wide(FusedArgs a,
                     for (int nt = 0; nt < NT; ++nt)
                         B[nt] = pack8(O[2 * qq][nt], O[2 * qq + 1][nt]);
                     mfma_chunk_nt<MT, NT>(ws.chunk(), lane, B, F);
-                    ws.next(tid);
+                    ws.template next<0>(tid);
                 }
             }
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
-                const f4 bb = *reinterpret_cast<const f4 *>(b1 + 16 * mt + 4 * g);
                 const f4 cc = *reinterpret_cast<const f4 *>(b2 + 16 * mt + 4 * g);
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
-                        F[mt][nt][i] = fmaxf(F[mt][nt][i] + bb[i], 0.f);
+                        F[mt][nt][i] = fmaxf(F[mt][nt][i], 0.f);
                     O[mt][nt] += cc;
                 }
             }
@@ -936,7 +976,7 @@ __global__ void __launch_bounds__(64 * NW, 1) k_fused_wide(FusedArgs a,
                     B[nt] = pack8(F[2 * qq][nt],
                                   (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0][nt] : z4);
                 mfma_chunk_nt<MT, NT>(ws.chunk(), lane, B, O);
-                ws.next(tid);
+                ws.template next<0>(tid);
             }
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
@@ -1002,17 +1042,9 @@ __device__ __forceinline__ int column_sample(int c, int g, int j)
 __global__ void __launch_bounds__(256) k_gather_packed(FusedArgs a, float *__restrict__ z)
 {
     __shared__ float4 plane[32];
+    __shared__ float2 cols[24];
     const int tid = threadIdx.x, lane = tid & 63, g = lane >> 4, n = lane & 15;
-    if (tid < 32) {
-        const int gg = tid >> 3, j = tid & 7;
-        if (gg == 0) {
-            plane[tid] = make_float4(4.f, 4.f, (float)j, 0.f);
-        } else {
-            const int G = 2 * (gg - 1) + (j >> 2), jj = j & 3;
-            plane[tid] = G < 5 ? make_float4((float)jj, (float)G, 8.f, 0.f)
-                               : make_float4(4.f, (float)jj, 8.f, 0.f);
-        }
-    }
+    init_tables(tid, plane, cols);
     __syncthreads();
     const FusedCloud &cl = a.cl[0];
     const int64_t p = (int64_t)blockIdx.x * 64 + (tid >> 6) * 16 + n;
@@ -1028,7 +1060,7 @@ __global__ void __launch_bounds__(256) k_gather_packed(FusedArgs a, float *__res
         level_from_geom(L, make_geom(x, fr, cl.amin, valid), q);
         Pending pa;
         for (int h = 0; h < 12; ++h) {
-            issue_column_half(cells, L, q, h, g, pa);
+            issue_column_half(cells, L, q, h, g, cols, pa);
             for (int j = 0; j < 4; ++j) {
                 float v = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
                 if (in)
