@@ -277,7 +277,9 @@ __device__ __forceinline__ void vm_wait()
 
 template <int MT, int NW>
 struct WeightStage {
-    static constexpr int G = 2;
+    // chunks per buffer: two workgroups of four waves share a compute unit's LDS;
+    // an eight-wave workgroup has it alone and stages four chunks per barrier
+    static constexpr int G = NW == 8 ? 4 : 2;
     static constexpr int FR = MT * 64;
     static constexpr int T = 64 * NW;
     static constexpr int SLOT = FR;            // LDS entries per chunk
@@ -1109,9 +1111,9 @@ int chunk_count(int MT, int K, int H)
     return (8 + C2) + (K - 1) * (C1 + C2) + (H - 1) * C2;
 }
 
-// zeroed entries after the last chunk: the copies run up to two groups (2 x 2 chunks of
+// zeroed entries after the last chunk: the copies run up to two groups (2 x 4 chunks of
 // at most 16 x 64 entries) past the chunk being consumed
-constexpr size_t kFragPad = 4096;
+constexpr size_t kFragPad = 8192;
 
 // Tile partition of the clouds for tiles of `per` points; returns the tile count.
 int64_t assign_tiles(FusedArgs &a, int64_t per)
