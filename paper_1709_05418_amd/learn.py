@@ -103,8 +103,32 @@ def image_errors(img, ref):
     return l1, rmse
 
 
+def reference(ctx, cloud, params, light_dir, ray_o, ray_d, spp, seed, batch=256, log=None):
+    """Path-traced image of spp samples per pixel, rendered in batches of independent
+    streams (seed + 1 + b) whose means and variances are combined in FP64.
+    Returns (mean, variance of the mean)."""
+    import torch
+    mean = torch.zeros(ray_o.shape[0], dtype=torch.float64, device=ray_o.device)
+    var = torch.zeros_like(mean)
+    done = 0
+    b = 0
+    t0 = time.time()
+    while done < spp:
+        n = min(batch, spp - done)
+        m, v = ds.ds_render_mc(ctx.h, cloud.h, params, light_dir, ray_o, ray_d, n, seed + 1 + b)
+        w = n / (done + n)
+        mean = mean * (1 - w) + m * w
+        var = var * (1 - w) ** 2 + v * w * w
+        done += n
+        b += 1
+        if log:
+            torch.cuda.synchronize()
+            log(f"reference: {done}/{spp} samples per pixel ({time.time() - t0:.1f}s)")
+    return mean, var
+
+
 def judge(ctx, cloud, net, precision, params, light_dir, ray_o, ray_d, spp, ref_spp, seed,
-          fallback_spp=0):
+          fallback_spp=0, log=None):
     """Network image vs path-traced reference, and the direct-only image vs the same."""
     t0 = time.time()
     img, var, direct, nfb = ds.ds_render_rpnn(ctx.h, cloud.h, net.h, precision, params, light_dir,
@@ -114,8 +138,7 @@ def judge(ctx, cloud, net, precision, params, light_dir, ray_o, ray_d, spp, ref_
     torch.cuda.synchronize()
     t_net = time.time() - t0
     t0 = time.time()
-    ref, ref_var = ds.ds_render_mc(ctx.h, cloud.h, params, light_dir, ray_o, ray_d, ref_spp,
-                                   seed + 1)
+    ref, ref_var = reference(ctx, cloud, params, light_dir, ray_o, ray_d, ref_spp, seed, log=log)
     torch.cuda.synchronize()
     t_ref = time.time() - t0
     l1, rmse = image_errors(img, ref)
@@ -186,6 +209,8 @@ def main(argv=None):
     ap.add_argument("--fallback-spp", type=int, default=64)
     ap.add_argument("--seed", type=int, default=1000)
     ap.add_argument("--save-theta", default=None)
+    ap.add_argument("--load-theta", default=None,
+                    help="judge a network saved by --save-theta instead of training one")
     args = ap.parse_args(argv)
     log = lambda *a: print("[learn]", *a, flush=True)
     dev = "cuda"
@@ -194,6 +219,11 @@ def main(argv=None):
     K, W = args.K, args.W
     L = int(math.ceil(math.log2(args.n))) + 1
     per = args.records // args.clouds
+    if args.load_theta:
+        net = ds.Net(ctx, K, W, 3)
+        net.set_params(np.load(args.load_theta))
+        log(f"network loaded from {args.load_theta}")
+        return judge_only(args, ctx, net, prm, log)
     D = ds.STENCIL_N * K + 1
     z = torch.empty((per * args.clouds, D), dtype=torch.float32, device=dev)
     t = torch.empty(per * args.clouds, dtype=torch.float32, device=dev)
@@ -254,7 +284,7 @@ def main(argv=None):
     co, cd = camera(args.width, args.height, crop=(cx0, cy0, args.crop, args.crop), seed=2)
     for name, prec in (("bf16", ds.DS_PREC_BF16), ("fp32", ds.DS_PREC_F32)):
         j = judge(ctx, jc, net, prec, prm, light, co, cd, args.crop_spp, args.ref_spp, 11,
-                  args.fallback_spp)
+                  args.fallback_spp, log=log)
         for k in ("rel_l1", "rmse", "rel_l1_direct_only", "rmse_direct_only", "ref_noise_rel",
                   "seconds_network", "seconds_reference", "fallback_samples"):
             summary[f"crop_{k}_{name}"] = j[k]
@@ -271,6 +301,53 @@ def main(argv=None):
                     "crop": args.crop, "crop_spp": args.crop_spp, "ref_spp": args.ref_spp})
     print(json.dumps(summary), flush=True)
     ds.ds_adam_destroy(opt)
+    net.close()
+    jc.close()
+    ctx.close()
+
+
+def judge_only(args, ctx, net, prm, log):
+    """The judge part of main() for a given network: a full frame and the crop."""
+    import json
+    import torch
+    from paper_1709_05418_amd import synth
+    K = net.K
+    t0 = time.time()
+    d = synth.cloud_density(args.judge_n, args.seed + 5000, worley=0.3, device="cuda",
+                            dtype=torch.bfloat16)
+    amin, h0 = synth.unit_box(args.judge_n)
+    Lj = min(16, int(math.ceil(math.log2(args.judge_n))) + 1)
+    jc = ds.Cloud(ctx, d, float(args.n), amin, h0, Lj, K)
+    del d
+    log(f"judge cloud {args.judge_n}^3 built ({time.time() - t0:.1f}s)")
+    light = synth.table1_lights()["side"]
+    o, dd = camera(args.width, args.height, seed=1)
+    summary = {}
+    torch.cuda.synchronize()
+    tf = time.time()
+    img, _, direct, nfb = ds.ds_render_rpnn(ctx.h, jc.h, net.h, ds.DS_PREC_BF16, prm, light, o, dd,
+                                            args.frame_spp, 5, args.fallback_spp,
+                                            count_fallback=True)
+    torch.cuda.synchronize()
+    summary["frame_ms_bf16"] = (time.time() - tf) * 1e3
+    log(f"{args.width}x{args.height} frame bf16, {args.frame_spp} spp: "
+        f"{summary['frame_ms_bf16']:.1f} ms, fallback samples {nfb}")
+    cx0 = (args.width - args.crop) // 2
+    cy0 = (args.height - args.crop) // 2
+    co, cd = camera(args.width, args.height, crop=(cx0, cy0, args.crop, args.crop), seed=2)
+    j = judge(ctx, jc, net, ds.DS_PREC_BF16, prm, light, co, cd, args.crop_spp, args.ref_spp, 11,
+              args.fallback_spp, log=log)
+    for k in ("rel_l1", "rmse", "rel_l1_direct_only", "rmse_direct_only", "ref_noise_rel",
+              "seconds_network", "seconds_reference", "fallback_samples"):
+        summary[f"crop_{k}_bf16"] = j[k]
+    log(f"crop {args.crop}^2 bf16: rel L1 {j['rel_l1']:.4f} (direct only "
+        f"{j['rel_l1_direct_only']:.4f}), RMSE {j['rmse']:.5f}; reference noise "
+        f"{j['ref_noise_rel']:.4f}; network {j['seconds_network']:.2f}s vs reference "
+        f"{j['seconds_reference']:.2f}s ({args.ref_spp} spp)")
+    summary.update({"judge_n": args.judge_n, "frame": [args.width, args.height],
+                    "crop": args.crop, "crop_spp": args.crop_spp, "ref_spp": args.ref_spp,
+                    "theta": args.load_theta})
+    print(json.dumps(summary), flush=True)
     net.close()
     jc.close()
     ctx.close()
