@@ -51,10 +51,13 @@ typedef int32_t ds_status;
 
 typedef enum { DS_F32 = 0, DS_BF16 = 1 } ds_dtype;
 
-/* Arithmetic of the network layers.  DS_PREC_F32: plain form, every layer in FP32
- * (descriptor materialised, one kernel per layer).  DS_PREC_BF16 / DS_PREC_FP8:
- * fused kernel, layer inputs and weights in BF16 or FP8 E4M3 (OCP, per-layer
- * scales) on the matrix cores, accumulation, biases and residual sums in FP32. */
+/* Arithmetic of the network layers (Sec. 4.3).  DS_PREC_F32: plain form, every layer
+ * in FP32 (descriptor materialised, one kernel per layer).  DS_PREC_BF16: fused
+ * kernel, every layer's inputs and weights in BF16 on the matrix cores.  DS_PREC_FP8:
+ * fused kernel with the W x W layers (W1, W2 of every block and the dense trailing
+ * layers) in FP8 E4M3 (OCP) with power-of-two per-layer scales and the descriptor
+ * layers V^k in BF16 (see ds_net_quantize).  Accumulation, biases and residual sums
+ * are FP32 in every form. */
 typedef enum { DS_PREC_F32 = 0, DS_PREC_BF16 = 1, DS_PREC_FP8 = 2 } ds_precision;
 
 /* Per-point flag bits written by ds_gather / ds_predict. */
@@ -174,7 +177,7 @@ ds_status ds_forward(ds_ctx *ctx, const ds_net *net, const float *z, int64_t P, 
  * DS_PREC_BF16 / DS_PREC_FP8 run the fused kernel (descriptor stays on chip).
  * out (device, P floats), pre_out (device, P floats, may be NULL: final
  * pre-activation) and flags (device, P bytes, may be NULL).  Invalid points get
- * out = pre_out = 0.  FP8 needs ds_net_quantize_fp8 first (else DS_ERR_STATE). */
+ * out = pre_out = 0.  FP8 needs ds_net_quantize first (else DS_ERR_STATE). */
 ds_status ds_predict(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
                      ds_precision precision, const float *pos, const float *view_dir,
                      const float *light_dir, int64_t P, float *out, float *pre_out,
@@ -211,12 +214,13 @@ ds_status ds_batch_get_config(const ds_batch *batch, int32_t *kernel, int32_t *w
                               int32_t *grid, float *ms);
 /* Prediction for all clouds of the plan: as ds_predict per cloud, on the
  * concatenated arrays (device, offsets[n] points).  DS_PREC_BF16 (and DS_PREC_FP8
- * once quantised) runs one launch; DS_PREC_F32 runs the plain form per cloud. */
+ * once quantised, register kernel only: DS_ERR_UNSUPPORTED for the other kinds) runs
+ * one launch; DS_PREC_F32 runs the plain form per cloud. */
 ds_status ds_batch_predict(ds_batch *batch, ds_precision precision, const float *pos,
                            const float *view_dir, const float *light_dir, float *out,
                            float *pre_out, uint8_t *flags);
 /* Times every available variant (kernel x waves x grid in {one per tile, 1, 2, 4
- * workgroups per compute unit}) on these arrays, `reps` launches each after one
+ * workgroups per compute unit}; for DS_PREC_FP8 the register kernel's) on these arrays, `reps` launches each after one
  * warm-up, keeps the fastest and drops a captured graph.  Synchronises; writes
  * out.  Results depend on the arrays' contents only through timing. */
 ds_status ds_batch_autotune(ds_batch *batch, ds_precision precision, const float *pos,
@@ -229,6 +233,31 @@ ds_status ds_batch_capture(ds_batch *batch, ds_precision precision, const float 
                            const float *view_dir, const float *light_dir, float *out,
                            float *pre_out, uint8_t *flags);
 ds_status ds_batch_replay(ds_batch *batch);
+
+/* ---------------------------------------------------------------- FP8 form */
+/* Builds the network's FP8 form from its current parameters (precision must be
+ * DS_PREC_FP8).  Calibration: the P_cal points (device, as for ds_predict) of `cloud`
+ * run through the FP32 plain form, recording the largest activation of every layer.
+ * Each scaled tensor gets the power of two 2^e, e the largest integer with
+ * amax * 2^e <= 448 (clamped to -32..32; 0 for an all-zero tensor): weights per matrix,
+ * activations per layer (the first layer of every block, one scale for the residual
+ * stream, the dense trailing layers).  Weights are encoded as E4M3(w * 2^e), round to
+ * nearest even, saturating; activations the same way inside the kernel, saturating at
+ * 448 (inputs beyond the calibrated range are clamped).  The descriptor layers V^k stay
+ * BF16.  Synchronises the stream; a later parameter change (ds_net_set_params,
+ * ds_train_step) drops the FP8 form until the next call. */
+ds_status ds_net_quantize(ds_ctx *ctx, ds_net *net, const ds_cloud *cloud,
+                          ds_precision precision, const float *pos, const float *view_dir,
+                          const float *light_dir, int64_t P_cal);
+/* The exponents e of the FP8 form (host array of exactly 3K + 2H - 2 entries): the
+ * activation scales (first layer of blocks 1..K, residual stream, dense trailing layers
+ * 1..H-1), then the weight scales (W1 of blocks 2..K, W2 of blocks 1..K, dense trailing
+ * layers 1..H-1).  DS_ERR_STATE without an FP8 form. */
+ds_status ds_net_fp8_scales(const ds_net *net, int32_t *log2_scales, int32_t n);
+/* The library's host E4M3 encoder, as used for the weights: codes[i] = E4M3(x[i] * 2^e)
+ * (OCP E4M3: bias 7, no infinities, 0x7F / 0xFF NaN; round to nearest even;
+ * magnitudes from 464 up saturate to 448).  Host arrays; e in -64..64. */
+ds_status ds_fp8_e4m3_encode(const float *x, int64_t n, int32_t log2_scale, uint8_t *codes);
 
 /* ---------------------------------------------------------------- training (Sec. 5.2) */
 /* Adam (Kingma and Ba; the paper uses the default learning rate and decay rates:

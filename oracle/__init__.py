@@ -23,6 +23,8 @@ What each part follows in the paper and what pins it (tests/test_oracle_*.py):
   first_hits      Sec. 4.4 camera sample: first collision   homogeneous box: hit fraction
                   and direct single scattering              1 - exp(-sigma L), direct term against
                                                             albedo p exp(-sigma s) E
+  e4m3_encode     OCP 8-bit floating point, E4M3 format     torch.float8_e4m3fn cast, hand values,
+                  (round to nearest even, saturating)       decode/encode round trip of every code
 """
 from __future__ import annotations
 
@@ -320,3 +322,28 @@ def render_pixels(grid: Grid, ray_o, ray_d, light_dir, albedo=0.999, g=0.85, irr
                                    light_mode, max_interactions, _p(ld), _p(o), _p(d), N, spp,
                                    seed, _p(mean), _p(var)), "render_pixels")
     return mean, var
+
+
+# ----------------------------------------------------------------------------- FP8 E4M3
+def e4m3_value(code: int) -> float:
+    """Value of a finite OCP E4M3 code 0..126 (sign bit clear): exponent bias 7, three
+    mantissa bits, subnormals m * 2^-9; 0x7F is NaN and there are no infinities."""
+    e, m = code >> 3, code & 7
+    return m * 2.0 ** -9 if e == 0 else (1.0 + m / 8.0) * 2.0 ** (e - 7)
+
+
+def e4m3_encode(x) -> np.ndarray:
+    """OCP E4M3 codes of x: the nearest of the 127 finite magnitudes, ties to the even
+    code (even mantissa), magnitudes above 448 saturated to 448, NaN to 0x7F, the sign in
+    bit 7.  Written as a search over the value table so that it can be read against the
+    format's definition."""
+    x = np.asarray(x, dtype=np.float64)
+    vals = np.array([e4m3_value(c) for c in range(127)])
+    a = np.minimum(np.abs(x), vals[-1])
+    hi = np.clip(np.searchsorted(vals, a, side="left"), 0, 126)
+    lo = np.clip(hi - 1, 0, 126)
+    dlo, dhi = a - vals[lo], vals[hi] - a
+    code = np.where(dhi < dlo, hi, np.where(dlo < dhi, lo, np.where(hi % 2 == 0, hi, lo)))
+    code = code.astype(np.uint8) | (np.signbit(x).astype(np.uint8) << 7)
+    return np.where(np.isnan(x), np.uint8(0x7F), code).astype(np.uint8)
+

@@ -73,6 +73,9 @@ def lib():
         "ds_loss_grad": (S, [P, P, P, I, P, P]),
         "ds_train_step": (S, [P, P, P, P, I, P]),
         "ds_net_set_train_precision": (S, [P, I]),
+        "ds_net_quantize": (S, [P, P, P, I, P, P, P, I64]),
+        "ds_net_fp8_scales": (S, [P, P, S]),
+        "ds_fp8_e4m3_encode": (S, [P, I64, S, P]),
         "ds_cloud_majorant": (S, [P, P]),
         "ds_trace_li": (S, [P, P, P, P, P, P, I64, I, C.c_uint64, P, P]),
         "ds_sample_records": (S, [P, P, I64, C.c_uint64, P, P, P, P]),
@@ -290,6 +293,32 @@ def ds_predict(ctx, cloud, net, precision, pos, view_dir, light_dir, out=None, p
 
 def ds_net_set_train_precision(net, precision):
     _check(lib().ds_net_set_train_precision(net, int(precision)))
+
+
+def ds_net_quantize(ctx, net, cloud, precision, pos, view_dir, light_dir):
+    """Build the FP8 form, calibrated on these points of `cloud` (device tensors)."""
+    P = pos.shape[0]
+    _check(lib().ds_net_quantize(ctx, net, cloud, int(precision), _pts(pos), _pts(view_dir, P),
+                                 _pts(light_dir, P), P))
+
+
+def ds_net_fp8_scales(net, K: int, H: int):
+    """log2 units of the FP8 form's activations, then its matrix exponents (numpy int32)."""
+    import numpy as np
+    n = 3 * K + 2 * H - 2
+    out = np.zeros(n, dtype=np.int32)
+    _check(lib().ds_net_fp8_scales(net, out.ctypes.data_as(C.c_void_p), n))
+    return out
+
+
+def ds_fp8_e4m3_encode(x, log2_scale: int = 0):
+    """The library's host E4M3 encoder on a float32 numpy array (codes as uint8)."""
+    import numpy as np
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    codes = np.zeros(x.shape, dtype=np.uint8)
+    _check(lib().ds_fp8_e4m3_encode(x.ctypes.data_as(C.c_void_p), x.size, int(log2_scale),
+                                    codes.ctypes.data_as(C.c_void_p)))
+    return codes
 
 
 def ds_adam_create(net, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

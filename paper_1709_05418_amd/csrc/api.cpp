@@ -164,8 +164,11 @@ void gather_args(const ds_cloud *c, const float *pos, const float *view, const f
 constexpr int64_t kChunk = 65536;  // points per plain-form chunk
 
 // Plain FP32 network over `rows` descriptor rows (ldz = 225K + 1).
+// amax (may be NULL): running maxima of |activation| per layer, as float bits: the first
+// layer of every block (K), the residual stream over all blocks (1), the dense trailing
+// layers (H - 1).
 ds_status forward_plain(ds_ctx *ctx, const ds_net *net, const float *z, int64_t rows, float *out,
-                        float *pre, float *O, float *F, float *T)
+                        float *pre, float *O, float *F, float *T, unsigned *amax = nullptr)
 {
     const int K = net->K, W = net->W, H = net->H;
     const int D = kStencil * K + 1;
@@ -199,6 +202,8 @@ ds_status forward_plain(ds_ctx *ctx, const ds_net *net, const float *z, int64_t 
             g1.ldc = W;
             g1.relu = 1;
             ds_status st = gemm_f32(ctx->stream, g1);
+            if (!st && amax)
+                st = amax_into(ctx->stream, F, (int64_t)M * W, amax + k);
             if (st)
                 return st;
             GemmArgs g2 = {};
@@ -218,6 +223,8 @@ ds_status forward_plain(ds_ctx *ctx, const ds_net *net, const float *z, int64_t 
             g2.ldc = W;
             g2.relu = 1;
             st = gemm_f32(ctx->stream, g2);
+            if (!st && amax)
+                st = amax_into(ctx->stream, O, (int64_t)M * W, amax + K);
             if (st)
                 return st;
         }
@@ -242,6 +249,8 @@ ds_status forward_plain(ds_ctx *ctx, const ds_net *net, const float *z, int64_t 
             }
             g.relu = 1;
             ds_status st = gemm_f32(ctx->stream, g);
+            if (!st && amax && !last)
+                st = amax_into(ctx->stream, bufs[m & 1], (int64_t)M * W, amax + K + 1 + m);
             if (st)
                 return st;
             in = bufs[m & 1];
@@ -796,7 +805,7 @@ ds_status ds_net_set_params(ds_net *net, const float *theta_host, int64_t n)
                  "ds_net_set_params: parameter %lld is not finite", (long long)i);
     DS_HIP(hipStreamSynchronize(net->ctx->stream));
     DS_HIP(hipMemcpy(net->theta, theta_host, sizeof(float) * n, hipMemcpyHostToDevice));
-    net->has_fp8 = false;
+    net->fp8_ready = false;
     if (fused_tiles(net->W) > 0) {
         ds_status st = fused_pack_bf16(net->ctx->stream, net);
         if (st)
@@ -827,6 +836,8 @@ ds_status ds_net_destroy(ds_net *net)
     (void)hipFree(net->vec);
     (void)hipFree(net->fmap);
     (void)hipFree(net->vmap);
+    (void)hipFree(net->frag_fp8);
+    (void)hipFree(net->vec8);
     (void)hipFree(net->tws);
     delete net;
     return DS_OK;
@@ -884,6 +895,42 @@ ds_status ds_forward(ds_ctx *ctx, const ds_net *net, const float *z, int64_t P, 
                          O + 2 * rows * net->W);
 }
 
+// The plain FP32 form in chunks of kChunk points: descriptor rows to HBM, then one GEMM
+// per layer (amax: see forward_plain).
+static ds_status predict_plain(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
+                               const float *pos, const float *view_dir, const float *light_dir,
+                               int64_t P, float *out, float *pre_out, uint8_t *flags,
+                               unsigned *amax)
+{
+    const int D = kStencil * net->K + 1;
+    const int64_t rows = P < kChunk ? P : kChunk;
+    size_t need = sizeof(float) * (size_t)rows * ((size_t)D + 3 * net->W) + (size_t)rows;
+    ds_status st = ensure_ws(ctx, need);
+    if (st)
+        return st;
+    float *z = static_cast<float *>(ctx->ws);
+    float *O = z + rows * D;
+    uint8_t *fl_ws = reinterpret_cast<uint8_t *>(O + 3 * rows * net->W);
+    GatherArgs a;
+    gather_args(cloud, pos, view_dir, light_dir, P, a);
+    for (int64_t p0 = 0; p0 < P; p0 += kChunk) {
+        int64_t np = (P - p0) < kChunk ? (P - p0) : kChunk;
+        // the gather writes flags at absolute point indices
+        uint8_t *fl = flags ? flags : fl_ws - p0;
+        st = gather_plain(ctx->stream, a, p0, np, DS_F32, z, D, fl);
+        if (st)
+            return st;
+        st = forward_plain(ctx, net, z, np, out + p0, pre_out ? pre_out + p0 : nullptr, O,
+                           O + rows * net->W, O + 2 * rows * net->W, amax);
+        if (st)
+            return st;
+        st = mask_invalid(ctx->stream, fl + p0, np, out + p0, pre_out ? pre_out + p0 : nullptr);
+        if (st)
+            return st;
+    }
+    return DS_OK;
+}
+
 ds_status ds_predict(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
                      ds_precision precision, const float *pos, const float *view_dir,
                      const float *light_dir, int64_t P, float *out, float *pre_out,
@@ -897,45 +944,14 @@ ds_status ds_predict(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
         return DS_OK;
     DS_CHECK(pos && view_dir && light_dir && out, DS_ERR_INVALID_ARG,
              "ds_predict: NULL device pointer");
-    if (precision == DS_PREC_F32) {
-        const int D = kStencil * net->K + 1;
-        const int64_t rows = P < kChunk ? P : kChunk;
-        size_t need = sizeof(float) * (size_t)rows * ((size_t)D + 3 * net->W) + (size_t)rows;
-        ds_status st = ensure_ws(ctx, need);
-        if (st)
-            return st;
-        float *z = static_cast<float *>(ctx->ws);
-        float *O = z + rows * D;
-        uint8_t *fl_ws = reinterpret_cast<uint8_t *>(O + 3 * rows * net->W);
-        GatherArgs a;
-        gather_args(cloud, pos, view_dir, light_dir, P, a);
-        for (int64_t p0 = 0; p0 < P; p0 += kChunk) {
-            int64_t np = (P - p0) < kChunk ? (P - p0) : kChunk;
-            // the gather writes flags at absolute point indices
-            uint8_t *fl = flags ? flags : fl_ws - p0;
-            st = gather_plain(ctx->stream, a, p0, np, DS_F32, z, D, fl);
-            if (st)
-                return st;
-            st = forward_plain(ctx, net, z, np, out + p0, pre_out ? pre_out + p0 : nullptr, O,
-                               O + rows * net->W, O + 2 * rows * net->W);
-            if (st)
-                return st;
-            st = mask_invalid(ctx->stream, fl + p0, np, out + p0, pre_out ? pre_out + p0 : nullptr);
-            if (st)
-                return st;
-        }
-        return DS_OK;
-    }
-    if (precision == DS_PREC_BF16) {
-        DS_CHECK(net->frag_bf16, DS_ERR_STATE, "ds_predict: network parameters were never set");
+    if (precision == DS_PREC_F32)
+        return predict_plain(ctx, cloud, net, pos, view_dir, light_dir, P, out, pre_out, flags,
+                             nullptr);
+    if (precision == DS_PREC_BF16 || precision == DS_PREC_FP8) {
         FusedArgs a = {};
         fused_args(pos, view_dir, light_dir, out, pre_out, flags, net->K, net->W, net->H, a);
         add_cloud(a, cloud, 0, P);
-        return fused_predict_bf16(ctx->stream, net, a, kDefaultVariant);
-    }
-    if (precision == DS_PREC_FP8) {
-        set_error("ds_predict: FP8 weights are not available for this network");
-        return net->has_fp8 ? DS_ERR_UNSUPPORTED : DS_ERR_STATE;
+        return fused_predict(ctx->stream, net, a, kDefaultVariant, precision);
     }
     set_error("ds_predict: unknown precision %d", (int)precision);
     return DS_ERR_INVALID_ARG;
@@ -962,12 +978,11 @@ static ds_status batch_fused(ds_batch *b, hipStream_t s, ds_precision prec, cons
                              const float *view, const float *light, float *out, float *pre,
                              uint8_t *flags, const FusedVariant &v)
 {
-    DS_CHECK(prec == DS_PREC_BF16, prec == DS_PREC_FP8 ? DS_ERR_STATE : DS_ERR_INVALID_ARG,
-             "batched launch: precision %d is not available for this network", (int)prec);
-    DS_CHECK(b->net->frag_bf16, DS_ERR_STATE, "batched launch: network parameters never set");
+    DS_CHECK(prec == DS_PREC_BF16 || prec == DS_PREC_FP8, DS_ERR_INVALID_ARG,
+             "batched launch: precision %d is not a fused precision", (int)prec);
     FusedArgs a = {};
     batch_args(b, pos, view, light, out, pre, flags, a);
-    return fused_predict_bf16(s, b->net, a, v);
+    return fused_predict(s, b->net, a, v, prec);
 }
 
 ds_status ds_batch_create(ds_ctx *ctx, const ds_net *net, int n_clouds,
@@ -1099,7 +1114,8 @@ ds_status ds_batch_autotune(ds_batch *b, ds_precision precision, const float *po
         for (int waves = 4; waves <= 8 && !st; waves += 4)
             for (int gi = 0; gi < 4 && !st; ++gi) {
                 FusedVariant v = {kind, waves, grids[gi]};
-                if (!fused_variant_ok(b->net, v))
+                if (!(precision == DS_PREC_FP8 ? fused_variant_ok_fp8(b->net, v)
+                                               : fused_variant_ok(b->net, v)))
                     continue;
                 st = batch_fused(b, s, precision, pos, view_dir, light_dir, out, nullptr, nullptr,
                                  v);
@@ -1144,10 +1160,11 @@ ds_status ds_batch_capture(ds_batch *b, ds_precision precision, const float *pos
              "ds_batch_capture: the plain FP32 form is not captured");
     DS_CHECK(b->offsets[b->n] == 0 || (pos && view_dir && light_dir && out), DS_ERR_INVALID_ARG,
              "ds_batch_capture: NULL device pointer");
-    DS_CHECK(precision == DS_PREC_BF16, precision == DS_PREC_FP8 ? DS_ERR_STATE
-                                                                 : DS_ERR_INVALID_ARG,
+    DS_CHECK(precision == DS_PREC_BF16 || precision == DS_PREC_FP8, DS_ERR_INVALID_ARG,
              "ds_batch_capture: precision %d is not available", (int)precision);
-    DS_CHECK(b->net->frag_bf16, DS_ERR_STATE, "ds_batch_capture: network parameters never set");
+    DS_CHECK(precision == DS_PREC_FP8 ? b->net->fp8_ready : b->net->frag_bf16 != nullptr,
+             DS_ERR_STATE, "ds_batch_capture: the network has no %s form",
+             precision == DS_PREC_FP8 ? "FP8 (quantize it first)" : "BF16 (set its parameters)");
     DS_HIP(hipSetDevice(b->ctx->device));
     batch_drop_graph(b);
     if (!b->cap_stream)
@@ -1194,6 +1211,91 @@ ds_status ds_net_set_train_precision(ds_net *net, ds_precision precision)
              precision == DS_PREC_FP8 ? DS_ERR_UNSUPPORTED : DS_ERR_INVALID_ARG,
              "ds_net_set_train_precision: training runs in FP32 or BF16");
     net->train_prec = precision;
+    return DS_OK;
+}
+
+// ---------------------------------------------------------------- FP8 form
+ds_status ds_net_quantize(ds_ctx *ctx, ds_net *net, const ds_cloud *cloud, ds_precision precision,
+                          const float *pos, const float *view_dir, const float *light_dir,
+                          int64_t n_calib)
+{
+    DS_CHECK(ctx && net && cloud, DS_ERR_INVALID_ARG, "ds_net_quantize: NULL argument");
+    DS_CHECK(precision == DS_PREC_FP8, DS_ERR_INVALID_ARG,
+             "ds_net_quantize: only DS_PREC_FP8 is built by this call (the BF16 form follows "
+             "every parameter change)");
+    DS_CHECK(fused_tiles(net->W) > 0, DS_ERR_UNSUPPORTED,
+             "ds_net_quantize: width %d is not supported by the fused kernel", net->W);
+    DS_CHECK(net->frag_bf16, DS_ERR_STATE, "ds_net_quantize: network parameters were never set");
+    DS_CHECK(cloud->K == net->K, DS_ERR_INVALID_ARG,
+             "ds_net_quantize: cloud has %d stencil levels, the network %d", cloud->K, net->K);
+    DS_CHECK(n_calib >= 1 && n_calib <= ((int64_t)1 << 31), DS_ERR_INVALID_ARG,
+             "ds_net_quantize: calibration count %lld outside 1..2^31", (long long)n_calib);
+    DS_CHECK(pos && view_dir && light_dir, DS_ERR_INVALID_ARG,
+             "ds_net_quantize: NULL device pointer");
+    DS_HIP(hipSetDevice(ctx->device));
+    const int K = net->K, H = net->H;
+    const int na = K + H;  // activation maxima, see forward_plain
+    // calibration: the FP32 plain form, recording the largest activation of every layer
+    unsigned *amax = nullptr;
+    float *out = nullptr;
+    DS_CHECK(hipMalloc(&amax, sizeof(unsigned) * na) == hipSuccess, DS_ERR_OOM,
+             "ds_net_quantize: out of device memory");
+    ds_status st = DS_OK;
+    if (hipMalloc(&out, sizeof(float) * (size_t)n_calib) != hipSuccess) {
+        st = DS_ERR_OOM;
+        set_error("ds_net_quantize: out of device memory");
+    }
+    if (!st) {
+        hipError_t e = hipMemsetAsync(amax, 0, sizeof(unsigned) * na, ctx->stream);
+        if (e != hipSuccess)
+            st = hip_fail(e, "ds_net_quantize: clear");
+    }
+    if (!st)
+        st = predict_plain(ctx, cloud, net, pos, view_dir, light_dir, n_calib, out, nullptr,
+                           nullptr, amax);
+    std::vector<unsigned> bits(na);
+    std::vector<float> theta((size_t)net->n_params);
+    if (!st) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e == hipSuccess)
+            e = hipMemcpy(bits.data(), amax, sizeof(unsigned) * na, hipMemcpyDeviceToHost);
+        if (e == hipSuccess)
+            e = hipMemcpy(theta.data(), net->theta, sizeof(float) * theta.size(),
+                          hipMemcpyDeviceToHost);
+        if (e != hipSuccess)
+            st = hip_fail(e, "ds_net_quantize");
+    }
+    (void)hipFree(amax);
+    (void)hipFree(out);
+    if (st)
+        return st;
+    std::vector<float> act(na);
+    for (int i = 0; i < na; ++i)
+        memcpy(&act[i], &bits[i], 4);
+    return fused_quantize_fp8(net, theta.data(), act.data());
+}
+
+ds_status ds_net_fp8_scales(const ds_net *net, int32_t *log2_scales, int32_t n)
+{
+    DS_CHECK(net && log2_scales, DS_ERR_INVALID_ARG, "ds_net_fp8_scales: NULL argument");
+    DS_CHECK(net->fp8_ready, DS_ERR_STATE, "ds_net_fp8_scales: the network has no FP8 form");
+    DS_CHECK(n == fp8_exp_count(net->K, net->H), DS_ERR_INVALID_ARG,
+             "ds_net_fp8_scales: %d entries given, %d expected", n,
+             fp8_exp_count(net->K, net->H));
+    memcpy(log2_scales, net->fp8_exps.data(), sizeof(int32_t) * n);
+    return DS_OK;
+}
+
+ds_status ds_fp8_e4m3_encode(const float *x, int64_t n, int32_t log2_scale, uint8_t *codes)
+{
+    DS_CHECK(n >= 0, DS_ERR_INVALID_ARG, "ds_fp8_e4m3_encode: negative count");
+    if (n == 0)
+        return DS_OK;
+    DS_CHECK(x && codes, DS_ERR_INVALID_ARG, "ds_fp8_e4m3_encode: NULL argument");
+    DS_CHECK(log2_scale >= -64 && log2_scale <= 64, DS_ERR_INVALID_ARG,
+             "ds_fp8_e4m3_encode: scale exponent %d outside -64..64", log2_scale);
+    for (int64_t i = 0; i < n; ++i)
+        codes[i] = e4m3_encode((float)ldexp((double)x[i], log2_scale));
     return DS_OK;
 }
 
@@ -1284,7 +1386,7 @@ ds_status ds_train_step(ds_net *net, ds_adam *opt, const float *z, const float *
                      opt->lr, opt->b1, opt->b2, opt->eps, (float)c1, (float)c2);
     if (st)
         return st;
-    net->has_fp8 = false;
+    net->fp8_ready = false;
     if (fused_tiles(net->W) > 0)
         return fused_pack_bf16(net->ctx->stream, net);
     return DS_OK;

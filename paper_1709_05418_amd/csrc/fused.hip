@@ -30,6 +30,7 @@
 // Densities come from a corner-packed FP16 copy of the mip level (the 8 corners
 // of a cell in one 16-byte load) addressed in cell coordinates shifted by one and
 // clamped to [0, n+1], which reproduces zero outside the grid.
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -48,6 +49,20 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ f4 mfma_bf16(const uint4 &a, const bf16x8 &b, const f4 &c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), b, c, 0, 0, 0);
+}
+
+// 32 E4M3 bytes: one lane's operand of the 16x16x128 FP8 MFMA
+typedef int fp8x32 __attribute__((ext_vector_type(8)));
+
+// FP8 E4M3 x E4M3 over 128 inputs, FP32 accumulation, no operand scales (constant
+// zero scale arguments select the unscaled v_mfma_f32_16x16x128_f8f6f4; the scaled
+// form with register scales makes the register allocator spill this kernel's
+// accumulators).  Operand layout: lane 16 g + r holds row r of A at inputs (g, byte
+// b), lane 16 g + n column n of B at the same (g, b); the pairing of (g, b) is all the
+// packing relies on.
+__device__ __forceinline__ f4 mfma_fp8(const fp8x32 &a, const fp8x32 &b, const f4 &c)
+{
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, c, 0, 0, 0, 0, 0, 0);
 }
 
 // Per point and level: cell coordinate (shifted by +1) of lattice point (0,0,0)
@@ -356,6 +371,71 @@ __device__ __forceinline__ void mfma_chunk(const uint4 *w, int lane, const bf16x
         acc[mt] = mfma_bf16(w[mt * 64 + lane], B, acc[mt]);
 }
 
+// B operand of FP8 chunk Q of a W-wide layer: tiles 8Q..8Q+7 of the input in
+// accumulator layout, dword d holding tile 8Q + d's four features of this lane.  The
+// hardware conversion rounds to nearest even but does not saturate (>= 464 gives
+// NaN), so inputs that may exceed 448 are clamped first.
+template <int MT, bool CLAMP>
+__device__ __forceinline__ fp8x32 pack_fp8(const f4 (&x)[MT], int Q)
+{
+    fp8x32 r;
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        const int t = 8 * Q + d;
+        if (t < MT) {
+            f4 v = x[t < MT ? t : 0];
+            if (CLAMP) {  // inputs are ReLU outputs, >= 0
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    v[i] = __builtin_amdgcn_fmed3f(v[i], 0.f, 448.f);
+            }
+            int w = __builtin_amdgcn_cvt_pk_fp8_f32(v[0], v[1], 0, false);
+            r[d] = __builtin_amdgcn_cvt_pk_fp8_f32(v[2], v[3], w, true);
+        } else {
+            r[d] = 0;
+        }
+    }
+    return r;
+}
+
+// One FP8 chunk: its 32-byte A fragments are split over two consecutive staging
+// slots (bytes 0..15 of every lane entry in the first, 16..31 in the second).
+template <int MT>
+__device__ __forceinline__ void mfma8_chunk(const uint4 *w, int lane, const fp8x32 &B,
+                                            f4 (&acc)[MT])
+{
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const uint4 lo = w[mt * 64 + lane], hi = w[(MT + mt) * 64 + lane];
+        const fp8x32 A = {(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
+                          (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
+        acc[mt] = mfma_fp8(A, B, acc[mt]);
+    }
+    // each A operand is eight registers: interleave two fragment reads (LDS) with one
+    // MFMA instead of letting the scheduler issue every read first
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+}
+
+// Consume one FP8 chunk (two staging slots) of a W-wide layer.
+template <int MT, int NW, bool CLAMP>
+__device__ __forceinline__ void fp8_layer(WeightStage<MT, NW> &ws, int tid, int lane,
+                                          const f4 (&in)[MT], f4 (&acc)[MT])
+{
+#pragma unroll
+    for (int Q = 0; Q < (MT + 7) / 8; ++Q) {
+        ws.fetch(tid);
+        mfma8_chunk<MT>(ws.chunk(), lane, pack_fp8<MT, CLAMP>(in, Q), acc);
+        ws.template next<0>(tid);
+        ws.template next<0>(tid);
+    }
+}
+
 // out = relu(Wmat in + bias) for a W-wide input held in accumulator layout.
 template <int MT, int NW>
 __device__ __forceinline__ void dense(WeightStage<MT, NW> &ws, const float *__restrict__ bias,
@@ -379,6 +459,24 @@ __device__ __forceinline__ void dense(WeightStage<MT, NW> &ws, const float *__re
 #pragma unroll
         for (int i = 0; i < 4; ++i)
             out[mt][i] = fmaxf(out[mt][i], 0.f);
+}
+
+// FP8 form of dense(): the output stays in its scaled units (biases pre-scaled), and the
+// ReLU clamps at 448 so that the next FP8 layer can take it unclamped.
+template <int MT, int NW>
+__device__ __forceinline__ void dense8(WeightStage<MT, NW> &ws, const float *__restrict__ bias,
+                                       int tid, int lane, const f4 (&in)[MT], f4 (&out)[MT])
+{
+    const int g = lane >> 4;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+        out[mt] = *reinterpret_cast<const f4 *>(bias + 16 * mt + 4 * g);
+    fp8_layer<MT, NW, true>(ws, tid, lane, in, out);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            out[mt][i] = __builtin_amdgcn_fmed3f(out[mt][i], 0.f, 448.f);
 }
 
 template <int MT, int NW>
@@ -599,9 +697,17 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
 }
 
 // Register variant: 16 points per wave, two waves per SIMD, the residual stream in
-// registers and no cross-chunk pipelining (each chunk issues its 8 samples and
-// interpolates them); the other wave on the SIMD covers the load latency.
-template <int MT, int NW>
+// registers; samples pipelined across the stencil chunks of a level.
+//
+// F8: the FP8 form.  W1, W2 and the dense trailing layers run on the 16x16x128 E4M3
+// MFMA; the descriptor layers stay BF16.  Activations live in power-of-two scaled
+// units chosen on the host: block k's first-layer output in units of 2^f_k (its BF16
+// weights and bias are pre-multiplied), the residual stream in units of 2^o, trailing
+// layer m in units of 2^h_m.  An FP8 matrix is encoded at the exponent (output unit -
+// input unit), so the unscaled product lands in the output's units.  ReLU outputs that
+// feed an FP8 layer are clamped at 448, the residual stream only where it is
+// converted.
+template <int MT, int NW, bool F8>
 __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
                                                           const uint4 *__restrict__ frags,
                                                           const float *__restrict__ vec)
@@ -713,31 +819,42 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
                 ws.fetch(tid);
                 const float sv = finish_one(pa.v[0], pa.fx[0], pa.fy[0], pa.fz[0]);
                 const f4 lo = f4{g == 0 ? sv : 0.f, g == 0 ? gamma : 0.f, 0.f, 0.f};
-                mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, (MT & 1) ? O[MT - 1] : z4), F);
+                mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, (!F8 && (MT & 1)) ? O[MT - 1] : z4),
+                               F);
                 ws.template next<0>(tid);
             }
             if (k > 0) {
+                if constexpr (F8) {
+                    fp8_layer<MT, NW, true>(ws, tid, lane, O, F);
+                } else {
 #pragma unroll
-                for (int qq = 0; qq < MT / 2; ++qq) {
-                    ws.fetch(tid);
-                    mfma_chunk<MT>(ws.chunk(), lane, pack8(O[2 * qq], O[2 * qq + 1]), F);
-                    ws.template next<0>(tid);
+                    for (int qq = 0; qq < MT / 2; ++qq) {
+                        ws.fetch(tid);
+                        mfma_chunk<MT>(ws.chunk(), lane, pack8(O[2 * qq], O[2 * qq + 1]), F);
+                        ws.template next<0>(tid);
+                    }
                 }
             }
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    F[mt][i] = fmaxf(F[mt][i], 0.f);
+                    F[mt][i] = F8 ? __builtin_amdgcn_fmed3f(F[mt][i], 0.f, 448.f)
+                                  : fmaxf(F[mt][i], 0.f);
                 O[mt] += *reinterpret_cast<const f4 *>(b2 + 16 * mt + 4 * g);
             }
+            if constexpr (F8) {
+                fp8_layer<MT, NW, false>(ws, tid, lane, F, O);
+            } else {
 #pragma unroll
-            for (int qq = 0; qq < C2; ++qq) {
-                ws.fetch(tid);
-                mfma_chunk<MT>(ws.chunk(), lane,
-                               pack8(F[2 * qq], (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0] : z4),
-                               O);
-                ws.template next<0>(tid);
+                for (int qq = 0; qq < C2; ++qq) {
+                    ws.fetch(tid);
+                    mfma_chunk<MT>(
+                        ws.chunk(), lane,
+                        pack8(F[2 * qq], (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0] : z4),
+                        O);
+                    ws.template next<0>(tid);
+                }
             }
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
@@ -747,15 +864,28 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
         }
         const float *bh = vec + (size_t)a.K * 2 * WP;
         int h = 0;
-        for (; h + 1 < a.H - 1; h += 2) {
-            dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
-            dense<MT, NW>(ws, bh + (size_t)(h + 1) * WP, tid, lane, F, O);
-        }
-        if (h < a.H - 1) {
-            dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+        if constexpr (F8) {
+            for (; h + 1 < a.H - 1; h += 2) {
+                dense8<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+                dense8<MT, NW>(ws, bh + (size_t)(h + 1) * WP, tid, lane, F, O);
+            }
+            if (h < a.H - 1) {
+                dense8<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-                O[mt] = F[mt];
+                for (int mt = 0; mt < MT; ++mt)
+                    O[mt] = F[mt];
+            }
+        } else {
+            for (; h + 1 < a.H - 1; h += 2) {
+                dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+                dense<MT, NW>(ws, bh + (size_t)(h + 1) * WP, tid, lane, F, O);
+            }
+            if (h < a.H - 1) {
+                dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    O[mt] = F[mt];
+            }
         }
         const float *wl = bh + (size_t)(a.H - 1) * WP;
         const float bl = wl[WP];
@@ -1127,7 +1257,7 @@ int64_t assign_tiles(FusedArgs &a, int64_t per)
     return t;
 }
 
-template <int MT, int NW, int KIND>
+template <int MT, int NW, int KIND, bool F8 = false>
 ds_status launch_kind(hipStream_t s, const ds_net *net, FusedArgs a, int grid)
 {
     const int64_t tiles = assign_tiles(a, 16 * NW * (KIND == DS_KERNEL_WIDE ? 2 : 1));
@@ -1135,12 +1265,16 @@ ds_status launch_kind(hipStream_t s, const ds_net *net, FusedArgs a, int grid)
         return DS_OK;
     const int64_t g = grid > 0 && grid < tiles ? grid : tiles;
     DS_CHECK(g < ((int64_t)1 << 31), DS_ERR_INVALID_ARG, "too many tiles for one launch");
-    if constexpr (KIND == DS_KERNEL_PIPELINED)
+    if constexpr (F8) {
+        static_assert(KIND == DS_KERNEL_REGISTER, "the FP8 form has the register kernel only");
+        k_fused_reg<MT, NW, true><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_fp8, net->vec8);
+    } else if constexpr (KIND == DS_KERNEL_PIPELINED) {
         k_fused<MT, NW><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_bf16, net->vec);
-    else if constexpr (KIND == DS_KERNEL_WIDE)
+    } else if constexpr (KIND == DS_KERNEL_WIDE) {
         k_fused_wide<MT, NW><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_bf16, net->vec);
-    else
-        k_fused_reg<MT, NW><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_bf16, net->vec);
+    } else {
+        k_fused_reg<MT, NW, false><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_bf16, net->vec);
+    }
     DS_HIP(hipGetLastError());
     return DS_OK;
 }
@@ -1156,8 +1290,19 @@ constexpr bool fits(int MT, int waves, int kind)
 }
 
 template <int MT>
-ds_status launch(hipStream_t s, const ds_net *net, const FusedArgs &a, const FusedVariant &v)
+ds_status launch(hipStream_t s, const ds_net *net, const FusedArgs &a, const FusedVariant &v,
+                 bool fp8)
 {
+    if (fp8) {
+        if constexpr (fits(MT, 8, DS_KERNEL_REGISTER)) {
+            if (v.waves == 8)
+                return launch_kind<MT, 8, DS_KERNEL_REGISTER, true>(s, net, a, v.grid);
+        }
+        if (v.waves == 4)
+            return launch_kind<MT, 4, DS_KERNEL_REGISTER, true>(s, net, a, v.grid);
+        set_error("eight waves per workgroup do not fit this kernel at width %d", net->W);
+        return DS_ERR_UNSUPPORTED;
+    }
     if (v.waves == 8) {
         if constexpr (fits(MT, 8, DS_KERNEL_PIPELINED)) {
             if (v.kind == DS_KERNEL_PIPELINED)
@@ -1189,6 +1334,54 @@ int fused_tiles(int W)
     return -1;
 }
 
+namespace {
+// Offsets of every parameter block in the canonical order: per block V [W][226],
+// W1 [W][W] (not for the first block), b1, W2 [W][W], b2; then per trailing layer its
+// matrix and bias (the last one has a single output).
+struct ParamBlocks {
+    std::vector<int64_t> V, W1, b1, W2, b2, hw, hb;
+};
+ParamBlocks param_blocks(int K, int W, int H)
+{
+    ParamBlocks o;
+    int64_t off = 0;
+    for (int k = 0; k < K; ++k) {
+        o.V.push_back(off);
+        off += (int64_t)W * 226;
+        o.W1.push_back(k ? off : -1);
+        if (k)
+            off += (int64_t)W * W;
+        o.b1.push_back(off);
+        off += W;
+        o.W2.push_back(off);
+        off += (int64_t)W * W;
+        o.b2.push_back(off);
+        off += W;
+    }
+    for (int m = 0; m < H; ++m) {
+        int rows = m == H - 1 ? 1 : W;
+        o.hw.push_back(off);
+        off += (int64_t)rows * W;
+        o.hb.push_back(off);
+        off += rows;
+    }
+    return o;
+}
+
+// Stencil sample (index n = ix + 5 iy + 25 iz) held by slot (g, j) of stencil chunk
+// c < 7: chunks 0..5 and g = 0 of chunk 6 walk the 25 columns (iz = j); lanes g = 1..3
+// of chunk 6 cover the iz = 8 plane as five rows of four and one column of four.
+int stencil_slot(int c, int g, int j)
+{
+    if (c < 6 || g == 0) {
+        int col = 4 * c + g;  // column (ix, iy), iz = j
+        return (col % 5) + 5 * (col / 5) + 25 * j;
+    }
+    int G = 2 * (g - 1) + (j >> 2), jj = j & 3;  // plane iz = 8
+    return G < 5 ? jj + 5 * G + 25 * 8 : 4 + 5 * jj + 25 * 8;
+}
+}  // namespace
+
 // Packing maps: for every bf16 element of the weight fragments (in kernel order)
 // and every FP32 entry of the bias / final-layer vector, the index of the
 // canonical parameter it holds, or -1 for padding.
@@ -1197,41 +1390,13 @@ static void build_pack_maps(int K, int W, int H, std::vector<int32_t> &fmap,
 {
     const int MT = fused_tiles(W);
     const int C1 = 8 + MT / 2, C2 = (MT + 1) / 2, WP = 16 * MT;
-    std::vector<int64_t> oV(K), oW1(K), ob1(K), oW2(K), ob2(K), ohw(H), ohb(H);
-    int64_t off = 0;
-    for (int k = 0; k < K; ++k) {
-        oV[k] = off;
-        off += (int64_t)W * 226;
-        oW1[k] = k ? off : -1;
-        if (k)
-            off += (int64_t)W * W;
-        ob1[k] = off;
-        off += W;
-        oW2[k] = off;
-        off += (int64_t)W * W;
-        ob2[k] = off;
-        off += W;
-    }
-    for (int m = 0; m < H; ++m) {
-        int rows = m == H - 1 ? 1 : W;
-        ohw[m] = off;
-        off += (int64_t)rows * W;
-        ohb[m] = off;
-        off += rows;
-    }
+    const ParamBlocks pb = param_blocks(K, W, H);
+    const std::vector<int64_t> &oV = pb.V, &oW1 = pb.W1, &ob1 = pb.b1, &oW2 = pb.W2,
+                               &ob2 = pb.b2, &ohw = pb.hw, &ohb = pb.hb;
     const int64_t nfr = (int64_t)chunk_count(MT, K, H) * MT;
     fmap.assign((size_t)nfr * 64 * 8, -1);
     auto put = [&](int64_t frag, int g, int r, int j, int64_t idx) {
         fmap[((size_t)frag * 64 + 16 * g + r) * 8 + j] = (int32_t)idx;
-    };
-    // stencil sample (index n = ix + 5 iy + 25 iz) held by slot (g, j) of chunk c < 7
-    auto stencil_slot = [](int c, int g, int j) {
-        if (c < 6 || g == 0) {
-            int col = 4 * c + g;               // column (ix, iy), iz = j
-            return (col % 5) + 5 * (col / 5) + 25 * j;
-        }
-        int G = 2 * (g - 1) + (j >> 2), jj = j & 3;  // plane iz = 8
-        return G < 5 ? jj + 5 * G + 25 * 8 : 4 + 5 * jj + 25 * 8;
     };
     int64_t frag = 0;
     for (int k = 0; k < K; ++k) {
@@ -1377,6 +1542,231 @@ ds_status fused_pack_bf16(hipStream_t s, ds_net *net)
     return DS_OK;
 }
 
+// ------------------------------------------------------------------ FP8 form
+int fp8_exp_count(int K, int H) { return 3 * K + 2 * H - 2; }
+
+uint8_t e4m3_encode(float x)
+{
+    if (isnan(x))
+        return 0x7F;
+    const uint8_t sign = signbit(x) ? 0x80 : 0x00;
+    const double a = fabs((double)x);
+    if (a >= 464.0)  // beyond the rounding range of 448 = 1.75 * 2^8: saturate
+        return sign | 0x7E;
+    if (a < 0.015625) {  // below 2^-6: subnormal, a multiple of 2^-9 (8 -> smallest normal)
+        return sign | (uint8_t)nearbyint(a * 512.0);
+    }
+    int e;
+    frexp(a, &e);
+    e -= 1;                                        // a in [2^e, 2^(e+1)), e in -6..8
+    int q = (int)nearbyint(ldexp(a, 3 - e));       // 8..16, ties to even
+    if (q == 16) {
+        q = 8;
+        ++e;
+    }
+    const int code = ((e + 7) << 3) | (q - 8);
+    return sign | (uint8_t)(code > 0x7E ? 0x7E : code);
+}
+
+namespace {
+// Largest e with amax * 2^e <= 448 (0 for an all-zero tensor), kept within +-32 so that
+// every E8M0 operand scale of the kernel stays inside its range.
+int log2_scale(double amax)
+{
+    if (!(amax > 0.0) || !isfinite(amax))
+        return 0;
+    int e = (int)floor(log2(448.0 / amax));
+    while (ldexp(amax, e) > 448.0)
+        --e;
+    while (ldexp(amax, e + 1) <= 448.0)
+        ++e;
+    return e < -32 ? -32 : (e > 32 ? 32 : e);
+}
+
+uint16_t bf16_rne(float x)
+{
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+double tensor_amax(const float *th, int64_t off, int64_t n)
+{
+    double m = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        m = fmax(m, fabs((double)th[off + i]));
+    return m;
+}
+}  // namespace
+
+// The FP8 form in kernel order.  Per block: the 8 stencil chunks in BF16 with V and the
+// gamma weights multiplied by 2^f_k (exact: a power of two), then (blocks 2..K) the W1
+// chunks and the W2 chunks in E4M3, each FP8 chunk covering 128 inputs (8 tiles of the
+// previous layer) in two 16-byte staging slots; then the dense trailing layers.  A
+// matrix is encoded as RNE(w * 2^e), e = its output unit - its input unit.
+ds_status fused_quantize_fp8(ds_net *net, const float *th, const float *act_amax)
+{
+    const int K = net->K, W = net->W, H = net->H, MT = fused_tiles(W);
+    DS_CHECK(MT > 0, DS_ERR_UNSUPPORTED, "width %d is not supported by the fused kernel", W);
+    const int C8 = (MT + 7) / 8, WP = 16 * MT;
+    const ParamBlocks pb = param_blocks(K, W, H);
+    // Range-filling exponents: activations from the calibration maxima, weights from
+    // their own maxima.
+    std::vector<int> eF(K), eH(H > 1 ? H - 1 : 1), wW1(K, 0), wW2(K), wH(H > 1 ? H - 1 : 1);
+    for (int k = 0; k < K; ++k)
+        eF[k] = log2_scale(act_amax[k]);
+    const int eO = log2_scale(act_amax[K]);
+    for (int m = 0; m < H - 1; ++m)
+        eH[m] = log2_scale(act_amax[K + 1 + m]);
+    for (int k = 1; k < K; ++k)
+        wW1[k] = log2_scale(tensor_amax(th, pb.W1[k], (int64_t)W * W));
+    for (int k = 0; k < K; ++k)
+        wW2[k] = log2_scale(tensor_amax(th, pb.W2[k], (int64_t)W * W));
+    for (int m = 0; m < H - 1; ++m)
+        wH[m] = log2_scale(tensor_amax(th, pb.hw[m], (int64_t)W * W));
+    // Units: f_k <= eF_k, o <= eO, h_m <= eH_m (activations fit under 448), with every
+    // matrix exponent (output unit - input unit) at most its range-filling one (weights
+    // fit under 448): f_k - o <= wW1_k, o - f_k <= wW2_k, h_m - in_m <= wH_m.  Lowering
+    // o only lowers the bounds, so the loop ends.
+    int o = eO;
+    std::vector<int> f(K);
+    for (int it = 0;; ++it) {
+        bool again = false;
+        for (int k = 0; k < K && !again; ++k) {
+            f[k] = k > 0 && o + wW1[k] < eF[k] ? o + wW1[k] : eF[k];
+            if (o - f[k] > wW2[k]) {
+                o = f[k] + wW2[k];
+                again = true;
+            }
+        }
+        if (!again)
+            break;
+        if (it > 4 * K + 8) {
+            set_error("ds_net_quantize: no consistent FP8 scales for this network");
+            return DS_ERR_STATE;
+        }
+    }
+    std::vector<int> h(H > 1 ? H - 1 : 1);
+    for (int m = 0; m < H - 1; ++m) {
+        const int in = m == 0 ? o : h[m - 1];
+        h[m] = in + wH[m] < eH[m] ? in + wH[m] : eH[m];
+    }
+    // exported: units, then matrix exponents
+    std::vector<int32_t> ex;
+    for (int k = 0; k < K; ++k)
+        ex.push_back(f[k]);
+    ex.push_back(o);
+    for (int m = 0; m < H - 1; ++m)
+        ex.push_back(h[m]);
+    for (int k = 1; k < K; ++k)
+        ex.push_back(f[k] - o);
+    for (int k = 0; k < K; ++k)
+        ex.push_back(o - f[k]);
+    for (int m = 0; m < H - 1; ++m)
+        ex.push_back(h[m] - (m == 0 ? o : h[m - 1]));
+    if ((int)ex.size() != fp8_exp_count(K, H)) {
+        set_error("internal error: FP8 scale count");
+        return DS_ERR_STATE;
+    }
+
+    const int64_t slots = (8 + 2 * C8) + (int64_t)(K - 1) * (8 + 4 * C8) + (int64_t)(H - 1) * 2 * C8;
+    std::vector<uint4> fr((size_t)(slots * MT * 64 + kFragPad), uint4{0, 0, 0, 0});
+    auto entry = [&](int64_t slot, int mt, int lane) -> uint8_t * {
+        return reinterpret_cast<uint8_t *>(&fr[(size_t)((slot * MT + mt) * 64 + lane)]);
+    };
+    // one FP8 matrix [W][W] at offset off, scale 2^e, starting at `slot`
+    auto put_fp8 = [&](int64_t slot, int64_t off, int e) {
+        for (int Q = 0; Q < C8; ++Q)
+            for (int h = 0; h < 2; ++h)
+                for (int mt = 0; mt < MT; ++mt)
+                    for (int g = 0; g < 4; ++g)
+                        for (int r = 0; r < 16; ++r) {
+                            const int row = 16 * mt + r;
+                            if (row >= W)
+                                continue;
+                            uint8_t *dst = entry(slot + 2 * Q + h, mt, 16 * g + r);
+                            for (int bb = 0; bb < 16; ++bb) {
+                                const int b = 16 * h + bb, t = 8 * Q + b / 4;
+                                const int col = 16 * t + 4 * g + (b & 3);
+                                dst[bb] = (t < MT && col < W)
+                                              ? e4m3_encode((float)ldexp(
+                                                    (double)th[off + (int64_t)row * W + col], e))
+                                              : 0;
+                            }
+                        }
+    };
+    int64_t slot = 0;
+    for (int k = 0; k < K; ++k) {
+        for (int c = 0; c < 8; ++c, ++slot)
+            for (int mt = 0; mt < MT; ++mt)
+                for (int g = 0; g < 4; ++g)
+                    for (int r = 0; r < 16; ++r) {
+                        const int row = 16 * mt + r;
+                        if (row >= W)
+                            continue;
+                        uint16_t *dst = reinterpret_cast<uint16_t *>(entry(slot, mt, 16 * g + r));
+                        for (int j = 0; j < 8; ++j) {
+                            int col = -1;
+                            if (c < 7)
+                                col = stencil_slot(c, g, j);
+                            else if (g == 0 && j < 2)
+                                col = 224 + j;  // sample (4, 4, 8), gamma
+                            dst[j] = col < 0 ? 0
+                                             : bf16_rne((float)ldexp(
+                                                   (double)th[pb.V[k] + (int64_t)row * 226 + col],
+                                                   f[k]));
+                        }
+                    }
+        if (k > 0) {
+            put_fp8(slot, pb.W1[k], f[k] - o);
+            slot += 2 * C8;
+        }
+        put_fp8(slot, pb.W2[k], o - f[k]);
+        slot += 2 * C8;
+    }
+    for (int m = 0; m < H - 1; ++m) {
+        put_fp8(slot, pb.hw[m], h[m] - (m == 0 ? o : h[m - 1]));
+        slot += 2 * C8;
+    }
+    if (slot != slots) {
+        set_error("internal error: FP8 packing produced %lld slots, expected %lld",
+                  (long long)slot, (long long)slots);
+        return DS_ERR_STATE;
+    }
+
+    // vectors in the same layout as the BF16 form's, in the FP8 form's units
+    const int64_t nvec = (int64_t)K * 2 * WP + (int64_t)(H - 1) * WP + WP + 4;
+    std::vector<float> vec((size_t)nvec, 0.f);
+    for (int k = 0; k < K; ++k)
+        for (int r = 0; r < W; ++r) {
+            vec[(size_t)k * 2 * WP + r] = (float)ldexp((double)th[pb.b1[k] + r], f[k]);
+            vec[(size_t)k * 2 * WP + WP + r] = (float)ldexp((double)th[pb.b2[k] + r], o);
+        }
+    for (int m = 0; m < H - 1; ++m)
+        for (int r = 0; r < W; ++r)
+            vec[(size_t)K * 2 * WP + (size_t)m * WP + r] =
+                (float)ldexp((double)th[pb.hb[m] + r], h[m]);
+    const size_t wl = (size_t)K * 2 * WP + (size_t)(H - 1) * WP;
+    const int e_last = H >= 2 ? h[H - 2] : o;  // units of the final layer's input
+    for (int c = 0; c < W; ++c)
+        vec[wl + c] = (float)ldexp((double)th[pb.hw[H - 1] + c], -e_last);
+    vec[wl + WP] = th[pb.hb[H - 1]];
+
+    if (!net->frag_fp8) {
+        DS_CHECK(hipMalloc(&net->frag_fp8, fr.size() * sizeof(uint4)) == hipSuccess, DS_ERR_OOM,
+                 "out of device memory for the FP8 weights");
+        DS_CHECK(hipMalloc(&net->vec8, vec.size() * sizeof(float)) == hipSuccess, DS_ERR_OOM,
+                 "out of device memory for the FP8 vectors");
+        net->frag8_count = (int64_t)fr.size();
+    }
+    DS_HIP(hipMemcpy(net->frag_fp8, fr.data(), fr.size() * sizeof(uint4), hipMemcpyHostToDevice));
+    DS_HIP(hipMemcpy(net->vec8, vec.data(), vec.size() * sizeof(float), hipMemcpyHostToDevice));
+    net->fp8_exps = ex;
+    net->fp8_ready = true;
+    return DS_OK;
+}
+
 ds_status fused_gather_packed(hipStream_t s, const FusedArgs &a, float *z)
 {
     int64_t blocks = (a.cl[0].P + 63) / 64;
@@ -1398,21 +1788,39 @@ bool fused_variant_ok(const ds_net *net, const FusedVariant &v)
     return v.grid >= 0;
 }
 
-ds_status fused_predict_bf16(hipStream_t s, const ds_net *net, const FusedArgs &a,
-                             const FusedVariant &v)
+bool fused_variant_ok_fp8(const ds_net *net, const FusedVariant &v)
+{
+    return v.kind == DS_KERNEL_REGISTER && fused_variant_ok(net, v);
+}
+
+ds_status fused_predict(hipStream_t s, const ds_net *net, const FusedArgs &a,
+                        const FusedVariant &v, ds_precision precision)
 {
     DS_CHECK(a.n_clouds >= 1 && a.n_clouds <= kMaxBatch, DS_ERR_INVALID_ARG,
              "between 1 and %d clouds per launch", kMaxBatch);
-    DS_CHECK(fused_variant_ok(net, v), DS_ERR_INVALID_ARG,
-             "kernel variant (kind %d, %d waves, grid %d) is not available at width %d", v.kind,
-             v.waves, v.grid, net->W);
+    DS_CHECK(precision == DS_PREC_BF16 || precision == DS_PREC_FP8, DS_ERR_INVALID_ARG,
+             "fused prediction: precision %d", (int)precision);
+    const bool fp8 = precision == DS_PREC_FP8;
+    if (fp8) {
+        DS_CHECK(net->fp8_ready, DS_ERR_STATE,
+                 "FP8 weights are not available: quantize the network (ds_net_quantize) after "
+                 "its parameters were last set");
+        DS_CHECK(fused_variant_ok_fp8(net, v), DS_ERR_UNSUPPORTED,
+                 "kernel variant (kind %d, %d waves, grid %d) has no FP8 form at width %d", v.kind,
+                 v.waves, v.grid, net->W);
+    } else {
+        DS_CHECK(net->frag_bf16, DS_ERR_STATE, "network parameters were never set");
+        DS_CHECK(fused_variant_ok(net, v), DS_ERR_INVALID_ARG,
+                 "kernel variant (kind %d, %d waves, grid %d) is not available at width %d",
+                 v.kind, v.waves, v.grid, net->W);
+    }
     switch (fused_tiles(net->W)) {
-    case 1: return launch<1>(s, net, a, v);
-    case 2: return launch<2>(s, net, a, v);
-    case 4: return launch<4>(s, net, a, v);
-    case 8: return launch<8>(s, net, a, v);
-    case 13: return launch<13>(s, net, a, v);
-    case 16: return launch<16>(s, net, a, v);
+    case 1: return launch<1>(s, net, a, v, fp8);
+    case 2: return launch<2>(s, net, a, v, fp8);
+    case 4: return launch<4>(s, net, a, v, fp8);
+    case 8: return launch<8>(s, net, a, v, fp8);
+    case 13: return launch<13>(s, net, a, v, fp8);
+    case 16: return launch<16>(s, net, a, v, fp8);
     default:
         set_error("width %d is not supported by the fused kernel", net->W);
         return DS_ERR_UNSUPPORTED;

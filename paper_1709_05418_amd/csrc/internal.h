@@ -88,7 +88,13 @@ struct ds_net {
     int64_t vec_count = 0;
     int32_t *fmap = nullptr;      // parameter index of every fragment element (-1: zero)
     int32_t *vmap = nullptr;      // parameter index of every vector entry
-    bool has_fp8 = false;
+    // FP8 form (DS_PREC_FP8): the W x W layers in E4M3 with power-of-two scales, the
+    // descriptor layers in BF16 pre-multiplied by their output scale; see fused.hip
+    uint4 *frag_fp8 = nullptr;    // packed fragments of the FP8 form (BF16 and E4M3 chunks)
+    int64_t frag8_count = 0;
+    float *vec8 = nullptr;        // biases and final layer, scaled to the FP8 form's units
+    std::vector<int32_t> fp8_exps;  // log2 units of the activations, then matrix exponents
+    bool fp8_ready = false;       // FP8 form matches the current parameters
     // training workspace (activations and gradients of one minibatch)
     float *tws = nullptr;
     size_t tws_floats = 0;
@@ -158,6 +164,8 @@ struct GemmArgs {
     int relu;
 };
 ds_status gemm_f32(hipStream_t s, const GemmArgs &a);
+// out = max(out, max |x|) over n floats, as the bit pattern of a non-negative float
+ds_status amax_into(hipStream_t s, const float *x, int64_t n, unsigned *out);
 
 // train.hip: C (+)= A B with A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn]
 struct StridedGemm {
@@ -221,8 +229,19 @@ struct FusedVariant {
     int kind, waves, grid;
 };
 bool fused_variant_ok(const ds_net *net, const FusedVariant &v);
-ds_status fused_predict_bf16(hipStream_t s, const ds_net *net, const FusedArgs &a,
-                             const FusedVariant &v);
+// precision DS_PREC_BF16 or DS_PREC_FP8 (the latter needs net->fp8_ready)
+ds_status fused_predict(hipStream_t s, const ds_net *net, const FusedArgs &a,
+                        const FusedVariant &v, ds_precision precision);
+bool fused_variant_ok_fp8(const ds_net *net, const FusedVariant &v);
+// Number of log2 scales of the FP8 form: K + 1 + (H - 1) activation units (F of every
+// block, the residual stream, the dense trailing layers), then (K - 1) + K + (H - 1)
+// matrix exponents (W1 of blocks 2..K, W2 of every block, the dense trailing layers).
+int fp8_exp_count(int K, int H);
+// Build the FP8 form from host parameters and the activation maxima of a calibration
+// pass (same order as the activation scales), and upload it.
+ds_status fused_quantize_fp8(ds_net *net, const float *theta_host, const float *act_amax);
+// Host encoder: x * 2^e to OCP E4M3 (round to nearest even, saturating at 448).
+uint8_t e4m3_encode(float x);
 ds_status fused_gather_packed(hipStream_t s, const FusedArgs &a, float *z);
 
 // tracer.hip

@@ -83,7 +83,39 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs a)
     }
 }
 
+// Largest magnitude of x, merged into *out as the bits of a non-negative float (whose
+// order as unsigned integers is the order of the values).
+__global__ void __launch_bounds__(256) k_amax(const float *__restrict__ x, int64_t n,
+                                              unsigned *out)
+{
+    __shared__ float part[4];
+    float m = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        m = fmaxf(m, fabsf(x[i]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0)
+        part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = fmaxf(fmaxf(part[0], part[1]), fmaxf(part[2], part[3]));
+        atomicMax(out, __float_as_uint(m));
+    }
+}
+
 }  // namespace
+
+ds_status amax_into(hipStream_t s, const float *x, int64_t n, unsigned *out)
+{
+    if (n <= 0)
+        return DS_OK;
+    int64_t blocks = (n + 255) / 256;
+    k_amax<<<(unsigned)(blocks < 1024 ? blocks : 1024), 256, 0, s>>>(x, n, out);
+    DS_HIP(hipGetLastError());
+    return DS_OK;
+}
 
 ds_status gemm_f32(hipStream_t s, const GemmArgs &a)
 {

@@ -75,3 +75,49 @@ def test_full_size_bench_launch_matches_oracle(full):
         net.close()
         cloud.close()
         ctx.close()
+
+
+def test_full_size_fp8_bench_launch_matches_oracle(full):
+    """The FP8 form at the full size, in the benchmark's launch (autotuned plan replayed
+    from a graph), calibrated on 65536 evenly strided points.  Parameters with the
+    residual branches scaled by 1/sqrt(K) and a live output unit (with unscaled branches
+    the final pre-activation cancels and amplifies any rounding)."""
+    f = full
+    theta = synth.init_params(K, W, H, 12, branch_scale=1.0 / np.sqrt(K), out_scale=0.2,
+                              out_bias=0.5)
+    ctx = ds.Context(0)
+    cloud = ds.Cloud(ctx, f["d"], SIGMA, f["aabb_min"], f["h0"], L, K)
+    net = ds.Net(ctx, K, W, H)
+    try:
+        net.set_params(theta)
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        pos, view, light = t(f["pos"]), t(f["view"]), t(f["light"])
+        cal = torch.arange(0, P, 16, device="cuda")
+        ds.ds_net_quantize(ctx.h, net.h, cloud.h, ds.DS_PREC_FP8, pos[cal].contiguous(),
+                           view[cal].contiguous(), light[cal].contiguous())
+        out = torch.empty(P, device="cuda")
+        pre = torch.empty(P, device="cuda")
+        b = ds.ds_batch_create(ctx.h, net.h, [cloud.h], [0, P])
+        try:
+            cfg = ds.ds_batch_autotune(b, ds.DS_PREC_FP8, pos, view, light, out, 1)
+            print("fp8 autotuned", cfg, flush=True)
+            ds.ds_batch_capture(b, ds.DS_PREC_FP8, pos, view, light, out, pre)
+            out.fill_(-1.0)
+            ds.ds_batch_replay(b)
+            torch.cuda.synchronize()
+        finally:
+            ds.ds_batch_destroy(b)
+        idx = np.linspace(1, P - 2, 3000).astype(np.int64)  # off the calibration stride
+        pyr, dims, offs = f["pyr"]
+        z, _ = O.gather(f["grid"], pyr, dims, offs, f["mean"], K, f["mips"], f["pos"][idx],
+                        f["view"][idx], f["light"][idx])
+        gr, prer = O.forward(theta.astype(np.float64), K, W, H, z)
+        e8 = (rel_l2(out.cpu().numpy()[idx], gr), rel_l2(pre.cpu().numpy()[idx], prer))
+        print(f"full size: fp8 g {e8[0]:.2e} pre {e8[1]:.2e}; alive {(gr > 0).mean():.2f}",
+              flush=True)
+        assert max(e8) < 5e-2
+        assert bool(torch.isfinite(out).all()) and float(out.min()) >= 0.0
+    finally:
+        net.close()
+        cloud.close()
+        ctx.close()
