@@ -1,9 +1,12 @@
 #!/usr/bin/env python3
 """Throughput of the radiance-prediction hot path on one MI355X.
 
-One step = one ds_predict over the whole batch of shading points: the
+One step = one prediction over the whole batch of shading points: the
 hierarchical stencil gather from the mip pyramid plus the residual network, in
-the fused BF16 kernel.  Inputs are resident in HBM before timing starts.
+the fused BF16 kernel (the headline), replayed from a captured graph of the
+autotuned launch.  Inputs are resident in HBM before timing starts.  The FP8
+form (W x W layers on the FP8 matrix cores) is timed the same way and reported
+beside it.
 
 Default workload (paper-sized inference): seeded 512^3 fBm + Worley cloud,
 sigma_max 512/unit, 10 mip levels, K = 10 stencil levels, 10 residual blocks of
@@ -12,7 +15,8 @@ width 200 plus 3 trailing layers, 2^20 shading points = primary hits of a
 descriptor through HBM, one kernel per layer) on the same points, and the FP64
 oracle on a bounded sample of them on the host cores.
 
-    python bench.py [--steps K] [--warmup W] [--workload paper|tiny] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--workload paper|tiny|batched] [--no-cpu]
+                    [--no-fp8]
 """
 from __future__ import annotations
 
@@ -27,6 +31,7 @@ import numpy as np
 
 METRIC = "shading points/s (stencil+RPNN) BF16/FP8 vs FP32 at stated rel. error; MFMA %"
 PEAK_BF16_TFLOPS = 2500.0
+PEAK_FP8_TFLOPS = 5000.0
 
 WORKLOADS = {
     "paper": dict(n=512, sigma=512.0, L=10, K=10, W=200, H=3, P=1 << 20, res=1024, worley=0.3,
@@ -77,6 +82,19 @@ def macs_per_point(K, W, H):
     return 226 * K * W + (K - 1) * W * W + K * W * W + (H - 1) * W * W + W
 
 
+def fp8_macs_per_point(K, W, H):
+    """MACs the FP8 form runs on the FP8 matrix cores: W1, W2 and the dense trailing
+    layers (the descriptor layers stay BF16, the final W -> 1 layer FP32)."""
+    return (K - 1) * W * W + K * W * W + (H - 1) * W * W
+
+
+def theta_for(synth, K, W, H, seed):
+    """He-uniform parameters with the residual branches scaled by 1/sqrt(K) and a live
+    output unit, as in the parity tests (timing does not depend on the values)."""
+    return synth.init_params(K, W, H, seed, branch_scale=1.0 / math.sqrt(K), out_scale=0.2,
+                             out_bias=0.5)
+
+
 BATCHED = dict(sizes=[128, 192, 256, 384, 512, 640, 768, 1024], seeds=list(range(100, 108)),
                point_seed=200, pts_seeds=list(range(300, 308)), K=10, W=200, H=3, seed_theta=12,
                name="batched uneven inference: 8 BF16 clouds 128^3..1024^3 (sigma_max = n/unit, "
@@ -114,7 +132,7 @@ def run_batched(args, log):
     offsets = np.concatenate([[0], np.cumsum(counts)])
     N = int(offsets[-1])
     net = ds.Net(ctx, K, W, H)
-    net.set_params(synth.init_params(K, W, H, cfg["seed_theta"]))
+    net.set_params(theta_for(synth, K, W, H, cfg["seed_theta"]))
     out = torch.empty(N, dtype=torch.float32, device=dev)
     b = ds.ds_batch_create(ctx.h, net.h, [c.h for c in clouds], offsets)
     ta = time.time()
@@ -122,20 +140,22 @@ def run_batched(args, log):
     log(f"autotune {time.time() - ta:.1f}s: {tuned}")
     ds.ds_batch_capture(b, ds.DS_PREC_BF16, pos, view, light, out)
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        ds.ds_batch_replay(b)
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    tw = time.perf_counter()
-    for a, e in evs:
-        a.record(stream)
-        ds.ds_batch_replay(b)
-        e.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - tw
-    ms_step = wall * 1e3 / args.steps
-    kernel_ms = float(np.mean([a.elapsed_time(e) for a, e in evs]))
+
+    def replay_timed(plan):
+        for _ in range(args.warmup):
+            ds.ds_batch_replay(plan)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        tw = time.perf_counter()
+        for a, e in evs:
+            a.record(stream)
+            ds.ds_batch_replay(plan)
+            e.record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - tw
+        return wall * 1e3 / args.steps, float(np.mean([a.elapsed_time(e) for a, e in evs]))
+    ms_step, kernel_ms = replay_timed(b)
     # the same points, one default ds_predict per cloud
     seq = torch.empty_like(out)
     def per_cloud():
@@ -150,6 +170,23 @@ def run_batched(args, log):
     torch.cuda.synchronize()
     ms_seq = (time.perf_counter() - ts) * 1e3 / args.steps
     same = bool(torch.equal(seq, out))
+    # the FP8 form: calibrated on the 512^3 cloud's points, the same plan shape
+    fp8 = None
+    if not args.no_fp8:
+        ci = cfg["sizes"].index(512)
+        a0, a1 = int(offsets[ci]), int(offsets[ci + 1])
+        ds.ds_net_quantize(ctx.h, net.h, clouds[ci].h, ds.DS_PREC_FP8, pos[a0:a1], view[a0:a1],
+                           light[a0:a1])
+        out8 = torch.empty_like(out)
+        b8 = ds.ds_batch_create(ctx.h, net.h, [c.h for c in clouds], offsets)
+        tuned8 = ds.ds_batch_autotune(b8, ds.DS_PREC_FP8, pos, view, light, out8, 2)
+        ds.ds_batch_capture(b8, ds.DS_PREC_FP8, pos, view, light, out8)
+        ms8, kms8 = replay_timed(b8)
+        ds.ds_batch_destroy(b8)
+        fp8 = {"ms_per_step": round(ms8, 4), "value": round(N / (ms8 / 1e3), 1),
+               "kernel_ms": round(kms8, 4), "speedup_over_bf16": round(ms_step / ms8, 3),
+               "autotuned": tuned8}
+        log(f"batched fp8 graph replay {ms8:.3f} ms ({kms8:.3f} ms events), {tuned8}")
     flop = 2.0 * macs_per_point(K, W, H) * N
     achieved = flop / (kernel_ms / 1e3) / 1e12
     log(f"batched graph replay {ms_step:.3f} ms ({kernel_ms:.3f} ms events), per-cloud "
@@ -166,7 +203,7 @@ def run_batched(args, log):
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
                      "traffic": None, "kernel": "fused prediction, autotuned variant",
                      "flop_per_point": 2 * macs_per_point(K, W, H), "points_per_launch": N},
-        "cpu_baseline": None,
+        "cpu_baseline": None, "fp8": fp8,
     }
     ds.ds_batch_destroy(b)
     net.close()
@@ -189,6 +226,7 @@ def main():
     ap.add_argument("--load-inputs", default=None,
                     help="read inputs written by --save-inputs instead of generating them "
                          "(keeps generator kernels out of profiled runs)")
+    ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 form")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default kernel variant instead of the autotuned one")
     ap.add_argument("--calib-copy", action="store_true",
@@ -233,7 +271,7 @@ def main():
     pos = torch.from_numpy(pos_np).to(dev)
     view = torch.from_numpy(view_np).to(dev)
     light = torch.from_numpy(light_np).to(dev)
-    theta = synth.init_params(K, W, H, cfg["seed_theta"])
+    theta = theta_for(synth, K, W, H, cfg["seed_theta"])
     net = ds.Net(ctx, K, W, H)
     net.set_params(theta)
     out = torch.empty(P, dtype=torch.float32, device=dev)
@@ -293,6 +331,34 @@ def main():
                                   "(BF16 MFMA, stencil gather fused)",
                 "flop_per_point": 2 * macs_per_point(K, W, H), "points_per_launch": P}
 
+    # ---------------------------------------------------------------- FP8 form
+    fp8 = None
+    out8 = torch.empty(P, dtype=torch.float32, device=dev)
+    if not args.no_fp8:
+        cal = torch.arange(0, P, 16, device=dev)  # calibration: every 16th point
+        ds.ds_net_quantize(ctx.h, net.h, cloud.h, ds.DS_PREC_FP8, pos[cal].contiguous(),
+                           view[cal].contiguous(), light[cal].contiguous())
+        batch8 = ds.ds_batch_create(ctx.h, net.h, [cloud.h], [0, P])
+        tuned8 = {"kernel": ds.DS_KERNEL_REGISTER, "waves": 4, "grid": 0, "ms": None}
+        if not args.no_autotune:
+            tuned8 = ds.ds_batch_autotune(batch8, ds.DS_PREC_FP8, pos, view, light, out8, 3)
+        ds.ds_batch_capture(batch8, ds.DS_PREC_FP8, pos, view, light, out8)
+        ms8, kms8 = timed(lambda: ds.ds_batch_replay(batch8))
+        f16 = 2.0 * (macs_per_point(K, W, H) - fp8_macs_per_point(K, W, H)) * P
+        f8 = 2.0 * fp8_macs_per_point(K, W, H) * P
+        ideal_ms = (f16 / PEAK_BF16_TFLOPS + f8 / PEAK_FP8_TFLOPS) / 1e12 * 1e3
+        fp8 = {"ms_per_step": round(ms8, 4), "value": round(P / (ms8 / 1e3), 1),
+               "kernel_ms": round(kms8, 4), "speedup_over_bf16": round(ms_step / ms8, 3),
+               "autotuned": tuned8,
+               "roofline": {"bound": "mfma", "achieved": round((f16 + f8) / (kms8 / 1e3) / 1e12, 2),
+                            "peak": round((f16 + f8) / (ideal_ms / 1e3) / 1e12, 1),
+                            "unit": "TFLOP/s", "frac": round(ideal_ms / kms8, 4),
+                            "peak_note": "time-weighted: BF16 layers at 2500, FP8 layers at "
+                                         "5000 TFLOP/s"}}
+        log(f"fp8 form, graph replay of the tuned launch: {ms8:.3f} ms/step, kernel "
+            f"{kms8:.3f} ms, {P / (ms8 / 1e3):.3e} points/s, {tuned8}")
+        ds.ds_batch_destroy(batch8)
+
     # ---------------------------------------------------------------- FP32 plain form
     out32 = torch.empty(P, dtype=torch.float32, device=dev)
     fp32 = None
@@ -350,10 +416,12 @@ def main():
         g16 = out.cpu().numpy()[idx]
         g32 = out32.cpu().numpy()[idx] if fp32 else None
         rl = lambda a, b: float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+        g8 = out8.cpu().numpy()[idx] if fp8 else None
         parity = {"sampled_points": S, "same_mip_map": same_mips,
                   "rel_l2_bf16": rl(g16, g_ref) if same_mips else None,
+                  "rel_l2_fp8": rl(g8, g_ref) if (same_mips and fp8) else None,
                   "rel_l2_fp32": rl(g32, g_ref) if (same_mips and fp32) else None,
-                  "tolerance_bf16": 2e-2, "tolerance_fp32": 1e-5}
+                  "tolerance_bf16": 2e-2, "tolerance_fp8": 5e-2, "tolerance_fp32": 1e-5}
         log(f"parity on sample: {parity}")
 
     line = {
@@ -364,7 +432,8 @@ def main():
         "config": {"workload": cfg["name"], "grid": cfg["n"], "mip_levels": cfg["L"], "K": K,
                    "W": W, "trailing_layers": H, "points": P, "precision": "bf16",
                    "light": "side"},
-        "roofline": roofline, "cpu_baseline": cpu, "fp32_plain": fp32, "parity": parity,
+        "roofline": roofline, "cpu_baseline": cpu, "fp32_plain": fp32, "fp8": fp8,
+        "parity": parity,
         "kernel_ms": round(avg_kernel_ms, 4), "default_variant_ms": round(ms_default, 4),
         "autotuned": tuned,
     }

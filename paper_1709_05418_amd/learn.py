@@ -127,26 +127,44 @@ def reference(ctx, cloud, params, light_dir, ray_o, ray_d, spp, seed, batch=256,
     return mean, var
 
 
-def judge(ctx, cloud, net, precision, params, light_dir, ray_o, ray_d, spp, ref_spp, seed,
+def judge(ctx, cloud, net, precisions, params, light_dir, ray_o, ray_d, spp, ref_spp, seed,
           fallback_spp=0, log=None):
-    """Network image vs path-traced reference, and the direct-only image vs the same."""
-    t0 = time.time()
-    img, var, direct, nfb = ds.ds_render_rpnn(ctx.h, cloud.h, net.h, precision, params, light_dir,
-                                              ray_o, ray_d, spp, seed, fallback_spp,
-                                              count_fallback=True)
+    """Network images (one per (name, precision)) and the direct-only image, each against
+    one path-traced reference rendered once."""
     import torch
-    torch.cuda.synchronize()
-    t_net = time.time() - t0
+    renders = {}
+    for name, prec in precisions:
+        torch.cuda.synchronize()
+        t0 = time.time()
+        img, var, direct, nfb = ds.ds_render_rpnn(ctx.h, cloud.h, net.h, prec, params,
+                                                  light_dir, ray_o, ray_d, spp, seed,
+                                                  fallback_spp, count_fallback=True)
+        torch.cuda.synchronize()
+        renders[name] = (img, direct, nfb, time.time() - t0)
     t0 = time.time()
     ref, ref_var = reference(ctx, cloud, params, light_dir, ray_o, ray_d, ref_spp, seed, log=log)
     torch.cuda.synchronize()
     t_ref = time.time() - t0
-    l1, rmse = image_errors(img, ref)
-    l1d, rmsed = image_errors(direct, ref)
-    return {"rel_l1": l1, "rmse": rmse, "rel_l1_direct_only": l1d, "rmse_direct_only": rmsed,
-            "ref_noise_rel": float(math.sqrt(float(ref_var.sum())) / max(float(ref.sum()), 1e-300)),
-            "fallback_samples": nfb, "seconds_network": t_net, "seconds_reference": t_ref,
-            "image": img, "reference": ref, "direct": direct}
+    noise = float(math.sqrt(float(ref_var.sum())) / max(float(ref.sum()), 1e-300))
+    out = {}
+    for name, (img, direct, nfb, t_net) in renders.items():
+        l1, rmse = image_errors(img, ref)
+        l1d, rmsed = image_errors(direct, ref)
+        out[name] = {"rel_l1": l1, "rmse": rmse, "rel_l1_direct_only": l1d,
+                     "rmse_direct_only": rmsed, "ref_noise_rel": noise, "fallback_samples": nfb,
+                     "seconds_network": t_net, "seconds_reference": t_ref}
+    return out
+
+
+def quantize_on(ctx, net, cloud, n=65536, seed=77):
+    """FP8 form of net, calibrated on records sampled in cloud (the training
+    distribution of shading configurations)."""
+    pos, view, light, _ = ds.ds_sample_records(ctx.h, cloud.h, n, seed, want_attempts=False)
+    ds.ds_net_quantize(ctx.h, net.h, cloud.h, ds.DS_PREC_FP8, pos, view, light)
+
+
+JUDGE_KEYS = ("rel_l1", "rmse", "rel_l1_direct_only", "rmse_direct_only", "ref_noise_rel",
+              "seconds_network", "seconds_reference", "fallback_samples")
 
 
 def camera(width, height, cam_pos=(0.0, 0.12, 2.3), look_at=(0.0, 0.0, 0.0), fov_deg=42.0,
@@ -268,7 +286,9 @@ def main(argv=None):
     light = synth.table1_lights()["side"]
     o, dd = camera(args.width, args.height, seed=1)
     summary = {}
-    for name, prec in (("bf16", ds.DS_PREC_BF16), ("fp32", ds.DS_PREC_F32)):
+    quantize_on(ctx, net, jc)
+    precs = (("bf16", ds.DS_PREC_BF16), ("fp8", ds.DS_PREC_FP8), ("fp32", ds.DS_PREC_F32))
+    for name, prec in precs:
         torch.cuda.synchronize()
         tf = time.time()
         img, _, direct, nfb = ds.ds_render_rpnn(ctx.h, jc.h, net.h, prec, prm, light, o, dd,
@@ -282,11 +302,10 @@ def main(argv=None):
     cx0 = (args.width - args.crop) // 2
     cy0 = (args.height - args.crop) // 2
     co, cd = camera(args.width, args.height, crop=(cx0, cy0, args.crop, args.crop), seed=2)
-    for name, prec in (("bf16", ds.DS_PREC_BF16), ("fp32", ds.DS_PREC_F32)):
-        j = judge(ctx, jc, net, prec, prm, light, co, cd, args.crop_spp, args.ref_spp, 11,
-                  args.fallback_spp, log=log)
-        for k in ("rel_l1", "rmse", "rel_l1_direct_only", "rmse_direct_only", "ref_noise_rel",
-                  "seconds_network", "seconds_reference", "fallback_samples"):
+    js = judge(ctx, jc, net, precs, prm, light, co, cd, args.crop_spp, args.ref_spp, 11,
+               args.fallback_spp, log=log)
+    for name, j in js.items():
+        for k in JUDGE_KEYS:
             summary[f"crop_{k}_{name}"] = j[k]
         log(f"crop {args.crop}^2 {name}: rel L1 {j['rel_l1']:.4f} (direct only "
             f"{j['rel_l1_direct_only']:.4f}), RMSE {j['rmse']:.5f}; reference noise "
@@ -323,27 +342,30 @@ def judge_only(args, ctx, net, prm, log):
     light = synth.table1_lights()["side"]
     o, dd = camera(args.width, args.height, seed=1)
     summary = {}
-    torch.cuda.synchronize()
-    tf = time.time()
-    img, _, direct, nfb = ds.ds_render_rpnn(ctx.h, jc.h, net.h, ds.DS_PREC_BF16, prm, light, o, dd,
-                                            args.frame_spp, 5, args.fallback_spp,
-                                            count_fallback=True)
-    torch.cuda.synchronize()
-    summary["frame_ms_bf16"] = (time.time() - tf) * 1e3
-    log(f"{args.width}x{args.height} frame bf16, {args.frame_spp} spp: "
-        f"{summary['frame_ms_bf16']:.1f} ms, fallback samples {nfb}")
+    quantize_on(ctx, net, jc)
+    precs = (("bf16", ds.DS_PREC_BF16), ("fp8", ds.DS_PREC_FP8))
+    for name, prec in precs:
+        torch.cuda.synchronize()
+        tf = time.time()
+        img, _, direct, nfb = ds.ds_render_rpnn(ctx.h, jc.h, net.h, prec, prm, light, o, dd,
+                                                args.frame_spp, 5, args.fallback_spp,
+                                                count_fallback=True)
+        torch.cuda.synchronize()
+        summary[f"frame_ms_{name}"] = (time.time() - tf) * 1e3
+        log(f"{args.width}x{args.height} frame {name}, {args.frame_spp} spp: "
+            f"{summary[f'frame_ms_{name}']:.1f} ms, fallback samples {nfb}")
     cx0 = (args.width - args.crop) // 2
     cy0 = (args.height - args.crop) // 2
     co, cd = camera(args.width, args.height, crop=(cx0, cy0, args.crop, args.crop), seed=2)
-    j = judge(ctx, jc, net, ds.DS_PREC_BF16, prm, light, co, cd, args.crop_spp, args.ref_spp, 11,
-              args.fallback_spp, log=log)
-    for k in ("rel_l1", "rmse", "rel_l1_direct_only", "rmse_direct_only", "ref_noise_rel",
-              "seconds_network", "seconds_reference", "fallback_samples"):
-        summary[f"crop_{k}_bf16"] = j[k]
-    log(f"crop {args.crop}^2 bf16: rel L1 {j['rel_l1']:.4f} (direct only "
-        f"{j['rel_l1_direct_only']:.4f}), RMSE {j['rmse']:.5f}; reference noise "
-        f"{j['ref_noise_rel']:.4f}; network {j['seconds_network']:.2f}s vs reference "
-        f"{j['seconds_reference']:.2f}s ({args.ref_spp} spp)")
+    js = judge(ctx, jc, net, precs, prm, light, co, cd, args.crop_spp, args.ref_spp, 11,
+               args.fallback_spp, log=log)
+    for name, j in js.items():
+        for k in JUDGE_KEYS:
+            summary[f"crop_{k}_{name}"] = j[k]
+        log(f"crop {args.crop}^2 {name}: rel L1 {j['rel_l1']:.4f} (direct only "
+            f"{j['rel_l1_direct_only']:.4f}), RMSE {j['rmse']:.5f}; reference noise "
+            f"{j['ref_noise_rel']:.4f}; network {j['seconds_network']:.2f}s vs reference "
+            f"{j['seconds_reference']:.2f}s ({args.ref_spp} spp)")
     summary.update({"judge_n": args.judge_n, "frame": [args.width, args.height],
                     "crop": args.crop, "crop_spp": args.crop_spp, "ref_spp": args.ref_spp,
                     "theta": args.load_theta})

@@ -219,11 +219,16 @@ def test_trained_network_beats_direct_light_only(ctx):
             assert v1 < 0.25 * v0, res["held_out"]
             o, dd = _rays(40, 1, crop=True)
             ld = synth.table1_lights()["side"]
-            j = learn.judge(ctx, clouds[4], net, ds.DS_PREC_BF16, prm, ld, _cuda(o), _cuda(dd),
-                            16, 512, 77, fallback_spp=32)
-            print({k: v for k, v in j.items() if not hasattr(v, "shape")}, flush=True)
-            assert j["ref_noise_rel"] < 0.02
-            assert j["rel_l1"] < 0.4 and j["rel_l1"] < 0.5 * j["rel_l1_direct_only"]
+            learn.quantize_on(ctx, net, clouds[4], n=8192)
+            js = learn.judge(ctx, clouds[4], net, (("bf16", ds.DS_PREC_BF16),
+                                                   ("fp8", ds.DS_PREC_FP8)),
+                             prm, ld, _cuda(o), _cuda(dd), 16, 512, 77, fallback_spp=32)
+            print(js, flush=True)
+            for name, j in js.items():
+                assert j["ref_noise_rel"] < 0.02
+                assert j["rel_l1"] < 0.4 and j["rel_l1"] < 0.5 * j["rel_l1_direct_only"], name
+            # the FP8 image stays close to the BF16 one
+            assert abs(js["fp8"]["rel_l1"] - js["bf16"]["rel_l1"]) < 0.05
         finally:
             ds.ds_adam_destroy(opt)
             net.close()
