@@ -577,7 +577,7 @@ ds_status ds_cloud_create(ds_ctx *ctx, const void *density_dev, ds_dtype dtype, 
     c->mean = (double)sigma_max * sum / (double)count;
     c->L = n_levels;
     c->K = K;
-    int64_t off = 0, coff = 0;
+    int64_t off = 0, coff = 0, poff = 0;
     for (int i = 0; i < n_levels; ++i) {
         Level &l = c->lv[i];
         l.nx = level_dim(nx, i);
@@ -585,12 +585,15 @@ ds_status ds_cloud_create(ds_ctx *ctx, const void *density_dev, ds_dtype dtype, 
         l.nz = level_dim(nz, i);
         l.off = off;
         l.cell_off = coff;
+        l.pad_off = poff;
         l.h = (float)ldexp((double)voxel_size, i);
         off += (int64_t)l.nx * l.ny * l.nz;
         coff += (int64_t)(l.nx + 2) * (l.ny + 2) * (l.nz + 2);
+        poff += (int64_t)(l.nx + 3) * (l.ny + 3) * (l.nz + 3);
     }
     c->pyr_elems = off;
     c->n_cells = coff;
+    c->pad_elems = poff;
     if (mip_of_level) {
         memcpy(c->mips, mip_of_level, sizeof(int) * K);
     } else {
@@ -610,6 +613,11 @@ ds_status ds_cloud_create(ds_ctx *ctx, const void *density_dev, ds_dtype dtype, 
                   (long long)c->pyr_elems);
         return fail(DS_ERR_OOM);
     }
+    if (hipMalloc(&c->pyr_pad, sizeof(float) * c->pad_elems) != hipSuccess) {
+        set_error("ds_cloud_create: out of device memory for the padded pyramid (%lld floats)",
+                  (long long)c->pad_elems);
+        return fail(DS_ERR_OOM);
+    }
     if (hipMalloc(&c->cells, sizeof(uint4) * c->n_cells) != hipSuccess) {
         set_error("ds_cloud_create: out of device memory for the packed pyramid (%lld cells)",
                   (long long)c->n_cells);
@@ -622,6 +630,9 @@ ds_status ds_cloud_create(ds_ctx *ctx, const void *density_dev, ds_dtype dtype, 
     st = cloud_pack(ctx->stream, c->pyr, n_levels, c->lv, c->cells);
     if (st)
         return fail(st);
+    st = cloud_pad(ctx->stream, c->pyr, n_levels, c->lv, c->pyr_pad);
+    if (st)
+        return fail(st);
     st = tracer_prepare(c, density_dev, dtype);
     if (st)
         return fail(st);
@@ -632,10 +643,12 @@ ds_status ds_cloud_create(ds_ctx *ctx, const void *density_dev, ds_dtype dtype, 
         const Level &l = c->lv[c->mips[k]];
         double h = ldexp((double)voxel_size, c->mips[k]);
         double step = ldexp(1.0, k) / c->mean;
-        gl[k].data = c->pyr + l.off;
-        gl[k].nx = l.nx;
-        gl[k].ny = l.ny;
-        gl[k].nz = l.nz;
+        gl[k].pad = c->pyr_pad + l.pad_off;
+        gl[k].px = l.nx + 3;
+        gl[k].py = l.ny + 3;
+        gl[k].hx = (float)(l.nx + 1);  // padded coordinates are shifted by one
+        gl[k].hy = (float)(l.ny + 1);
+        gl[k].hz = (float)(l.nz + 1);
         gl[k].inv_h = (float)(1.0 / h);
         gl[k].step = (float)step;
         fl[k].cells = c->cells + l.cell_off;
@@ -744,6 +757,7 @@ ds_status ds_cloud_destroy(ds_cloud *c)
     if (c->ctx)
         (void)hipStreamSynchronize(c->ctx->stream);
     (void)hipFree(c->pyr);
+    (void)hipFree(c->pyr_pad);
     (void)hipFree(c->cells);
     (void)hipFree(c->tables);
     (void)hipFree(c->mu);

@@ -182,6 +182,24 @@ __global__ void __launch_bounds__(256) k_pack(const float *__restrict__ lv, int 
     }
 }
 
+// Zero-padded copy of a level: dims (n + 3) per axis, element (i, j, k) holding voxel
+// (i - 1, j - 1, k - 1) and zero where that voxel does not exist.  A trilinear sample
+// at padded coordinate u clamped to [0, n + 1] then reads in bounds and returns zero
+// outside the grid without per-tap tests.
+__global__ void __launch_bounds__(256) k_pad(const float *__restrict__ lv, int nx, int ny, int nz,
+                                             float *__restrict__ pad)
+{
+    const int64_t px = nx + 3, py = ny + 3, pz = nz + 3;
+    const int64_t total = px * py * pz;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
+        const int64_t i = idx % px - 1, r = idx / px;
+        const int64_t j = r % py - 1, k = r / py - 1;
+        const bool in = i >= 0 && j >= 0 && k >= 0 && i < nx && j < ny && k < nz;
+        pad[idx] = in ? lv[(k * ny + j) * nx + i] : 0.f;
+    }
+}
+
 int grid_for(int64_t n)
 {
     int64_t b = (n + 255) / 256;
@@ -296,6 +314,17 @@ ds_status cloud_pyramid(hipStream_t s, const void *d, ds_dtype dt, int nx, int n
     (void)hipFree(A);
     (void)hipFree(B);
     return st;
+}
+
+ds_status cloud_pad(hipStream_t s, const float *pyr, int L, const Level *lv, float *pad)
+{
+    for (int i = 0; i < L; ++i) {
+        const Level &l = lv[i];
+        int64_t n = (int64_t)(l.nx + 3) * (l.ny + 3) * (l.nz + 3);
+        k_pad<<<grid_for(n), 256, 0, s>>>(pyr + l.off, l.nx, l.ny, l.nz, pad + l.pad_off);
+    }
+    DS_HIP(hipGetLastError());
+    return DS_OK;
 }
 
 ds_status cloud_pack(hipStream_t s, const float *pyr, int L, const Level *lv, uint4 *cells)

@@ -1,6 +1,6 @@
 // Plain-form descriptor gather (Sec. 4.2, Fig. 5): per shading point the K levels of
-// the 5x5x9 light-oriented stencil, trilinearly interpolated from float32 mip levels,
-// written row by row to HBM together with gamma.
+// the 5x5x9 light-oriented stencil, trilinearly interpolated from the zero-padded
+// float32 mip levels, written row by row to HBM together with gamma.
 #include "internal.h"
 #include "frame.h"
 
@@ -24,64 +24,145 @@ __device__ __forceinline__ void store<uint16_t>(uint16_t *z, int64_t i, float v)
     z[i] = (uint16_t)(u >> 16);
 }
 
-// Voxel-centred trilinear interpolation with zero outside the level grid.
-__device__ __forceinline__ float trilinear(const float *__restrict__ d, int nx, int ny, int nz,
-                                           float ux, float uy, float uz)
+// Voxel-centred trilinear interpolation with zero outside the level grid, at padded
+// coordinate u (the voxel-centred coordinate plus one).  Clamping u to [0, n + 1]
+// changes nothing inside the grid and puts every sample outside it on zero border
+// elements, so the eight taps need no bounds tests.
+__device__ __forceinline__ float trilinear_padded(const GatherLevel &L, float ux, float uy,
+                                                  float uz)
 {
-    float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
-    float fx = ux - fx0, fy = uy - fy0, fz = uz - fz0;
-    int ix = (int)fx0, iy = (int)fy0, iz = (int)fz0;
-    float acc = 0.f;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
-        int a = ix + dx, b = iy + dy, e = iz + dz;
-        if (a >= 0 && b >= 0 && e >= 0 && a < nx && b < ny && e < nz) {
-            float w = (dx ? fx : 1.f - fx) * (dy ? fy : 1.f - fy) * (dz ? fz : 1.f - fz);
-            acc += w * d[((int64_t)e * ny + b) * nx + a];
-        }
-    }
-    return acc;
+    ux = __builtin_amdgcn_fmed3f(ux, 0.f, L.hx);
+    uy = __builtin_amdgcn_fmed3f(uy, 0.f, L.hy);
+    uz = __builtin_amdgcn_fmed3f(uz, 0.f, L.hz);
+    const float x0 = floorf(ux), y0 = floorf(uy), z0 = floorf(uz);
+    const float fx = ux - x0, fy = uy - y0, fz = uz - z0;
+    const int64_t sy = L.px, sz = (int64_t)L.px * L.py;
+    const float *c = L.pad + ((int64_t)z0 * L.py + (int)y0) * L.px + (int)x0;
+    const float a00 = fmaf(fx, c[1] - c[0], c[0]);
+    const float a01 = fmaf(fx, c[sy + 1] - c[sy], c[sy]);
+    const float a10 = fmaf(fx, c[sz + 1] - c[sz], c[sz]);
+    const float a11 = fmaf(fx, c[sz + sy + 1] - c[sz + sy], c[sz + sy]);
+    const float b0 = fmaf(fy, a01 - a00, a00), b1 = fmaf(fy, a11 - a10, a10);
+    return fmaf(fz, b1 - b0, b0);
 }
 
-// One block per point: the block's threads stride over the 225 K samples.
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_gather(GatherArgs a, int64_t p0, T *z, int64_t ldz,
-                                                     uint8_t *flags)
+constexpr int kGatherPts = 2;  // shading points per workgroup
+
+// Lattice geometry of one point at one stencil level, in padded voxel coordinates:
+// lattice point (ix, iy, iz) sits at u0 + ix a + iy b + iz c.
+struct LatticeGeom {
+    float u0[3], a[3], b[3], c[3];
+};
+
+size_t gather_lds_bytes(int K)
 {
-    int64_t p = p0 + blockIdx.x;
-    if (p >= a.P)
-        return;
-    T *row = z + (int64_t)blockIdx.x * ldz;
-    float x[3] = {a.pos[3 * p], a.pos[3 * p + 1], a.pos[3 * p + 2]};
-    Frame f;
-    bool ok = isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) &&
-              light_frame(&a.view[3 * p], &a.light[3 * p], f);
-    const int D = kStencil * a.K + 1;
-    if (!ok) {
-        for (int i = threadIdx.x; i < D; i += kThreads)
-            store<T>(row, i, 0.f);
-        if (flags && threadIdx.x == 0)
-            flags[p] = DS_FLAG_INVALID;
-        return;
-    }
-    for (int i = threadIdx.x; i < D - 1; i += kThreads) {
-        int k = i / kStencil, n = i - k * kStencil;
-        const GatherLevel L = a.lv[k];
-        int ix = n % 5, iy = (n / 5) % 5, iz = n / 25;
-        float ox = -1.f + 0.5f * ix, oy = -1.f + 0.5f * iy, oz = -1.f + 0.5f * iz;
-        float u[3];
+    return sizeof(float) * (size_t)kGatherPts * (kStencil * K + 1) +
+           sizeof(LatticeGeom) * (size_t)kGatherPts * K;
+}
+
+// kGatherPts points per workgroup.  One thread per (point, level) sets up the lattice
+// geometry; one thread per (point, level, stencil column (ix, iy)) then walks the nine
+// samples iz = 0..8 of that column into the points' rows staged in LDS; the rows leave
+// in coalesced stores (one linear run when the rows are contiguous).
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_gather(GatherArgs a, int64_t p0, int64_t np, T *z,
+                                                     int64_t ldz, uint8_t *flags)
+{
+    extern __shared__ float smem[];
+    __shared__ int ok_s[kGatherPts];
+    const int K = a.K, D = kStencil * K + 1, tid = threadIdx.x;
+    float *rows = smem;
+    LatticeGeom *geo = reinterpret_cast<LatticeGeom *>(smem + kGatherPts * D);
+    const int64_t pb = (int64_t)blockIdx.x * kGatherPts;  // first point (chunk-relative)
+    if (tid < kGatherPts * K) {
+        const int i = tid / K, k = tid - i * K;
+        const int64_t pl = pb + i;
+        LatticeGeom G = {};
+        bool ok = false;
+        float gamma = 0.f;
+        if (pl < np) {
+            const int64_t p = p0 + pl;
+            const float x[3] = {a.pos[3 * p], a.pos[3 * p + 1], a.pos[3 * p + 2]};
+            Frame f;
+            ok = isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) &&
+                 light_frame(&a.view[3 * p], &a.light[3 * p], f);
+            if (ok) {
+                const GatherLevel L = a.lv[k];
+                const float hs = 0.5f * L.step * L.inv_h;  // half a lattice unit, in voxels
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            float q = x[c] + L.step * (ox * f.X[c] + oy * f.Y[c] + oz * f.Z[c]);
-            u[c] = (q - a.amin[c]) * L.inv_h - 0.5f;
+                for (int c = 0; c < 3; ++c) {
+                    // lattice point (0, 0, 0) has offset (-1, -1, -1) mean free paths
+                    const float q = x[c] - L.step * (f.X[c] + f.Y[c] + f.Z[c]);
+                    G.u0[c] = (q - a.amin[c]) * L.inv_h + 0.5f;
+                    G.a[c] = hs * f.X[c];
+                    G.b[c] = hs * f.Y[c];
+                    G.c[c] = hs * f.Z[c];
+                }
+                gamma = f.gamma;
+            }
+            if (k == 0) {
+                rows[i * D + D - 1] = gamma;
+                if (flags)
+                    flags[p] = ok ? point_flags(x, f, a.amin, a.amax, a.inv_mean)
+                                  : (uint8_t)DS_FLAG_INVALID;
+            }
         }
-        store<T>(row, i, trilinear(L.data, L.nx, L.ny, L.nz, u[0], u[1], u[2]));
+        geo[i * K + k] = G;
+        if (k == 0)
+            ok_s[i] = ok;
     }
-    if (threadIdx.x == 0) {
-        store<T>(row, D - 1, f.gamma);
-        if (flags)
-            flags[p] = point_flags(x, f, a.amin, a.amax, a.inv_mean);
+    __syncthreads();
+    const int items = kGatherPts * K * 25;
+    for (int it = tid; it < items; it += kThreads) {
+        const int i = it / (K * 25), r = it - i * (K * 25);
+        const int k = r / 25, col = r - k * 25;
+        float *out = rows + i * D + k * kStencil + col;
+        if (!ok_s[i]) {
+#pragma unroll
+            for (int iz = 0; iz < 9; ++iz)
+                out[25 * iz] = 0.f;
+            continue;
+        }
+        const LatticeGeom G = geo[i * K + k];
+        const GatherLevel L = a.lv[k];
+        const float ix = (float)(col % 5), iy = (float)(col / 5);
+        float ub[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            ub[c] = fmaf(iy, G.b[c], fmaf(ix, G.a[c], G.u0[c]));
+#pragma unroll
+        for (int iz = 0; iz < 9; ++iz)
+            out[25 * iz] = trilinear_padded(L, fmaf((float)iz, G.c[0], ub[0]),
+                                            fmaf((float)iz, G.c[1], ub[1]),
+                                            fmaf((float)iz, G.c[2], ub[2]));
+    }
+    __syncthreads();
+    const int n = (int)(np - pb < kGatherPts ? np - pb : kGatherPts);
+    if (ldz == D) {
+        T *dst = z + pb * D;
+        const int len = n * D;
+        if constexpr (sizeof(T) == 4) {
+            // 16-byte stores from the first 16-byte boundary on; head and tail singly
+            const int head = (int)((16 - (reinterpret_cast<uintptr_t>(dst) & 15)) & 15) / 4;
+            const int h = head < len ? head : len;
+            if (tid < h)
+                store<T>(dst, tid, rows[tid]);
+            const int nv = (len - h) / 4;
+            float4 *dv = reinterpret_cast<float4 *>(dst + h);
+            for (int j = tid; j < nv; j += kThreads) {
+                const float *r = rows + h + 4 * j;
+                dv[j] = make_float4(r[0], r[1], r[2], r[3]);
+            }
+            for (int j = h + 4 * nv + tid; j < len; j += kThreads)
+                store<T>(dst, j, rows[j]);
+        } else {
+            for (int j = tid; j < len; j += kThreads)
+                store<T>(dst, j, rows[j]);
+        }
+    } else {
+        for (int i = 0; i < n; ++i)
+            for (int j = tid; j < D; j += kThreads)
+                store<T>(z + (pb + i) * ldz, j, rows[i * D + j]);
     }
 }
 
@@ -113,10 +194,13 @@ ds_status gather_plain(hipStream_t s, const GatherArgs &a, int64_t p0, int64_t n
 {
     if (np <= 0)
         return DS_OK;
+    const int64_t blocks = (np + kGatherPts - 1) / kGatherPts;
+    const size_t lds = gather_lds_bytes(a.K);
     if (odt == DS_F32)
-        k_gather<float><<<(unsigned)np, kThreads, 0, s>>>(a, p0, (float *)z, ldz, flags);
+        k_gather<float><<<(unsigned)blocks, kThreads, lds, s>>>(a, p0, np, (float *)z, ldz, flags);
     else
-        k_gather<uint16_t><<<(unsigned)np, kThreads, 0, s>>>(a, p0, (uint16_t *)z, ldz, flags);
+        k_gather<uint16_t><<<(unsigned)blocks, kThreads, lds, s>>>(a, p0, np, (uint16_t *)z, ldz,
+                                                                   flags);
     DS_HIP(hipGetLastError());
     return DS_OK;
 }

@@ -40,6 +40,7 @@ struct Level {
     int nx, ny, nz;          // level dims (ceil(n / 2^i))
     int64_t off;             // offset in the float32 pyramid (elements)
     int64_t cell_off;        // offset in the corner-packed pyramid (cells)
+    int64_t pad_off;         // offset in the zero-padded float32 pyramid (elements)
     float h;                 // voxel size (world units)
 };
 
@@ -69,6 +70,8 @@ struct ds_cloud {
     int mips[ds::kMaxK];
     float *pyr = nullptr;      // float32 levels, concatenated
     int64_t pyr_elems = 0;
+    float *pyr_pad = nullptr;  // the same levels with zero borders (1 below, 2 above per axis)
+    int64_t pad_elems = 0;
     uint4 *cells = nullptr;    // corner-packed FP16 levels (8 corners per cell)
     int64_t n_cells = 0;
     void *tables = nullptr;    // device: GatherLevel[K] then FusedLevel[K]
@@ -131,11 +134,13 @@ ds_status cloud_mean(hipStream_t s, const void *d, ds_dtype dt, int64_t n, doubl
 ds_status cloud_pyramid(hipStream_t s, const void *d, ds_dtype dt, int nx, int ny, int nz,
                         float scale, int L, const Level *lv, float *pyr);
 ds_status cloud_pack(hipStream_t s, const float *pyr, int L, const Level *lv, uint4 *cells);
+ds_status cloud_pad(hipStream_t s, const float *pyr, int L, const Level *lv, float *pad);
 
 // gather.hip
 struct GatherLevel {
-    const float *data;  // level base (float32)
-    int nx, ny, nz;
+    const float *pad;   // zero-padded level: element (i, j, k) holds voxel (i-1, j-1, k-1)
+    int px, py;         // padded dims in x and y (level dims + 3)
+    float hx, hy, hz;   // clamp bounds of the padded coordinate (level dims + 1)
     float inv_h;        // 1 / h_m
     float step;         // 2^(k-1) / mean  (world units per lattice unit of 1 mfp)
 };
