@@ -154,11 +154,11 @@ ds_status ds_gather(ds_ctx *ctx, const ds_cloud *cloud, const float *pos, const 
                     uint8_t *flags);
 
 /* The descriptor as the fused kernel gathers it: the same samples as ds_gather,
- * interpolated in FP32 from the corner-packed FP16 copy of the pyramid (eight
- * corners per 16-byte cell, values rounded to nearest even and saturated at the
- * largest finite FP16 value), written as float32 rows of 225K+1
- * values in ds_gather's order.  For checking the fused path; z_out is device
- * memory of P*(225K+1) floats. */
+ * interpolated from the corner-packed FP16 copy of the pyramid (eight corners per
+ * 16-byte cell, values rounded to nearest even and saturated at the largest finite
+ * FP16 value; the y and z lerps in FP16 arithmetic with the fractions rounded toward
+ * zero, the x lerp in FP32), written as float32 rows of 225K+1 values in ds_gather's
+ * order.  For checking the fused path; z_out is device memory of P*(225K+1) floats. */
 ds_status ds_gather_packed(ds_ctx *ctx, const ds_cloud *cloud, const float *pos,
                            const float *view_dir, const float *light_dir, int64_t P,
                            float *z_out);

@@ -93,8 +93,13 @@ __device__ __forceinline__ void issue_one(gcell_ptr cells, const FusedLevel &L, 
     fx = __builtin_amdgcn_fractf(ux);
     fy = __builtin_amdgcn_fractf(uy);
     fz = __builtin_amdgcn_fractf(uz);
-    // 24-bit multiplies: cell dims stay below 2^13 and j + cy k below 2^24
-    const uint32_t idx = i + __umul24((uint32_t)L.cx, j + __umul24((uint32_t)L.cy, k));
+    // 24-bit multiply-adds: cell dims stay below 2^13 and j + cy k below 2^24.  The empty
+    // asm statements keep both partial indices 32-bit values in registers, so the compiler
+    // emits two full-rate v_mad_u32_u24 instead of widening one into v_mad_u64_u32.
+    uint32_t t = j + __umul24((uint32_t)L.cy, k);
+    asm volatile("" : "+v"(t));
+    uint32_t idx = i + __umul24((uint32_t)L.cx, t);
+    asm volatile("" : "+v"(idx));
     v = cells[idx];
 }
 
@@ -111,15 +116,23 @@ __device__ __forceinline__ float lerp_pair(uint32_t w, float fx, float gx)
     return fmaf((float)v[1], fx, fmaf((float)v[0], gx, 0.f));
 }
 
-// Trilinear value of a sample from its 8 corners (FP16) in FP32.
+// Trilinear value of a sample from its 8 corners (FP16): the y and z lerps run on the
+// (x0, x1) corner pairs as packed FP16 arithmetic (two lerps per instruction), the
+// final x lerp in FP32 on the two halves in place.
 __device__ __forceinline__ float finish_one(const u32x4 &v, float fx, float fy, float fz)
 {
-    const float gx = 1.f - fx;
-    const float x00 = lerp_pair(v[0], fx, gx);
-    const float x10 = lerp_pair(v[1], fx, gx);
-    const float x01 = lerp_pair(v[2], fx, gx);
-    const float x11 = lerp_pair(v[3], fx, gx);
-    return lerp(lerp(x00, x10, fy), lerp(x01, x11, fy), fz);
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    // element copies first: a bit cast applied to a vector element itself reads the
+    // vector's first element (seen with this compiler)
+    const uint32_t u0 = v[0], u1 = v[1], u2 = v[2], u3 = v[3];
+    const h2 w0 = __builtin_bit_cast(h2, u0), w1 = __builtin_bit_cast(h2, u1);
+    const h2 w2 = __builtin_bit_cast(h2, u2), w3 = __builtin_bit_cast(h2, u3);
+    const h2 t = __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(fy, fz));  // (fy, fz)
+    const h2 a = w0 + t[0] * (w1 - w0);  // y lerps in the z0 plane, both x ends
+    const h2 b = w2 + t[0] * (w3 - w2);  // the same in the z1 plane
+    const h2 c = a + t[1] * (b - a);     // z lerp
+    const _Float16 d = c[1] - c[0];
+    return fmaf(fx, (float)d, (float)c[0]);
 }
 
 // Lattice tables shared by a workgroup: (ix, iy) of stencil columns 0..23 (the
