@@ -154,23 +154,49 @@ __device__ __forceinline__ void init_tables(int tid, float4 *plane, float2 *cols
         cols[tid] = make_float2((float)(tid % 5), (float)(tid / 5));
 }
 
-// Halves 0..11 (chunks 0..5): lane group g walks stencil column 4c + g along z,
-// iz = 4 (h & 1) + j, so consecutive samples differ by the step vector c.
-__device__ __forceinline__ void issue_column_half(gcell_ptr cells, const FusedLevel &L,
-                                                  const PtLevel &q, int h, int g,
-                                                  const float2 *cols, Pending &p)
+// Four samples of a stencil column from the coordinate (bx, by, bz) of its first one:
+// consecutive samples along z differ by the step vector c.
+__device__ __forceinline__ void issue_four(gcell_ptr cells, const FusedLevel &L, const PtLevel &q,
+                                           float bx, float by, float bz, Pending &p)
 {
-    // (ix, iy) of column 4 (h >> 1) + g from the table (see init_tables)
-    const float2 xy = cols[4 * (h >> 1) + g];
-    const float ix = xy.x, iy = xy.y, iz0 = (float)(4 * (h & 1));
-    const float bx = q.u0[0] + ix * q.a[0] + iy * q.b[0] + iz0 * q.c[0];
-    const float by = q.u0[1] + ix * q.a[1] + iy * q.b[1] + iz0 * q.c[1];
-    const float bz = q.u0[2] + ix * q.a[2] + iy * q.b[2] + iz0 * q.c[2];
     issue_one(cells, L, bx, by, bz, p.v[0], p.fx[0], p.fy[0], p.fz[0]);
 #pragma unroll
     for (int j = 1; j < 4; ++j)
         issue_one(cells, L, fmaf((float)j, q.c[0], bx), fmaf((float)j, q.c[1], by),
                   fmaf((float)j, q.c[2], bz), p.v[j], p.fx[j], p.fy[j], p.fz[j]);
+}
+
+// Coordinate of lattice point (ix, iy, 0) of stencil column 4 s + g, (ix, iy) from the
+// table (see init_tables).
+__device__ __forceinline__ float3 column_base(const PtLevel &q, int s, int g, const float2 *cols)
+{
+    const float2 xy = cols[4 * s + g];
+    return make_float3(fmaf(xy.y, q.b[0], fmaf(xy.x, q.a[0], q.u0[0])),
+                       fmaf(xy.y, q.b[1], fmaf(xy.x, q.a[1], q.u0[1])),
+                       fmaf(xy.y, q.b[2], fmaf(xy.x, q.a[2], q.u0[2])));
+}
+
+// Both halves (iz = 0..3 into lo, 4..7 into hi) of column 4 s + g from one base.
+__device__ __forceinline__ void issue_column(gcell_ptr cells, const FusedLevel &L,
+                                             const PtLevel &q, int s, int g, const float2 *cols,
+                                             Pending &lo, Pending &hi)
+{
+    const float3 b = column_base(q, s, g, cols);
+    issue_four(cells, L, q, b.x, b.y, b.z, lo);
+    issue_four(cells, L, q, fmaf(4.f, q.c[0], b.x), fmaf(4.f, q.c[1], b.y),
+               fmaf(4.f, q.c[2], b.z), hi);
+}
+
+// Halves 0..11 (chunks 0..5): lane group g walks stencil column 4c + g along z,
+// iz = 4 (h & 1) + j.
+__device__ __forceinline__ void issue_column_half(gcell_ptr cells, const FusedLevel &L,
+                                                  const PtLevel &q, int h, int g,
+                                                  const float2 *cols, Pending &p)
+{
+    const float3 b = column_base(q, h >> 1, g, cols);
+    const float iz0 = (float)(4 * (h & 1));
+    issue_four(cells, L, q, fmaf(iz0, q.c[0], b.x), fmaf(iz0, q.c[1], b.y),
+               fmaf(iz0, q.c[2], b.z), p);
 }
 
 // Halves 12, 13 (chunk 6) mix directions: lattice coordinates come from a table
@@ -775,8 +801,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
             PtLevel q;
             level_from_geom(L, geom[(tid >> 6) * 16 + n], q);
             Pending pa, pb;
-            issue_column_half(cells, L, q, 0, g, cols, pa);
-            issue_column_half(cells, L, q, 1, g, cols, pb);
+            issue_column(cells, L, q, 0, g, cols, pa, pb);
             const float *b1 = vec + (size_t)k * 2 * WP;
             const float *b2 = b1 + WP;
             // the first layer accumulates onto its bias
@@ -787,14 +812,17 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
             for (int c = 0; c < 5; ++c) {  // chunks 0..4: halves 2c, 2c+1 in, 2c+2, 2c+3 out
                 ws.fetch(tid);
                 f4 lo, hi;
+                // both halves of the next column share its base
+                const float3 cb = column_base(q, c + 1, g, cols);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
-                issue_column_half(cells, L, q, 2 * c + 2, g, cols, pa);
+                issue_four(cells, L, q, cb.x, cb.y, cb.z, pa);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
-                issue_column_half(cells, L, q, 2 * c + 3, g, cols, pb);
+                issue_four(cells, L, q, fmaf(4.f, q.c[0], cb.x), fmaf(4.f, q.c[1], cb.y),
+                           fmaf(4.f, q.c[2], cb.z), pb);
                 mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
                 ws.template next<8>(tid);
             }

@@ -37,13 +37,7 @@ __device__ __forceinline__ float trilinear_padded(const GatherLevel &L, float ux
     const float x0 = floorf(ux), y0 = floorf(uy), z0 = floorf(uz);
     const float fx = ux - x0, fy = uy - y0, fz = uz - z0;
     const int64_t sy = L.px, sz = (int64_t)L.px * L.py;
-    // 32-bit index by 24-bit multiply-adds: padded dims stay below 2^13 and a level below
-    // 2^31 elements (the empty asm keeps the partial index from being widened to 64 bits)
-    uint32_t t = (uint32_t)y0 + __umul24((uint32_t)L.py, (uint32_t)z0);
-    asm volatile("" : "+v"(t));
-    uint32_t idx = (uint32_t)x0 + __umul24((uint32_t)L.px, t);
-    asm volatile("" : "+v"(idx));
-    const float *c = L.pad + idx;
+    const float *c = L.pad + ((int64_t)z0 * L.py + (int)y0) * L.px + (int)x0;
     const float a00 = fmaf(fx, c[1] - c[0], c[0]);
     const float a01 = fmaf(fx, c[sy + 1] - c[sy], c[sy]);
     const float a10 = fmaf(fx, c[sz + 1] - c[sz], c[sz]);
