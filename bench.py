@@ -235,7 +235,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this library has no multi-GPU path "
-              "(shading points are independent; see DESIGN.md for how it would shard)",
+              "(shading points are independent: each GPU would take its own range of point tiles)",
               file=sys.stderr)
         sys.exit(2)
 
