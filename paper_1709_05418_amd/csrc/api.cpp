@@ -161,6 +161,38 @@ void gather_args(const ds_cloud *c, const float *pos, const float *view, const f
     a.lv = static_cast<const GatherLevel *>(c->tables);
 }
 
+// Builds the corner-packed float32 levels of the cloud if they do not exist yet and points
+// the gather table at them (synchronises the context stream the first time).
+ds_status gather_cells(ds_ctx *ctx, const ds_cloud *c)
+{
+    if (c->cells32)
+        return DS_OK;
+    float4 *cells = nullptr;
+    DS_CHECK(hipMalloc(&cells, sizeof(float4) * 2 * (size_t)c->n_cells) == hipSuccess, DS_ERR_OOM,
+             "out of device memory for the float32 corner cells (%lld cells of 32 bytes)",
+             (long long)c->n_cells);
+    ds_status st = cloud_pack32(ctx->stream, c->pyr, c->L, c->lv, cells);
+    std::vector<GatherLevel> gl((size_t)c->K);
+    hipError_t e = st ? hipSuccess
+                      : hipMemcpyAsync(gl.data(), c->tables, sizeof(GatherLevel) * c->K,
+                                       hipMemcpyDeviceToHost, ctx->stream);
+    if (!st && e == hipSuccess)
+        e = hipStreamSynchronize(ctx->stream);
+    if (!st && e == hipSuccess) {
+        for (int k = 0; k < c->K; ++k)
+            gl[k].cells = cells + 2 * c->lv[c->mips[k]].cell_off;
+        e = hipMemcpy(c->tables, gl.data(), sizeof(GatherLevel) * c->K, hipMemcpyHostToDevice);
+    }
+    if (!st && e != hipSuccess)
+        st = hip_fail(e, "building the float32 corner cells");
+    if (st) {
+        (void)hipFree(cells);
+        return st;
+    }
+    c->cells32 = cells;
+    return DS_OK;
+}
+
 constexpr int64_t kChunk = 65536;  // points per plain-form chunk
 
 // Plain FP32 network over `rows` descriptor rows (ldz = 225K + 1).
@@ -577,7 +609,7 @@ ds_status ds_cloud_create(ds_ctx *ctx, const void *density_dev, ds_dtype dtype, 
     c->mean = (double)sigma_max * sum / (double)count;
     c->L = n_levels;
     c->K = K;
-    int64_t off = 0, coff = 0, poff = 0;
+    int64_t off = 0, coff = 0;
     for (int i = 0; i < n_levels; ++i) {
         Level &l = c->lv[i];
         l.nx = level_dim(nx, i);
@@ -585,15 +617,12 @@ ds_status ds_cloud_create(ds_ctx *ctx, const void *density_dev, ds_dtype dtype, 
         l.nz = level_dim(nz, i);
         l.off = off;
         l.cell_off = coff;
-        l.pad_off = poff;
         l.h = (float)ldexp((double)voxel_size, i);
         off += (int64_t)l.nx * l.ny * l.nz;
         coff += (int64_t)(l.nx + 2) * (l.ny + 2) * (l.nz + 2);
-        poff += (int64_t)(l.nx + 3) * (l.ny + 3) * (l.nz + 3);
     }
     c->pyr_elems = off;
     c->n_cells = coff;
-    c->pad_elems = poff;
     if (mip_of_level) {
         memcpy(c->mips, mip_of_level, sizeof(int) * K);
     } else {
@@ -613,11 +642,6 @@ ds_status ds_cloud_create(ds_ctx *ctx, const void *density_dev, ds_dtype dtype, 
                   (long long)c->pyr_elems);
         return fail(DS_ERR_OOM);
     }
-    if (hipMalloc(&c->pyr_pad, sizeof(float) * c->pad_elems) != hipSuccess) {
-        set_error("ds_cloud_create: out of device memory for the padded pyramid (%lld floats)",
-                  (long long)c->pad_elems);
-        return fail(DS_ERR_OOM);
-    }
     if (hipMalloc(&c->cells, sizeof(uint4) * c->n_cells) != hipSuccess) {
         set_error("ds_cloud_create: out of device memory for the packed pyramid (%lld cells)",
                   (long long)c->n_cells);
@@ -630,9 +654,6 @@ ds_status ds_cloud_create(ds_ctx *ctx, const void *density_dev, ds_dtype dtype, 
     st = cloud_pack(ctx->stream, c->pyr, n_levels, c->lv, c->cells);
     if (st)
         return fail(st);
-    st = cloud_pad(ctx->stream, c->pyr, n_levels, c->lv, c->pyr_pad);
-    if (st)
-        return fail(st);
     st = tracer_prepare(c, density_dev, dtype);
     if (st)
         return fail(st);
@@ -643,10 +664,10 @@ ds_status ds_cloud_create(ds_ctx *ctx, const void *density_dev, ds_dtype dtype, 
         const Level &l = c->lv[c->mips[k]];
         double h = ldexp((double)voxel_size, c->mips[k]);
         double step = ldexp(1.0, k) / c->mean;
-        gl[k].pad = c->pyr_pad + l.pad_off;
-        gl[k].px = l.nx + 3;
-        gl[k].py = l.ny + 3;
-        gl[k].hx = (float)(l.nx + 1);  // padded coordinates are shifted by one
+        gl[k].cells = nullptr;  // set by gather_cells on the first plain-form call
+        gl[k].cx = l.nx + 2;
+        gl[k].cy = l.ny + 2;
+        gl[k].hx = (float)(l.nx + 1);  // cell coordinates are shifted by one
         gl[k].hy = (float)(l.ny + 1);
         gl[k].hz = (float)(l.nz + 1);
         gl[k].inv_h = (float)(1.0 / h);
@@ -757,7 +778,7 @@ ds_status ds_cloud_destroy(ds_cloud *c)
     if (c->ctx)
         (void)hipStreamSynchronize(c->ctx->stream);
     (void)hipFree(c->pyr);
-    (void)hipFree(c->pyr_pad);
+    (void)hipFree(c->cells32);
     (void)hipFree(c->cells);
     (void)hipFree(c->tables);
     (void)hipFree(c->mu);
@@ -871,6 +892,9 @@ ds_status ds_gather(ds_ctx *ctx, const ds_cloud *cloud, const float *pos, const 
         return DS_OK;
     DS_CHECK(pos && view_dir && light_dir && z_out, DS_ERR_INVALID_ARG,
              "ds_gather: NULL device pointer");
+    ds_status st = gather_cells(ctx, cloud);
+    if (st)
+        return st;
     GatherArgs a;
     gather_args(cloud, pos, view_dir, light_dir, P, a);
     return gather_plain(ctx->stream, a, 0, P, out_dtype, z_out, kStencil * cloud->K + 1, flags);
@@ -920,6 +944,8 @@ static ds_status predict_plain(ds_ctx *ctx, const ds_cloud *cloud, const ds_net 
     const int64_t rows = P < kChunk ? P : kChunk;
     size_t need = sizeof(float) * (size_t)rows * ((size_t)D + 3 * net->W) + (size_t)rows;
     ds_status st = ensure_ws(ctx, need);
+    if (!st)
+        st = gather_cells(ctx, cloud);
     if (st)
         return st;
     float *z = static_cast<float *>(ctx->ws);
@@ -1556,6 +1582,9 @@ ds_status ds_make_records(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_pa
         return st;
     st = tracer_li(s, cloud, tp, p, v, l, N, spp, derived_key(seed, 0),
                    static_cast<double *>(ctx->ws), m, li_var);
+    if (st)
+        return st;
+    st = gather_cells(ctx, cloud);
     if (st)
         return st;
     GatherArgs ga;

@@ -182,21 +182,27 @@ __global__ void __launch_bounds__(256) k_pack(const float *__restrict__ lv, int 
     }
 }
 
-// Zero-padded copy of a level: dims (n + 3) per axis, element (i, j, k) holding voxel
-// (i - 1, j - 1, k - 1) and zero where that voxel does not exist.  A trilinear sample
-// at padded coordinate u clamped to [0, n + 1] then reads in bounds and returns zero
-// outside the grid without per-tap tests.
-__global__ void __launch_bounds__(256) k_pad(const float *__restrict__ lv, int nx, int ny, int nz,
-                                             float *__restrict__ pad)
+// Corner-packed float32 level (the plain gather's copy): cell (i, j, k) holds the 8
+// corners of the lattice cell whose lower corner is voxel (i - 1, j - 1, k - 1), corner
+// c = dx + 2 dy + 4 dz at float c of the cell's 32 bytes, zero outside the grid.
+__global__ void __launch_bounds__(256) k_pack32(const float *__restrict__ lv, int nx, int ny,
+                                                int nz, float4 *__restrict__ cells)
 {
-    const int64_t px = nx + 3, py = ny + 3, pz = nz + 3;
-    const int64_t total = px * py * pz;
+    const int64_t cx = nx + 2, cy = ny + 2, cz = nz + 2;
+    const int64_t total = cx * cy * cz;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
-        const int64_t i = idx % px - 1, r = idx / px;
-        const int64_t j = r % py - 1, k = r / py - 1;
-        const bool in = i >= 0 && j >= 0 && k >= 0 && i < nx && j < ny && k < nz;
-        pad[idx] = in ? lv[(k * ny + j) * nx + i] : 0.f;
+        const int64_t i = idx % cx - 1, r = idx / cx;
+        const int64_t j = r % cy - 1, k = r / cy - 1;
+        float v[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int64_t a = i + (c & 1), b = j + ((c >> 1) & 1), e = k + ((c >> 2) & 1);
+            const bool in = a >= 0 && b >= 0 && e >= 0 && a < nx && b < ny && e < nz;
+            v[c] = in ? lv[(e * ny + b) * nx + a] : 0.f;
+        }
+        cells[2 * idx] = make_float4(v[0], v[1], v[2], v[3]);
+        cells[2 * idx + 1] = make_float4(v[4], v[5], v[6], v[7]);
     }
 }
 
@@ -316,12 +322,12 @@ ds_status cloud_pyramid(hipStream_t s, const void *d, ds_dtype dt, int nx, int n
     return st;
 }
 
-ds_status cloud_pad(hipStream_t s, const float *pyr, int L, const Level *lv, float *pad)
+ds_status cloud_pack32(hipStream_t s, const float *pyr, int L, const Level *lv, float4 *cells)
 {
     for (int i = 0; i < L; ++i) {
         const Level &l = lv[i];
-        int64_t n = (int64_t)(l.nx + 3) * (l.ny + 3) * (l.nz + 3);
-        k_pad<<<grid_for(n), 256, 0, s>>>(pyr + l.off, l.nx, l.ny, l.nz, pad + l.pad_off);
+        int64_t n = (int64_t)(l.nx + 2) * (l.ny + 2) * (l.nz + 2);
+        k_pack32<<<grid_for(n), 256, 0, s>>>(pyr + l.off, l.nx, l.ny, l.nz, cells + 2 * l.cell_off);
     }
     DS_HIP(hipGetLastError());
     return DS_OK;

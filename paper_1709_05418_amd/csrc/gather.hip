@@ -1,6 +1,6 @@
 // Plain-form descriptor gather (Sec. 4.2, Fig. 5): per shading point the K levels of
-// the 5x5x9 light-oriented stencil, trilinearly interpolated from the zero-padded
-// float32 mip levels, written row by row to HBM together with gamma.
+// the 5x5x9 light-oriented stencil, trilinearly interpolated from corner-packed float32
+// copies of the mip levels, written row by row to HBM together with gamma.
 #include "internal.h"
 #include "frame.h"
 
@@ -24,31 +24,31 @@ __device__ __forceinline__ void store<uint16_t>(uint16_t *z, int64_t i, float v)
     z[i] = (uint16_t)(u >> 16);
 }
 
-// Voxel-centred trilinear interpolation with zero outside the level grid, at padded
-// coordinate u (the voxel-centred coordinate plus one).  Clamping u to [0, n + 1]
-// changes nothing inside the grid and puts every sample outside it on zero border
-// elements, so the eight taps need no bounds tests.
-__device__ __forceinline__ float trilinear_padded(const GatherLevel &L, float ux, float uy,
-                                                  float uz)
+// Voxel-centred trilinear interpolation with zero outside the level grid, at the cell
+// coordinate u (the voxel-centred coordinate plus one).  Clamping u to [0, n + 1] changes
+// nothing inside the grid and puts every sample outside it on all-zero border cells, so
+// the eight corners need no bounds tests; they arrive in two 16-byte loads.
+__device__ __forceinline__ float trilinear_cells(const GatherLevel &L, float ux, float uy,
+                                                 float uz)
 {
     ux = __builtin_amdgcn_fmed3f(ux, 0.f, L.hx);
     uy = __builtin_amdgcn_fmed3f(uy, 0.f, L.hy);
     uz = __builtin_amdgcn_fmed3f(uz, 0.f, L.hz);
-    const float x0 = floorf(ux), y0 = floorf(uy), z0 = floorf(uz);
-    const float fx = ux - x0, fy = uy - y0, fz = uz - z0;
-    const int64_t sy = L.px, sz = (int64_t)L.px * L.py;
-    const float *c = L.pad + ((int64_t)z0 * L.py + (int)y0) * L.px + (int)x0;
-    const float a00 = fmaf(fx, c[1] - c[0], c[0]);
-    const float a01 = fmaf(fx, c[sy + 1] - c[sy], c[sy]);
-    const float a10 = fmaf(fx, c[sz + 1] - c[sz], c[sz]);
-    const float a11 = fmaf(fx, c[sz + sy + 1] - c[sz + sy], c[sz + sy]);
-    const float b0 = fmaf(fy, a01 - a00, a00), b1 = fmaf(fy, a11 - a10, a10);
+    const uint32_t i = (uint32_t)ux, j = (uint32_t)uy, k = (uint32_t)uz;
+    const float fx = __builtin_amdgcn_fractf(ux), fy = __builtin_amdgcn_fractf(uy),
+                fz = __builtin_amdgcn_fractf(uz);
+    const int64_t cell = (int64_t)i + (int64_t)L.cx * ((int64_t)j + (int64_t)L.cy * k);
+    const float4 lo = L.cells[2 * cell], hi = L.cells[2 * cell + 1];
+    // corner c = dx + 2 dy + 4 dz
+    const float a00 = fmaf(fx, lo.y - lo.x, lo.x), a10 = fmaf(fx, lo.w - lo.z, lo.z);
+    const float a01 = fmaf(fx, hi.y - hi.x, hi.x), a11 = fmaf(fx, hi.w - hi.z, hi.z);
+    const float b0 = fmaf(fy, a10 - a00, a00), b1 = fmaf(fy, a11 - a01, a01);
     return fmaf(fz, b1 - b0, b0);
 }
 
 constexpr int kGatherPts = 2;  // shading points per workgroup
 
-// Lattice geometry of one point at one stencil level, in padded voxel coordinates:
+// Lattice geometry of one point at one stencil level, in cell coordinates:
 // lattice point (ix, iy, iz) sits at u0 + ix a + iy b + iz c.
 struct LatticeGeom {
     float u0[3], a[3], b[3], c[3];
@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(kThreads) k_gather(GatherArgs a, int64_t p0, i
             ub[c] = fmaf(iy, G.b[c], fmaf(ix, G.a[c], G.u0[c]));
 #pragma unroll
         for (int iz = 0; iz < 9; ++iz)
-            out[25 * iz] = trilinear_padded(L, fmaf((float)iz, G.c[0], ub[0]),
+            out[25 * iz] = trilinear_cells(L, fmaf((float)iz, G.c[0], ub[0]),
                                             fmaf((float)iz, G.c[1], ub[1]),
                                             fmaf((float)iz, G.c[2], ub[2]));
     }

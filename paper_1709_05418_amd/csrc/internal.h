@@ -39,8 +39,7 @@ constexpr int kMaxK = 16;
 struct Level {
     int nx, ny, nz;          // level dims (ceil(n / 2^i))
     int64_t off;             // offset in the float32 pyramid (elements)
-    int64_t cell_off;        // offset in the corner-packed pyramid (cells)
-    int64_t pad_off;         // offset in the zero-padded float32 pyramid (elements)
+    int64_t cell_off;        // offset in the corner-packed pyramids (cells)
     float h;                 // voxel size (world units)
 };
 
@@ -70,8 +69,9 @@ struct ds_cloud {
     int mips[ds::kMaxK];
     float *pyr = nullptr;      // float32 levels, concatenated
     int64_t pyr_elems = 0;
-    float *pyr_pad = nullptr;  // the same levels with zero borders (1 below, 2 above per axis)
-    int64_t pad_elems = 0;
+    // corner-packed float32 levels for the plain gather (8 corners, 32 bytes per cell), built
+    // on the first plain-form call; the gather table points at them from then on
+    mutable float4 *cells32 = nullptr;
     uint4 *cells = nullptr;    // corner-packed FP16 levels (8 corners per cell)
     int64_t n_cells = 0;
     void *tables = nullptr;    // device: GatherLevel[K] then FusedLevel[K]
@@ -134,15 +134,15 @@ ds_status cloud_mean(hipStream_t s, const void *d, ds_dtype dt, int64_t n, doubl
 ds_status cloud_pyramid(hipStream_t s, const void *d, ds_dtype dt, int nx, int ny, int nz,
                         float scale, int L, const Level *lv, float *pyr);
 ds_status cloud_pack(hipStream_t s, const float *pyr, int L, const Level *lv, uint4 *cells);
-ds_status cloud_pad(hipStream_t s, const float *pyr, int L, const Level *lv, float *pad);
+ds_status cloud_pack32(hipStream_t s, const float *pyr, int L, const Level *lv, float4 *cells);
 
 // gather.hip
 struct GatherLevel {
-    const float *pad;   // zero-padded level: element (i, j, k) holds voxel (i-1, j-1, k-1)
-    int px, py;         // padded dims in x and y (level dims + 3)
-    float hx, hy, hz;   // clamp bounds of the padded coordinate (level dims + 1)
-    float inv_h;        // 1 / h_m
-    float step;         // 2^(k-1) / mean  (world units per lattice unit of 1 mfp)
+    const float4 *cells;  // corner-packed float32 level: cell c = entries 2c, 2c + 1
+    int cx, cy;           // cell-grid dims in x and y (level dims + 2)
+    float hx, hy, hz;     // clamp bounds of the shifted cell coordinate (level dims + 1)
+    float inv_h;          // 1 / h_m
+    float step;           // 2^(k-1) / mean  (world units per lattice unit of 1 mfp)
 };
 struct GatherArgs {
     const float *pos, *view, *light;
