@@ -71,7 +71,6 @@ struct PtLevel {
     float u0[3], a[3], b[3], c[3];
 };
 
-__device__ __forceinline__ float lerp(float a, float b, float t) { return fmaf(t, b - a, a); }
 
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 typedef const __attribute__((address_space(1))) u32x4 *gcell_ptr;
@@ -101,19 +100,6 @@ __device__ __forceinline__ void issue_one(gcell_ptr cells, const FusedLevel &L, 
     uint32_t idx = i + __umul24((uint32_t)L.cx, t);
     asm volatile("" : "+v"(idx));
     v = cells[idx];
-}
-
-// Trilinear interpolation of a loaded cell in FP32.  (Corners stored as BF16 pairs
-// would need a shift or a mask per corner before the lerps; a v_dot2c_f32_bf16
-// form of the x lerps read its zeroed accumulator register stale when the
-// compiler placed the zeroing move right before it.)
-// x-lerp of the FP16 pair (lo, hi) of word w with weights (gx, fx): the mixed-
-// precision FMAs read the halves in place, so no unpacking instructions.
-__device__ __forceinline__ float lerp_pair(uint32_t w, float fx, float gx)
-{
-    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-    const h2 v = __builtin_bit_cast(h2, w);
-    return fmaf((float)v[1], fx, fmaf((float)v[0], gx, 0.f));
 }
 
 // Trilinear value of a sample from its 8 corners (FP16): the y and z lerps run on the
@@ -305,6 +291,16 @@ __device__ __forceinline__ bf16x8 pack8(const f4 &lo, const f4 &hi)
     r[6] = (__bf16)hi[2];
     r[7] = (__bf16)hi[3];
     return r;
+}
+
+// pack8 with a ReLU: BF16 bit patterns read as signed 16-bit integers order every
+// negative value (and -0) below +0, so one packed integer max per pair replaces the
+// two FP32 max operations, with identical results.
+__device__ __forceinline__ bf16x8 pack8_relu(const f4 &lo, const f4 &hi)
+{
+    typedef short s16x8 __attribute__((ext_vector_type(8)));
+    const s16x8 v = __builtin_bit_cast(s16x8, pack8(lo, hi));
+    return __builtin_bit_cast(bf16x8, __builtin_elementwise_max(v, (s16x8)0));
 }
 
 // Double-buffered staging of weight chunks (MT fragments of 64 x 16 bytes), G chunks
@@ -878,10 +874,11 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
             }
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
+                if constexpr (F8) {  // the BF16 form applies this ReLU when packing
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    F[mt][i] = F8 ? __builtin_amdgcn_fmed3f(F[mt][i], 0.f, 448.f)
-                                  : fmaxf(F[mt][i], 0.f);
+                    for (int i = 0; i < 4; ++i)
+                        F[mt][i] = __builtin_amdgcn_fmed3f(F[mt][i], 0.f, 448.f);
+                }
                 O[mt] += *reinterpret_cast<const f4 *>(b2 + 16 * mt + 4 * g);
             }
             if constexpr (F8) {
@@ -890,10 +887,11 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
 #pragma unroll
                 for (int qq = 0; qq < C2; ++qq) {
                     ws.fetch(tid);
-                    mfma_chunk<MT>(
-                        ws.chunk(), lane,
-                        pack8(F[2 * qq], (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0] : z4),
-                        O);
+                    mfma_chunk<MT>(ws.chunk(), lane,
+                                   pack8_relu(F[2 * qq],
+                                              (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0]
+                                                                : z4),
+                                   O);
                     ws.template next<0>(tid);
                 }
             }
