@@ -479,7 +479,7 @@ ds_status loss_grad(ds_net *net, const float *z, const float *target, int B, flo
         }
         // dW = dY^T in, db = column sums of dY
         DS_TRY(mm({rows, W, B, dY, 1, ldy, in, W, 1, grad + po.hw[m], W, 0}));
-        DS_TRY(colsum(s, dY, ldy, B, rows, grad + po.hb[m]));
+        DS_TRY(colsum(s, dY, ldy, B, rows, grad + po.hb[m], w.split));
         // d in = dY W
         DS_TRY(mm({B, W, rows, dY, ldy, 1, th + po.hw[m], W, 1, w.dnext, W, 0}));
         std::swap(w.dcur, w.dnext);
@@ -489,7 +489,7 @@ ds_status loss_grad(ds_net *net, const float *z, const float *target, int B, flo
         float *da = w.dcur;
         DS_TRY(relu_mask(s, da, W, A(k), W, B, W));
         DS_TRY(mm({W, W, B, da, 1, W, F1(k), W, 1, grad + po.W2[k], W, 0}));
-        DS_TRY(colsum(s, da, W, B, W, grad + po.b2[k]));
+        DS_TRY(colsum(s, da, W, B, W, grad + po.b2[k], w.split));
         // dh = (da W2) masked by h > 0
         DS_TRY(mm({B, W, W, da, W, 1, th + po.W2[k], W, 1, w.dh, W, 0}));
         DS_TRY(relu_mask(s, w.dh, W, H(k), W, B, W));
@@ -498,7 +498,7 @@ ds_status loss_grad(ds_net *net, const float *z, const float *target, int B, flo
                                 grad + po.V[k], 226, 0}));
         DS_TRY(mm({W, 1, B, w.dh, 1, W, z + (int64_t)kStencil * K, D, 1,
                                 grad + po.V[k] + 225, 226, 0}));
-        DS_TRY(colsum(s, w.dh, W, B, W, grad + po.b1[k]));
+        DS_TRY(colsum(s, w.dh, W, B, W, grad + po.b1[k], w.split));
         if (k > 0) {
             DS_TRY(mm({W, W, B, w.dh, 1, W, O(k - 1), W, 1, grad + po.W1[k], W, 0}));
             // d o^{k-1} = da + dh W1

@@ -189,7 +189,9 @@ ds_status layer_epilogue(hipStream_t s, int M, int N, float *pre, int ldp, const
                          const float *gw, int ldgw, const float *bias, const float *R, int ldr,
                          float *out, int ldo);
 ds_status relu_mask(hipStream_t s, float *x, int ldx, const float *pre, int ldp, int R, int C);
-ds_status colsum(hipStream_t s, const float *d, int ldd, int R, int C, float *db);
+// column sums in a fixed order; scratch holds colsum_scratch(C) floats
+ds_status colsum(hipStream_t s, const float *d, int ldd, int R, int C, float *db, float *scratch);
+int colsum_scratch(int C);
 ds_status loss_head(hipStream_t s, const float *pre, const float *t, int B, float *dpre, float *sq,
                     float *loss);
 ds_status adam_update(hipStream_t s, float *theta, float *m, float *v, const float *grad,

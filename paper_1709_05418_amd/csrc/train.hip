@@ -80,15 +80,46 @@ __global__ void __launch_bounds__(256) k_relu_mask(float *x, int ldx, const floa
     }
 }
 
-// db[c] (+)= sum_r d[r][c], rows in order.
-__global__ void __launch_bounds__(256) k_colsum(const float *d, int ldd, int R, int C, float *db)
+constexpr int kColBlocks = 64;  // row blocks of a column sum (pass-1 partials per column)
+
+// Column sums db[c] = sum_r d[r][c] in a fixed order, in two passes.  Pass 1: workgroup
+// (x, y) covers 64 columns and the y-th block of `rows` rows, split over 4 slices of
+// consecutive rows (each summed in order) that are then added in slice order; pass 2
+// adds the row blocks of every column in block order.
+__global__ void __launch_bounds__(256) k_colsum_part(const float *__restrict__ d, int ldd, int R,
+                                                     int C, int rows, float *__restrict__ part)
+{
+    __shared__ float red[4][64];
+    const int c = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int slice = threadIdx.x >> 6;
+    const int per = (rows + 3) / 4;
+    const int r0 = blockIdx.y * rows + slice * per;
+    int r1 = r0 + per;
+    r1 = r1 < (int)(blockIdx.y + 1) * rows ? r1 : (int)(blockIdx.y + 1) * rows;
+    r1 = r1 < R ? r1 : R;
+    float s = 0.f;
+    if (c < C) {
+#pragma unroll 8
+        for (int r = r0; r < r1; ++r)
+            s += d[(int64_t)r * ldd + c];
+    }
+    red[slice][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (slice == 0 && c < C) {
+        const int t = threadIdx.x;
+        part[(int64_t)blockIdx.y * C + c] = ((red[0][t] + red[1][t]) + red[2][t]) + red[3][t];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_colsum_final(const float *__restrict__ part, int RB, int C,
+                                                      float *__restrict__ db)
 {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= C)
         return;
     float s = 0.f;
-    for (int r = 0; r < R; ++r)
-        s += d[(int64_t)r * ldd + c];
+    for (int b = 0; b < RB; ++b)
+        s += part[(int64_t)b * C + c];
     db[c] = s;
 }
 
@@ -316,9 +347,22 @@ ds_status relu_mask(hipStream_t s, float *x, int ldx, const float *pre, int ldp,
     return DS_OK;
 }
 
-ds_status colsum(hipStream_t s, const float *d, int ldd, int R, int C, float *db)
+int colsum_scratch(int C) { return kColBlocks * C; }
+
+ds_status colsum(hipStream_t s, const float *d, int ldd, int R, int C, float *db, float *scratch)
 {
-    k_colsum<<<(C + 255) / 256, 256, 0, s>>>(d, ldd, R, C, db);
+    if (C <= 0)
+        return DS_OK;
+    // at most kColBlocks row blocks of at least 64 rows each
+    int rows = (R + kColBlocks - 1) / kColBlocks;
+    rows = rows < 64 ? 64 : rows;
+    const int RB = R > 0 ? (R + rows - 1) / rows : 0;
+    if (RB == 0) {
+        DS_HIP(hipMemsetAsync(db, 0, sizeof(float) * C, s));
+        return DS_OK;
+    }
+    k_colsum_part<<<dim3((C + 63) / 64, RB), 256, 0, s>>>(d, ldd, R, C, rows, scratch);
+    k_colsum_final<<<(C + 255) / 256, 256, 0, s>>>(scratch, RB, C, db);
     DS_HIP(hipGetLastError());
     return DS_OK;
 }
