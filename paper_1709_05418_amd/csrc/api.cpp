@@ -779,6 +779,7 @@ ds_status ds_cloud_destroy(ds_cloud *c)
         (void)hipStreamSynchronize(c->ctx->stream);
     (void)hipFree(c->pyr);
     (void)hipFree(c->cells32);
+    (void)hipFree(c->mu_cells);
     (void)hipFree(c->cells);
     (void)hipFree(c->tables);
     (void)hipFree(c->mu);

@@ -76,6 +76,9 @@ struct ds_cloud {
     int64_t n_cells = 0;
     void *tables = nullptr;    // device: GatherLevel[K] then FusedLevel[K]
     float *mu = nullptr;       // extinction sigma_max * d on the base grid (tracer medium)
+    // the same extinction corner-packed (8 float32 corners, 32 bytes per cell, zero border),
+    // built on the cloud's first tracer call; the tracer reads one cell per lookup
+    mutable float4 *mu_cells = nullptr;
     float majorant = 0.f;      // sigma_max * max(d)
 };
 

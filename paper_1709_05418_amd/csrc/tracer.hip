@@ -101,32 +101,32 @@ __device__ __forceinline__ void basis(V3 n, V3 &t1, V3 &t2)
 
 // ------------------------------------------------------------------ medium
 struct Medium {
-    const float *mu;   // extinction sigma_max * d, [nz][ny][nx]
-    int nx, ny, nz;
+    const float4 *cells;  // corner-packed extinction: cell c = entries 2c, 2c + 1
+    int cx, cy;           // cell-grid dims in x and y (grid dims + 2)
+    float hx, hy, hz;     // clamp bounds of the shifted cell coordinate (grid dims + 1)
     V3 amin, amax;
     float inv_h, maj;
 };
 
-// Voxel-centred trilinear extinction, zero outside the grid.
+// Voxel-centred trilinear extinction, zero outside the grid.  The cell coordinate (the
+// voxel-centred coordinate plus one), clamped to [0, n + 1], selects a cell whose eight
+// corners are the lattice values around the point; the border cells hold zeros, so points
+// outside the grid read zero without tests.
 __device__ float mu_at(const Medium &M, V3 p)
 {
-    const float ux = (p.x - M.amin.x) * M.inv_h - 0.5f;
-    const float uy = (p.y - M.amin.y) * M.inv_h - 0.5f;
-    const float uz = (p.z - M.amin.z) * M.inv_h - 0.5f;
-    const float fx0 = floorf(ux), fy0 = floorf(uy), fz0 = floorf(uz);
-    const float fx = ux - fx0, fy = uy - fy0, fz = uz - fz0;
-    const int ix = (int)fx0, iy = (int)fy0, iz = (int)fz0;
-    float acc = 0.f;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const int dx = c & 1, dy = (c >> 1) & 1, dz = (c >> 2) & 1;
-        const int a = ix + dx, b = iy + dy, e = iz + dz;
-        if (a >= 0 && b >= 0 && e >= 0 && a < M.nx && b < M.ny && e < M.nz) {
-            const float w = (dx ? fx : 1.f - fx) * (dy ? fy : 1.f - fy) * (dz ? fz : 1.f - fz);
-            acc += w * M.mu[((int64_t)e * M.ny + b) * M.nx + a];
-        }
-    }
-    return acc;
+    const float ux = __builtin_amdgcn_fmed3f((p.x - M.amin.x) * M.inv_h + 0.5f, 0.f, M.hx);
+    const float uy = __builtin_amdgcn_fmed3f((p.y - M.amin.y) * M.inv_h + 0.5f, 0.f, M.hy);
+    const float uz = __builtin_amdgcn_fmed3f((p.z - M.amin.z) * M.inv_h + 0.5f, 0.f, M.hz);
+    const uint32_t i = (uint32_t)ux, j = (uint32_t)uy, k = (uint32_t)uz;
+    const float fx = __builtin_amdgcn_fractf(ux), fy = __builtin_amdgcn_fractf(uy),
+                fz = __builtin_amdgcn_fractf(uz);
+    const int64_t cell = (int64_t)i + (int64_t)M.cx * ((int64_t)j + (int64_t)M.cy * k);
+    const float4 lo = M.cells[2 * cell], hi = M.cells[2 * cell + 1];
+    // corner c = dx + 2 dy + 4 dz
+    const float a00 = fmaf(fx, lo.y - lo.x, lo.x), a10 = fmaf(fx, lo.w - lo.z, lo.z);
+    const float a01 = fmaf(fx, hi.y - hi.x, hi.x), a11 = fmaf(fx, hi.w - hi.z, hi.z);
+    const float b0 = fmaf(fy, a10 - a00, a00), b1 = fmaf(fy, a11 - a01, a01);
+    return fmaf(fz, b1 - b0, b0);
 }
 
 // Parametric interval [t0, t1] of o + t d inside the grid box, t >= 0.
@@ -554,13 +554,45 @@ __global__ void __launch_bounds__(256) k_zero64(double *v, int64_t n)
         v[i] = 0.0;
 }
 
+#define DS_TRY_MEDIUM(s, c)                \
+    do {                                   \
+        ds_status st_ = medium_cells(s, c); \
+        if (st_)                           \
+            return st_;                    \
+    } while (0)
+
+// The corner-packed extinction of the cloud, built on the first tracer call.
+ds_status medium_cells(hipStream_t s, const ds_cloud *c)
+{
+    if (c->mu_cells)
+        return DS_OK;
+    const int64_t n = (int64_t)(c->nx + 2) * (c->ny + 2) * (c->nz + 2);
+    float4 *cells = nullptr;
+    DS_CHECK(hipMalloc(&cells, sizeof(float4) * 2 * (size_t)n) == hipSuccess, DS_ERR_OOM,
+             "out of device memory for the corner-packed extinction (%lld cells of 32 bytes)",
+             (long long)n);
+    Level base = {};
+    base.nx = c->nx;
+    base.ny = c->ny;
+    base.nz = c->nz;
+    ds_status st = cloud_pack32(s, c->mu, 1, &base, cells);
+    if (st) {
+        (void)hipFree(cells);
+        return st;
+    }
+    c->mu_cells = cells;
+    return DS_OK;
+}
+
 Medium medium(const ds_cloud *c)
 {
     Medium M;
-    M.mu = c->mu;
-    M.nx = c->nx;
-    M.ny = c->ny;
-    M.nz = c->nz;
+    M.cells = c->mu_cells;
+    M.cx = c->nx + 2;
+    M.cy = c->ny + 2;
+    M.hx = (float)(c->nx + 1);
+    M.hy = (float)(c->ny + 1);
+    M.hz = (float)(c->nz + 1);
     M.amin = v3(c->aabb_min[0], c->aabb_min[1], c->aabb_min[2]);
     M.amax = v3((float)((double)c->aabb_min[0] + (double)c->nx * c->h0),
                 (float)((double)c->aabb_min[1] + (double)c->ny * c->h0),
@@ -627,6 +659,7 @@ ds_status tracer_li(hipStream_t s, const ds_cloud *c, const TracerParams &tp, co
                     uint8_t mask_bits)
 {
     const Split sp = split(spp);
+    DS_TRY_MEDIUM(s, c);
     k_trace_li<<<grid_of(P, sp), kPaths, 0, s>>>(medium(c), tp, pos, view, light, P, spp, sp,
                                                   seed, mask, mask_bits, partial);
     DS_HIP(hipGetLastError());
@@ -636,6 +669,7 @@ ds_status tracer_li(hipStream_t s, const ds_cloud *c, const TracerParams &tp, co
 ds_status tracer_records(hipStream_t s, const ds_cloud *c, int64_t N, uint64_t seed, float *pos,
                          float *view, float *light, int32_t *attempts)
 {
+    DS_TRY_MEDIUM(s, c);
     k_sample_records<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(medium(c), N, seed, pos, view,
                                                                  light, attempts);
     DS_HIP(hipGetLastError());
@@ -651,6 +685,7 @@ ds_status tracer_render(hipStream_t s, const ds_cloud *c, const TracerParams &tp
              "the light direction is not a usable vector");
     const V3 wl = v3(l[0], l[1], l[2]);
     const Split sp = split(spp);
+    DS_TRY_MEDIUM(s, c);
     k_render_mc<<<grid_of(N, sp), kPaths, 0, s>>>(medium(c), tp, wl, ray_o, ray_d, N, spp, sp,
                                                    seed, partial);
     DS_HIP(hipGetLastError());
@@ -666,6 +701,7 @@ ds_status tracer_first_hits(hipStream_t s, const ds_cloud *c, const TracerParams
     DS_CHECK(light_dir && unit_host(light_dir, l), DS_ERR_INVALID_ARG,
              "the light direction is not a usable vector");
     const V3 wl = v3(l[0], l[1], l[2]);
+    DS_TRY_MEDIUM(s, c);
     k_first_hits<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(medium(c), tp, wl, ray_o, ray_d, N,
                                                              seed, sample, pos, view, direct, hit);
     DS_HIP(hipGetLastError());
