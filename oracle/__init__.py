@@ -86,6 +86,10 @@ def lib():
                                       P, P]),
             "dso_first_hits": (I, [P, I, I, I, I, D, P, D, D, D, D, P, P, P, I64, U64, U64, P, P,
                                    P, P]),
+            "dso_render_pixels_lights": (I, [P, I, I, I, I, D, P, D, D, D, D, I, I, P, P, P, P, P,
+                                             I64, I, U64, P, P]),
+            "dso_first_hits_lights": (I, [P, I, I, I, I, D, P, D, D, D, D, I, P, P, P, I, P, P,
+                                          I64, U64, U64, P, P, P, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -322,6 +326,95 @@ def render_pixels(grid: Grid, ray_o, ray_d, light_dir, albedo=0.999, g=0.85, irr
                                    light_mode, max_interactions, _p(ld), _p(o), _p(d), N, spp,
                                    seed, _p(mean), _p(var)), "render_pixels")
     return mean, var
+
+
+# ---------------------------------------------------------------------------- light sets
+def light_table(irradiance):
+    """Selection table of a set of directional lights (Sec. 4.4: a distant emitter
+    approximated by directional samples), for drawing light j with probability close
+    to E_j / sum(E) from the top 24 bits k of one uniform: j is the first index with
+    k < thr[j].  thr[j] is the running sum of E up to j (in order, FP64) over the
+    total, times 2^24, rounded half up, then kept at least one above thr[j-1] and low
+    enough to leave one step for each later light, so every light has a nonzero
+    probability p_j = (thr[j] - thr[j-1]) / 2^24 and thr[-1] = 2^24.  The weight
+    w[j] = E_j / p_j makes one draw an unbiased estimate of the sum over the set."""
+    E = np.asarray(irradiance, np.float64).reshape(-1)
+    m = E.size
+    if m < 1 or m > 65536 or not np.all(np.isfinite(E)) or not np.all(E > 0):
+        raise ValueError("a light set needs 1..65536 finite positive irradiances")
+    thr = np.zeros(m, np.uint32)
+    w = np.zeros(m, np.float64)
+    total = 0.0
+    for j in range(m):
+        total += E[j]
+    run, prev = 0.0, 0
+    for j in range(m):
+        run += E[j]
+        t = int(np.floor(run / total * 16777216.0 + 0.5))
+        t = min(max(t, prev + 1), (1 << 24) - (m - 1 - j))
+        thr[j] = t
+        w[j] = E[j] / ((t - prev) / 16777216.0)
+        prev = t
+    return thr, w
+
+
+def light_pick(thr, k):
+    """The light drawn by the 24-bit integer k: the first j with k < thr[j]."""
+    for j, t in enumerate(thr):
+        if k < int(t):
+            return j
+    raise ValueError("k must be below 2^24")
+
+
+def _light_args(dirs, irradiance):
+    d = np.asarray(dirs, np.float64).reshape(-1, 3)
+    n = np.linalg.norm(d, axis=1, keepdims=True)
+    if not np.all(np.isfinite(d)) or not np.all(n > 0):
+        raise ValueError("unusable light direction")
+    d = np.ascontiguousarray(d / n)
+    thr, w = light_table(irradiance)
+    if thr.size != d.shape[0]:
+        raise ValueError("one irradiance per light direction")
+    return d, thr, w
+
+
+def render_pixels_lights(grid: Grid, ray_o, ray_d, dirs, irradiances, albedo=0.999, g=0.85,
+                         irradiance=1.0, max_interactions=0, spp=16, seed=1):
+    """Path-traced pixels under a set of directional lights (one light drawn per
+    next-event estimate)."""
+    o = np.ascontiguousarray(ray_o, np.float32)
+    d = np.ascontiguousarray(ray_d, np.float32)
+    ld, thr, w = _light_args(dirs, irradiances)
+    N = o.shape[0]
+    mean = np.zeros(N, np.float64)
+    var = np.zeros(N, np.float64)
+    _check(lib().dso_render_pixels_lights(*grid.args(), _p(grid.aabb_min), grid.h0, albedo, g,
+                                          irradiance, max_interactions, ld.shape[0], _p(ld),
+                                          _p(thr), _p(w), _p(o), _p(d), N, spp, seed, _p(mean),
+                                          _p(var)), "render_pixels_lights")
+    return mean, var
+
+
+def first_hits_lights(grid: Grid, ray_o, ray_d, dirs, irradiances, draws, albedo=0.999, g=0.85,
+                      irradiance=1.0, seed=1, sample=0):
+    """First collision, view direction, `draws` lights drawn from the set (rows
+    i * draws + q: direction and weight) and the averaged NEE direct term per ray."""
+    o = np.ascontiguousarray(ray_o, np.float32)
+    d = np.ascontiguousarray(ray_d, np.float32)
+    ld, thr, w = _light_args(dirs, irradiances)
+    N = o.shape[0]
+    pos = np.zeros((N, 3))
+    view = np.zeros((N, 3))
+    light = np.zeros((N * draws, 3))
+    weight = np.zeros(N * draws)
+    direct = np.zeros(N)
+    hit = np.zeros(N, np.uint8)
+    _check(lib().dso_first_hits_lights(*grid.args(), _p(grid.aabb_min), grid.h0, albedo, g,
+                                       irradiance, ld.shape[0], _p(ld), _p(thr), _p(w), draws,
+                                       _p(o), _p(d), N, seed, sample, _p(pos), _p(view),
+                                       _p(light), _p(weight), _p(direct), _p(hit)),
+           "first_hits_lights")
+    return pos, view, light, weight, direct, hit
 
 
 # ----------------------------------------------------------------------------- FP8 E4M3

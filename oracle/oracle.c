@@ -928,13 +928,36 @@ static void uniform_sphere(double u, double v, double out[3])
     out[2] = z;
 }
 
+/* A distant emitter as m directional lights (Sec. 4.4): unit directions dir[3j..3j+2]
+ * toward the light, selection thresholds thr[j] and weights w[j] (see set_pick). */
+typedef struct {
+    int m;
+    const double *dir;
+    const uint32_t *thr;
+    const double *w;
+} light_set;
+
 typedef struct {
     double albedo;
     double g;
     double irradiance;   /* E of the directional light, or radiance of the uniform environment */
-    int light_mode;      /* 0: directional light with next-event estimation; 1: uniform environment */
+    int light_mode;      /* 0: directional light with next-event estimation; 1: uniform environment;
+                            2: a set of directional lights, one drawn per next-event estimate */
     int max_interactions; /* 0: unlimited */
+    const light_set *set; /* mode 2 only */
 } tracer_params;
+
+/* Mode 2: light j is drawn with probability (thr[j] - thr[j-1]) / 2^24 (thr[-1] = 0) by the
+ * top 24 bits k of one uniform, as the first j with k < thr[j]; its estimate is weighted by
+ * w[j] = E_j / that probability, so each draw is unbiased for the sum over the set. */
+static int set_pick(const light_set *ls, rng_t *r)
+{
+    uint32_t k = (uint32_t)(rng_u(r) * 16777216.0);
+    for (int j = 0; j < ls->m; ++j)
+        if (k < ls->thr[j])
+            return j;
+    return ls->m - 1; /* not reached: thr[m-1] = 2^24 */
+}
 
 /* One path estimate of the indirect in-scattered radiance L_i(x, w) (Sec. 4):
  * the light that reaches x travelling along w_hat, after at least one collision,
@@ -965,6 +988,12 @@ static double li_path(const medium_t *M, const tracer_params *tp, const double x
             double mu = -dot3(wh, wl);
             double T = ratio_track(M, p, wl, r);
             sum += dso_hg(tp->g, mu) * T * tp->irradiance;
+        } else if (tp->light_mode == 2) {
+            int j = set_pick(tp->set, r);
+            const double *lj = tp->set->dir + 3 * j;
+            double mu = -dot3(wh, lj);
+            double T = ratio_track(M, p, lj, r);
+            sum += tp->set->w[j] * dso_hg(tp->g, mu) * T * tp->irradiance;
         }
         wprev[0] = wh[0];
         wprev[1] = wh[1];
@@ -1014,7 +1043,7 @@ int dso_trace_li(const void *dens, int dtype, int nx, int ny, int nz, double sig
     if (!medium_init(&M, dens, dtype, nx, ny, nz, sigma_max, aabb_min, h0) || spp <= 0 ||
         spp > (1 << 20))
         return DSO_ERR_INVALID;
-    tracer_params tp = {albedo, g, irradiance, light_mode, max_interactions};
+    tracer_params tp = {albedo, g, irradiance, light_mode, max_interactions, NULL};
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t i = 0; i < P; ++i) {
         double x[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
@@ -1173,6 +1202,32 @@ int dso_first_hits(const void *dens, int dtype, int nx, int ny, int nz, double s
     return DSO_OK;
 }
 
+/* One path-traced camera sample: the first collision x along o + t d (background 0,
+ * or the environment radiance in mode 1), then albedo times the in-scattered radiance
+ * at x toward the camera: direct single scattering by next-event estimation plus the
+ * L_i path estimate in modes 0 and 2, the full in-scattered environment light in
+ * mode 1. */
+static double pixel_sample(const medium_t *M, const tracer_params *tp, const double wl[3],
+                           const double o[3], const double d[3], rng_t *r)
+{
+    double x[3];
+    if (!delta_track(M, o, d, r, x))
+        return tp->light_mode == 1 ? tp->irradiance : 0.0;
+    double w[3] = {-d[0], -d[1], -d[2]};
+    if (tp->light_mode == 1)
+        return tp->albedo * li_path(M, tp, x, w, wl, 1, r);
+    double direct;
+    if (tp->light_mode == 0) {
+        direct = dso_hg(tp->g, -dot3(w, wl)) * ratio_track(M, x, wl, r) * tp->irradiance;
+    } else {
+        int j = set_pick(tp->set, r);
+        const double *lj = tp->set->dir + 3 * j;
+        direct = tp->set->w[j] * dso_hg(tp->g, -dot3(w, lj)) * ratio_track(M, x, lj, r) *
+                 tp->irradiance;
+    }
+    return tp->albedo * (direct + li_path(M, tp, x, w, wl, 0, r));
+}
+
 /* Path-traced pixels (Sec. 4.4 with the network replaced by the path estimate):
  * a delta-tracked first collision x along each camera ray o + t d (background 0,
  * or the environment radiance in mode 1), then albedo times the in-scattered
@@ -1190,7 +1245,7 @@ int dso_render_pixels(const void *dens, int dtype, int nx, int ny, int nz, doubl
     if (!medium_init(&M, dens, dtype, nx, ny, nz, sigma_max, aabb_min, h0) || spp <= 0 ||
         spp > (1 << 20))
         return DSO_ERR_INVALID;
-    tracer_params tp = {albedo, g, irradiance, light_mode, max_interactions};
+    tracer_params tp = {albedo, g, irradiance, light_mode, max_interactions, NULL};
     double wl[3];
     if (!unit3(light_dir, wl))
         return DSO_ERR_INVALID;
@@ -1208,18 +1263,7 @@ int dso_render_pixels(const void *dens, int dtype, int nx, int ny, int nz, doubl
         for (int s = 0; s < spp; ++s) {
             rng_t r;
             rng_init(&r, seed, ((uint64_t)i << 20) + (uint64_t)s);
-            double x[3], e;
-            if (!delta_track(&M, o, d, &r, x)) {
-                e = (light_mode == 1) ? irradiance : 0.0;
-            } else {
-                double w[3] = {-d[0], -d[1], -d[2]};
-                if (light_mode == 0) {
-                    double direct = dso_hg(g, -dot3(w, wl)) * ratio_track(&M, x, wl, &r) * irradiance;
-                    e = albedo * (direct + li_path(&M, &tp, x, w, wl, 0, &r));
-                } else {
-                    e = albedo * li_path(&M, &tp, x, w, wl, 1, &r);
-                }
-            }
+            double e = pixel_sample(&M, &tp, wl, o, d, &r);
             s1 += e;
             s2 += e * e;
         }
@@ -1227,6 +1271,114 @@ int dso_render_pixels(const void *dens, int dtype, int nx, int ny, int nz, doubl
         mean_out[i] = mean;
         if (var_out)
             var_out[i] = spp > 1 ? fmax(0.0, (s2 - spp * mean * mean) / (spp - 1)) / spp : 0.0;
+    }
+    return DSO_OK;
+}
+
+/* The light-set forms (Sec. 4.4: a distant emitter approximated by directional
+ * samples).  The set is m unit directions dir ([m][3]) with thresholds thr and
+ * weights w as set_pick states; every directional term is scaled by irradiance. */
+static int set_ok(int m, const double *dir, const uint32_t *thr, const double *w)
+{
+    if (m < 1 || !dir || !thr || !w || thr[m - 1] != (1u << 24))
+        return 0;
+    for (int j = 0; j < m; ++j)
+        if ((j > 0 && thr[j] <= thr[j - 1]) || thr[j] == 0 || !(w[j] >= 0))
+            return 0;
+    return 1;
+}
+
+/* Path-traced pixels under a light set: per sample, the first collision, the direct
+ * term of one light drawn from the set, and the L_i path estimate with one light
+ * drawn at every collision.  Streams as dso_render_pixels. */
+int dso_render_pixels_lights(const void *dens, int dtype, int nx, int ny, int nz, double sigma_max,
+                             const double *aabb_min, double h0, double albedo, double g,
+                             double irradiance, int max_interactions, int m, const double *dir,
+                             const uint32_t *thr, const double *w, const float *ray_o,
+                             const float *ray_d, int64_t NPix, int spp, uint64_t seed,
+                             double *mean_out, double *var_out)
+{
+    medium_t M;
+    if (!medium_init(&M, dens, dtype, nx, ny, nz, sigma_max, aabb_min, h0) || spp <= 0 ||
+        spp > (1 << 20) || !set_ok(m, dir, thr, w))
+        return DSO_ERR_INVALID;
+    light_set ls = {m, dir, thr, w};
+    tracer_params tp = {albedo, g, irradiance, 2, max_interactions, &ls};
+    const double wl[3] = {0.0, 0.0, 1.0}; /* unused in mode 2 */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < NPix; ++i) {
+        double o[3] = {ray_o[3 * i], ray_o[3 * i + 1], ray_o[3 * i + 2]};
+        double dv[3] = {ray_d[3 * i], ray_d[3 * i + 1], ray_d[3 * i + 2]}, d[3];
+        double s1 = 0.0, s2 = 0.0;
+        if (unit3(dv, d)) {
+            for (int s = 0; s < spp; ++s) {
+                rng_t r;
+                rng_init(&r, seed, ((uint64_t)i << 20) + (uint64_t)s);
+                double e = pixel_sample(&M, &tp, wl, o, d, &r);
+                s1 += e;
+                s2 += e * e;
+            }
+        }
+        double mean = s1 / spp;
+        mean_out[i] = mean;
+        if (var_out)
+            var_out[i] = spp > 1 ? fmax(0.0, (s2 - spp * mean * mean) / (spp - 1)) / spp : 0.0;
+    }
+    return DSO_OK;
+}
+
+/* One camera sample per ray for the network renderer under a light set: the first
+ * collision x and view direction as dso_first_hits, then D lights drawn from the set
+ * (draw q of ray i goes to row i * D + q of light_out and weight_out: the direction
+ * and w[j]), each with one ratio-tracking estimate T_q toward it; direct =
+ * albedo * irradiance * (1/D) * sum_q w[j_q] p(d . l_q) T_q.  Rays that escape get
+ * hit = 0 and zero rows.  The stream of ray i, sample s (id i * 2^20 + s) is used for
+ * the flight, then for each draw its choice and its ratio tracking, in draw order. */
+int dso_first_hits_lights(const void *dens, int dtype, int nx, int ny, int nz, double sigma_max,
+                          const double *aabb_min, double h0, double albedo, double g,
+                          double irradiance, int m, const double *dir, const uint32_t *thr,
+                          const double *w, int D, const float *ray_o, const float *ray_d,
+                          int64_t N, uint64_t seed, uint64_t sample, double *pos, double *view,
+                          double *light_out, double *weight_out, double *direct, uint8_t *hit)
+{
+    medium_t M;
+    if (!medium_init(&M, dens, dtype, nx, ny, nz, sigma_max, aabb_min, h0) ||
+        sample >= (1u << 20) || D < 1 || !set_ok(m, dir, thr, w))
+        return DSO_ERR_INVALID;
+    light_set ls = {m, dir, thr, w};
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < N; ++i) {
+        double o[3] = {ray_o[3 * i], ray_o[3 * i + 1], ray_o[3 * i + 2]};
+        double dv[3] = {ray_d[3 * i], ray_d[3 * i + 1], ray_d[3 * i + 2]}, d[3], x[3];
+        int h = 0;
+        double e = 0.0;
+        rng_t r;
+        if (unit3(dv, d)) {
+            rng_init(&r, seed, ((uint64_t)i << 20) + sample);
+            h = delta_track(&M, o, d, &r, x);
+        }
+        for (int q = 0; q < D; ++q) {
+            double *lo = light_out + 3 * (i * D + q);
+            if (!h) {
+                lo[0] = lo[1] = lo[2] = 0.0;
+                weight_out[i * D + q] = 0.0;
+                continue;
+            }
+            int j = set_pick(&ls, &r);
+            const double *lj = dir + 3 * j;
+            double T = ratio_track(&M, x, lj, &r);
+            e += w[j] * dso_hg(g, dot3(d, lj)) * T;
+            lo[0] = lj[0];
+            lo[1] = lj[1];
+            lo[2] = lj[2];
+            weight_out[i * D + q] = w[j];
+        }
+        for (int a = 0; a < 3; ++a) {
+            pos[3 * i + a] = h ? x[a] : 0.0;
+            view[3 * i + a] = h ? -d[a] : 0.0;
+        }
+        direct[i] = albedo * irradiance * e / D;
+        hit[i] = (uint8_t)h;
     }
     return DSO_OK;
 }

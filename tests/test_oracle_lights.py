@@ -1,0 +1,141 @@
+"""Pins of the oracle's light sets (Sec. 4.4: a distant emitter approximated by a number
+of directional samples): the selection table against exact identities and brute-force
+counting, the camera-sample direct term against the closed form of a homogeneous box,
+and the path-traced pixels against the directional renderer by linearity in the lights.
+CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1709_05418_amd import synth
+
+from test_oracle_tracer import ramp_int
+
+
+@pytest.mark.parametrize("E", [[1.0], [1.0, 2.0, 3.0, 1e-9], list(np.geomspace(1e-6, 1e3, 40)),
+                               list(np.random.default_rng(3).random(1000) + 1e-3)])
+def test_table_is_an_unbiased_selection(E):
+    E = np.asarray(E)
+    thr, w = O.light_table(E)
+    t = thr.astype(np.int64)
+    assert np.all(np.diff(t) >= 1) and t[0] >= 1 and t[-1] == 1 << 24
+    p = np.diff(np.concatenate([[0], t])) / 2.0 ** 24
+    assert p.sum() == 1.0
+    # one draw is unbiased for the sum over the set: sum_j p_j w_j f_j = sum_j E_j f_j
+    f = np.random.default_rng(1).standard_normal(E.size)
+    np.testing.assert_allclose((p * w * f).sum(), (E * f).sum(), rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(p * w, E, rtol=1e-12)
+    # the probabilities follow E wherever no light needed the minimum step
+    q = E / E.sum()
+    big = q > 4 * E.size / 2.0 ** 24
+    assert np.all(np.abs(p[big] - q[big]) <= E.size / 2.0 ** 24)
+
+
+def test_pick_counts_every_24_bit_value():
+    thr, _ = O.light_table([0.5, 3.0, 1e-7, 2.0, 0.25])
+    k = np.arange(1 << 24, dtype=np.int64)
+    # brute force over every value of the 24 bits: how often each light is chosen
+    chosen = np.searchsorted(thr.astype(np.int64), k, side="right")
+    counts = np.bincount(chosen, minlength=thr.size)
+    np.testing.assert_array_equal(counts, np.diff(np.concatenate([[0], thr.astype(np.int64)])))
+    for j, t in enumerate(thr.astype(int)):
+        assert O.light_pick(thr, t - 1) == j
+        if t < 1 << 24:
+            assert O.light_pick(thr, t) == j + 1
+    assert O.light_pick(thr, 0) == 0
+
+
+def test_table_rejects_bad_sets():
+    for E in ([], [1.0, 0.0], [1.0, -1.0], [np.inf], [np.nan]):
+        with pytest.raises(ValueError):
+            O.light_table(E)
+
+
+def test_first_hits_lights_homogeneous_box_closed_form():
+    # rays along +x through a homogeneous box; lights along +z, -z and +y, all at right
+    # angles to the ray, so the phase function is p(0) for each.  Given a collision at
+    # height z, one draw has mean albedo * E * p(0) * sum_j E_j exp(-sigma * depth_j)
+    n = 12
+    h = 1.0 / n
+    grid = O.Grid(np.ones((n, n, n), np.float32), 1.7, [-0.5] * 3, h)
+    sigma, albedo, gg, Eg = 1.7, 0.9, 0.6, 1.5
+    dirs = np.array([[0, 0, 1.0], [0, 0, -1.0], [0, 2.0, 0]])
+    E = np.array([2.0, 0.5, 1.0])
+    thr, w = O.light_table(E)
+    R, S, D = 5, 800, 8
+    zs = np.linspace(-0.3, 0.3, R)
+    o = np.stack([np.full(R, -0.9), np.full(R, 0.05), zs], 1).astype(np.float32)
+    rays = np.tile(np.array([[1.0, 0, 0]], np.float32), (R, 1))
+    hits = np.zeros(R)
+    dsum = np.zeros(R)
+    picks = np.zeros(3)
+    for s in range(S):
+        pos, view, light, weight, direct, hit = O.first_hits_lights(
+            grid, o, rays, dirs, E, D, albedo=albedo, g=gg, irradiance=Eg, seed=6, sample=s)
+        h1 = hit == 1
+        assert np.all(np.abs(pos[h1, 1:] - o[h1, 1:]) < 1e-6)
+        assert np.all(direct[~h1] == 0) and np.all(light.reshape(R, D, 3)[~h1] == 0)
+        rows = np.repeat(h1, D)
+        j = np.argmax(light[rows] @ (dirs / np.linalg.norm(dirs, axis=1, keepdims=True)).T, 1)
+        np.testing.assert_array_equal(weight[rows], w[j])
+        picks += np.bincount(j, minlength=3)
+        hits += h1
+        dsum += direct
+    # the draws follow the table's probabilities
+    p = np.diff(np.concatenate([[0], thr.astype(np.int64)])) / 2.0 ** 24
+    n_draws = picks.sum()
+    assert np.all(np.abs(picks / n_draws - p) < 5 * np.sqrt(p * (1 - p) / n_draws))
+    depth = np.stack([[ramp_int(z + 0.5, 1.0, n, h) for z in zs],
+                      [ramp_int(0.0, z + 0.5, n, h) for z in zs],
+                      [ramp_int(0.55, 1.0, n, h)] * R], 1)
+    want = albedo * Eg * O.hg(gg, 0.0) * (np.exp(-sigma * depth) @ E)
+    mean = dsum / hits
+    # a draw lies in [0, albedo E p(0) max w]: its variance is at most that bound times its mean
+    top = albedo * Eg * O.hg(gg, 0.0) * w.max()
+    sd = np.sqrt(top * want / (hits * D))
+    assert np.all(np.abs(mean - want) < 5 * sd), (mean, want)
+
+
+@pytest.fixture(scope="module")
+def small_scene():
+    n = 16
+    d = synth.cloud_density(n, seed=7)
+    grid = O.Grid(d, 16.0, [-0.5] * 3, 1.0 / n)
+    rng = np.random.default_rng(8)
+    R = 12
+    cam = np.array([0.0, 0.1, 2.2])
+    tgt = rng.uniform(-0.2, 0.2, (R, 3))
+    dirs = tgt - cam
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    return grid, np.tile(cam, (R, 1)).astype(np.float32), dirs.astype(np.float32)
+
+
+def test_single_light_set_equals_the_directional_renderer(small_scene):
+    # a set holding one light with E = 1 is the directional light itself; the only
+    # difference is one extra uniform per next-event estimate, so the two estimates
+    # agree within their errors
+    grid, o, d = small_scene
+    ld = synth.table1_lights()["side"]
+    m0, v0 = O.render_pixels(grid, o, d, ld, albedo=0.95, g=0.7, irradiance=1.3, spp=3000, seed=2)
+    m1, v1 = O.render_pixels_lights(grid, o, d, [ld], [1.0], albedo=0.95, g=0.7,
+                                    irradiance=1.3, spp=3000, seed=3)
+    assert m0.max() > 0
+    assert np.all(np.abs(m0 - m1) < 5 * np.sqrt(v0 + v1) + 1e-12)
+
+
+def test_light_set_is_linear_in_its_lights(small_scene):
+    # under two lights the pixel is E_a I(a) + E_b I(b), I the directional image
+    grid, o, d = small_scene
+    la, lb = synth.table1_lights()["side"], synth.table1_lights()["back"]
+    Ea, Eb = 2.0, 0.7
+    spp = 3000
+    ma, va = O.render_pixels(grid, o, d, la, albedo=0.95, g=0.7, spp=spp, seed=4)
+    mb, vb = O.render_pixels(grid, o, d, lb, albedo=0.95, g=0.7, spp=spp, seed=5)
+    ms, vs = O.render_pixels_lights(grid, o, d, [la, lb], [Ea, Eb], albedo=0.95, g=0.7,
+                                    spp=spp, seed=6)
+    want = Ea * ma + Eb * mb
+    sd = np.sqrt(Ea ** 2 * va + Eb ** 2 * vb + vs)
+    assert np.all(np.abs(ms - want) < 5 * sd + 1e-12), (ms, want)
+    assert math.isclose(ms.sum(), want.sum(), rel_tol=0.05)
