@@ -403,6 +403,77 @@ ds_status ds_render_rpnn(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
                          int64_t N, int spp, uint64_t seed, int fallback_spp, double *mean_out,
                          double *var_out, double *direct_out, int64_t *n_fallback);
 
+/* ---------------------------------------------------------------- light sets
+ * A distant emitter (a sun and sky, an environment map) approximated by m
+ * directional lights (Sec. 4.4: the renderer handles any distant light by
+ * drawing directional samples of it and querying the network once per sample,
+ * having been trained for one directional light only).  Member j has a unit
+ * direction toward the light and an irradiance E_j > 0.  Every next-event
+ * estimate draws one member from the top 24 bits k of one uniform: the first j
+ * with k < thr[j], where thr[j] is the running FP64 sum of E up to j divided by
+ * the total, times 2^24, rounded half up, then kept at least thr[j-1] + 1 and at
+ * most 2^24 - (m - 1 - j) (so thr[m-1] = 2^24 and every member can be drawn).
+ * The drawn member's term is weighted by w_j = E_j / p_j with
+ * p_j = (thr[j] - thr[j-1]) / 2^24, so one draw is an unbiased estimate of the
+ * sum over the set.  params->light_mode must be DS_LIGHT_DIRECTIONAL in the
+ * calls below; params->irradiance scales every member. */
+typedef struct ds_lights ds_lights;
+
+/* dirs: host [m][3] float32 (normalised here; zero or non-finite rejected);
+ * irradiance: host m doubles, finite and > 0; 1 <= m <= 65536.  The set owns a
+ * small device table on ctx's device (20 bytes per member), uploaded
+ * synchronously. */
+ds_status ds_lights_create(ds_ctx *ctx, int32_t m, const float *dirs, const double *irradiance,
+                           ds_lights **out);
+/* The selection table ds_lights_create builds, on the host (no device needed):
+ * thresholds (m uint32) and the FP64 weights w_j (m doubles) of the irradiances
+ * (host, m doubles, finite and > 0; 1 <= m <= 65536). */
+ds_status ds_light_table(int32_t m, const double *irradiance, uint32_t *thresholds,
+                         double *weights);
+/* Waits for the context's stream, then frees the set. */
+ds_status ds_lights_destroy(ds_lights *lights);
+
+/* Path-traced pixels under a light set: as ds_render_mc in DS_LIGHT_DIRECTIONAL
+ * mode, except that the direct term and every next-event estimate of the path
+ * draw one member of the set (one uniform, taken just before that estimate's
+ * ratio tracking) and weight it by w_j.  Escaping rays see 0.  Same streams,
+ * limits and workspace as ds_render_mc. */
+ds_status ds_render_mc_lights(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params *params,
+                              const ds_lights *lights, const float *ray_o, const float *ray_d,
+                              int64_t N, int spp, uint64_t seed, double *mean_out,
+                              double *var_out);
+
+/* Camera samples for the network renderer under a light set: per ray the first
+ * collision as ds_first_hits, then `draws` members of the set (1 <= draws <=
+ * 256), each drawn by one uniform and followed by one ratio-tracking estimate
+ * T_q toward it, on the ray's stream in draw order.  Row i * draws + q of pos,
+ * view_dir and light_dir (device, [N * draws][3] float32) and of weight (device,
+ * N * draws floats) holds the collision, the view direction, the drawn
+ * direction and its w_j; direct (device, N floats) = albedo * E * (1 / draws) *
+ * sum_q w_q p(d . l_q) T_q; hit (device, N bytes).  Rays that escape get hit = 0
+ * and zero rows.  N * draws <= 2^31. */
+ds_status ds_first_hits_lights(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params *params,
+                               const ds_lights *lights, int32_t draws, const float *ray_o,
+                               const float *ray_d, int64_t N, uint64_t seed, uint64_t sample,
+                               float *pos, float *view_dir, float *light_dir, float *weight,
+                               float *direct, uint8_t *hit);
+
+/* Image formation with the network under a light set (Sec. 4.4, Fig. 7): per
+ * camera sample s, the rows of ds_first_hits_lights (sample index s), one
+ * prediction per row at `precision` (N * draws points in one ds_predict), and
+ * radiance = direct + albedo * E * (1 / draws) * sum_q w_q L_i(x, omega, l_q).
+ * Where a row's stencil leaves the grid and fallback_spp > 0, its L_i comes from
+ * fallback_spp path-traced estimates per unit irradiance toward l_q (streams as
+ * ds_render_rpnn's fallback, over rows).  Outputs, n_fallback (counted per row)
+ * and the synchronisation rule as ds_render_rpnn.  Library-owned workspace:
+ * about 57 bytes per row plus 41 per pixel, plus the fallback's. */
+ds_status ds_render_rpnn_lights(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
+                                ds_precision precision, const ds_tracer_params *params,
+                                const ds_lights *lights, int32_t draws, const float *ray_o,
+                                const float *ray_d, int64_t N, int spp, uint64_t seed,
+                                int fallback_spp, double *mean_out, double *var_out,
+                                double *direct_out, int64_t *n_fallback);
+
 /* The tracer's random generator itself: for n (counter, key) pairs
  * ctr_key (device, [n][6] uint32: c0 c1 c2 c3 k0 k1) the Philox4x32-10 block
  * (device out, [n][4] uint32), as defined by Salmon et al., SC'11. */

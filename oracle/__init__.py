@@ -23,6 +23,10 @@ What each part follows in the paper and what pins it (tests/test_oracle_*.py):
   first_hits      Sec. 4.4 camera sample: first collision   homogeneous box: hit fraction
                   and direct single scattering              1 - exp(-sigma L), direct term against
                                                             albedo p exp(-sigma s) E
+  light_table,    Sec. 4.4 distant emitter as directional   p_j w_j = E_j exactly, all 2^24 draws
+  *_lights        lights, one drawn per estimate            counted, homogeneous-box closed form,
+                                                            one-light set = directional renderer,
+                                                            linearity in the lights
   e4m3_encode     OCP 8-bit floating point, E4M3 format     torch.float8_e4m3fn cast, hand values,
                   (round to nearest even, saturating)       decode/encode round trip of every code
 """

@@ -92,6 +92,14 @@ def lib():
         "ds_batch_replay": (S, [P]),
         "ds_make_records": (S, [P, P, P, I64, I, C.c_uint64, I64, P, P, P, P, P, P, P]),
         "ds_render_rpnn": (S, [P, P, P, I, P, P, P, P, I64, I, C.c_uint64, I, P, P, P, P]),
+        "ds_lights_create": (S, [P, S, P, P, P]),
+        "ds_light_table": (S, [S, P, P, P]),
+        "ds_lights_destroy": (S, [P]),
+        "ds_render_mc_lights": (S, [P, P, P, P, P, P, I64, I, C.c_uint64, P, P]),
+        "ds_first_hits_lights": (S, [P, P, P, P, S, P, P, I64, C.c_uint64, C.c_uint64, P, P, P,
+                                     P, P, P]),
+        "ds_render_rpnn_lights": (S, [P, P, P, I, P, P, S, P, P, I64, I, C.c_uint64, I, P, P, P,
+                                      P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -518,6 +526,78 @@ def ds_render_rpnn(ctx, cloud, net, precision, params: TracerParams, light_dir, 
     return mean, var, direct, (nfb.value if count_fallback else None)
 
 
+def ds_lights_create(ctx, dirs, irradiance):
+    """dirs: (m, 3) host array; irradiance: m positive values.  Returns the handle."""
+    d = np.ascontiguousarray(np.asarray(dirs, np.float32).reshape(-1, 3))
+    e = np.ascontiguousarray(np.asarray(irradiance, np.float64).reshape(-1))
+    if e.size != d.shape[0]:
+        raise ValueError("one irradiance per light direction")
+    h = C.c_void_p()
+    _check(lib().ds_lights_create(ctx, int(d.shape[0]), d.ctypes.data, e.ctypes.data,
+                                  C.byref(h)))
+    return h
+
+
+def ds_light_table(irradiance):
+    """The library's selection table of a light set (host only): thresholds, weights."""
+    e = np.ascontiguousarray(np.asarray(irradiance, np.float64).reshape(-1))
+    thr = np.zeros(e.size, np.uint32)
+    w = np.zeros(e.size, np.float64)
+    _check(lib().ds_light_table(int(e.size), e.ctypes.data, thr.ctypes.data, w.ctypes.data))
+    return thr, w
+
+
+def ds_lights_destroy(lights):
+    _check(lib().ds_lights_destroy(lights))
+
+
+def ds_render_mc_lights(ctx, cloud, params: TracerParams, lights, ray_o, ray_d, spp, seed,
+                        want_var=True):
+    N = ray_o.shape[0]
+    mean = _f64(N, ray_o.device)
+    var = _f64(N, ray_o.device) if want_var else None
+    _check(lib().ds_render_mc_lights(ctx, cloud, C.byref(params), lights, _pts(ray_o),
+                                     _pts(ray_d, N), N, int(spp), int(seed), _ptr(mean),
+                                     _ptr(var)))
+    return mean, var
+
+
+def ds_first_hits_lights(ctx, cloud, params: TracerParams, lights, draws, ray_o, ray_d, seed,
+                         sample=0):
+    """Per ray and draw (rows i * draws + q): pos, view, light, weight; per ray: direct, hit."""
+    import torch
+    N = ray_o.shape[0]
+    R = N * int(draws)
+    dev = ray_o.device
+    pos = torch.empty((R, 3), dtype=torch.float32, device=dev)
+    view = torch.empty((R, 3), dtype=torch.float32, device=dev)
+    light = torch.empty((R, 3), dtype=torch.float32, device=dev)
+    weight = torch.empty(R, dtype=torch.float32, device=dev)
+    direct = torch.empty(N, dtype=torch.float32, device=dev)
+    hit = torch.empty(N, dtype=torch.uint8, device=dev)
+    _check(lib().ds_first_hits_lights(ctx, cloud, C.byref(params), lights, int(draws),
+                                      _pts(ray_o), _pts(ray_d, N), N, int(seed), int(sample),
+                                      _ptr(pos), _ptr(view), _ptr(light), _ptr(weight),
+                                      _ptr(direct), _ptr(hit)))
+    return pos, view, light, weight, direct, hit
+
+
+def ds_render_rpnn_lights(ctx, cloud, net, precision, params: TracerParams, lights, draws, ray_o,
+                          ray_d, spp, seed, fallback_spp=0, want_var=True, want_direct=True,
+                          count_fallback=False):
+    """Per pixel: (mean, variance of the mean, mean of the direct term, fallback count)."""
+    N = ray_o.shape[0]
+    mean = _f64(N, ray_o.device)
+    var = _f64(N, ray_o.device) if want_var else None
+    direct = _f64(N, ray_o.device) if want_direct else None
+    nfb = C.c_int64(0)
+    _check(lib().ds_render_rpnn_lights(ctx, cloud, net, int(precision), C.byref(params), lights,
+                                       int(draws), _pts(ray_o), _pts(ray_d, N), N, int(spp),
+                                       int(seed), int(fallback_spp), _ptr(mean), _ptr(var),
+                                       _ptr(direct), C.byref(nfb) if count_fallback else None))
+    return mean, var, direct, (nfb.value if count_fallback else None)
+
+
 def ds_philox4x32_10(ctx, ctr_key):
     """ctr_key: int32/uint32 device tensor (n, 6) = c0 c1 c2 c3 k0 k1; returns (n, 4) words
     (as int32 bit patterns)."""
@@ -577,4 +657,18 @@ class Net:
     def close(self):
         if self.h is not None:
             ds_net_destroy(self.h)
+            self.h = None
+
+
+class Lights:
+    """A light set: m directional lights with irradiances (a discretised distant emitter)."""
+
+    def __init__(self, ctx: Context, dirs, irradiance):
+        self.ctx = ctx
+        self.m = int(np.asarray(irradiance).size)
+        self.h = ds_lights_create(ctx.h, dirs, irradiance)
+
+    def close(self):
+        if self.h is not None:
+            ds_lights_destroy(self.h)
             self.h = None

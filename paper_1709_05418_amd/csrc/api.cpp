@@ -515,6 +515,45 @@ ds_status loss_grad(ds_net *net, const float *z, const float *target, int B, flo
 
 using namespace ds;
 
+// A distant emitter as m directional lights (Sec. 4.4): per light the unit direction and
+// the weight E_j / p_j (device float4), and the selection thresholds (device).
+constexpr int kMaxLights = 65536;  // members of a light set
+constexpr int kMaxDraws = 256;     // lights drawn per camera sample
+
+struct ds_lights {
+    ds_ctx *ctx = nullptr;
+    int m = 0;
+    float4 *dw = nullptr;
+    uint32_t *thr = nullptr;
+};
+
+namespace {
+
+// Selection table of a light set: thr[j] = the running FP64 sum of E to j over the
+// total, times 2^24, rounded half up, kept one above thr[j-1] and low enough to leave
+// one step per later light (so thr[m-1] = 2^24 and each p_j > 0); w[j] = E_j / p_j with
+// p_j = (thr[j] - thr[j-1]) / 2^24.
+void light_table(const double *E, int m, uint32_t *thr, double *w)
+{
+    double total = 0.0;
+    for (int j = 0; j < m; ++j)
+        total += E[j];
+    double run = 0.0;
+    int64_t prev = 0;
+    for (int j = 0; j < m; ++j) {
+        run += E[j];
+        int64_t t = (int64_t)std::floor(run / total * 16777216.0 + 0.5);
+        t = t < prev + 1 ? prev + 1 : t;
+        const int64_t cap = ((int64_t)1 << 24) - (m - 1 - j);
+        t = t > cap ? cap : t;
+        thr[j] = (uint32_t)t;
+        w[j] = E[j] / ((double)(t - prev) / 16777216.0);
+        prev = t;
+    }
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *ds_last_error(void) { return g_err; }
@@ -1453,6 +1492,23 @@ static ds_status tracer_params(const ds_tracer_params *p, TracerParams &tp, cons
     return DS_OK;
 }
 
+static ds_status set_params(const ds_tracer_params *params, const ds_lights *lights, TracerParams &tp,
+                     const char *fn)
+{
+    DS_CHECK(lights && lights->dw, DS_ERR_INVALID_ARG, "%s: NULL light set", fn);
+    ds_status st = tracer_params(params, tp, fn);
+    if (st)
+        return st;
+    DS_CHECK(tp.light_mode == DS_LIGHT_DIRECTIONAL, DS_ERR_INVALID_ARG,
+             "%s: the members of a light set are directional lights (light_mode must be "
+             "DS_LIGHT_DIRECTIONAL)", fn);
+    tp.light_mode = kLightSetMode;
+    tp.set_dw = lights->dw;
+    tp.set_thr = lights->thr;
+    tp.set_m = lights->m;
+    return DS_OK;
+}
+
 ds_status ds_cloud_majorant(const ds_cloud *c, float *majorant)
 {
     DS_CHECK(c && majorant, DS_ERR_INVALID_ARG, "ds_cloud_majorant: NULL argument");
@@ -1666,6 +1722,228 @@ ds_status ds_render_rpnn(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
         }
         st = tracer_accumulate(s, N, hit, direct, li, flags, mc, tp.albedo, tp.irradiance, sums,
                                dsum, n_fallback ? cnt : nullptr);
+        if (st)
+            return st;
+    }
+    st = tracer_finish(s, sums, N, spp, mean_out, var_out);
+    if (st)
+        return st;
+    if (direct_out) {
+        st = tracer_finish(s, dsum, N, spp, direct_out, nullptr);
+        if (st)
+            return st;
+    }
+    if (n_fallback) {
+        unsigned long long h = 0;
+        DS_HIP(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, s));
+        DS_HIP(hipStreamSynchronize(s));
+        *n_fallback = (int64_t)h;
+    }
+    return DS_OK;
+}
+
+// ---------------------------------------------------------------- light sets
+ds_status ds_lights_create(ds_ctx *ctx, int32_t m, const float *dirs, const double *irradiance,
+                           ds_lights **out)
+{
+    DS_CHECK(ctx && dirs && irradiance && out, DS_ERR_INVALID_ARG,
+             "ds_lights_create: NULL argument");
+    *out = nullptr;
+    DS_CHECK(m >= 1 && m <= kMaxLights, DS_ERR_INVALID_ARG,
+             "ds_lights_create: %d lights outside [1, %d]", m, kMaxLights);
+    std::vector<float4> dw((size_t)m);
+    for (int j = 0; j < m; ++j) {
+        float u[3];
+        DS_CHECK(unit_host(dirs + 3 * j, u), DS_ERR_INVALID_ARG,
+                 "ds_lights_create: light %d has an unusable direction", j);
+        DS_CHECK(std::isfinite(irradiance[j]) && irradiance[j] > 0.0, DS_ERR_INVALID_ARG,
+                 "ds_lights_create: light %d has irradiance %g (must be finite and > 0)", j,
+                 irradiance[j]);
+        dw[j] = make_float4(u[0], u[1], u[2], 0.f);
+    }
+    std::vector<uint32_t> thr((size_t)m);
+    std::vector<double> w((size_t)m);
+    light_table(irradiance, m, thr.data(), w.data());
+    for (int j = 0; j < m; ++j)
+        dw[j].w = (float)w[j];
+    ds_lights *L = new (std::nothrow) ds_lights;
+    DS_CHECK(L, DS_ERR_OOM, "ds_lights_create: out of host memory");
+    L->ctx = ctx;
+    L->m = m;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess)
+        e = hipMalloc(&L->dw, sizeof(float4) * (size_t)m);
+    if (e == hipSuccess)
+        e = hipMalloc(&L->thr, sizeof(uint32_t) * (size_t)m);
+    if (e == hipSuccess)
+        e = hipMemcpy(L->dw, dw.data(), sizeof(float4) * (size_t)m, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(L->thr, thr.data(), sizeof(uint32_t) * (size_t)m, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(L->dw);
+        (void)hipFree(L->thr);
+        delete L;
+        return hip_fail(e, "ds_lights_create");
+    }
+    *out = L;
+    return DS_OK;
+}
+
+ds_status ds_light_table(int32_t m, const double *irradiance, uint32_t *thresholds,
+                         double *weights)
+{
+    DS_CHECK(irradiance && thresholds && weights, DS_ERR_INVALID_ARG,
+             "ds_light_table: NULL argument");
+    DS_CHECK(m >= 1 && m <= kMaxLights, DS_ERR_INVALID_ARG,
+             "ds_light_table: %d lights outside [1, %d]", m, kMaxLights);
+    for (int j = 0; j < m; ++j)
+        DS_CHECK(std::isfinite(irradiance[j]) && irradiance[j] > 0.0, DS_ERR_INVALID_ARG,
+                 "ds_light_table: light %d has irradiance %g (must be finite and > 0)", j,
+                 irradiance[j]);
+    light_table(irradiance, m, thresholds, weights);
+    return DS_OK;
+}
+
+ds_status ds_lights_destroy(ds_lights *lights)
+{
+    if (!lights)
+        return DS_OK;
+    (void)hipSetDevice(lights->ctx->device);
+    (void)hipStreamSynchronize(lights->ctx->stream);
+    (void)hipFree(lights->dw);
+    (void)hipFree(lights->thr);
+    delete lights;
+    return DS_OK;
+}
+
+ds_status ds_render_mc_lights(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params *params,
+                              const ds_lights *lights, const float *ray_o, const float *ray_d,
+                              int64_t N, int spp, uint64_t seed, double *mean_out,
+                              double *var_out)
+{
+    DS_CHECK(ctx && cloud && (N == 0 || (ray_o && ray_d && mean_out)), DS_ERR_INVALID_ARG,
+             "ds_render_mc_lights: NULL argument");
+    DS_CHECK(N >= 0 && N < (int64_t(1) << 40), DS_ERR_INVALID_ARG,
+             "ds_render_mc_lights: N out of range");
+    DS_CHECK(spp >= 1 && spp <= (1 << 20), DS_ERR_INVALID_ARG,
+             "ds_render_mc_lights: spp %d outside [1, 2^20]", spp);
+    TracerParams tp;
+    ds_status st = set_params(params, lights, tp, "ds_render_mc_lights");
+    if (st)
+        return st;
+    if (N == 0)
+        return DS_OK;
+    DS_HIP(hipSetDevice(ctx->device));
+    st = ensure_ws(ctx, sizeof(double) * 2 * (size_t)N * tracer_blocks(spp));
+    if (st)
+        return st;
+    const float unused[3] = {0.f, 0.f, 1.f};
+    return tracer_render(ctx->stream, cloud, tp, unused, ray_o, ray_d, N, spp, seed,
+                         static_cast<double *>(ctx->ws), mean_out, var_out);
+}
+
+ds_status ds_first_hits_lights(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params *params,
+                               const ds_lights *lights, int32_t draws, const float *ray_o,
+                               const float *ray_d, int64_t N, uint64_t seed, uint64_t sample,
+                               float *pos, float *view_dir, float *light_dir, float *weight,
+                               float *direct, uint8_t *hit)
+{
+    DS_CHECK(ctx && cloud &&
+                 (N == 0 || (ray_o && ray_d && pos && view_dir && light_dir && weight && direct &&
+                             hit)),
+             DS_ERR_INVALID_ARG, "ds_first_hits_lights: NULL argument");
+    DS_CHECK(draws >= 1 && draws <= kMaxDraws, DS_ERR_INVALID_ARG,
+             "ds_first_hits_lights: draws %d outside [1, %d]", draws, kMaxDraws);
+    DS_CHECK(N >= 0 && N * (int64_t)draws <= ((int64_t)1 << 31), DS_ERR_INVALID_ARG,
+             "ds_first_hits_lights: N * draws above 2^31");
+    DS_CHECK(sample < (uint64_t(1) << 20), DS_ERR_INVALID_ARG,
+             "ds_first_hits_lights: sample index must be below 2^20");
+    TracerParams tp;
+    ds_status st = set_params(params, lights, tp, "ds_first_hits_lights");
+    if (st)
+        return st;
+    if (N == 0)
+        return DS_OK;
+    DS_HIP(hipSetDevice(ctx->device));
+    return tracer_first_hits_set(ctx->stream, cloud, tp, draws, ray_o, ray_d, N, seed, sample, pos,
+                                 view_dir, light_dir, weight, direct, hit);
+}
+
+ds_status ds_render_rpnn_lights(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
+                                ds_precision precision, const ds_tracer_params *params,
+                                const ds_lights *lights, int32_t draws, const float *ray_o,
+                                const float *ray_d, int64_t N, int spp, uint64_t seed,
+                                int fallback_spp, double *mean_out, double *var_out,
+                                double *direct_out, int64_t *n_fallback)
+{
+    DS_CHECK(ctx && cloud && net && (N == 0 || (ray_o && ray_d && mean_out)), DS_ERR_INVALID_ARG,
+             "ds_render_rpnn_lights: NULL argument");
+    DS_CHECK(draws >= 1 && draws <= kMaxDraws, DS_ERR_INVALID_ARG,
+             "ds_render_rpnn_lights: draws %d outside [1, %d]", draws, kMaxDraws);
+    DS_CHECK(N >= 0 && N * (int64_t)draws <= ((int64_t)1 << 31), DS_ERR_INVALID_ARG,
+             "ds_render_rpnn_lights: N * draws above 2^31");
+    DS_CHECK(spp >= 1 && spp <= (1 << 20), DS_ERR_INVALID_ARG,
+             "ds_render_rpnn_lights: spp %d outside [1, 2^20]", spp);
+    DS_CHECK(fallback_spp >= 0 && fallback_spp <= (1 << 20), DS_ERR_INVALID_ARG,
+             "ds_render_rpnn_lights: fallback_spp %d outside [0, 2^20]", fallback_spp);
+    DS_CHECK(cloud->K == net->K, DS_ERR_INVALID_ARG,
+             "ds_render_rpnn_lights: the cloud has %d stencil levels, the network %d", cloud->K,
+             net->K);
+    TracerParams tp;
+    ds_status st = set_params(params, lights, tp, "ds_render_rpnn_lights");
+    if (st)
+        return st;
+    if (n_fallback)
+        *n_fallback = 0;
+    if (N == 0)
+        return DS_OK;
+    DS_HIP(hipSetDevice(ctx->device));
+    const size_t n = (size_t)N, r = n * (size_t)draws;
+    st = ensure_ws2(ctx, r * (11 * sizeof(float) + 1 + sizeof(double)) +
+                             n * (sizeof(float) + 1 + 4 * sizeof(double)) + 16 * 256);
+    if (st)
+        return st;
+    Carve cv(ctx->ws2);
+    float *pos = cv.take<float>(3 * r), *view = cv.take<float>(3 * r);
+    float *light = cv.take<float>(3 * r), *weight = cv.take<float>(r), *li = cv.take<float>(r);
+    uint8_t *flags = cv.take<uint8_t>(r);
+    double *li_mc = cv.take<double>(r);
+    float *direct = cv.take<float>(n);
+    uint8_t *hit = cv.take<uint8_t>(n);
+    double *sums = cv.take<double>(2 * n);
+    double *dsum = direct_out ? cv.take<double>(2 * n) : nullptr;
+    unsigned long long *cnt = cv.take<unsigned long long>(1);
+    hipStream_t s = ctx->stream;
+    if ((st = tracer_zero(s, sums, 2 * N)) || (dsum && (st = tracer_zero(s, dsum, 2 * N))) ||
+        (st = tracer_zero(s, reinterpret_cast<double *>(cnt), 1)))
+        return st;
+    // the fallback estimates L_i per unit irradiance for each drawn direction
+    TracerParams dir_tp = tp;
+    dir_tp.light_mode = DS_LIGHT_DIRECTIONAL;
+    dir_tp.irradiance = 1.f;
+    const int64_t R = N * draws;
+    for (int smp = 0; smp < spp; ++smp) {
+        st = tracer_first_hits_set(s, cloud, tp, draws, ray_o, ray_d, N, seed, (uint64_t)smp, pos,
+                                   view, light, weight, direct, hit);
+        if (st)
+            return st;
+        st = ds_predict(ctx, cloud, net, precision, pos, view, light, R, li, nullptr, flags);
+        if (st)
+            return st;
+        const double *mc = nullptr;
+        if (fallback_spp > 0) {
+            st = ensure_ws(ctx, sizeof(double) * 2 * r * tracer_blocks(fallback_spp));
+            if (st)
+                return st;
+            st = tracer_li(s, cloud, dir_tp, pos, view, light, R, fallback_spp,
+                           derived_key(seed, 1 + (uint64_t)smp), static_cast<double *>(ctx->ws),
+                           li_mc, nullptr, flags, DS_FLAG_FALLBACK);
+            if (st)
+                return st;
+            mc = li_mc;
+        }
+        st = tracer_accumulate_set(s, N, draws, hit, direct, li, flags, mc, weight, tp.albedo,
+                                   tp.irradiance, sums, dsum, n_fallback ? cnt : nullptr);
         if (st)
             return st;
     }

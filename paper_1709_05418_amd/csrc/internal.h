@@ -255,9 +255,16 @@ uint8_t e4m3_encode(float x);
 ds_status fused_gather_packed(hipStream_t s, const FusedArgs &a, float *z);
 
 // tracer.hip
+// light_mode 0: one directional light; 1: uniform environment; 2: a light set, one
+// member drawn per next-event estimate (set_dw: unit direction and weight per light,
+// set_thr: selection thresholds on the top 24 bits of a uniform, both device arrays).
+constexpr int kLightSetMode = 2;
 struct TracerParams {
     float albedo, g, irradiance;
     int light_mode, max_interactions;
+    const float4 *set_dw = nullptr;
+    const uint32_t *set_thr = nullptr;
+    int set_m = 0;
 };
 bool unit_host(const float *v, float *u);  // normalise a host 3-vector; false if unusable
 ds_status tracer_prepare(ds_cloud *c, const void *density, ds_dtype dt);
@@ -287,5 +294,19 @@ ds_status tracer_first_hits(hipStream_t s, const ds_cloud *c, const TracerParams
                             int64_t N, uint64_t seed, uint64_t sample, float *pos, float *view,
                             float *direct, uint8_t *hit);
 ds_status philox_blocks(hipStream_t s, const uint32_t *ctr_key, int64_t n, uint32_t *out);
+// Light sets (tp.light_mode == kLightSetMode).  Camera samples: per ray the first
+// collision, then `draws` lights, each with one ratio-tracking estimate; rows
+// i * draws + q of pos / view / light / weight (pos and view repeated per draw);
+// direct = albedo * E * mean over draws of weight * p * T.
+ds_status tracer_first_hits_set(hipStream_t s, const ds_cloud *c, const TracerParams &tp,
+                                int draws, const float *ray_o, const float *ray_d, int64_t N,
+                                uint64_t seed, uint64_t sample, float *pos, float *view,
+                                float *light, float *weight, float *direct, uint8_t *hit);
+// Pixel sums of one camera sample under a light set: direct + albedo * E * mean over the
+// draws of weight * L_i (network, or li_mc where the row's fallback flag is set).
+ds_status tracer_accumulate_set(hipStream_t s, int64_t N, int draws, const uint8_t *hit,
+                                const float *direct, const float *li_net, const uint8_t *flags,
+                                const double *li_mc, const float *weight, float albedo, float E,
+                                double *sums, double *dsum, unsigned long long *n_fb);
 
 }  // namespace ds

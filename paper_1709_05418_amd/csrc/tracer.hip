@@ -55,14 +55,32 @@ struct Rng {
             ++c3;
         used = 0;
     }
-    // uniform in [0, 1) on the 2^-24 grid
-    __device__ float u()
+    // the top 24 bits of the next word
+    __device__ uint32_t bits24()
     {
         if (used == 4)
             refill();
-        return (float)(buf[used++] >> 8) * (1.f / 16777216.f);
+        return buf[used++] >> 8;
     }
+    // uniform in [0, 1) on the 2^-24 grid
+    __device__ float u() { return (float)bits24() * (1.f / 16777216.f); }
 };
+
+// Member of a light set drawn by one uniform's top 24 bits k: the first j with
+// k < thr[j] (thresholds strictly increasing, the last 2^24), by binary search.
+__device__ __forceinline__ int set_pick(const TracerParams &tp, Rng &r)
+{
+    const uint32_t k = r.bits24();
+    int lo = 0, hi = tp.set_m - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (k < tp.set_thr[mid])
+            hi = mid;
+        else
+            lo = mid + 1;
+    }
+    return lo;
+}
 
 // ------------------------------------------------------------------ geometry helpers
 struct V3 {
@@ -247,8 +265,13 @@ __device__ float li_path(const Medium &M, const TracerParams &tp, V3 x, V3 w, V3
         p = xn;
         if (r.u() >= tp.albedo)
             break;
-        if (tp.light_mode == 0)
+        if (tp.light_mode == 0) {
             sum += hg(tp.g, -dot(wh, wl)) * ratio_track(M, p, wl, r, steps) * tp.irradiance;
+        } else if (tp.light_mode == kLightSetMode) {
+            const float4 lw = tp.set_dw[set_pick(tp, r)];
+            const V3 lj = v3(lw.x, lw.y, lw.z);
+            sum += lw.w * hg(tp.g, -dot(wh, lj)) * ratio_track(M, p, lj, r, steps) * tp.irradiance;
+        }
         wprev = wh;
     }
     return sum;
@@ -405,6 +428,12 @@ __global__ void __launch_bounds__(kPaths) k_render_mc(Medium M, TracerParams tp,
             if (tp.light_mode == 0) {
                 const float direct = hg(tp.g, -dot(w, wl)) * ratio_track(M, x, wl, r, steps) * tp.irradiance;
                 e = (double)tp.albedo * (double)(direct + li_path(M, tp, x, w, wl, false, r));
+            } else if (tp.light_mode == kLightSetMode) {
+                const float4 lw = tp.set_dw[set_pick(tp, r)];
+                const V3 lj = v3(lw.x, lw.y, lw.z);
+                const float direct =
+                    lw.w * hg(tp.g, -dot(w, lj)) * ratio_track(M, x, lj, r, steps) * tp.irradiance;
+                e = (double)tp.albedo * (double)(direct + li_path(M, tp, x, w, wl, false, r));
             } else {
                 e = (double)tp.albedo * (double)li_path(M, tp, x, w, wl, true, r);
             }
@@ -446,6 +475,54 @@ __global__ void __launch_bounds__(256) k_first_hits(Medium M, TracerParams tp, V
     view[3 * i + 1] = h ? -d.y : 0.f;
     view[3 * i + 2] = h ? -d.z : 0.f;
     direct[i] = dir;
+    hit[i] = h ? 1 : 0;
+}
+
+// Camera samples under a light set: the first collision as k_first_hits, then `draws`
+// members of the set, each drawn by one uniform and followed by one ratio-tracking
+// estimate toward it, on the same stream in draw order.  Row i * draws + q receives the
+// collision, the view direction, the drawn direction and its weight; rays that escape
+// get zero rows.
+__global__ void __launch_bounds__(256) k_first_hits_set(Medium M, TracerParams tp, int draws,
+                                                        const float *ray_o, const float *ray_d,
+                                                        int64_t N, uint64_t seed, uint64_t sample,
+                                                        float *pos, float *view, float *light,
+                                                        float *weight, float *direct, uint8_t *hit)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N)
+        return;
+    V3 d;
+    bool h = false;
+    V3 x = v3(0, 0, 0);
+    Rng r;
+    int64_t steps = 0;
+    if (unit(ray_d + 3 * i, d)) {
+        const V3 o = v3(ray_o[3 * i], ray_o[3 * i + 1], ray_o[3 * i + 2]);
+        r.init(seed, ((uint64_t)i << 20) + sample);
+        h = delta_track(M, o, d, r, x, steps);
+    }
+    float sum = 0.f;
+    for (int q = 0; q < draws; ++q) {
+        const int64_t row = i * draws + q;
+        float4 lw = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (h) {
+            lw = tp.set_dw[set_pick(tp, r)];
+            const V3 lj = v3(lw.x, lw.y, lw.z);
+            sum += lw.w * hg(tp.g, dot(d, lj)) * ratio_track(M, x, lj, r, steps);
+        }
+        pos[3 * row] = x.x;
+        pos[3 * row + 1] = x.y;
+        pos[3 * row + 2] = x.z;
+        view[3 * row] = h ? -d.x : 0.f;
+        view[3 * row + 1] = h ? -d.y : 0.f;
+        view[3 * row + 2] = h ? -d.z : 0.f;
+        light[3 * row] = lw.x;
+        light[3 * row + 1] = lw.y;
+        light[3 * row + 2] = lw.z;
+        weight[row] = lw.w;
+    }
+    direct[i] = h ? tp.albedo * tp.irradiance * sum / (float)draws : 0.f;
     hit[i] = h ? 1 : 0;
 }
 
@@ -530,6 +607,40 @@ __global__ void __launch_bounds__(256) k_accumulate(int64_t N, const uint8_t *hi
         e = d + (double)albedo * li;
         if (fb && n_fb)
             atomicAdd(n_fb, 1ull);
+    }
+    sums[2 * i] += e;
+    sums[2 * i + 1] += e * e;
+    if (dsum)
+        dsum[2 * i] += d;
+}
+
+// One camera sample per pixel under a light set: direct + albedo * E * (1 / draws) *
+// sum over the draws of weight * L_i (the network's per unit irradiance, or the
+// path-traced estimate where the row's fallback flag is set).
+__global__ void __launch_bounds__(256) k_accumulate_set(int64_t N, int draws, const uint8_t *hit,
+                                                        const float *direct, const float *li_net,
+                                                        const uint8_t *flags, const double *li_mc,
+                                                        const float *weight, float albedo, float E,
+                                                        double *sums, double *dsum,
+                                                        unsigned long long *n_fb)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N)
+        return;
+    double e = 0.0, d = 0.0;
+    if (hit[i]) {
+        double li = 0.0;
+        unsigned long long nf = 0;
+        for (int q = 0; q < draws; ++q) {
+            const int64_t row = i * draws + q;
+            const bool fb = li_mc && (flags[row] & DS_FLAG_FALLBACK);
+            li += (double)weight[row] * (fb ? li_mc[row] : (double)li_net[row]);
+            nf += fb ? 1 : 0;
+        }
+        d = (double)direct[i];
+        e = d + (double)albedo * (double)E * li / draws;
+        if (nf && n_fb)
+            atomicAdd(n_fb, nf);
     }
     sums[2 * i] += e;
     sums[2 * i + 1] += e * e;
@@ -752,6 +863,31 @@ ds_status tracer_finish(hipStream_t s, const double *sums, int64_t N, int spp, d
                         double *var)
 {
     return reduce_records(s, sums, N, 1, spp, mean, var);
+}
+
+ds_status tracer_first_hits_set(hipStream_t s, const ds_cloud *c, const TracerParams &tp,
+                                int draws, const float *ray_o, const float *ray_d, int64_t N,
+                                uint64_t seed, uint64_t sample, float *pos, float *view,
+                                float *light, float *weight, float *direct, uint8_t *hit)
+{
+    DS_CHECK(tp.light_mode == kLightSetMode && tp.set_dw && tp.set_thr && tp.set_m >= 1,
+             DS_ERR_INVALID_ARG, "internal error: no light set");
+    DS_TRY_MEDIUM(s, c);
+    k_first_hits_set<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(
+        medium(c), tp, draws, ray_o, ray_d, N, seed, sample, pos, view, light, weight, direct, hit);
+    DS_HIP(hipGetLastError());
+    return DS_OK;
+}
+
+ds_status tracer_accumulate_set(hipStream_t s, int64_t N, int draws, const uint8_t *hit,
+                                const float *direct, const float *li_net, const uint8_t *flags,
+                                const double *li_mc, const float *weight, float albedo, float E,
+                                double *sums, double *dsum, unsigned long long *n_fb)
+{
+    k_accumulate_set<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(
+        N, draws, hit, direct, li_net, flags, li_mc, weight, albedo, E, sums, dsum, n_fb);
+    DS_HIP(hipGetLastError());
+    return DS_OK;
 }
 
 int tracer_blocks(int spp) { return split(spp).nblk; }

@@ -6,7 +6,10 @@
                  (ds_loss_grad), no host synchronisation inside an epoch
   judge          one view rendered with the network (ds_render_rpnn) and by
                  path tracing (ds_render_mc); relative L1 and RMSE of the network
-                 image and of the direct-only image against the path-traced one
+                 image and of the direct-only image against the path-traced one,
+                 and the time-to-unit-variance speedup; under a light set (a sun and
+                 sky as directional lights) through ds_render_rpnn_lights and
+                 ds_render_mc_lights
 
 All arithmetic runs in libdeepscatter's kernels; this module allocates buffers,
 slices them and reads scalars back.
@@ -17,6 +20,7 @@ import math
 import time
 
 import paper_1709_05418_amd as ds
+from paper_1709_05418_amd import synth
 
 
 def make_dataset(ctx, clouds, n_per_cloud, spp, seed, params=None, device="cuda"):
@@ -105,8 +109,8 @@ def image_errors(img, ref):
 
 def reference(ctx, cloud, params, light_dir, ray_o, ray_d, spp, seed, batch=256, log=None):
     """Path-traced image of spp samples per pixel, rendered in batches of independent
-    streams (seed + 1 + b) whose means and variances are combined in FP64.
-    Returns (mean, variance of the mean)."""
+    streams (seed + 1 + b) whose means and variances are combined in FP64.  light_dir is
+    one direction, or a ds.Lights set.  Returns (mean, variance of the mean)."""
     import torch
     mean = torch.zeros(ray_o.shape[0], dtype=torch.float64, device=ray_o.device)
     var = torch.zeros_like(mean)
@@ -115,7 +119,12 @@ def reference(ctx, cloud, params, light_dir, ray_o, ray_d, spp, seed, batch=256,
     t0 = time.time()
     while done < spp:
         n = min(batch, spp - done)
-        m, v = ds.ds_render_mc(ctx.h, cloud.h, params, light_dir, ray_o, ray_d, n, seed + 1 + b)
+        if isinstance(light_dir, ds.Lights):
+            m, v = ds.ds_render_mc_lights(ctx.h, cloud.h, params, light_dir.h, ray_o, ray_d, n,
+                                          seed + 1 + b)
+        else:
+            m, v = ds.ds_render_mc(ctx.h, cloud.h, params, light_dir, ray_o, ray_d, n,
+                                   seed + 1 + b)
         w = n / (done + n)
         mean = mean * (1 - w) + m * w
         var = var * (1 - w) ** 2 + v * w * w
@@ -128,31 +137,43 @@ def reference(ctx, cloud, params, light_dir, ray_o, ray_d, spp, seed, batch=256,
 
 
 def judge(ctx, cloud, net, precisions, params, light_dir, ray_o, ray_d, spp, ref_spp, seed,
-          fallback_spp=0, log=None):
+          fallback_spp=0, log=None, draws=8):
     """Network images (one per (name, precision)) and the direct-only image, each against
-    one path-traced reference rendered once."""
+    one path-traced reference rendered once.  light_dir is one direction, or a ds.Lights
+    set (then `draws` members are drawn per camera sample, Sec. 4.4).  Also the time to
+    unit variance (render time times mean pixel variance, Sec. 6) of both renderers and
+    its ratio, the speedup over path tracing."""
     import torch
     renders = {}
     for name, prec in precisions:
         torch.cuda.synchronize()
         t0 = time.time()
-        img, var, direct, nfb = ds.ds_render_rpnn(ctx.h, cloud.h, net.h, prec, params,
-                                                  light_dir, ray_o, ray_d, spp, seed,
-                                                  fallback_spp, count_fallback=True)
+        if isinstance(light_dir, ds.Lights):
+            img, var, direct, nfb = ds.ds_render_rpnn_lights(
+                ctx.h, cloud.h, net.h, prec, params, light_dir.h, draws, ray_o, ray_d, spp, seed,
+                fallback_spp, count_fallback=True)
+        else:
+            img, var, direct, nfb = ds.ds_render_rpnn(ctx.h, cloud.h, net.h, prec, params,
+                                                      light_dir, ray_o, ray_d, spp, seed,
+                                                      fallback_spp, count_fallback=True)
         torch.cuda.synchronize()
-        renders[name] = (img, direct, nfb, time.time() - t0)
+        renders[name] = (img, var, direct, nfb, time.time() - t0)
     t0 = time.time()
     ref, ref_var = reference(ctx, cloud, params, light_dir, ray_o, ray_d, ref_spp, seed, log=log)
     torch.cuda.synchronize()
     t_ref = time.time() - t0
     noise = float(math.sqrt(float(ref_var.sum())) / max(float(ref.sum()), 1e-300))
+    ttuv_ref = t_ref * float(ref_var.mean())
     out = {}
-    for name, (img, direct, nfb, t_net) in renders.items():
+    for name, (img, var, direct, nfb, t_net) in renders.items():
         l1, rmse = image_errors(img, ref)
         l1d, rmsed = image_errors(direct, ref)
+        ttuv = t_net * float(var.mean())
         out[name] = {"rel_l1": l1, "rmse": rmse, "rel_l1_direct_only": l1d,
                      "rmse_direct_only": rmsed, "ref_noise_rel": noise, "fallback_samples": nfb,
-                     "seconds_network": t_net, "seconds_reference": t_ref}
+                     "seconds_network": t_net, "seconds_reference": t_ref,
+                     "ttuv_network": ttuv, "ttuv_reference": ttuv_ref,
+                     "ttuv_speedup": ttuv_ref / max(ttuv, 1e-300)}
     return out
 
 
@@ -164,7 +185,35 @@ def quantize_on(ctx, net, cloud, n=65536, seed=77):
 
 
 JUDGE_KEYS = ("rel_l1", "rmse", "rel_l1_direct_only", "rmse_direct_only", "ref_noise_rel",
-              "seconds_network", "seconds_reference", "fallback_samples")
+              "seconds_network", "seconds_reference", "fallback_samples", "ttuv_network",
+              "ttuv_reference", "ttuv_speedup")
+
+
+def judge_sun_sky(args, ctx, cloud, net, prm, precs, log):
+    """The crop judged under a synthetic sun and sky (a set of directional lights, Fig. 7):
+    the network renderer drawing args.draws members per camera sample against the path
+    tracer drawing one member per next-event estimate.  Returns summary entries."""
+    dirs, E = synth.sun_sky_lights(synth.table1_lights()["side"])
+    lights = ds.Lights(ctx, dirs, E)
+    try:
+        c = args.sky_crop
+        co, cd = camera(args.width, args.height,
+                        crop=((args.width - c) // 2, (args.height - c) // 2, c, c), seed=3)
+        js = judge(ctx, cloud, net, precs, prm, lights, co, cd, args.crop_spp, args.sky_ref_spp,
+                   13, args.fallback_spp, log=log, draws=args.draws)
+    finally:
+        lights.close()
+    out = {"sunsky_lights": int(E.size), "sunsky_draws": args.draws, "sunsky_crop": c,
+           "sunsky_ref_spp": args.sky_ref_spp}
+    for name, j in js.items():
+        for k in JUDGE_KEYS:
+            out[f"sunsky_{k}_{name}"] = j[k]
+        log(f"sun-sky crop {c}^2 {name} ({E.size} lights, {args.draws} draws per sample): "
+            f"rel L1 {j['rel_l1']:.4f} (direct only {j['rel_l1_direct_only']:.4f}), RMSE "
+            f"{j['rmse']:.5f}; reference noise {j['ref_noise_rel']:.4f}; network "
+            f"{j['seconds_network']:.2f}s vs reference {j['seconds_reference']:.2f}s; TTUV "
+            f"speedup {j['ttuv_speedup']:.1f}x")
+    return out
 
 
 def camera(width, height, cam_pos=(0.0, 0.12, 2.3), look_at=(0.0, 0.0, 0.0), fov_deg=42.0,
@@ -202,7 +251,6 @@ def main(argv=None):
     import json
     import numpy as np
     import torch
-    from paper_1709_05418_amd import synth
     ap = argparse.ArgumentParser()
     ap.add_argument("--clouds", type=int, default=32)
     ap.add_argument("--n", type=int, default=256)
@@ -226,6 +274,11 @@ def main(argv=None):
     ap.add_argument("--ref-spp", type=int, default=512)
     ap.add_argument("--fallback-spp", type=int, default=64)
     ap.add_argument("--seed", type=int, default=1000)
+    ap.add_argument("--sun-sky", action="store_true",
+                    help="also judge a crop under a synthetic sun and sky light set")
+    ap.add_argument("--draws", type=int, default=8, help="light-set members per camera sample")
+    ap.add_argument("--sky-crop", type=int, default=128)
+    ap.add_argument("--sky-ref-spp", type=int, default=1024)
     ap.add_argument("--save-theta", default=None)
     ap.add_argument("--load-theta", default=None,
                     help="judge a network saved by --save-theta instead of training one")
@@ -311,6 +364,8 @@ def main(argv=None):
             f"{j['rel_l1_direct_only']:.4f}), RMSE {j['rmse']:.5f}; reference noise "
             f"{j['ref_noise_rel']:.4f}; network {j['seconds_network']:.2f}s vs reference "
             f"{j['seconds_reference']:.2f}s")
+    if args.sun_sky:
+        summary.update(judge_sun_sky(args, ctx, jc, net, prm, precs, log))
     summary.update({"train_precision": args.train_precision,
                     "clouds": args.clouds, "n": args.n, "pairs": per * args.clouds,
                     "spp": args.spp, "K": K, "W": W, "steps": args.steps, "batch": args.batch,
@@ -329,7 +384,6 @@ def judge_only(args, ctx, net, prm, log):
     """The judge part of main() for a given network: a full frame and the crop."""
     import json
     import torch
-    from paper_1709_05418_amd import synth
     K = net.K
     t0 = time.time()
     d = synth.cloud_density(args.judge_n, args.seed + 5000, worley=0.3, device="cuda",
@@ -366,6 +420,8 @@ def judge_only(args, ctx, net, prm, log):
             f"{j['rel_l1_direct_only']:.4f}), RMSE {j['rmse']:.5f}; reference noise "
             f"{j['ref_noise_rel']:.4f}; network {j['seconds_network']:.2f}s vs reference "
             f"{j['seconds_reference']:.2f}s ({args.ref_spp} spp)")
+    if args.sun_sky:
+        summary.update(judge_sun_sky(args, ctx, jc, net, prm, precs, log))
     summary.update({"judge_n": args.judge_n, "frame": [args.width, args.height],
                     "crop": args.crop, "crop_spp": args.crop_spp, "ref_spp": args.ref_spp,
                     "theta": args.load_theta})

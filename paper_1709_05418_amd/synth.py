@@ -393,3 +393,34 @@ def table1_lights(cam_pos=(0.0, 0.12, 2.3), look_at=(0.0, 0.0, 0.0)):
         "front": nrm(-fwd + 0.35 * up + 0.2 * right),
         "back": nrm(fwd + 0.35 * up + 0.2 * right),
     }
+
+
+def sun_sky_lights(sun_dir, sun_irradiance: float = 1.0, sky_radiance: float = 0.08,
+                   n_bands: int = 8, n_az: int = 16, ground: float = 0.25):
+    """A synthetic sun and sky as a set of directional lights (the paper's sun-sky
+    illumination, Fig. 7, approximated by directions): the sun as one light of
+    irradiance sun_irradiance, plus the sphere cut into n_bands equal-height bands of
+    the up coordinate y times n_az equal azimuth sectors (equal solid angle 4 pi /
+    (n_bands n_az) each), one light at each cell centre with irradiance radiance times
+    that solid angle.  Sky radiance (y > 0): sky_radiance * (0.6 + 0.4 (1 - y)) * (1 + 2
+    exp(-3 angle to the sun)), brighter toward the horizon and around the sun; below the
+    horizon a constant ground * sky_radiance.  Input data only: returns (dirs (m, 3)
+    float32, irradiance (m,) float64)."""
+    s = np.asarray(sun_dir, np.float64)
+    s = s / np.linalg.norm(s)
+    dirs, E = [s], [float(sun_irradiance)]
+    dw = 4.0 * np.pi / (n_bands * n_az)
+    for b in range(n_bands):
+        y = -1.0 + (2.0 * b + 1.0) / n_bands
+        r = np.sqrt(max(0.0, 1.0 - y * y))
+        for a in range(n_az):
+            phi = 2.0 * np.pi * (a + 0.5) / n_az
+            v = np.array([r * np.cos(phi), y, r * np.sin(phi)])
+            if y > 0:
+                ang = np.arccos(np.clip(v @ s, -1.0, 1.0))
+                L = sky_radiance * (0.6 + 0.4 * (1.0 - y)) * (1.0 + 2.0 * np.exp(-3.0 * ang))
+            else:
+                L = ground * sky_radiance
+            dirs.append(v)
+            E.append(L * dw)
+    return np.asarray(dirs, np.float32), np.asarray(E, np.float64)

@@ -51,6 +51,14 @@ def test_null_and_bad_arguments_are_rejected_before_any_launch():
     assert L.ds_predict(None, None, None, 1, None, None, None, 10, None, None, None) == -1
     assert L.ds_gather(None, None, None, None, None, 4, 0, None, None) == -1
     assert L.ds_net_create(None, None, C.byref(out)) == -1
+    assert L.ds_lights_create(None, 1, None, None, C.byref(out)) == -1
+    assert L.ds_render_mc_lights(None, None, None, None, None, None, 4, 1, 0, None, None) == -1
+    assert L.ds_first_hits_lights(None, None, None, None, 1, None, None, 4, 0, 0, None, None,
+                                  None, None, None, None) == -1
+    assert L.ds_render_rpnn_lights(None, None, None, 1, None, None, 1, None, None, 4, 1, 0, 0,
+                                   None, None, None, None) == -1
+    assert L.ds_light_table(0, None, None, None) == -1
+    assert L.ds_lights_destroy(None) == 0
     # destroying NULL handles is a no-op
     assert L.ds_destroy(None) == 0 and L.ds_cloud_destroy(None) == 0 and L.ds_net_destroy(None) == 0
 

@@ -4,11 +4,13 @@ counting, the camera-sample direct term against the closed form of a homogeneous
 and the path-traced pixels against the directional renderer by linearity in the lights.
 CPU only."""
 import math
+import os
 
 import numpy as np
 import pytest
 
 import oracle as O
+import paper_1709_05418_amd as ds
 from paper_1709_05418_amd import synth
 
 from test_oracle_tracer import ramp_int
@@ -139,3 +141,16 @@ def test_light_set_is_linear_in_its_lights(small_scene):
     sd = np.sqrt(Ea ** 2 * va + Eb ** 2 * vb + vs)
     assert np.all(np.abs(ms - want) < 5 * sd + 1e-12), (ms, want)
     assert math.isclose(ms.sum(), want.sum(), rel_tol=0.05)
+
+
+@pytest.mark.skipif(not os.path.exists(ds.LIB_PATH), reason="libdeepscatter.so not built")
+@pytest.mark.parametrize("E", [[1.0], [1.0, 2.0, 3.0, 1e-9], list(np.geomspace(1e-6, 1e3, 40)),
+                               list(np.random.default_rng(5).random(65536) + 1e-9)])
+def test_library_light_table_matches_oracle(E):
+    thr, w = ds.ds_light_table(E)
+    thr_o, w_o = O.light_table(E)
+    np.testing.assert_array_equal(thr, thr_o)
+    np.testing.assert_array_equal(w, w_o)
+    for bad in ([], [1.0, 0.0], [np.nan], [1.0, -2.0]):
+        with pytest.raises(ds.DSError):
+            ds.ds_light_table(bad)
