@@ -193,9 +193,24 @@ def judge_sun_sky(args, ctx, cloud, net, prm, precs, log):
     """The crop judged under a synthetic sun and sky (a set of directional lights, Fig. 7):
     the network renderer drawing args.draws members per camera sample against the path
     tracer drawing one member per next-event estimate.  Returns summary entries."""
+    import torch
     dirs, E = synth.sun_sky_lights(synth.table1_lights()["side"])
     lights = ds.Lights(ctx, dirs, E)
+    out = {"sunsky_lights": int(E.size), "sunsky_draws": args.draws, "sunsky_crop": args.sky_crop,
+           "sunsky_ref_spp": args.sky_ref_spp}
     try:
+        o, dd = camera(args.width, args.height, seed=1)
+        for name, prec in precs:
+            torch.cuda.synchronize()
+            tf = time.time()
+            ds.ds_render_rpnn_lights(ctx.h, cloud.h, net.h, prec, prm, lights.h, args.draws, o,
+                                     dd, args.frame_spp, 5, args.fallback_spp, want_var=False,
+                                     want_direct=False)
+            torch.cuda.synchronize()
+            out[f"sunsky_frame_ms_{name}"] = (time.time() - tf) * 1e3
+            log(f"sun-sky {args.width}x{args.height} frame {name}, {args.frame_spp} spp x "
+                f"{args.draws} lights: {out[f'sunsky_frame_ms_{name}']:.1f} ms")
+        del o, dd
         c = args.sky_crop
         co, cd = camera(args.width, args.height,
                         crop=((args.width - c) // 2, (args.height - c) // 2, c, c), seed=3)
@@ -203,8 +218,6 @@ def judge_sun_sky(args, ctx, cloud, net, prm, precs, log):
                    13, args.fallback_spp, log=log, draws=args.draws)
     finally:
         lights.close()
-    out = {"sunsky_lights": int(E.size), "sunsky_draws": args.draws, "sunsky_crop": c,
-           "sunsky_ref_spp": args.sky_ref_spp}
     for name, j in js.items():
         for k in JUDGE_KEYS:
             out[f"sunsky_{k}_{name}"] = j[k]
@@ -363,7 +376,7 @@ def main(argv=None):
         log(f"crop {args.crop}^2 {name}: rel L1 {j['rel_l1']:.4f} (direct only "
             f"{j['rel_l1_direct_only']:.4f}), RMSE {j['rmse']:.5f}; reference noise "
             f"{j['ref_noise_rel']:.4f}; network {j['seconds_network']:.2f}s vs reference "
-            f"{j['seconds_reference']:.2f}s")
+            f"{j['seconds_reference']:.2f}s; TTUV speedup {j['ttuv_speedup']:.0f}x")
     if args.sun_sky:
         summary.update(judge_sun_sky(args, ctx, jc, net, prm, precs, log))
     summary.update({"train_precision": args.train_precision,
@@ -410,16 +423,19 @@ def judge_only(args, ctx, net, prm, log):
             f"{summary[f'frame_ms_{name}']:.1f} ms, fallback samples {nfb}")
     cx0 = (args.width - args.crop) // 2
     cy0 = (args.height - args.crop) // 2
-    co, cd = camera(args.width, args.height, crop=(cx0, cy0, args.crop, args.crop), seed=2)
-    js = judge(ctx, jc, net, precs, prm, light, co, cd, args.crop_spp, args.ref_spp, 11,
-               args.fallback_spp, log=log)
+    js = {}
+    if args.crop > 0:   # --crop 0 judges the frame and the light-set crop only
+        co, cd = camera(args.width, args.height, crop=(cx0, cy0, args.crop, args.crop), seed=2)
+        js = judge(ctx, jc, net, precs, prm, light, co, cd, args.crop_spp, args.ref_spp, 11,
+                   args.fallback_spp, log=log)
     for name, j in js.items():
         for k in JUDGE_KEYS:
             summary[f"crop_{k}_{name}"] = j[k]
         log(f"crop {args.crop}^2 {name}: rel L1 {j['rel_l1']:.4f} (direct only "
             f"{j['rel_l1_direct_only']:.4f}), RMSE {j['rmse']:.5f}; reference noise "
             f"{j['ref_noise_rel']:.4f}; network {j['seconds_network']:.2f}s vs reference "
-            f"{j['seconds_reference']:.2f}s ({args.ref_spp} spp)")
+            f"{j['seconds_reference']:.2f}s ({args.ref_spp} spp); TTUV speedup "
+            f"{j['ttuv_speedup']:.0f}x")
     if args.sun_sky:
         summary.update(judge_sun_sky(args, ctx, jc, net, prm, precs, log))
     summary.update({"judge_n": args.judge_n, "frame": [args.width, args.height],
