@@ -23,6 +23,10 @@ What each part follows in the paper and what pins it (tests/test_oracle_*.py):
   first_hits      Sec. 4.4 camera sample: first collision   homogeneous box: hit fraction
                   and direct single scattering              1 - exp(-sigma L), direct term against
                                                             albedo p exp(-sigma s) E
+  trace_li_       Sec. 5.1 progressive estimate (+-2 % at   equals the fixed-count estimate at its
+  adaptive        95 %), Sec. 7 target L_s = L_d + L_i      path count, rule fails one batch
+                                                            earlier; L_s - L_i against the direct
+                                                            closed form, L_s furnace = E exactly
   light_table,    Sec. 4.4 distant emitter as directional   p_j w_j = E_j exactly, all 2^24 draws
   *_lights        lights, one drawn per estimate            counted, homogeneous-box closed form,
                                                             one-light set = directional renderer,
@@ -83,7 +87,10 @@ def lib():
             "dso_philox4x32_10": (None, [P, P, P]),
             "dso_hg": (D, [D, D]),
             "dso_hg_sample_cos": (D, [D, D]),
-            "dso_trace_li": (I, [P, I, I, I, I, D, P, D, D, D, D, I, I, I, U64, P, P, P, I64, P, P]),
+            "dso_trace_li": (I, [P, I, I, I, I, D, P, D, D, D, D, I, I, I, I, U64, P, P, P, I64, P,
+                                 P]),
+            "dso_trace_li_adaptive": (I, [P, I, I, I, I, D, P, D, D, D, D, I, I, I, I, I, D, D, U64,
+                                          P, P, P, I64, P, P, P]),
             "dso_transmittance": (I, [P, I, I, I, I, D, P, D, P, P, I64, I, U64, P, P]),
             "dso_sample_records": (I, [P, I, I, I, I, D, P, D, I64, U64, P, P, P, P]),
             "dso_render_pixels": (I, [P, I, I, I, I, D, P, D, D, D, D, I, I, P, P, P, I64, I, U64,
@@ -266,8 +273,9 @@ def hg_sample_cos(g, u):
 
 
 def trace_li(grid: Grid, pos, view, light, albedo=0.999, g=0.85, irradiance=1.0, light_mode=0,
-             max_interactions=0, spp=64, seed=1):
-    """Per record: mean of spp path estimates of L_i and the variance of that mean."""
+             max_interactions=0, spp=64, seed=1, include_direct=False):
+    """Per record: mean of spp path estimates of L_i (of L_s = L_d + L_i with
+    include_direct) and the variance of that mean."""
     pos = np.ascontiguousarray(pos, np.float32)
     view = np.ascontiguousarray(view, np.float32)
     light = np.ascontiguousarray(light, np.float32)
@@ -275,9 +283,30 @@ def trace_li(grid: Grid, pos, view, light, albedo=0.999, g=0.85, irradiance=1.0,
     mean = np.zeros(P, np.float64)
     var = np.zeros(P, np.float64)
     _check(lib().dso_trace_li(*grid.args(), _p(grid.aabb_min), grid.h0, albedo, g, irradiance,
-                              light_mode, max_interactions, spp, seed, _p(pos), _p(view),
-                              _p(light), P, _p(mean), _p(var)), "trace_li")
+                              light_mode, max_interactions, int(include_direct), spp, seed,
+                              _p(pos), _p(view), _p(light), P, _p(mean), _p(var)), "trace_li")
     return mean, var
+
+
+def trace_li_adaptive(grid: Grid, pos, view, light, batch=64, max_spp=4096, rel=0.02, zq=1.96,
+                      albedo=0.999, g=0.85, irradiance=1.0, light_mode=0, max_interactions=0,
+                      seed=1, include_direct=False):
+    """Progressive estimates: batches of paths until zq * sqrt(var of mean) <= rel * |mean|
+    (the mean within +-rel at the confidence of zq) or max_spp paths.  Returns (mean,
+    variance of the mean, paths used)."""
+    pos = np.ascontiguousarray(pos, np.float32)
+    view = np.ascontiguousarray(view, np.float32)
+    light = np.ascontiguousarray(light, np.float32)
+    P = pos.shape[0]
+    mean = np.zeros(P, np.float64)
+    var = np.zeros(P, np.float64)
+    n = np.zeros(P, np.int32)
+    _check(lib().dso_trace_li_adaptive(*grid.args(), _p(grid.aabb_min), grid.h0, albedo, g,
+                                       irradiance, light_mode, max_interactions,
+                                       int(include_direct), batch, max_spp, rel, zq, seed,
+                                       _p(pos), _p(view), _p(light), P, _p(mean), _p(var), _p(n)),
+           "trace_li_adaptive")
+    return mean, var, n
 
 
 def transmittance(grid: Grid, orig, dirs, spp=256, seed=1):

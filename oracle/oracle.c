@@ -1033,11 +1033,27 @@ static int medium_init(medium_t *M, const void *dens, int dtype, int nx, int ny,
 /* Per record i: mean of spp path estimates and the variance of that mean
  * (sample variance / spp), accumulated in double.  Path s of record i uses
  * random stream id = i * 2^20 + s under key `seed`. */
+/* One record estimate: the indirect in-scattered radiance L_i (li_path), or with
+ * include_direct all in-scattered radiance L_s = L_d + L_i (Sec. 7): for the
+ * directional light the direct term p(-w . w_l) T(x -> light) E by ratio tracking,
+ * drawn before the path; for the uniform environment the light that reaches x
+ * without a collision is counted as well. */
+static double record_path(const medium_t *M, const tracer_params *tp, const double x[3],
+                          const double w[3], const double wl[3], int include_direct, rng_t *r)
+{
+    if (!include_direct)
+        return li_path(M, tp, x, w, wl, 0, r);
+    if (tp->light_mode == 1)
+        return li_path(M, tp, x, w, wl, 1, r);
+    double d = dso_hg(tp->g, -dot3(w, wl)) * ratio_track(M, x, wl, r) * tp->irradiance;
+    return d + li_path(M, tp, x, w, wl, 0, r);
+}
+
 int dso_trace_li(const void *dens, int dtype, int nx, int ny, int nz, double sigma_max,
                  const double *aabb_min, double h0, double albedo, double g, double irradiance,
-                 int light_mode, int max_interactions, int spp, uint64_t seed, const float *pos,
-                 const float *view, const float *light, int64_t P, double *mean_out,
-                 double *var_out)
+                 int light_mode, int max_interactions, int include_direct, int spp, uint64_t seed,
+                 const float *pos, const float *view, const float *light, int64_t P,
+                 double *mean_out, double *var_out)
 {
     medium_t M;
     if (!medium_init(&M, dens, dtype, nx, ny, nz, sigma_max, aabb_min, h0) || spp <= 0 ||
@@ -1060,7 +1076,7 @@ int dso_trace_li(const void *dens, int dtype, int nx, int ny, int nz, double sig
         for (int s = 0; s < spp; ++s) {
             rng_t r;
             rng_init(&r, seed, ((uint64_t)i << 20) + (uint64_t)s);
-            double e = li_path(&M, &tp, x, w, wl, 0, &r);
+            double e = record_path(&M, &tp, x, w, wl, include_direct, &r);
             s1 += e;
             s2 += e * e;
         }
@@ -1068,6 +1084,59 @@ int dso_trace_li(const void *dens, int dtype, int nx, int ny, int nz, double sig
         mean_out[i] = mean;
         if (var_out)
             var_out[i] = spp > 1 ? fmax(0.0, (s2 - spp * mean * mean) / (spp - 1)) / spp : 0.0;
+    }
+    return DSO_OK;
+}
+
+/* Progressive estimates (Sec. 5.1): paths are added one batch at a time until the
+ * sample mean lies within +-rel of the true value at the confidence of the normal
+ * quantile zq, i.e. zq * sqrt(variance of the mean) <= rel * |mean| after a whole
+ * batch, or until max_spp paths.  Path s of record i uses stream id i * 2^20 + s as in
+ * dso_trace_li, so the result at n paths is dso_trace_li's at spp = n.  n_out receives
+ * the number of paths used (0 for records with an unusable direction). */
+int dso_trace_li_adaptive(const void *dens, int dtype, int nx, int ny, int nz, double sigma_max,
+                          const double *aabb_min, double h0, double albedo, double g,
+                          double irradiance, int light_mode, int max_interactions,
+                          int include_direct, int batch, int max_spp, double rel, double zq,
+                          uint64_t seed, const float *pos, const float *view, const float *light,
+                          int64_t P, double *mean_out, double *var_out, int32_t *n_out)
+{
+    medium_t M;
+    if (!medium_init(&M, dens, dtype, nx, ny, nz, sigma_max, aabb_min, h0) || batch < 2 ||
+        max_spp < batch || max_spp > (1 << 20) || max_spp % batch != 0 || !(rel > 0) ||
+        !(zq > 0))
+        return DSO_ERR_INVALID;
+    tracer_params tp = {albedo, g, irradiance, light_mode, max_interactions, NULL};
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t i = 0; i < P; ++i) {
+        double x[3] = {pos[3 * i], pos[3 * i + 1], pos[3 * i + 2]};
+        double wv[3] = {view[3 * i], view[3 * i + 1], view[3 * i + 2]};
+        double lv[3] = {light[3 * i], light[3 * i + 1], light[3 * i + 2]};
+        double w[3], wl[3];
+        mean_out[i] = 0.0;
+        var_out[i] = 0.0;
+        n_out[i] = 0;
+        if (!unit3(wv, w) || !unit3(lv, wl))
+            continue;
+        double s1 = 0.0, s2 = 0.0, mean = 0.0, vm = 0.0;
+        int n = 0;
+        while (n < max_spp) {
+            rng_t r;
+            rng_init(&r, seed, ((uint64_t)i << 20) + (uint64_t)n);
+            double e = record_path(&M, &tp, x, w, wl, include_direct, &r);
+            s1 += e;
+            s2 += e * e;
+            ++n;
+            if (n % batch == 0) {
+                mean = s1 / n;
+                vm = fmax(0.0, (s2 - n * mean * mean) / (n - 1)) / n;
+                if (zq * sqrt(vm) <= rel * fabs(mean))
+                    break;
+            }
+        }
+        mean_out[i] = mean;
+        var_out[i] = vm;
+        n_out[i] = n;
     }
     return DSO_OK;
 }
