@@ -314,6 +314,9 @@ typedef struct ds_tracer_params {
     float irradiance;     /* E of the light (DS_LIGHT_DIRECTIONAL) or of the environment */
     int32_t light_mode;   /* DS_LIGHT_DIRECTIONAL or DS_LIGHT_ENVIRONMENT                 */
     int32_t max_interactions; /* path length cap in collisions; 0 = unlimited          */
+    int32_t include_direct;   /* 0: estimates of L_i; 1: of all in-scattered radiance L_s =
+                                 L_d + L_i (Sec. 7's target ablation): ds_trace_li and the
+                                 record calls only, the render calls reject it           */
 } ds_tracer_params;
 
 /* The cloud's majorant sigma_max * max(d) (host write). */
@@ -331,6 +334,31 @@ ds_status ds_cloud_majorant(const ds_cloud *cloud, float *majorant);
 ds_status ds_trace_li(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params *params,
                       const float *pos, const float *view_dir, const float *light_dir, int64_t P,
                       int spp, uint64_t seed, double *mean_out, double *var_out);
+
+/* Progressive estimation (Sec. 5.1: paths are drawn until the mean lies within
+ * +-rel of the true value at a given confidence).  Per record, batches of batch_spp
+ * paths (path s on stream id i * 2^20 + s, as ds_trace_li) until
+ * z * sqrt(variance of the mean) <= rel * |mean| after a whole batch, or max_spp
+ * paths.  2 <= batch_spp, max_spp a multiple of batch_spp and <= 2^20, rel > 0,
+ * z > 0 (1.96 for 95 %). */
+typedef struct ds_adaptive {
+    int32_t batch_spp;
+    int32_t max_spp;
+    double rel;
+    double z;
+} ds_adaptive;
+
+/* ds_trace_li with progressive stopping: mean_out and var_out as ds_trace_li (var_out
+ * may be NULL), spp_out (device, P int32, may be NULL) the number of paths used (0
+ * for records with an unusable direction).  The estimate of a record that used n
+ * paths is the one ds_trace_li gives at spp = n, up to summation order.  Synchronises
+ * once per batch.  Library-owned workspace: 16 * P * ceil(batch_spp / 256) + 17 * P
+ * bytes. */
+ds_status ds_trace_li_adaptive(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params *params,
+                               const ds_adaptive *adaptive, const float *pos,
+                               const float *view_dir, const float *light_dir, int64_t P,
+                               uint64_t seed, double *mean_out, double *var_out,
+                               int32_t *spp_out);
 
 /* Training-record configurations (Sec. 5.1): per record a direction d uniform on
  * the sphere, a ray origin uniform over the disc of the box's bounding sphere
@@ -383,6 +411,16 @@ ds_status ds_make_records(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_pa
                           int64_t N, int spp, uint64_t seed, int64_t stride, float *z,
                           float *target_log1p, float *pos, float *view_dir, float *light_dir,
                           double *li_mean, double *li_var);
+
+/* ds_make_records with each target estimated progressively (ds_trace_li_adaptive's
+ * rule, same derived key), as Sec. 5.1 does; spp_out (device, N int32, may be NULL)
+ * receives the paths each record used.  Synchronises once per batch. */
+ds_status ds_make_records_adaptive(ds_ctx *ctx, const ds_cloud *cloud,
+                                   const ds_tracer_params *params, const ds_adaptive *adaptive,
+                                   int64_t N, uint64_t seed, int64_t stride, float *z,
+                                   float *target_log1p, float *pos, float *view_dir,
+                                   float *light_dir, double *li_mean, double *li_var,
+                                   int32_t *spp_out);
 
 /* Image formation with the network (Sec. 4.4): for each camera ray o + t d
  * (device [N][3] each) and each of spp samples s, a delta-tracked first

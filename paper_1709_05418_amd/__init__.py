@@ -92,6 +92,9 @@ def lib():
         "ds_batch_replay": (S, [P]),
         "ds_make_records": (S, [P, P, P, I64, I, C.c_uint64, I64, P, P, P, P, P, P, P]),
         "ds_render_rpnn": (S, [P, P, P, I, P, P, P, P, I64, I, C.c_uint64, I, P, P, P, P]),
+        "ds_trace_li_adaptive": (S, [P, P, P, P, P, P, P, I64, C.c_uint64, P, P, P]),
+        "ds_make_records_adaptive": (S, [P, P, P, P, I64, C.c_uint64, I64, P, P, P, P, P, P, P,
+                                         P]),
         "ds_lights_create": (S, [P, S, P, P, P]),
         "ds_light_table": (S, [S, P, P, P]),
         "ds_lights_destroy": (S, [P]),
@@ -115,13 +118,26 @@ class _NetDesc(C.Structure):
 
 class TracerParams(C.Structure):
     """ds_tracer_params: albedo, HG g, light irradiance (or environment radiance),
-    light_mode (DS_LIGHT_DIRECTIONAL / DS_LIGHT_ENVIRONMENT), max_interactions (0: none)."""
+    light_mode (DS_LIGHT_DIRECTIONAL / DS_LIGHT_ENVIRONMENT), max_interactions (0: none),
+    include_direct (record estimates of L_s = L_d + L_i instead of L_i)."""
     _fields_ = [("albedo", C.c_float), ("g", C.c_float), ("irradiance", C.c_float),
-                ("light_mode", C.c_int32), ("max_interactions", C.c_int32)]
+                ("light_mode", C.c_int32), ("max_interactions", C.c_int32),
+                ("include_direct", C.c_int32)]
 
-    def __init__(self, albedo=0.999, g=0.85, irradiance=1.0, light_mode=0, max_interactions=0):
+    def __init__(self, albedo=0.999, g=0.85, irradiance=1.0, light_mode=0, max_interactions=0,
+                 include_direct=0):
         super().__init__(float(albedo), float(g), float(irradiance), int(light_mode),
-                         int(max_interactions))
+                         int(max_interactions), int(include_direct))
+
+
+class Adaptive(C.Structure):
+    """ds_adaptive: paths in batches of batch_spp until z * sqrt(var of mean) <= rel * |mean|
+    or max_spp paths (Sec. 5.1 uses rel 0.02 at 95 %, z = 1.96)."""
+    _fields_ = [("batch_spp", C.c_int32), ("max_spp", C.c_int32), ("rel", C.c_double),
+                ("z", C.c_double)]
+
+    def __init__(self, batch_spp=256, max_spp=65536, rel=0.02, z=1.96):
+        super().__init__(int(batch_spp), int(max_spp), float(rel), float(z))
 
 
 def _check(st):
@@ -399,6 +415,20 @@ def ds_trace_li(ctx, cloud, params: TracerParams, pos, view_dir, light_dir, spp,
     return mean, var
 
 
+def ds_trace_li_adaptive(ctx, cloud, params: TracerParams, adaptive: Adaptive, pos, view_dir,
+                         light_dir, seed, want_var=True):
+    """Per record: (mean, variance of the mean, paths used) of the progressive estimate."""
+    import torch
+    P = pos.shape[0]
+    mean = _f64(P, pos.device)
+    var = _f64(P, pos.device) if want_var else None
+    n = torch.empty(P, dtype=torch.int32, device=pos.device)
+    _check(lib().ds_trace_li_adaptive(ctx, cloud, C.byref(params), C.byref(adaptive), _pts(pos),
+                                      _pts(view_dir, P), _pts(light_dir, P), P, int(seed),
+                                      _ptr(mean), _ptr(var), _ptr(n)))
+    return mean, var, n
+
+
 def ds_sample_records(ctx, cloud, N, seed, device="cuda", want_attempts=True):
     import torch
     pos = torch.empty((N, 3), dtype=torch.float32, device=device)
@@ -488,7 +518,8 @@ def ds_make_records(ctx, cloud, params: TracerParams, N, spp, seed, z, target, o
                     stride=1, want_records=False, want_li=False):
     """Training pairs into rows offset + i * stride of z ((M, 225K+1) float32) and
     target ((M,) float32, log(1 + L_i)).  Optionally returns (pos, view, light) and
-    (li_mean, li_var) of the N records."""
+    (li_mean, li_var) of the N records.  spp may be an Adaptive (progressive path
+    counts); then the second tuple also holds the paths each record used."""
     import torch
     D = z.shape[1]
     if z.dtype != torch.float32 or target.dtype != torch.float32 or z.dim() != 2:
@@ -503,9 +534,17 @@ def ds_make_records(ctx, cloud, params: TracerParams, N, spp, seed, z, target, o
         if want_li else [None, None]
     zp = C.c_void_p(z.data_ptr() + 4 * D * offset) if N > 0 else None
     tp = C.c_void_p(target.data_ptr() + 4 * offset) if N > 0 else None
-    _check(lib().ds_make_records(ctx, cloud, C.byref(params), int(N), int(spp), int(seed),
-                                 int(stride), zp, tp, *[_ptr(t) for t in rec],
-                                 *[_ptr(t) for t in li]))
+    if isinstance(spp, Adaptive):   # progressive path counts (ds_make_records_adaptive)
+        n = torch.empty(N, dtype=torch.int32, device=dev) if want_li else None
+        _check(lib().ds_make_records_adaptive(ctx, cloud, C.byref(params), C.byref(spp), int(N),
+                                              int(seed), int(stride), zp, tp,
+                                              *[_ptr(t) for t in rec], *[_ptr(t) for t in li],
+                                              _ptr(n)))
+        li = li + [n] if want_li else li
+    else:
+        _check(lib().ds_make_records(ctx, cloud, C.byref(params), int(N), int(spp), int(seed),
+                                     int(stride), zp, tp, *[_ptr(t) for t in rec],
+                                     *[_ptr(t) for t in li]))
     return (tuple(rec) if want_records else None), (tuple(li) if want_li else None)
 
 

@@ -1484,11 +1484,38 @@ static ds_status tracer_params(const ds_tracer_params *p, TracerParams &tp, cons
     DS_CHECK(p->light_mode == DS_LIGHT_DIRECTIONAL || p->light_mode == DS_LIGHT_ENVIRONMENT,
              DS_ERR_INVALID_ARG, "%s: unknown light_mode %d", fn, p->light_mode);
     DS_CHECK(p->max_interactions >= 0, DS_ERR_INVALID_ARG, "%s: max_interactions < 0", fn);
+    DS_CHECK(p->include_direct == 0 || p->include_direct == 1, DS_ERR_INVALID_ARG,
+             "%s: include_direct must be 0 or 1", fn);
     tp.albedo = p->albedo;
     tp.g = p->g;
     tp.irradiance = p->irradiance;
     tp.light_mode = p->light_mode;
     tp.max_interactions = p->max_interactions;
+    tp.include_direct = p->include_direct;
+    return DS_OK;
+}
+
+// The render calls add the direct term themselves: L_s estimates are for records only.
+static ds_status render_params(const ds_tracer_params *p, TracerParams &tp, const char *fn)
+{
+    ds_status st = tracer_params(p, tp, fn);
+    if (st)
+        return st;
+    DS_CHECK(!tp.include_direct, DS_ERR_INVALID_ARG,
+             "%s: include_direct is for record estimates; the renderer adds the direct term", fn);
+    return DS_OK;
+}
+
+static ds_status adaptive_params(const ds_adaptive *a, const char *fn)
+{
+    DS_CHECK(a, DS_ERR_INVALID_ARG, "%s: adaptive is NULL", fn);
+    DS_CHECK(a->batch_spp >= 2 && a->max_spp >= a->batch_spp && a->max_spp <= (1 << 20) &&
+                 a->max_spp % a->batch_spp == 0,
+             DS_ERR_INVALID_ARG,
+             "%s: need 2 <= batch_spp <= max_spp <= 2^20 with max_spp a multiple of batch_spp "
+             "(got %d, %d)", fn, a->batch_spp, a->max_spp);
+    DS_CHECK(std::isfinite(a->rel) && a->rel > 0.0 && std::isfinite(a->z) && a->z > 0.0,
+             DS_ERR_INVALID_ARG, "%s: rel and z must be finite and > 0", fn);
     return DS_OK;
 }
 
@@ -1496,7 +1523,7 @@ static ds_status set_params(const ds_tracer_params *params, const ds_lights *lig
                      const char *fn)
 {
     DS_CHECK(lights && lights->dw, DS_ERR_INVALID_ARG, "%s: NULL light set", fn);
-    ds_status st = tracer_params(params, tp, fn);
+    ds_status st = render_params(params, tp, fn);
     if (st)
         return st;
     DS_CHECK(tp.light_mode == DS_LIGHT_DIRECTIONAL, DS_ERR_INVALID_ARG,
@@ -1537,6 +1564,49 @@ ds_status ds_trace_li(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params
                      static_cast<double *>(ctx->ws), mean_out, var_out);
 }
 
+// Workspace of the progressive estimate: partial sums in ws, the rest carved from cv.
+static ds_status adaptive_li(ds_ctx *ctx, const ds_cloud *cloud, const TracerParams &tp,
+                             const ds_adaptive *ad, const float *pos, const float *view,
+                             const float *light, int64_t P, uint64_t seed, Carve &cv,
+                             double *mean, double *var, int32_t *n_out)
+{
+    ds_status st = ensure_ws(ctx, sizeof(double) * 2 * (size_t)P * tracer_blocks(ad->batch_spp));
+    if (st)
+        return st;
+    uint8_t *active = cv.take<uint8_t>((size_t)P);
+    double *sums = cv.take<double>(2 * (size_t)P);
+    unsigned long long *left = cv.take<unsigned long long>(1);
+    return tracer_li_adaptive(ctx->stream, cloud, tp, pos, view, light, P, ad->batch_spp,
+                              ad->max_spp, ad->rel, ad->z, seed, static_cast<double *>(ctx->ws),
+                              active, sums, left, mean, var, n_out, nullptr);
+}
+
+static size_t adaptive_ws2(int64_t P) { return (size_t)P * (1 + 2 * sizeof(double)) + 4 * 256; }
+
+ds_status ds_trace_li_adaptive(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params *params,
+                               const ds_adaptive *adaptive, const float *pos,
+                               const float *view_dir, const float *light_dir, int64_t P,
+                               uint64_t seed, double *mean_out, double *var_out,
+                               int32_t *spp_out)
+{
+    DS_CHECK(ctx && cloud && (P == 0 || (pos && view_dir && light_dir && mean_out)),
+             DS_ERR_INVALID_ARG, "ds_trace_li_adaptive: NULL argument");
+    DS_CHECK(P >= 0 && P <= ((int64_t)1 << 31) - 1, DS_ERR_INVALID_ARG,
+             "ds_trace_li_adaptive: P out of range");
+    TracerParams tp;
+    ds_status st = tracer_params(params, tp, "ds_trace_li_adaptive");
+    if (st)
+        return st;
+    if ((st = adaptive_params(adaptive, "ds_trace_li_adaptive")) || P == 0)
+        return st;
+    DS_HIP(hipSetDevice(ctx->device));
+    if ((st = ensure_ws2(ctx, adaptive_ws2(P))))
+        return st;
+    Carve cv(ctx->ws2);
+    return adaptive_li(ctx, cloud, tp, adaptive, pos, view_dir, light_dir, P, seed, cv, mean_out,
+                       var_out, spp_out);
+}
+
 ds_status ds_sample_records(ds_ctx *ctx, const ds_cloud *cloud, int64_t N, uint64_t seed,
                             float *pos, float *view_dir, float *light_dir, int32_t *attempts)
 {
@@ -1560,7 +1630,7 @@ ds_status ds_render_mc(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_param
     DS_CHECK(spp >= 1 && spp <= (1 << 20), DS_ERR_INVALID_ARG,
              "ds_render_mc: spp %d outside [1, 2^20]", spp);
     TracerParams tp;
-    ds_status st = tracer_params(params, tp, "ds_render_mc");
+    ds_status st = render_params(params, tp, "ds_render_mc");
     if (st)
         return st;
     float l[3];
@@ -1588,7 +1658,7 @@ ds_status ds_first_hits(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_para
     DS_CHECK(sample < (uint64_t(1) << 20), DS_ERR_INVALID_ARG,
              "ds_first_hits: sample index must be below 2^20");
     TracerParams tp;
-    ds_status st = tracer_params(params, tp, "ds_first_hits");
+    ds_status st = render_params(params, tp, "ds_first_hits");
     if (st)
         return st;
     float l[3];
@@ -1600,29 +1670,35 @@ ds_status ds_first_hits(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_para
                              view_dir, direct, hit);
 }
 
-ds_status ds_make_records(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params *params,
-                          int64_t N, int spp, uint64_t seed, int64_t stride, float *z,
-                          float *target_log1p, float *pos, float *view_dir, float *light_dir,
-                          double *li_mean, double *li_var)
+// Training pairs with fixed (ad == NULL) or progressive path counts.
+static ds_status make_records(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params *params,
+                              const ds_adaptive *ad, int64_t N, int spp, uint64_t seed,
+                              int64_t stride, float *z, float *target_log1p, float *pos,
+                              float *view_dir, float *light_dir, double *li_mean, double *li_var,
+                              int32_t *spp_out, const char *fn)
 {
     DS_CHECK(ctx && cloud && (N == 0 || (z && target_log1p)), DS_ERR_INVALID_ARG,
-             "ds_make_records: NULL argument");
-    DS_CHECK(N >= 0 && N <= ((int64_t)1 << 31) - 1, DS_ERR_INVALID_ARG,
-             "ds_make_records: N out of range");
-    DS_CHECK(stride >= 1, DS_ERR_INVALID_ARG, "ds_make_records: stride must be >= 1");
-    DS_CHECK(spp >= 1 && spp <= (1 << 20), DS_ERR_INVALID_ARG,
-             "ds_make_records: spp %d outside [1, 2^20]", spp);
+             "%s: NULL argument", fn);
+    DS_CHECK(N >= 0 && N <= ((int64_t)1 << 31) - 1, DS_ERR_INVALID_ARG, "%s: N out of range", fn);
+    DS_CHECK(stride >= 1, DS_ERR_INVALID_ARG, "%s: stride must be >= 1", fn);
     TracerParams tp;
-    ds_status st = tracer_params(params, tp, "ds_make_records");
+    ds_status st = tracer_params(params, tp, fn);
     if (st)
         return st;
+    if (ad) {
+        if ((st = adaptive_params(ad, fn)))
+            return st;
+    } else {
+        DS_CHECK(spp >= 1 && spp <= (1 << 20), DS_ERR_INVALID_ARG, "%s: spp %d outside [1, 2^20]",
+                 fn, spp);
+    }
     DS_CHECK(tp.light_mode == DS_LIGHT_DIRECTIONAL, DS_ERR_INVALID_ARG,
-             "ds_make_records: records need a directional light");
+             "%s: records need a directional light", fn);
     if (N == 0)
         return DS_OK;
     DS_HIP(hipSetDevice(ctx->device));
     st = ensure_ws2(ctx, 3 * 3 * sizeof(float) * (size_t)N + 2 * sizeof(double) * (size_t)N +
-                             5 * 256);
+                             5 * 256 + (ad ? adaptive_ws2(N) : 0));
     if (st)
         return st;
     Carve cv(ctx->ws2);
@@ -1634,11 +1710,16 @@ ds_status ds_make_records(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_pa
     st = tracer_records(s, cloud, N, seed, p, v, l, nullptr);
     if (st)
         return st;
-    st = ensure_ws(ctx, sizeof(double) * 2 * (size_t)N * tracer_blocks(spp));
-    if (st)
-        return st;
-    st = tracer_li(s, cloud, tp, p, v, l, N, spp, derived_key(seed, 0),
-                   static_cast<double *>(ctx->ws), m, li_var);
+    if (ad) {
+        st = adaptive_li(ctx, cloud, tp, ad, p, v, l, N, derived_key(seed, 0), cv, m, li_var,
+                         spp_out);
+    } else {
+        st = ensure_ws(ctx, sizeof(double) * 2 * (size_t)N * tracer_blocks(spp));
+        if (st)
+            return st;
+        st = tracer_li(s, cloud, tp, p, v, l, N, spp, derived_key(seed, 0),
+                       static_cast<double *>(ctx->ws), m, li_var);
+    }
     if (st)
         return st;
     st = gather_cells(ctx, cloud);
@@ -1651,6 +1732,27 @@ ds_status ds_make_records(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_pa
     if (st)
         return st;
     return tracer_targets(s, m, N, stride, target_log1p);
+}
+
+ds_status ds_make_records(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params *params,
+                          int64_t N, int spp, uint64_t seed, int64_t stride, float *z,
+                          float *target_log1p, float *pos, float *view_dir, float *light_dir,
+                          double *li_mean, double *li_var)
+{
+    return make_records(ctx, cloud, params, nullptr, N, spp, seed, stride, z, target_log1p, pos,
+                        view_dir, light_dir, li_mean, li_var, nullptr, "ds_make_records");
+}
+
+ds_status ds_make_records_adaptive(ds_ctx *ctx, const ds_cloud *cloud,
+                                   const ds_tracer_params *params, const ds_adaptive *adaptive,
+                                   int64_t N, uint64_t seed, int64_t stride, float *z,
+                                   float *target_log1p, float *pos, float *view_dir,
+                                   float *light_dir, double *li_mean, double *li_var,
+                                   int32_t *spp_out)
+{
+    return make_records(ctx, cloud, params, adaptive, N, 0, seed, stride, z, target_log1p, pos,
+                        view_dir, light_dir, li_mean, li_var, spp_out,
+                        "ds_make_records_adaptive");
 }
 
 ds_status ds_render_rpnn(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
@@ -1670,7 +1772,7 @@ ds_status ds_render_rpnn(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
     DS_CHECK(cloud->K == net->K, DS_ERR_INVALID_ARG,
              "ds_render_rpnn: the cloud has %d stencil levels, the network %d", cloud->K, net->K);
     TracerParams tp;
-    ds_status st = tracer_params(params, tp, "ds_render_rpnn");
+    ds_status st = render_params(params, tp, "ds_render_rpnn");
     if (st)
         return st;
     DS_CHECK(tp.light_mode == DS_LIGHT_DIRECTIONAL, DS_ERR_INVALID_ARG,

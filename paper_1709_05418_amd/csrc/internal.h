@@ -262,6 +262,7 @@ constexpr int kLightSetMode = 2;
 struct TracerParams {
     float albedo, g, irradiance;
     int light_mode, max_interactions;
+    int include_direct = 0;  // record estimates of L_s = L_d + L_i instead of L_i
     const float4 *set_dw = nullptr;
     const uint32_t *set_thr = nullptr;
     int set_m = 0;
@@ -275,6 +276,16 @@ ds_status tracer_li(hipStream_t s, const ds_cloud *c, const TracerParams &tp, co
                     const float *view, const float *light, int64_t P, int spp, uint64_t seed,
                     double *partial, double *mean, double *var, const uint8_t *mask = nullptr,
                     uint8_t mask_bits = 0);
+// Progressive estimates: batches of `batch` paths per active record until
+// zq * sqrt(var of mean) <= rel * |mean| or max_spp (a multiple of batch) paths.  Workspace:
+// partial (2 * P * tracer_blocks(batch) doubles), active (P bytes), sums (2 P doubles), left
+// (one counter).  Synchronises once per batch; rounds (may be NULL) gets the batch count.
+ds_status tracer_li_adaptive(hipStream_t s, const ds_cloud *c, const TracerParams &tp,
+                             const float *pos, const float *view, const float *light, int64_t P,
+                             int batch, int max_spp, double rel, double zq, uint64_t seed,
+                             double *partial, uint8_t *active, double *sums,
+                             unsigned long long *left, double *mean, double *var, int32_t *n_out,
+                             int *rounds);
 ds_status tracer_targets(hipStream_t s, const double *li, int64_t N, int64_t stride, float *t);
 ds_status tracer_accumulate(hipStream_t s, int64_t N, const uint8_t *hit, const float *direct,
                             const float *li_net, const uint8_t *flags, const double *li_mc,

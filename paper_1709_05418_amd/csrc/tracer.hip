@@ -306,11 +306,26 @@ __device__ void segment_sums(double s1, double s2, int seg, bool write, double *
     }
 }
 
+// One record estimate: L_i, or with tp.include_direct all in-scattered radiance L_s =
+// L_d + L_i (directional light: the direct term by ratio tracking, drawn before the path;
+// uniform environment: uncollided light counted too).
+__device__ float record_path(const Medium &M, const TracerParams &tp, V3 x, V3 w, V3 wl, Rng &r)
+{
+    if (!tp.include_direct)
+        return li_path(M, tp, x, w, wl, false, r);
+    if (tp.light_mode == 1)
+        return li_path(M, tp, x, w, wl, true, r);
+    int64_t steps = 0;
+    const float d = hg(tp.g, -dot(w, wl)) * ratio_track(M, x, wl, r, steps) * tp.irradiance;
+    return d + li_path(M, tp, x, w, wl, false, r);
+}
+
+// Paths s0 .. s0 + spp - 1 of every record (path s on stream id rec * 2^20 + s).
 __global__ void __launch_bounds__(kPaths) k_trace_li(Medium M, TracerParams tp, const float *pos,
                                                      const float *view, const float *light,
-                                                     int64_t P, int spp, Split sp, uint64_t seed,
-                                                     const uint8_t *mask, uint8_t mask_bits,
-                                                     double *partial)
+                                                     int64_t P, int s0, int spp, Split sp,
+                                                     uint64_t seed, const uint8_t *mask,
+                                                     uint8_t mask_bits, double *partial)
 {
     const int64_t group = blockIdx.x / sp.nblk;
     const int blk = blockIdx.x % sp.nblk;
@@ -322,8 +337,8 @@ __global__ void __launch_bounds__(kPaths) k_trace_li(Medium M, TracerParams tp, 
     if (wanted && s < spp && unit(view + 3 * rec, w) && unit(light + 3 * rec, wl)) {
         const V3 x = v3(pos[3 * rec], pos[3 * rec + 1], pos[3 * rec + 2]);
         Rng r;
-        r.init(seed, ((uint64_t)rec << 20) + (uint64_t)s);
-        e = (double)li_path(M, tp, x, w, wl, false, r);
+        r.init(seed, ((uint64_t)rec << 20) + (uint64_t)(s0 + s));
+        e = (double)record_path(M, tp, x, w, wl, r);
     }
     segment_sums(e, e * e, sp.seg, rec < P, partial + 2 * ((size_t)rec * sp.nblk + blk));
 }
@@ -343,6 +358,59 @@ __global__ void __launch_bounds__(256) k_finish_sums(const double *partial, int6
     mean[rec] = m;
     if (var)
         var[rec] = spp > 1 ? fmax(0.0, (s2 - spp * m * m) / (spp - 1)) / spp : 0.0;
+}
+
+// Progressive estimates (Sec. 5.1).  k_adapt_init marks the records with usable
+// directions active and zeroes their sums; after each batch of paths k_adapt_step adds
+// the batch's per-block partial sums (in block order), and a record stops once
+// zq * sqrt(variance of the mean) <= rel * |mean| or max_spp paths are reached, writing
+// its mean, variance of the mean and path count; records still active are counted.
+__global__ void __launch_bounds__(256) k_adapt_init(const float *view, const float *light,
+                                                    int64_t P, uint8_t *active, double *sums,
+                                                    double *mean, double *var, int32_t *n_out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P)
+        return;
+    V3 w, wl;
+    active[i] = unit(view + 3 * i, w) && unit(light + 3 * i, wl) ? 1 : 0;
+    sums[2 * i] = 0.0;
+    sums[2 * i + 1] = 0.0;
+    mean[i] = 0.0;
+    if (var)
+        var[i] = 0.0;
+    if (n_out)
+        n_out[i] = 0;
+}
+
+__global__ void __launch_bounds__(256) k_adapt_step(const double *partial, int nblk, int64_t P,
+                                                    int n, int max_spp, double rel, double zq,
+                                                    uint8_t *active, double *sums, double *mean,
+                                                    double *var, int32_t *n_out,
+                                                    unsigned long long *left)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P || !active[i])
+        return;
+    double s1 = sums[2 * i], s2 = sums[2 * i + 1];
+    for (int b = 0; b < nblk; ++b) {
+        s1 += partial[2 * (i * nblk + b)];
+        s2 += partial[2 * (i * nblk + b) + 1];
+    }
+    sums[2 * i] = s1;
+    sums[2 * i + 1] = s2;
+    const double m = s1 / n;
+    const double vm = fmax(0.0, (s2 - n * m * m) / (n - 1)) / n;
+    if (zq * sqrt(vm) <= rel * fabs(m) || n >= max_spp) {
+        active[i] = 0;
+        mean[i] = m;
+        if (var)
+            var[i] = vm;
+        if (n_out)
+            n_out[i] = n;
+    } else {
+        atomicAdd(left, 1ull);
+    }
 }
 
 // Record configurations (Sec. 5.1): direction d uniform on the sphere, origin
@@ -771,10 +839,44 @@ ds_status tracer_li(hipStream_t s, const ds_cloud *c, const TracerParams &tp, co
 {
     const Split sp = split(spp);
     DS_TRY_MEDIUM(s, c);
-    k_trace_li<<<grid_of(P, sp), kPaths, 0, s>>>(medium(c), tp, pos, view, light, P, spp, sp,
+    k_trace_li<<<grid_of(P, sp), kPaths, 0, s>>>(medium(c), tp, pos, view, light, P, 0, spp, sp,
                                                   seed, mask, mask_bits, partial);
     DS_HIP(hipGetLastError());
     return reduce_records(s, partial, P, sp.nblk, spp, mean, var);
+}
+
+ds_status tracer_li_adaptive(hipStream_t s, const ds_cloud *c, const TracerParams &tp,
+                             const float *pos, const float *view, const float *light, int64_t P,
+                             int batch, int max_spp, double rel, double zq, uint64_t seed,
+                             double *partial, uint8_t *active, double *sums,
+                             unsigned long long *left, double *mean, double *var, int32_t *n_out,
+                             int *rounds)
+{
+    const Split sp = split(batch);
+    const unsigned g256 = (unsigned)((P + 255) / 256);
+    DS_TRY_MEDIUM(s, c);
+    k_adapt_init<<<g256, 256, 0, s>>>(view, light, P, active, sums, mean, var, n_out);
+    DS_HIP(hipGetLastError());
+    int r = 0;
+    for (int n = batch; n <= max_spp; n += batch) {
+        ++r;
+        k_trace_li<<<grid_of(P, sp), kPaths, 0, s>>>(medium(c), tp, pos, view, light, P,
+                                                      n - batch, batch, sp, seed, active, 1,
+                                                      partial);
+        DS_HIP(hipGetLastError());
+        unsigned long long h = 0;
+        DS_HIP(hipMemsetAsync(left, 0, sizeof(*left), s));
+        k_adapt_step<<<g256, 256, 0, s>>>(partial, sp.nblk, P, n, max_spp, rel, zq, active, sums,
+                                          mean, var, n_out, left);
+        DS_HIP(hipGetLastError());
+        DS_HIP(hipMemcpyAsync(&h, left, sizeof(h), hipMemcpyDeviceToHost, s));
+        DS_HIP(hipStreamSynchronize(s));
+        if (h == 0)
+            break;
+    }
+    if (rounds)
+        *rounds = r;
+    return DS_OK;
 }
 
 ds_status tracer_records(hipStream_t s, const ds_cloud *c, int64_t N, uint64_t seed, float *pos,
