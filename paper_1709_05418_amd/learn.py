@@ -137,12 +137,15 @@ def reference(ctx, cloud, params, light_dir, ray_o, ray_d, spp, seed, batch=256,
 
 
 def judge(ctx, cloud, net, precisions, params, light_dir, ray_o, ray_d, spp, ref_spp, seed,
-          fallback_spp=0, log=None, draws=8):
+          fallback_spp=0, log=None, draws=8, ls_target=False):
     """Network images (one per (name, precision)) and the direct-only image, each against
     one path-traced reference rendered once.  light_dir is one direction, or a ds.Lights
     set (then `draws` members are drawn per camera sample, Sec. 4.4).  Also the time to
     unit variance (render time times mean pixel variance, Sec. 6) of both renderers and
-    its ratio, the speedup over path tracing."""
+    its ratio, the speedup over path tracing.  With ls_target the network predicts all
+    in-scattered radiance (Sec. 7's ablation): its image is albedo * E * g without the
+    renderer's direct term, i.e. the rendered mean minus the mean direct term (the
+    variance and TTUV then still describe the image with the direct term)."""
     import torch
     renders = {}
     for name, prec in precisions:
@@ -166,6 +169,8 @@ def judge(ctx, cloud, net, precisions, params, light_dir, ray_o, ray_d, spp, ref
     ttuv_ref = t_ref * float(ref_var.mean())
     out = {}
     for name, (img, var, direct, nfb, t_net) in renders.items():
+        if ls_target:
+            img = img - direct
         l1, rmse = image_errors(img, ref)
         l1d, rmsed = image_errors(direct, ref)
         ttuv = t_net * float(var.mean())
@@ -292,6 +297,17 @@ def main(argv=None):
     ap.add_argument("--draws", type=int, default=8, help="light-set members per camera sample")
     ap.add_argument("--sky-crop", type=int, default=128)
     ap.add_argument("--sky-ref-spp", type=int, default=1024)
+    ap.add_argument("--light", default="side", choices=["side", "front", "back"],
+                    help="the judge's directional light (Table 1's set-ups)")
+    ap.add_argument("--target", default="li", choices=["li", "ls"],
+                    help="train on L_i (indirect, Sec. 4) or on all in-scattered radiance L_s "
+                         "(the ablation of Sec. 7); an L_s network replaces the direct term")
+    ap.add_argument("--adaptive-rel", type=float, default=0.0,
+                    help="> 0: estimate each target progressively until its mean lies within "
+                         "+- this fraction at 95 %% confidence (Sec. 5.1), instead of --spp paths")
+    ap.add_argument("--adaptive-batch", type=int, default=256)
+    ap.add_argument("--adaptive-max", type=int, default=65536)
+    ap.add_argument("--no-judge", action="store_true", help="stop after training")
     ap.add_argument("--save-theta", default=None)
     ap.add_argument("--load-theta", default=None,
                     help="judge a network saved by --save-theta instead of training one")
@@ -311,23 +327,50 @@ def main(argv=None):
     D = ds.STENCIL_N * K + 1
     z = torch.empty((per * args.clouds, D), dtype=torch.float32, device=dev)
     t = torch.empty(per * args.clouds, dtype=torch.float32, device=dev)
+    rec_prm = ds.TracerParams(0.999, 0.85, 1.0, ds.DS_LIGHT_DIRECTIONAL, 0,
+                              include_direct=int(args.target == "ls"))
+    ad = (ds.Adaptive(args.adaptive_batch, args.adaptive_max, args.adaptive_rel, 1.96)
+          if args.adaptive_rel > 0 else None)
+    used = []
     t0 = time.time()
     for c in range(args.clouds):
         d = synth.cloud_density(args.n, args.seed + c, worley=0.3, device=dev)
         amin, h0 = synth.unit_box(args.n)
         cl = ds.Cloud(ctx, d, float(args.n), amin, h0, L, K)
-        ds.ds_make_records(ctx.h, cl.h, prm, per, args.spp, args.seed + 7919 * c, z, t,
-                           offset=c, stride=args.clouds)
+        _, li_out = ds.ds_make_records(ctx.h, cl.h, rec_prm, per, ad or args.spp,
+                                       args.seed + 7919 * c, z, t, offset=c, stride=args.clouds,
+                                       want_li=ad is not None)
         torch.cuda.synchronize()
+        if ad is not None:
+            used.append(li_out[2].cpu())
         cl.close()
         del d
-        log(f"cloud {c + 1}/{args.clouds}: {per} pairs x {args.spp} paths "
-            f"({time.time() - t0:.1f}s)")
+        log(f"cloud {c + 1}/{args.clouds}: {per} pairs x "
+            f"{'progressive' if ad else args.spp} paths ({time.time() - t0:.1f}s)")
     t_data = time.time() - t0
-    paths = per * args.clouds * args.spp
+    stats = {}
+    if ad is not None:
+        n_used = torch.cat(used).double()
+        paths = float(n_used.sum())
+        stats = {"adaptive_rel": args.adaptive_rel, "adaptive_batch": args.adaptive_batch,
+                 "adaptive_max": args.adaptive_max, "paths_mean": float(n_used.mean()),
+                 "paths_median": float(n_used.median()),
+                 "at_cap_fraction": float((n_used >= args.adaptive_max).double().mean())}
+        log(f"progressive targets: +-{100 * args.adaptive_rel:g} % at 95 %: mean "
+            f"{stats['paths_mean']:.0f} paths per pair (median {stats['paths_median']:.0f}), "
+            f"{100 * stats['at_cap_fraction']:.1f} % at the cap of {args.adaptive_max}")
+    else:
+        paths = per * args.clouds * args.spp
     li = torch.expm1(t)
     log(f"data: {z.shape[0]} pairs, {paths:.3e} paths in {t_data:.1f}s "
-        f"({paths / t_data:.3e} paths/s); mean L_i {float(li.mean()):.4f}")
+        f"({paths / t_data:.3e} paths/s); mean {'L_s' if args.target == 'ls' else 'L_i'} "
+        f"{float(li.mean()):.4f}")
+    if args.steps == 0:   # training data only
+        print(json.dumps({"target": args.target, "clouds": args.clouds, "n": args.n,
+                          "pairs": per * args.clouds, "spp": args.spp, "data_seconds": t_data,
+                          "paths_per_second": paths / t_data, **stats}), flush=True)
+        ctx.close()
+        return
     net = ds.Net(ctx, K, W, 3)
     net.set_params(synth.init_params(K, W, 3, args.seed + 1, branch_scale=1 / math.sqrt(K),
                                      out_scale=0.01, out_bias=float(li.mean())))
@@ -341,6 +384,17 @@ def main(argv=None):
         np.save(args.save_theta, net.get_params())
     del z, t
     torch.cuda.empty_cache()
+    base = {"target": args.target, "train_precision": args.train_precision,
+            "clouds": args.clouds, "n": args.n, "pairs": per * args.clouds, "spp": args.spp,
+            "K": K, "W": W, "steps": args.steps, "batch": args.batch, "data_seconds": t_data,
+            "paths_per_second": paths / t_data, "train_seconds": res["seconds"],
+            "held_out": res["held_out"], **stats}
+    if args.no_judge:
+        print(json.dumps(base), flush=True)
+        ds.ds_adam_destroy(opt)
+        net.close()
+        ctx.close()
+        return
     # held-out cloud, larger grid, same optical size in mean free paths per unit
     d = synth.cloud_density(args.judge_n, args.seed + 5000, worley=0.3, device=dev,
                             dtype=torch.bfloat16)
@@ -349,7 +403,7 @@ def main(argv=None):
     jc = ds.Cloud(ctx, d, float(args.n), amin, h0, Lj, K)
     del d
     log(f"judge cloud {args.judge_n}^3 built ({time.time() - t0:.1f}s)")
-    light = synth.table1_lights()["side"]
+    light = synth.table1_lights()[args.light]
     o, dd = camera(args.width, args.height, seed=1)
     summary = {}
     quantize_on(ctx, net, jc)
@@ -369,7 +423,7 @@ def main(argv=None):
     cy0 = (args.height - args.crop) // 2
     co, cd = camera(args.width, args.height, crop=(cx0, cy0, args.crop, args.crop), seed=2)
     js = judge(ctx, jc, net, precs, prm, light, co, cd, args.crop_spp, args.ref_spp, 11,
-               args.fallback_spp, log=log)
+               args.fallback_spp, log=log, ls_target=args.target == "ls")
     for name, j in js.items():
         for k in JUDGE_KEYS:
             summary[f"crop_{k}_{name}"] = j[k]
@@ -377,15 +431,12 @@ def main(argv=None):
             f"{j['rel_l1_direct_only']:.4f}), RMSE {j['rmse']:.5f}; reference noise "
             f"{j['ref_noise_rel']:.4f}; network {j['seconds_network']:.2f}s vs reference "
             f"{j['seconds_reference']:.2f}s; TTUV speedup {j['ttuv_speedup']:.0f}x")
-    if args.sun_sky:
+    if args.sun_sky and args.target == "li":
         summary.update(judge_sun_sky(args, ctx, jc, net, prm, precs, log))
-    summary.update({"train_precision": args.train_precision,
-                    "clouds": args.clouds, "n": args.n, "pairs": per * args.clouds,
-                    "spp": args.spp, "K": K, "W": W, "steps": args.steps, "batch": args.batch,
-                    "data_seconds": t_data, "paths_per_second": paths / t_data,
-                    "train_seconds": res["seconds"], "held_out": res["held_out"],
-                    "judge_n": args.judge_n, "frame": [args.width, args.height],
-                    "crop": args.crop, "crop_spp": args.crop_spp, "ref_spp": args.ref_spp})
+    summary.update(base)
+    summary.update({"judge_n": args.judge_n, "frame": [args.width, args.height],
+                    "crop": args.crop, "crop_spp": args.crop_spp, "ref_spp": args.ref_spp,
+                    "light": args.light})
     print(json.dumps(summary), flush=True)
     ds.ds_adam_destroy(opt)
     net.close()
@@ -406,7 +457,7 @@ def judge_only(args, ctx, net, prm, log):
     jc = ds.Cloud(ctx, d, float(args.n), amin, h0, Lj, K)
     del d
     log(f"judge cloud {args.judge_n}^3 built ({time.time() - t0:.1f}s)")
-    light = synth.table1_lights()["side"]
+    light = synth.table1_lights()[args.light]
     o, dd = camera(args.width, args.height, seed=1)
     summary = {}
     quantize_on(ctx, net, jc)
