@@ -31,6 +31,9 @@ What each part follows in the paper and what pins it (tests/test_oracle_*.py):
   *_lights        lights, one drawn per estimate            counted, homogeneous-box closed form,
                                                             one-light set = directional renderer,
                                                             linearity in the lights
+  mlp_forward,    Sec. 7 / Fig. 10 all-at-once MLPs         equal to forward / loss_grad of a K = 1
+  mlp_loss_grad   (numpy, FP64)                             RPNN (same parameter vector), central
+                                                            finite differences
   e4m3_encode     OCP 8-bit floating point, E4M3 format     torch.float8_e4m3fn cast, hand values,
                   (round to nearest even, saturating)       decode/encode round trip of every code
 """
@@ -247,6 +250,64 @@ def loss_grad(theta, K, W, H, z, target_log1p, want_grad=True):
     grad = np.zeros(th.size, np.float64) if want_grad else None
     _check(lib().dso_loss_grad(_p(th), K, W, H, _p(z), _p(t), B, _p(loss), _p(grad)), "loss_grad")
     return float(loss[0]), grad
+
+
+# ------------------------------------------------------------ all-at-once MLP baselines
+def mlp_param_count(widths) -> int:
+    """widths: input width first, output width (1) last.  Per layer W [out][in], b [out]."""
+    return int(sum(o * i + o for i, o in zip(widths[:-1], widths[1:])))
+
+
+def _mlp_layers(theta, widths):
+    th = np.asarray(theta, np.float64)
+    if th.size != mlp_param_count(widths):
+        raise ValueError("parameter vector has the wrong length")
+    out, at = [], 0
+    for i, o in zip(widths[:-1], widths[1:]):
+        W = th[at:at + o * i].reshape(o, i)
+        at += o * i
+        b = th[at:at + o]
+        at += o
+        out.append((W, b))
+    return out
+
+
+def mlp_forward(theta, widths, z):
+    """The comparison networks of Sec. 7 (Fig. 10): the whole descriptor enters the first
+    layer, every layer is ReLU(W h + b), the last one included (as the RPNN's).  Returns
+    (g, final pre-activation), both (P,)."""
+    h = np.asarray(z, np.float64)
+    pre = None
+    for W, b in _mlp_layers(theta, widths):
+        pre = h @ W.T + b
+        h = np.maximum(pre, 0.0)
+    return h[:, 0], pre[:, 0]
+
+
+def mlp_loss_grad(theta, widths, z, target_log1p):
+    """Loss of Sec. 5.2, mean over the batch of (log(1 + g) - t)^2, and its gradient by
+    backpropagation in FP64 (ReLU' = 1 where the pre-activation is > 0)."""
+    layers = _mlp_layers(theta, widths)
+    z = np.asarray(z, np.float64)
+    t = np.asarray(target_log1p, np.float64)
+    B = z.shape[0]
+    hs, pres = [z], []
+    for W, b in layers:
+        pres.append(hs[-1] @ W.T + b)
+        hs.append(np.maximum(pres[-1], 0.0))
+    g = hs[-1][:, 0]
+    r = np.log1p(g) - t
+    loss = float(np.mean(r * r))
+    d = (2.0 * r / (B * (1.0 + g)))[:, None]          # d loss / d g
+    grads = []
+    for l in range(len(layers) - 1, -1, -1):
+        d = d * (pres[l] > 0)                          # through the ReLU
+        grads.append((d.T @ hs[l], d.sum(0)))          # dW, db
+        d = d @ layers[l][0]                           # d loss / d input of layer l
+    out = []
+    for dW, db in reversed(grads):
+        out += [dW.reshape(-1), db]
+    return loss, np.concatenate(out)
 
 
 def adam(theta, m, v, grad, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
