@@ -135,6 +135,18 @@ ds_status ds_net_create(ds_ctx *ctx, const ds_net_desc *desc, ds_net **out);
 /* Upload / read back the FP32 master parameters (host arrays of exactly
  * ds_net_param_count() floats).  set_params also refreshes the BF16 copy and
  * invalidates the FP8 copy; both synchronise the stream. */
+/* The comparison networks of Sec. 7 (Fig. 10): a plain MLP fed the whole descriptor
+ * (225 K + 1 values) at its first layer, widths[0..n_layers-1] the output widths of its
+ * layers (the last must be 1), every layer ReLU(W h + b) including the last, as the RPNN's
+ * head.  Parameters: per layer W [out][in] row-major, then b [out].  The result is a
+ * ds_net that ds_net_set_params / get_params, ds_forward, ds_loss_grad, ds_train_step,
+ * ds_adam_*, ds_net_set_train_precision and ds_predict / ds_render_rpnn in DS_PREC_F32
+ * accept; the fused BF16 / FP8 forms, ds_net_quantize and the batch API return
+ * DS_ERR_UNSUPPORTED.  1 <= K <= 16, 1 <= n_layers <= 64, widths in 1..1024.  The count
+ * function returns -1 for an invalid shape. */
+int64_t ds_net_param_count_mlp(int32_t K, int32_t n_layers, const int32_t *widths);
+ds_status ds_net_create_mlp(ds_ctx *ctx, int32_t K, int32_t n_layers, const int32_t *widths,
+                            ds_net **out);
 ds_status ds_net_set_params(ds_net *net, const float *theta_host, int64_t n);
 ds_status ds_net_get_params(ds_net *net, float *theta_host, int64_t n);
 ds_status ds_net_destroy(ds_net *net);

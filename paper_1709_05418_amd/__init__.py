@@ -21,6 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdeepscatter.so")
 
 DS_OK = 0
+DS_ERR_INVALID_ARG, DS_ERR_OOM, DS_ERR_DEVICE, DS_ERR_UNSUPPORTED, DS_ERR_STATE = -1, -2, -3, -4, -5
 DS_F32, DS_BF16 = 0, 1
 DS_PREC_F32, DS_PREC_BF16, DS_PREC_FP8 = 0, 1, 2
 DS_FLAG_INVALID, DS_FLAG_OUTSIDE, DS_FLAG_FALLBACK = 1, 2, 4
@@ -95,6 +96,8 @@ def lib():
         "ds_trace_li_adaptive": (S, [P, P, P, P, P, P, P, I64, C.c_uint64, P, P, P]),
         "ds_make_records_adaptive": (S, [P, P, P, P, I64, C.c_uint64, I64, P, P, P, P, P, P, P,
                                          P]),
+        "ds_net_param_count_mlp": (I64, [S, S, P]),
+        "ds_net_create_mlp": (S, [P, S, S, P, P]),
         "ds_lights_create": (S, [P, S, P, P, P]),
         "ds_light_table": (S, [S, P, P, P]),
         "ds_lights_destroy": (S, [P]),
@@ -697,6 +700,25 @@ class Net:
         if self.h is not None:
             ds_net_destroy(self.h)
             self.h = None
+
+
+def ds_net_param_count_mlp(K, widths):
+    w = np.ascontiguousarray(np.asarray(widths, np.int32))
+    return int(lib().ds_net_param_count_mlp(int(K), int(w.size), w.ctypes.data))
+
+
+class NetMLP(Net):
+    """An all-at-once MLP on the K-level descriptor (Sec. 7's comparison networks);
+    widths are the layer output widths, the last 1."""
+
+    def __init__(self, ctx: Context, K: int, widths):
+        w = np.ascontiguousarray(np.asarray(widths, np.int32))
+        self.ctx, self.K, self.W, self.H = ctx, K, int(w.max()), int(w.size)
+        self.widths = [225 * K + 1] + [int(v) for v in w]
+        h = C.c_void_p()
+        _check(lib().ds_net_create_mlp(ctx.h, int(K), int(w.size), w.ctypes.data, C.byref(h)))
+        self.h = h
+        self.n_params = ds_net_param_count_mlp(K, w)
 
 
 class Lights:

@@ -193,7 +193,44 @@ ds_status gather_cells(ds_ctx *ctx, const ds_cloud *c)
     return DS_OK;
 }
 
+#define DS_TRY(expr)          \
+    do {                      \
+        ds_status s_ = (expr); \
+        if (s_)               \
+            return s_;        \
+    } while (0)
+
 constexpr int64_t kChunk = 65536;  // points per plain-form chunk
+
+// All-at-once MLP over `rows` descriptor rows in FP32: per layer one GEMM and a
+// bias + ReLU epilogue, ping-ponging between O and F (rows x W each); the scalar
+// output layer's pre-activation goes to pre (or T).
+static ds_status mlp_forward(ds_ctx *ctx, const ds_net *net, const float *z, int64_t rows,
+                             float *out, float *pre, float *O, float *F, float *T)
+{
+    hipStream_t s = ctx->stream;
+    const std::vector<int> &wd = net->mlp_widths;
+    const int L = (int)wd.size() - 1, D = wd[0];
+    for (int64_t r0 = 0; r0 < rows; r0 += kChunk) {
+        const int M = (int)((rows - r0) < kChunk ? (rows - r0) : kChunk);
+        const float *in = z + r0 * D;
+        int ld = D;
+        const float *th = net->theta;
+        for (int l = 0; l < L; ++l) {
+            const int ni = wd[l], no = wd[l + 1];
+            const float *Wl = th, *bl = th + (int64_t)no * ni;
+            th = bl + no;
+            const bool last = l == L - 1;
+            float *C = last ? (pre ? pre + r0 : T) : (l & 1 ? F : O);
+            DS_TRY(gemm_strided(s, {M, no, ni, in, ld, 1, Wl, 1, ni, C, no, 0}));
+            DS_TRY(layer_epilogue(s, M, no, C, no, nullptr, 0, nullptr, 0, bl, nullptr, 0,
+                                  last ? out + r0 : C, no));
+            in = C;
+            ld = no;
+        }
+    }
+    return DS_OK;
+}
 
 // Plain FP32 network over `rows` descriptor rows (ldz = 225K + 1).
 // amax (may be NULL): running maxima of |activation| per layer, as float bits: the first
@@ -202,6 +239,8 @@ constexpr int64_t kChunk = 65536;  // points per plain-form chunk
 ds_status forward_plain(ds_ctx *ctx, const ds_net *net, const float *z, int64_t rows, float *out,
                         float *pre, float *O, float *F, float *T, unsigned *amax = nullptr)
 {
+    if (net->kind == 1)
+        return mlp_forward(ctx, net, z, rows, out, pre, O, F, T);
     const int K = net->K, W = net->W, H = net->H;
     const int D = kStencil * K + 1;
     const float *th = net->theta;
@@ -343,12 +382,92 @@ ds_status train_ws(ds_net *net, int B, TrainWs &w)
     return DS_OK;
 }
 
-#define DS_TRY(expr)          \
-    do {                      \
-        ds_status s_ = (expr); \
-        if (s_)               \
-            return s_;        \
-    } while (0)
+// Loss and gradient of the all-at-once MLP: per layer its pre-activations and outputs
+// are kept, then backpropagation last layer first (FP32, or BF16 GEMM operands with FP32
+// accumulation as for the RPNN).
+static ds_status mlp_loss_grad(ds_net *net, const float *z, const float *target, int B,
+                               float *loss, float *grad)
+{
+    hipStream_t s = net->ctx->stream;
+    const bool bf = net->train_prec == DS_PREC_BF16;
+    const std::vector<int> &wd = net->mlp_widths;
+    const int L = (int)wd.size() - 1, D = wd[0], Wm = net->W;
+    size_t act = 0;
+    for (int l = 1; l <= L; ++l)
+        act += (size_t)B * wd[l];
+    size_t split = (size_t)16 * Wm * 226;
+    const size_t csum = (size_t)colsum_scratch(Wm);
+    split = split > csum ? split : csum;
+    const size_t need = 2 * act + 2 * (size_t)B * Wm + 2 * (size_t)B + split;
+    if (net->tws_floats < need) {
+        if (net->tws) {
+            DS_HIP(hipStreamSynchronize(s));
+            (void)hipFree(net->tws);
+            net->tws = nullptr;
+            net->tws_floats = 0;
+        }
+        DS_HIP(hipMalloc(&net->tws, need * sizeof(float)));
+        net->tws_floats = need;
+    }
+    std::vector<float *> A(L), Y(L);
+    std::vector<int64_t> ow(L), ob(L);
+    float *p = net->tws;
+    int64_t at = 0;
+    for (int l = 0; l < L; ++l) {
+        A[l] = p;
+        p += (size_t)B * wd[l + 1];
+        Y[l] = p;
+        p += (size_t)B * wd[l + 1];
+        ow[l] = at;
+        at += (int64_t)wd[l + 1] * wd[l];
+        ob[l] = at;
+        at += wd[l + 1];
+    }
+    const size_t wide = (size_t)B * Wm;  // d loss / d (hidden layer), at most W wide
+    float *dcur = p, *dnext = p + wide;
+    p += 2 * wide;
+    float *dpre = p, *sq = p + B;
+    p += 2 * (size_t)B;
+    float *sp = p;
+    auto mm = [&](const StridedGemm &g) {
+        return bf ? gemm_bf16(s, g, sp, split) : gemm_strided(s, g);
+    };
+    const float *th = net->theta;
+    // forward
+    const float *in = z;
+    int ld = D;
+    for (int l = 0; l < L; ++l) {
+        const int ni = wd[l], no = wd[l + 1];
+        DS_TRY(mm({B, no, ni, in, ld, 1, th + ow[l], 1, ni, A[l], no, 0}));
+        DS_TRY(layer_epilogue(s, B, no, A[l], no, nullptr, 0, nullptr, 0, th + ob[l], nullptr, 0,
+                              Y[l], no));
+        in = Y[l];
+        ld = no;
+    }
+    DS_TRY(loss_head(s, A[L - 1], target, B, dpre, sq, loss));
+    if (!grad)
+        return DS_OK;
+    // backward; dY = d loss / d (pre-activation of layer l)
+    const float *dY = dpre;
+    int ldy = 1;
+    for (int l = L - 1; l >= 0; --l) {
+        const int ni = wd[l], no = wd[l + 1];
+        if (l < L - 1) {
+            DS_TRY(relu_mask(s, dcur, no, A[l], no, B, no));
+            dY = dcur;
+            ldy = no;
+        }
+        const float *x = l == 0 ? z : Y[l - 1];
+        const int ldx = l == 0 ? D : ni;
+        DS_TRY(mm({no, ni, B, dY, 1, ldy, x, ldx, 1, grad + ow[l], ni, 0}));
+        DS_TRY(colsum(s, dY, ldy, B, no, grad + ob[l], sp));
+        if (l > 0) {
+            DS_TRY(mm({B, ni, no, dY, ldy, 1, th + ow[l], ni, 1, dnext, ni, 0}));
+            std::swap(dcur, dnext);
+        }
+    }
+    return DS_OK;
+}
 
 // Loss and gradient of a minibatch: forward keeping pre-activations, then
 // backpropagation layer by layer; every parameter gradient is written exactly once.
@@ -357,6 +476,8 @@ ds_status train_ws(ds_net *net, int B, TrainWs &w)
 ds_status loss_grad(ds_net *net, const float *z, const float *target, int B, float *loss,
                     float *grad)
 {
+    if (net->kind == 1)
+        return mlp_loss_grad(net, z, target, B, loss, grad);
     hipStream_t s = net->ctx->stream;
     const bool bf = net->train_prec == DS_PREC_BF16;
     const int K = net->K, W = net->W, Hn = net->H, D = kStencil * K + 1;
@@ -869,6 +990,55 @@ ds_status ds_net_create(ds_ctx *ctx, const ds_net_desc *desc, ds_net **out)
     return DS_OK;
 }
 
+int64_t ds_net_param_count_mlp(int32_t K, int32_t n_layers, const int32_t *widths)
+{
+    if (!widths || K < 1 || K > kMaxK || n_layers < 1 || n_layers > 64 || widths[n_layers - 1] != 1)
+        return -1;
+    int64_t n = 0, in = (int64_t)kStencil * K + 1;
+    for (int l = 0; l < n_layers; ++l) {
+        if (widths[l] < 1 || widths[l] > 1024)
+            return -1;
+        n += (int64_t)widths[l] * in + widths[l];
+        in = widths[l];
+    }
+    return n;
+}
+
+ds_status ds_net_create_mlp(ds_ctx *ctx, int32_t K, int32_t n_layers, const int32_t *widths,
+                            ds_net **out)
+{
+    DS_CHECK(ctx && widths && out, DS_ERR_INVALID_ARG, "ds_net_create_mlp: NULL argument");
+    const int64_t np = ds_net_param_count_mlp(K, n_layers, widths);
+    DS_CHECK(np > 0, DS_ERR_INVALID_ARG,
+             "ds_net_create_mlp: need 1 <= K <= %d, 1 <= n_layers <= 64, widths in 1..1024 and "
+             "a last width of 1", kMaxK);
+    ds_net *n = new (std::nothrow) ds_net();
+    DS_CHECK(n, DS_ERR_OOM, "ds_net_create_mlp: out of host memory");
+    n->ctx = ctx;
+    n->kind = 1;
+    n->K = K;
+    n->H = n_layers;
+    n->mlp_widths.push_back(kStencil * K + 1);
+    for (int l = 0; l < n_layers; ++l) {
+        n->mlp_widths.push_back(widths[l]);
+        n->W = widths[l] > n->W ? widths[l] : n->W;
+    }
+    n->n_params = np;
+    if (hipMalloc(&n->theta, sizeof(float) * np) != hipSuccess) {
+        delete n;
+        set_error("ds_net_create_mlp: out of device memory");
+        return DS_ERR_OOM;
+    }
+    hipError_t e = hipMemsetAsync(n->theta, 0, sizeof(float) * np, ctx->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(n->theta);
+        delete n;
+        return hip_fail(e, "ds_net_create_mlp");
+    }
+    *out = n;
+    return DS_OK;
+}
+
 ds_status ds_net_set_params(ds_net *net, const float *theta_host, int64_t n)
 {
     DS_CHECK(net && theta_host, DS_ERR_INVALID_ARG, "ds_net_set_params: NULL argument");
@@ -881,7 +1051,7 @@ ds_status ds_net_set_params(ds_net *net, const float *theta_host, int64_t n)
     DS_HIP(hipStreamSynchronize(net->ctx->stream));
     DS_HIP(hipMemcpy(net->theta, theta_host, sizeof(float) * n, hipMemcpyHostToDevice));
     net->fp8_ready = false;
-    if (fused_tiles(net->W) > 0) {
+    if (net->kind == 0 && fused_tiles(net->W) > 0) {
         ds_status st = fused_pack_bf16(net->ctx->stream, net);
         if (st)
             return st;
@@ -1028,6 +1198,8 @@ ds_status ds_predict(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
         return predict_plain(ctx, cloud, net, pos, view_dir, light_dir, P, out, pre_out, flags,
                              nullptr);
     if (precision == DS_PREC_BF16 || precision == DS_PREC_FP8) {
+        DS_CHECK(net->kind == 0, DS_ERR_UNSUPPORTED,
+                 "ds_predict: the all-at-once MLP runs in DS_PREC_F32 only");
         FusedArgs a = {};
         fused_args(pos, view_dir, light_dir, out, pre_out, flags, net->K, net->W, net->H, a);
         add_cloud(a, cloud, 0, P);
@@ -1072,6 +1244,8 @@ ds_status ds_batch_create(ds_ctx *ctx, const ds_net *net, int n_clouds,
              "ds_batch_create: NULL argument");
     DS_CHECK(n_clouds >= 1 && n_clouds <= kMaxBatch, DS_ERR_INVALID_ARG,
              "ds_batch_create: n_clouds %d outside 1..%d", n_clouds, kMaxBatch);
+    DS_CHECK(net->kind == 0, DS_ERR_UNSUPPORTED,
+             "ds_batch_create: batched prediction runs the RPNN's fused kernel");
     DS_CHECK(offsets[0] == 0, DS_ERR_INVALID_ARG, "ds_batch_create: offsets[0] must be 0");
     for (int c = 0; c < n_clouds; ++c) {
         DS_CHECK(clouds[c], DS_ERR_INVALID_ARG, "ds_batch_create: cloud %d is NULL", c);
@@ -1303,6 +1477,8 @@ ds_status ds_net_quantize(ds_ctx *ctx, ds_net *net, const ds_cloud *cloud, ds_pr
     DS_CHECK(precision == DS_PREC_FP8, DS_ERR_INVALID_ARG,
              "ds_net_quantize: only DS_PREC_FP8 is built by this call (the BF16 form follows "
              "every parameter change)");
+    DS_CHECK(net->kind == 0, DS_ERR_UNSUPPORTED,
+             "ds_net_quantize: the FP8 form exists for the RPNN only");
     DS_CHECK(fused_tiles(net->W) > 0, DS_ERR_UNSUPPORTED,
              "ds_net_quantize: width %d is not supported by the fused kernel", net->W);
     DS_CHECK(net->frag_bf16, DS_ERR_STATE, "ds_net_quantize: network parameters were never set");
@@ -1467,7 +1643,7 @@ ds_status ds_train_step(ds_net *net, ds_adam *opt, const float *z, const float *
     if (st)
         return st;
     net->fp8_ready = false;
-    if (fused_tiles(net->W) > 0)
+    if (net->kind == 0 && fused_tiles(net->W) > 0)
         return fused_pack_bf16(net->ctx->stream, net);
     return DS_OK;
 }

@@ -85,6 +85,11 @@ struct ds_cloud {
 struct ds_net {
     ds_ctx *ctx = nullptr;
     int K = 0, W = 0, H = 0;
+    // 0: the progressive RPNN; 1: an all-at-once MLP on the whole descriptor (the
+    // comparison networks of Sec. 7), layer widths in mlp_widths (input 225 K + 1 first,
+    // output 1 last), W = the widest layer, H = the number of layers
+    int kind = 0;
+    std::vector<int> mlp_widths;
     int64_t n_params = 0;
     float *theta = nullptr;       // FP32 master parameters (canonical order), device
     // fused-kernel operands, see fused.hip for the layout

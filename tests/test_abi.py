@@ -58,6 +58,11 @@ def test_null_and_bad_arguments_are_rejected_before_any_launch():
     assert L.ds_render_rpnn_lights(None, None, None, 1, None, None, 1, None, None, 4, 1, 0, 0,
                                    None, None, None, None) == -1
     assert L.ds_light_table(0, None, None, None) == -1
+    assert L.ds_net_create_mlp(None, 1, 1, None, C.byref(out)) == -1
+    assert ds.ds_net_param_count_mlp(10, [200] * 22 + [1]) == 1_294_801
+    assert ds.ds_net_param_count_mlp(10, [400, 400, 200, 200, 200, 1]) == 1_222_001
+    assert ds.ds_net_param_count_mlp(10, [200, 2]) == -1    # the output must be scalar
+    assert ds.ds_net_param_count_mlp(0, [1]) == -1
     assert L.ds_lights_destroy(None) == 0
     # destroying NULL handles is a no-op
     assert L.ds_destroy(None) == 0 and L.ds_cloud_destroy(None) == 0 and L.ds_net_destroy(None) == 0
