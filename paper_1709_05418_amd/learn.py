@@ -308,6 +308,9 @@ def main(argv=None):
     ap.add_argument("--adaptive-batch", type=int, default=256)
     ap.add_argument("--adaptive-max", type=int, default=65536)
     ap.add_argument("--no-judge", action="store_true", help="stop after training")
+    ap.add_argument("--compare", action="store_true",
+                    help="train the RPNN and the two all-at-once MLPs of Sec. 7 (23 x 200 and "
+                         "[400, 400, 200, 200, 200]) on the same pairs and judge each in FP32")
     ap.add_argument("--save-theta", default=None)
     ap.add_argument("--load-theta", default=None,
                     help="judge a network saved by --save-theta instead of training one")
@@ -371,6 +374,10 @@ def main(argv=None):
                           "paths_per_second": paths / t_data, **stats}), flush=True)
         ctx.close()
         return
+    if args.compare:
+        return compare_architectures(args, ctx, prm, z, t, float(li.mean()), log,
+                                     {"data_seconds": t_data, "paths_per_second": paths / t_data,
+                                      "pairs": per * args.clouds, "spp": args.spp, **stats})
     net = ds.Net(ctx, K, W, 3)
     net.set_params(synth.init_params(K, W, 3, args.seed + 1, branch_scale=1 / math.sqrt(K),
                                      out_scale=0.01, out_bias=float(li.mean())))
@@ -441,6 +448,75 @@ def main(argv=None):
     ds.ds_adam_destroy(opt)
     net.close()
     jc.close()
+    ctx.close()
+
+
+ARCHS = {"rpnn": None, "mlp_deep_23x200": [200] * 22 + [1],
+         "mlp_wide_400_400_200_200_200": [400, 400, 200, 200, 200, 1]}
+
+
+def compare_architectures(args, ctx, prm, z, t, mean_li, log, data):
+    """Sec. 7, Fig. 10: the progressive RPNN against two MLPs fed the whole descriptor at
+    once, trained on the same pairs with the same minibatches, learning-rate schedule and
+    step count, then judged on the same crop (all in FP32 for the judge, the plain form)."""
+    import json
+    import torch
+    K, W = args.K, args.W
+    out = dict(data)
+    held = {}
+    nets = {}
+    for name, widths in ARCHS.items():
+        if widths is None:
+            net = ds.Net(ctx, K, W, 3)
+            net.set_params(synth.init_params(K, W, 3, args.seed + 1, branch_scale=1 / math.sqrt(K),
+                                             out_scale=0.01, out_bias=mean_li))
+        else:
+            net = ds.NetMLP(ctx, K, widths)
+            net.set_params(synth.init_mlp([ds.STENCIL_N * K + 1] + widths, args.seed + 1,
+                                          out_scale=0.01, out_bias=mean_li))
+        ds.ds_net_set_train_precision(net.h, ds.DS_PREC_BF16 if args.train_precision == "bf16"
+                                      else ds.DS_PREC_F32)
+        opt = ds.ds_adam_create(net.h, args.lr)
+        log(f"{name}: {net.n_params} parameters")
+        res = train(net, opt, z, t, args.steps, args.batch, 0.25,
+                    eval_every=max(1, args.steps // 20), log=log, lr=args.lr,
+                    decay_at=tuple(args.decay_at))
+        ds.ds_adam_destroy(opt)
+        held[name] = res["held_out"]
+        out[f"{name}_params"] = net.n_params
+        out[f"{name}_train_seconds"] = res["seconds"]
+        out[f"{name}_held_out_final"] = res["held_out"][-1][1]
+        log(f"{name}: training {res['seconds']:.1f}s, final held-out {res['held_out'][-1][1]:.6f}")
+        nets[name] = net
+    del z, t
+    torch.cuda.empty_cache()
+    if not args.no_judge:
+        d = synth.cloud_density(args.judge_n, args.seed + 5000, worley=0.3, device="cuda",
+                                dtype=torch.bfloat16)
+        amin, h0 = synth.unit_box(args.judge_n)
+        Lj = min(16, int(math.ceil(math.log2(args.judge_n))) + 1)
+        jc = ds.Cloud(ctx, d, float(args.n), amin, h0, Lj, K)
+        del d
+        light = synth.table1_lights()[args.light]
+        c = args.crop
+        co, cd = camera(args.width, args.height,
+                        crop=((args.width - c) // 2, (args.height - c) // 2, c, c), seed=2)
+        ref, _ = reference(ctx, jc, prm, light, co, cd, args.ref_spp, 11)
+        for name, net in nets.items():
+            img, _, direct, _ = ds.ds_render_rpnn(ctx.h, jc.h, net.h, ds.DS_PREC_F32, prm, light,
+                                                  co, cd, args.crop_spp, 11, args.fallback_spp)
+            l1, rmse = image_errors(img, ref)
+            out[f"{name}_crop_rel_l1"] = l1
+            out[f"{name}_crop_rmse"] = rmse
+            log(f"{name}: crop {c}^2 rel L1 {l1:.4f}, RMSE {rmse:.5f}")
+        jc.close()
+    for name, net in nets.items():
+        log(f"{name} held-out curve: " + ", ".join(f"({a}, {b:.3g})" for a, b in held[name]))
+        net.close()
+    out.update({"steps": args.steps, "batch": args.batch, "K": K, "W": W,
+                "light": args.light, "crop": args.crop, "ref_spp": args.ref_spp,
+                "judge_n": args.judge_n, "held_out": held})
+    print(json.dumps(out), flush=True)
     ctx.close()
 
 

@@ -424,3 +424,21 @@ def sun_sky_lights(sun_dir, sun_irradiance: float = 1.0, sky_radiance: float = 0
             dirs.append(v)
             E.append(L * dw)
     return np.asarray(dirs, np.float32), np.asarray(E, np.float64)
+
+
+def init_mlp(widths, seed: int, out_scale: float = 1.0, out_bias: float = 0.0) -> np.ndarray:
+    """He-uniform weights and zero biases for an all-at-once MLP (widths: input first,
+    output last; per layer W [out][in] then b [out]); out_scale multiplies the last
+    layer's weights and out_bias sets its bias.  float32 vector."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    L = len(widths) - 1
+    for l, (i, o) in enumerate(zip(widths[:-1], widths[1:])):
+        b = math.sqrt(6.0 / i)
+        w = rng.uniform(-b, b, size=o * i)
+        bias = np.zeros(o)
+        if l == L - 1:
+            w = w * out_scale
+            bias[:] = out_bias
+        parts += [w, bias]
+    return np.concatenate(parts).astype(np.float32)
