@@ -442,3 +442,73 @@ def init_mlp(widths, seed: int, out_scale: float = 1.0, out_bias: float = 0.0) -
             bias[:] = out_bias
         parts += [w, bias]
     return np.concatenate(parts).astype(np.float32)
+
+
+# --------------------------------------------------------------------------------------
+# Lorenz-Mie phase function of a cloud droplet population (input data for the tracer)
+# --------------------------------------------------------------------------------------
+def mie_amplitudes(x: float, m: complex, mu: np.ndarray):
+    """Lorenz-Mie scattering of a homogeneous sphere of size parameter x = 2 pi r / lambda
+    and relative refractive index m, by the series of Bohren and Huffman (1983, Ch. 4 and
+    App. A): a_n, b_n from the logarithmic derivative D_n(m x) (downward recurrence) and
+    the Riccati-Bessel functions (upward recurrence), the angle functions pi_n, tau_n by
+    their recurrences in mu = cos(theta).  Returns (S1(mu), S2(mu), Q_ext, Q_sca)."""
+    mu = np.asarray(mu, np.float64)
+    y = m * x
+    nstop = int(x + 4.0 * x ** (1.0 / 3.0) + 2.0)
+    nmx = int(max(nstop, abs(y))) + 16
+    D = np.zeros(nmx + 1, complex)
+    for n in range(nmx, 0, -1):
+        D[n - 1] = n / y - 1.0 / (D[n] + n / y)
+    psi0, psi1 = np.cos(x), np.sin(x)          # psi_{-1}, psi_0
+    chi0, chi1 = -np.sin(x), np.cos(x)         # chi_{-1}, chi_0
+    xi1 = complex(psi1, -chi1)
+    pi0, pi1 = np.zeros_like(mu), np.ones_like(mu)
+    S1 = np.zeros(mu.shape, complex)
+    S2 = np.zeros(mu.shape, complex)
+    qext = qsca = 0.0
+    for n in range(1, nstop + 1):
+        psi = (2 * n - 1) / x * psi1 - psi0
+        chi = (2 * n - 1) / x * chi1 - chi0
+        xi = complex(psi, -chi)
+        da = D[n] / m + n / x
+        db = D[n] * m + n / x
+        an = (da * psi - psi1) / (da * xi - xi1)
+        bn = (db * psi - psi1) / (db * xi - xi1)
+        tau = n * mu * pi1 - (n + 1) * pi0
+        f = (2 * n + 1) / (n * (n + 1))
+        S1 += f * (an * pi1 + bn * tau)
+        S2 += f * (an * tau + bn * pi1)
+        qext += (2 * n + 1) * (an + bn).real
+        qsca += (2 * n + 1) * (abs(an) ** 2 + abs(bn) ** 2)
+        pi0, pi1 = pi1, ((2 * n + 1) * mu * pi1 - (n + 1) * pi0) / n
+        psi0, psi1, chi0, chi1, xi1 = psi1, psi, chi1, chi, xi
+    return S1, S2, 2.0 * qext / x ** 2, 2.0 * qsca / x ** 2
+
+
+def cloud_droplet_phase(n_theta: int = 3601, wavelength_um: float = 0.55,
+                        r_eff_um: float = 8.0, v_eff: float = 0.1, m: complex = 1.333 + 0j,
+                        n_r: int = 160):
+    """Phase function (per steradian, unpolarised light) of water droplets following the
+    gamma size distribution of Hansen and Travis (1974), n(r) ~ r^((1 - 3 v) / v)
+    exp(-r / (r_eff v)), on n_theta angles theta_i = i pi / (n_theta - 1).  The paper's
+    own droplet parameters are not given; these are typical of cumulus.  Radii: n_r
+    Gauss-Legendre nodes over [r_eff / 20, r_eff (1 + 12 sqrt(v))].  Returns (theta,
+    p(theta), mean cosine)."""
+    theta = np.linspace(0.0, np.pi, n_theta)
+    mu = np.cos(theta)
+    lo, hi = r_eff_um / 20.0, r_eff_um * (1.0 + 12.0 * math.sqrt(v_eff))
+    t, w = np.polynomial.legendre.leggauss(n_r)
+    r = 0.5 * (hi - lo) * t + 0.5 * (hi + lo)
+    w = 0.5 * (hi - lo) * w
+    nr = r ** ((1.0 - 3.0 * v_eff) / v_eff) * np.exp(-r / (r_eff_um * v_eff))
+    num = np.zeros(n_theta)
+    den = 0.0
+    for ri, wi, ni in zip(r, w, nr):
+        x = 2.0 * math.pi * ri / wavelength_um
+        S1, S2, _, qs = mie_amplitudes(x, m, mu)
+        num += wi * ni * (np.abs(S1) ** 2 + np.abs(S2) ** 2)
+        den += wi * ni * 2.0 * math.pi * x * x * qs
+    p = num / den
+    g = float(np.trapezoid(2.0 * math.pi * p * mu * np.sin(theta), theta))
+    return theta, p, g
