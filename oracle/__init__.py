@@ -34,6 +34,9 @@ What each part follows in the paper and what pins it (tests/test_oracle_*.py):
   mlp_forward,    Sec. 7 / Fig. 10 all-at-once MLPs         equal to forward / loss_grad of a K = 1
   mlp_loss_grad   (numpy, FP64)                             RPNN (same parameter vector), central
                                                             finite differences
+  phase_table,    Sec. 5.1 tabulated (chopped) Lorenz-Mie   normalisation, chopped mass, HG table
+  set_phase       phase function, unchopped at the first    against analytic HG (moments, CDF and
+                  collision when rendering                  the tracer's estimates)
   e4m3_encode     OCP 8-bit floating point, E4M3 format     torch.float8_e4m3fn cast, hand values,
                   (round to nearest even, saturating)       decode/encode round trip of every code
 """
@@ -100,6 +103,8 @@ def lib():
                                       P, P]),
             "dso_first_hits": (I, [P, I, I, I, I, D, P, D, D, D, D, P, P, P, I64, U64, U64, P, P,
                                    P, P]),
+            "dso_set_phase": (None, [I, P, P, I, P, P]),
+            "dso_tab_sample": (D, [I, P, P, D]),
             "dso_render_pixels_lights": (I, [P, I, I, I, I, D, P, D, D, D, D, I, I, P, P, P, P, P,
                                              I64, I, U64, P, P]),
             "dso_first_hits_lights": (I, [P, I, I, I, I, D, P, D, D, D, D, I, P, P, P, I, P, P,
@@ -420,6 +425,63 @@ def render_pixels(grid: Grid, ray_o, ray_d, light_dir, albedo=0.999, g=0.85, irr
                                    light_mode, max_interactions, _p(ld), _p(o), _p(d), N, spp,
                                    seed, _p(mean), _p(var)), "render_pixels")
     return mean, var
+
+
+# ------------------------------------------------------------------- tabulated phases
+def phase_table(p, chop_deg=0.0):
+    """Tracer table of a phase function given at theta_i = i pi / (n - 1) (per steradian):
+    normalised so that the trapezoid rule on 2 pi p sin(theta) gives 1; with chop_deg > 0
+    the forward peak is chopped (Sec. 5.1's chopped Lorenz-Mie function): below the node
+    nearest chop_deg the value is held at that node's, the lost fraction f of the
+    scattering is reported and the rest renormalised (the medium then scatters (1 - f) of
+    its original scattering, the chopped part travelling on as if unscattered).  Returns a
+    dict: p, cdf (normalised running trapezoid sums), removed (f), g (mean cosine)."""
+    p = np.asarray(p, np.float64)
+    n = p.size
+    if n < 2 or not np.all(np.isfinite(p)) or np.any(p < 0):
+        raise ValueError("a phase table needs at least two finite non-negative values")
+    theta = np.arange(n) * (np.pi / (n - 1))
+
+    def integral(q):
+        f = 2 * np.pi * q * np.sin(theta)
+        return float(np.sum(0.5 * (f[1:] + f[:-1])) * (np.pi / (n - 1)))
+
+    q = p / integral(p)
+    removed = 0.0
+    if chop_deg > 0:
+        ic = int(round(np.radians(chop_deg) / (np.pi / (n - 1))))
+        q = q.copy()
+        q[:ic] = q[ic]
+        removed = 1.0 - integral(q)
+        q = q / (1.0 - removed)
+    f = 2 * np.pi * q * np.sin(theta)
+    c = np.concatenate([[0.0], np.cumsum(0.5 * (f[1:] + f[:-1]) * (np.pi / (n - 1)))])
+    cdf = c / c[-1]
+    g = float(np.sum(0.5 * ((f * np.cos(theta))[1:] + (f * np.cos(theta))[:-1])) * (np.pi / (n - 1)))
+    return {"p": q, "cdf": cdf, "removed": removed, "g": g}
+
+
+def set_phase(table=None, first=None):
+    """Use `table` (from phase_table) for every scattering and `first` for the direct
+    term at the first collision of camera rays in all later tracer calls; None restores
+    Henyey-Greenstein (first falls back to table)."""
+    L = lib()
+    keep = []
+
+    def args(t):
+        if t is None:
+            return [0, None, None]
+        a, b = np.ascontiguousarray(t["p"]), np.ascontiguousarray(t["cdf"])
+        keep.extend([a, b])
+        return [a.size, _p(a), _p(b)]
+
+    L.dso_set_phase(*args(table), *args(first))
+
+
+def tab_sample(table, u):
+    """cos(theta) the tracer draws from `table` for the uniform u."""
+    a, b = np.ascontiguousarray(table["p"]), np.ascontiguousarray(table["cdf"])
+    return lib().dso_tab_sample(a.size, _p(a), _p(b), float(u))
 
 
 # ---------------------------------------------------------------------------- light sets

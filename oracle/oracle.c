@@ -904,6 +904,93 @@ double dso_hg_sample_cos(double g, double u)
     return c > 1.0 ? 1.0 : (c < -1.0 ? -1.0 : c);
 }
 
+/* Tabulated phase functions (a chopped Lorenz-Mie table for every scattering, and an
+ * optional unchopped one for the direct term at the first collision of a camera ray):
+ * p at theta_i = i pi / (n - 1), per steradian, and the normalised cumulative
+ * distribution of theta at the same nodes (the trapezoid rule on 2 pi p sin theta).
+ * Set for all later tracer calls by dso_set_phase; n = 0 clears (Henyey-Greenstein). */
+typedef struct {
+    int n;
+    double dth;
+    double *p, *cdf;
+} phase_tab;
+
+static phase_tab g_phase, g_first;
+
+static void tab_set(phase_tab *t, int n, const double *p, const double *cdf)
+{
+    free(t->p);
+    free(t->cdf);
+    t->p = t->cdf = NULL;
+    t->n = 0;
+    if (n < 2 || !p || !cdf)
+        return;
+    t->p = malloc(sizeof(double) * n);
+    t->cdf = malloc(sizeof(double) * n);
+    memcpy(t->p, p, sizeof(double) * n);
+    memcpy(t->cdf, cdf, sizeof(double) * n);
+    t->n = n;
+    t->dth = M_PI / (n - 1);
+}
+
+void dso_set_phase(int n, const double *p, const double *cdf, int n_first, const double *p_first,
+                   const double *cdf_first)
+{
+    tab_set(&g_phase, n, p, cdf);
+    tab_set(&g_first, n_first, p_first, cdf_first);
+}
+
+/* p(mu): linear in theta between nodes */
+static double tab_eval(const phase_tab *t, double mu)
+{
+    double th = acos(fmax(-1.0, fmin(1.0, mu))) / t->dth;
+    int i = (int)th;
+    if (i > t->n - 2)
+        i = t->n - 2;
+    double f = th - i;
+    return t->p[i] + f * (t->p[i + 1] - t->p[i]);
+}
+
+/* cos(theta) drawn from the table: the node interval by the cumulative distribution,
+ * then theta inside it from the density linear between the nodes' p sin(theta). */
+double dso_tab_sample(int n, const double *p, const double *cdf, double u)
+{
+    int lo = 0, hi = n - 1; /* cdf[lo] <= u < cdf[hi] */
+    while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (cdf[mid] <= u)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    double dth = M_PI / (n - 1);
+    double fa = p[lo] * sin(lo * dth), fb = p[lo + 1] * sin((lo + 1) * dth);
+    double q = (u - cdf[lo]) / (cdf[lo + 1] - cdf[lo]);
+    double t;
+    if (fabs(fb - fa) <= 1e-12 * (fa + fb))
+        t = q;
+    else
+        t = (-fa + sqrt(fa * fa + (fb - fa) * q * (fa + fb))) / (fb - fa);
+    t = fmin(1.0, fmax(0.0, t));
+    return cos((lo + t) * dth);
+}
+
+static double ph_eval(double g, int first, double mu)
+{
+    if (first && g_first.n)
+        return tab_eval(&g_first, mu);
+    if (g_phase.n)
+        return tab_eval(&g_phase, mu);
+    return dso_hg(g, mu);
+}
+
+static double ph_sample(double g, double u)
+{
+    if (g_phase.n)
+        return dso_tab_sample(g_phase.n, g_phase.p, g_phase.cdf, u);
+    return dso_hg_sample_cos(g, u);
+}
+
 static void sample_dir_around(const double w[3], double cos_t, double u, double out[3])
 {
     double t1[3], t2[3];
@@ -970,7 +1057,7 @@ static double li_path(const medium_t *M, const tracer_params *tp, const double x
     for (int j = 1;; ++j) {
         if (tp->max_interactions > 0 && j > tp->max_interactions)
             break;
-        double c = dso_hg_sample_cos(tp->g, rng_u(r));
+        double c = ph_sample(tp->g, rng_u(r));
         double wh[3];
         sample_dir_around(wprev, c, rng_u(r), wh);
         double back[3] = {-wh[0], -wh[1], -wh[2]}, xn[3];
@@ -987,13 +1074,13 @@ static double li_path(const medium_t *M, const tracer_params *tp, const double x
         if (tp->light_mode == 0) {
             double mu = -dot3(wh, wl);
             double T = ratio_track(M, p, wl, r);
-            sum += dso_hg(tp->g, mu) * T * tp->irradiance;
+            sum += ph_eval(tp->g, 0, mu) * T * tp->irradiance;
         } else if (tp->light_mode == 2) {
             int j = set_pick(tp->set, r);
             const double *lj = tp->set->dir + 3 * j;
             double mu = -dot3(wh, lj);
             double T = ratio_track(M, p, lj, r);
-            sum += tp->set->w[j] * dso_hg(tp->g, mu) * T * tp->irradiance;
+            sum += tp->set->w[j] * ph_eval(tp->g, 0, mu) * T * tp->irradiance;
         }
         wprev[0] = wh[0];
         wprev[1] = wh[1];
@@ -1045,7 +1132,7 @@ static double record_path(const medium_t *M, const tracer_params *tp, const doub
         return li_path(M, tp, x, w, wl, 0, r);
     if (tp->light_mode == 1)
         return li_path(M, tp, x, w, wl, 1, r);
-    double d = dso_hg(tp->g, -dot3(w, wl)) * ratio_track(M, x, wl, r) * tp->irradiance;
+    double d = ph_eval(tp->g, 0, -dot3(w, wl)) * ratio_track(M, x, wl, r) * tp->irradiance;
     return d + li_path(M, tp, x, w, wl, 0, r);
 }
 
@@ -1259,7 +1346,7 @@ int dso_first_hits(const void *dens, int dtype, int nx, int ny, int nz, double s
             rng_init(&r, seed, ((uint64_t)i << 20) + sample);
             h = delta_track(&M, o, d, &r, x);
             if (h)
-                e = albedo * dso_hg(g, dot3(d, wl)) * ratio_track(&M, x, wl, &r) * irradiance;
+                e = albedo * ph_eval(g, 1, dot3(d, wl)) * ratio_track(&M, x, wl, &r) * irradiance;
         }
         for (int a = 0; a < 3; ++a) {
             pos[3 * i + a] = h ? x[a] : 0.0;
@@ -1287,11 +1374,11 @@ static double pixel_sample(const medium_t *M, const tracer_params *tp, const dou
         return tp->albedo * li_path(M, tp, x, w, wl, 1, r);
     double direct;
     if (tp->light_mode == 0) {
-        direct = dso_hg(tp->g, -dot3(w, wl)) * ratio_track(M, x, wl, r) * tp->irradiance;
+        direct = ph_eval(tp->g, 1, -dot3(w, wl)) * ratio_track(M, x, wl, r) * tp->irradiance;
     } else {
         int j = set_pick(tp->set, r);
         const double *lj = tp->set->dir + 3 * j;
-        direct = tp->set->w[j] * dso_hg(tp->g, -dot3(w, lj)) * ratio_track(M, x, lj, r) *
+        direct = tp->set->w[j] * ph_eval(tp->g, 1, -dot3(w, lj)) * ratio_track(M, x, lj, r) *
                  tp->irradiance;
     }
     return tp->albedo * (direct + li_path(M, tp, x, w, wl, 0, r));
@@ -1436,7 +1523,7 @@ int dso_first_hits_lights(const void *dens, int dtype, int nx, int ny, int nz, d
             int j = set_pick(&ls, &r);
             const double *lj = dir + 3 * j;
             double T = ratio_track(&M, x, lj, &r);
-            e += w[j] * dso_hg(g, dot3(d, lj)) * T;
+            e += w[j] * ph_eval(g, 1, dot3(d, lj)) * T;
             lo[0] = lj[0];
             lo[1] = lj[1];
             lo[2] = lj[2];

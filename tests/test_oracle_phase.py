@@ -1,0 +1,95 @@
+"""Pins of the oracle's tabulated phase functions (Sec. 5.1: a chopped Lorenz-Mie
+table for data generation and rendering, the unchopped one for the direct term at the
+first collision): the table's normalisation and chopped mass, its sampling against the
+table's own moments, a Henyey-Greenstein table against the analytic function inside the
+tracer, and the first-collision direct term against the homogeneous-box closed form.
+CPU only."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1709_05418_amd import synth
+
+from test_oracle_tracer import ramp_int
+
+
+def hg_table(g, n=3601):
+    theta = np.linspace(0, math.pi, n)
+    return np.array([O.hg(g, c) for c in np.cos(theta)])
+
+
+@pytest.fixture
+def clean_phase():
+    yield
+    O.set_phase(None)
+
+
+def test_table_normalisation_and_chop():
+    theta, p, _ = synth.cloud_droplet_phase(n_theta=1801, n_r=60)
+    t = O.phase_table(p)
+    assert t["removed"] == 0.0 and t["cdf"][0] == 0.0 and t["cdf"][-1] == 1.0
+    assert np.all(np.diff(t["cdf"]) >= 0)
+    t0 = O.phase_table(p, chop_deg=0.0)
+    np.testing.assert_array_equal(t0["p"], t["p"])
+    c = O.phase_table(p, chop_deg=5.0)
+    ic = int(round(math.radians(5.0) / (math.pi / 1800)))
+    # above the chop angle the chopped function is the original over (1 - f)
+    np.testing.assert_allclose(c["p"][ic:] * (1 - c["removed"]), t["p"][ic:], rtol=1e-12)
+    assert np.all(c["p"][:ic] == c["p"][ic])
+    assert 0.2 < c["removed"] < 0.6            # the diffraction peak holds a large share
+    assert c["g"] < t["g"]
+
+
+@pytest.mark.parametrize("g", [0.0, 0.5, 0.857])
+def test_hg_table_moments_and_sampling(g):
+    t = O.phase_table(hg_table(g))
+    assert t["g"] == pytest.approx(g, abs=2e-3)
+    us = (np.arange(20000) + 0.5) / 20000
+    mus = np.array([O.tab_sample(t, u) for u in us])
+    assert np.all(np.diff(mus) <= 1e-15)        # monotone in u
+    assert mus.mean() == pytest.approx(t["g"], abs=1e-3)
+    # the drawn cosines follow the analytic inverse CDF of HG (the table walks theta
+    # upward, the analytic form mu upward: u and 1 - u)
+    ref = np.array([O.hg_sample_cos(g, 1 - u) for u in us[::97]])
+    np.testing.assert_allclose(mus[::97], ref, atol=5e-3)
+
+
+def test_hg_table_in_the_tracer_matches_analytic_hg(clean_phase):
+    n = 16
+    d = synth.cloud_density(n, seed=7).numpy()
+    grid = O.Grid(d, 16.0, [-0.5] * 3, 1.0 / n)
+    pos, view, light, _ = O.sample_records(grid, 24, 3)
+    m0, v0 = O.trace_li(grid, pos, view, light, albedo=0.95, g=0.7, spp=3000, seed=2)
+    O.set_phase(O.phase_table(hg_table(0.7)))
+    m1, v1 = O.trace_li(grid, pos, view, light, albedo=0.95, g=0.7, spp=3000, seed=2)
+    assert np.all(np.abs(m0 - m1) < 5 * np.sqrt(v0 + v1) + 1e-12)
+    assert np.any(m0 != m1)
+
+
+def test_first_collision_uses_the_unchopped_table(clean_phase):
+    # homogeneous box, rays along +x, light along +z: the direct term of a collision has
+    # mean albedo * p_first(0) * exp(-sigma depth) * E, p_first the first-collision table
+    n = 12
+    h = 1.0 / n
+    grid = O.Grid(np.ones((n, n, n), np.float32), 1.7, [-0.5] * 3, h)
+    theta, p, _ = synth.cloud_droplet_phase(n_theta=1801, n_r=60)
+    full, chop = O.phase_table(p), O.phase_table(p, chop_deg=5.0)
+    O.set_phase(chop, first=full)
+    R, S = 4, 2500
+    zs = np.linspace(-0.3, 0.3, R)
+    o = np.stack([np.full(R, -0.9), np.full(R, 0.05), zs], 1).astype(np.float32)
+    dirs = np.tile(np.array([[1.0, 0, 0]], np.float32), (R, 1))
+    hits, dsum = np.zeros(R), np.zeros(R)
+    for s in range(S):
+        _, _, direct, hit = O.first_hits(grid, o, dirs, [0, 0, 1], albedo=0.9, irradiance=2.0,
+                                         seed=4, sample=s)
+        hits += hit == 1
+        dsum += direct
+    p90 = full["p"][900]                         # theta = 90 degrees is node 900
+    assert p90 != chop["p"][900]
+    T = np.exp(-1.7 * np.array([ramp_int(z + 0.5, 1.0, n, h) for z in zs]))
+    want = 0.9 * p90 * T * 2.0
+    sd = 0.9 * p90 * 2.0 * np.sqrt(T * (1 - T) / hits)
+    assert np.all(np.abs(dsum / hits - want) < 5 * sd + 1e-12)
