@@ -320,6 +320,29 @@ ds_status ds_train_step(ds_net *net, ds_adam *opt, const float *z, const float *
 #define DS_LIGHT_DIRECTIONAL 0 /* a directional light of irradiance E, next-event estimation */
 #define DS_LIGHT_ENVIRONMENT 1 /* a uniform environment of radiance E, counted on escape     */
 
+/* A tabulated phase function (Sec. 5.1: the paper renders and generates data with a
+ * tabulated Lorenz-Mie function whose forward peak is chopped, the density reduced
+ * accordingly, and uses the unchopped function for the first scattering event while
+ * rendering).  p: host, n values (2 <= n <= 65536, finite, >= 0) at theta_i =
+ * i pi / (n - 1) per steradian.  The table is normalised so that the trapezoid rule
+ * on 2 pi p sin(theta) gives 1.  chop_deg > 0 holds p below the node nearest
+ * chop_deg at that node's value; the fraction f of the scattering that this removes
+ * is reported and the rest renormalised: a caller that chops should scale the
+ * extinction by (1 - albedo f) and use albedo (1 - f) / (1 - albedo f).  The tracer
+ * evaluates p linearly in theta between nodes and draws theta from the cumulative
+ * trapezoid sums, linear density inside a node interval.  ds_phase_build does the
+ * host part only: p_out and cdf_out (n doubles each, may be NULL), removed and
+ * mean_cos (may be NULL).  ds_phase_create uploads the table (8 bytes per node) to
+ * ctx's device. */
+typedef struct ds_phase ds_phase;
+ds_status ds_phase_build(int32_t n, const double *p, double chop_deg, double *p_out,
+                         double *cdf_out, double *removed, double *mean_cos);
+ds_status ds_phase_create(ds_ctx *ctx, int32_t n, const double *p, double chop_deg,
+                          ds_phase **out);
+ds_status ds_phase_info(const ds_phase *phase, double *removed, double *mean_cos);
+/* Waits for the context's stream, then frees the table. */
+ds_status ds_phase_destroy(ds_phase *phase);
+
 typedef struct ds_tracer_params {
     float albedo;         /* survival probability per collision, in [0, 1]              */
     float g;              /* HG mean cosine, in (-1, 1)                                   */
@@ -329,6 +352,10 @@ typedef struct ds_tracer_params {
     int32_t include_direct;   /* 0: estimates of L_i; 1: of all in-scattered radiance L_s =
                                  L_d + L_i (Sec. 7's target ablation): ds_trace_li and the
                                  record calls only, the render calls reject it           */
+    const ds_phase *phase;       /* NULL: Henyey-Greenstein with g; else this table for
+                                    every scattering and next-event estimate             */
+    const ds_phase *phase_first; /* NULL: as phase; else the table for the direct term at
+                                    the first collision of camera rays (render calls)    */
 } ds_tracer_params;
 
 /* The cloud's majorant sigma_max * max(d) (host write). */

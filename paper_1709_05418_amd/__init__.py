@@ -98,6 +98,10 @@ def lib():
                                          P]),
         "ds_net_param_count_mlp": (I64, [S, S, P]),
         "ds_net_create_mlp": (S, [P, S, S, P, P]),
+        "ds_phase_build": (S, [S, P, D, P, P, P, P]),
+        "ds_phase_create": (S, [P, S, P, D, P]),
+        "ds_phase_info": (S, [P, P, P]),
+        "ds_phase_destroy": (S, [P]),
         "ds_lights_create": (S, [P, S, P, P, P]),
         "ds_light_table": (S, [S, P, P, P]),
         "ds_lights_destroy": (S, [P]),
@@ -125,12 +129,16 @@ class TracerParams(C.Structure):
     include_direct (record estimates of L_s = L_d + L_i instead of L_i)."""
     _fields_ = [("albedo", C.c_float), ("g", C.c_float), ("irradiance", C.c_float),
                 ("light_mode", C.c_int32), ("max_interactions", C.c_int32),
-                ("include_direct", C.c_int32)]
+                ("include_direct", C.c_int32), ("phase", C.c_void_p),
+                ("phase_first", C.c_void_p)]
 
     def __init__(self, albedo=0.999, g=0.85, irradiance=1.0, light_mode=0, max_interactions=0,
-                 include_direct=0):
+                 include_direct=0, phase=None, phase_first=None):
+        """phase / phase_first: Phase objects (tabulated phase functions) or None."""
+        h = lambda ph: None if ph is None else (ph.h.value if hasattr(ph, "h") else ph)
         super().__init__(float(albedo), float(g), float(irradiance), int(light_mode),
-                         int(max_interactions), int(include_direct))
+                         int(max_interactions), int(include_direct), h(phase),
+                         h(phase_first))
 
 
 class Adaptive(C.Structure):
@@ -719,6 +727,36 @@ class NetMLP(Net):
         _check(lib().ds_net_create_mlp(ctx.h, int(K), int(w.size), w.ctypes.data, C.byref(h)))
         self.h = h
         self.n_params = ds_net_param_count_mlp(K, w)
+
+
+def ds_phase_build(p, chop_deg=0.0):
+    """The library's phase table on the host: (p, cdf, removed fraction, mean cosine)."""
+    a = np.ascontiguousarray(np.asarray(p, np.float64).reshape(-1))
+    q = np.zeros(a.size)
+    c = np.zeros(a.size)
+    rem, g = C.c_double(), C.c_double()
+    _check(lib().ds_phase_build(int(a.size), a.ctypes.data, float(chop_deg), q.ctypes.data,
+                                c.ctypes.data, C.byref(rem), C.byref(g)))
+    return q, c, rem.value, g.value
+
+
+class Phase:
+    """A tabulated phase function on the device (ds_phase_create)."""
+
+    def __init__(self, ctx: Context, p, chop_deg=0.0):
+        a = np.ascontiguousarray(np.asarray(p, np.float64).reshape(-1))
+        h = C.c_void_p()
+        _check(lib().ds_phase_create(ctx.h, int(a.size), a.ctypes.data, float(chop_deg),
+                                     C.byref(h)))
+        self.h = h
+        rem, g = C.c_double(), C.c_double()
+        _check(lib().ds_phase_info(h, C.byref(rem), C.byref(g)))
+        self.removed, self.mean_cos = rem.value, g.value
+
+    def close(self):
+        if self.h is not None:
+            _check(lib().ds_phase_destroy(self.h))
+            self.h = None
 
 
 class Lights:

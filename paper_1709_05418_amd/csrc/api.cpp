@@ -638,6 +638,14 @@ using namespace ds;
 
 // A distant emitter as m directional lights (Sec. 4.4): per light the unit direction and
 // the weight E_j / p_j (device float4), and the selection thresholds (device).
+// A tabulated phase function on the device (FP32 copies of the host FP64 table).
+struct ds_phase {
+    ds_ctx *ctx = nullptr;
+    int n = 0;
+    float *p = nullptr, *cdf = nullptr;
+    double removed = 0.0, mean_cos = 0.0;
+};
+
 constexpr int kMaxLights = 65536;  // members of a light set
 constexpr int kMaxDraws = 256;     // lights drawn per camera sample
 
@@ -1652,6 +1660,12 @@ ds_status ds_train_step(ds_net *net, ds_adam *opt, const float *z, const float *
 static ds_status tracer_params(const ds_tracer_params *p, TracerParams &tp, const char *fn)
 {
     DS_CHECK(p, DS_ERR_INVALID_ARG, "%s: params is NULL", fn);
+    tp.ph_p = p->phase ? p->phase->p : nullptr;
+    tp.ph_cdf = p->phase ? p->phase->cdf : nullptr;
+    tp.ph_n = p->phase ? p->phase->n : 0;
+    tp.pf_p = p->phase_first ? p->phase_first->p : nullptr;
+    tp.pf_cdf = p->phase_first ? p->phase_first->cdf : nullptr;
+    tp.pf_n = p->phase_first ? p->phase_first->n : 0;
     DS_CHECK(p->albedo >= 0.f && p->albedo <= 1.f, DS_ERR_INVALID_ARG,
              "%s: albedo %g outside [0, 1]", fn, (double)p->albedo);
     DS_CHECK(p->g > -1.f && p->g < 1.f, DS_ERR_INVALID_ARG, "%s: g %g outside (-1, 1)", fn,
@@ -2017,6 +2031,121 @@ ds_status ds_render_rpnn(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
         DS_HIP(hipStreamSynchronize(s));
         *n_fallback = (int64_t)h;
     }
+    return DS_OK;
+}
+
+// ---------------------------------------------------------------- phase tables
+ds_status ds_phase_build(int32_t n, const double *p, double chop_deg, double *p_out,
+                         double *cdf_out, double *removed, double *mean_cos)
+{
+    DS_CHECK(p, DS_ERR_INVALID_ARG, "ds_phase_build: NULL table");
+    DS_CHECK(n >= 2 && n <= 65536, DS_ERR_INVALID_ARG, "ds_phase_build: %d nodes outside 2..65536",
+             n);
+    DS_CHECK(std::isfinite(chop_deg) && chop_deg >= 0.0 && chop_deg < 180.0, DS_ERR_INVALID_ARG,
+             "ds_phase_build: chop angle %g outside [0, 180)", chop_deg);
+    for (int i = 0; i < n; ++i)
+        DS_CHECK(std::isfinite(p[i]) && p[i] >= 0.0, DS_ERR_INVALID_ARG,
+                 "ds_phase_build: value %d is negative or not finite", i);
+    const double dth = M_PI / (n - 1);
+    std::vector<double> q(p, p + n), f(n);
+    auto integral = [&](const std::vector<double> &v) {
+        double acc = 0.0;
+        for (int i = 0; i < n; ++i)
+            f[i] = 2.0 * M_PI * v[i] * std::sin(i * dth);
+        for (int i = 0; i + 1 < n; ++i)
+            acc += 0.5 * (f[i] + f[i + 1]) * dth;
+        return acc;
+    };
+    const double tot = integral(q);
+    DS_CHECK(tot > 0.0, DS_ERR_INVALID_ARG, "ds_phase_build: the table integrates to zero");
+    for (double &v : q)
+        v /= tot;
+    double rem = 0.0;
+    if (chop_deg > 0.0) {
+        const int ic = (int)std::lround(chop_deg * M_PI / 180.0 / dth);
+        for (int i = 0; i < ic && i < n; ++i)
+            q[i] = q[ic < n ? ic : n - 1];
+        rem = 1.0 - integral(q);
+        DS_CHECK(rem < 1.0, DS_ERR_INVALID_ARG, "ds_phase_build: chopping removes everything");
+        for (double &v : q)
+            v /= 1.0 - rem;
+    }
+    for (int i = 0; i < n; ++i)
+        f[i] = 2.0 * M_PI * q[i] * std::sin(i * dth);
+    std::vector<double> c(n, 0.0);
+    double g = 0.0;
+    for (int i = 0; i + 1 < n; ++i) {
+        c[i + 1] = c[i] + 0.5 * (f[i] + f[i + 1]) * dth;
+        g += 0.5 * (f[i] * std::cos(i * dth) + f[i + 1] * std::cos((i + 1) * dth)) * dth;
+    }
+    for (int i = 0; i < n; ++i) {
+        if (p_out)
+            p_out[i] = q[i];
+        if (cdf_out)
+            cdf_out[i] = c[i] / c[n - 1];
+    }
+    if (removed)
+        *removed = rem;
+    if (mean_cos)
+        *mean_cos = g;
+    return DS_OK;
+}
+
+ds_status ds_phase_create(ds_ctx *ctx, int32_t n, const double *p, double chop_deg,
+                          ds_phase **out)
+{
+    DS_CHECK(ctx && p && out, DS_ERR_INVALID_ARG, "ds_phase_create: NULL argument");
+    *out = nullptr;
+    std::vector<double> q((size_t)(n > 0 ? n : 0)), c((size_t)(n > 0 ? n : 0));
+    double rem = 0.0, g = 0.0;
+    ds_status st = ds_phase_build(n, p, chop_deg, q.data(), c.data(), &rem, &g);
+    if (st)
+        return st;
+    std::vector<float> hf(2 * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+        hf[i] = (float)q[i];
+        hf[n + i] = (float)c[i];
+    }
+    hf[2 * (size_t)n - 1] = 1.f;
+    ds_phase *ph = new (std::nothrow) ds_phase;
+    DS_CHECK(ph, DS_ERR_OOM, "ds_phase_create: out of host memory");
+    ph->ctx = ctx;
+    ph->n = n;
+    ph->removed = rem;
+    ph->mean_cos = g;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e == hipSuccess)
+        e = hipMalloc(&ph->p, sizeof(float) * 2 * (size_t)n);
+    if (e == hipSuccess)
+        e = hipMemcpy(ph->p, hf.data(), sizeof(float) * 2 * (size_t)n, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(ph->p);
+        delete ph;
+        return hip_fail(e, "ds_phase_create");
+    }
+    ph->cdf = ph->p + n;
+    *out = ph;
+    return DS_OK;
+}
+
+ds_status ds_phase_info(const ds_phase *phase, double *removed, double *mean_cos)
+{
+    DS_CHECK(phase, DS_ERR_INVALID_ARG, "ds_phase_info: NULL table");
+    if (removed)
+        *removed = phase->removed;
+    if (mean_cos)
+        *mean_cos = phase->mean_cos;
+    return DS_OK;
+}
+
+ds_status ds_phase_destroy(ds_phase *phase)
+{
+    if (!phase)
+        return DS_OK;
+    (void)hipSetDevice(phase->ctx->device);
+    (void)hipStreamSynchronize(phase->ctx->stream);
+    (void)hipFree(phase->p);
+    delete phase;
     return DS_OK;
 }
 

@@ -268,6 +268,13 @@ struct TracerParams {
     float albedo, g, irradiance;
     int light_mode, max_interactions;
     int include_direct = 0;  // record estimates of L_s = L_d + L_i instead of L_i
+    // tabulated phase functions (device, n values at theta_i = i pi / (n - 1) and the
+    // normalised CDF of theta at the same nodes); ph_n = 0: Henyey-Greenstein with g.
+    // The first-collision table (pf) serves the direct term of camera rays only.
+    const float *ph_p = nullptr, *ph_cdf = nullptr;
+    int ph_n = 0;
+    const float *pf_p = nullptr, *pf_cdf = nullptr;
+    int pf_n = 0;
     const float4 *set_dw = nullptr;
     const uint32_t *set_thr = nullptr;
     int set_m = 0;

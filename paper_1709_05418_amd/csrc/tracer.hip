@@ -228,6 +228,53 @@ __device__ __forceinline__ float hg_cos(float g, float u)
     return fminf(1.f, fmaxf(-1.f, (1.f + g * g - s * s) / (2.f * g)));
 }
 
+// Tabulated phase function p at theta_i = i pi / (n - 1): linear in theta between nodes.
+__device__ __forceinline__ float tab_eval(const float *p, int n, float mu)
+{
+    const float th = acosf(fminf(1.f, fmaxf(-1.f, mu))) * ((float)(n - 1) / (float)M_PI);
+    const int i = min((int)th, n - 2);
+    const float f = th - (float)i;
+    return fmaf(f, p[i + 1] - p[i], p[i]);
+}
+
+// cos(theta) from the table: the node interval by binary search of the CDF, then theta
+// inside it from the density linear between the nodes' p sin(theta) (the root of the
+// interval's quadratic CDF, in the form without cancellation).
+__device__ __forceinline__ float tab_sample(const float *p, const float *cdf, int n, float u)
+{
+    int lo = 0, hi = n - 1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (cdf[mid] <= u)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    const float dth = (float)M_PI / (float)(n - 1);
+    const float fa = p[lo] * sinf((float)lo * dth), fb = p[lo + 1] * sinf((float)(lo + 1) * dth);
+    const float den = cdf[lo + 1] - cdf[lo];
+    const float q = den > 0.f ? (u - cdf[lo]) / den : 0.f;
+    const float sq = sqrtf(fmaxf(0.f, fa * fa + (fb - fa) * q * (fa + fb)));
+    const float t = fa + sq > 0.f ? fminf(1.f, fmaxf(0.f, q * (fa + fb) / (fa + sq))) : q;
+    return cosf(((float)lo + t) * dth);
+}
+
+// Phase function of the medium: the table when one is set (first: the first-collision
+// table of camera rays, else the scattering table), else Henyey-Greenstein.
+__device__ __forceinline__ float phase_eval(const TracerParams &tp, bool first, float mu)
+{
+    if (first && tp.pf_n)
+        return tab_eval(tp.pf_p, tp.pf_n, mu);
+    if (tp.ph_n)
+        return tab_eval(tp.ph_p, tp.ph_n, mu);
+    return hg(tp.g, mu);
+}
+
+__device__ __forceinline__ float phase_sample(const TracerParams &tp, float u)
+{
+    return tp.ph_n ? tab_sample(tp.ph_p, tp.ph_cdf, tp.ph_n, u) : hg_cos(tp.g, u);
+}
+
 __device__ V3 around(V3 w, float c, float u)
 {
     V3 t1, t2;
@@ -254,7 +301,7 @@ __device__ float li_path(const Medium &M, const TracerParams &tp, V3 x, V3 w, V3
     for (int j = 1;; ++j) {
         if ((tp.max_interactions > 0 && j > tp.max_interactions) || steps >= kMaxSteps)
             break;
-        const float c = hg_cos(tp.g, r.u());
+        const float c = phase_sample(tp, r.u());
         const V3 wh = around(wprev, c, r.u());
         V3 xn;
         if (!delta_track(M, p, neg(wh), r, xn, steps)) {
@@ -266,11 +313,12 @@ __device__ float li_path(const Medium &M, const TracerParams &tp, V3 x, V3 w, V3
         if (r.u() >= tp.albedo)
             break;
         if (tp.light_mode == 0) {
-            sum += hg(tp.g, -dot(wh, wl)) * ratio_track(M, p, wl, r, steps) * tp.irradiance;
+            sum += phase_eval(tp, false, -dot(wh, wl)) * ratio_track(M, p, wl, r, steps) * tp.irradiance;
         } else if (tp.light_mode == kLightSetMode) {
             const float4 lw = tp.set_dw[set_pick(tp, r)];
             const V3 lj = v3(lw.x, lw.y, lw.z);
-            sum += lw.w * hg(tp.g, -dot(wh, lj)) * ratio_track(M, p, lj, r, steps) * tp.irradiance;
+            sum += lw.w * phase_eval(tp, false, -dot(wh, lj)) * ratio_track(M, p, lj, r, steps) *
+                   tp.irradiance;
         }
         wprev = wh;
     }
@@ -316,7 +364,7 @@ __device__ float record_path(const Medium &M, const TracerParams &tp, V3 x, V3 w
     if (tp.light_mode == 1)
         return li_path(M, tp, x, w, wl, true, r);
     int64_t steps = 0;
-    const float d = hg(tp.g, -dot(w, wl)) * ratio_track(M, x, wl, r, steps) * tp.irradiance;
+    const float d = phase_eval(tp, false, -dot(w, wl)) * ratio_track(M, x, wl, r, steps) * tp.irradiance;
     return d + li_path(M, tp, x, w, wl, false, r);
 }
 
@@ -494,13 +542,15 @@ __global__ void __launch_bounds__(kPaths) k_render_mc(Medium M, TracerParams tp,
         } else {
             const V3 w = neg(d);
             if (tp.light_mode == 0) {
-                const float direct = hg(tp.g, -dot(w, wl)) * ratio_track(M, x, wl, r, steps) * tp.irradiance;
+                const float direct = phase_eval(tp, true, -dot(w, wl)) *
+                                     ratio_track(M, x, wl, r, steps) * tp.irradiance;
                 e = (double)tp.albedo * (double)(direct + li_path(M, tp, x, w, wl, false, r));
             } else if (tp.light_mode == kLightSetMode) {
                 const float4 lw = tp.set_dw[set_pick(tp, r)];
                 const V3 lj = v3(lw.x, lw.y, lw.z);
                 const float direct =
-                    lw.w * hg(tp.g, -dot(w, lj)) * ratio_track(M, x, lj, r, steps) * tp.irradiance;
+                    lw.w * phase_eval(tp, true, -dot(w, lj)) * ratio_track(M, x, lj, r, steps) *
+                    tp.irradiance;
                 e = (double)tp.albedo * (double)(direct + li_path(M, tp, x, w, wl, false, r));
             } else {
                 e = (double)tp.albedo * (double)li_path(M, tp, x, w, wl, true, r);
@@ -534,7 +584,8 @@ __global__ void __launch_bounds__(256) k_first_hits(Medium M, TracerParams tp, V
         int64_t steps = 0;
         h = delta_track(M, o, d, r, x, steps);
         if (h)
-            dir = tp.albedo * hg(tp.g, dot(d, wl)) * ratio_track(M, x, wl, r, steps) * tp.irradiance;
+            dir = tp.albedo * phase_eval(tp, true, dot(d, wl)) * ratio_track(M, x, wl, r, steps) *
+                  tp.irradiance;
     }
     pos[3 * i] = x.x;
     pos[3 * i + 1] = x.y;
@@ -577,7 +628,7 @@ __global__ void __launch_bounds__(256) k_first_hits_set(Medium M, TracerParams t
         if (h) {
             lw = tp.set_dw[set_pick(tp, r)];
             const V3 lj = v3(lw.x, lw.y, lw.z);
-            sum += lw.w * hg(tp.g, dot(d, lj)) * ratio_track(M, x, lj, r, steps);
+            sum += lw.w * phase_eval(tp, true, dot(d, lj)) * ratio_track(M, x, lj, r, steps);
         }
         pos[3 * row] = x.x;
         pos[3 * row + 1] = x.y;

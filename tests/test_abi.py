@@ -59,6 +59,9 @@ def test_null_and_bad_arguments_are_rejected_before_any_launch():
                                    None, None, None, None) == -1
     assert L.ds_light_table(0, None, None, None) == -1
     assert L.ds_net_create_mlp(None, 1, 1, None, C.byref(out)) == -1
+    assert L.ds_phase_create(None, 4, None, 0.0, C.byref(out)) == -1
+    assert L.ds_phase_build(1, None, 0.0, None, None, None, None) == -1
+    assert L.ds_phase_destroy(None) == 0
     assert ds.ds_net_param_count_mlp(10, [200] * 22 + [1]) == 1_294_801
     assert ds.ds_net_param_count_mlp(10, [400, 400, 200, 200, 200, 1]) == 1_222_001
     assert ds.ds_net_param_count_mlp(10, [200, 2]) == -1    # the output must be scalar

@@ -93,3 +93,20 @@ def test_first_collision_uses_the_unchopped_table(clean_phase):
     want = 0.9 * p90 * T * 2.0
     sd = 0.9 * p90 * 2.0 * np.sqrt(T * (1 - T) / hits)
     assert np.all(np.abs(dsum / hits - want) < 5 * sd + 1e-12)
+
+
+@pytest.mark.skipif(not __import__("os").path.exists(__import__("paper_1709_05418_amd").LIB_PATH),
+                    reason="libdeepscatter.so not built")
+@pytest.mark.parametrize("chop", [0.0, 5.0, 20.0])
+def test_library_phase_table_matches_oracle(chop):
+    import paper_1709_05418_amd as ds
+    theta, p, _ = synth.cloud_droplet_phase(n_theta=1801, n_r=60)
+    q, c, rem, g = ds.ds_phase_build(p, chop)
+    t = O.phase_table(p, chop_deg=chop)
+    np.testing.assert_allclose(q, t["p"], rtol=1e-12)
+    np.testing.assert_allclose(c, t["cdf"], rtol=1e-12, atol=1e-15)
+    assert rem == pytest.approx(t["removed"], rel=1e-10, abs=1e-15)
+    assert g == pytest.approx(t["g"], rel=1e-12)
+    for bad in ([1.0], [1.0, -1.0], [np.nan, 1.0]):
+        with pytest.raises(ds.DSError):
+            ds.ds_phase_build(bad)
