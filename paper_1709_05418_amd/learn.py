@@ -234,6 +234,14 @@ def judge_sun_sky(args, ctx, cloud, net, prm, precs, log):
     return out
 
 
+def _close(args, ctx):
+    """Free the phase tables of a run, then its context."""
+    for ph in getattr(args, "phases", ()):
+        if ph is not None:
+            ph.close()
+    ctx.close()
+
+
 def camera(width, height, cam_pos=(0.0, 0.12, 2.3), look_at=(0.0, 0.0, 0.0), fov_deg=42.0,
            crop=None, seed=0, device="cuda"):
     """Jittered pinhole rays of a width x height view (fov over the larger side), as
@@ -307,6 +315,11 @@ def main(argv=None):
                          "+- this fraction at 95 %% confidence (Sec. 5.1), instead of --spp paths")
     ap.add_argument("--adaptive-batch", type=int, default=256)
     ap.add_argument("--adaptive-max", type=int, default=65536)
+    ap.add_argument("--phase", default="hg", choices=["hg", "lm"],
+                    help="Henyey-Greenstein g = 0.85, or a tabulated Lorenz-Mie function of "
+                         "cloud droplets, chopped (reduced density) for data and rendering and "
+                         "unchopped for the first collision's direct term (Sec. 5.1)")
+    ap.add_argument("--chop-deg", type=float, default=5.0)
     ap.add_argument("--no-judge", action="store_true", help="stop after training")
     ap.add_argument("--compare", action="store_true",
                     help="train the RPNN and the two all-at-once MLPs of Sec. 7 (23 x 200 and "
@@ -318,7 +331,21 @@ def main(argv=None):
     log = lambda *a: print("[learn]", *a, flush=True)
     dev = "cuda"
     ctx = ds.Context(0)
-    prm = ds.TracerParams(0.999, 0.85, 1.0, ds.DS_LIGHT_DIRECTIONAL, 0)
+    albedo, sigma_scale, phases = 0.999, 1.0, (None, None)
+    if args.phase == "lm":
+        _, p_lm, g_lm = synth.cloud_droplet_phase()
+        phases = (ds.Phase(ctx, p_lm, args.chop_deg), ds.Phase(ctx, p_lm))
+        f = phases[0].removed
+        # the chopped forward peak travels on unscattered: reduced extinction and albedo
+        sigma_scale = 1.0 - albedo * f
+        albedo = albedo * (1.0 - f) / sigma_scale
+        log(f"Lorenz-Mie phase: mean cosine {g_lm:.4f}; chopped at {args.chop_deg} deg, "
+            f"{100 * f:.1f} % of the scattering removed; extinction x{sigma_scale:.4f}, albedo "
+            f"{albedo:.5f}, chopped mean cosine {phases[0].mean_cos:.4f}")
+    args.sigma = lambda n: float(n) * sigma_scale
+    prm = ds.TracerParams(albedo, 0.85, 1.0, ds.DS_LIGHT_DIRECTIONAL, 0, phase=phases[0],
+                          phase_first=phases[1])
+    args.phases = phases
     K, W = args.K, args.W
     L = int(math.ceil(math.log2(args.n))) + 1
     per = args.records // args.clouds
@@ -330,8 +357,8 @@ def main(argv=None):
     D = ds.STENCIL_N * K + 1
     z = torch.empty((per * args.clouds, D), dtype=torch.float32, device=dev)
     t = torch.empty(per * args.clouds, dtype=torch.float32, device=dev)
-    rec_prm = ds.TracerParams(0.999, 0.85, 1.0, ds.DS_LIGHT_DIRECTIONAL, 0,
-                              include_direct=int(args.target == "ls"))
+    rec_prm = ds.TracerParams(albedo, 0.85, 1.0, ds.DS_LIGHT_DIRECTIONAL, 0,
+                              include_direct=int(args.target == "ls"), phase=phases[0])
     ad = (ds.Adaptive(args.adaptive_batch, args.adaptive_max, args.adaptive_rel, 1.96)
           if args.adaptive_rel > 0 else None)
     used = []
@@ -339,7 +366,7 @@ def main(argv=None):
     for c in range(args.clouds):
         d = synth.cloud_density(args.n, args.seed + c, worley=0.3, device=dev)
         amin, h0 = synth.unit_box(args.n)
-        cl = ds.Cloud(ctx, d, float(args.n), amin, h0, L, K)
+        cl = ds.Cloud(ctx, d, args.sigma(args.n), amin, h0, L, K)
         _, li_out = ds.ds_make_records(ctx.h, cl.h, rec_prm, per, ad or args.spp,
                                        args.seed + 7919 * c, z, t, offset=c, stride=args.clouds,
                                        want_li=ad is not None)
@@ -372,7 +399,7 @@ def main(argv=None):
         print(json.dumps({"target": args.target, "clouds": args.clouds, "n": args.n,
                           "pairs": per * args.clouds, "spp": args.spp, "data_seconds": t_data,
                           "paths_per_second": paths / t_data, **stats}), flush=True)
-        ctx.close()
+        _close(args, ctx)
         return
     if args.compare:
         return compare_architectures(args, ctx, prm, z, t, float(li.mean()), log,
@@ -400,14 +427,14 @@ def main(argv=None):
         print(json.dumps(base), flush=True)
         ds.ds_adam_destroy(opt)
         net.close()
-        ctx.close()
+        _close(args, ctx)
         return
     # held-out cloud, larger grid, same optical size in mean free paths per unit
     d = synth.cloud_density(args.judge_n, args.seed + 5000, worley=0.3, device=dev,
                             dtype=torch.bfloat16)
     amin, h0 = synth.unit_box(args.judge_n)
     Lj = min(16, int(math.ceil(math.log2(args.judge_n))) + 1)
-    jc = ds.Cloud(ctx, d, float(args.n), amin, h0, Lj, K)
+    jc = ds.Cloud(ctx, d, args.sigma(args.n), amin, h0, Lj, K)
     del d
     log(f"judge cloud {args.judge_n}^3 built ({time.time() - t0:.1f}s)")
     light = synth.table1_lights()[args.light]
@@ -443,12 +470,12 @@ def main(argv=None):
     summary.update(base)
     summary.update({"judge_n": args.judge_n, "frame": [args.width, args.height],
                     "crop": args.crop, "crop_spp": args.crop_spp, "ref_spp": args.ref_spp,
-                    "light": args.light})
+                    "light": args.light, "phase": args.phase})
     print(json.dumps(summary), flush=True)
     ds.ds_adam_destroy(opt)
     net.close()
     jc.close()
-    ctx.close()
+    _close(args, ctx)
 
 
 ARCHS = {"rpnn": None, "mlp_deep_23x200": [200] * 22 + [1],
@@ -495,7 +522,7 @@ def compare_architectures(args, ctx, prm, z, t, mean_li, log, data):
                                 dtype=torch.bfloat16)
         amin, h0 = synth.unit_box(args.judge_n)
         Lj = min(16, int(math.ceil(math.log2(args.judge_n))) + 1)
-        jc = ds.Cloud(ctx, d, float(args.n), amin, h0, Lj, K)
+        jc = ds.Cloud(ctx, d, args.sigma(args.n), amin, h0, Lj, K)
         del d
         light = synth.table1_lights()[args.light]
         c = args.crop
@@ -517,7 +544,7 @@ def compare_architectures(args, ctx, prm, z, t, mean_li, log, data):
                 "light": args.light, "crop": args.crop, "ref_spp": args.ref_spp,
                 "judge_n": args.judge_n, "held_out": held})
     print(json.dumps(out), flush=True)
-    ctx.close()
+    _close(args, ctx)
 
 
 def judge_only(args, ctx, net, prm, log):
@@ -530,7 +557,7 @@ def judge_only(args, ctx, net, prm, log):
                             dtype=torch.bfloat16)
     amin, h0 = synth.unit_box(args.judge_n)
     Lj = min(16, int(math.ceil(math.log2(args.judge_n))) + 1)
-    jc = ds.Cloud(ctx, d, float(args.n), amin, h0, Lj, K)
+    jc = ds.Cloud(ctx, d, args.sigma(args.n), amin, h0, Lj, K)
     del d
     log(f"judge cloud {args.judge_n}^3 built ({time.time() - t0:.1f}s)")
     light = synth.table1_lights()[args.light]
@@ -571,7 +598,7 @@ def judge_only(args, ctx, net, prm, log):
     print(json.dumps(summary), flush=True)
     net.close()
     jc.close()
-    ctx.close()
+    _close(args, ctx)
 
 
 if __name__ == "__main__":
