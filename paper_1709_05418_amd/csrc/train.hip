@@ -176,58 +176,143 @@ __global__ void __launch_bounds__(256) k_adam(float *theta, float *m, float *v, 
 // C (+)= A B with the strided operands of StridedGemm, every operand rounded to BF16
 // (nearest even) as it is staged into LDS, products accumulated in FP32 by
 // v_mfma_f32_16x16x32_bf16.  A 256-thread block computes a 64 x 64 tile of C, each
-// wave a 32 x 32 quarter (2 x 2 MFMA tiles).  Split s (blockIdx.z) covers
-// k in [s kc, (s+1) kc); with several splits the partial tiles go to P[s][M][N] and
-// k_splitk_sum adds them in split order, so results do not depend on timing.
+// wave a 32 x 32 quarter (2 x 2 MFMA tiles), over k steps of TK = 64.  Each operand is
+// read along its contiguous index: with unit k stride a thread loads 16 consecutive k
+// of one row (constant offsets from one pointer, two 16-byte LDS stores); with unit
+// row stride the 64 threads of a wave cover 64 consecutive rows and a thread walks
+// 16 k values 4 apart.  The next step's values are loaded into registers before the
+// current step's products, so their latency overlaps the matrix-core work.  Split s
+// (blockIdx.z) covers k in [s kc, (s+1) kc); with several splits the partial tiles go
+// to P[s][M][N] and k_splitk_sum adds them in split order, so results do not depend
+// on timing.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
-constexpr int TM = 64, TN = 64, TK = 32, TKP = TK + 8;
+constexpr int TM = 64, TN = 64, TK = 64, TKP = TK + 8;
+
+// One operand's share of a k step: 16 values of row `row` (of rows) at k = k0 + kq + j
+// (kc: unit k stride) or k = k0 + kq + 4 j (otherwise), zero outside.
+struct Stage {
+    const float *p;   // element (row, kbeg + kq)
+    int64_t sk;       // k stride
+    int kbeg;         // first k of the split
+    int kq;           // first k of this thread inside a step
+    bool kc, ok;      // unit k stride; row inside the matrix
+
+    __device__ __forceinline__ void load(int k0, int kend, float (&v)[16]) const
+    {
+        const float *q = p + (int64_t)(k0 - kbeg) * sk;
+        if (kc) {
+            if (ok && k0 + kq + 16 <= kend) {
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    v[j] = q[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < 16; ++j)
+                    v[j] = ok && k0 + kq + j < kend ? q[j] : 0.f;
+            }
+        } else if (ok && k0 + kq + 60 < kend) {
+            const int64_t s4 = 4 * sk;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                v[j] = *q;
+                q += s4;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 16; ++j)
+                v[j] = ok && k0 + kq + 4 * j < kend ? q[(int64_t)4 * j * sk] : 0.f;
+        }
+    }
+};
+
+__device__ __forceinline__ Stage stage_of(const float *base, int64_t s_row, int64_t s_k, int row0,
+                                          int rows, int kbeg, int tid)
+{
+    Stage st;
+    st.kc = s_k == 1;
+    int r;
+    if (st.kc) {
+        r = tid >> 2;
+        st.kq = 16 * (tid & 3);
+    } else {
+        r = tid & 63;
+        st.kq = tid >> 6;
+    }
+    st.ok = row0 + r < rows;
+    st.sk = s_k;
+    st.kbeg = kbeg;
+    st.p = base + (int64_t)(st.ok ? row0 + r : 0) * s_row + (int64_t)(kbeg + st.kq) * s_k;
+    return st;
+}
+
+// Stores one operand's 16 values (as BF16) at rows [row][k] of an LDS tile.
+__device__ __forceinline__ void stage_store(__bf16 (*T)[TKP], const Stage &st, int tid,
+                                            const float (&v)[16])
+{
+    if (st.kc) {
+        bf16x8 lo, hi;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            lo[j] = (__bf16)v[j];
+            hi[j] = (__bf16)v[8 + j];
+        }
+        *reinterpret_cast<bf16x8 *>(&T[tid >> 2][st.kq]) = lo;
+        *reinterpret_cast<bf16x8 *>(&T[tid >> 2][st.kq + 8]) = hi;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            T[tid & 63][st.kq + 4 * j] = (__bf16)v[j];
+    }
+}
 
 __global__ void __launch_bounds__(256) k_gemm_bf16(StridedGemm g, int kc, float *P)
 {
-    __shared__ __bf16 As[TM][TKP];  // [row][k]
-    __shared__ __bf16 Bt[TN][TKP];  // [col][k]
+    __shared__ __attribute__((aligned(16))) __bf16 As[TM][TKP];  // [row][k]
+    __shared__ __attribute__((aligned(16))) __bf16 Bt[TN][TKP];  // [col][k]
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int g4 = lane >> 4, n16 = lane & 15;
     const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
     const int kbeg = blockIdx.z * kc;
     const int kend = min(g.K, kbeg + kc);
     const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-    const bool a_kc = g.sak == 1;  // consecutive threads walk the contiguous index
-    const bool b_nc = g.sbn == 1;
+    // A as rows m over k; B read as columns n over k (B(k, n) = B[k sbk + n sbn])
+    const Stage sa = stage_of(g.A, g.sam, g.sak, m0, g.M, kbeg, tid);
+    const Stage sb = stage_of(g.B, g.sbn, g.sbk, n0, g.N, kbeg, tid);
     f4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j)
             acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    float va[16], vb[16];
+    if (kbeg < kend) {
+        sa.load(kbeg, kend, va);
+        sb.load(kbeg, kend, vb);
+    }
     for (int k0 = kbeg; k0 < kend; k0 += TK) {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int e = tid + 256 * i;
-            const int r = a_kc ? e >> 5 : e & 63, ka = a_kc ? e & 31 : e >> 6;
-            float v = 0.f;
-            if (m0 + r < g.M && k0 + ka < kend)
-                v = g.A[(int64_t)(m0 + r) * g.sam + (int64_t)(k0 + ka) * g.sak];
-            As[r][ka] = (__bf16)v;
-            const int c = b_nc ? e & 63 : e >> 5, kb = b_nc ? e >> 6 : e & 31;
-            float u = 0.f;
-            if (n0 + c < g.N && k0 + kb < kend)
-                u = g.B[(int64_t)(k0 + kb) * g.sbk + (int64_t)(n0 + c) * g.sbn];
-            Bt[c][kb] = (__bf16)u;
-        }
+        stage_store(As, sa, tid, va);
+        stage_store(Bt, sb, tid, vb);
         __syncthreads();
-        bf16x8 a[2], b[2];
-#pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            a[t] = *reinterpret_cast<const bf16x8 *>(&As[wr + 16 * t + n16][8 * g4]);
-            b[t] = *reinterpret_cast<const bf16x8 *>(&Bt[wc + 16 * t + n16][8 * g4]);
+        if (k0 + TK < kend) {  // the next step's values, in flight during the products
+            sa.load(k0 + TK, kend, va);
+            sb.load(k0 + TK, kend, vb);
         }
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int ks = 0; ks < TK; ks += 32) {
+            bf16x8 a[2], b[2];
 #pragma unroll
-            for (int j = 0; j < 2; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+            for (int t = 0; t < 2; ++t) {
+                a[t] = *reinterpret_cast<const bf16x8 *>(&As[wr + 16 * t + n16][ks + 8 * g4]);
+                b[t] = *reinterpret_cast<const bf16x8 *>(&Bt[wc + 16 * t + n16][ks + 8 * g4]);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] =
+                        __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
         __syncthreads();
     }
     // lane 16 g4 + n16 holds rows 4 g4 .. 4 g4 + 3, column n16 of each 16 x 16 tile
