@@ -176,21 +176,22 @@ __global__ void __launch_bounds__(256) k_adam(float *theta, float *m, float *v, 
 // C (+)= A B with the strided operands of StridedGemm, every operand rounded to BF16
 // (nearest even) as it is staged into LDS, products accumulated in FP32 by
 // v_mfma_f32_16x16x32_bf16.  A 256-thread block computes a 64 x 64 tile of C, each
-// wave a 32 x 32 quarter (2 x 2 MFMA tiles), over k steps of TK = 64.  Each operand is
-// read along its contiguous index: with unit k stride a thread loads 16 consecutive k
-// of one row (constant offsets from one pointer, two 16-byte LDS stores); with unit
-// row stride the 64 threads of a wave cover 64 consecutive rows and a thread walks
-// 16 k values 4 apart.  The next step's values are loaded into registers before the
+// wave a 32 x 32 quarter (2 x 2 MFMA tiles), over k steps of TK = 128.  Each operand is
+// read along its contiguous index: with unit k stride a thread loads 32 consecutive k
+// of one row (constant offsets from one pointer, 16-byte LDS stores); with unit row
+// stride the 64 threads of a wave cover 64 consecutive rows and a thread walks 32 k
+// values 4 apart.  The next step's values are loaded into registers before the
 // current step's products, so their latency overlaps the matrix-core work.  Split s
 // (blockIdx.z) covers k in [s kc, (s+1) kc); with several splits the partial tiles go
 // to P[s][M][N] and k_splitk_sum adds them in split order, so results do not depend
 // on timing.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
-constexpr int TM = 64, TN = 64, TK = 64, TKP = TK + 8;
+constexpr int TM = 64, TN = 64, TK = 128, TKP = TK + 8;
+constexpr int NE = TK / 4;  // elements of each operand a thread stages per k step
 
-// One operand's share of a k step: 16 values of row `row` (of rows) at k = k0 + kq + j
-// (kc: unit k stride) or k = k0 + kq + 4 j (otherwise), zero outside.
+// One operand's share of a k step: NE values of one row at k = k0 + kq + j (kc: unit k
+// stride) or k = k0 + kq + 4 j (otherwise), zero outside.
 struct Stage {
     const float *p;   // element (row, kbeg + kq)
     int64_t sk;       // k stride
@@ -198,29 +199,29 @@ struct Stage {
     int kq;           // first k of this thread inside a step
     bool kc, ok;      // unit k stride; row inside the matrix
 
-    __device__ __forceinline__ void load(int k0, int kend, float (&v)[16]) const
+    __device__ __forceinline__ void load(int k0, int kend, float (&v)[NE]) const
     {
         const float *q = p + (int64_t)(k0 - kbeg) * sk;
         if (kc) {
-            if (ok && k0 + kq + 16 <= kend) {
+            if (ok && k0 + kq + NE <= kend) {
 #pragma unroll
-                for (int j = 0; j < 16; ++j)
+                for (int j = 0; j < NE; ++j)
                     v[j] = q[j];
             } else {
 #pragma unroll
-                for (int j = 0; j < 16; ++j)
+                for (int j = 0; j < NE; ++j)
                     v[j] = ok && k0 + kq + j < kend ? q[j] : 0.f;
             }
-        } else if (ok && k0 + kq + 60 < kend) {
+        } else if (ok && k0 + kq + 4 * (NE - 1) < kend) {
             const int64_t s4 = 4 * sk;
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
+            for (int j = 0; j < NE; ++j) {
                 v[j] = *q;
                 q += s4;
             }
         } else {
 #pragma unroll
-            for (int j = 0; j < 16; ++j)
+            for (int j = 0; j < NE; ++j)
                 v[j] = ok && k0 + kq + 4 * j < kend ? q[(int64_t)4 * j * sk] : 0.f;
         }
     }
@@ -234,7 +235,7 @@ __device__ __forceinline__ Stage stage_of(const float *base, int64_t s_row, int6
     int r;
     if (st.kc) {
         r = tid >> 2;
-        st.kq = 16 * (tid & 3);
+        st.kq = NE * (tid & 3);
     } else {
         r = tid & 63;
         st.kq = tid >> 6;
@@ -246,22 +247,22 @@ __device__ __forceinline__ Stage stage_of(const float *base, int64_t s_row, int6
     return st;
 }
 
-// Stores one operand's 16 values (as BF16) at rows [row][k] of an LDS tile.
+// Stores one operand's NE values (as BF16) at [row][k] of an LDS tile.
 __device__ __forceinline__ void stage_store(__bf16 (*T)[TKP], const Stage &st, int tid,
-                                            const float (&v)[16])
+                                            const float (&v)[NE])
 {
     if (st.kc) {
-        bf16x8 lo, hi;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            lo[j] = (__bf16)v[j];
-            hi[j] = (__bf16)v[8 + j];
+        for (int h = 0; h < NE; h += 8) {
+            bf16x8 x;
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                x[j] = (__bf16)v[h + j];
+            *reinterpret_cast<bf16x8 *>(&T[tid >> 2][st.kq + h]) = x;
         }
-        *reinterpret_cast<bf16x8 *>(&T[tid >> 2][st.kq]) = lo;
-        *reinterpret_cast<bf16x8 *>(&T[tid >> 2][st.kq + 8]) = hi;
     } else {
 #pragma unroll
-        for (int j = 0; j < 16; ++j)
+        for (int j = 0; j < NE; ++j)
             T[tid & 63][st.kq + 4 * j] = (__bf16)v[j];
     }
 }
@@ -285,7 +286,7 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(StridedGemm g, int kc, float 
 #pragma unroll
         for (int j = 0; j < 2; ++j)
             acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-    float va[16], vb[16];
+    float va[NE], vb[NE];
     if (kbeg < kend) {
         sa.load(kbeg, kend, va);
         sb.load(kbeg, kend, vb);
@@ -393,8 +394,10 @@ int splitk_count(const StridedGemm &g)
 {
     const int64_t tiles = (int64_t)((g.N + TN - 1) / TN) * ((g.M + TM - 1) / TM);
     const int ksteps = (g.K + TK - 1) / TK;
+    if (tiles >= 64)  // enough blocks already: no extra pass over partial sums
+        return 1;
     int S = 1;
-    while (S < 16 && tiles * S < 256 && ksteps >= 8 * S)
+    while (S < 16 && tiles * S < 256 && ksteps >= 2 * S)
         S *= 2;
     return S;
 }
