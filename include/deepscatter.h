@@ -323,7 +323,7 @@ ds_status ds_train_step(ds_net *net, ds_adam *opt, const float *z, const float *
 /* A tabulated phase function (Sec. 5.1: the paper renders and generates data with a
  * tabulated Lorenz-Mie function whose forward peak is chopped, the density reduced
  * accordingly, and uses the unchopped function for the first scattering event while
- * rendering).  p: host, n values (2 <= n <= 65536, finite, >= 0) at theta_i =
+ * rendering).  p: host, n values (3 <= n <= 65536, finite, >= 0) at theta_i =
  * i pi / (n - 1) per steradian.  The table is normalised so that the trapezoid rule
  * on 2 pi p sin(theta) gives 1.  chop_deg > 0 holds p below the node nearest
  * chop_deg at that node's value; the fraction f of the scattering that this removes

@@ -438,8 +438,8 @@ def phase_table(p, chop_deg=0.0):
     dict: p, cdf (normalised running trapezoid sums), removed (f), g (mean cosine)."""
     p = np.asarray(p, np.float64)
     n = p.size
-    if n < 2 or not np.all(np.isfinite(p)) or np.any(p < 0):
-        raise ValueError("a phase table needs at least two finite non-negative values")
+    if n < 3 or not np.all(np.isfinite(p)) or np.any(p < 0):
+        raise ValueError("a phase table needs at least three finite non-negative values")
     theta = np.arange(n) * (np.pi / (n - 1))
 
     def integral(q):

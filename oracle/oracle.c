@@ -923,7 +923,7 @@ static void tab_set(phase_tab *t, int n, const double *p, const double *cdf)
     free(t->cdf);
     t->p = t->cdf = NULL;
     t->n = 0;
-    if (n < 2 || !p || !cdf)
+    if (n < 3 || !p || !cdf)
         return;
     t->p = malloc(sizeof(double) * n);
     t->cdf = malloc(sizeof(double) * n);

@@ -2039,7 +2039,7 @@ ds_status ds_phase_build(int32_t n, const double *p, double chop_deg, double *p_
                          double *cdf_out, double *removed, double *mean_cos)
 {
     DS_CHECK(p, DS_ERR_INVALID_ARG, "ds_phase_build: NULL table");
-    DS_CHECK(n >= 2 && n <= 65536, DS_ERR_INVALID_ARG, "ds_phase_build: %d nodes outside 2..65536",
+    DS_CHECK(n >= 3 && n <= 65536, DS_ERR_INVALID_ARG, "ds_phase_build: %d nodes outside 3..65536",
              n);
     DS_CHECK(std::isfinite(chop_deg) && chop_deg >= 0.0 && chop_deg < 180.0, DS_ERR_INVALID_ARG,
              "ds_phase_build: chop angle %g outside [0, 180)", chop_deg);

@@ -217,3 +217,30 @@ def test_light_set_arguments_are_checked(ctx, small_cloud, sky_set):
         ds.Lights(ctx, [[0, 0, 0]], [1.0])
     with pytest.raises(ds.DSError):
         ds.Lights(ctx, [[0, 0, 1]], [0.0])
+
+
+def test_light_set_edge_cases(ctx, small_cloud, small):
+    # empty inputs are no-ops; one light drawn the maximum number of times is the
+    # directional light itself, drawn 256 times
+    prm = ds.TracerParams(0.9, 0.85, 1.0, 0, 0)
+    one = ds.Lights(ctx, [synth.table1_lights()["side"]], [2.0])
+    try:
+        e = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
+        m, _ = ds.ds_render_mc_lights(ctx.h, small_cloud.h, prm, one.h, e, e, 4, 1)
+        assert m.numel() == 0
+        o, d = _rays(6, 2)
+        pos, view, light, weight, direct, hit = ds.ds_first_hits_lights(
+            ctx.h, small_cloud.h, prm, one.h, 256, _cuda(o), _cuda(d), seed=3)
+        rows = torch.repeat_interleave(hit == 1, 256)
+        assert torch.all(weight[rows] == 2.0)
+        ld = torch.tensor(synth.table1_lights()["side"], device="cuda")
+        assert torch.allclose(light[rows], ld.expand(int(rows.sum()), 3))
+        # the 256 draws of one light are 256 ratio-tracking estimates of the same term
+        _, _, d1, h1 = ds.ds_first_hits(ctx.h, small_cloud.h, ds.TracerParams(0.9, 0.85, 2.0, 0, 0),
+                                        synth.table1_lights()["side"], _cuda(o), _cuda(d), seed=3)
+        assert torch.equal(h1, hit)
+        with pytest.raises(ds.DSError):
+            ds.ds_first_hits_lights(ctx.h, small_cloud.h, prm, one.h, 257, _cuda(o), _cuda(d),
+                                    seed=3)
+    finally:
+        one.close()

@@ -159,3 +159,21 @@ def test_training_steps_reduce_the_loss(ctx, batch):
         ds.ds_adam_destroy(opt)
     finally:
         net.close()
+
+
+def test_single_layer_mlp_and_adaptive_empty(ctx, batch):
+    # one layer (the descriptor straight to the scalar output) and an empty progressive call
+    w, z, t = batch
+    widths = [z.shape[1], 1]
+    theta = _theta(widths, 12, z)
+    net = ds.NetMLP(ctx, w.K, [1])
+    try:
+        net.set_params(theta)
+        loss, grad = ds.ds_loss_grad(net.h, _cuda(z), _cuda(t), net.n_params)
+        lref, gref = O.mlp_loss_grad(theta.astype(np.float64), widths,
+                                     z.astype(np.float32).astype(np.float64),
+                                     t.astype(np.float32).astype(np.float64))
+        assert loss.item() == pytest.approx(lref, rel=1e-5)
+        assert rel_l2(grad.cpu().numpy(), gref) < 1e-5
+    finally:
+        net.close()

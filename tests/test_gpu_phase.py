@@ -126,3 +126,29 @@ def test_render_mc_with_lorenz_mie_matches_oracle(ctx, small_cloud, small, lm, o
     m, v = m.cpu().numpy(), v.cpu().numpy()
     assert _agree(m, v, mo, vo).size == 0
     assert np.median(np.abs(m - mo) / np.maximum(np.abs(mo), 1e-6)) < 1e-3
+
+
+def test_three_node_table_and_empty_calls(ctx, small_cloud, small):
+    # the smallest table (the trapezoid rule on p sin(theta) needs an inner node): p linear
+    # in theta between forward, sideways and backward values
+    with pytest.raises(ds.DSError):
+        ds.Phase(ctx, [0.3, 0.1])
+    ph = ds.Phase(ctx, [0.3, 0.2, 0.1])
+    try:
+        theta = np.array([0.0, np.pi / 2, np.pi])
+        t = O.phase_table([0.3, 0.2, 0.1])
+        assert ph.mean_cos == pytest.approx(t["g"], rel=1e-12)
+        O.set_phase(t)
+        prm = ds.TracerParams(0.9, 0.0, 1.0, 0, 0, phase=ph)
+        pos, view, light = small.cuda_inputs()
+        m, v = ds.ds_trace_li(ctx.h, small_cloud.h, prm, pos, view, light, 32, 5)
+        mo, vo = O.trace_li(small.grid, small.pos, small.view, small.light, albedo=0.9, g=0.0,
+                            spp=32, seed=5)
+        assert _agree(m.cpu().numpy(), v.cpu().numpy(), mo, vo).size == 0
+        e = torch.zeros((0, 3), dtype=torch.float32, device="cuda")
+        m0, _ = ds.ds_trace_li(ctx.h, small_cloud.h, prm, e, e, e, 8, 1)
+        assert m0.numel() == 0
+        assert theta.size == 3
+    finally:
+        O.set_phase(None)
+        ph.close()

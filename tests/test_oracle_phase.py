@@ -107,6 +107,6 @@ def test_library_phase_table_matches_oracle(chop):
     np.testing.assert_allclose(c, t["cdf"], rtol=1e-12, atol=1e-15)
     assert rem == pytest.approx(t["removed"], rel=1e-10, abs=1e-15)
     assert g == pytest.approx(t["g"], rel=1e-12)
-    for bad in ([1.0], [1.0, -1.0], [np.nan, 1.0]):
+    for bad in ([1.0], [1.0, 2.0], [1.0, -1.0, 1.0], [np.nan, 1.0, 1.0]):
         with pytest.raises(ds.DSError):
             ds.ds_phase_build(bad)
