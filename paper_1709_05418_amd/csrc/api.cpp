@@ -430,7 +430,7 @@ static ds_status mlp_loss_grad(ds_net *net, const float *z, const float *target,
     p += 2 * (size_t)B;
     float *sp = p;
     auto mm = [&](const StridedGemm &g) {
-        return bf ? gemm_bf16(s, g, sp, split) : gemm_strided(s, g);
+        return bf ? gemm_bf16(s, g, sp, split) : gemm_strided(s, g, sp, split);
     };
     const float *th = net->theta;
     // forward
@@ -486,7 +486,8 @@ ds_status loss_grad(ds_net *net, const float *z, const float *target, int B, flo
     TrainWs w;
     DS_TRY(train_ws(net, B, w));
     auto mm = [&](const StridedGemm &g) {
-        return bf ? gemm_bf16(s, g, w.split, w.split_floats) : gemm_strided(s, g);
+        return bf ? gemm_bf16(s, g, w.split, w.split_floats)
+                  : gemm_strided(s, g, w.split, w.split_floats);
     };
     const size_t BW = (size_t)B * W;
     auto H = [&](int k) { return w.H + k * BW; };

@@ -188,7 +188,10 @@ struct StridedGemm {
     float *C; int64_t ldc;
     int accumulate;
 };
-ds_status gemm_strided(hipStream_t s, const StridedGemm &g);
+// FP32 on the vector units; split_ws (ws_floats floats, may be NULL) enables
+// deterministic split-K for products with few output tiles
+ds_status gemm_strided(hipStream_t s, const StridedGemm &g, float *split_ws = nullptr,
+                       size_t ws_floats = 0);
 // same product with operands rounded to BF16 and FP32 accumulation on the matrix
 // cores; split_ws (ws_floats floats, may be NULL) enables deterministic split-K
 ds_status gemm_bf16(hipStream_t s, const StridedGemm &g, float *split_ws, size_t ws_floats);

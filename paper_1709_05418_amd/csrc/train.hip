@@ -7,34 +7,83 @@
 namespace ds {
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int BM = 64, BN = 64, BK = 32;
+constexpr int NF = BK / 4;  // elements of each operand a thread stages per k step
+
+// One operand's share of a k step of the FP32 GEMM: NF values of one row (m of A, n of B)
+// at k = k0 + kq + j with unit k stride (kc), else at k = k0 + kq + 4 j, zero outside.
+struct StageF {
+    const float *p;   // element (row, kbeg + kq)
+    int64_t sk;
+    int kbeg, kq, row;
+    bool kc, ok;
+
+    __device__ __forceinline__ void load(int k0, int kend, float (&v)[NF]) const
+    {
+        const float *q = p + (int64_t)(k0 - kbeg) * sk;
+        if (kc) {
+#pragma unroll
+            for (int j = 0; j < NF; ++j)
+                v[j] = ok && k0 + kq + j < kend ? q[j] : 0.f;
+        } else {
+#pragma unroll
+            for (int j = 0; j < NF; ++j)
+                v[j] = ok && k0 + kq + 4 * j < kend ? q[(int64_t)4 * j * sk] : 0.f;
+        }
+    }
+    // stored k-major: T[k][row]
+    __device__ __forceinline__ void store(float (*T)[BM + 4], const float (&v)[NF]) const
+    {
+#pragma unroll
+        for (int j = 0; j < NF; ++j)
+            T[kc ? kq + j : kq + 4 * j][row] = v[j];
+    }
+};
+
+__device__ __forceinline__ StageF stage_f(const float *base, int64_t s_row, int64_t s_k, int row0,
+                                          int rows, int kbeg, int tid)
+{
+    StageF st;
+    st.kc = s_k == 1;
+    st.row = st.kc ? tid >> 2 : tid & 63;
+    st.kq = st.kc ? NF * (tid & 3) : tid >> 6;
+    st.ok = row0 + st.row < rows;
+    st.sk = s_k;
+    st.kbeg = kbeg;
+    st.p = base + (int64_t)(st.ok ? row0 + st.row : 0) * s_row + (int64_t)(kbeg + st.kq) * s_k;
+    return st;
+}
 
 // C[m][n] (+)= sum_k A(m, k) B(k, n) with A(m, k) = A[m sam + k sak] and
-// B(k, n) = B[k sbk + n sbn]; each output element sums over k in order.
-__global__ void __launch_bounds__(256) k_gemm_strided(StridedGemm g)
+// B(k, n) = B[k sbk + n sbn], in FP32 on the vector units: a 64 x 64 tile per block,
+// 4 x 4 outputs per thread.  Operands are read along their contiguous index and the
+// next k step is prefetched into registers.  Split s (blockIdx.z) covers k in
+// [s kc, (s+1) kc) in order; several splits write partial tiles to P[s][M][N], which
+// k_splitk_sum adds in split order, so every result is reproducible.
+__global__ void __launch_bounds__(256) k_gemm_strided(StridedGemm g, int kc, float *P)
 {
     __shared__ float As[BK][BM + 4];
     __shared__ float Bs[BK][BN + 4];
     const int t = threadIdx.x, tx = t % 16, ty = t / 16;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int kbeg = blockIdx.z * kc;
+    const int kend = min(g.K, kbeg + kc);
+    const StageF sa = stage_f(g.A, g.sam, g.sak, m0, g.M, kbeg, t);
+    const StageF sb = stage_f(g.B, g.sbn, g.sbk, n0, g.N, kbeg, t);
     float acc[4][4] = {};
-    for (int k0 = 0; k0 < g.K; k0 += BK) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = t + q * 256;
-            const int r = e % BM, kk = e / BM;  // consecutive threads walk m (or n)
-            const int k = k0 + kk;
-            float av = 0.f, bv = 0.f;
-            if (k < g.K) {
-                if (m0 + r < g.M)
-                    av = g.A[(int64_t)(m0 + r) * g.sam + (int64_t)k * g.sak];
-                if (n0 + r < g.N)
-                    bv = g.B[(int64_t)k * g.sbk + (int64_t)(n0 + r) * g.sbn];
-            }
-            As[kk][r] = av;
-            Bs[kk][r] = bv;
-        }
+    float va[NF], vb[NF];
+    if (kbeg < kend) {
+        sa.load(kbeg, kend, va);
+        sb.load(kbeg, kend, vb);
+    }
+    for (int k0 = kbeg; k0 < kend; k0 += BK) {
+        sa.store(As, va);
+        sb.store(Bs, vb);
         __syncthreads();
+        if (k0 + BK < kend) {
+            sa.load(k0 + BK, kend, va);
+            sb.load(k0 + BK, kend, vb);
+        }
 #pragma unroll
         for (int kk = 0; kk < BK; ++kk) {
             float a[4], b[4];
@@ -61,8 +110,12 @@ __global__ void __launch_bounds__(256) k_gemm_strided(StridedGemm g)
             const int n = n0 + tx * 4 + j;
             if (n >= g.N)
                 continue;
-            float *c = g.C + (int64_t)m * g.ldc + n;
-            *c = g.accumulate ? *c + acc[i][j] : acc[i][j];
+            if (P) {
+                P[((int64_t)blockIdx.z * g.M + m) * g.N + n] = acc[i][j];
+            } else {
+                float *c = g.C + (int64_t)m * g.ldc + n;
+                *c = g.accumulate ? *c + acc[i][j] : acc[i][j];
+            }
         }
     }
 }
@@ -380,12 +433,22 @@ int grid1(int64_t n)
 
 }  // namespace
 
-ds_status gemm_strided(hipStream_t s, const StridedGemm &g)
+ds_status gemm_strided(hipStream_t s, const StridedGemm &g, float *split_ws, size_t ws_floats)
 {
     if (g.M <= 0 || g.N <= 0)
         return DS_OK;
-    dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM);
-    k_gemm_strided<<<grid, 256, 0, s>>>(g);
+    const int64_t tiles = (int64_t)((g.N + BN - 1) / BN) * ((g.M + BM - 1) / BM);
+    const int ksteps = (g.K + BK - 1) / BK;
+    int S = 1;
+    if (split_ws && tiles < 64)  // few output tiles: split k, at least four k steps each
+        while (S < 16 && tiles * S < 256 && ksteps >= 8 * S)
+            S *= 2;
+    const bool split = S > 1 && (size_t)S * g.M * g.N <= ws_floats;
+    const int kc = split ? ((ksteps + S - 1) / S) * BK : ksteps * BK;
+    dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, split ? S : 1);
+    k_gemm_strided<<<grid, 256, 0, s>>>(g, kc, split ? split_ws : nullptr);
+    if (split)
+        k_splitk_sum<<<grid1((int64_t)g.M * g.N), 256, 0, s>>>(split_ws, S, g);
     DS_HIP(hipGetLastError());
     return DS_OK;
 }

@@ -169,7 +169,10 @@ def test_bf16_training_steps_reduce_loss_and_run_faster(ctx):
         net.set_params(synth.init_params(K, W, 3, 4, branch_scale=1 / np.sqrt(K), out_scale=0.01,
                                          out_bias=float(np.expm1(t).mean())))
         ds.ds_net_set_train_precision(net.h, prec)
-        opt = ds.ds_adam_create(net.h, 1e-3)
+        # lr 1e-4: at 1e-3 this problem is chaotic after its first steps (the trajectory,
+        # and whether it leaves the initial plateau within 150 steps, turns on rounding
+        # order); at 1e-4 every GEMM variant and both precisions follow the same curve
+        opt = ds.ds_adam_create(net.h, 1e-4)
         losses = torch.zeros(150, device="cuda")
         ds.ds_train_step(net.h, opt, zt, tt, loss=losses[0:1])
         torch.cuda.synchronize()
@@ -181,7 +184,7 @@ def test_bf16_training_steps_reduce_loss_and_run_faster(ctx):
         rates[prec] = 149 / (time.perf_counter() - t0)
         l = losses.cpu().numpy()
         print(f"precision {prec}: loss {l[0]:.5f} -> {l[-1]:.5f}, {rates[prec]:.1f} steps/s")
-        assert l[-1] < 0.75 * l[0]
+        assert l[-1] < 0.05 * l[0]
         ds.ds_adam_destroy(opt)
         net.close()
     assert rates[ds.DS_PREC_BF16] > rates[ds.DS_PREC_F32]
