@@ -260,19 +260,28 @@ __device__ __forceinline__ float tab_sample(const float *p, const float *cdf, in
 }
 
 // Phase function of the medium: the table when one is set (first: the first-collision
-// table of camera rays, else the scattering table), else Henyey-Greenstein.
+// table of camera rays, else the scattering table), else Henyey-Greenstein.  TAB (any
+// table set) is a compile-time choice, so the kernels without tables keep the registers
+// (and the occupancy) of the plain Henyey-Greenstein code.
+template <bool TAB>
 __device__ __forceinline__ float phase_eval(const TracerParams &tp, bool first, float mu)
 {
-    if (first && tp.pf_n)
-        return tab_eval(tp.pf_p, tp.pf_n, mu);
-    if (tp.ph_n)
-        return tab_eval(tp.ph_p, tp.ph_n, mu);
+    if constexpr (TAB) {
+        if (first && tp.pf_n)
+            return tab_eval(tp.pf_p, tp.pf_n, mu);
+        if (tp.ph_n)
+            return tab_eval(tp.ph_p, tp.ph_n, mu);
+    }
     return hg(tp.g, mu);
 }
 
-__device__ __forceinline__ float phase_sample(const TracerParams &tp, float u)
+template <bool TAB> __device__ __forceinline__ float phase_sample(const TracerParams &tp, float u)
 {
-    return tp.ph_n ? tab_sample(tp.ph_p, tp.ph_cdf, tp.ph_n, u) : hg_cos(tp.g, u);
+    if constexpr (TAB) {
+        if (tp.ph_n)
+            return tab_sample(tp.ph_p, tp.ph_cdf, tp.ph_n, u);
+    }
+    return hg_cos(tp.g, u);
 }
 
 __device__ V3 around(V3 w, float c, float u)
@@ -292,6 +301,7 @@ __device__ V3 around(V3 w, float c, float u)
 // (directional light: next-event estimation at every collision; uniform
 // environment: the radiance of escaping paths after at least one collision, or
 // any escape when count_uncollided).
+template <bool TAB, bool SET>
 __device__ float li_path(const Medium &M, const TracerParams &tp, V3 x, V3 w, V3 wl,
                          bool count_uncollided, Rng &r)
 {
@@ -301,7 +311,7 @@ __device__ float li_path(const Medium &M, const TracerParams &tp, V3 x, V3 w, V3
     for (int j = 1;; ++j) {
         if ((tp.max_interactions > 0 && j > tp.max_interactions) || steps >= kMaxSteps)
             break;
-        const float c = phase_sample(tp, r.u());
+        const float c = phase_sample<TAB>(tp, r.u());
         const V3 wh = around(wprev, c, r.u());
         V3 xn;
         if (!delta_track(M, p, neg(wh), r, xn, steps)) {
@@ -312,12 +322,13 @@ __device__ float li_path(const Medium &M, const TracerParams &tp, V3 x, V3 w, V3
         p = xn;
         if (r.u() >= tp.albedo)
             break;
-        if (tp.light_mode == 0) {
-            sum += phase_eval(tp, false, -dot(wh, wl)) * ratio_track(M, p, wl, r, steps) * tp.irradiance;
-        } else if (tp.light_mode == kLightSetMode) {
+        if constexpr (SET) {
             const float4 lw = tp.set_dw[set_pick(tp, r)];
             const V3 lj = v3(lw.x, lw.y, lw.z);
-            sum += lw.w * phase_eval(tp, false, -dot(wh, lj)) * ratio_track(M, p, lj, r, steps) *
+            sum += lw.w * phase_eval<TAB>(tp, false, -dot(wh, lj)) *
+                   ratio_track(M, p, lj, r, steps) * tp.irradiance;
+        } else if (tp.light_mode == 0) {
+            sum += phase_eval<TAB>(tp, false, -dot(wh, wl)) * ratio_track(M, p, wl, r, steps) *
                    tp.irradiance;
         }
         wprev = wh;
@@ -357,18 +368,23 @@ __device__ void segment_sums(double s1, double s2, int seg, bool write, double *
 // One record estimate: L_i, or with tp.include_direct all in-scattered radiance L_s =
 // L_d + L_i (directional light: the direct term by ratio tracking, drawn before the path;
 // uniform environment: uncollided light counted too).
+template <bool TAB, bool DIRECT>
 __device__ float record_path(const Medium &M, const TracerParams &tp, V3 x, V3 w, V3 wl, Rng &r)
 {
-    if (!tp.include_direct)
-        return li_path(M, tp, x, w, wl, false, r);
-    if (tp.light_mode == 1)
-        return li_path(M, tp, x, w, wl, true, r);
-    int64_t steps = 0;
-    const float d = phase_eval(tp, false, -dot(w, wl)) * ratio_track(M, x, wl, r, steps) * tp.irradiance;
-    return d + li_path(M, tp, x, w, wl, false, r);
+    if constexpr (!DIRECT) {
+        return li_path<TAB, false>(M, tp, x, w, wl, false, r);
+    } else {
+        if (tp.light_mode == 1)
+            return li_path<TAB, false>(M, tp, x, w, wl, true, r);
+        int64_t steps = 0;
+        const float d =
+            phase_eval<TAB>(tp, false, -dot(w, wl)) * ratio_track(M, x, wl, r, steps) * tp.irradiance;
+        return d + li_path<TAB, false>(M, tp, x, w, wl, false, r);
+    }
 }
 
 // Paths s0 .. s0 + spp - 1 of every record (path s on stream id rec * 2^20 + s).
+template <bool TAB, bool DIRECT>
 __global__ void __launch_bounds__(kPaths) k_trace_li(Medium M, TracerParams tp, const float *pos,
                                                      const float *view, const float *light,
                                                      int64_t P, int s0, int spp, Split sp,
@@ -386,7 +402,7 @@ __global__ void __launch_bounds__(kPaths) k_trace_li(Medium M, TracerParams tp, 
         const V3 x = v3(pos[3 * rec], pos[3 * rec + 1], pos[3 * rec + 2]);
         Rng r;
         r.init(seed, ((uint64_t)rec << 20) + (uint64_t)(s0 + s));
-        e = (double)record_path(M, tp, x, w, wl, r);
+        e = (double)record_path<TAB, DIRECT>(M, tp, x, w, wl, r);
     }
     segment_sums(e, e * e, sp.seg, rec < P, partial + 2 * ((size_t)rec * sp.nblk + blk));
 }
@@ -520,6 +536,7 @@ __global__ void __launch_bounds__(256) k_sample_records(Medium M, int64_t N, uin
 // Path-traced pixels: first collision along each camera ray, then albedo times the
 // in-scattered radiance there (direct by next-event estimation plus the indirect
 // path estimate for a directional light; all in-scattered environment light in mode 1).
+template <bool TAB, bool SET>
 __global__ void __launch_bounds__(kPaths) k_render_mc(Medium M, TracerParams tp, V3 wl,
                                                       const float *ray_o, const float *ray_d,
                                                       int64_t N, int spp, Split sp, uint64_t seed,
@@ -541,19 +558,20 @@ __global__ void __launch_bounds__(kPaths) k_render_mc(Medium M, TracerParams tp,
             e = tp.light_mode == 1 ? tp.irradiance : 0.0;
         } else {
             const V3 w = neg(d);
-            if (tp.light_mode == 0) {
-                const float direct = phase_eval(tp, true, -dot(w, wl)) *
-                                     ratio_track(M, x, wl, r, steps) * tp.irradiance;
-                e = (double)tp.albedo * (double)(direct + li_path(M, tp, x, w, wl, false, r));
-            } else if (tp.light_mode == kLightSetMode) {
+            if constexpr (SET) {
                 const float4 lw = tp.set_dw[set_pick(tp, r)];
                 const V3 lj = v3(lw.x, lw.y, lw.z);
-                const float direct =
-                    lw.w * phase_eval(tp, true, -dot(w, lj)) * ratio_track(M, x, lj, r, steps) *
-                    tp.irradiance;
-                e = (double)tp.albedo * (double)(direct + li_path(M, tp, x, w, wl, false, r));
+                const float direct = lw.w * phase_eval<TAB>(tp, true, -dot(w, lj)) *
+                                     ratio_track(M, x, lj, r, steps) * tp.irradiance;
+                e = (double)tp.albedo *
+                    (double)(direct + li_path<TAB, true>(M, tp, x, w, wl, false, r));
+            } else if (tp.light_mode == 0) {
+                const float direct = phase_eval<TAB>(tp, true, -dot(w, wl)) *
+                                     ratio_track(M, x, wl, r, steps) * tp.irradiance;
+                e = (double)tp.albedo *
+                    (double)(direct + li_path<TAB, false>(M, tp, x, w, wl, false, r));
             } else {
-                e = (double)tp.albedo * (double)li_path(M, tp, x, w, wl, true, r);
+                e = (double)tp.albedo * (double)li_path<TAB, false>(M, tp, x, w, wl, true, r);
             }
         }
     }
@@ -584,7 +602,7 @@ __global__ void __launch_bounds__(256) k_first_hits(Medium M, TracerParams tp, V
         int64_t steps = 0;
         h = delta_track(M, o, d, r, x, steps);
         if (h)
-            dir = tp.albedo * phase_eval(tp, true, dot(d, wl)) * ratio_track(M, x, wl, r, steps) *
+            dir = tp.albedo * phase_eval<true>(tp, true, dot(d, wl)) * ratio_track(M, x, wl, r, steps) *
                   tp.irradiance;
     }
     pos[3 * i] = x.x;
@@ -628,7 +646,7 @@ __global__ void __launch_bounds__(256) k_first_hits_set(Medium M, TracerParams t
         if (h) {
             lw = tp.set_dw[set_pick(tp, r)];
             const V3 lj = v3(lw.x, lw.y, lw.z);
-            sum += lw.w * phase_eval(tp, true, dot(d, lj)) * ratio_track(M, x, lj, r, steps);
+            sum += lw.w * phase_eval<true>(tp, true, dot(d, lj)) * ratio_track(M, x, lj, r, steps);
         }
         pos[3 * row] = x.x;
         pos[3 * row + 1] = x.y;
@@ -856,6 +874,30 @@ ds_status reduce_records(hipStream_t s, const double *partial, int64_t P, int nb
     return DS_OK;
 }
 
+// The specialisation of the path kernels a call needs: tabulated phase functions and
+// L_s records (k_trace_li), tables and light sets (k_render_mc).
+void launch_trace_li(hipStream_t s, const ds_cloud *c, const TracerParams &tp, const float *pos,
+                     const float *view, const float *light, int64_t P, int s0, int spp, Split sp,
+                     uint64_t seed, const uint8_t *mask, uint8_t mask_bits, double *partial)
+{
+    const bool tab = tp.ph_n > 0 || tp.pf_n > 0, dir = tp.include_direct != 0;
+    auto k = tab ? (dir ? k_trace_li<true, true> : k_trace_li<true, false>)
+                 : (dir ? k_trace_li<false, true> : k_trace_li<false, false>);
+    k<<<grid_of(P, sp), kPaths, 0, s>>>(medium(c), tp, pos, view, light, P, s0, spp, sp, seed,
+                                         mask, mask_bits, partial);
+}
+
+void launch_render_mc(hipStream_t s, const ds_cloud *c, const TracerParams &tp, V3 wl,
+                      const float *ray_o, const float *ray_d, int64_t N, int spp, Split sp,
+                      uint64_t seed, double *partial)
+{
+    const bool tab = tp.ph_n > 0 || tp.pf_n > 0, set = tp.light_mode == kLightSetMode;
+    auto k = tab ? (set ? k_render_mc<true, true> : k_render_mc<true, false>)
+                 : (set ? k_render_mc<false, true> : k_render_mc<false, false>);
+    k<<<grid_of(N, sp), kPaths, 0, s>>>(medium(c), tp, wl, ray_o, ray_d, N, spp, sp, seed,
+                                         partial);
+}
+
 }  // namespace
 
 ds_status tracer_prepare(ds_cloud *c, const void *density, ds_dtype dt)
@@ -890,8 +932,7 @@ ds_status tracer_li(hipStream_t s, const ds_cloud *c, const TracerParams &tp, co
 {
     const Split sp = split(spp);
     DS_TRY_MEDIUM(s, c);
-    k_trace_li<<<grid_of(P, sp), kPaths, 0, s>>>(medium(c), tp, pos, view, light, P, 0, spp, sp,
-                                                  seed, mask, mask_bits, partial);
+    launch_trace_li(s, c, tp, pos, view, light, P, 0, spp, sp, seed, mask, mask_bits, partial);
     DS_HIP(hipGetLastError());
     return reduce_records(s, partial, P, sp.nblk, spp, mean, var);
 }
@@ -911,9 +952,8 @@ ds_status tracer_li_adaptive(hipStream_t s, const ds_cloud *c, const TracerParam
     int r = 0;
     for (int n = batch; n <= max_spp; n += batch) {
         ++r;
-        k_trace_li<<<grid_of(P, sp), kPaths, 0, s>>>(medium(c), tp, pos, view, light, P,
-                                                      n - batch, batch, sp, seed, active, 1,
-                                                      partial);
+        launch_trace_li(s, c, tp, pos, view, light, P, n - batch, batch, sp, seed, active, 1,
+                        partial);
         DS_HIP(hipGetLastError());
         unsigned long long h = 0;
         DS_HIP(hipMemsetAsync(left, 0, sizeof(*left), s));
@@ -950,8 +990,7 @@ ds_status tracer_render(hipStream_t s, const ds_cloud *c, const TracerParams &tp
     const V3 wl = v3(l[0], l[1], l[2]);
     const Split sp = split(spp);
     DS_TRY_MEDIUM(s, c);
-    k_render_mc<<<grid_of(N, sp), kPaths, 0, s>>>(medium(c), tp, wl, ray_o, ray_d, N, spp, sp,
-                                                   seed, partial);
+    launch_render_mc(s, c, tp, wl, ray_o, ray_d, N, spp, sp, seed, partial);
     DS_HIP(hipGetLastError());
     return reduce_records(s, partial, N, sp.nblk, spp, mean, var);
 }
