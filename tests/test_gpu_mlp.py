@@ -177,3 +177,50 @@ def test_single_layer_mlp_and_adaptive_empty(ctx, batch):
         assert rel_l2(grad.cpu().numpy(), gref) < 1e-5
     finally:
         net.close()
+
+
+def test_render_with_an_mlp_matches_oracle_composition(ctx):
+    # the network renderer with an all-at-once MLP (FP32 plain form): direct + albedo E g
+    w = Workload(32, 32.0, L=5, K=5, P=8, seed_cloud=4, seed_pts=21)
+    cloud = ds.Cloud(ctx, w.density.cuda(), w.sigma_max, w.aabb_min, w.h0, w.L, w.K, w.mips)
+    D = 225 * w.K + 1
+    widths = [D, 48, 24, 1]
+    theta = _theta(widths, 14)
+    theta[-1] = 0.3
+    net = ds.NetMLP(ctx, w.K, widths[1:])
+    try:
+        net.set_params(theta)
+        rng = np.random.default_rng(8)
+        res = 10
+        px, py = np.meshgrid(np.arange(res), np.arange(res))
+        cam = np.array([0.0, 0.12, 2.3])
+        d = synth.camera_rays(res, cam, (0, 0, 0), 42.0, px.reshape(-1), py.reshape(-1),
+                              rng.random(res * res), rng.random(res * res)).astype(np.float32)
+        o = np.broadcast_to(cam, d.shape).astype(np.float32).copy()
+        ld = synth.table1_lights()["side"]
+        prm = ds.TracerParams(0.9, 0.85, 1.5, 0, 0)
+        img, _, _, _ = ds.ds_render_rpnn(ctx.h, cloud.h, net.h, ds.DS_PREC_F32, prm, ld,
+                                         _cuda(o), _cuda(d), 2, 19, fallback_spp=0)
+        img = img.cpu().numpy()
+        N = o.shape[0]
+        acc = np.zeros(N)
+        same = np.ones(N, bool)
+        pyr, dims, offs = w.pyr
+        for s in range(2):
+            po, vo, do, ho = O.first_hits(w.grid, o, d, ld, albedo=0.9, g=0.85, irradiance=1.5,
+                                          seed=19, sample=s)
+            pg, _, _, hg = (t.cpu().numpy() for t in ds.ds_first_hits(
+                ctx.h, cloud.h, prm, ld, _cuda(o), _cuda(d), seed=19, sample=s))
+            same &= (hg == ho) & (np.linalg.norm(pg - po, axis=1) < 1e-4)
+            li = np.zeros(N)
+            h = ho == 1
+            if h.any():
+                z, _ = O.gather(w.grid, pyr, dims, offs, w.mean, w.K, w.mips, po[h], vo[h],
+                                np.broadcast_to(np.asarray(ld, np.float64), (h.sum(), 3)))
+                li[h], _ = O.mlp_forward(theta.astype(np.float64), widths, z)
+            acc += np.where(h, do + 0.9 * 1.5 * li, 0.0)
+        assert same.mean() > 0.9
+        assert rel_l2(img[same], acc[same] / 2) < 1e-4
+    finally:
+        net.close()
+        cloud.close()
