@@ -173,6 +173,14 @@ __device__ bool clip(const Medium &M, V3 o, V3 d, float &t0, float &t1)
     return hi > lo;
 }
 
+// Exponential free-flight length in units of the mean free path, -ln(1 - u), for u on the
+// 2^-24 grid in [0, 1): 1 - u is exact and at least 2^-24, so the hardware base-2 logarithm
+// (v_log_f32, no denormal inputs here) times ln 2 serves.
+__device__ __forceinline__ float exp_flight(float u)
+{
+    return -__builtin_amdgcn_logf(1.f - u) * 0.693147180559945f;
+}
+
 // Free flight from o along unit d: true and the collision point, false on escape.
 __device__ bool delta_track(const Medium &M, V3 o, V3 d, Rng &r, V3 &x, int64_t &steps)
 {
@@ -183,7 +191,7 @@ __device__ bool delta_track(const Medium &M, V3 o, V3 d, Rng &r, V3 &x, int64_t 
     const float inv = 1.f / M.maj;
     while (steps < kMaxSteps) {
         ++steps;
-        t += -logf(1.f - r.u()) * inv;
+        t += exp_flight(r.u()) * inv;
         if (t >= t1)
             return false;
         const V3 p = madd(o, t, d);
@@ -205,7 +213,7 @@ __device__ float ratio_track(const Medium &M, V3 o, V3 d, Rng &r, int64_t &steps
     const float inv = 1.f / M.maj;
     while (steps < kMaxSteps) {
         ++steps;
-        t += -logf(1.f - r.u()) * inv;
+        t += exp_flight(r.u()) * inv;
         if (t >= t1)
             break;
         T *= 1.f - mu_at(M, madd(o, t, d)) * inv;
