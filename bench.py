@@ -46,8 +46,7 @@ WORKLOADS = {
 
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-FUSED_KERNEL = "k_fused_reg<13,4>"
-TRAFFIC_FILE = os.path.join(HERE, "profiles", "k_fused_reg_bf16_512cube_1M_points_hbm_traffic.txt")
+PROFILES = os.path.join(HERE, "profiles")
 KERNEL_SOURCES = ["fused.hip", "frame.h", "internal.h"]
 
 
@@ -60,22 +59,27 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the fused kernel from the committed counter summary,
-    or None when the kernel sources changed since the counters were taken."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    vals = {}
-    for ln in open(TRAFFIC_FILE):
-        if ":" in ln and not ln.startswith("#"):
-            k, v = ln.split(":", 1)
-            vals[k.strip()] = v.strip()
-    if vals.get("kernel_sources_sha256") != kernel_sources_sha256():
-        return None
-    try:
-        return int(vals["traffic_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+def measured_traffic(kname):
+    """(HBM bytes per launch, grid) of the fused BF16 kernel instantiation kname (as
+    "k_fused_reg<13,8>") from the committed counter summaries, or (None, "") when none
+    covers it or the kernel sources changed since the counters were taken.  The persistent
+    grid of a launch does not change the kernel's code; each summary states the grid it was
+    taken at, returned beside the bytes."""
+    import glob
+    for f in sorted(glob.glob(os.path.join(PROFILES, "*bf16*_hbm_traffic.txt"))):
+        vals = {}
+        for ln in open(f):
+            if ":" in ln and not ln.startswith("#"):
+                k, v = ln.split(":", 1)
+                vals[k.strip()] = v.strip()
+        k = vals.get("kernel", "").replace(",false>", ">")
+        if k != kname or vals.get("kernel_sources_sha256") != kernel_sources_sha256():
+            continue
+        try:
+            return int(vals["traffic_bytes_per_launch"]), vals.get("grid", "")
+        except (KeyError, ValueError):
+            return None, ""
+    return None, ""
 
 
 def macs_per_point(K, W, H):
@@ -229,6 +233,9 @@ def main():
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 form")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default kernel variant instead of the autotuned one")
+    ap.add_argument("--variant", default=None,
+                    help="time this BF16 kernel variant, 'kind,waves,grid' (as ds_batch_set_config), "
+                         "instead of the autotuned one")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB elementwise copy kernel (counter calibration)")
     args = ap.parse_args()
@@ -307,7 +314,12 @@ def main():
     log(f"bf16 fused, default variant: {ms_default:.3f} ms/step")
     batch = ds.ds_batch_create(ctx.h, net.h, [cloud.h], [0, P])
     tuned = {"kernel": ds.DS_KERNEL_REGISTER, "waves": 4, "grid": 0, "ms": None}
-    if not args.no_autotune:
+    if args.variant:
+        kv, wv, gv = (int(x) for x in args.variant.split(","))
+        ds.ds_batch_set_config(batch, kv, wv, gv)
+        tuned = {"kernel": kv, "waves": wv, "grid": gv, "ms": None}
+        log(f"fixed variant: {tuned}")
+    elif not args.no_autotune:
         tuned = ds.ds_batch_autotune(batch, ds.DS_PREC_BF16, pos, view, light, out, 3)
         log(f"autotuned variant: {tuned}")
     ds.ds_batch_capture(batch, ds.DS_PREC_BF16, pos, view, light, out, None, flags)
@@ -322,11 +334,10 @@ def main():
     mt = next(v for v in (1, 2, 4, 8, 13, 16) if v >= mt)
     kname = {ds.DS_KERNEL_REGISTER: "k_fused_reg", ds.DS_KERNEL_PIPELINED: "k_fused",
              ds.DS_KERNEL_WIDE: "k_fused_wide"}[tuned["kernel"]] + f"<{mt},{tuned['waves']}>"
-    traffic = measured_traffic() if (args.workload == "paper" and kname == FUSED_KERNEL and
-                                     tuned["grid"] == 0) else None
+    traffic, traffic_grid = measured_traffic(kname) if args.workload == "paper" else (None, "")
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
-                "traffic": traffic,
+                "traffic": traffic, "traffic_grid": traffic_grid or None,
                 "kernel": kname + f" grid {tuned['grid'] or 'one workgroup per tile'} "
                                   "(BF16 MFMA, stencil gather fused)",
                 "flop_per_point": 2 * macs_per_point(K, W, H), "points_per_launch": P}
