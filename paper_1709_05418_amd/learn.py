@@ -174,7 +174,10 @@ def judge(ctx, cloud, net, precisions, params, light_dir, ray_o, ray_d, spp, ref
         l1, rmse = image_errors(img, ref)
         l1d, rmsed = image_errors(direct, ref)
         ttuv = t_net * float(var.mean())
-        out[name] = {"rel_l1": l1, "rmse": rmse, "rel_l1_direct_only": l1d,
+        # brightness bias of the network image: its sum over the reference's sum
+        ratio = float(img.double().sum() / ref.sum().clamp_min(1e-300))
+        out[name] = {"rel_l1": l1, "rmse": rmse, "mean_ratio": ratio,
+                     "rel_l1_direct_only": l1d,
                      "rmse_direct_only": rmsed, "ref_noise_rel": noise, "fallback_samples": nfb,
                      "seconds_network": t_net, "seconds_reference": t_ref,
                      "ttuv_network": ttuv, "ttuv_reference": ttuv_ref,
@@ -189,7 +192,7 @@ def quantize_on(ctx, net, cloud, n=65536, seed=77):
     ds.ds_net_quantize(ctx.h, net.h, cloud.h, ds.DS_PREC_FP8, pos, view, light)
 
 
-JUDGE_KEYS = ("rel_l1", "rmse", "rel_l1_direct_only", "rmse_direct_only", "ref_noise_rel",
+JUDGE_KEYS = ("rel_l1", "rmse", "mean_ratio", "rel_l1_direct_only", "rmse_direct_only", "ref_noise_rel",
               "seconds_network", "seconds_reference", "fallback_samples", "ttuv_network",
               "ttuv_reference", "ttuv_speedup")
 
@@ -232,6 +235,16 @@ def judge_sun_sky(args, ctx, cloud, net, prm, precs, log):
             f"{j['seconds_network']:.2f}s vs reference {j['seconds_reference']:.2f}s; TTUV "
             f"speedup {j['ttuv_speedup']:.1f}x")
     return out
+
+
+def judge_density(args, dev="cuda"):
+    """The held-out judge scene: a seeded cloud, or the sphere-and-box scene that tests the
+    network on shapes unlike its training clouds."""
+    import torch
+    if args.judge_scene == "spherebox":
+        return synth.sphere_box_density(args.judge_n, device=dev, dtype=torch.bfloat16)
+    return synth.cloud_density(args.judge_n, args.seed + 5000, worley=0.3, device=dev,
+                               dtype=torch.bfloat16)
 
 
 def _close(args, ctx):
@@ -321,6 +334,8 @@ def main(argv=None):
                          "unchopped for the first collision's direct term (Sec. 5.1)")
     ap.add_argument("--chop-deg", type=float, default=5.0)
     ap.add_argument("--no-judge", action="store_true", help="stop after training")
+    ap.add_argument("--judge-scene", default="cloud", choices=["cloud", "spherebox"],
+                    help="held-out judge scene: a seeded cloud, or a homogeneous sphere and box")
     ap.add_argument("--compare", action="store_true",
                     help="train the RPNN and the two all-at-once MLPs of Sec. 7 (23 x 200 and "
                          "[400, 400, 200, 200, 200]) on the same pairs and judge each in FP32")
@@ -430,8 +445,7 @@ def main(argv=None):
         _close(args, ctx)
         return
     # held-out cloud, larger grid, same optical size in mean free paths per unit
-    d = synth.cloud_density(args.judge_n, args.seed + 5000, worley=0.3, device=dev,
-                            dtype=torch.bfloat16)
+    d = judge_density(args, dev)
     amin, h0 = synth.unit_box(args.judge_n)
     Lj = min(16, int(math.ceil(math.log2(args.judge_n))) + 1)
     jc = ds.Cloud(ctx, d, args.sigma(args.n), amin, h0, Lj, K)
@@ -461,7 +475,8 @@ def main(argv=None):
     for name, j in js.items():
         for k in JUDGE_KEYS:
             summary[f"crop_{k}_{name}"] = j[k]
-        log(f"crop {args.crop}^2 {name}: rel L1 {j['rel_l1']:.4f} (direct only "
+        log(f"crop {args.crop}^2 {name}: rel L1 {j['rel_l1']:.4f}, mean ratio "
+            f"{j['mean_ratio']:.3f} (direct only "
             f"{j['rel_l1_direct_only']:.4f}), RMSE {j['rmse']:.5f}; reference noise "
             f"{j['ref_noise_rel']:.4f}; network {j['seconds_network']:.2f}s vs reference "
             f"{j['seconds_reference']:.2f}s; TTUV speedup {j['ttuv_speedup']:.0f}x")
@@ -470,7 +485,7 @@ def main(argv=None):
     summary.update(base)
     summary.update({"judge_n": args.judge_n, "frame": [args.width, args.height],
                     "crop": args.crop, "crop_spp": args.crop_spp, "ref_spp": args.ref_spp,
-                    "light": args.light, "phase": args.phase})
+                    "light": args.light, "phase": args.phase, "judge_scene": args.judge_scene})
     print(json.dumps(summary), flush=True)
     ds.ds_adam_destroy(opt)
     net.close()
@@ -518,8 +533,7 @@ def compare_architectures(args, ctx, prm, z, t, mean_li, log, data):
     del z, t
     torch.cuda.empty_cache()
     if not args.no_judge:
-        d = synth.cloud_density(args.judge_n, args.seed + 5000, worley=0.3, device="cuda",
-                                dtype=torch.bfloat16)
+        d = judge_density(args)
         amin, h0 = synth.unit_box(args.judge_n)
         Lj = min(16, int(math.ceil(math.log2(args.judge_n))) + 1)
         jc = ds.Cloud(ctx, d, args.sigma(args.n), amin, h0, Lj, K)
@@ -553,8 +567,7 @@ def judge_only(args, ctx, net, prm, log):
     import torch
     K = net.K
     t0 = time.time()
-    d = synth.cloud_density(args.judge_n, args.seed + 5000, worley=0.3, device="cuda",
-                            dtype=torch.bfloat16)
+    d = judge_density(args)
     amin, h0 = synth.unit_box(args.judge_n)
     Lj = min(16, int(math.ceil(math.log2(args.judge_n))) + 1)
     jc = ds.Cloud(ctx, d, args.sigma(args.n), amin, h0, Lj, K)
@@ -585,7 +598,8 @@ def judge_only(args, ctx, net, prm, log):
     for name, j in js.items():
         for k in JUDGE_KEYS:
             summary[f"crop_{k}_{name}"] = j[k]
-        log(f"crop {args.crop}^2 {name}: rel L1 {j['rel_l1']:.4f} (direct only "
+        log(f"crop {args.crop}^2 {name}: rel L1 {j['rel_l1']:.4f}, mean ratio "
+            f"{j['mean_ratio']:.3f} (direct only "
             f"{j['rel_l1_direct_only']:.4f}), RMSE {j['rmse']:.5f}; reference noise "
             f"{j['ref_noise_rel']:.4f}; network {j['seconds_network']:.2f}s vs reference "
             f"{j['seconds_reference']:.2f}s ({args.ref_spp} spp); TTUV speedup "
