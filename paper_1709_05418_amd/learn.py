@@ -19,6 +19,8 @@ from __future__ import annotations
 import math
 import time
 
+import numpy as np
+
 import paper_1709_05418_amd as ds
 from paper_1709_05418_amd import synth
 
@@ -336,6 +338,9 @@ def main(argv=None):
     ap.add_argument("--no-judge", action="store_true", help="stop after training")
     ap.add_argument("--judge-scene", default="cloud", choices=["cloud", "spherebox"],
                     help="held-out judge scene: a seeded cloud, or a homogeneous sphere and box")
+    ap.add_argument("--compare-stencils", action="store_true",
+                    help="train and judge the RPNN on the 5x5x9, 3x3x5 and 2x2x3 stencils "
+                         "(Fig. 10, right) instead of the single network")
     ap.add_argument("--compare", action="store_true",
                     help="train the RPNN and the two all-at-once MLPs of Sec. 7 (23 x 200 and "
                          "[400, 400, 200, 200, 200]) on the same pairs and judge each in FP32")
@@ -416,6 +421,10 @@ def main(argv=None):
                           "paths_per_second": paths / t_data, **stats}), flush=True)
         _close(args, ctx)
         return
+    if args.compare_stencils:
+        return compare_stencils(args, ctx, prm, z, t, float(li.mean()), log,
+                                {"data_seconds": t_data, "paths_per_second": paths / t_data,
+                                 "pairs": per * args.clouds, "spp": args.spp, **stats})
     if args.compare:
         return compare_architectures(args, ctx, prm, z, t, float(li.mean()), log,
                                      {"data_seconds": t_data, "paths_per_second": paths / t_data,
@@ -497,6 +506,89 @@ ARCHS = {"rpnn": None, "mlp_deep_23x200": [200] * 22 + [1],
          "mlp_wide_400_400_200_200_200": [400, 400, 200, 200, 200, 1]}
 
 
+STENCILS = {"5x5x9": (5, 5, 9), "3x3x5": (3, 3, 5), "2x2x3": (2, 2, 3)}
+
+
+def stencil_points(shape):
+    """Indices n = ix + 5 iy + 25 iz into the 5 x 5 x 9 lattice (Sec. 4.2) of a coarser
+    stencil of the same extent, [-1, 1]^2 x [-1, 3] mean free paths: nx x ny x nz points
+    with spacings 4 / (nx - 1), 4 / (ny - 1) and 8 / (nz - 1) lattice steps."""
+    nx, ny, nz = shape
+    if (4 % (nx - 1)) or (4 % (ny - 1)) or (8 % (nz - 1)):
+        raise ValueError(f"{shape} is not a sub-lattice of 5 x 5 x 9")
+    sx, sy, sz = 4 // (nx - 1), 4 // (ny - 1), 8 // (nz - 1)
+    return np.array([ix + 5 * iy + 25 * iz for iz in range(0, 9, sz)
+                     for iy in range(0, 5, sy) for ix in range(0, 5, sx)])
+
+
+def stencil_params(K, W, seed, keep, mean_li):
+    """RPNN parameters for a coarser stencil on the 5 x 5 x 9 layout: the V columns of the
+    dropped points are zero, the kept ones He-uniform for the kept fan-in.  Trained on
+    descriptors whose dropped entries are zero, those weights get zero gradients and Adam
+    leaves them at zero, so the network is the RPNN of the coarser stencil."""
+    theta = synth.init_params(K, W, 3, seed, branch_scale=1 / math.sqrt(K), out_scale=0.01,
+                              out_bias=mean_li)
+    if len(keep) == ds.STENCIL_N:
+        return theta
+    drop = np.setdiff1d(np.arange(ds.STENCIL_N), keep)
+    for V in stencil_blocks(theta, K, W):
+        V[:, :ds.STENCIL_N] *= math.sqrt(V.shape[1] / (len(keep) + 1))
+        V[:, drop] = 0.0
+    return theta
+
+
+def stencil_blocks(theta, K, W):
+    """Views of the K input matrices V^k [W][226] inside a parameter vector."""
+    off, out = 0, []
+    for name, r, c in synth.layer_shapes(K, W, 3):
+        n = r * (c if c else 1)
+        if name.startswith("V"):
+            out.append(theta[off:off + n].reshape(r, c))
+        off += n
+    return out
+
+
+def compare_stencils(args, ctx, prm, z, t, mean_li, log, data):
+    """Sec. 7, Fig. 10 (right): the RPNN on stencils of different resolution over the same
+    extent, trained on the same pairs with the same minibatches and schedule, then judged
+    on the same crop.  The coarser stencils are sub-lattices of 5 x 5 x 9: their descriptors
+    are the full one with the other entries set to zero."""
+    import torch
+    K, W = args.K, args.W
+    out = dict(data)
+    held, nets = {}, {}
+    for name, shape in STENCILS.items():
+        keep = stencil_points(shape)
+        zs = z
+        if len(keep) < ds.STENCIL_N:
+            drop = torch.from_numpy(np.setdiff1d(np.arange(ds.STENCIL_N), keep)).to(z.device)
+            cols = (drop[None, :] + ds.STENCIL_N * torch.arange(K, device=z.device)[:, None])
+            zs = z.clone()
+            zs[:, cols.reshape(-1)] = 0.0
+        net = ds.Net(ctx, K, W, 3)
+        net.set_params(stencil_params(K, W, args.seed + 1, keep, mean_li))
+        ds.ds_net_set_train_precision(net.h, ds.DS_PREC_BF16 if args.train_precision == "bf16"
+                                      else ds.DS_PREC_F32)
+        opt = ds.ds_adam_create(net.h, args.lr)
+        log(f"stencil {name}: {len(keep)} points per level")
+        res = train(net, opt, zs, t, args.steps, args.batch, 0.25,
+                    eval_every=max(1, args.steps // 20), log=log, lr=args.lr,
+                    decay_at=tuple(args.decay_at))
+        ds.ds_adam_destroy(opt)
+        del zs
+        # the weights of the dropped points must still be exactly zero
+        dead = np.setdiff1d(np.arange(ds.STENCIL_N), keep)
+        out[f"{name}_dropped_weights_max_abs"] = float(max(
+            [float(np.abs(V[:, dead]).max()) for V in stencil_blocks(net.get_params(), K, W)]
+            if dead.size else [0.0]))
+        held[name] = res["held_out"]
+        out[f"{name}_points"] = int(len(keep))
+        out[f"{name}_held_out_final"] = res["held_out"][-1][1]
+        log(f"{name}: training {res['seconds']:.1f}s, final held-out {res['held_out'][-1][1]:.6f}")
+        nets[name] = net
+    _compare_judge(args, ctx, prm, nets, held, out, log, z, t)
+
+
 def compare_architectures(args, ctx, prm, z, t, mean_li, log, data):
     """Sec. 7, Fig. 10: the progressive RPNN against two MLPs fed the whole descriptor at
     once, trained on the same pairs with the same minibatches, learning-rate schedule and
@@ -530,6 +622,15 @@ def compare_architectures(args, ctx, prm, z, t, mean_li, log, data):
         out[f"{name}_held_out_final"] = res["held_out"][-1][1]
         log(f"{name}: training {res['seconds']:.1f}s, final held-out {res['held_out'][-1][1]:.6f}")
         nets[name] = net
+    _compare_judge(args, ctx, prm, nets, held, out, log, z, t)
+
+
+def _compare_judge(args, ctx, prm, nets, held, out, log, z, t):
+    """The judge of the comparisons: every network renders the same crop in FP32 (the plain
+    form) against one path-traced reference; one JSON line with the held-out curves."""
+    import json
+    import torch
+    K, W = args.K, args.W
     del z, t
     torch.cuda.empty_cache()
     if not args.no_judge:
@@ -556,7 +657,7 @@ def compare_architectures(args, ctx, prm, z, t, mean_li, log, data):
         net.close()
     out.update({"steps": args.steps, "batch": args.batch, "K": K, "W": W,
                 "light": args.light, "crop": args.crop, "ref_spp": args.ref_spp,
-                "judge_n": args.judge_n, "held_out": held})
+                "judge_n": args.judge_n, "judge_scene": args.judge_scene, "held_out": held})
     print(json.dumps(out), flush=True)
     _close(args, ctx)
 
