@@ -199,15 +199,22 @@ JUDGE_KEYS = ("rel_l1", "rmse", "mean_ratio", "rel_l1_direct_only", "rmse_direct
               "ttuv_reference", "ttuv_speedup")
 
 
-def judge_sun_sky(args, ctx, cloud, net, prm, precs, log):
-    """The crop judged under a synthetic sun and sky (a set of directional lights, Fig. 7):
-    the network renderer drawing args.draws members per camera sample against the path
-    tracer drawing one member per next-event estimate.  Returns summary entries."""
+def judge_sun_sky(args, ctx, cloud, net, prm, precs, log, kind="sunsky"):
+    """The crop judged under a distant emitter given as a set of directional lights (Fig. 7):
+    a synthetic sun and sky (kind "sunsky") or a synthetic HDR environment map with an
+    extended bright lobe (kind "envmap", one light per texel).  The network renderer draws
+    args.draws members per camera sample, the path tracer one member per next-event
+    estimate.  Returns summary entries prefixed with kind."""
     import torch
-    dirs, E = synth.sun_sky_lights(synth.table1_lights()["side"])
+    sun = synth.table1_lights()["side"]
+    if kind == "envmap":
+        dirs, E = synth.envmap_lights(synth.synthetic_envmap(sun))
+    else:
+        dirs, E = synth.sun_sky_lights(sun)
     lights = ds.Lights(ctx, dirs, E)
-    out = {"sunsky_lights": int(E.size), "sunsky_draws": args.draws, "sunsky_crop": args.sky_crop,
-           "sunsky_ref_spp": args.sky_ref_spp}
+    label = "sun-sky" if kind == "sunsky" else "env-map"
+    out = {f"{kind}_lights": int(E.size), f"{kind}_draws": args.draws,
+           f"{kind}_crop": args.sky_crop, f"{kind}_ref_spp": args.sky_ref_spp}
     try:
         o, dd = camera(args.width, args.height, seed=1)
         for name, prec in precs:
@@ -217,9 +224,9 @@ def judge_sun_sky(args, ctx, cloud, net, prm, precs, log):
                                      dd, args.frame_spp, 5, args.fallback_spp, want_var=False,
                                      want_direct=False)
             torch.cuda.synchronize()
-            out[f"sunsky_frame_ms_{name}"] = (time.time() - tf) * 1e3
-            log(f"sun-sky {args.width}x{args.height} frame {name}, {args.frame_spp} spp x "
-                f"{args.draws} lights: {out[f'sunsky_frame_ms_{name}']:.1f} ms")
+            out[f"{kind}_frame_ms_{name}"] = (time.time() - tf) * 1e3
+            log(f"{label} {args.width}x{args.height} frame {name}, {args.frame_spp} spp x "
+                f"{args.draws} lights: {out[f'{kind}_frame_ms_{name}']:.1f} ms")
         del o, dd
         c = args.sky_crop
         co, cd = camera(args.width, args.height,
@@ -230,8 +237,8 @@ def judge_sun_sky(args, ctx, cloud, net, prm, precs, log):
         lights.close()
     for name, j in js.items():
         for k in JUDGE_KEYS:
-            out[f"sunsky_{k}_{name}"] = j[k]
-        log(f"sun-sky crop {c}^2 {name} ({E.size} lights, {args.draws} draws per sample): "
+            out[f"{kind}_{k}_{name}"] = j[k]
+        log(f"{label} crop {c}^2 {name} ({E.size} lights, {args.draws} draws per sample): "
             f"rel L1 {j['rel_l1']:.4f} (direct only {j['rel_l1_direct_only']:.4f}), RMSE "
             f"{j['rmse']:.5f}; reference noise {j['ref_noise_rel']:.4f}; network "
             f"{j['seconds_network']:.2f}s vs reference {j['seconds_reference']:.2f}s; TTUV "
@@ -317,6 +324,9 @@ def main(argv=None):
     ap.add_argument("--seed", type=int, default=1000)
     ap.add_argument("--sun-sky", action="store_true",
                     help="also judge a crop under a synthetic sun and sky light set")
+    ap.add_argument("--envmap", action="store_true",
+                    help="also judge a crop under a synthetic HDR environment map (32 x 64 "
+                         "texels, one directional light each)")
     ap.add_argument("--draws", type=int, default=8, help="light-set members per camera sample")
     ap.add_argument("--sky-crop", type=int, default=128)
     ap.add_argument("--sky-ref-spp", type=int, default=1024)
@@ -491,6 +501,8 @@ def main(argv=None):
             f"{j['seconds_reference']:.2f}s; TTUV speedup {j['ttuv_speedup']:.0f}x")
     if args.sun_sky and args.target == "li":
         summary.update(judge_sun_sky(args, ctx, jc, net, prm, precs, log))
+    if args.envmap and args.target == "li":
+        summary.update(judge_sun_sky(args, ctx, jc, net, prm, precs, log, kind="envmap"))
     summary.update(base)
     summary.update({"judge_n": args.judge_n, "frame": [args.width, args.height],
                     "crop": args.crop, "crop_spp": args.crop_spp, "ref_spp": args.ref_spp,
@@ -707,6 +719,8 @@ def judge_only(args, ctx, net, prm, log):
             f"{j['ttuv_speedup']:.0f}x")
     if args.sun_sky:
         summary.update(judge_sun_sky(args, ctx, jc, net, prm, precs, log))
+    if args.envmap:
+        summary.update(judge_sun_sky(args, ctx, jc, net, prm, precs, log, kind="envmap"))
     summary.update({"judge_n": args.judge_n, "frame": [args.width, args.height],
                     "crop": args.crop, "crop_spp": args.crop_spp, "ref_spp": args.ref_spp,
                     "theta": args.load_theta})

@@ -446,6 +446,50 @@ def sun_sky_lights(sun_dir, sun_irradiance: float = 1.0, sky_radiance: float = 0
     return np.asarray(dirs, np.float32), np.asarray(E, np.float64)
 
 
+def envmap_lights(radiance, min_radiance: float = 0.0):
+    """An environment map as a set of directional lights (Sec. 4.4: a distant emitter of
+    any shape is a set of directions).  radiance is an equirectangular map (H, W): row i
+    covers polar angles [i, i + 1] pi / H from the up axis +y, column j azimuths
+    [j, j + 1] 2 pi / W.  One light per texel at its centre (mid polar angle, mid
+    azimuth), with irradiance radiance times the texel's exact solid angle
+    (cos theta_i - cos theta_{i+1}) 2 pi / W; texels at or below min_radiance are
+    dropped.  Input data only: returns (dirs (m, 3) float32, irradiance (m,) float64)."""
+    L = np.asarray(radiance, np.float64)
+    H, W = L.shape
+    t0 = np.pi * np.arange(H) / H
+    t1 = np.pi * np.arange(1, H + 1) / H
+    dw = (np.cos(t0) - np.cos(t1)) * 2.0 * np.pi / W
+    th = 0.5 * (t0 + t1)
+    ph = 2.0 * np.pi * (np.arange(W) + 0.5) / W
+    st, ct = np.sin(th)[:, None], np.cos(th)[:, None]
+    dirs = np.stack(np.broadcast_arrays(st * np.cos(ph)[None, :], ct, st * np.sin(ph)[None, :]),
+                    -1).reshape(-1, 3)
+    E = (L * dw[:, None]).reshape(-1)
+    keep = L.reshape(-1) > min_radiance
+    return dirs[keep].astype(np.float32), E[keep]
+
+
+def synthetic_envmap(sun_dir, H: int = 32, W: int = 64, lobe_power: float = 1.0,
+                     lobe_width: float = 0.1, sky_radiance: float = 0.08,
+                     ground: float = 0.25) -> np.ndarray:
+    """A synthetic HDR environment map (H, W) in the layout of envmap_lights: a bright
+    lobe around sun_dir, radiance S exp((cos a - 1) / w^2) at angle a with S = lobe_power
+    / (2 pi w^2) (the lobe integrates to lobe_power (1 - exp(-2 / w^2)) over the sphere),
+    over a sky of sky_radiance (0.6 + 0.4 (1 - y)) above the horizon and ground *
+    sky_radiance below it, each evaluated at the texel centre.  Input data only."""
+    s = np.asarray(sun_dir, np.float64)
+    s = s / np.linalg.norm(s)
+    th = np.pi * (np.arange(H) + 0.5) / H
+    ph = 2.0 * np.pi * (np.arange(W) + 0.5) / W
+    x = np.sin(th)[:, None] * np.cos(ph)[None, :]
+    y = np.broadcast_to(np.cos(th)[:, None], (H, W))
+    z = np.sin(th)[:, None] * np.sin(ph)[None, :]
+    cos_a = x * s[0] + y * s[1] + z * s[2]
+    lobe = lobe_power / (2.0 * np.pi * lobe_width ** 2) * np.exp((cos_a - 1.0) / lobe_width ** 2)
+    sky = np.where(y > 0, sky_radiance * (0.6 + 0.4 * (1.0 - y)), ground * sky_radiance)
+    return lobe + sky
+
+
 def init_mlp(widths, seed: int, out_scale: float = 1.0, out_bias: float = 0.0) -> np.ndarray:
     """He-uniform weights and zero biases for an all-at-once MLP (widths: input first,
     output last; per layer W [out][in] then b [out]); out_scale multiplies the last
