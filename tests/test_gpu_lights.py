@@ -244,3 +244,30 @@ def test_light_set_edge_cases(ctx, small_cloud, small):
                                     seed=3)
     finally:
         one.close()
+
+
+def test_environment_map_set_matches_oracle(ctx, small_cloud, small):
+    # 2048 texel lights: a deep selection table (11 levels of the member search), most
+    # members weak and a few in the bright lobe; thresholds bit-exact, pixels statistical
+    dirs, E = synth.envmap_lights(synth.synthetic_envmap(synth.table1_lights()["side"]))
+    assert E.size == 2048
+    thr, w = ds.ds_light_table(E)
+    thr_o, w_o = O.light_table(E)
+    np.testing.assert_array_equal(thr, thr_o)
+    np.testing.assert_array_equal(w, w_o)
+    env = ds.Lights(ctx, dirs, E)
+    try:
+        o, d = _rays(8, 9)
+        spp, seed = 32, 17
+        prm = ds.TracerParams(0.95, 0.85, 1.0, 0, 0)
+        m, v = ds.ds_render_mc_lights(ctx.h, small_cloud.h, prm, env.h, _cuda(o), _cuda(d), spp,
+                                      seed)
+        mo, vo = O.render_pixels_lights(small.grid, o, d, dirs, E, albedo=0.95, g=0.85,
+                                        irradiance=1.0, spp=spp, seed=seed)
+        m, v = m.cpu().numpy(), v.cpu().numpy()
+        tol = 5 * np.sqrt(v + vo) + 1e-7 * max(1.0, np.abs(mo).max())
+        assert np.all(np.abs(m - mo) <= tol)
+        rel = np.abs(m - mo) / np.maximum(np.abs(mo), 1e-6)
+        assert np.median(rel) < 1e-3, np.median(rel)
+    finally:
+        env.close()
