@@ -354,6 +354,10 @@ def main(argv=None):
     ap.add_argument("--compare", action="store_true",
                     help="train the RPNN and the two all-at-once MLPs of Sec. 7 (23 x 200 and "
                          "[400, 400, 200, 200, 200]) on the same pairs and judge each in FP32")
+    ap.add_argument("--caps", type=int, nargs="*", default=None,
+                    help="no network: path-trace the judge crop at --ref-spp with each cap on "
+                         "the scattering events per path (0: none) and report time and image "
+                         "change (Fig. 2)")
     ap.add_argument("--save-theta", default=None)
     ap.add_argument("--load-theta", default=None,
                     help="judge a network saved by --save-theta instead of training one")
@@ -379,6 +383,8 @@ def main(argv=None):
     K, W = args.K, args.W
     L = int(math.ceil(math.log2(args.n))) + 1
     per = args.records // args.clouds
+    if args.caps:
+        return cap_study(args, ctx, prm, log)
     if args.load_theta:
         net = ds.Net(ctx, K, W, 3)
         net.set_params(np.load(args.load_theta))
@@ -671,6 +677,51 @@ def _compare_judge(args, ctx, prm, nets, held, out, log, z, t):
                 "light": args.light, "crop": args.crop, "ref_spp": args.ref_spp,
                 "judge_n": args.judge_n, "judge_scene": args.judge_scene, "held_out": held})
     print(json.dumps(out), flush=True)
+    _close(args, ctx)
+
+
+def cap_study(args, ctx, prm, log):
+    """Fig. 2: path-traced render time and image against a cap on the scattering events of
+    a path (max_interactions, 0 = none), on the centred crop of the judge scene.  Every cap
+    uses the same random streams, so the image differences are the light of the longer
+    paths that the cap removes."""
+    import json
+    import torch
+    d = judge_density(args)
+    amin, h0 = synth.unit_box(args.judge_n)
+    Lj = min(16, int(math.ceil(math.log2(args.judge_n))) + 1)
+    jc = ds.Cloud(ctx, d, args.sigma(args.n), amin, h0, Lj, args.K)
+    del d
+    light = synth.table1_lights()[args.light]
+    c = args.crop
+    co, cd = camera(args.width, args.height,
+                    crop=((args.width - c) // 2, (args.height - c) // 2, c, c), seed=2)
+    out = {"judge_n": args.judge_n, "crop": c, "spp": args.ref_spp, "light": args.light,
+           "albedo": prm.albedo, "caps": args.caps}
+    imgs = {}
+    for cap in args.caps:
+        p = ds.TracerParams(prm.albedo, prm.g, prm.irradiance, prm.light_mode, cap, 0,
+                            prm.phase, prm.phase_first)
+        torch.cuda.synchronize()
+        t0 = time.time()
+        m, v = reference(ctx, jc, p, light, co, cd, args.ref_spp, 11)
+        torch.cuda.synchronize()
+        sec = time.time() - t0
+        imgs[cap] = m
+        out[f"cap_{cap}_seconds"] = sec
+        out[f"cap_{cap}_mean"] = float(m.mean())
+        out[f"cap_{cap}_noise_rel"] = float(math.sqrt(float(v.sum())) / max(float(m.sum()), 1e-300))
+        log(f"cap {cap or 'none'}: {sec:.2f}s for {c}^2 x {args.ref_spp} spp, mean pixel "
+            f"{float(m.mean()):.5f}")
+    full = imgs[0] if 0 in imgs else imgs[max(args.caps)]
+    for cap, m in imgs.items():
+        l1, _ = image_errors(m, full)
+        out[f"cap_{cap}_rel_l1_vs_uncapped"] = l1
+        log(f"cap {cap or 'none'}: rel L1 against the uncapped image {l1:.4f}, time "
+            f"{out[f'cap_{cap}_seconds'] / out[f'cap_{0 if 0 in imgs else max(args.caps)}_seconds']:.3f}"
+            f" of it")
+    print(json.dumps(out), flush=True)
+    jc.close()
     _close(args, ctx)
 
 
