@@ -354,6 +354,9 @@ def main(argv=None):
     ap.add_argument("--compare", action="store_true",
                     help="train the RPNN and the two all-at-once MLPs of Sec. 7 (23 x 200 and "
                          "[400, 400, 200, 200, 200]) on the same pairs and judge each in FP32")
+    ap.add_argument("--spp-study", action="store_true",
+                    help="also render the crop with the network at 1, 2, 4 ... --crop-spp "
+                         "samples per pixel: noise, error and time (Fig. 12)")
     ap.add_argument("--caps", type=int, nargs="*", default=None,
                     help="no network: path-trace the judge crop at --ref-spp with each cap on "
                          "the scattering events per path (0: none) and report time and image "
@@ -505,6 +508,8 @@ def main(argv=None):
             f"{j['rel_l1_direct_only']:.4f}), RMSE {j['rmse']:.5f}; reference noise "
             f"{j['ref_noise_rel']:.4f}; network {j['seconds_network']:.2f}s vs reference "
             f"{j['seconds_reference']:.2f}s; TTUV speedup {j['ttuv_speedup']:.0f}x")
+    if args.spp_study:
+        summary.update(spp_study(args, ctx, jc, net, prm, light, log))
     if args.sun_sky and args.target == "li":
         summary.update(judge_sun_sky(args, ctx, jc, net, prm, precs, log))
     if args.envmap and args.target == "li":
@@ -678,6 +683,35 @@ def _compare_judge(args, ctx, prm, nets, held, out, log, z, t):
                 "judge_n": args.judge_n, "judge_scene": args.judge_scene, "held_out": held})
     print(json.dumps(out), flush=True)
     _close(args, ctx)
+
+
+def spp_study(args, ctx, cloud, net, prm, light, log):
+    """Fig. 12: noise and error of the network renderer against samples per pixel, on the
+    centred crop, BF16: relative noise (sqrt of the summed pixel variances of the mean over
+    the image sum), relative L1 against a path-traced reference, and time per sample per
+    pixel.  Returns summary entries."""
+    import torch
+    c = args.crop
+    co, cd = camera(args.width, args.height,
+                    crop=((args.width - c) // 2, (args.height - c) // 2, c, c), seed=2)
+    ref, _ = reference(ctx, cloud, prm, light, co, cd, args.ref_spp, 11)
+    out = {}
+    spp = 1
+    while spp <= args.crop_spp:
+        torch.cuda.synchronize()
+        t0 = time.time()
+        img, var, _, _ = ds.ds_render_rpnn(ctx.h, cloud.h, net.h, ds.DS_PREC_BF16, prm, light,
+                                           co, cd, spp, 23, args.fallback_spp)
+        torch.cuda.synchronize()
+        sec = time.time() - t0
+        noise = float(math.sqrt(float(var.double().sum())) / max(float(img.double().sum()), 1e-300))
+        l1, _ = image_errors(img, ref)
+        out.update({f"spp_{spp}_noise_rel": noise, f"spp_{spp}_rel_l1": l1,
+                    f"spp_{spp}_seconds": sec})
+        log(f"{spp} spp: noise {noise:.5f}, rel L1 {l1:.4f}, {sec * 1e3:.1f} ms "
+            f"({c}^2 crop, BF16)")
+        spp *= 2
+    return out
 
 
 def cap_study(args, ctx, prm, log):
