@@ -355,7 +355,12 @@ typedef struct ds_tracer_params {
     const ds_phase *phase;       /* NULL: Henyey-Greenstein with g; else this table for
                                     every scattering and next-event estimate             */
     const ds_phase *phase_first; /* NULL: as phase; else the table for the direct term at
-                                    the first collision of camera rays (render calls)    */
+                                    the first collision of camera rays (render calls),
+                                    weighted by (1 - f_first) / (1 - f) with f, f_first the
+                                    fractions the two tables' chops removed (Sec. 5.1: with
+                                    a chopped phase, albedo holds the reduced albedo; a full
+                                    first-collision function needs the unreduced
+                                    scattering, 1 / (1 - f) times it)                    */
 } ds_tracer_params;
 
 /* The cloud's majorant sigma_max * max(d) (host write). */

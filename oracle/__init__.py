@@ -103,7 +103,7 @@ def lib():
                                       P, P]),
             "dso_first_hits": (I, [P, I, I, I, I, D, P, D, D, D, D, P, P, P, I64, U64, U64, P, P,
                                    P, P]),
-            "dso_set_phase": (None, [I, P, P, I, P, P]),
+            "dso_set_phase": (None, [I, P, P, I, P, P, D]),
             "dso_tab_sample": (D, [I, P, P, D]),
             "dso_render_pixels_lights": (I, [P, I, I, I, I, D, P, D, D, D, D, I, I, P, P, P, P, P,
                                              I64, I, U64, P, P]),
@@ -463,8 +463,9 @@ def phase_table(p, chop_deg=0.0):
 
 def set_phase(table=None, first=None):
     """Use `table` (from phase_table) for every scattering and `first` for the direct
-    term at the first collision of camera rays in all later tracer calls; None restores
-    Henyey-Greenstein (first falls back to table)."""
+    term at the first collision of camera rays in all later tracer calls, weighted by
+    (1 - first["removed"]) / (1 - table["removed"]) (a chopped table carries 1 - removed of
+    the scattering); None restores Henyey-Greenstein (first falls back to table)."""
     L = lib()
     keep = []
 
@@ -475,7 +476,11 @@ def set_phase(table=None, first=None):
         keep.extend([a, b])
         return [a.size, _p(a), _p(b)]
 
-    L.dso_set_phase(*args(table), *args(first))
+    # a full first-collision function next to a chopped table weighs the scattering the
+    # chop removed: 1 / (1 - removed)
+    scale = ((1.0 - first.get("removed", 0.0)) / (1.0 - table.get("removed", 0.0))
+             if (table is not None and first is not None) else 1.0)
+    L.dso_set_phase(*args(table), *args(first), float(scale))
 
 
 def tab_sample(table, u):

@@ -916,6 +916,12 @@ typedef struct {
 } phase_tab;
 
 static phase_tab g_phase, g_first;
+/* the first-collision table's weight against a chopped scattering table that removed the
+ * fraction f: 1 / (1 - f) for the full function ((1 - f_first) / (1 - f) in general).  The chop moves f of the scattering into unscattered travel
+ * (extinction times 1 - albedo f, albedo albedo (1 - f) / (1 - albedo f)); a direct term
+ * with the full function must weigh the full scattering, albedo / (1 - albedo f), which is
+ * the reduced albedo divided by 1 - f. */
+static double g_first_scale = 1.0;
 
 static void tab_set(phase_tab *t, int n, const double *p, const double *cdf)
 {
@@ -934,10 +940,11 @@ static void tab_set(phase_tab *t, int n, const double *p, const double *cdf)
 }
 
 void dso_set_phase(int n, const double *p, const double *cdf, int n_first, const double *p_first,
-                   const double *cdf_first)
+                   const double *cdf_first, double first_scale)
 {
     tab_set(&g_phase, n, p, cdf);
     tab_set(&g_first, n_first, p_first, cdf_first);
+    g_first_scale = first_scale;
 }
 
 /* p(mu): linear in theta between nodes */
@@ -978,7 +985,7 @@ double dso_tab_sample(int n, const double *p, const double *cdf, double u)
 static double ph_eval(double g, int first, double mu)
 {
     if (first && g_first.n)
-        return tab_eval(&g_first, mu);
+        return g_first_scale * tab_eval(&g_first, mu);
     if (g_phase.n)
         return tab_eval(&g_phase, mu);
     return dso_hg(g, mu);

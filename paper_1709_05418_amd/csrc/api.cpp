@@ -1667,6 +1667,11 @@ static ds_status tracer_params(const ds_tracer_params *p, TracerParams &tp, cons
     tp.pf_p = p->phase_first ? p->phase_first->p : nullptr;
     tp.pf_cdf = p->phase_first ? p->phase_first->cdf : nullptr;
     tp.pf_n = p->phase_first ? p->phase_first->n : 0;
+    // a table chopped with removed fraction f carries 1 - f of the scattering: the
+    // first-collision table is weighed against the scattering table by the ratio
+    tp.pf_scale = (p->phase_first && p->phase)
+                      ? (float)((1.0 - p->phase_first->removed) / (1.0 - p->phase->removed))
+                      : 1.f;
     DS_CHECK(p->albedo >= 0.f && p->albedo <= 1.f, DS_ERR_INVALID_ARG,
              "%s: albedo %g outside [0, 1]", fn, (double)p->albedo);
     DS_CHECK(p->g > -1.f && p->g < 1.f, DS_ERR_INVALID_ARG, "%s: g %g outside (-1, 1)", fn,

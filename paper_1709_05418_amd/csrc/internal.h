@@ -278,6 +278,10 @@ struct TracerParams {
     int ph_n = 0;
     const float *pf_p = nullptr, *pf_cdf = nullptr;
     int pf_n = 0;
+    // weight of the first-collision table against a chopped scattering table that removed
+    // the fraction f: 1 / (1 - f), so that albedo x weight is the unreduced medium's
+    // scattering over the reduced extinction
+    float pf_scale = 1.f;
     const float4 *set_dw = nullptr;
     const uint32_t *set_thr = nullptr;
     int set_m = 0;

@@ -276,7 +276,7 @@ __device__ __forceinline__ float phase_eval(const TracerParams &tp, bool first, 
 {
     if constexpr (TAB) {
         if (first && tp.pf_n)
-            return tab_eval(tp.pf_p, tp.pf_n, mu);
+            return tp.pf_scale * tab_eval(tp.pf_p, tp.pf_n, mu);
         if (tp.ph_n)
             return tab_eval(tp.ph_p, tp.ph_n, mu);
     }

@@ -70,7 +70,9 @@ def test_hg_table_in_the_tracer_matches_analytic_hg(clean_phase):
 
 def test_first_collision_uses_the_unchopped_table(clean_phase):
     # homogeneous box, rays along +x, light along +z: the direct term of a collision has
-    # mean albedo * p_first(0) * exp(-sigma depth) * E, p_first the first-collision table
+    # mean albedo / (1 - f) * p_first(90 deg) * exp(-sigma depth) * E, p_first the
+    # first-collision table and f the fraction the chopped table removed (the albedo
+    # passed is the reduced one, the full function's term weighs the unreduced scattering)
     n = 12
     h = 1.0 / n
     grid = O.Grid(np.ones((n, n, n), np.float32), 1.7, [-0.5] * 3, h)
@@ -90,8 +92,9 @@ def test_first_collision_uses_the_unchopped_table(clean_phase):
     p90 = full["p"][900]                         # theta = 90 degrees is node 900
     assert p90 != chop["p"][900]
     T = np.exp(-1.7 * np.array([ramp_int(z + 0.5, 1.0, n, h) for z in zs]))
-    want = 0.9 * p90 * T * 2.0
-    sd = 0.9 * p90 * 2.0 * np.sqrt(T * (1 - T) / hits)
+    w = 0.9 / (1.0 - chop["removed"])
+    want = w * p90 * T * 2.0
+    sd = w * p90 * 2.0 * np.sqrt(T * (1 - T) / hits)
     assert np.all(np.abs(dsum / hits - want) < 5 * sd + 1e-12)
 
 
