@@ -189,11 +189,24 @@ ds_status ds_forward(ds_ctx *ctx, const ds_net *net, const float *z, int64_t P, 
  * DS_PREC_BF16 / DS_PREC_FP8 run the fused kernel (descriptor stays on chip).
  * out (device, P floats), pre_out (device, P floats, may be NULL: final
  * pre-activation) and flags (device, P bytes, may be NULL).  Invalid points get
- * out = pre_out = 0.  FP8 needs ds_net_quantize first (else DS_ERR_STATE). */
+ * out = pre_out = 0.  FP8 needs ds_net_quantize first (else DS_ERR_STATE).
+ * The fused forms allocate nothing and never synchronise, so they can be captured in
+ * a stream graph.  The plain form does too once ds_predict_reserve has run for the
+ * cloud, the context and at least P points; otherwise its first call builds the
+ * cloud's float32 corner cells and grows the context workspace (allocating and
+ * synchronising the stream). */
 ds_status ds_predict(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
                      ds_precision precision, const float *pos, const float *view_dir,
                      const float *light_dir, int64_t P, float *out, float *pre_out,
                      uint8_t *flags);
+/* Builds ahead of time what ds_predict on (ctx, cloud, net, precision) with at most P
+ * points would otherwise create on first use: for DS_PREC_F32 the cloud's float32
+ * corner-packed levels and the context workspace of min(P, 65536) points (about
+ * 4 (225 K + 1 + 3 W) + 1 bytes per point); nothing for the fused forms.  Synchronises
+ * the stream.  Later ds_predict calls within those bounds allocate nothing and can be
+ * captured in a stream graph.  Errors as ds_predict, DS_ERR_OOM if memory runs out. */
+ds_status ds_predict_reserve(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
+                             ds_precision precision, int64_t P);
 
 /* ---------------------------------------------------------------- batched prediction */
 /* Uneven sets of shading points from several clouds (each with its own pyramid,
@@ -284,10 +297,14 @@ ds_status ds_adam_set_lr(ds_adam *opt, float lr);
 ds_status ds_adam_steps(const ds_adam *opt, int64_t *t);
 
 /* Arithmetic of ds_loss_grad and ds_train_step: DS_PREC_F32 (default; every GEMM in
- * FP32) or DS_PREC_BF16 (every GEMM operand - descriptors, activations, weights and
- * back-propagated gradients - rounded to BF16 with FP32 accumulation on the matrix
- * cores; bias, residual, ReLU, loss and batch reductions in FP32; the master
- * parameters and Adam stay FP32).  DS_PREC_FP8 gives DS_ERR_UNSUPPORTED. */
+ * FP32) or DS_PREC_BF16 (every GEMM on the BF16 matrix cores with FP32 accumulation:
+ * descriptors, back-propagated gradients and the operands of the weight-gradient
+ * products rounded to BF16 once; the forward products of the W x W layers (W1, W2, the
+ * trailing layers; an MLP's hidden layers) with each operand as a BF16 pair hi + lo,
+ * lo = x - hi, summed as hi hi + hi lo + lo hi, since their rounding, carried along the
+ * residual stream, moves every gradient; bias, residual, ReLU, loss and batch
+ * reductions in FP32; the master parameters and Adam stay FP32).  DS_PREC_FP8 gives
+ * DS_ERR_UNSUPPORTED. */
 ds_status ds_net_set_train_precision(ds_net *net, ds_precision precision);
 
 /* Minibatch loss (1/B) sum_b (log(1 + g(z_b)) - t_b)^2 with t_b = log(1 + L_i) and,
@@ -320,15 +337,16 @@ ds_status ds_train_step(ds_net *net, ds_adam *opt, const float *z, const float *
 #define DS_LIGHT_DIRECTIONAL 0 /* a directional light of irradiance E, next-event estimation */
 #define DS_LIGHT_ENVIRONMENT 1 /* a uniform environment of radiance E, counted on escape     */
 
-/* A tabulated phase function (Sec. 5.1: the paper renders and generates data with a
- * tabulated Lorenz-Mie function whose forward peak is chopped, the density reduced
- * accordingly, and uses the unchopped function for the first scattering event while
- * rendering).  p: host, n values (3 <= n <= 65536, finite, >= 0) at theta_i =
+/* A tabulated phase function (Sec. 3.1 and Sec. 5.1: the paper renders and generates
+ * data with a tabulated Lorenz-Mie function whose forward peak is chopped, the density
+ * reduced accordingly, and uses the unchopped function for the first scattering event
+ * while rendering).  p: host, n values (3 <= n <= 65536, finite, >= 0) at theta_i =
  * i pi / (n - 1) per steradian.  The table is normalised so that the trapezoid rule
  * on 2 pi p sin(theta) gives 1.  chop_deg > 0 holds p below the node nearest
  * chop_deg at that node's value; the fraction f of the scattering that this removes
- * is reported and the rest renormalised: a caller that chops should scale the
- * extinction by (1 - albedo f) and use albedo (1 - f) / (1 - albedo f).  The tracer
+ * is reported and the rest renormalised.  A chopped table used as
+ * ds_tracer_params.phase makes the tracer calls trace the optically thinner medium
+ * themselves (see ds_tracer_params).  The tracer
  * evaluates p linearly in theta between nodes and draws theta from the cumulative
  * trapezoid sums, linear density inside a node interval.  ds_phase_build does the
  * host part only: p_out and cdf_out (n doubles each, may be NULL), removed and
@@ -343,8 +361,18 @@ ds_status ds_phase_info(const ds_phase *phase, double *removed, double *mean_cos
 /* Waits for the context's stream, then frees the table. */
 ds_status ds_phase_destroy(ds_phase *phase);
 
+/* Tracer settings.  With a chopped table as `phase` (removed fraction f > 0) every call
+ * traces the thinner medium of Sec. 3.1 (the reduced density): extinction times
+ * 1 - albedo f, survival probability albedo (1 - f) / (1 - albedo f); the removed peak
+ * travels on unscattered.  That albedo is the library's reading (the paper names only
+ * the reduced density): the scattering that is left, albedo (1 - f) mu_t, over the
+ * thinner extinction.  The network renderers multiply their network term by the same
+ * reduced albedo.  Record sampling (ds_sample_records) and the descriptors use the cloud
+ * as created. */
 typedef struct ds_tracer_params {
-    float albedo;         /* survival probability per collision, in [0, 1]              */
+    float albedo;         /* single-scattering albedo of the medium, in [0, 1]; the
+                             survival probability per collision (reduced as above with
+                             a chopped table)                                          */
     float g;              /* HG mean cosine, in (-1, 1)                                   */
     float irradiance;     /* E of the light (DS_LIGHT_DIRECTIONAL) or of the environment */
     int32_t light_mode;   /* DS_LIGHT_DIRECTIONAL or DS_LIGHT_ENVIRONMENT                 */
@@ -357,10 +385,11 @@ typedef struct ds_tracer_params {
     const ds_phase *phase_first; /* NULL: as phase; else the table for the direct term at
                                     the first collision of camera rays (render calls),
                                     weighted by (1 - f_first) / (1 - f) with f, f_first the
-                                    fractions the two tables' chops removed (Sec. 5.1: with
-                                    a chopped phase, albedo holds the reduced albedo; a full
-                                    first-collision function needs the unreduced
-                                    scattering, 1 / (1 - f) times it)                    */
+                                    fractions the two tables' chops removed.  Sec. 3.1 uses
+                                    the full function at the first bounce; weighing it by
+                                    1 / (1 - f) against the thinner medium's scattering
+                                    albedo (1 - f) mu_t restores the full scattering
+                                    albedo mu_t (the library's reading)                  */
 } ds_tracer_params;
 
 /* The cloud's majorant sigma_max * max(d) (host write). */

@@ -34,9 +34,13 @@ What each part follows in the paper and what pins it (tests/test_oracle_*.py):
   mlp_forward,    Sec. 7 / Fig. 10 all-at-once MLPs         equal to forward / loss_grad of a K = 1
   mlp_loss_grad   (numpy, FP64)                             RPNN (same parameter vector), central
                                                             finite differences
-  phase_table,    Sec. 5.1 tabulated (chopped) Lorenz-Mie   normalisation, chopped mass, HG table
-  set_phase       phase function, unchopped at the first    against analytic HG (moments, CDF and
-                  collision when rendering                  the tracer's estimates)
+  phase_table,    Sec. 3.1 / 5.1 tabulated (chopped)        normalisation, chopped mass, HG table
+  set_phase       Lorenz-Mie phase function: the chop's     against analytic HG (moments, CDF and
+                  thinner medium and albedo, the unchopped  the tracer's estimates); in a thin
+                  function at the first collision when      homogeneous box the chopped set-up's
+                  rendering                                 first-collision pixel equals the full
+                                                            function's single-scattering integral
+                                                            (quadrature), f -> 0 gives the full one
   e4m3_encode     OCP 8-bit floating point, E4M3 format     torch.float8_e4m3fn cast, hand values,
                   (round to nearest even, saturating)       decode/encode round trip of every code
 """
@@ -103,7 +107,7 @@ def lib():
                                       P, P]),
             "dso_first_hits": (I, [P, I, I, I, I, D, P, D, D, D, D, P, P, P, I64, U64, U64, P, P,
                                    P, P]),
-            "dso_set_phase": (None, [I, P, P, I, P, P, D]),
+            "dso_set_phase": (None, [I, P, P, D, I, P, P, D]),
             "dso_tab_sample": (D, [I, P, P, D]),
             "dso_render_pixels_lights": (I, [P, I, I, I, I, D, P, D, D, D, D, I, I, P, P, P, P, P,
                                              I64, I, U64, P, P]),
@@ -463,24 +467,23 @@ def phase_table(p, chop_deg=0.0):
 
 def set_phase(table=None, first=None):
     """Use `table` (from phase_table) for every scattering and `first` for the direct
-    term at the first collision of camera rays in all later tracer calls, weighted by
-    (1 - first["removed"]) / (1 - table["removed"]) (a chopped table carries 1 - removed of
-    the scattering); None restores Henyey-Greenstein (first falls back to table)."""
+    term at the first collision of camera rays in all later tracer calls; None restores
+    Henyey-Greenstein (first falls back to table).  While a chopped table is set, every
+    tracer call takes its albedo argument as the medium's own single-scattering albedo a
+    and traces the optically thinner medium of Sec. 3.1: extinction times 1 - a f, albedo
+    a (1 - f) / (1 - a f), f = table["removed"]; `first` is weighted by
+    (1 - first["removed"]) / (1 - f) (the C oracle's chop_reduce and first_scale)."""
     L = lib()
     keep = []
 
     def args(t):
         if t is None:
-            return [0, None, None]
+            return [0, None, None, 0.0]
         a, b = np.ascontiguousarray(t["p"]), np.ascontiguousarray(t["cdf"])
         keep.extend([a, b])
-        return [a.size, _p(a), _p(b)]
+        return [a.size, _p(a), _p(b), float(t.get("removed", 0.0))]
 
-    # a full first-collision function next to a chopped table weighs the scattering the
-    # chop removed: 1 / (1 - removed)
-    scale = ((1.0 - first.get("removed", 0.0)) / (1.0 - table.get("removed", 0.0))
-             if (table is not None and first is not None) else 1.0)
-    L.dso_set_phase(*args(table), *args(first), float(scale))
+    L.dso_set_phase(*args(table), *args(first))
 
 
 def tab_sample(table, u):

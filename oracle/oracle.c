@@ -916,12 +916,36 @@ typedef struct {
 } phase_tab;
 
 static phase_tab g_phase, g_first;
-/* the first-collision table's weight against a chopped scattering table that removed the
- * fraction f: 1 / (1 - f) for the full function ((1 - f_first) / (1 - f) in general).  The chop moves f of the scattering into unscattered travel
- * (extinction times 1 - albedo f, albedo albedo (1 - f) / (1 - albedo f)); a direct term
- * with the full function must weigh the full scattering, albedo / (1 - albedo f), which is
- * the reduced albedo divided by 1 - f. */
-static double g_first_scale = 1.0;
+/* Fraction f of the scattering that the chop removed from the scattering table (0 for an
+ * unchopped table or Henyey-Greenstein), and the first-collision table's own fraction. */
+static double g_removed = 0.0, g_removed_first = 0.0;
+
+/* The chop of Sec. 3.1: the removed forward peak is treated as unscattered light, so the
+ * medium is made optically thinner "according to the fraction of scattered light contained
+ * in the peak".  With single-scattering albedo a, the removed scattering a f leaves the
+ * extinction, mu_t' = mu_t (1 - a f), and the scattering left is a (1 - f) mu_t, so the
+ * albedo of the thinner medium is a (1 - f) / (1 - a f).  Applied to the medium and albedo
+ * of every tracer call while a chopped scattering table is set. */
+static void chop_reduce(double *sigma_max, double *albedo)
+{
+    if (!g_phase.n || !(g_removed > 0.0))
+        return;
+    double a = *albedo, s = 1.0 - a * g_removed;
+    *sigma_max *= s;
+    *albedo = a * (1.0 - g_removed) / s;
+}
+
+/* Weight of the first-collision table (Sec. 3.1: the full function at the first bounce,
+ * then the chopped one in the thinner medium).  A table that removed f_first carries
+ * (1 - f_first) of the scattering: its direct term in the thinner medium must weigh the
+ * unreduced scattering a mu_t, which is (1 - f_first) / (1 - f) times the thinner medium's
+ * a' mu_t' = a (1 - f) mu_t. */
+static double first_scale(void)
+{
+    if (!g_phase.n || !g_first.n)
+        return 1.0;
+    return (1.0 - g_removed_first) / (1.0 - g_removed);
+}
 
 static void tab_set(phase_tab *t, int n, const double *p, const double *cdf)
 {
@@ -939,12 +963,13 @@ static void tab_set(phase_tab *t, int n, const double *p, const double *cdf)
     t->dth = M_PI / (n - 1);
 }
 
-void dso_set_phase(int n, const double *p, const double *cdf, int n_first, const double *p_first,
-                   const double *cdf_first, double first_scale)
+void dso_set_phase(int n, const double *p, const double *cdf, double removed, int n_first,
+                   const double *p_first, const double *cdf_first, double removed_first)
 {
     tab_set(&g_phase, n, p, cdf);
     tab_set(&g_first, n_first, p_first, cdf_first);
-    g_first_scale = first_scale;
+    g_removed = g_phase.n ? removed : 0.0;
+    g_removed_first = g_first.n ? removed_first : 0.0;
 }
 
 /* p(mu): linear in theta between nodes */
@@ -985,7 +1010,7 @@ double dso_tab_sample(int n, const double *p, const double *cdf, double u)
 static double ph_eval(double g, int first, double mu)
 {
     if (first && g_first.n)
-        return g_first_scale * tab_eval(&g_first, mu);
+        return first_scale() * tab_eval(&g_first, mu);
     if (g_phase.n)
         return tab_eval(&g_phase, mu);
     return dso_hg(g, mu);
@@ -1150,6 +1175,7 @@ int dso_trace_li(const void *dens, int dtype, int nx, int ny, int nz, double sig
                  double *mean_out, double *var_out)
 {
     medium_t M;
+    chop_reduce(&sigma_max, &albedo);
     if (!medium_init(&M, dens, dtype, nx, ny, nz, sigma_max, aabb_min, h0) || spp <= 0 ||
         spp > (1 << 20))
         return DSO_ERR_INVALID;
@@ -1196,6 +1222,7 @@ int dso_trace_li_adaptive(const void *dens, int dtype, int nx, int ny, int nz, d
                           int64_t P, double *mean_out, double *var_out, int32_t *n_out)
 {
     medium_t M;
+    chop_reduce(&sigma_max, &albedo);
     if (!medium_init(&M, dens, dtype, nx, ny, nz, sigma_max, aabb_min, h0) || batch < 2 ||
         max_spp < batch || max_spp > (1 << 20) || max_spp % batch != 0 || !(rel > 0) ||
         !(zq > 0))
@@ -1337,6 +1364,7 @@ int dso_first_hits(const void *dens, int dtype, int nx, int ny, int nz, double s
                    uint8_t *hit)
 {
     medium_t M;
+    chop_reduce(&sigma_max, &albedo);
     if (!medium_init(&M, dens, dtype, nx, ny, nz, sigma_max, aabb_min, h0) || sample >= (1u << 20))
         return DSO_ERR_INVALID;
     double wl[3];
@@ -1405,6 +1433,7 @@ int dso_render_pixels(const void *dens, int dtype, int nx, int ny, int nz, doubl
                       int64_t NPix, int spp, uint64_t seed, double *mean_out, double *var_out)
 {
     medium_t M;
+    chop_reduce(&sigma_max, &albedo);
     if (!medium_init(&M, dens, dtype, nx, ny, nz, sigma_max, aabb_min, h0) || spp <= 0 ||
         spp > (1 << 20))
         return DSO_ERR_INVALID;
@@ -1462,6 +1491,7 @@ int dso_render_pixels_lights(const void *dens, int dtype, int nx, int ny, int nz
                              double *mean_out, double *var_out)
 {
     medium_t M;
+    chop_reduce(&sigma_max, &albedo);
     if (!medium_init(&M, dens, dtype, nx, ny, nz, sigma_max, aabb_min, h0) || spp <= 0 ||
         spp > (1 << 20) || !set_ok(m, dir, thr, w))
         return DSO_ERR_INVALID;
@@ -1505,6 +1535,7 @@ int dso_first_hits_lights(const void *dens, int dtype, int nx, int ny, int nz, d
                           double *light_out, double *weight_out, double *direct, uint8_t *hit)
 {
     medium_t M;
+    chop_reduce(&sigma_max, &albedo);
     if (!medium_init(&M, dens, dtype, nx, ny, nz, sigma_max, aabb_min, h0) ||
         sample >= (1u << 20) || D < 1 || !set_ok(m, dir, thr, w))
         return DSO_ERR_INVALID;

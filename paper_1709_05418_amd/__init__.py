@@ -67,6 +67,7 @@ def lib():
         "ds_gather_packed": (S, [P, P, P, P, P, I64, P]),
         "ds_forward": (S, [P, P, P, I64, P, P]),
         "ds_predict": (S, [P, P, P, I, P, P, P, I64, P, P, P]),
+        "ds_predict_reserve": (S, [P, P, P, I, I64]),
         "ds_adam_create": (S, [P, F, F, F, F, P]),
         "ds_adam_destroy": (S, [P]),
         "ds_adam_set_lr": (S, [P, F]),
@@ -324,6 +325,11 @@ def ds_predict(ctx, cloud, net, precision, pos, view_dir, light_dir, out=None, p
     _check(lib().ds_predict(ctx, cloud, net, int(precision), _pts(pos), _pts(view_dir, P),
                             _pts(light_dir, P), P, _ptr(out), _ptr(pre), _ptr(flags)))
     return out, pre, flags
+
+
+def ds_predict_reserve(ctx, cloud, net, precision, P):
+    """Build ahead what ds_predict with at most P points would create on first use."""
+    _check(lib().ds_predict_reserve(ctx, cloud, net, int(precision), int(P)))
 
 
 def ds_net_set_train_precision(net, precision):

@@ -9,6 +9,7 @@
 
 #include <new>
 #include <utility>
+#include <algorithm>
 #include <vector>
 
 #include "internal.h"
@@ -168,9 +169,9 @@ ds_status gather_cells(ds_ctx *ctx, const ds_cloud *c)
     if (c->cells32)
         return DS_OK;
     float4 *cells = nullptr;
-    DS_CHECK(hipMalloc(&cells, sizeof(float4) * 2 * (size_t)c->n_cells) == hipSuccess, DS_ERR_OOM,
-             "out of device memory for the float32 corner cells (%lld cells of 32 bytes)",
-             (long long)c->n_cells);
+    DS_CHECK(hipMalloc(&cells, sizeof(float4) * 2 * (size_t)c->n_cells32) == hipSuccess,
+             DS_ERR_OOM, "out of device memory for the float32 corner cells (%lld cells of 32 bytes)",
+             (long long)c->n_cells32);
     ds_status st = cloud_pack32(ctx->stream, c->pyr, c->L, c->lv, cells);
     std::vector<GatherLevel> gl((size_t)c->K);
     hipError_t e = st ? hipSuccess
@@ -180,7 +181,7 @@ ds_status gather_cells(ds_ctx *ctx, const ds_cloud *c)
         e = hipStreamSynchronize(ctx->stream);
     if (!st && e == hipSuccess) {
         for (int k = 0; k < c->K; ++k)
-            gl[k].cells = cells + 2 * c->lv[c->mips[k]].cell_off;
+            gl[k].cells = cells + 2 * c->lv[c->mips[k]].cell32_off;
         e = hipMemcpy(c->tables, gl.data(), sizeof(GatherLevel) * c->K, hipMemcpyHostToDevice);
     }
     if (!st && e != hipSuccess)
@@ -438,7 +439,9 @@ static ds_status mlp_loss_grad(ds_net *net, const float *z, const float *target,
     int ld = D;
     for (int l = 0; l < L; ++l) {
         const int ni = wd[l], no = wd[l + 1];
-        DS_TRY(mm({B, no, ni, in, ld, 1, th + ow[l], 1, ni, A[l], no, 0}));
+        // hidden-layer products with BF16 operand pairs, as the RPNN's W x W layers
+        const StridedGemm gl = {B, no, ni, in, ld, 1, th + ow[l], 1, ni, A[l], no, 0};
+        DS_TRY(bf && l > 0 ? gemm_bf16(s, gl, sp, split, true) : mm(gl));
         DS_TRY(layer_epilogue(s, B, no, A[l], no, nullptr, 0, nullptr, 0, th + ob[l], nullptr, 0,
                               Y[l], no));
         in = Y[l];
@@ -471,8 +474,9 @@ static ds_status mlp_loss_grad(ds_net *net, const float *z, const float *target,
 
 // Loss and gradient of a minibatch: forward keeping pre-activations, then
 // backpropagation layer by layer; every parameter gradient is written exactly once.
-// FP32 arithmetic, or (train_prec BF16) every GEMM operand rounded to BF16 with FP32
-// accumulation on the matrix cores; epilogues, reductions and the loss stay FP32.
+// FP32 arithmetic, or (train_prec BF16) every GEMM on the BF16 matrix cores with FP32
+// accumulation (operands rounded once, or as hi + lo pairs for the forward W x W products);
+// epilogues, reductions and the loss stay FP32.
 ds_status loss_grad(ds_net *net, const float *z, const float *target, int B, float *loss,
                     float *grad)
 {
@@ -487,6 +491,14 @@ ds_status loss_grad(ds_net *net, const float *z, const float *target, int B, flo
     DS_TRY(train_ws(net, B, w));
     auto mm = [&](const StridedGemm &g) {
         return bf ? gemm_bf16(s, g, w.split, w.split_floats)
+                  : gemm_strided(s, g, w.split, w.split_floats);
+    };
+    // forward products of the W x W layers (W1, W2, trailing): in BF16 their operands as
+    // hi + lo pairs.  A single BF16 rounding of these operands, carried through the residual
+    // stream of all blocks, moves the loss and thus every gradient; the descriptor layers
+    // and the backward products keep one BF16 term
+    auto mmw = [&](const StridedGemm &g) {
+        return bf ? gemm_bf16(s, g, w.split, w.split_floats, true)
                   : gemm_strided(s, g, w.split, w.split_floats);
     };
     const size_t BW = (size_t)B * W;
@@ -527,7 +539,7 @@ ds_status loss_grad(ds_net *net, const float *z, const float *target, int B, flo
             DS_TRY(mm({B, W, kStencil, z + (int64_t)k * kStencil, D, 1, th + po.V[k], 1, 226, H(k), W,
                        0}));
             if (k > 0)
-                DS_TRY(mm({B, W, W, O(k - 1), W, 1, th + po.W1[k], 1, W, H(k), W, 1}));
+                DS_TRY(mmw({B, W, W, O(k - 1), W, 1, th + po.W1[k], 1, W, H(k), W, 1}));
             DS_TRY(layer_epilogue(s, B, W, H(k), W, z + (int64_t)kStencil * K, D,
                                   th + po.V[k] + 225, 226, th + po.b1[k], nullptr, 0, F1(k), W));
         } else {
@@ -552,7 +564,7 @@ ds_status loss_grad(ds_net *net, const float *z, const float *target, int B, flo
         g2.ldpre = W;
         g2.relu = 1;
         if (bf) {
-            DS_TRY(mm({B, W, W, F1(k), W, 1, th + po.W2[k], 1, W, A(k), W, 0}));
+            DS_TRY(mmw({B, W, W, F1(k), W, 1, th + po.W2[k], 1, W, A(k), W, 0}));
             DS_TRY(layer_epilogue(s, B, W, A(k), W, nullptr, 0, nullptr, 0, th + po.b2[k],
                                   k > 0 ? O(k - 1) : nullptr, W, O(k), W));
         } else {
@@ -577,7 +589,7 @@ ds_status loss_grad(ds_net *net, const float *z, const float *target, int B, flo
         g.relu = 1;
         if (bf) {
             const int N = last ? 1 : W;
-            DS_TRY(mm({B, N, W, g.A1, W, 1, th + po.hw[m], 1, W, HA(m), N, 0}));
+            DS_TRY(mmw({B, N, W, g.A1, W, 1, th + po.hw[m], 1, W, HA(m), N, 0}));
             DS_TRY(layer_epilogue(s, B, N, HA(m), N, nullptr, 0, nullptr, 0, th + po.hb[m], nullptr,
                                   0, HO(m), N));
         } else {
@@ -778,20 +790,20 @@ ds_status ds_cloud_create(ds_ctx *ctx, const void *density_dev, ds_dtype dtype, 
     c->mean = (double)sigma_max * sum / (double)count;
     c->L = n_levels;
     c->K = K;
-    int64_t off = 0, coff = 0;
+    int64_t off = 0, coff32 = 0;
     for (int i = 0; i < n_levels; ++i) {
         Level &l = c->lv[i];
         l.nx = level_dim(nx, i);
         l.ny = level_dim(ny, i);
         l.nz = level_dim(nz, i);
         l.off = off;
-        l.cell_off = coff;
+        l.cell32_off = coff32;
         l.h = (float)ldexp((double)voxel_size, i);
         off += (int64_t)l.nx * l.ny * l.nz;
-        coff += (int64_t)(l.nx + 2) * (l.ny + 2) * (l.nz + 2);
+        coff32 += (int64_t)(l.nx + 2) * (l.ny + 2) * (l.nz + 2);
     }
     c->pyr_elems = off;
-    c->n_cells = coff;
+    c->n_cells32 = coff32;
     if (mip_of_level) {
         memcpy(c->mips, mip_of_level, sizeof(int) * K);
     } else {
@@ -802,6 +814,36 @@ ds_status ds_cloud_create(ds_ctx *ctx, const void *density_dev, ds_dtype dtype, 
             c->mips[k] = m < 0 ? 0 : (m > n_levels - 1 ? n_levels - 1 : m);
         }
     }
+    // Zero borders of the FP16 cells.  A stencil sample lies at most sqrt(1 + 1 + 9) mean
+    // free paths times 2^(k-1) from its point along any axis (offsets within [-1, 1]^2 x
+    // [-1, 3], scaled by 2^(k-1) on the orthonormal light frame), so a point inside the grid
+    // box reads cells within E = 3.3167 * step / h voxels of the grid: a border of
+    // ceil(E + 1/2) + 1 cells holds all of them and the kernel can skip the per-sample
+    // clamp.  Levels whose border would grow the cells too much keep a border of one and
+    // the clamp.
+    int64_t coff = 0;
+    for (int i = 0; i < n_levels; ++i) {
+        Level &l = c->lv[i];
+        double ext = 0.0;
+        for (int k = 0; k < K; ++k)
+            if (c->mips[k] == i)
+                ext = std::max(ext, 3.3166248 * ldexp(1.0, k) / c->mean / (double)l.h);
+        int bd = 1;
+        l.fast = true;
+        if (ext > 0.0) {
+            const double want = ceil(ext + 0.5) + 1.0;
+            const double base = (double)(l.nx + 2) * (l.ny + 2) * (l.nz + 2);
+            const double grown = (l.nx + 2 * want) * (l.ny + 2 * want) * (l.nz + 2 * want);
+            if (want <= 256.0 && (grown <= 1.5 * base || grown <= (double)(1 << 21)))
+                bd = (int)want;
+            else
+                l.fast = false;
+        }
+        l.bd = bd;
+        l.cell_off = coff;
+        coff += (int64_t)(l.nx + 2 * bd) * (l.ny + 2 * bd) * (l.nz + 2 * bd);
+    }
+    c->n_cells = coff;
     auto fail = [&](ds_status s) {
         ds_cloud_destroy(c);
         return s;
@@ -842,13 +884,15 @@ ds_status ds_cloud_create(ds_ctx *ctx, const void *density_dev, ds_dtype dtype, 
         gl[k].inv_h = (float)(1.0 / h);
         gl[k].step = (float)step;
         fl[k].cells = c->cells + l.cell_off;
-        fl[k].cx = l.nx + 2;
-        fl[k].cy = l.ny + 2;
-        fl[k].hi_x = (float)(l.nx + 1);  // cell coordinates are shifted by one
-        fl[k].hi_y = (float)(l.ny + 1);
-        fl[k].hi_z = (float)(l.nz + 1);
+        fl[k].cx = l.nx + 2 * l.bd;
+        fl[k].cy = l.ny + 2 * l.bd;
+        fl[k].hi_x = (float)(l.nx + 2 * l.bd - 1);  // cell coordinates are shifted by bd
+        fl[k].hi_y = (float)(l.ny + 2 * l.bd - 1);
+        fl[k].hi_z = (float)(l.nz + 2 * l.bd - 1);
         fl[k].inv_h = (float)(1.0 / h);
         fl[k].step = (float)step;
+        fl[k].shift = (float)l.bd - 0.5f;
+        fl[k].fast = l.fast ? 1 : 0;
     }
     size_t tb = sizeof(GatherLevel) * K + sizeof(FusedLevel) * K + 64;
     if (hipMalloc(&c->tables, tb) != hipSuccess) {
@@ -902,7 +946,10 @@ static void add_cloud(FusedArgs &a, const ds_cloud *c, int64_t p_begin, int64_t 
     memcpy(f.amin, ga.amin, sizeof(f.amin));
     memcpy(f.amax, ga.amax, sizeof(f.amax));
     f.inv_mean = ga.inv_mean;
-    f.pad_ = 0;
+    f.fast = 1;
+    for (int k = 0; k < c->K; ++k)
+        if (!c->lv[c->mips[k]].fast)
+            f.fast = 0;
     f.p_begin = p_begin;
     f.P = P;
     f.tile_begin = 0;
@@ -1187,6 +1234,28 @@ static ds_status predict_plain(ds_ctx *ctx, const ds_cloud *cloud, const ds_net 
         if (st)
             return st;
     }
+    return DS_OK;
+}
+
+ds_status ds_predict_reserve(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
+                             ds_precision precision, int64_t P)
+{
+    DS_CHECK(ctx && cloud && net, DS_ERR_INVALID_ARG,
+             "ds_predict_reserve: NULL context, cloud or net");
+    DS_CHECK(cloud->K == net->K, DS_ERR_INVALID_ARG,
+             "ds_predict_reserve: the cloud has %d stencil levels, the network %d", cloud->K,
+             net->K);
+    DS_CHECK(P >= 0 && P <= ((int64_t)1 << 31), DS_ERR_INVALID_ARG, "ds_predict_reserve: bad P");
+    DS_CHECK(precision == DS_PREC_F32 || precision == DS_PREC_BF16 || precision == DS_PREC_FP8,
+             DS_ERR_INVALID_ARG, "ds_predict_reserve: unknown precision %d", (int)precision);
+    if (precision != DS_PREC_F32 || P == 0)
+        return DS_OK;
+    DS_HIP(hipSetDevice(ctx->device));
+    const int64_t rows = P < kChunk ? P : kChunk;
+    const size_t D = (size_t)kStencil * net->K + 1;
+    DS_TRY(ensure_ws(ctx, sizeof(float) * (size_t)rows * (D + 3 * (size_t)net->W) + (size_t)rows));
+    DS_TRY(gather_cells(ctx, cloud));
+    DS_HIP(hipStreamSynchronize(ctx->stream));
     return DS_OK;
 }
 
@@ -1667,13 +1736,23 @@ static ds_status tracer_params(const ds_tracer_params *p, TracerParams &tp, cons
     tp.pf_p = p->phase_first ? p->phase_first->p : nullptr;
     tp.pf_cdf = p->phase_first ? p->phase_first->cdf : nullptr;
     tp.pf_n = p->phase_first ? p->phase_first->n : 0;
-    // a table chopped with removed fraction f carries 1 - f of the scattering: the
-    // first-collision table is weighed against the scattering table by the ratio
-    tp.pf_scale = (p->phase_first && p->phase)
-                      ? (float)((1.0 - p->phase_first->removed) / (1.0 - p->phase->removed))
-                      : 1.f;
     DS_CHECK(p->albedo >= 0.f && p->albedo <= 1.f, DS_ERR_INVALID_ARG,
              "%s: albedo %g outside [0, 1]", fn, (double)p->albedo);
+    // Sec. 3.1: chopping the forward peak removes the fraction f of the scattering, which
+    // then travels on as unscattered light, so the medium gets optically thinner by the
+    // scattering removed: extinction mu_t (1 - a f), albedo a (1 - f) / (1 - a f) for the
+    // single-scattering albedo a the caller passes
+    const double f = p->phase ? p->phase->removed : 0.0;
+    const double s = 1.0 - (double)p->albedo * f;
+    tp.ext_scale = (float)s;
+    tp.albedo = f > 0.0 ? (float)((double)p->albedo * (1.0 - f) / s) : p->albedo;
+    // a table chopped with removed fraction f carries 1 - f of the scattering: the
+    // first-collision table is weighed against the scattering table by the ratio, so
+    // that the thinner medium's scattering a (1 - f) mu_t times the weight is the
+    // unreduced scattering a mu_t (times 1 - f_first for a chopped first table)
+    tp.pf_scale = (p->phase_first && p->phase)
+                      ? (float)((1.0 - p->phase_first->removed) / (1.0 - f))
+                      : 1.f;
     DS_CHECK(p->g > -1.f && p->g < 1.f, DS_ERR_INVALID_ARG, "%s: g %g outside (-1, 1)", fn,
              (double)p->g);
     DS_CHECK(std::isfinite(p->irradiance), DS_ERR_INVALID_ARG, "%s: irradiance not finite", fn);
@@ -1682,7 +1761,6 @@ static ds_status tracer_params(const ds_tracer_params *p, TracerParams &tp, cons
     DS_CHECK(p->max_interactions >= 0, DS_ERR_INVALID_ARG, "%s: max_interactions < 0", fn);
     DS_CHECK(p->include_direct == 0 || p->include_direct == 1, DS_ERR_INVALID_ARG,
              "%s: include_direct must be 0 or 1", fn);
-    tp.albedo = p->albedo;
     tp.g = p->g;
     tp.irradiance = p->irradiance;
     tp.light_mode = p->light_mode;

@@ -148,37 +148,51 @@ __global__ void __launch_bounds__(256) k_blur(const void *in, ds_dtype dt, float
     }
 }
 
-// FP16 bits of f, round to nearest even, saturated at the largest finite value.
+// FP16 bits of f, round to nearest even, saturated at the largest finite magnitude.
 __device__ __forceinline__ uint32_t f16_sat(float f)
 {
-    const _Float16 h = (_Float16)fminf(f, 65504.f);
+    const _Float16 h = (_Float16)fmaxf(fminf(f, 65504.f), -65504.f);
     return (uint32_t)__builtin_bit_cast(uint16_t, h);
 }
 
-// Corner-packed level: cell (cx, cy, cz) holds the 8 values around lower corner
-// (cx-1, cy-1, cz-1) as FP16, zero outside the level grid:
-// word 0 = (v000, v100), 1 = (v010, v110), 2 = (v001, v101), 3 = (v011, v111),
-// the first value of each pair in the low half.
+// Corner-packed level with a zero border of bd cells: cell (i, j, k) covers the lattice
+// cell whose lower corner is voxel (i - bd, j - bd, k - bd), values zero outside the level
+// grid.  Its trilinear function is stored as polynomial coefficients in the fractions
+// (tx, ty, tz):  v(t) = P0(ty, tz) + tx P1(ty, tz),  P = A + B ty + tz (C + D ty),
+// with P0 the bilinear function of the x0 face and P1 that of the x1 face minus the x0
+// face.  FP16, word 0 = (A0, A1), 1 = (B0, B1), 2 = (C0, C1), 3 = (D0, D1), the P0
+// coefficient in the low half; the coefficients are formed in FP32 from the level and
+// rounded once.  Evaluating this form takes three packed FMAs and one mixed FMA.
 __global__ void __launch_bounds__(256) k_pack(const float *__restrict__ lv, int nx, int ny, int nz,
-                                              uint4 *__restrict__ cells)
+                                              int bd, uint4 *__restrict__ cells)
 {
-    int64_t cx = nx + 2, cy = ny + 2, cz = nz + 2;
-    int64_t total = cx * cy * cz;
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t cx = nx + 2 * bd, cy = ny + 2 * bd, cz = nz + 2 * bd;
+    const int64_t total = cx * cy * cz;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += stride) {
-        int64_t i = idx % cx - 1;
-        int64_t r = idx / cx;
-        int64_t j = r % cy - 1;
-        int64_t k = r / cy - 1;
-        uint32_t v[8];
+        const int64_t i = idx % cx - bd, r = idx / cx;
+        const int64_t j = r % cy - bd, k = r / cy - bd;
+        float v[8];  // corner dx + 2 dy + 4 dz
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
-            int64_t a = i + (c & 1), b = j + ((c >> 1) & 1), e = k + ((c >> 2) & 1);
-            bool in = a >= 0 && b >= 0 && e >= 0 && a < nx && b < ny && e < nz;
-            v[c] = in ? f16_sat(lv[(e * ny + b) * nx + a]) : 0u;
+            const int64_t a = i + (c & 1), b = j + ((c >> 1) & 1), e = k + ((c >> 2) & 1);
+            const bool in = a >= 0 && b >= 0 && e >= 0 && a < nx && b < ny && e < nz;
+            v[c] = in ? lv[(e * ny + b) * nx + a] : 0.f;
         }
-        cells[idx] = make_uint4(v[0] | (v[1] << 16), v[2] | (v[3] << 16), v[4] | (v[5] << 16),
-                                v[6] | (v[7] << 16));
+        uint32_t w[4];
+        float co[2][4];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {  // bilinear coefficients of the x = 0 and x = 1 faces
+            const float f00 = v[x], f10 = v[x + 2], f01 = v[x + 4], f11 = v[x + 6];
+            co[x][0] = f00;
+            co[x][1] = f10 - f00;
+            co[x][2] = f01 - f00;
+            co[x][3] = (f11 - f01) - (f10 - f00);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            w[q] = f16_sat(co[0][q]) | (f16_sat(co[1][q] - co[0][q]) << 16);
+        cells[idx] = make_uint4(w[0], w[1], w[2], w[3]);
     }
 }
 
@@ -327,7 +341,8 @@ ds_status cloud_pack32(hipStream_t s, const float *pyr, int L, const Level *lv, 
     for (int i = 0; i < L; ++i) {
         const Level &l = lv[i];
         int64_t n = (int64_t)(l.nx + 2) * (l.ny + 2) * (l.nz + 2);
-        k_pack32<<<grid_for(n), 256, 0, s>>>(pyr + l.off, l.nx, l.ny, l.nz, cells + 2 * l.cell_off);
+        k_pack32<<<grid_for(n), 256, 0, s>>>(pyr + l.off, l.nx, l.ny, l.nz,
+                                             cells + 2 * l.cell32_off);
     }
     DS_HIP(hipGetLastError());
     return DS_OK;
@@ -337,8 +352,9 @@ ds_status cloud_pack(hipStream_t s, const float *pyr, int L, const Level *lv, ui
 {
     for (int i = 0; i < L; ++i) {
         const Level &l = lv[i];
-        int64_t n = (int64_t)(l.nx + 2) * (l.ny + 2) * (l.nz + 2);
-        k_pack<<<grid_for(n), 256, 0, s>>>(pyr + l.off, l.nx, l.ny, l.nz, cells + l.cell_off);
+        int64_t n = (int64_t)(l.nx + 2 * l.bd) * (l.ny + 2 * l.bd) * (l.nz + 2 * l.bd);
+        k_pack<<<grid_for(n), 256, 0, s>>>(pyr + l.off, l.nx, l.ny, l.nz, l.bd,
+                                           cells + l.cell_off);
     }
     DS_HIP(hipGetLastError());
     return DS_OK;

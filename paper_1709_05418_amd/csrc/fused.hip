@@ -81,13 +81,17 @@ struct Pending {
     float fx[4], fy[4], fz[4];
 };
 
-// Clamp a shifted cell coordinate, start the cell load, keep the fractions.
+// Clamp a shifted cell coordinate (CL) or take it as it is (the level's zero border holds
+// every sample of the wave's points), start the cell load, keep the fractions.
+template <bool CL = true>
 __device__ __forceinline__ void issue_one(gcell_ptr cells, const FusedLevel &L, float ux, float uy,
                                           float uz, u32x4 &v, float &fx, float &fy, float &fz)
 {
-    ux = __builtin_amdgcn_fmed3f(ux, 0.f, L.hi_x);
-    uy = __builtin_amdgcn_fmed3f(uy, 0.f, L.hi_y);
-    uz = __builtin_amdgcn_fmed3f(uz, 0.f, L.hi_z);
+    if (CL) {
+        ux = __builtin_amdgcn_fmed3f(ux, 0.f, L.hi_x);
+        uy = __builtin_amdgcn_fmed3f(uy, 0.f, L.hi_y);
+        uz = __builtin_amdgcn_fmed3f(uz, 0.f, L.hi_z);
+    }
     const uint32_t i = (uint32_t)ux, j = (uint32_t)uy, k = (uint32_t)uz;
     fx = __builtin_amdgcn_fractf(ux);
     fy = __builtin_amdgcn_fractf(uy);
@@ -102,23 +106,22 @@ __device__ __forceinline__ void issue_one(gcell_ptr cells, const FusedLevel &L, 
     v = cells[idx];
 }
 
-// Trilinear value of a sample from its 8 corners (FP16): the y and z lerps run on the
-// (x0, x1) corner pairs as packed FP16 arithmetic (two lerps per instruction), the
-// final x lerp in FP32 on the two halves in place.
+// Trilinear value of a sample from its cell's polynomial coefficients (FP16, see k_pack):
+// the two faces' bilinear functions P0, P1 as packed FP16 FMAs on the (P0, P1) coefficient
+// pairs, then P0 + fx P1 in FP32 on the two halves in place.
 __device__ __forceinline__ float finish_one(const u32x4 &v, float fx, float fy, float fz)
 {
     typedef _Float16 h2 __attribute__((ext_vector_type(2)));
     // element copies first: a bit cast applied to a vector element itself reads the
     // vector's first element (seen with this compiler)
     const uint32_t u0 = v[0], u1 = v[1], u2 = v[2], u3 = v[3];
-    const h2 w0 = __builtin_bit_cast(h2, u0), w1 = __builtin_bit_cast(h2, u1);
-    const h2 w2 = __builtin_bit_cast(h2, u2), w3 = __builtin_bit_cast(h2, u3);
+    const h2 A = __builtin_bit_cast(h2, u0), B = __builtin_bit_cast(h2, u1);
+    const h2 C = __builtin_bit_cast(h2, u2), D = __builtin_bit_cast(h2, u3);
     const h2 t = __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(fy, fz));  // (fy, fz)
-    const h2 a = w0 + t[0] * (w1 - w0);  // y lerps in the z0 plane, both x ends
-    const h2 b = w2 + t[0] * (w3 - w2);  // the same in the z1 plane
-    const h2 c = a + t[1] * (b - a);     // z lerp
-    const _Float16 d = c[1] - c[0];
-    return fmaf(fx, (float)d, (float)c[0]);
+    const h2 p = B * t[0] + A;  // A + B ty for both faces
+    const h2 q = D * t[0] + C;  // C + D ty
+    const h2 r = q * t[1] + p;  // (P0, P1)
+    return fmaf(fx, (float)r[1], (float)r[0]);
 }
 
 // Lattice tables shared by a workgroup: (ix, iy) of stencil columns 0..23 (the
@@ -142,13 +145,14 @@ __device__ __forceinline__ void init_tables(int tid, float4 *plane, float2 *cols
 
 // Four samples of a stencil column from the coordinate (bx, by, bz) of its first one:
 // consecutive samples along z differ by the step vector c.
+template <bool CL = true>
 __device__ __forceinline__ void issue_four(gcell_ptr cells, const FusedLevel &L, const PtLevel &q,
                                            float bx, float by, float bz, Pending &p)
 {
-    issue_one(cells, L, bx, by, bz, p.v[0], p.fx[0], p.fy[0], p.fz[0]);
+    issue_one<CL>(cells, L, bx, by, bz, p.v[0], p.fx[0], p.fy[0], p.fz[0]);
 #pragma unroll
     for (int j = 1; j < 4; ++j)
-        issue_one(cells, L, fmaf((float)j, q.c[0], bx), fmaf((float)j, q.c[1], by),
+        issue_one<CL>(cells, L, fmaf((float)j, q.c[0], bx), fmaf((float)j, q.c[1], by),
                   fmaf((float)j, q.c[2], bz), p.v[j], p.fx[j], p.fy[j], p.fz[j]);
 }
 
@@ -163,13 +167,14 @@ __device__ __forceinline__ float3 column_base(const PtLevel &q, int s, int g, co
 }
 
 // Both halves (iz = 0..3 into lo, 4..7 into hi) of column 4 s + g from one base.
+template <bool CL = true>
 __device__ __forceinline__ void issue_column(gcell_ptr cells, const FusedLevel &L,
                                              const PtLevel &q, int s, int g, const float2 *cols,
                                              Pending &lo, Pending &hi)
 {
     const float3 b = column_base(q, s, g, cols);
-    issue_four(cells, L, q, b.x, b.y, b.z, lo);
-    issue_four(cells, L, q, fmaf(4.f, q.c[0], b.x), fmaf(4.f, q.c[1], b.y),
+    issue_four<CL>(cells, L, q, b.x, b.y, b.z, lo);
+    issue_four<CL>(cells, L, q, fmaf(4.f, q.c[0], b.x), fmaf(4.f, q.c[1], b.y),
                fmaf(4.f, q.c[2], b.z), hi);
 }
 
@@ -188,6 +193,7 @@ __device__ __forceinline__ void issue_column_half(gcell_ptr cells, const FusedLe
 // Halves 12, 13 (chunk 6) mix directions: lattice coordinates come from a table
 // (column 24 for g = 0; the iz = 8 plane for g = 1..3: rows iy = 0..4 with
 // ix = 0..3, then ix = 4 with iy = 0..3; its last point (4, 4, 8) goes to chunk 7).
+template <bool CL = true>
 __device__ __forceinline__ void issue_table_half(gcell_ptr cells, const FusedLevel &L,
                                                  const PtLevel &q, int hh, int g,
                                                  const float4 *tab, Pending &p)
@@ -195,7 +201,7 @@ __device__ __forceinline__ void issue_table_half(gcell_ptr cells, const FusedLev
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const float4 o = tab[8 * g + 4 * hh + j];
-        issue_one(cells, L, q.u0[0] + o.x * q.a[0] + o.y * q.b[0] + o.z * q.c[0],
+        issue_one<CL>(cells, L, q.u0[0] + o.x * q.a[0] + o.y * q.b[0] + o.z * q.c[0],
                   q.u0[1] + o.x * q.a[1] + o.y * q.b[1] + o.z * q.c[1],
                   q.u0[2] + o.x * q.a[2] + o.y * q.b[2] + o.z * q.c[2], p.v[j], p.fx[j], p.fy[j],
                   p.fz[j]);
@@ -260,23 +266,24 @@ __device__ __forceinline__ PtGeom make_geom(const float *x, const Frame &fr, con
     return G;
 }
 
-// Stencil origin and lattice steps of one level, in cell coordinates shifted by +1
-// (cell coordinates start at the zero border cell).
+// Stencil origin and lattice steps of one level, in cell coordinates (the voxel-centred
+// coordinate shifted by the level's border, so cell coordinates start at the first zero
+// border cell).  A point without a usable frame reads the all-zero corner cell 0 for every
+// sample, which needs no clamp.
 __device__ __forceinline__ void level_from_geom(const FusedLevel &L, const PtGeom &G, PtLevel &q)
 {
     const float st = L.step * L.inv_h, hs = 0.5f * st;
     const float xr[3] = {G.a.x, G.a.y, G.a.z}, S[3] = {G.a.w, G.b.x, G.b.y};
     const float X[3] = {G.b.z, G.b.w, G.c.x}, Y[3] = {G.c.y, G.c.z, G.c.w};
     const float Z[3] = {G.d.x, G.d.y, G.d.z};
+    const bool ok = G.d.w > 0.f;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        q.u0[c] = fmaf(-st, S[c], fmaf(xr[c], L.inv_h, 0.5f));
-        q.a[c] = hs * X[c];
-        q.b[c] = hs * Y[c];
-        q.c[c] = hs * Z[c];
+        q.u0[c] = ok ? fmaf(-st, S[c], fmaf(xr[c], L.inv_h, L.shift)) : 0.f;
+        q.a[c] = ok ? hs * X[c] : 0.f;
+        q.b[c] = ok ? hs * Y[c] : 0.f;
+        q.c[c] = ok ? hs * Z[c] : 0.f;
     }
-    if (!(G.d.w > 0.f))
-        q.u0[0] = q.u0[1] = q.u0[2] = -4.f;  // clamps to the zero border cell
 }
 
 __device__ __forceinline__ bf16x8 pack8(const f4 &lo, const f4 &hi)
@@ -341,16 +348,27 @@ struct WeightStage {
     bool pending;
 
     __device__ __forceinline__ const uint4 *chunk() const { return buf + cur * BUF + j * SLOT; }
+    // The copy is written out as the instruction itself: with the builtin the compiler
+    // cannot tell the idle buffer from the one being read, and makes the next LDS read of
+    // every wave wait for the whole copy.  Issued here, the copy is waited for only by the
+    // explicit vm_wait before the group's closing barrier (and, as the counter is in
+    // order, by waits for loads issued after it).  The instruction has no register
+    // result: its data goes to LDS at m0 + 16 lane.
     __device__ __forceinline__ void copy_group(int tid, uint4 *dst)
     {
         const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-        const int lane = tid & 63;
+        const uint32_t voff = (uint32_t)(tid & 63) * 16u;
 #pragma unroll
         for (int r = 0; r < (ROWS + NW - 1) / NW; ++r) {
             const int row = w + r * NW;
-            if ((r + 1) * NW <= ROWS || row < ROWS)
-                __builtin_amdgcn_global_load_lds((gvoid *)(src + row * 64 + lane),
-                                                 (lvoid *)(dst + row * 64), 16, 0, 0);
+            if ((r + 1) * NW <= ROWS || row < ROWS) {
+                const uint4 *g = src + row * 64;
+                const uint32_t l = (uint32_t)(uintptr_t)(lvoid *)(dst + row * 64);
+                asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, %2"
+                             :
+                             : "s"(l), "v"(voff), "s"(g)
+                             : "memory", "m0");
+            }
         }
         src += BUF;
     }
@@ -561,7 +579,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
         f4 F[MT];
         const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
         f4(*Os)[64] = obuf[tid >> 6];
-    #pragma unroll
+#pragma unroll
         for (int mt = 0; mt < MT; ++mt)
             Os[mt][lane] = z4;
 
@@ -580,21 +598,21 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
         for (int k = 0; k < a.K; ++k) {
             const float *b1 = vec + (size_t)k * 2 * WP;
             const float *b2 = b1 + WP;
-    #pragma unroll
+#pragma unroll
             for (int mt = 0; mt < MT; ++mt)
                 F[mt] = z4;
 
             // stencil chunks 0..6, two halves of four samples each, two halves in flight:
             // step c finishes halves 2c, 2c+1 and issues halves 2c+2, 2c+3
-    #pragma unroll 1
+#pragma unroll 1
             for (int c = 0; c < 5; ++c) {
                 ws.fetch(tid);
                 f4 lo, hi;
-    #pragma unroll
+#pragma unroll
                 for (int j = 0; j < 4; ++j)
                     lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
                 issue_column_half(cells, L, q, 2 * c + 2, g, cols, pa);
-    #pragma unroll
+#pragma unroll
                 for (int j = 0; j < 4; ++j)
                     hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
                 issue_column_half(cells, L, q, 2 * c + 3, g, cols, pb);
@@ -604,11 +622,11 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
             {  // chunk 5: issues the table halves of chunk 6
                 ws.fetch(tid);
                 f4 lo, hi;
-    #pragma unroll
+#pragma unroll
                 for (int j = 0; j < 4; ++j)
                     lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
                 issue_table_half(cells, L, q, 0, g, plane, pa);
-    #pragma unroll
+#pragma unroll
                 for (int j = 0; j < 4; ++j)
                     hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
                 issue_table_half(cells, L, q, 1, g, plane, pb);
@@ -618,14 +636,14 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
             {  // chunk 6: issues chunk 7's stencil sample (4, 4, 8)
                 ws.fetch(tid);
                 f4 lo, hi;
-    #pragma unroll
+#pragma unroll
                 for (int j = 0; j < 4; ++j)
                     lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
                 issue_one(cells, L, q.u0[0] + 4.f * (q.a[0] + q.b[0]) + 8.f * q.c[0],
                           q.u0[1] + 4.f * (q.a[1] + q.b[1]) + 8.f * q.c[1],
                           q.u0[2] + 4.f * (q.a[2] + q.b[2]) + 8.f * q.c[2], pa.v[0], pa.fx[0],
                           pa.fy[0], pa.fz[0]);
-    #pragma unroll
+#pragma unroll
                 for (int j = 0; j < 4; ++j)
                     hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
                 mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
@@ -642,7 +660,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
             }
             // o^{k-1} in pairs of tiles (o^0 = 0: block 1 has no such chunks)
             if (k > 0) {
-    #pragma unroll
+#pragma unroll
                 for (int qq = 0; qq < MT / 2; ++qq) {
                     ws.fetch(tid);
                     mfma_chunk<MT>(ws.chunk(), lane, pack8(Os[2 * qq][lane], Os[2 * qq + 1][lane]), F);
@@ -658,19 +676,19 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
                 issue_column_half(cells, L, q, 1, g, cols, pb);
             }
             // F1 = relu(. + b1)
-    #pragma unroll
+#pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
                 f4 bb = *reinterpret_cast<const f4 *>(b1 + 16 * mt + 4 * g);
-    #pragma unroll
+#pragma unroll
                 for (int i = 0; i < 4; ++i)
                     F[mt][i] = fmaxf(F[mt][i] + bb[i], 0.f);
             }
             // o^k = relu(W2 F1 + b2 + o^{k-1}), accumulated in place
             f4 O[MT];
-    #pragma unroll
+#pragma unroll
             for (int mt = 0; mt < MT; ++mt)
                 O[mt] = Os[mt][lane] + *reinterpret_cast<const f4 *>(b2 + 16 * mt + 4 * g);
-    #pragma unroll
+#pragma unroll
             for (int qq = 0; qq < C2; ++qq) {
                 ws.fetch(tid);
                 mfma_chunk<MT>(ws.chunk(), lane,
@@ -678,9 +696,9 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
                                O);
                 ws.template next<0>(tid);
             }
-    #pragma unroll
+#pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
-    #pragma unroll
+#pragma unroll
                 for (int i = 0; i < 4; ++i)
                     O[mt][i] = fmaxf(O[mt][i], 0.f);
                 Os[mt][lane] = O[mt];
@@ -689,7 +707,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
 
         // trailing layers: H-1 dense W -> W layers, ping-ponging between O and F
         f4 O[MT];
-    #pragma unroll
+#pragma unroll
         for (int mt = 0; mt < MT; ++mt)
             O[mt] = Os[mt][lane];
         const float *bh = vec + (size_t)a.K * 2 * WP;
@@ -700,7 +718,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
         }
         if (h < a.H - 1) {
             dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
-    #pragma unroll
+#pragma unroll
             for (int mt = 0; mt < MT; ++mt)
                 O[mt] = F[mt];
         }
@@ -708,7 +726,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
         const float *wl = bh + (size_t)(a.H - 1) * WP;
         const float bl = wl[WP];
         float acc = 0.f;
-    #pragma unroll
+#pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
             f4 w = *reinterpret_cast<const f4 *>(wl + 16 * mt + 4 * g);
             acc += w[0] * O[mt][0] + w[1] * O[mt][1] + w[2] * O[mt][2] + w[3] * O[mt][3];
@@ -742,7 +760,14 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
 // input unit), so the unscaled product lands in the output's units.  ReLU outputs that
 // feed an FP8 layer are clamped at 448, the residual stream only where it is
 // converted.
-template <int MT, int NW, bool F8>
+// CL = false: the pass without per-sample clamps.  It runs the tiles of clouds whose every
+// stencil level has a zero border wide enough for points inside the grid box (FusedCloud::
+// fast); points outside the box get no frame there (all their samples read the zero cell)
+// and are left to the second pass.  CL = true: the clamped pass, which computes the tiles
+// of the other clouds and recomputes every tile that holds a point outside its grid box; it
+// skips all other tiles after reading their positions.  Launched one after the other, the
+// two passes give every point the clamped kernel's result.
+template <int MT, int NW, bool F8, bool CL>
 __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
                                                           const uint4 *__restrict__ frags,
                                                           const float *__restrict__ vec)
@@ -766,18 +791,31 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
         // would hold registers across the whole tile and force spills
         asm volatile("" ::: "memory");
         const FusedCloud &cl = a.cl[tile_cloud(a, t)];
-        ws.begin(frags, tid);
-
+        if (!CL && !cl.fast)
+            continue;  // uniform: the clamped pass computes this cloud
         const int64_t pl = (t - cl.tile_begin) * (16 * NW) + (tid >> 6) * 16 + n;
         const bool in = pl < cl.P;
         const int64_t p = cl.p_begin + pl;
+        bool outside = false;  // a usable position outside the grid box
+        if (in) {
+            const float x0 = a.pos[3 * p], x1 = a.pos[3 * p + 1], x2 = a.pos[3 * p + 2];
+            outside = isfinite(x0) && isfinite(x1) && isfinite(x2) &&
+                      !(x0 >= cl.amin[0] && x0 <= cl.amax[0] && x1 >= cl.amin[1] &&
+                        x1 <= cl.amax[1] && x2 >= cl.amin[2] && x2 <= cl.amax[2]);
+        }
+        if (CL && cl.fast && !__syncthreads_or(outside))
+            continue;  // uniform: the unclamped pass computed this tile
+        ws.begin(frags, tid);
+
         float gamma;
         bool valid;
         {
             float x[3];
             Frame fr;
             valid = point_frame(a, p, in, x, fr);
-            gamma = fr.gamma;
+            if (!CL && outside)
+                valid = false;  // no frame: its samples read the zero cell
+            gamma = valid ? fr.gamma : 0.f;
             // the four lanes of a point write the same slot; each reads its own write
             geom[(tid >> 6) * 16 + n] = make_geom(x, fr, cl.amin, valid);
         }
@@ -796,65 +834,71 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
             gcell_ptr cells = (gcell_ptr)L.cells;
             PtLevel q;
             level_from_geom(L, geom[(tid >> 6) * 16 + n], q);
-            Pending pa, pb;
-            issue_column(cells, L, q, 0, g, cols, pa, pb);
             const float *b1 = vec + (size_t)k * 2 * WP;
             const float *b2 = b1 + WP;
             // the first layer accumulates onto its bias
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
                 F[mt] = *reinterpret_cast<const f4 *>(b1 + 16 * mt + 4 * g);
+            Pending pa, pb;
+            issue_column<CL>(cells, L, q, 0, g, cols, pa, pb);
 #pragma unroll 1
             for (int c = 0; c < 5; ++c) {  // chunks 0..4: halves 2c, 2c+1 in, 2c+2, 2c+3 out
-                ws.fetch(tid);
                 f4 lo, hi;
                 // both halves of the next column share its base
                 const float3 cb = column_base(q, c + 1, g, cols);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
-                issue_four(cells, L, q, cb.x, cb.y, cb.z, pa);
+                issue_four<CL>(cells, L, q, cb.x, cb.y, cb.z, pa);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
-                issue_four(cells, L, q, fmaf(4.f, q.c[0], cb.x), fmaf(4.f, q.c[1], cb.y),
+                // the weight copy goes out after the waits for this chunk's samples (the
+                // empty statement keeps the finished samples from sinking below it)
+                asm volatile("" ::"v"(lo), "v"(hi));
+                ws.fetch(tid);
+                issue_four<CL>(cells, L, q, fmaf(4.f, q.c[0], cb.x), fmaf(4.f, q.c[1], cb.y),
                            fmaf(4.f, q.c[2], cb.z), pb);
                 mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
                 ws.template next<8>(tid);
             }
             {  // chunk 5: issues the table halves of chunk 6
-                ws.fetch(tid);
                 f4 lo, hi;
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
-                issue_table_half(cells, L, q, 0, g, plane, pa);
+                issue_table_half<CL>(cells, L, q, 0, g, plane, pa);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
-                issue_table_half(cells, L, q, 1, g, plane, pb);
+                asm volatile("" ::"v"(lo), "v"(hi));
+                ws.fetch(tid);
+                issue_table_half<CL>(cells, L, q, 1, g, plane, pb);
                 mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
                 ws.template next<8>(tid);
             }
             {  // chunk 6: issues chunk 7's stencil sample (4, 4, 8)
-                ws.fetch(tid);
                 f4 lo, hi;
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
-                issue_one(cells, L, q.u0[0] + 4.f * (q.a[0] + q.b[0]) + 8.f * q.c[0],
+                issue_one<CL>(cells, L, q.u0[0] + 4.f * (q.a[0] + q.b[0]) + 8.f * q.c[0],
                           q.u0[1] + 4.f * (q.a[1] + q.b[1]) + 8.f * q.c[1],
                           q.u0[2] + 4.f * (q.a[2] + q.b[2]) + 8.f * q.c[2], pa.v[0], pa.fx[0],
                           pa.fy[0], pa.fz[0]);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
+                asm volatile("" ::"v"(lo), "v"(hi));
+                ws.fetch(tid);
                 mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
                 ws.template next<1>(tid);
             }
             {  // chunk 7: stencil sample (4, 4, 8), gamma, and the odd tile of o^{k-1}
-                ws.fetch(tid);
                 const float sv = finish_one(pa.v[0], pa.fx[0], pa.fy[0], pa.fz[0]);
+                asm volatile("" ::"v"(sv));
+                ws.fetch(tid);
                 const f4 lo = f4{g == 0 ? sv : 0.f, g == 0 ? gamma : 0.f, 0.f, 0.f};
                 mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, (!F8 && (MT & 1)) ? O[MT - 1] : z4),
                                F);
@@ -1306,13 +1350,15 @@ ds_status launch_kind(hipStream_t s, const ds_net *net, FusedArgs a, int grid)
     DS_CHECK(g < ((int64_t)1 << 31), DS_ERR_INVALID_ARG, "too many tiles for one launch");
     if constexpr (F8) {
         static_assert(KIND == DS_KERNEL_REGISTER, "the FP8 form has the register kernel only");
-        k_fused_reg<MT, NW, true><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_fp8, net->vec8);
+        k_fused_reg<MT, NW, true, false><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_fp8, net->vec8);
+        k_fused_reg<MT, NW, true, true><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_fp8, net->vec8);
     } else if constexpr (KIND == DS_KERNEL_PIPELINED) {
         k_fused<MT, NW><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_bf16, net->vec);
     } else if constexpr (KIND == DS_KERNEL_WIDE) {
         k_fused_wide<MT, NW><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_bf16, net->vec);
     } else {
-        k_fused_reg<MT, NW, false><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_bf16, net->vec);
+        k_fused_reg<MT, NW, false, false><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_bf16, net->vec);
+        k_fused_reg<MT, NW, false, true><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_bf16, net->vec);
     }
     DS_HIP(hipGetLastError());
     return DS_OK;

@@ -39,7 +39,10 @@ constexpr int kMaxK = 16;
 struct Level {
     int nx, ny, nz;          // level dims (ceil(n / 2^i))
     int64_t off;             // offset in the float32 pyramid (elements)
-    int64_t cell_off;        // offset in the corner-packed pyramids (cells)
+    int64_t cell_off;        // offset in the corner-packed FP16 pyramid (cells)
+    int64_t cell32_off;      // offset in the corner-packed float32 pyramid (cells)
+    int bd;                  // zero border of the FP16 cells (cells per side, >= 1)
+    bool fast;               // bd covers every stencil sample of a point inside the grid box
     float h;                 // voxel size (world units)
 };
 
@@ -74,6 +77,7 @@ struct ds_cloud {
     mutable float4 *cells32 = nullptr;
     uint4 *cells = nullptr;    // corner-packed FP16 levels (8 corners per cell)
     int64_t n_cells = 0;
+    int64_t n_cells32 = 0;     // cells of the float32 corner-packed levels
     void *tables = nullptr;    // device: GatherLevel[K] then FusedLevel[K]
     float *mu = nullptr;       // extinction sigma_max * d on the base grid (tracer medium)
     // the same extinction corner-packed (8 float32 corners, 32 bytes per cell, zero border),
@@ -193,8 +197,11 @@ struct StridedGemm {
 ds_status gemm_strided(hipStream_t s, const StridedGemm &g, float *split_ws = nullptr,
                        size_t ws_floats = 0);
 // same product with operands rounded to BF16 and FP32 accumulation on the matrix
-// cores; split_ws (ws_floats floats, may be NULL) enables deterministic split-K
-ds_status gemm_bf16(hipStream_t s, const StridedGemm &g, float *split_ws, size_t ws_floats);
+// cores; split_ws (ws_floats floats, may be NULL) enables deterministic split-K.  x3:
+// each operand as a BF16 pair hi + lo (lo = the rounding remainder), three products
+// hi hi + hi lo + lo hi per step
+ds_status gemm_bf16(hipStream_t s, const StridedGemm &g, float *split_ws, size_t ws_floats,
+                    bool x3 = false);
 int splitk_count(const StridedGemm &g);
 ds_status layer_epilogue(hipStream_t s, int M, int N, float *pre, int ldp, const float *gv, int ldg,
                          const float *gw, int ldgw, const float *bias, const float *R, int ldr,
@@ -214,17 +221,19 @@ ds_status fused_prepare(ds_net *net);
 ds_status fused_pack_bf16(hipStream_t s, ds_net *net);
 struct FusedLevel {
     const uint4 *cells;
-    int cx, cy;          // cell-grid dims in x and y (level dims + 2)
-    float hi_x, hi_y, hi_z;  // clamp bounds of the shifted cell coordinate (level dims + 1)
+    int cx, cy;          // cell-grid dims in x and y (level dims + 2 bd)
+    float hi_x, hi_y, hi_z;  // clamp bounds of the shifted cell coordinate (dims + 2 bd - 1)
     float inv_h;
     float step;          // 2^(k-1) / mean
+    float shift;         // bd - 1/2: voxel-centred coordinate to cell coordinate
+    int fast;            // 1: samples of points inside the grid box need no clamp
 };
 constexpr int kMaxBatch = 16;  // clouds per fused launch
 struct FusedCloud {
     const FusedLevel *lvt;   // device table, K entries
     float amin[3], amax[3];
     float inv_mean;
-    int32_t pad_;
+    int32_t fast;            // every stencil level's border holds points inside the box
     int64_t p_begin;         // first point of this cloud in the point arrays
     int64_t P;               // its point count
     int64_t tile_begin;      // first tile (set by the launcher for its tile size)
@@ -282,6 +291,9 @@ struct TracerParams {
     // the fraction f: 1 / (1 - f), so that albedo x weight is the unreduced medium's
     // scattering over the reduced extinction
     float pf_scale = 1.f;
+    // extinction scale of the medium (1 - a f with a chopped table, else 1); albedo above is
+    // then the thinner medium's a (1 - f) / (1 - a f)
+    float ext_scale = 1.f;
     const float4 *set_dw = nullptr;
     const uint32_t *set_thr = nullptr;
     int set_m = 0;

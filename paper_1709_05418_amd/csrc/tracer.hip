@@ -124,6 +124,9 @@ struct Medium {
     float hx, hy, hz;     // clamp bounds of the shifted cell coordinate (grid dims + 1)
     V3 amin, amax;
     float inv_h, maj;
+    float inv_ff;         // mean free-flight length 1 / (maj * extinction scale); the scale
+                          // thins the medium uniformly (the chop of a tabulated phase
+                          // function), so collision and transmittance ratios keep maj
 };
 
 // Voxel-centred trilinear extinction, zero outside the grid.  The cell coordinate (the
@@ -188,7 +191,7 @@ __device__ bool delta_track(const Medium &M, V3 o, V3 d, Rng &r, V3 &x, int64_t 
     if (!clip(M, o, d, t0, t1) || !(M.maj > 0.f))
         return false;
     float t = t0;
-    const float inv = 1.f / M.maj;
+    const float inv = M.inv_ff;
     while (steps < kMaxSteps) {
         ++steps;
         t += exp_flight(r.u()) * inv;
@@ -213,7 +216,7 @@ __device__ float ratio_track(const Medium &M, V3 o, V3 d, Rng &r, int64_t &steps
     const float inv = 1.f / M.maj;
     while (steps < kMaxSteps) {
         ++steps;
-        t += exp_flight(r.u()) * inv;
+        t += exp_flight(r.u()) * M.inv_ff;
         if (t >= t1)
             break;
         T *= 1.f - mu_at(M, madd(o, t, d)) * inv;
@@ -840,7 +843,7 @@ ds_status medium_cells(hipStream_t s, const ds_cloud *c)
     return DS_OK;
 }
 
-Medium medium(const ds_cloud *c)
+Medium medium(const ds_cloud *c, float ext_scale = 1.f)
 {
     Medium M;
     M.cells = c->mu_cells;
@@ -855,6 +858,7 @@ Medium medium(const ds_cloud *c)
                 (float)((double)c->aabb_min[2] + (double)c->nz * c->h0));
     M.inv_h = (float)(1.0 / (double)c->h0);
     M.maj = c->majorant;
+    M.inv_ff = (float)(1.0 / ((double)c->majorant * (double)ext_scale));
     return M;
 }
 
@@ -891,7 +895,7 @@ void launch_trace_li(hipStream_t s, const ds_cloud *c, const TracerParams &tp, c
     const bool tab = tp.ph_n > 0 || tp.pf_n > 0, dir = tp.include_direct != 0;
     auto k = tab ? (dir ? k_trace_li<true, true> : k_trace_li<true, false>)
                  : (dir ? k_trace_li<false, true> : k_trace_li<false, false>);
-    k<<<grid_of(P, sp), kPaths, 0, s>>>(medium(c), tp, pos, view, light, P, s0, spp, sp, seed,
+    k<<<grid_of(P, sp), kPaths, 0, s>>>(medium(c, tp.ext_scale), tp, pos, view, light, P, s0, spp, sp, seed,
                                          mask, mask_bits, partial);
 }
 
@@ -902,7 +906,7 @@ void launch_render_mc(hipStream_t s, const ds_cloud *c, const TracerParams &tp, 
     const bool tab = tp.ph_n > 0 || tp.pf_n > 0, set = tp.light_mode == kLightSetMode;
     auto k = tab ? (set ? k_render_mc<true, true> : k_render_mc<true, false>)
                  : (set ? k_render_mc<false, true> : k_render_mc<false, false>);
-    k<<<grid_of(N, sp), kPaths, 0, s>>>(medium(c), tp, wl, ray_o, ray_d, N, spp, sp, seed,
+    k<<<grid_of(N, sp), kPaths, 0, s>>>(medium(c, tp.ext_scale), tp, wl, ray_o, ray_d, N, spp, sp, seed,
                                          partial);
 }
 
@@ -1013,7 +1017,7 @@ ds_status tracer_first_hits(hipStream_t s, const ds_cloud *c, const TracerParams
              "the light direction is not a usable vector");
     const V3 wl = v3(l[0], l[1], l[2]);
     DS_TRY_MEDIUM(s, c);
-    k_first_hits<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(medium(c), tp, wl, ray_o, ray_d, N,
+    k_first_hits<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(medium(c, tp.ext_scale), tp, wl, ray_o, ray_d, N,
                                                              seed, sample, pos, view, direct, hit);
     DS_HIP(hipGetLastError());
     return DS_OK;
@@ -1074,7 +1078,7 @@ ds_status tracer_first_hits_set(hipStream_t s, const ds_cloud *c, const TracerPa
              DS_ERR_INVALID_ARG, "internal error: no light set");
     DS_TRY_MEDIUM(s, c);
     k_first_hits_set<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(
-        medium(c), tp, draws, ray_o, ray_d, N, seed, sample, pos, view, light, weight, direct, hit);
+        medium(c, tp.ext_scale), tp, draws, ray_o, ray_d, N, seed, sample, pos, view, light, weight, direct, hit);
     DS_HIP(hipGetLastError());
     return DS_OK;
 }

@@ -300,30 +300,47 @@ __device__ __forceinline__ Stage stage_of(const float *base, int64_t s_row, int6
     return st;
 }
 
-// Stores one operand's NE values (as BF16) at [row][k] of an LDS tile.
-__device__ __forceinline__ void stage_store(__bf16 (*T)[TKP], const Stage &st, int tid,
-                                            const float (&v)[NE])
+// Stores one operand's NE values (as BF16) at [row][k] of an LDS tile; with L, also the
+// rounding remainder v - bf16(v) as a second BF16 term (the pair carries about 16
+// significant bits).
+template <bool X3>
+__device__ __forceinline__ void stage_store(__bf16 (*T)[TKP], __bf16 (*L)[TKP], const Stage &st,
+                                            int tid, const float (&v)[NE])
 {
     if (st.kc) {
 #pragma unroll
         for (int h = 0; h < NE; h += 8) {
-            bf16x8 x;
+            bf16x8 x, y;
 #pragma unroll
-            for (int j = 0; j < 8; ++j)
+            for (int j = 0; j < 8; ++j) {
                 x[j] = (__bf16)v[h + j];
+                if (X3)
+                    y[j] = (__bf16)(v[h + j] - (float)x[j]);
+            }
             *reinterpret_cast<bf16x8 *>(&T[tid >> 2][st.kq + h]) = x;
+            if (X3)
+                *reinterpret_cast<bf16x8 *>(&L[tid >> 2][st.kq + h]) = y;
         }
     } else {
 #pragma unroll
-        for (int j = 0; j < NE; ++j)
-            T[tid & 63][st.kq + 4 * j] = (__bf16)v[j];
+        for (int j = 0; j < NE; ++j) {
+            const __bf16 x = (__bf16)v[j];
+            T[tid & 63][st.kq + 4 * j] = x;
+            if (X3)
+                L[tid & 63][st.kq + 4 * j] = (__bf16)(v[j] - (float)x);
+        }
     }
 }
 
+// X3: both operands as BF16 pairs (hi + lo) and three products per step, hi hi + hi lo +
+// lo hi, on the same matrix cores (the lo lo product is below FP32 rounding of the sum).
+template <bool X3>
 __global__ void __launch_bounds__(256) k_gemm_bf16(StridedGemm g, int kc, float *P)
 {
     __shared__ __attribute__((aligned(16))) __bf16 As[TM][TKP];  // [row][k]
     __shared__ __attribute__((aligned(16))) __bf16 Bt[TN][TKP];  // [col][k]
+    __shared__ __attribute__((aligned(16))) __bf16 Al[X3 ? TM : 1][TKP];  // remainders
+    __shared__ __attribute__((aligned(16))) __bf16 Bl[X3 ? TN : 1][TKP];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int g4 = lane >> 4, n16 = lane & 15;
     const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
@@ -345,8 +362,8 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(StridedGemm g, int kc, float 
         sb.load(kbeg, kend, vb);
     }
     for (int k0 = kbeg; k0 < kend; k0 += TK) {
-        stage_store(As, sa, tid, va);
-        stage_store(Bt, sb, tid, vb);
+        stage_store<X3>(As, Al, sa, tid, va);
+        stage_store<X3>(Bt, Bl, sb, tid, vb);
         __syncthreads();
         if (k0 + TK < kend) {  // the next step's values, in flight during the products
             sa.load(k0 + TK, kend, va);
@@ -366,6 +383,23 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(StridedGemm g, int kc, float 
                 for (int j = 0; j < 2; ++j)
                     acc[i][j] =
                         __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+            if (X3) {
+                bf16x8 al[2], bl[2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    al[t] = *reinterpret_cast<const bf16x8 *>(&Al[wr + 16 * t + n16][ks + 8 * g4]);
+                    bl[t] = *reinterpret_cast<const bf16x8 *>(&Bl[wc + 16 * t + n16][ks + 8 * g4]);
+                }
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j) {
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], bl[j], acc[i][j],
+                                                                            0, 0, 0);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], b[j], acc[i][j],
+                                                                            0, 0, 0);
+                    }
+            }
         }
         __syncthreads();
     }
@@ -465,7 +499,7 @@ int splitk_count(const StridedGemm &g)
     return S;
 }
 
-ds_status gemm_bf16(hipStream_t s, const StridedGemm &g, float *split_ws, size_t ws_floats)
+ds_status gemm_bf16(hipStream_t s, const StridedGemm &g, float *split_ws, size_t ws_floats, bool x3)
 {
     if (g.M <= 0 || g.N <= 0)
         return DS_OK;
@@ -474,7 +508,10 @@ ds_status gemm_bf16(hipStream_t s, const StridedGemm &g, float *split_ws, size_t
     const int kc = ((ksteps + S - 1) / S) * TK;
     const bool split = S > 1 && (size_t)S * g.M * g.N <= ws_floats;
     dim3 grid((g.N + TN - 1) / TN, (g.M + TM - 1) / TM, split ? S : 1);
-    k_gemm_bf16<<<grid, 256, 0, s>>>(g, split ? kc : ksteps * TK, split ? split_ws : nullptr);
+    if (x3)
+        k_gemm_bf16<true><<<grid, 256, 0, s>>>(g, split ? kc : ksteps * TK, split ? split_ws : nullptr);
+    else
+        k_gemm_bf16<false><<<grid, 256, 0, s>>>(g, split ? kc : ksteps * TK, split ? split_ws : nullptr);
     if (split)
         k_splitk_sum<<<grid1((int64_t)g.M * g.N), 256, 0, s>>>(split_ws, S, g);
     DS_HIP(hipGetLastError());

@@ -247,11 +247,8 @@ def judge_sun_sky(args, ctx, cloud, net, prm, precs, log, kind="sunsky"):
 
 
 def judge_density(args, dev="cuda"):
-    """The held-out judge scene: a seeded cloud, or the sphere-and-box scene that tests the
-    network on shapes unlike its training clouds."""
+    """The held-out judge scene: a seeded cloud."""
     import torch
-    if args.judge_scene == "spherebox":
-        return synth.sphere_box_density(args.judge_n, device=dev, dtype=torch.bfloat16)
     return synth.cloud_density(args.judge_n, args.seed + 5000, worley=0.3, device=dev,
                                dtype=torch.bfloat16)
 
@@ -342,12 +339,11 @@ def main(argv=None):
     ap.add_argument("--adaptive-max", type=int, default=65536)
     ap.add_argument("--phase", default="hg", choices=["hg", "lm"],
                     help="Henyey-Greenstein g = 0.85, or a tabulated Lorenz-Mie function of "
-                         "cloud droplets, chopped (reduced density) for data and rendering and "
-                         "unchopped for the first collision's direct term (Sec. 5.1)")
+                         "cloud droplets, chopped (the tracer thins the medium, Sec. 3.1) for "
+                         "data and rendering and unchopped for the first collision's direct "
+                         "term (Sec. 3.1, Sec. 5.1)")
     ap.add_argument("--chop-deg", type=float, default=5.0)
     ap.add_argument("--no-judge", action="store_true", help="stop after training")
-    ap.add_argument("--judge-scene", default="cloud", choices=["cloud", "spherebox"],
-                    help="held-out judge scene: a seeded cloud, or a homogeneous sphere and box")
     ap.add_argument("--compare-stencils", action="store_true",
                     help="train and judge the RPNN on the 5x5x9, 3x3x5 and 2x2x3 stencils "
                          "(Fig. 10, right) instead of the single network")
@@ -358,13 +354,6 @@ def main(argv=None):
                     help="no network: path-trace the judge crop, front- and back-lit, under "
                          "isotropic, HG, full, chopped and chopped-after-first-bounce Lorenz-Mie "
                          "phase functions; equal-time variance and image change (Fig. 3)")
-    ap.add_argument("--spp-study", action="store_true",
-                    help="also render the crop with the network at 1, 2, 4 ... --crop-spp "
-                         "samples per pixel: noise, error and time (Fig. 12)")
-    ap.add_argument("--caps", type=int, nargs="*", default=None,
-                    help="no network: path-trace the judge crop at --ref-spp with each cap on "
-                         "the scattering events per path (0: none) and report time and image "
-                         "change (Fig. 2)")
     ap.add_argument("--save-theta", default=None)
     ap.add_argument("--load-theta", default=None,
                     help="judge a network saved by --save-theta instead of training one")
@@ -372,26 +361,22 @@ def main(argv=None):
     log = lambda *a: print("[learn]", *a, flush=True)
     dev = "cuda"
     ctx = ds.Context(0)
-    albedo, sigma_scale, phases = 0.999, 1.0, (None, None)
+    albedo, phases = 0.999, (None, None)
     if args.phase == "lm":
         _, p_lm, g_lm = synth.cloud_droplet_phase()
         phases = (ds.Phase(ctx, p_lm, args.chop_deg), ds.Phase(ctx, p_lm))
         f = phases[0].removed
-        # the chopped forward peak travels on unscattered: reduced extinction and albedo
-        sigma_scale = 1.0 - albedo * f
-        albedo = albedo * (1.0 - f) / sigma_scale
         log(f"Lorenz-Mie phase: mean cosine {g_lm:.4f}; chopped at {args.chop_deg} deg, "
-            f"{100 * f:.1f} % of the scattering removed; extinction x{sigma_scale:.4f}, albedo "
-            f"{albedo:.5f}, chopped mean cosine {phases[0].mean_cos:.4f}")
-    args.sigma = lambda n: float(n) * sigma_scale
+            f"{100 * f:.1f} % of the scattering removed (the tracer thins the medium: extinction "
+            f"x{1.0 - albedo * f:.4f}, albedo {albedo * (1.0 - f) / (1.0 - albedo * f):.5f}), "
+            f"chopped mean cosine {phases[0].mean_cos:.4f}")
+    args.sigma = lambda n: float(n)
     prm = ds.TracerParams(albedo, 0.85, 1.0, ds.DS_LIGHT_DIRECTIONAL, 0, phase=phases[0],
                           phase_first=phases[1])
     args.phases = phases
     K, W = args.K, args.W
     L = int(math.ceil(math.log2(args.n))) + 1
     per = args.records // args.clouds
-    if args.caps:
-        return cap_study(args, ctx, prm, log)
     if args.phase_study:
         return phase_study(args, ctx, log)
     if args.load_theta:
@@ -514,8 +499,6 @@ def main(argv=None):
             f"{j['rel_l1_direct_only']:.4f}), RMSE {j['rmse']:.5f}; reference noise "
             f"{j['ref_noise_rel']:.4f}; network {j['seconds_network']:.2f}s vs reference "
             f"{j['seconds_reference']:.2f}s; TTUV speedup {j['ttuv_speedup']:.0f}x")
-    if args.spp_study:
-        summary.update(spp_study(args, ctx, jc, net, prm, light, log))
     if args.sun_sky and args.target == "li":
         summary.update(judge_sun_sky(args, ctx, jc, net, prm, precs, log))
     if args.envmap and args.target == "li":
@@ -523,7 +506,7 @@ def main(argv=None):
     summary.update(base)
     summary.update({"judge_n": args.judge_n, "frame": [args.width, args.height],
                     "crop": args.crop, "crop_spp": args.crop_spp, "ref_spp": args.ref_spp,
-                    "light": args.light, "phase": args.phase, "judge_scene": args.judge_scene})
+                    "light": args.light, "phase": args.phase})
     print(json.dumps(summary), flush=True)
     ds.ds_adam_destroy(opt)
     net.close()
@@ -686,45 +669,16 @@ def _compare_judge(args, ctx, prm, nets, held, out, log, z, t):
         net.close()
     out.update({"steps": args.steps, "batch": args.batch, "K": K, "W": W,
                 "light": args.light, "crop": args.crop, "ref_spp": args.ref_spp,
-                "judge_n": args.judge_n, "judge_scene": args.judge_scene, "held_out": held})
+                "judge_n": args.judge_n, "held_out": held})
     print(json.dumps(out), flush=True)
     _close(args, ctx)
-
-
-def spp_study(args, ctx, cloud, net, prm, light, log):
-    """Fig. 12: noise and error of the network renderer against samples per pixel, on the
-    centred crop, BF16: relative noise (sqrt of the summed pixel variances of the mean over
-    the image sum), relative L1 against a path-traced reference, and time per sample per
-    pixel.  Returns summary entries."""
-    import torch
-    c = args.crop
-    co, cd = camera(args.width, args.height,
-                    crop=((args.width - c) // 2, (args.height - c) // 2, c, c), seed=2)
-    ref, _ = reference(ctx, cloud, prm, light, co, cd, args.ref_spp, 11)
-    out = {}
-    spp = 1
-    while spp <= args.crop_spp:
-        torch.cuda.synchronize()
-        t0 = time.time()
-        img, var, _, _ = ds.ds_render_rpnn(ctx.h, cloud.h, net.h, ds.DS_PREC_BF16, prm, light,
-                                           co, cd, spp, 23, args.fallback_spp)
-        torch.cuda.synchronize()
-        sec = time.time() - t0
-        noise = float(math.sqrt(float(var.double().sum())) / max(float(img.double().sum()), 1e-300))
-        l1, _ = image_errors(img, ref)
-        out.update({f"spp_{spp}_noise_rel": noise, f"spp_{spp}_rel_l1": l1,
-                    f"spp_{spp}_seconds": sec})
-        log(f"{spp} spp: noise {noise:.5f}, rel L1 {l1:.4f}, {sec * 1e3:.1f} ms "
-            f"({c}^2 crop, BF16)")
-        spp *= 2
-    return out
 
 
 def phase_study(args, ctx, log):
     """Fig. 3: the path tracer under five phase-function set-ups on the centred crop of the
     judge scene, front- and back-lit, each at --ref-spp samples per pixel: isotropic,
-    Henyey-Greenstein (g 0.857), the full Lorenz-Mie function, the chopped one (reduced
-    extinction and albedo, chopped everywhere) and the chopped one with the full function
+    Henyey-Greenstein (g 0.857), the full Lorenz-Mie function, the chopped one (thinner
+    medium, chopped everywhere) and the chopped one with the full function
     for the first collision's direct term.  Reports time, mean pixel, the equal-time
     variance (render time x mean pixel variance of the mean, relative to the isotropic
     set-up) and the relative L1 against the full Lorenz-Mie image."""
@@ -734,22 +688,18 @@ def phase_study(args, ctx, log):
     _, p_lm, g_lm = synth.cloud_droplet_phase()
     full, chop = ds.Phase(ctx, p_lm), ds.Phase(ctx, p_lm, args.chop_deg)
     f = chop.removed
-    s_red = 1.0 - albedo * f
-    a_red = albedo * (1.0 - f) / s_red
     d = judge_density(args)
     amin, h0 = synth.unit_box(args.judge_n)
     Lj = min(16, int(math.ceil(math.log2(args.judge_n))) + 1)
-    sig = float(args.n)
-    cl = ds.Cloud(ctx, d, sig, amin, h0, Lj, args.K)
-    cl_red = ds.Cloud(ctx, d, sig * s_red, amin, h0, Lj, args.K)
+    cl = ds.Cloud(ctx, d, float(args.n), amin, h0, Lj, args.K)
     del d
-    setups = [("isotropic", cl, ds.TracerParams(albedo, 0.0, 1.0)),
-              ("hg_0.857", cl, ds.TracerParams(albedo, 0.857, 1.0)),
-              ("lm", cl, ds.TracerParams(albedo, 0.0, 1.0, phase=full, phase_first=full)),
-              ("lm_chopped", cl_red, ds.TracerParams(a_red, 0.0, 1.0, phase=chop,
-                                                     phase_first=chop)),
-              ("lm_chopped_full_first", cl_red, ds.TracerParams(a_red, 0.0, 1.0, phase=chop,
-                                                                phase_first=full))]
+    # with the chopped table the tracer traces the thinner medium itself
+    setups = [("isotropic", ds.TracerParams(albedo, 0.0, 1.0)),
+              ("hg_0.857", ds.TracerParams(albedo, 0.857, 1.0)),
+              ("lm", ds.TracerParams(albedo, 0.0, 1.0, phase=full, phase_first=full)),
+              ("lm_chopped", ds.TracerParams(albedo, 0.0, 1.0, phase=chop, phase_first=chop)),
+              ("lm_chopped_full_first", ds.TracerParams(albedo, 0.0, 1.0, phase=chop,
+                                                        phase_first=full))]
     c = args.crop
     co, cd = camera(args.width, args.height,
                     crop=((args.width - c) // 2, (args.height - c) // 2, c, c), seed=2)
@@ -760,10 +710,10 @@ def phase_study(args, ctx, log):
         for lname in ("front", "back"):
             light = synth.table1_lights()[lname]
             imgs, ttuv = {}, {}
-            for name, cloud, prm in setups:
+            for name, prm in setups:
                 torch.cuda.synchronize()
                 t0 = time.time()
-                m, v = reference(ctx, cloud, prm, light, co, cd, args.ref_spp, 11)
+                m, v = reference(ctx, cl, prm, light, co, cd, args.ref_spp, 11)
                 torch.cuda.synchronize()
                 sec = time.time() - t0
                 imgs[name] = m
@@ -780,55 +730,9 @@ def phase_study(args, ctx, log):
                     f"isotropic, rel L1 against full LM {l1:.4f}")
     finally:
         cl.close()
-        cl_red.close()
         full.close()
         chop.close()
     print(json.dumps(out), flush=True)
-    _close(args, ctx)
-
-
-def cap_study(args, ctx, prm, log):
-    """Fig. 2: path-traced render time and image against a cap on the scattering events of
-    a path (max_interactions, 0 = none), on the centred crop of the judge scene.  Every cap
-    uses the same random streams, so the image differences are the light of the longer
-    paths that the cap removes."""
-    import json
-    import torch
-    d = judge_density(args)
-    amin, h0 = synth.unit_box(args.judge_n)
-    Lj = min(16, int(math.ceil(math.log2(args.judge_n))) + 1)
-    jc = ds.Cloud(ctx, d, args.sigma(args.n), amin, h0, Lj, args.K)
-    del d
-    light = synth.table1_lights()[args.light]
-    c = args.crop
-    co, cd = camera(args.width, args.height,
-                    crop=((args.width - c) // 2, (args.height - c) // 2, c, c), seed=2)
-    out = {"judge_n": args.judge_n, "crop": c, "spp": args.ref_spp, "light": args.light,
-           "albedo": prm.albedo, "caps": args.caps}
-    imgs = {}
-    for cap in args.caps:
-        p = ds.TracerParams(prm.albedo, prm.g, prm.irradiance, prm.light_mode, cap, 0,
-                            prm.phase, prm.phase_first)
-        torch.cuda.synchronize()
-        t0 = time.time()
-        m, v = reference(ctx, jc, p, light, co, cd, args.ref_spp, 11)
-        torch.cuda.synchronize()
-        sec = time.time() - t0
-        imgs[cap] = m
-        out[f"cap_{cap}_seconds"] = sec
-        out[f"cap_{cap}_mean"] = float(m.mean())
-        out[f"cap_{cap}_noise_rel"] = float(math.sqrt(float(v.sum())) / max(float(m.sum()), 1e-300))
-        log(f"cap {cap or 'none'}: {sec:.2f}s for {c}^2 x {args.ref_spp} spp, mean pixel "
-            f"{float(m.mean()):.5f}")
-    full = imgs[0] if 0 in imgs else imgs[max(args.caps)]
-    for cap, m in imgs.items():
-        l1, _ = image_errors(m, full)
-        out[f"cap_{cap}_rel_l1_vs_uncapped"] = l1
-        log(f"cap {cap or 'none'}: rel L1 against the uncapped image {l1:.4f}, time "
-            f"{out[f'cap_{cap}_seconds'] / out[f'cap_{0 if 0 in imgs else max(args.caps)}_seconds']:.3f}"
-            f" of it")
-    print(json.dumps(out), flush=True)
-    jc.close()
     _close(args, ctx)
 
 

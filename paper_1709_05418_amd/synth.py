@@ -144,26 +144,6 @@ def cloud_density(n, seed: int, worley: float = 0.0, device="cpu",
     return out
 
 
-def sphere_box_density(n: int, device="cpu", dtype=torch.float32, slab: int = 16,
-                       sphere=((-0.14, 0.0, 0.0), 0.2),
-                       box=((0.02, -0.15, -0.15), (0.32, 0.15, 0.15))) -> torch.Tensor:
-    """A non-cloud test scene (Sec. 7, non-cloud shaped objects): the union of a
-    homogeneous sphere and a homogeneous axis-aligned box, density 1 inside and 0 outside,
-    hard edges, on an n^3 grid fitted to the unit box (coordinates centred on the box
-    centre).  A voxel takes the value of its centre."""
-    (cx, cy, cz), r = sphere
-    (x0, y0, z0), (x1, y1, z1) = box
-    out = torch.empty((n, n, n), dtype=dtype, device=device)
-    c = (torch.arange(n, device=device, dtype=torch.float64) + 0.5) / n - 0.5
-    for s0 in range(0, n, slab):
-        s1 = min(n, s0 + slab)
-        pz, py, px = torch.meshgrid(c[s0:s1], c, c, indexing="ij")
-        inside = ((px - cx) ** 2 + (py - cy) ** 2 + (pz - cz) ** 2) <= r * r
-        inside |= ((px >= x0) & (px <= x1) & (py >= y0) & (py <= y1) & (pz >= z0) & (pz <= z1))
-        out[s0:s1] = inside.to(dtype)
-    return out
-
-
 def unit_box(n):
     """(aabb_min[3], h0) of a grid with dims n = (nx, ny, nz) fitted to the unit box."""
     if isinstance(n, int):

@@ -70,7 +70,7 @@ def test_forward_matches_oracle(ctx, batch, name):
 @pytest.mark.parametrize("name,prec,tol", [("narrow", ds.DS_PREC_F32, 1e-5),
                                            ("deep", ds.DS_PREC_F32, 1e-5),
                                            ("wide_first", ds.DS_PREC_F32, 1e-5),
-                                           ("narrow", ds.DS_PREC_BF16, 3e-2)])
+                                           ("narrow", ds.DS_PREC_BF16, 2e-2)])
 def test_loss_and_gradient_match_oracle(ctx, batch, name, prec, tol):
     w, z, t = batch
     widths = [z.shape[1]] + CASES[name]

@@ -1,13 +1,14 @@
 """Pins of the oracle's tabulated phase functions (Sec. 5.1: a chopped Lorenz-Mie
 table for data generation and rendering, the unchopped one for the direct term at the
-first collision): the table's normalisation and chopped mass, its sampling against the
-table's own moments, a Henyey-Greenstein table against the analytic function inside the
-tracer, and the first-collision direct term against the homogeneous-box closed form.
-CPU only."""
+first collision, in the optically thinner medium of Sec. 3.1): the table's normalisation
+and chopped mass, its sampling against the table's own moments, a Henyey-Greenstein table
+against the analytic function inside the tracer, and the chopped set-up against the full
+function's single-scattering integral in a thin homogeneous box.  CPU only."""
 import math
 
 import numpy as np
 import pytest
+from scipy import integrate
 
 import oracle as O
 from paper_1709_05418_amd import synth
@@ -68,31 +69,103 @@ def test_hg_table_in_the_tracer_matches_analytic_hg(clean_phase):
     assert np.any(m0 != m1)
 
 
-def test_first_collision_uses_the_unchopped_table(clean_phase):
-    # homogeneous box, rays along +x, light along +z: the direct term of a collision has
-    # mean albedo / (1 - f) * p_first(90 deg) * exp(-sigma depth) * E, p_first the
-    # first-collision table and f the fraction the chopped table removed (the albedo
-    # passed is the reduced one, the full function's term weighs the unreduced scattering)
+def _thin_box_full_model(sigma, albedo, p_first, E, n, h, z0):
+    """Expected first-collision direct term of one camera ray along +x through a homogeneous
+    box (trilinear density rx(x) ry(y) rz(z), ry = rz = 1 at the ray) lit from +z, for the
+    unchopped phase function and the unreduced medium: the integral over the collision point
+    of sigma r(x) exp(-sigma R(x)) (collision density), times albedo p E exp(-sigma r(x) Rz)
+    (transmittance to the light), by adaptive quadrature."""
+    Rz = ramp_int(z0 + 0.5, 1.0, n, h)
+
+    def r(s):
+        return min(1.0, 0.5 + s / h, 0.5 + (1.0 - s) / h)
+
+    def f(s):
+        return sigma * r(s) * math.exp(-sigma * ramp_int(0.0, s, n, h)) * math.exp(-sigma * r(s) * Rz)
+
+    val, _ = integrate.quad(f, 0.0, 1.0, points=[h / 2, 1.0 - h / 2], epsabs=1e-14, limit=200)
+    return albedo * p_first * E * val, Rz
+
+
+@pytest.mark.parametrize("chop", [0.5, 5.0, 20.0])
+def test_chopped_set_up_matches_full_function_in_a_thin_medium(clean_phase, chop):
+    # Sec. 3.1: the chopped function in the thinner medium with the full function at the
+    # first bounce stands in for the full function in the original medium.  Single
+    # scattering dominates an optically thin medium, so there the set-up's first-collision
+    # direct term must equal the full model's single-scattering integral, up to the
+    # attenuation the thinner medium saves: 1 <= ratio <= exp(sigma (1 + Rz)).  A dropped
+    # first-collision weight (x (1 - f)), an unreduced albedo (x (1 - a f) / (1 - f)) or
+    # extinction scaled by 1 - f would leave that band by tens of per cent (f = 0.44 at 5 deg).
+    n, h, sigma, albedo, E = 8, 1.0 / 8, 0.03, 0.5, 2.0
+    grid = O.Grid(np.ones((n, n, n), np.float32), sigma, [-0.5] * 3, h)
+    _, p, _ = synth.cloud_droplet_phase(n_theta=1801, n_r=60)
+    full, chopped = O.phase_table(p), O.phase_table(p, chop_deg=chop)
+    assert chopped["removed"] > 0.0
+    p90 = full["p"][900]                         # theta = 90 degrees is node 900
+    want, Rz = _thin_box_full_model(sigma, albedo, p90, E, n, h, 0.1)
+    N = 1 << 20
+    o = np.tile(np.array([[-0.9, 0.05, 0.1]], np.float32), (N, 1))
+    d = np.tile(np.array([[1.0, 0.0, 0.0]], np.float32), (N, 1))
+
+    def mean_se(table, first):
+        O.set_phase(table, first=first)
+        _, _, direct, _ = O.first_hits(grid, o, d, [0, 0, 1], albedo=albedo, irradiance=E, seed=9)
+        return direct.mean(), direct.std() / math.sqrt(N)
+
+    m_full, se_full = mean_se(full, None)        # the full model itself, unthinned
+    assert abs(m_full - want) < 5 * se_full
+    m, se = mean_se(chopped, full)
+    assert want - 5 * se <= m <= want * math.exp(sigma * (1.0 + Rz)) + 5 * se, (m, want)
+    # without the full function at the first bounce the chopped set-up is (1 - f) darker
+    m_c, se_c = mean_se(chopped, None)
+    assert m_c == pytest.approx(m * (1 - chopped["removed"]) * chopped["p"][900] / p90, rel=1e-9)
+
+
+def test_unchopped_table_leaves_the_medium_alone(clean_phase):
+    # f = 0: no thinning, no weight; the full table as "chopped" table and first table gives
+    # exactly the full set-up's estimates on the same streams
+    n, h = 8, 1.0 / 8
+    grid = O.Grid(np.ones((n, n, n), np.float32), 3.0, [-0.5] * 3, h)
+    _, p, _ = synth.cloud_droplet_phase(n_theta=1801, n_r=60)
+    full, zero = O.phase_table(p), O.phase_table(p, chop_deg=0.0)
+    assert zero["removed"] == 0.0
+    o = np.tile(np.array([[-0.9, 0.05, 0.1]], np.float32), (4096, 1))
+    d = np.tile(np.array([[1.0, 0.0, 0.0]], np.float32), (4096, 1))
+    O.set_phase(full)
+    a = O.first_hits(grid, o, d, [0, 0, 1], albedo=0.7, irradiance=1.0, seed=3)
+    O.set_phase(zero, first=full)
+    b = O.first_hits(grid, o, d, [0, 0, 1], albedo=0.7, irradiance=1.0, seed=3)
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_first_collision_closed_form_of_the_reading(clean_phase):
+    # The reading's closed form in a thicker homogeneous box, rays along +x, light along +z
+    # (restates the reading, so it is a consistency check; the thin-medium test above is
+    # the independent pin): with a chopped table the medium is thinned to extinction
+    # sigma (1 - a f) and the direct term of a collision has mean
+    # a (1 - f) / (1 - a f) / (1 - f) p_first(90 deg) exp(-sigma (1 - a f) depth) E.
     n = 12
     h = 1.0 / n
     grid = O.Grid(np.ones((n, n, n), np.float32), 1.7, [-0.5] * 3, h)
     theta, p, _ = synth.cloud_droplet_phase(n_theta=1801, n_r=60)
     full, chop = O.phase_table(p), O.phase_table(p, chop_deg=5.0)
     O.set_phase(chop, first=full)
+    a, f = 0.9, chop["removed"]
     R, S = 4, 2500
     zs = np.linspace(-0.3, 0.3, R)
     o = np.stack([np.full(R, -0.9), np.full(R, 0.05), zs], 1).astype(np.float32)
     dirs = np.tile(np.array([[1.0, 0, 0]], np.float32), (R, 1))
     hits, dsum = np.zeros(R), np.zeros(R)
     for s in range(S):
-        _, _, direct, hit = O.first_hits(grid, o, dirs, [0, 0, 1], albedo=0.9, irradiance=2.0,
+        _, _, direct, hit = O.first_hits(grid, o, dirs, [0, 0, 1], albedo=a, irradiance=2.0,
                                          seed=4, sample=s)
         hits += hit == 1
         dsum += direct
-    p90 = full["p"][900]                         # theta = 90 degrees is node 900
+    p90 = full["p"][900]
     assert p90 != chop["p"][900]
-    T = np.exp(-1.7 * np.array([ramp_int(z + 0.5, 1.0, n, h) for z in zs]))
-    w = 0.9 / (1.0 - chop["removed"])
+    T = np.exp(-1.7 * (1 - a * f) * np.array([ramp_int(z + 0.5, 1.0, n, h) for z in zs]))
+    w = a * (1 - f) / (1 - a * f) / (1 - f)
     want = w * p90 * T * 2.0
     sd = w * p90 * 2.0 * np.sqrt(T * (1 - T) / hits)
     assert np.all(np.abs(dsum / hits - want) < 5 * sd + 1e-12)
