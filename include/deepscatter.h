@@ -291,9 +291,10 @@ ds_status ds_fp8_e4m3_encode(const float *x, int64_t n, int32_t log2_scale, uint
 ds_status ds_adam_create(ds_net *net, float lr, float beta1, float beta2, float eps,
                          ds_adam **out);
 ds_status ds_adam_destroy(ds_adam *opt);
-/* Learning rate of the following updates (moments and step count are kept). */
+/* Learning rate of the following updates, captured steps included (moments and step
+ * count are kept).  Synchronises the stream. */
 ds_status ds_adam_set_lr(ds_adam *opt, float lr);
-/* Number of updates applied so far (host read, no synchronisation). */
+/* Number of updates applied so far (read from the device; synchronises the stream). */
 ds_status ds_adam_steps(const ds_adam *opt, int64_t *t);
 
 /* Arithmetic of ds_loss_grad and ds_train_step: DS_PREC_F32 (default; every GEMM in
@@ -317,11 +318,22 @@ ds_status ds_loss_grad(ds_net *net, const float *z, const float *target_log1p, i
                        float *loss_dev, float *grad_dev);
 /* One training step: loss and gradient as ds_loss_grad, one Adam update of the
  * FP32 master parameters (step count t + 1, bias-corrected moments), then the
- * matrix-core copy of the weights is refreshed on the device.  Asynchronous;
- * capturable in a stream graph once the workspace exists (after the first call
- * with the same B). */
+ * matrix-core copy of the weights is refreshed on the device.  The step count, the
+ * bias corrections and the learning rate live on the device and advance with the
+ * step, so the step is kernels only.  Asynchronous. */
 ds_status ds_train_step(ds_net *net, ds_adam *opt, const float *z, const float *target_log1p,
                         int B, float *loss_dev);
+/* Captures one ds_train_step with these arguments (same buffers, B and loss_dev) into
+ * a graph owned by `opt`, replacing an earlier one; nothing runs.  ds_train_replay
+ * launches it on the context's stream: each replay is one training step on whatever
+ * the buffers then hold, bitwise equal to the eager call (ds_adam_set_lr changes the
+ * rate of later replays too).  The context must use a created stream, not the default
+ * one.  Errors: DS_ERR_STATE if the training workspace for B does not exist yet (run
+ * one ds_train_step or ds_loss_grad with B first; growing it allocates) or, for replay,
+ * if nothing was captured. */
+ds_status ds_train_capture(ds_net *net, ds_adam *opt, const float *z, const float *target_log1p,
+                           int B, float *loss_dev);
+ds_status ds_train_replay(ds_adam *opt);
 
 /* ---------------------------------------------------------------- Monte Carlo (Sec. 3.2, 4, 5.1) */
 /* The medium of every tracer call is the cloud's base grid: extinction

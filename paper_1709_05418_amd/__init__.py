@@ -74,6 +74,8 @@ def lib():
         "ds_adam_steps": (S, [P, P]),
         "ds_loss_grad": (S, [P, P, P, I, P, P]),
         "ds_train_step": (S, [P, P, P, P, I, P]),
+        "ds_train_capture": (S, [P, P, P, P, I, P]),
+        "ds_train_replay": (S, [P]),
         "ds_net_set_train_precision": (S, [P, I]),
         "ds_net_quantize": (S, [P, P, P, I, P, P, P, I64]),
         "ds_net_fp8_scales": (S, [P, P, S]),
@@ -408,6 +410,16 @@ def ds_train_step(net, opt, z, target_log1p, loss=None):
         loss = torch.empty(1, dtype=torch.float32, device=z.device)
     _check(lib().ds_train_step(net, opt, _ptr(z), _ptr(target_log1p), B, _ptr(loss)))
     return loss
+
+
+def ds_train_capture(net, opt, z, target_log1p, loss):
+    """Capture one ds_train_step on these buffers (loss: device tensor of one float)."""
+    B = _batch(z, target_log1p)
+    _check(lib().ds_train_capture(net, opt, _ptr(z), _ptr(target_log1p), B, _ptr(loss)))
+
+
+def ds_train_replay(opt):
+    _check(lib().ds_train_replay(opt))
 
 
 def ds_cloud_majorant(cloud) -> float:

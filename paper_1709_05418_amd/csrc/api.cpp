@@ -340,11 +340,29 @@ struct TrainWs {
     size_t split_floats;
 };
 
+// Training workspace of a minibatch of B samples, in floats (both network kinds).
+size_t train_ws_floats(const ds_net *net, int B)
+{
+    if (net->kind == 1) {
+        const std::vector<int> &wd = net->mlp_widths;
+        size_t act = 0;
+        for (size_t l = 1; l < wd.size(); ++l)
+            act += (size_t)B * wd[l];
+        size_t split = (size_t)16 * net->W * 226;
+        const size_t csum = (size_t)colsum_scratch(net->W);
+        split = split > csum ? split : csum;
+        return 2 * act + 2 * (size_t)B * net->W + 2 * (size_t)B + split;
+    }
+    const size_t BW = (size_t)B * net->W, K = net->K, Hh = net->H;
+    const size_t split = (size_t)16 * net->W * 226;
+    return 4 * K * BW + 2 * Hh * BW + 3 * BW + 2 * (size_t)B + split;
+}
+
 ds_status train_ws(ds_net *net, int B, TrainWs &w)
 {
     const size_t BW = (size_t)B * net->W, K = net->K, Hh = net->H;
     const size_t split = (size_t)16 * net->W * 226;
-    const size_t need = 4 * K * BW + 2 * Hh * BW + 3 * BW + 2 * (size_t)B + split;
+    const size_t need = train_ws_floats(net, B);
     if (net->tws_floats < need) {
         if (net->tws) {
             DS_HIP(hipStreamSynchronize(net->ctx->stream));
@@ -399,7 +417,7 @@ static ds_status mlp_loss_grad(ds_net *net, const float *z, const float *target,
     size_t split = (size_t)16 * Wm * 226;
     const size_t csum = (size_t)colsum_scratch(Wm);
     split = split > csum ? split : csum;
-    const size_t need = 2 * act + 2 * (size_t)B * Wm + 2 * (size_t)B + split;
+    const size_t need = train_ws_floats(net, B);
     if (net->tws_floats < need) {
         if (net->tws) {
             DS_HIP(hipStreamSynchronize(s));
@@ -636,7 +654,7 @@ ds_status loss_grad(ds_net *net, const float *z, const float *target, int B, flo
         if (k > 0) {
             DS_TRY(mm({W, W, B, w.dh, 1, W, O(k - 1), W, 1, grad + po.W1[k], W, 0}));
             // d o^{k-1} = da + dh W1
-            DS_HIP(hipMemcpyAsync(w.dnext, da, BW * sizeof(float), hipMemcpyDeviceToDevice, s));
+            DS_TRY(copy_f32(s, w.dnext, da, (int64_t)BW));
             DS_TRY(mm({B, W, W, w.dh, W, 1, th + po.W1[k], W, 1, w.dnext, W, 1}));
             std::swap(w.dcur, w.dnext);
         }
@@ -1647,19 +1665,22 @@ ds_status ds_adam_create(ds_net *net, float lr, float beta1, float beta2, float 
     a->eps = eps;
     const size_t n = (size_t)net->n_params;
     if (hipMalloc(&a->m, n * 4) != hipSuccess || hipMalloc(&a->v, n * 4) != hipSuccess ||
-        hipMalloc(&a->grad, n * 4) != hipSuccess) {
-        (void)hipFree(a->m);
-        (void)hipFree(a->v);
-        (void)hipFree(a->grad);
-        delete a;
+        hipMalloc(&a->grad, n * 4) != hipSuccess || hipMalloc(&a->steps, 8) != hipSuccess ||
+        hipMalloc(&a->state, 16) != hipSuccess) {
+        ds_adam_destroy(a);
         set_error("ds_adam_create: out of device memory");
         return DS_ERR_OOM;
     }
     hipStream_t s = net->ctx->stream;
+    const int64_t t0 = 0;
+    const float st0[4] = {lr, 1.f, 1.f, 0.f};
     if (hipMemsetAsync(a->m, 0, n * 4, s) != hipSuccess ||
-        hipMemsetAsync(a->v, 0, n * 4, s) != hipSuccess) {
+        hipMemsetAsync(a->v, 0, n * 4, s) != hipSuccess ||
+        hipMemcpyAsync(a->steps, &t0, 8, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(a->state, st0, 16, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
         ds_adam_destroy(a);
-        set_error("ds_adam_create: clearing the moments failed");
+        set_error("ds_adam_create: initialising the optimiser state failed");
         return DS_ERR_DEVICE;
     }
     *out = a;
@@ -1672,6 +1693,9 @@ ds_status ds_adam_set_lr(ds_adam *a, float lr)
     DS_CHECK(lr > 0.f && std::isfinite(lr), DS_ERR_INVALID_ARG,
              "ds_adam_set_lr: learning rate must be positive and finite");
     a->lr = lr;
+    hipStream_t s = a->net->ctx->stream;
+    DS_HIP(hipMemcpyAsync(a->state, &lr, sizeof(float), hipMemcpyHostToDevice, s));
+    DS_HIP(hipStreamSynchronize(s));
     return DS_OK;
 }
 
@@ -1680,9 +1704,13 @@ ds_status ds_adam_destroy(ds_adam *a)
     if (!a)
         return DS_OK;
     (void)hipStreamSynchronize(a->net->ctx->stream);
+    if (a->exec)
+        (void)hipGraphExecDestroy(a->exec);
     (void)hipFree(a->m);
     (void)hipFree(a->v);
     (void)hipFree(a->grad);
+    (void)hipFree(a->steps);
+    (void)hipFree(a->state);
     delete a;
     return DS_OK;
 }
@@ -1690,7 +1718,9 @@ ds_status ds_adam_destroy(ds_adam *a)
 ds_status ds_adam_steps(const ds_adam *a, int64_t *t)
 {
     DS_CHECK(a && t, DS_ERR_INVALID_ARG, "ds_adam_steps: NULL argument");
-    *t = a->t;
+    hipStream_t s = a->net->ctx->stream;
+    DS_HIP(hipMemcpyAsync(t, a->steps, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    DS_HIP(hipStreamSynchronize(s));
     return DS_OK;
 }
 
@@ -1703,6 +1733,24 @@ ds_status ds_loss_grad(ds_net *net, const float *z, const float *target_log1p, i
     return loss_grad(net, z, target_log1p, B, loss_dev, grad_dev);
 }
 
+// Loss, gradient, Adam update and refresh of the matrix-core weights: kernels only, so the
+// body can be captured once the training workspace exists.
+static ds_status train_step_body(ds_net *net, ds_adam *opt, const float *z,
+                                 const float *target_log1p, int B, float *loss_dev)
+{
+    ds_status st = loss_grad(net, z, target_log1p, B, loss_dev, opt->grad);
+    if (st)
+        return st;
+    st = adam_update(net->ctx->stream, net->theta, opt->m, opt->v, opt->grad, net->n_params,
+                     opt->b1, opt->b2, opt->eps, opt->steps, opt->state);
+    if (st)
+        return st;
+    net->fp8_ready = false;
+    if (net->kind == 0 && fused_tiles(net->W) > 0)
+        return fused_pack_bf16(net->ctx->stream, net);
+    return DS_OK;
+}
+
 ds_status ds_train_step(ds_net *net, ds_adam *opt, const float *z, const float *target_log1p,
                         int B, float *loss_dev)
 {
@@ -1710,19 +1758,54 @@ ds_status ds_train_step(ds_net *net, ds_adam *opt, const float *z, const float *
     DS_CHECK(opt->net == net, DS_ERR_INVALID_ARG, "ds_train_step: optimiser of another network");
     DS_CHECK(B >= 1 && B <= (1 << 20), DS_ERR_INVALID_ARG,
              "ds_train_step: batch %d outside 1..2^20", B);
-    ds_status st = loss_grad(net, z, target_log1p, B, loss_dev, opt->grad);
-    if (st)
+    return train_step_body(net, opt, z, target_log1p, B, loss_dev);
+}
+
+ds_status ds_train_capture(ds_net *net, ds_adam *opt, const float *z, const float *target_log1p,
+                           int B, float *loss_dev)
+{
+    DS_CHECK(net && opt && z && target_log1p, DS_ERR_INVALID_ARG,
+             "ds_train_capture: NULL argument");
+    DS_CHECK(opt->net == net, DS_ERR_INVALID_ARG, "ds_train_capture: optimiser of another network");
+    DS_CHECK(B >= 1 && B <= (1 << 20), DS_ERR_INVALID_ARG,
+             "ds_train_capture: batch %d outside 1..2^20", B);
+    DS_CHECK(net->tws && net->tws_floats >= train_ws_floats(net, B), DS_ERR_STATE,
+             "ds_train_capture: no training workspace for a batch of %d yet (growing it "
+             "allocates): run ds_train_step or ds_loss_grad with this batch size first", B);
+    DS_HIP(hipSetDevice(net->ctx->device));
+    hipStream_t s = net->ctx->stream;
+    DS_CHECK(s, DS_ERR_STATE, "ds_train_capture: the context uses the default stream, which "
+                              "cannot be captured");
+    if (opt->exec) {
+        (void)hipGraphExecDestroy(opt->exec);
+        opt->exec = nullptr;
+    }
+    DS_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    ds_status st = train_step_body(net, opt, z, target_log1p, B, loss_dev);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s, &g);
+    if (st) {
+        if (g)
+            (void)hipGraphDestroy(g);
         return st;
-    opt->t += 1;
-    const double c1 = 1.0 - pow((double)opt->b1, (double)opt->t);
-    const double c2 = 1.0 - pow((double)opt->b2, (double)opt->t);
-    st = adam_update(net->ctx->stream, net->theta, opt->m, opt->v, opt->grad, net->n_params,
-                     opt->lr, opt->b1, opt->b2, opt->eps, (float)c1, (float)c2);
-    if (st)
-        return st;
-    net->fp8_ready = false;
-    if (net->kind == 0 && fused_tiles(net->W) > 0)
-        return fused_pack_bf16(net->ctx->stream, net);
+    }
+    if (e == hipSuccess)
+        e = hipGraphInstantiate(&opt->exec, g, nullptr, nullptr, 0);
+    if (g)
+        (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        opt->exec = nullptr;
+        return hip_fail(e, "ds_train_capture");
+    }
+    return DS_OK;
+}
+
+ds_status ds_train_replay(ds_adam *opt)
+{
+    DS_CHECK(opt, DS_ERR_INVALID_ARG, "ds_train_replay: optimiser is NULL");
+    DS_CHECK(opt->exec, DS_ERR_STATE, "ds_train_replay: no captured step (ds_train_capture)");
+    DS_HIP(hipGraphLaunch(opt->exec, opt->net->ctx->stream));
+    opt->net->fp8_ready = false;
     return DS_OK;
 }
 

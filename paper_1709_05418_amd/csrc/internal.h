@@ -131,10 +131,14 @@ struct ds_batch {
 struct ds_adam {
     ds_net *net = nullptr;
     float lr = 1e-3f, b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    int64_t t = 0;       // steps taken
     float *m = nullptr;  // first and second moments, FP32
     float *v = nullptr;
     float *grad = nullptr;
+    // device: the step count and {lr, 1 - b1^t, 1 - b2^t}, advanced by the step itself, so
+    // a captured step replays with the right bias correction and the current rate
+    int64_t *steps = nullptr;
+    float *state = nullptr;
+    hipGraphExec_t exec = nullptr;  // captured training step (ds_train_capture)
 };
 
 namespace ds {
@@ -212,8 +216,12 @@ ds_status colsum(hipStream_t s, const float *d, int ldd, int R, int C, float *db
 int colsum_scratch(int C);
 ds_status loss_head(hipStream_t s, const float *pre, const float *t, int B, float *dpre, float *sq,
                     float *loss);
+// one Adam step: the step count and bias corrections advance on the device (state:
+// {lr, 1 - b1^t, 1 - b2^t}), then every parameter is updated
 ds_status adam_update(hipStream_t s, float *theta, float *m, float *v, const float *grad,
-                      int64_t n, float lr, float b1, float b2, float eps, float c1, float c2);
+                      int64_t n, float b1, float b2, float eps, int64_t *steps, float *state);
+// dst = src (n floats), as a kernel
+ds_status copy_f32(hipStream_t s, float *dst, const float *src, int64_t n);
 
 // fused.hip
 int fused_tiles(int W);

@@ -210,10 +210,23 @@ __global__ void __launch_bounds__(256) k_loss_mean(const float *sq, int B, float
 }
 
 // Adam (Kingma and Ba, Alg. 1) with the bias corrections folded into c1, c2.
-__global__ void __launch_bounds__(256) k_adam(float *theta, float *m, float *v, const float *grad,
-                                              int64_t n, float lr, float b1, float b2, float eps,
-                                              float c1, float c2)
+// Advances the step count and forms the bias corrections of Adam (Kingma and Ba, Alg. 1)
+// for it, in FP64, stored as FP32: state = {lr, 1 - b1^t, 1 - b2^t}.
+__global__ void k_adam_prep(int64_t *steps, float *state, float b1, float b2)
 {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const int64_t t = *steps + 1;
+        *steps = t;
+        state[1] = (float)(1.0 - pow((double)b1, (double)t));
+        state[2] = (float)(1.0 - pow((double)b2, (double)t));
+    }
+}
+
+__global__ void __launch_bounds__(256) k_adam(float *theta, float *m, float *v, const float *grad,
+                                              int64_t n, float b1, float b2, float eps,
+                                              const float *state)
+{
+    const float lr = state[0], c1 = state[1], c2 = state[2];
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const float gi = grad[i];
@@ -566,9 +579,26 @@ ds_status loss_head(hipStream_t s, const float *pre, const float *t, int B, floa
 }
 
 ds_status adam_update(hipStream_t s, float *theta, float *m, float *v, const float *grad,
-                      int64_t n, float lr, float b1, float b2, float eps, float c1, float c2)
+                      int64_t n, float b1, float b2, float eps, int64_t *steps, float *state)
 {
-    k_adam<<<grid1(n), 256, 0, s>>>(theta, m, v, grad, n, lr, b1, b2, eps, c1, c2);
+    k_adam_prep<<<1, 64, 0, s>>>(steps, state, b1, b2);
+    k_adam<<<grid1(n), 256, 0, s>>>(theta, m, v, grad, n, b1, b2, eps, state);
+    DS_HIP(hipGetLastError());
+    return DS_OK;
+}
+
+__global__ void __launch_bounds__(256) k_copy(float *dst, const float *src, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+ds_status copy_f32(hipStream_t s, float *dst, const float *src, int64_t n)
+{
+    if (n <= 0)
+        return DS_OK;
+    k_copy<<<grid1(n), 256, 0, s>>>(dst, src, n);
     DS_HIP(hipGetLastError());
     return DS_OK;
 }
