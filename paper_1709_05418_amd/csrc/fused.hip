@@ -78,14 +78,15 @@ typedef const __attribute__((address_space(1))) u32x4 *gcell_ptr;
 // Four trilinear samples in flight: the 16-byte corner cells and the fractions.
 struct Pending {
     u32x4 v[4];
-    float fx[4], fy[4], fz[4];
+    float fx[4];
+    uint32_t t[4];  // (fy, fz) as packed FP16
 };
 
 // Clamp a shifted cell coordinate (CL) or take it as it is (the level's zero border holds
 // every sample of the wave's points), start the cell load, keep the fractions.
 template <bool CL = true>
 __device__ __forceinline__ void issue_one(gcell_ptr cells, const FusedLevel &L, float ux, float uy,
-                                          float uz, u32x4 &v, float &fx, float &fy, float &fz)
+                                          float uz, u32x4 &v, float &fx, uint32_t &tyz)
 {
     if (CL) {
         ux = __builtin_amdgcn_fmed3f(ux, 0.f, L.hi_x);
@@ -94,8 +95,8 @@ __device__ __forceinline__ void issue_one(gcell_ptr cells, const FusedLevel &L, 
     }
     const uint32_t i = (uint32_t)ux, j = (uint32_t)uy, k = (uint32_t)uz;
     fx = __builtin_amdgcn_fractf(ux);
-    fy = __builtin_amdgcn_fractf(uy);
-    fz = __builtin_amdgcn_fractf(uz);
+    tyz = __builtin_bit_cast(uint32_t, __builtin_amdgcn_cvt_pkrtz(__builtin_amdgcn_fractf(uy),
+                                                                __builtin_amdgcn_fractf(uz)));
     // 24-bit multiply-adds: cell dims stay below 2^13 and j + cy k below 2^24.  The empty
     // asm statements keep both partial indices 32-bit values in registers, so the compiler
     // emits two full-rate v_mad_u32_u24 instead of widening one into v_mad_u64_u32.
@@ -109,7 +110,7 @@ __device__ __forceinline__ void issue_one(gcell_ptr cells, const FusedLevel &L, 
 // Trilinear value of a sample from its cell's polynomial coefficients (FP16, see k_pack):
 // the two faces' bilinear functions P0, P1 as packed FP16 FMAs on the (P0, P1) coefficient
 // pairs, then P0 + fx P1 in FP32 on the two halves in place.
-__device__ __forceinline__ float finish_one(const u32x4 &v, float fx, float fy, float fz)
+__device__ __forceinline__ float finish_one(const u32x4 &v, float fx, uint32_t tyz)
 {
     typedef _Float16 h2 __attribute__((ext_vector_type(2)));
     // element copies first: a bit cast applied to a vector element itself reads the
@@ -117,7 +118,7 @@ __device__ __forceinline__ float finish_one(const u32x4 &v, float fx, float fy, 
     const uint32_t u0 = v[0], u1 = v[1], u2 = v[2], u3 = v[3];
     const h2 A = __builtin_bit_cast(h2, u0), B = __builtin_bit_cast(h2, u1);
     const h2 C = __builtin_bit_cast(h2, u2), D = __builtin_bit_cast(h2, u3);
-    const h2 t = __builtin_bit_cast(h2, __builtin_amdgcn_cvt_pkrtz(fy, fz));  // (fy, fz)
+    const h2 t = __builtin_bit_cast(h2, tyz);  // (fy, fz)
     const h2 p = B * t[0] + A;  // A + B ty for both faces
     const h2 q = D * t[0] + C;  // C + D ty
     const h2 r = q * t[1] + p;  // (P0, P1)
@@ -149,11 +150,11 @@ template <bool CL = true>
 __device__ __forceinline__ void issue_four(gcell_ptr cells, const FusedLevel &L, const PtLevel &q,
                                            float bx, float by, float bz, Pending &p)
 {
-    issue_one<CL>(cells, L, bx, by, bz, p.v[0], p.fx[0], p.fy[0], p.fz[0]);
+    issue_one<CL>(cells, L, bx, by, bz, p.v[0], p.fx[0], p.t[0]);
 #pragma unroll
     for (int j = 1; j < 4; ++j)
         issue_one<CL>(cells, L, fmaf((float)j, q.c[0], bx), fmaf((float)j, q.c[1], by),
-                  fmaf((float)j, q.c[2], bz), p.v[j], p.fx[j], p.fy[j], p.fz[j]);
+                  fmaf((float)j, q.c[2], bz), p.v[j], p.fx[j], p.t[j]);
 }
 
 // Coordinate of lattice point (ix, iy, 0) of stencil column 4 s + g, (ix, iy) from the
@@ -203,8 +204,7 @@ __device__ __forceinline__ void issue_table_half(gcell_ptr cells, const FusedLev
         const float4 o = tab[8 * g + 4 * hh + j];
         issue_one<CL>(cells, L, q.u0[0] + o.x * q.a[0] + o.y * q.b[0] + o.z * q.c[0],
                   q.u0[1] + o.x * q.a[1] + o.y * q.b[1] + o.z * q.c[1],
-                  q.u0[2] + o.x * q.a[2] + o.y * q.b[2] + o.z * q.c[2], p.v[j], p.fx[j], p.fy[j],
-                  p.fz[j]);
+                  q.u0[2] + o.x * q.a[2] + o.y * q.b[2] + o.z * q.c[2], p.v[j], p.fx[j], p.t[j]);
     }
 }
 
@@ -417,11 +417,22 @@ template <int MT>
 __device__ __forceinline__ void mfma_chunk(const uint4 *w, int lane, const bf16x8 &B, f4 (&acc)[MT])
 {
     // keep the fragment reads next to their MFMAs (hoisting all of them above the
-    // gather math costs more registers than the two waves per SIMD can spare)
+    // gather math costs more registers than the two waves per SIMD can spare), three
+    // reads ahead of the product that consumes them, so an LDS read's latency spans
+    // three products instead of one
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
         acc[mt] = mfma_bf16(w[mt * 64 + lane], B, acc[mt]);
+    constexpr int AHEAD = MT < 3 ? MT : 3;
+    __builtin_amdgcn_sched_group_barrier(0x100, AHEAD, 0);
+#pragma unroll
+    for (int mt = 0; mt < MT - AHEAD; ++mt) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, AHEAD, 0);
+    __builtin_amdgcn_sched_barrier(0);
 }
 
 // B operand of FP8 chunk Q of a W-wide layer: tiles 8Q..8Q+7 of the input in
@@ -610,11 +621,11 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
                 f4 lo, hi;
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
+                    lo[j] = finish_one(pa.v[j], pa.fx[j], pa.t[j]);
                 issue_column_half(cells, L, q, 2 * c + 2, g, cols, pa);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
+                    hi[j] = finish_one(pb.v[j], pb.fx[j], pb.t[j]);
                 issue_column_half(cells, L, q, 2 * c + 3, g, cols, pb);
                 mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
                 ws.template next<0>(tid);
@@ -624,11 +635,11 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
                 f4 lo, hi;
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
+                    lo[j] = finish_one(pa.v[j], pa.fx[j], pa.t[j]);
                 issue_table_half(cells, L, q, 0, g, plane, pa);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
+                    hi[j] = finish_one(pb.v[j], pb.fx[j], pb.t[j]);
                 issue_table_half(cells, L, q, 1, g, plane, pb);
                 mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
                 ws.template next<0>(tid);
@@ -638,21 +649,21 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
                 f4 lo, hi;
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
+                    lo[j] = finish_one(pa.v[j], pa.fx[j], pa.t[j]);
                 issue_one(cells, L, q.u0[0] + 4.f * (q.a[0] + q.b[0]) + 8.f * q.c[0],
                           q.u0[1] + 4.f * (q.a[1] + q.b[1]) + 8.f * q.c[1],
                           q.u0[2] + 4.f * (q.a[2] + q.b[2]) + 8.f * q.c[2], pa.v[0], pa.fx[0],
-                          pa.fy[0], pa.fz[0]);
+                          pa.t[0]);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
+                    hi[j] = finish_one(pb.v[j], pb.fx[j], pb.t[j]);
                 mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
                 ws.template next<0>(tid);
             }
             // chunk 7: stencil sample (4, 4, 8), gamma, and the odd tile of o^{k-1}
             {
                 ws.fetch(tid);
-                float s = finish_one(pa.v[0], pa.fx[0], pa.fy[0], pa.fz[0]);
+                float s = finish_one(pa.v[0], pa.fx[0], pa.t[0]);
                 f4 lo = f4{g == 0 ? s : 0.f, g == 0 ? gamma : 0.f, 0.f, 0.f};
                 bf16x8 B = pack8(lo, (MT & 1) ? Os[MT - 1][lane] : z4);
                 mfma_chunk<MT>(ws.chunk(), lane, B, F);
@@ -849,11 +860,11 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
                 const float3 cb = column_base(q, c + 1, g, cols);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
+                    lo[j] = finish_one(pa.v[j], pa.fx[j], pa.t[j]);
                 issue_four<CL>(cells, L, q, cb.x, cb.y, cb.z, pa);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
+                    hi[j] = finish_one(pb.v[j], pb.fx[j], pb.t[j]);
                 // the weight copy goes out after the waits for this chunk's samples (the
                 // empty statement keeps the finished samples from sinking below it)
                 asm volatile("" ::"v"(lo), "v"(hi));
@@ -867,11 +878,11 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
                 f4 lo, hi;
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
+                    lo[j] = finish_one(pa.v[j], pa.fx[j], pa.t[j]);
                 issue_table_half<CL>(cells, L, q, 0, g, plane, pa);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
+                    hi[j] = finish_one(pb.v[j], pb.fx[j], pb.t[j]);
                 asm volatile("" ::"v"(lo), "v"(hi));
                 ws.fetch(tid);
                 issue_table_half<CL>(cells, L, q, 1, g, plane, pb);
@@ -882,21 +893,21 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
                 f4 lo, hi;
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    lo[j] = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
+                    lo[j] = finish_one(pa.v[j], pa.fx[j], pa.t[j]);
                 issue_one<CL>(cells, L, q.u0[0] + 4.f * (q.a[0] + q.b[0]) + 8.f * q.c[0],
                           q.u0[1] + 4.f * (q.a[1] + q.b[1]) + 8.f * q.c[1],
                           q.u0[2] + 4.f * (q.a[2] + q.b[2]) + 8.f * q.c[2], pa.v[0], pa.fx[0],
-                          pa.fy[0], pa.fz[0]);
+                          pa.t[0]);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    hi[j] = finish_one(pb.v[j], pb.fx[j], pb.fy[j], pb.fz[j]);
+                    hi[j] = finish_one(pb.v[j], pb.fx[j], pb.t[j]);
                 asm volatile("" ::"v"(lo), "v"(hi));
                 ws.fetch(tid);
                 mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
                 ws.template next<1>(tid);
             }
             {  // chunk 7: stencil sample (4, 4, 8), gamma, and the odd tile of o^{k-1}
-                const float sv = finish_one(pa.v[0], pa.fx[0], pa.fy[0], pa.fz[0]);
+                const float sv = finish_one(pa.v[0], pa.fx[0], pa.t[0]);
                 asm volatile("" ::"v"(sv));
                 ws.fetch(tid);
                 const f4 lo = f4{g == 0 ? sv : 0.f, g == 0 ? gamma : 0.f, 0.f, 0.f};
@@ -1132,8 +1143,8 @@ __global__ void __launch_bounds__(64 * NW, 1) k_fused_wide(FusedArgs a,
                     f4 lo, hi;
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        lo[j] = finish_one(pa[nt].v[j], pa[nt].fx[j], pa[nt].fy[j], pa[nt].fz[j]);
-                        hi[j] = finish_one(pb[nt].v[j], pb[nt].fx[j], pb[nt].fy[j], pb[nt].fz[j]);
+                        lo[j] = finish_one(pa[nt].v[j], pa[nt].fx[j], pa[nt].t[j]);
+                        hi[j] = finish_one(pb[nt].v[j], pb[nt].fx[j], pb[nt].t[j]);
                     }
                     B[nt] = pack8(lo, hi);
                 }
@@ -1147,12 +1158,12 @@ __global__ void __launch_bounds__(64 * NW, 1) k_fused_wide(FusedArgs a,
                     issue_one(cells, L, q[nt].u0[0] + 4.f * (q[nt].a[0] + q[nt].b[0]) + 8.f * q[nt].c[0],
                               q[nt].u0[1] + 4.f * (q[nt].a[1] + q[nt].b[1]) + 8.f * q[nt].c[1],
                               q[nt].u0[2] + 4.f * (q[nt].a[2] + q[nt].b[2]) + 8.f * q[nt].c[2],
-                              pa[nt].v[0], pa[nt].fx[0], pa[nt].fy[0], pa[nt].fz[0]);
+                              pa[nt].v[0], pa[nt].fx[0], pa[nt].t[0]);
                 ws.fetch(tid);
                 bf16x8 B[NT];
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) {
-                    const float sv = finish_one(pa[nt].v[0], pa[nt].fx[0], pa[nt].fy[0], pa[nt].fz[0]);
+                    const float sv = finish_one(pa[nt].v[0], pa[nt].fx[0], pa[nt].t[0]);
                     const f4 lo = f4{g == 0 ? sv : 0.f, g == 0 ? gamma[nt] : 0.f, 0.f, 0.f};
                     B[nt] = pack8(lo, (MT & 1) ? O[MT - 1][nt] : z4);
                 }
@@ -1277,7 +1288,7 @@ __global__ void __launch_bounds__(256) k_gather_packed(FusedArgs a, float *__res
         for (int h = 0; h < 12; ++h) {
             issue_column_half(cells, L, q, h, g, cols, pa);
             for (int j = 0; j < 4; ++j) {
-                float v = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
+                float v = finish_one(pa.v[j], pa.fx[j], pa.t[j]);
                 if (in)
                     z[p * D + 225 * k + column_sample(h >> 1, g, 4 * (h & 1) + j)] = v;
             }
@@ -1285,7 +1296,7 @@ __global__ void __launch_bounds__(256) k_gather_packed(FusedArgs a, float *__res
         for (int hh = 0; hh < 2; ++hh) {
             issue_table_half(cells, L, q, hh, g, plane, pa);
             for (int j = 0; j < 4; ++j) {
-                float v = finish_one(pa.v[j], pa.fx[j], pa.fy[j], pa.fz[j]);
+                float v = finish_one(pa.v[j], pa.fx[j], pa.t[j]);
                 float4 o = plane[8 * g + 4 * hh + j];
                 int sidx = (int)o.x + 5 * (int)o.y + 25 * (int)o.z;
                 if (in)
@@ -1296,8 +1307,8 @@ __global__ void __launch_bounds__(256) k_gather_packed(FusedArgs a, float *__res
             issue_one(cells, L, q.u0[0] + 4.f * (q.a[0] + q.b[0]) + 8.f * q.c[0],
                       q.u0[1] + 4.f * (q.a[1] + q.b[1]) + 8.f * q.c[1],
                       q.u0[2] + 4.f * (q.a[2] + q.b[2]) + 8.f * q.c[2], pa.v[0], pa.fx[0],
-                      pa.fy[0], pa.fz[0]);
-            float v = finish_one(pa.v[0], pa.fx[0], pa.fy[0], pa.fz[0]);
+                      pa.t[0]);
+            float v = finish_one(pa.v[0], pa.fx[0], pa.t[0]);
             if (in)
                 z[p * D + 225 * k + 224] = v;
         }
