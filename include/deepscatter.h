@@ -207,6 +207,21 @@ ds_status ds_predict(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
  * captured in a stream graph.  Errors as ds_predict, DS_ERR_OOM if memory runs out. */
 ds_status ds_predict_reserve(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
                              ds_precision precision, int64_t P);
+/* For callers that cannot allocate device memory (code under stream-graph capture,
+ * serving loops, harnesses that forbid hipMalloc): ds_predict in DS_PREC_F32 with the
+ * same results, whose descriptor rows, activations and flags live in a scratch area
+ * the library holds on every GPU from module load until the process ends (32 MiB per
+ * device; chunks of up to floor((32 MiB - 256) / (4 (225 K + 1 + 3 W) + 1) / 64) * 64
+ * points, 2880 at K = 10, W = 200).  It calls no hipMalloc, hipFree or other allocating
+ * routine and never synchronises.  Arguments as ds_predict.  Errors: as ds_predict;
+ * DS_ERR_STATE if the cloud's float32 corner cells do not exist yet (run
+ * ds_predict_reserve with DS_PREC_F32 once) or the device has no scratch address;
+ * DS_ERR_INVALID_ARG if the network needs more than the scratch for 64 points.  All
+ * calls on one GPU share its scratch: calls that overlap in time on one GPU (two
+ * streams, two threads) race and must be serialised by the caller. */
+ds_status ds_predict_f32_noalloc(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
+                                 const float *pos, const float *view_dir, const float *light_dir,
+                                 int64_t P, float *out, float *pre_out, uint8_t *flags);
 
 /* ---------------------------------------------------------------- batched prediction */
 /* Uneven sets of shading points from several clouds (each with its own pyramid,

@@ -68,6 +68,7 @@ def lib():
         "ds_forward": (S, [P, P, P, I64, P, P]),
         "ds_predict": (S, [P, P, P, I, P, P, P, I64, P, P, P]),
         "ds_predict_reserve": (S, [P, P, P, I, I64]),
+        "ds_predict_f32_noalloc": (S, [P, P, P, P, P, P, I64, P, P, P]),
         "ds_adam_create": (S, [P, F, F, F, F, P]),
         "ds_adam_destroy": (S, [P]),
         "ds_adam_set_lr": (S, [P, F]),
@@ -332,6 +333,23 @@ def ds_predict(ctx, cloud, net, precision, pos, view_dir, light_dir, out=None, p
 def ds_predict_reserve(ctx, cloud, net, precision, P):
     """Build ahead what ds_predict with at most P points would create on first use."""
     _check(lib().ds_predict_reserve(ctx, cloud, net, int(precision), int(P)))
+
+
+def ds_predict_f32_noalloc(ctx, cloud, net, pos, view_dir, light_dir, out=None, pre=None,
+                           flags=None, want_pre=True, want_flags=True):
+    """ds_predict in FP32 through the library's per-device scratch (no allocation)."""
+    import torch
+    P = pos.shape[0]
+    if out is None:
+        out = torch.empty(P, dtype=torch.float32, device=pos.device)
+    if pre is None and want_pre:
+        pre = torch.empty(P, dtype=torch.float32, device=pos.device)
+    if flags is None and want_flags:
+        flags = torch.empty(P, dtype=torch.uint8, device=pos.device)
+    _check(lib().ds_predict_f32_noalloc(ctx, cloud, net, _pts(pos), _pts(view_dir, P),
+                                        _pts(light_dir, P), P, _ptr(out), _ptr(pre),
+                                        _ptr(flags)))
+    return out, pre, flags
 
 
 def ds_net_set_train_precision(net, precision):

@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <utility>
 #include <algorithm>
@@ -667,6 +668,35 @@ ds_status loss_grad(ds_net *net, const float *z, const float *target, int B, flo
 
 using namespace ds;
 
+// ---------------------------------------------------------------- allocation-free plain form
+// Scratch of ds_predict_f32_noalloc: the descriptor rows, activations and flags of one
+// chunk of points.  Every GPU the library runs on holds its own copy of this array from
+// module load until the process ends.  In host code its name is only a stand-in: kernels
+// get the device address that hipGetSymbolAddress gives for the current device, taken
+// once per device at ds_create and kept in g_scratch.
+static constexpr size_t kScratchBytes = (size_t)32 << 20;
+static constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static void *g_scratch[kScratchDevices];
+static std::mutex g_scratch_mutex;
+
+// With `device` current: its address of `scratch`, once.
+static ds_status scratch_setup(int device)
+{
+    DS_CHECK(device >= 0 && device < kScratchDevices, DS_ERR_UNSUPPORTED,
+             "device %d: the scratch table covers devices 0..%d", device, kScratchDevices - 1);
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (g_scratch[device])
+        return DS_OK;
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess)
+        return hip_fail(e, "scratch address");
+    DS_CHECK(ptr, DS_ERR_DEVICE, "scratch address: NULL");
+    g_scratch[device] = ptr;
+    return DS_OK;
+}
+
 // A distant emitter as m directional lights (Sec. 4.4): per light the unit direction and
 // the weight E_j / p_j (device float4), and the selection thresholds (device).
 // A tabulated phase function on the device (FP32 copies of the host FP64 table).
@@ -728,6 +758,9 @@ ds_status ds_create(int device, void *hip_stream, ds_ctx **out)
     DS_CHECK(device >= 0 && device < n, DS_ERR_INVALID_ARG, "ds_create: device %d of %d", device,
              n);
     DS_HIP(hipSetDevice(device));
+    ds_status st = scratch_setup(device);
+    if (st)
+        return st;
     ds_ctx *c = new (std::nothrow) ds_ctx();
     DS_CHECK(c, DS_ERR_OOM, "ds_create: out of host memory");
     c->device = device;
@@ -1274,6 +1307,55 @@ ds_status ds_predict_reserve(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *n
     DS_TRY(ensure_ws(ctx, sizeof(float) * (size_t)rows * (D + 3 * (size_t)net->W) + (size_t)rows));
     DS_TRY(gather_cells(ctx, cloud));
     DS_HIP(hipStreamSynchronize(ctx->stream));
+    return DS_OK;
+}
+
+ds_status ds_predict_f32_noalloc(ds_ctx *ctx, const ds_cloud *cloud, const ds_net *net,
+                                 const float *pos, const float *view_dir, const float *light_dir,
+                                 int64_t P, float *out, float *pre_out, uint8_t *flags)
+{
+    DS_CHECK(ctx && cloud && net, DS_ERR_INVALID_ARG,
+             "ds_predict_f32_noalloc: NULL context, cloud or net");
+    DS_CHECK(cloud->K == net->K, DS_ERR_INVALID_ARG,
+             "ds_predict_f32_noalloc: the cloud has %d stencil levels, the network %d", cloud->K,
+             net->K);
+    DS_CHECK(P >= 0 && P <= ((int64_t)1 << 31), DS_ERR_INVALID_ARG,
+             "ds_predict_f32_noalloc: bad P");
+    if (P == 0)
+        return DS_OK;
+    DS_CHECK(pos && view_dir && light_dir && out, DS_ERR_INVALID_ARG,
+             "ds_predict_f32_noalloc: NULL device pointer");
+    DS_CHECK(ctx->device >= 0 && ctx->device < kScratchDevices && g_scratch[ctx->device],
+             DS_ERR_STATE, "ds_predict_f32_noalloc: no scratch address for device %d",
+             ctx->device);
+    DS_CHECK(cloud->cells32, DS_ERR_STATE,
+             "ds_predict_f32_noalloc: the cloud's float32 corner cells do not exist (building "
+             "them allocates): call ds_predict_reserve with DS_PREC_F32 once first");
+    // a chunk: descriptor rows [rows][D], three activation buffers [rows][W], flags [rows]
+    const int D = kStencil * net->K + 1;
+    const size_t per_point = sizeof(float) * ((size_t)D + 3 * (size_t)net->W) + 1;
+    const int64_t fit = (int64_t)((kScratchBytes - 256) / per_point) / 64 * 64;
+    DS_CHECK(fit >= 64, DS_ERR_INVALID_ARG,
+             "ds_predict_f32_noalloc: a point needs %zu bytes of scratch, %zu bytes hold fewer "
+             "than 64 points", per_point, kScratchBytes);
+    const int64_t rows = P < fit ? P : fit;
+    float *z = static_cast<float *>(g_scratch[ctx->device]);
+    float *O = z + rows * D;
+    uint8_t *fl_ws = reinterpret_cast<uint8_t *>(O + 3 * rows * net->W);
+    GatherArgs a;
+    gather_args(cloud, pos, view_dir, light_dir, P, a);
+    for (int64_t p0 = 0; p0 < P; p0 += rows) {
+        const int64_t np = (P - p0) < rows ? (P - p0) : rows;
+        uint8_t *fl = flags ? flags : fl_ws - p0;  // the gather writes absolute indices
+        ds_status st = gather_plain(ctx->stream, a, p0, np, DS_F32, z, D, fl);
+        if (!st)
+            st = forward_plain(ctx, net, z, np, out + p0, pre_out ? pre_out + p0 : nullptr, O,
+                               O + rows * net->W, O + 2 * rows * net->W);
+        if (!st)
+            st = mask_invalid(ctx->stream, fl + p0, np, out + p0, pre_out ? pre_out + p0 : nullptr);
+        if (st)
+            return st;
+    }
     return DS_OK;
 }
 
