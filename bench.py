@@ -82,6 +82,33 @@ def measured_traffic(kname):
     return None, ""
 
 
+def cpu_model():
+    """The host CPU's model name (first "model name" line of /proc/cpuinfo)."""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_rate(O, fn, n_points, threads, repeats=3):
+    """Median over `repeats` runs of fn() (which evaluates n_points points) on `threads`
+    host threads, as points/s; also the individual run times."""
+    old = O.threads()
+    O.set_threads(threads)
+    try:
+        times = []
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            fn()
+            times.append(time.perf_counter() - t0)
+    finally:
+        O.set_threads(old)
+    return n_points / float(np.median(times)), times
+
+
 def macs_per_point(K, W, H):
     return 226 * K * W + (K - 1) * W * W + K * W * W + (H - 1) * W * W + W
 
@@ -176,6 +203,7 @@ def run_batched(args, log):
     same = bool(torch.equal(seq, out))
     # the FP8 form: calibrated on the 512^3 cloud's points, the same plan shape
     fp8 = None
+    out8_keep = None
     if not args.no_fp8:
         ci = cfg["sizes"].index(512)
         a0, a1 = int(offsets[ci]), int(offsets[ci + 1])
@@ -187,6 +215,7 @@ def run_batched(args, log):
         ds.ds_batch_capture(b8, ds.DS_PREC_FP8, pos, view, light, out8)
         ms8, kms8 = replay_timed(b8)
         ds.ds_batch_destroy(b8)
+        out8_keep = out8
         fp8 = {"ms_per_step": round(ms8, 4), "value": round(N / (ms8 / 1e3), 1),
                "kernel_ms": round(kms8, 4), "speedup_over_bf16": round(ms_step / ms8, 3),
                "autotuned": tuned8}
@@ -195,6 +224,72 @@ def run_batched(args, log):
     achieved = flop / (kernel_ms / 1e3) / 1e12
     log(f"batched graph replay {ms_step:.3f} ms ({kernel_ms:.3f} ms events), per-cloud "
         f"launches {ms_seq:.3f} ms, identical outputs {same}")
+    # oracle on a strided sample of every cloud's points: parity of the BF16 (and FP8) batch
+    # outputs, and the oracle's own rate (gather + network, pyramids excluded)
+    cpu, parity = None, None
+    if not args.no_cpu:
+        sys.path.insert(0, HERE)
+        import oracle as O
+        theta64 = theta_for(synth, K, W, H, cfg["seed_theta"]).astype(np.float64)
+        out_h = out.cpu().numpy()
+        out8_h = out8_keep.cpu().numpy() if fp8 else None
+        pos_h, view_h, light_h = pos.cpu().numpy(), view.cpu().numpy(), light.cpu().numpy()
+        per = max(1, args.batch_cpu_sample // len(cfg["sizes"]))
+        want, got, got8, n_pts = [], [], [], 0
+        jobs = []
+        for ci, (n, sd) in enumerate(zip(cfg["sizes"], cfg["seeds"])):
+            a0, a1 = int(offsets[ci]), int(offsets[ci + 1])
+            sel = np.unique(np.linspace(a0, a1 - 1, min(per, a1 - a0)).astype(np.int64))
+            d = synth.cloud_density(n, sd, worley=0.3, device=dev, dtype=torch.bfloat16)
+            bits = d.cpu().view(torch.int16).numpy().view(np.uint16)
+            del d
+            amin, h0 = synth.unit_box(n)
+            L = min(16, int(math.ceil(math.log2(n))) + 1)
+            grid = O.Grid(bits, float(n), amin, h0)
+            tp = time.time()
+            mean, _ = O.normalize(grid)
+            pyr, dims, offs = O.pyramid(grid, mean, L)
+            mips = O.default_mips(mean, h0, K, L)
+            log(f"oracle pyramid {n}^3: {time.time() - tp:.1f}s")
+            if list(mips) != list(clouds[ci].info["mip_of_level"]):
+                log(f"cloud {n}^3: oracle and library mip maps differ, skipped")
+                continue
+            z, _ = O.gather(grid, pyr, dims, offs, mean, K, mips, pos_h[sel], view_h[sel],
+                            light_h[sel])
+            g, _ = O.forward(theta64, K, W, H, z)
+            want.append(g)
+            got.append(out_h[sel])
+            if out8_h is not None:
+                got8.append(out8_h[sel])
+            n_pts += sel.size
+            jobs.append((grid, pyr, dims, offs, mean, mips, sel))
+        rl = lambda x, y: float(np.linalg.norm(x - y) / max(np.linalg.norm(y), 1e-30))
+        want = np.concatenate(want)
+        parity = {"sampled_points": n_pts, "rel_l2_bf16": rl(np.concatenate(got), want),
+                  "rel_l2_fp8": rl(np.concatenate(got8), want) if got8 else None,
+                  "tolerance_bf16": 2e-2, "tolerance_fp8": 5e-2}
+        log(f"batched parity: {parity}")
+
+        def oracle_points(frac=1):
+            for grid, pyr, dims, offs, mean, mips, sel in jobs:
+                sl = sel[::frac]
+                z, _ = O.gather(grid, pyr, dims, offs, mean, K, mips, pos_h[sl], view_h[sl],
+                                light_h[sl])
+                O.forward(theta64, K, W, H, z)
+        all_threads = O.threads()
+        rate, runs = oracle_rate(O, oracle_points, n_pts, all_threads)
+        n1 = sum(j[-1][::16].size for j in jobs)
+        rate1, runs1 = oracle_rate(O, lambda: oracle_points(16), n1, 1)
+        cpu = {"value": round(rate, 2), "unit": "shading points/s", "cores": all_threads,
+               "kind": "oracle",
+               "sample": f"{n_pts} of the {N} points (evenly strided within each cloud), FP64 "
+                         f"gather + network, median of 3 runs "
+                         f"({', '.join(f'{t:.2f}' for t in runs)} s); pyramids excluded",
+               "single_thread": {"value": round(rate1, 2), "unit": "shading points/s",
+                                 "sample": f"{n1} of those points, median of 3 runs "
+                                           f"({', '.join(f'{t:.2f}' for t in runs1)} s)"},
+               "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+        log(f"oracle: {rate:.1f} points/s on {all_threads} threads, {rate1:.1f} on 1 thread")
     line = {
         "metric": METRIC, "value": round(N / (ms_step / 1e3), 1), "unit": "shading points/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
@@ -207,7 +302,7 @@ def run_batched(args, log):
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
                      "traffic": None, "kernel": "fused prediction, autotuned variant",
                      "flop_per_point": 2 * macs_per_point(K, W, H), "points_per_launch": N},
-        "cpu_baseline": None, "fp8": fp8,
+        "cpu_baseline": cpu, "fp8": fp8, "parity": parity,
     }
     ds.ds_batch_destroy(b)
     net.close()
@@ -224,13 +319,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper", choices=sorted(WORKLOADS) + ["batched"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the FP64 oracle baseline")
-    ap.add_argument("--cpu-sample", type=int, default=262144)
+    ap.add_argument("--cpu-sample", type=int, default=65536)
+    ap.add_argument("--batch-cpu-sample", type=int, default=16384,
+                    help="oracle sample of the batched workload, spread over its clouds")
     ap.add_argument("--fp32-steps", type=int, default=3, help="0 skips the FP32 plain form")
     ap.add_argument("--save-inputs", default=None, help="write the generated inputs to this .npz")
     ap.add_argument("--load-inputs", default=None,
                     help="read inputs written by --save-inputs instead of generating them "
                          "(keeps generator kernels out of profiled runs)")
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 form")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the shuffled-order and front/back-light timings")
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default kernel variant instead of the autotuned one")
     ap.add_argument("--variant", default=None,
@@ -342,6 +441,33 @@ def main():
                                   "(BF16 MFMA, stencil gather fused)",
                 "flop_per_point": 2 * macs_per_point(K, W, H), "points_per_launch": P}
 
+    # ------------------------------------------------- same launch: point order, lights
+    # the tuned BF16 launch on the same points in a random order (neighbouring lanes no
+    # longer share cells: the worst case of the camera-ordered workload) and under the
+    # front and back lights of the same view
+    variants = None
+    if not args.no_variants:
+        variants = {}
+        g = torch.Generator(device="cpu").manual_seed(cfg["seed_pts"] + 1)
+        perm = torch.randperm(P, generator=g).to(dev)
+        cases = [("shuffled_order", pos[perm].contiguous(), view[perm].contiguous(), light)]
+        for lname in ("front", "back"):
+            lt = torch.from_numpy(np.broadcast_to(synth.table1_lights()[lname], (P, 3)).copy())
+            cases.append((f"{lname}_light", pos, view, lt.to(dev)))
+        tv = ds.ds_batch_create(ctx.h, net.h, [cloud.h], [0, P])
+        try:
+            kv, wv, gv = tuned["kernel"], tuned["waves"], tuned["grid"]
+            ds.ds_batch_set_config(tv, kv, wv, gv)
+            out_v = torch.empty(P, dtype=torch.float32, device=dev)
+            for name, pv, vv, lv in cases:
+                ds.ds_batch_capture(tv, ds.DS_PREC_BF16, pv, vv, lv, out_v)
+                msv, kmsv = timed(lambda: ds.ds_batch_replay(tv))
+                variants[name] = {"ms_per_step": round(msv, 4), "kernel_ms": round(kmsv, 4),
+                                  "value": round(P / (msv / 1e3), 1)}
+                log(f"bf16 fused, {name}: {msv:.3f} ms/step, {P / (msv / 1e3):.3e} points/s")
+        finally:
+            ds.ds_batch_destroy(tv)
+
     # ---------------------------------------------------------------- FP8 form
     fp8 = None
     out8 = torch.empty(P, dtype=torch.float32, device=dev)
@@ -409,20 +535,33 @@ def main():
         pyr, dims, offs = O.pyramid(grid, mean, cfg["L"])
         mips = O.default_mips(mean, h0, K, cfg["L"])
         log(f"oracle pyramid {time.time() - tp:.1f}s (not part of the timed sample)")
-        tc = time.perf_counter()
+        th64 = theta.astype(np.float64)
         g_ref = np.zeros(S)
-        chunk = 4096
-        for c0 in range(0, S, chunk):
-            sl = idx[c0:c0 + chunk]
-            z, _ = O.gather(grid, pyr, dims, offs, mean, K, mips, pos_np[sl], view_np[sl],
-                            light_np[sl])
-            g_ref[c0:c0 + chunk], _ = O.forward(theta.astype(np.float64), K, W, H, z)
-        tcpu = time.perf_counter() - tc
-        cpu = {"value": round(S / tcpu, 2), "unit": "shading points/s", "cores": O.threads(),
+
+        def oracle_points(sel, dst=None):
+            for c0 in range(0, sel.size, 4096):
+                sl = sel[c0:c0 + 4096]
+                z, _ = O.gather(grid, pyr, dims, offs, mean, K, mips, pos_np[sl], view_np[sl],
+                                light_np[sl])
+                g, _ = O.forward(th64, K, W, H, z)
+                if dst is not None:
+                    dst[c0:c0 + sl.size] = g
+        all_threads = O.threads()
+        rate, runs = oracle_rate(O, lambda: oracle_points(idx, g_ref), S, all_threads)
+        S1 = max(1, S // 32)
+        idx1 = idx[:: max(1, S // S1)][:S1]
+        rate1, runs1 = oracle_rate(O, lambda: oracle_points(idx1), idx1.size, 1)
+        cpu = {"value": round(rate, 2), "unit": "shading points/s", "cores": all_threads,
                "kind": "oracle",
-               "sample": f"{S} of the {P} shading points (evenly strided), FP64 gather + "
-                         f"network, {tcpu:.1f} s"}
-        log(f"oracle: {S / tcpu:.1f} points/s on {O.threads()} threads")
+               "sample": f"{S} of the {P} shading points (evenly strided), FP64 gather + network, "
+                         f"median of 3 runs ({', '.join(f'{t:.2f}' for t in runs)} s) on "
+                         f"{all_threads} threads; pyramid build excluded",
+               "single_thread": {"value": round(rate1, 2), "unit": "shading points/s",
+                                 "sample": f"{idx1.size} of the same points, median of 3 runs "
+                                           f"({', '.join(f'{t:.2f}' for t in runs1)} s)"},
+               "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+        log(f"oracle: {rate:.1f} points/s on {all_threads} threads, {rate1:.1f} on 1 thread "
+            f"({cpu['cpu_model']})")
         same_mips = list(mips) == list(cloud.info["mip_of_level"])
         g16 = out.cpu().numpy()[idx]
         g32 = out32.cpu().numpy()[idx] if fp32 else None
@@ -444,7 +583,7 @@ def main():
                    "W": W, "trailing_layers": H, "points": P, "precision": "bf16",
                    "light": "side"},
         "roofline": roofline, "cpu_baseline": cpu, "fp32_plain": fp32, "fp8": fp8,
-        "parity": parity,
+        "parity": parity, "variants": variants,
         "kernel_ms": round(avg_kernel_ms, 4), "default_variant_ms": round(ms_default, 4),
         "autotuned": tuned,
     }

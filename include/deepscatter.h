@@ -360,7 +360,10 @@ ds_status ds_train_replay(ds_adam *opt);
  * Philox4x32-10 with key = seed and counter = (stream id low, high, block, 0),
  * uniforms are the top 24 bits of each word times 2^-24; stream ids are stated
  * per call.  Path estimates are FP32; per-record sums are FP64 and reduced in a
- * fixed order, so every result is bitwise reproducible for a given seed. */
+ * fixed order, so every result is bitwise reproducible for a given seed.  A path
+ * stops after 2^26 tentative collisions (free-flight and transmittance steps
+ * together): its estimate keeps what it gathered so far and the context counts it (see
+ * ds_tracer_truncated); the estimators of the paper have no such bound. */
 #define DS_LIGHT_DIRECTIONAL 0 /* a directional light of irradiance E, next-event estimation */
 #define DS_LIGHT_ENVIRONMENT 1 /* a uniform environment of radiance E, counted on escape     */
 
@@ -418,6 +421,11 @@ typedef struct ds_tracer_params {
                                     albedo (1 - f) mu_t restores the full scattering
                                     albedo mu_t (the library's reading)                  */
 } ds_tracer_params;
+
+/* Number of paths of this context's tracer calls that stopped at the bound of 2^26
+ * tentative collisions, since ds_create or the last reset (reset != 0 clears it).
+ * Synchronises the stream. */
+ds_status ds_tracer_truncated(ds_ctx *ctx, int64_t *count, int reset);
 
 /* The cloud's majorant sigma_max * max(d) (host write). */
 ds_status ds_cloud_majorant(const ds_cloud *cloud, float *majorant);

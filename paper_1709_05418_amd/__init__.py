@@ -82,6 +82,7 @@ def lib():
         "ds_net_fp8_scales": (S, [P, P, S]),
         "ds_fp8_e4m3_encode": (S, [P, I64, S, P]),
         "ds_cloud_majorant": (S, [P, P]),
+        "ds_tracer_truncated": (S, [P, P, I]),
         "ds_trace_li": (S, [P, P, P, P, P, P, I64, I, C.c_uint64, P, P]),
         "ds_sample_records": (S, [P, P, I64, C.c_uint64, P, P, P, P]),
         "ds_render_mc": (S, [P, P, P, P, P, P, I64, I, C.c_uint64, P, P]),
@@ -438,6 +439,13 @@ def ds_train_capture(net, opt, z, target_log1p, loss):
 
 def ds_train_replay(opt):
     _check(lib().ds_train_replay(opt))
+
+
+def ds_tracer_truncated(ctx, reset=False) -> int:
+    """Paths stopped at the tracer's bound on tentative collisions (see the header)."""
+    n = C.c_int64()
+    _check(lib().ds_tracer_truncated(ctx, C.byref(n), int(bool(reset))))
+    return n.value
 
 
 def ds_cloud_majorant(cloud) -> float:

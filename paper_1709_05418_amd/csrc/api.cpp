@@ -765,7 +765,28 @@ ds_status ds_create(int device, void *hip_stream, ds_ctx **out)
     DS_CHECK(c, DS_ERR_OOM, "ds_create: out of host memory");
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipMalloc(&c->truncated, sizeof(unsigned long long)) != hipSuccess ||
+        hipMemset(c->truncated, 0, sizeof(unsigned long long)) != hipSuccess) {
+        (void)hipFree(c->truncated);
+        delete c;
+        set_error("ds_create: out of device memory for the tracer counter");
+        return DS_ERR_OOM;
+    }
     *out = c;
+    return DS_OK;
+}
+
+ds_status ds_tracer_truncated(ds_ctx *ctx, int64_t *count, int reset)
+{
+    DS_CHECK(ctx && count, DS_ERR_INVALID_ARG, "ds_tracer_truncated: NULL argument");
+    unsigned long long h = 0;
+    DS_HIP(hipMemcpyAsync(&h, ctx->truncated, sizeof(h), hipMemcpyDeviceToHost, ctx->stream));
+    DS_HIP(hipStreamSynchronize(ctx->stream));
+    *count = (int64_t)h;
+    if (reset) {
+        DS_HIP(hipMemsetAsync(ctx->truncated, 0, sizeof(h), ctx->stream));
+        DS_HIP(hipStreamSynchronize(ctx->stream));
+    }
     return DS_OK;
 }
 
@@ -791,6 +812,7 @@ ds_status ds_destroy(ds_ctx *ctx)
         (void)hipStreamSynchronize(ctx->stream);
     (void)hipFree(ctx->ws);
     (void)hipFree(ctx->ws2);
+    (void)hipFree(ctx->truncated);
     delete ctx;
     return DS_OK;
 }

@@ -57,6 +57,8 @@ struct ds_ctx {
     // second workspace for calls that chain other calls using the first
     void *ws2 = nullptr;
     size_t ws2_bytes = 0;
+    // device: paths of the tracer calls stopped at the bound on tentative collisions
+    unsigned long long *truncated = nullptr;
 };
 
 struct ds_cloud {

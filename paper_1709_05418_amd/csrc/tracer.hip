@@ -127,7 +127,16 @@ struct Medium {
     float inv_ff;         // mean free-flight length 1 / (maj * extinction scale); the scale
                           // thins the medium uniformly (the chop of a tabulated phase
                           // function), so collision and transmittance ratios keep maj
+    unsigned long long *truncated;  // paths stopped at kMaxSteps (the context's counter)
 };
+
+// A path whose tentative collisions reach kMaxSteps stops there; the call that crosses
+// the bound counts it once in the context's counter (s0: the path's count before the call).
+__device__ __forceinline__ void note_cap(const Medium &M, int64_t s0, int64_t steps)
+{
+    if (steps >= kMaxSteps && s0 < kMaxSteps && M.truncated)
+        atomicAdd(M.truncated, 1ull);
+}
 
 // Voxel-centred trilinear extinction, zero outside the grid.  The cell coordinate (the
 // voxel-centred coordinate plus one), clamped to [0, n + 1], selects a cell whose eight
@@ -192,6 +201,7 @@ __device__ bool delta_track(const Medium &M, V3 o, V3 d, Rng &r, V3 &x, int64_t 
         return false;
     float t = t0;
     const float inv = M.inv_ff;
+    const int64_t s0 = steps;
     while (steps < kMaxSteps) {
         ++steps;
         t += exp_flight(r.u()) * inv;
@@ -203,6 +213,7 @@ __device__ bool delta_track(const Medium &M, V3 o, V3 d, Rng &r, V3 &x, int64_t 
             return true;
         }
     }
+    note_cap(M, s0, steps);
     return false;
 }
 
@@ -214,13 +225,15 @@ __device__ float ratio_track(const Medium &M, V3 o, V3 d, Rng &r, int64_t &steps
         return 1.f;
     float T = 1.f, t = t0;
     const float inv = 1.f / M.maj;
+    const int64_t s0 = steps;
     while (steps < kMaxSteps) {
         ++steps;
         t += exp_flight(r.u()) * M.inv_ff;
         if (t >= t1)
-            break;
+            return T;
         T *= 1.f - mu_at(M, madd(o, t, d)) * inv;
     }
+    note_cap(M, s0, steps);
     return T;
 }
 
@@ -859,6 +872,7 @@ Medium medium(const ds_cloud *c, float ext_scale = 1.f)
     M.inv_h = (float)(1.0 / (double)c->h0);
     M.maj = c->majorant;
     M.inv_ff = (float)(1.0 / ((double)c->majorant * (double)ext_scale));
+    M.truncated = c->ctx->truncated;
     return M;
 }
 

@@ -175,3 +175,70 @@ def test_batch_argument_checks(ctx, setup):
             ds.ds_batch_replay(b)
     finally:
         ds.ds_batch_destroy(b)
+
+
+@pytest.fixture(scope="module")
+def paper_width_batch(ctx):
+    # the batched configuration's shape at sizes the oracle handles: five BF16 clouds of
+    # 48^3 .. 128^3 (sigma_max = n / unit, fBm + Worley), log-uniform point counts, K = 10
+    # stencil levels with the mip levels clamped on the small clouds, W = 200
+    sizes = [48, 64, 80, 96, 128]
+    rng = np.random.default_rng(210)
+    counts = np.exp(rng.uniform(np.log(300), np.log(5000), len(sizes))).astype(np.int64).tolist()
+    Kp, Wp = 10, 200
+    ws, clouds = [], []
+    for i, (n, P) in enumerate(zip(sizes, counts)):
+        dens = synth.cloud_density(n, 110 + i, worley=0.3).to(torch.bfloat16)
+        L = int(np.ceil(np.log2(n))) + 1
+        w = Workload(n, float(n), L=L, K=Kp, P=P, seed_cloud=110 + i, seed_pts=310 + i,
+                     density=dens)
+        ws.append(w)
+        clouds.append(ds.Cloud(ctx, dens.cuda(), w.sigma_max, w.aabb_min, w.h0, w.L, Kp, w.mips))
+    offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    cat = lambda k: torch.from_numpy(np.concatenate([getattr(w, k) for w in ws])).cuda()
+    net = ds.Net(ctx, Kp, Wp, 3)
+    theta = synth.init_params(Kp, Wp, 3, 12, branch_scale=1 / np.sqrt(Kp), out_scale=0.2,
+                              out_bias=0.5)
+    net.set_params(theta)
+    yield dict(ws=ws, clouds=clouds, counts=counts, offsets=offsets, pos=cat("pos"),
+               view=cat("view"), light=cat("light"), net=net, theta=theta, K=Kp, W=Wp)
+    net.close()
+    for c in clouds:
+        c.close()
+
+
+@pytest.mark.parametrize("prec,tol", [(ds.DS_PREC_BF16, 2e-2), (ds.DS_PREC_FP8, 5e-2)])
+def test_paper_width_batch_autotuned_graph_matches_oracle(ctx, paper_width_batch, prec, tol):
+    s = paper_width_batch
+    N = int(s["offsets"][-1])
+    if prec == ds.DS_PREC_FP8:  # calibrated on the largest cloud's points, as the bench does
+        a, b = int(s["offsets"][-2]), int(s["offsets"][-1])
+        ds.ds_net_quantize(ctx.h, s["net"].h, s["clouds"][-1].h, ds.DS_PREC_FP8,
+                           s["pos"][a:b].contiguous(), s["view"][a:b].contiguous(),
+                           s["light"][a:b].contiguous())
+    bt = ds.ds_batch_create(ctx.h, s["net"].h, [c.h for c in s["clouds"]], s["offsets"])
+    try:
+        out = torch.full((N,), -1.0, device="cuda")
+        pre = torch.full((N,), -1.0, device="cuda")
+        cfg = ds.ds_batch_autotune(bt, prec, s["pos"], s["view"], s["light"], out, 2)
+        ds.ds_batch_capture(bt, prec, s["pos"], s["view"], s["light"], out, pre)
+        out.fill_(-1.0)
+        pre.fill_(-1.0)
+        ds.ds_batch_replay(bt)
+        torch.cuda.synchronize()
+        got, gotp, want, wantp = [], [], [], []
+        for w, P, a in zip(s["ws"], s["counts"], s["offsets"]):
+            idx = np.arange(0, P, 3)
+            z, _ = w.oracle_z(idx)
+            g, p = O.forward(s["theta"].astype(np.float64), s["K"], s["W"], 3, z)
+            want.append(g)
+            wantp.append(p)
+            got.append(out.cpu().numpy()[a + idx])
+            gotp.append(pre.cpu().numpy()[a + idx])
+        e = rel_l2(np.concatenate(gotp), np.concatenate(wantp))
+        eg = rel_l2(np.concatenate(got), np.concatenate(want))
+        print(f"paper-width batch, precision {prec}, {cfg}: relative L2 pre-activation {e:.2e}, "
+              f"g {eg:.2e}", flush=True)
+        assert e <= tol and eg <= tol
+    finally:
+        ds.ds_batch_destroy(bt)

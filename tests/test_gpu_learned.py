@@ -235,3 +235,51 @@ def test_trained_network_beats_direct_light_only(ctx):
     finally:
         for c in clouds:
             c.close()
+
+
+def test_trained_paper_width_network_matches_oracle(ctx):
+    # a K = 10, W = 200 network trained here on path-traced pairs (BF16 arithmetic, FP32
+    # masters), then its BF16 and FP8 predictions on points of a held-out cloud against the
+    # FP64 oracle's forward pass of the same trained parameters, element by element
+    n, sig, L, K, W = 64, 64.0, 7, 10, 200
+    prm = ds.TracerParams(0.999, 0.85, 1.0, 0, 0)
+    clouds = []
+    net = opt = cloud = None
+    try:
+        for c in range(3):
+            d = synth.cloud_density(n, 600 + c, worley=0.3, device="cuda")
+            amin, h0 = synth.unit_box(n)
+            clouds.append(ds.Cloud(ctx, d, sig, amin, h0, L, K))
+        z, t = learn.make_dataset(ctx, clouds, 16384, 64, 2100, prm)
+        net = ds.Net(ctx, K, W, 3)
+        net.set_params(synth.init_params(K, W, 3, 5, branch_scale=1 / np.sqrt(K), out_scale=0.01,
+                                         out_bias=float(torch.expm1(t).mean())))
+        ds.ds_net_set_train_precision(net.h, ds.DS_PREC_BF16)
+        opt = ds.ds_adam_create(net.h, 1e-3)
+        res = learn.train(net, opt, z, t, 1500, 1024, 0.25, eval_every=500,
+                          log=lambda m: print(m, flush=True))
+        assert res["held_out"][-1][1] < 0.5 * res["held_out"][0][1], res["held_out"]
+        theta = net.get_params().astype(np.float64)
+        w = Workload(n, sig, L=L, K=K, P=2048, seed_cloud=603, seed_pts=604, worley=0.3)
+        zo, _ = w.oracle_z()
+        g_ref, pre_ref = O.forward(theta, K, W, 3, zo)
+        cloud = ds.Cloud(ctx, w.density.cuda(), w.sigma_max, w.aabb_min, w.h0, w.L, w.K, w.mips)
+        pos, view, light = w.cuda_inputs()
+        errs = {}
+        for name, prec, tol in (("bf16", ds.DS_PREC_BF16, 2e-2), ("fp8", ds.DS_PREC_FP8, 5e-2)):
+            if prec == ds.DS_PREC_FP8:
+                ds.ds_net_quantize(ctx.h, net.h, cloud.h, ds.DS_PREC_FP8, pos, view, light)
+            g, pre, _ = ds.ds_predict(ctx.h, cloud.h, net.h, prec, pos, view, light)
+            errs[name] = (rel_l2(pre.cpu().numpy(), pre_ref), rel_l2(g.cpu().numpy(), g_ref))
+            print(f"trained K=10 W=200 network, {name}: relative L2 of the final "
+                  f"pre-activation {errs[name][0]:.2e}, of g {errs[name][1]:.2e}", flush=True)
+            assert errs[name][0] <= tol and errs[name][1] <= tol, (name, errs[name])
+    finally:
+        if opt is not None:
+            ds.ds_adam_destroy(opt)
+        if net is not None:
+            net.close()
+        if cloud is not None:
+            cloud.close()
+        for c in clouds:
+            c.close()

@@ -262,3 +262,32 @@ def test_first_hits(ctx, small_cloud, small):
     p_gpu = hits / S
     sd = np.sqrt(p_ref * (1 - p_ref) / S + p_gpu * (1 - p_gpu) / 256) + 1e-9
     assert np.all(np.abs(p_gpu - p_ref) <= 5 * sd + 1.0 / S)
+
+
+def test_long_paths_at_albedo_0999_without_a_cap_match_oracle(ctx):
+    # the training configuration's regime: albedo 0.999, HG g = 0.85, no interaction cap,
+    # in a 32^3 cloud as optically thick per unit length as the 256^3 training clouds
+    # (sigma_max 256 / unit); paths of hundreds to thousands of scattering events
+    w = Workload(32, 256.0, L=5, K=5, P=64, seed_cloud=4, seed_pts=21)
+    cloud = ds.Cloud(ctx, w.density.cuda(), w.sigma_max, w.aabb_min, w.h0, w.L, w.K, w.mips)
+    try:
+        ds.ds_tracer_truncated(ctx.h, reset=True)
+        spp, seed = 128, 5
+        prm = ds.TracerParams(0.999, 0.85, 1.0, 0, 0)
+        pos, view, light = w.cuda_inputs()
+        m, v = ds.ds_trace_li(ctx.h, cloud.h, prm, pos, view, light, spp, seed)
+        m, v = m.cpu().numpy(), v.cpu().numpy()
+        mo, vo = O.trace_li(w.grid, w.pos, w.view, w.light, albedo=0.999, g=0.85, spp=spp,
+                            seed=seed)
+        rel = np.abs(m - mo) / np.maximum(np.abs(mo), 1e-6)
+        print(f"albedo 0.999: mean L_i {mo.mean():.4f}, median relative difference "
+              f"{np.median(rel):.2e}, max |diff| / sigma "
+              f"{np.max(np.abs(m - mo) / np.sqrt(v + vo + 1e-30)):.2f}", flush=True)
+        assert _agree(m, v, mo, vo).size == 0
+        assert mo.mean() > 0.02                      # the paths gather light
+        # the same estimator: the per-record variances agree in the bulk
+        ratio = np.median(v / np.maximum(vo, 1e-30))
+        assert 0.5 < ratio < 2.0, ratio
+        assert ds.ds_tracer_truncated(ctx.h) == 0    # no path reached the collision bound
+    finally:
+        cloud.close()
