@@ -59,12 +59,23 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
+def short_kernel_name(k):
+    """Kernel and its first two template arguments (tiles, waves): "k_fused_reg<13, 4, false,
+    false>" -> "k_fused_reg<13,4>"."""
+    k = k.replace(" ", "")
+    if "<" in k:
+        name, args = k.split("<", 1)
+        k = name + "<" + ",".join(args.rstrip(">").split(",")[:2]) + ">"
+    return k
+
+
 def measured_traffic(kname):
     """(HBM bytes per launch, grid) of the fused BF16 kernel instantiation kname (as
-    "k_fused_reg<13,8>") from the committed counter summaries, or (None, "") when none
-    covers it or the kernel sources changed since the counters were taken.  The persistent
-    grid of a launch does not change the kernel's code; each summary states the grid it was
-    taken at, returned beside the bytes."""
+    "k_fused_reg<13,8>"; a launch is its unclamped pass plus its clamped pass) from the
+    committed counter summaries, or (None, "") when none covers it or the kernel sources
+    changed since the counters were taken.  The persistent grid of a launch does not change
+    the kernel's code; each summary states the grid it was taken at, returned beside the
+    bytes."""
     import glob
     for f in sorted(glob.glob(os.path.join(PROFILES, "*bf16*_hbm_traffic.txt"))):
         vals = {}
@@ -72,7 +83,7 @@ def measured_traffic(kname):
             if ":" in ln and not ln.startswith("#"):
                 k, v = ln.split(":", 1)
                 vals[k.strip()] = v.strip()
-        k = vals.get("kernel", "").replace(",false>", ">")
+        k = short_kernel_name(vals.get("kernel", ""))
         if k != kname or vals.get("kernel_sources_sha256") != kernel_sources_sha256():
             continue
         try:
@@ -130,12 +141,15 @@ BATCHED = dict(sizes=[128, 192, 256, 384, 512, 640, 768, 1024], seeds=list(range
                point_seed=200, pts_seeds=list(range(300, 308)), K=10, W=200, H=3, seed_theta=12,
                name="batched uneven inference: 8 BF16 clouds 128^3..1024^3 (sigma_max = n/unit, "
                     "fBm+Worley), 10^4..2x10^6 points each (log-uniform), K=10, W=200, one "
-                    "persistent launch replayed from a HIP graph, autotuned variant")
+                    "persistent launch replayed from a HIP graph (each cloud's points put in spatial order "
+                    "on the device per step), autotuned variant")
 
 
 def run_batched(args, log):
-    """Batched uneven workload: one autotuned persistent launch over 8 clouds,
-    captured in a HIP graph and replayed; compared with one ds_predict per cloud."""
+    """Batched uneven workload: one autotuned persistent launch over 8 clouds, the points
+    of each cloud put in spatial order on the device first (inside the timed step),
+    captured in a HIP graph and replayed; compared with the same plan in input order and
+    with one ds_predict per cloud."""
     import torch
     import paper_1709_05418_amd as ds
     from paper_1709_05418_amd import synth
@@ -165,7 +179,9 @@ def run_batched(args, log):
     net = ds.Net(ctx, K, W, H)
     net.set_params(theta_for(synth, K, W, H, cfg["seed_theta"]))
     out = torch.empty(N, dtype=torch.float32, device=dev)
+    order = {"input": ds.DS_ORDER_INPUT, "spatial": ds.DS_ORDER_SPATIAL}[args.batch_order]
     b = ds.ds_batch_create(ctx.h, net.h, [c.h for c in clouds], offsets)
+    ds.ds_batch_set_order(b, order)
     ta = time.time()
     tuned = ds.ds_batch_autotune(b, ds.DS_PREC_BF16, pos, view, light, out, 2)
     log(f"autotune {time.time() - ta:.1f}s: {tuned}")
@@ -187,6 +203,21 @@ def run_batched(args, log):
         wall = time.perf_counter() - tw
         return wall * 1e3 / args.steps, float(np.mean([a.elapsed_time(e) for a, e in evs]))
     ms_step, kernel_ms = replay_timed(b)
+    # the same plan in the other point order
+    other = None
+    if not args.no_variants:
+        b2 = ds.ds_batch_create(ctx.h, net.h, [c.h for c in clouds], offsets)
+        ds.ds_batch_set_order(b2, ds.DS_ORDER_SPATIAL if order == ds.DS_ORDER_INPUT
+                              else ds.DS_ORDER_INPUT)
+        out2 = torch.empty_like(out)
+        tuned2 = ds.ds_batch_autotune(b2, ds.DS_PREC_BF16, pos, view, light, out2, 2)
+        ds.ds_batch_capture(b2, ds.DS_PREC_BF16, pos, view, light, out2)
+        ms2, kms2 = replay_timed(b2)
+        ds.ds_batch_destroy(b2)
+        other = {"order": "input" if order == ds.DS_ORDER_SPATIAL else "spatial",
+                 "ms_per_step": round(ms2, 4), "kernel_ms": round(kms2, 4), "autotuned": tuned2,
+                 "identical_outputs": bool(torch.equal(out2, out))}
+        log(f"batched, {other['order']} order: {ms2:.3f} ms ({kms2:.3f} ms events), {tuned2}")
     # the same points, one default ds_predict per cloud
     seq = torch.empty_like(out)
     def per_cloud():
@@ -211,6 +242,7 @@ def run_batched(args, log):
                            light[a0:a1])
         out8 = torch.empty_like(out)
         b8 = ds.ds_batch_create(ctx.h, net.h, [c.h for c in clouds], offsets)
+        ds.ds_batch_set_order(b8, order)
         tuned8 = ds.ds_batch_autotune(b8, ds.DS_PREC_FP8, pos, view, light, out8, 2)
         ds.ds_batch_capture(b8, ds.DS_PREC_FP8, pos, view, light, out8)
         ms8, kms8 = replay_timed(b8)
@@ -296,8 +328,9 @@ def run_batched(args, log):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
         "data": "synthetic",
         "config": {"workload": cfg["name"], "points": N, "points_per_cloud": counts.tolist(),
-                   "autotuned": tuned, "per_cloud_launches_ms": round(ms_seq, 4),
-                   "batched_equals_per_cloud": same},
+                   "order": args.batch_order, "autotuned": tuned,
+                   "per_cloud_launches_ms": round(ms_seq, 4), "batched_equals_per_cloud": same,
+                   "other_order": other},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
                      "traffic": None, "kernel": "fused prediction, autotuned variant",
@@ -328,6 +361,9 @@ def main():
                     help="read inputs written by --save-inputs instead of generating them "
                          "(keeps generator kernels out of profiled runs)")
     ap.add_argument("--no-fp8", action="store_true", help="skip the FP8 form")
+    ap.add_argument("--batch-order", default="spatial", choices=["spatial", "input"],
+                    help="point order of the batched plan (spatial: each cloud's points sorted "
+                         "by a 32^3 grid cell on the device, inside the timed step)")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the shuffled-order and front/back-light timings")
     ap.add_argument("--no-autotune", action="store_true",

@@ -273,6 +273,21 @@ ds_status ds_batch_capture(ds_batch *batch, ds_precision precision, const float 
                            const float *view_dir, const float *light_dir, float *out,
                            float *pre_out, uint8_t *flags);
 ds_status ds_batch_replay(ds_batch *batch);
+/* Point order of the plan's fused launches (not of its arrays: outputs always follow the
+ * input rows).  DS_ORDER_INPUT (the default) cuts each cloud's rows into tiles as given,
+ * which suits camera-ordered points.  DS_ORDER_SPATIAL first sorts each cloud's points,
+ * on the device and on every call, by the cell of a 32^3 grid over the cloud's box that
+ * holds their position, cells in Morton order (a counting sort; points outside the box or
+ * with a non-finite position go to the nearest cell), so that a tile holds neighbouring
+ * points whose stencils share pyramid cells; the launch then reads and writes each point
+ * through that permutation.  Results are bitwise those of DS_ORDER_INPUT: a point's
+ * prediction does not depend on its tile.  The sort adds four small launches and a
+ * workspace of 8 bytes per point plus 128 KiB per cloud, allocated here (so later calls,
+ * captures included, allocate nothing); capture records the sort with the launch.
+ * Synchronises the context stream and drops a captured graph when the order changes. */
+#define DS_ORDER_INPUT 0
+#define DS_ORDER_SPATIAL 1
+ds_status ds_batch_set_order(ds_batch *batch, int32_t order);
 
 /* ---------------------------------------------------------------- FP8 form */
 /* Builds the network's FP8 form from its current parameters (precision must be

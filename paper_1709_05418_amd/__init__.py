@@ -27,6 +27,7 @@ DS_PREC_F32, DS_PREC_BF16, DS_PREC_FP8 = 0, 1, 2
 DS_FLAG_INVALID, DS_FLAG_OUTSIDE, DS_FLAG_FALLBACK = 1, 2, 4
 DS_LIGHT_DIRECTIONAL, DS_LIGHT_ENVIRONMENT = 0, 1
 DS_KERNEL_REGISTER, DS_KERNEL_PIPELINED, DS_KERNEL_WIDE = 0, 1, 2
+DS_ORDER_INPUT, DS_ORDER_SPATIAL = 0, 1
 STENCIL_N = 225
 
 _lib = None
@@ -96,6 +97,7 @@ def lib():
         "ds_batch_autotune": (S, [P, I, P, P, P, P, I]),
         "ds_batch_capture": (S, [P, I, P, P, P, P, P, P]),
         "ds_batch_replay": (S, [P]),
+        "ds_batch_set_order": (S, [P, S]),
         "ds_make_records": (S, [P, P, P, I64, I, C.c_uint64, I64, P, P, P, P, P, P, P]),
         "ds_render_rpnn": (S, [P, P, P, I, P, P, P, P, I64, I, C.c_uint64, I, P, P, P, P]),
         "ds_trace_li_adaptive": (S, [P, P, P, P, P, P, P, I64, C.c_uint64, P, P, P]),
@@ -567,6 +569,12 @@ def ds_batch_capture(batch, precision, pos, view_dir, light_dir, out, pre=None, 
 
 def ds_batch_replay(batch):
     _check(lib().ds_batch_replay(batch))
+
+
+def ds_batch_set_order(batch, order):
+    """DS_ORDER_INPUT or DS_ORDER_SPATIAL (points of each cloud sorted by a 32^3 grid cell
+    before every fused launch; outputs stay in input order)."""
+    _check(lib().ds_batch_set_order(batch, int(order)))
 
 
 def ds_make_records(ctx, cloud, params: TracerParams, N, spp, seed, z, target, offset=0,

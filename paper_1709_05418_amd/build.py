@@ -14,7 +14,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdeepscatter.so")
 ARCH = os.environ.get("DS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "cloud.hip", "gather.hip", "mlp.hip", "fused.hip", "train.hip", "tracer.hip"]
+SOURCES = ["api.cpp", "cloud.hip", "gather.hip", "mlp.hip", "fused.hip", "order.hip", "train.hip",
+           "tracer.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",

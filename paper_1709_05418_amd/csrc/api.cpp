@@ -1002,6 +1002,7 @@ static void fused_args(const float *pos, const float *view, const float *light, 
     a.out = out;
     a.pre = pre;
     a.flags = flags;
+    a.perm = nullptr;
     a.K = K;
     a.W = W;
     a.H = H;
@@ -1434,7 +1435,23 @@ static ds_status batch_fused(ds_batch *b, hipStream_t s, ds_precision prec, cons
              "batched launch: precision %d is not a fused precision", (int)prec);
     FusedArgs a = {};
     batch_args(b, pos, view, light, out, pre, flags, a);
+    if (b->order == DS_ORDER_SPATIAL) {
+        ds_status st = batch_order(s, a, b->offsets[b->n], b->perm, b->slot, b->counts, b->sums);
+        if (st)
+            return st;
+        a.perm = b->perm;
+    }
     return fused_predict(s, b->net, a, v, prec);
+}
+
+static void batch_free_order(ds_batch *b)
+{
+    int32_t **bufs[4] = {&b->perm, &b->slot, &b->counts, &b->sums};
+    for (int32_t **q : bufs) {
+        if (*q)
+            (void)hipFree(*q);
+        *q = nullptr;
+    }
 }
 
 ds_status ds_batch_create(ds_ctx *ctx, const ds_net *net, int n_clouds,
@@ -1479,7 +1496,41 @@ ds_status ds_batch_destroy(ds_batch *b)
     batch_drop_graph(b);
     if (b->cap_stream)
         (void)hipStreamDestroy(b->cap_stream);
+    if (b->perm)
+        (void)hipSetDevice(b->ctx->device);
+    batch_free_order(b);
     delete b;
+    return DS_OK;
+}
+
+ds_status ds_batch_set_order(ds_batch *b, int32_t order)
+{
+    DS_CHECK(b, DS_ERR_INVALID_ARG, "ds_batch_set_order: batch is NULL");
+    DS_CHECK(order == DS_ORDER_INPUT || order == DS_ORDER_SPATIAL, DS_ERR_INVALID_ARG,
+             "ds_batch_set_order: unknown order %d", (int)order);
+    if (order == b->order)
+        return DS_OK;
+    DS_HIP(hipSetDevice(b->ctx->device));
+    DS_HIP(hipStreamSynchronize(b->ctx->stream));  // no launch may still read the workspace
+    batch_drop_graph(b);
+    batch_free_order(b);
+    b->order = DS_ORDER_INPUT;
+    if (order == DS_ORDER_SPATIAL) {
+        const int64_t total = b->offsets[b->n];
+        const size_t sizes[4] = {(size_t)std::max<int64_t>(total, 1),
+                                 (size_t)std::max<int64_t>(total, 1),
+                                 (size_t)order_buckets(b->n), (size_t)order_sums(b->n)};
+        int32_t **bufs[4] = {&b->perm, &b->slot, &b->counts, &b->sums};
+        for (int i = 0; i < 4; ++i) {
+            hipError_t e = hipMalloc((void **)bufs[i], sizes[i] * sizeof(int32_t));
+            if (e != hipSuccess) {
+                *bufs[i] = nullptr;
+                batch_free_order(b);
+                return hip_fail(e, "ds_batch_set_order: workspace");
+            }
+        }
+        b->order = DS_ORDER_SPATIAL;
+    }
     return DS_OK;
 }
 

@@ -233,6 +233,31 @@ __device__ __forceinline__ bool point_frame(const FusedArgs &a, int64_t p, bool 
     return ok;
 }
 
+// Tile of the v-th step of the launch's walk (workgroup b takes steps b, b + grid, ...),
+// so that neighbouring tiles share an XCD.  Workgroups go to the eight XCDs in turn
+// (workgroup b to XCD b mod 8), each XCD with its own L2, and consecutive tiles hold
+// neighbouring points that read the same cells: blocks of kXcdBlock consecutive tiles are
+// dealt to the XCDs in turn, so an XCD walks whole blocks while every XCD still sees every
+// part of the launch (uneven clouds stay balanced).  A bijection of [0, n): steps past the
+// last whole round of 8 blocks keep their own tile.  With a grid that is a multiple of 8
+// every step of a workgroup stays on its XCD.
+constexpr int kXcdBlock = 32;
+
+__device__ __forceinline__ int64_t xcd_tile(int64_t v, int64_t n)
+{
+    constexpr int64_t R = 8 * kXcdBlock;
+    if (v >= n / R * R)
+        return v;
+    const int64_t q = v >> 3;
+    return ((q / kXcdBlock) * 8 + (v & 7)) * kXcdBlock + q % kXcdBlock;
+}
+
+// Row of the point arrays at launch position i (a lane past its cloud's points reads none)
+__device__ __forceinline__ int64_t point_row(const FusedArgs &a, int64_t i, bool in)
+{
+    return a.perm && in ? (int64_t)a.perm[i] : i;
+}
+
 // Cloud of tile t: the last cloud whose first tile is not after t (clouds without
 // points own no tiles).  Uniform across the workgroup.
 __device__ __forceinline__ int tile_cloud(const FusedArgs &a, int64_t t)
@@ -332,6 +357,53 @@ __device__ __forceinline__ void vm_wait()
     asm volatile("" ::: "memory");
 }
 
+// Copy of K consecutive 1 KB rows (K = 1..4) from global g into LDS at byte address l:
+// lane l of row r moves 16 bytes from g + r KB + 16 l to l + r KB + 16 l.  The immediate
+// offset of the instruction moves the global and the LDS address alike, so the rows of a
+// run share one m0 and one base pointer.
+template <int K>
+__device__ __forceinline__ void dma_rows(const uint4 *g, uint32_t l, uint32_t voff)
+{
+    static_assert(K >= 1 && K <= 4, "one to four rows per base");
+    if constexpr (K == 1)
+        asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, %2"
+                     :
+                     : "s"(l), "v"(voff), "s"(g)
+                     : "memory", "m0");
+    else if constexpr (K == 2)
+        asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, %2\n\t"
+                     "global_load_lds_dwordx4 %1, %2 offset:1024"
+                     :
+                     : "s"(l), "v"(voff), "s"(g)
+                     : "memory", "m0");
+    else if constexpr (K == 3)
+        asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, %2\n\t"
+                     "global_load_lds_dwordx4 %1, %2 offset:1024\n\t"
+                     "global_load_lds_dwordx4 %1, %2 offset:2048"
+                     :
+                     : "s"(l), "v"(voff), "s"(g)
+                     : "memory", "m0");
+    else
+        asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, %2\n\t"
+                     "global_load_lds_dwordx4 %1, %2 offset:1024\n\t"
+                     "global_load_lds_dwordx4 %1, %2 offset:2048\n\t"
+                     "global_load_lds_dwordx4 %1, %2 offset:3072"
+                     :
+                     : "s"(l), "v"(voff), "s"(g)
+                     : "memory", "m0");
+}
+
+// N consecutive rows in runs of up to four
+template <int N>
+__device__ __forceinline__ void dma_run(const uint4 *g, uint32_t l, uint32_t voff)
+{
+    if constexpr (N > 0) {
+        constexpr int K = N < 4 ? N : 4;
+        dma_rows<K>(g, l, voff);
+        dma_run<N - K>(g + K * 64, l + K * 1024u, voff);
+    }
+}
+
 template <int MT, int NW>
 struct WeightStage {
     // chunks per buffer: two workgroups of four waves share a compute unit's LDS;
@@ -353,23 +425,28 @@ struct WeightStage {
     // every wave wait for the whole copy.  Issued here, the copy is waited for only by the
     // explicit vm_wait before the group's closing barrier (and, as the counter is in
     // order, by waits for loads issued after it).  The instruction has no register
-    // result: its data goes to LDS at m0 + 16 lane.
+    // result: its data goes to LDS at m0 + offset + 16 lane.  Wave w copies a contiguous
+    // run of RB or RB + 1 rows, so a group costs a few scalar instructions per four rows
+    // instead of an address and an m0 per row.
+    static constexpr int RB = ROWS / NW, RX = ROWS % NW;
+    int r0;     // first row of this wave's run (uniform)
+    bool more;  // the run has RB + 1 rows
+    __device__ __forceinline__ void init(uint4 *lds, int tid)
+    {
+        buf = lds;
+        const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+        r0 = w * RB + (w < RX ? w : RX);
+        more = RX > 0 && w < RX;
+    }
     __device__ __forceinline__ void copy_group(int tid, uint4 *dst)
     {
-        const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const uint4 *g = src + r0 * 64;
+        const uint32_t l = (uint32_t)(uintptr_t)(lvoid *)(dst + r0 * 64);
         const uint32_t voff = (uint32_t)(tid & 63) * 16u;
-#pragma unroll
-        for (int r = 0; r < (ROWS + NW - 1) / NW; ++r) {
-            const int row = w + r * NW;
-            if ((r + 1) * NW <= ROWS || row < ROWS) {
-                const uint4 *g = src + row * 64;
-                const uint32_t l = (uint32_t)(uintptr_t)(lvoid *)(dst + row * 64);
-                asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, %2"
-                             :
-                             : "s"(l), "v"(voff), "s"(g)
-                             : "memory", "m0");
-            }
-        }
+        if (more)
+            dma_run<RB + 1>(g, l, voff);
+        else
+            dma_run<RB>(g, l, voff);
         src += BUF;
     }
     __device__ __forceinline__ void begin(const uint4 *frags, int tid)
@@ -563,10 +640,11 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
     init_tables(tid, plane, cols);
 
     WeightStage<MT, NW> ws;
-    ws.buf = wbuf;
+    ws.init(wbuf, tid);
     // persistent loop over tiles of 16 NW points; a tile never spans two clouds
 #pragma unroll 1
-    for (int64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
+    for (int64_t v = blockIdx.x; v < a.n_tiles; v += gridDim.x) {
+        const int64_t t = xcd_tile(v, a.n_tiles);
         // keeps tile-invariant LDS reads (the plane table) inside the loop: hoisted,
         // they would hold registers across the whole tile and force spills
         asm volatile("" ::: "memory");
@@ -575,7 +653,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
 
         const int64_t pl = (t - cl.tile_begin) * (16 * NW) + (tid >> 6) * 16 + n;
         const bool in = pl < cl.P;
-        const int64_t p = cl.p_begin + pl;
+        const int64_t p = point_row(a, cl.p_begin + pl, in);
         float gamma;
         bool valid;
         {
@@ -794,10 +872,11 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
     const int g = lane >> 4, n = lane & 15;
     init_tables(tid, plane, cols);
     WeightStage<MT, NW> ws;
-    ws.buf = wbuf;
+    ws.init(wbuf, tid);
     // persistent loop over tiles of 16 NW points; a tile never spans two clouds
 #pragma unroll 1
-    for (int64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
+    for (int64_t v = blockIdx.x; v < a.n_tiles; v += gridDim.x) {
+        const int64_t t = xcd_tile(v, a.n_tiles);
         // keeps tile-invariant LDS reads (the tables) inside the loop: hoisted, they
         // would hold registers across the whole tile and force spills
         asm volatile("" ::: "memory");
@@ -806,7 +885,7 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
             continue;  // uniform: the clamped pass computes this cloud
         const int64_t pl = (t - cl.tile_begin) * (16 * NW) + (tid >> 6) * 16 + n;
         const bool in = pl < cl.P;
-        const int64_t p = cl.p_begin + pl;
+        const int64_t p = point_row(a, cl.p_begin + pl, in);
         bool outside = false;  // a usable position outside the grid box
         if (in) {
             const float x0 = a.pos[3 * p], x1 = a.pos[3 * p + 1], x2 = a.pos[3 * p + 2];
@@ -1079,9 +1158,10 @@ __global__ void __launch_bounds__(64 * NW, 1) k_fused_wide(FusedArgs a,
     const int wv = tid >> 6;
     init_tables(tid, plane, cols);
     WeightStage<MT, NW> ws;
-    ws.buf = wbuf;
+    ws.init(wbuf, tid);
 #pragma unroll 1
-    for (int64_t t = blockIdx.x; t < a.n_tiles; t += gridDim.x) {
+    for (int64_t v = blockIdx.x; v < a.n_tiles; v += gridDim.x) {
+        const int64_t t = xcd_tile(v, a.n_tiles);
         asm volatile("" ::: "memory");
         const FusedCloud &cl = a.cl[tile_cloud(a, t)];
         ws.begin(frags, tid);
@@ -1092,7 +1172,7 @@ __global__ void __launch_bounds__(64 * NW, 1) k_fused_wide(FusedArgs a,
         for (int nt = 0; nt < NT; ++nt) {
             const int64_t pl = (t - cl.tile_begin) * TP + (wv * NT + nt) * 16 + n;
             in[nt] = pl < cl.P;
-            p[nt] = cl.p_begin + pl;
+            p[nt] = point_row(a, cl.p_begin + pl, in[nt]);
             float x[3];
             Frame fr;
             valid[nt] = point_frame(a, p[nt], in[nt], x, fr);

@@ -126,6 +126,10 @@ struct ds_batch {
     int64_t offsets[17] = {};
     int kind = 0, waves = 4, grid = 0;
     float tuned_ms = -1.f;
+    // DS_ORDER_SPATIAL: the launch reads points in a spatial order computed per call into
+    // perm, with the counting sort's workspace (slot per point, counts per cell, scan sums)
+    int order = 0;
+    int32_t *perm = nullptr, *slot = nullptr, *counts = nullptr, *sums = nullptr;
     hipStream_t cap_stream = nullptr;  // capture stream (created on first capture)
     hipGraphExec_t exec = nullptr;
 };
@@ -254,6 +258,9 @@ struct FusedArgs {
     const float *pos, *view, *light;
     float *out, *pre;
     uint8_t *flags;
+    // NULL, or the point row read (and written) at each position of the launch: a
+    // permutation that keeps every cloud's range (see batch_order)
+    const int32_t *perm;
     int K, W, H;
     int n_clouds;
     int64_t n_tiles;
@@ -280,6 +287,15 @@ ds_status fused_quantize_fp8(ds_net *net, const float *theta_host, const float *
 // Host encoder: x * 2^e to OCP E4M3 (round to nearest even, saturating at 448).
 uint8_t e4m3_encode(float x);
 ds_status fused_gather_packed(hipStream_t s, const FusedArgs &a, float *z);
+// order.hip: spatial order of a batch (cells of a 2^kOrderBits-per-axis grid over each
+// cloud's box, Morton order); perm and slot hold `total` entries, counts
+// order_buckets(n_clouds), sums order_sums(n_clouds)
+constexpr int kOrderBits = 5;
+constexpr int kOrderBuckets = 1 << (3 * kOrderBits);
+int64_t order_buckets(int n_clouds);
+int64_t order_sums(int n_clouds);
+ds_status batch_order(hipStream_t s, const FusedArgs &a, int64_t total, int32_t *perm,
+                      int32_t *slot, int32_t *counts, int32_t *sums);
 
 // tracer.hip
 // light_mode 0: one directional light; 1: uniform environment; 2: a light set, one

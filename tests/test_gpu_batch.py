@@ -155,6 +155,54 @@ def test_autotune_then_graph_replay(ctx, setup):
         ds.ds_batch_destroy(b)
 
 
+def test_spatial_order_is_bitwise_the_input_order(ctx, setup):
+    # the spatial order only changes which tile carries a point: outputs, pre-activations
+    # and flags stay bitwise those of the input order, for every kernel kind, eagerly and
+    # through a captured graph; points outside the box and a non-finite position included
+    s = setup
+    N = int(s["offsets"][-1])
+    pos = s["pos"].clone()
+    pos[5] = torch.tensor([9.0, -9.0, 0.0])          # outside its cloud's box
+    pos[s["counts"][0] + 7, 1] = float("nan")        # unusable position
+    b = _batch(ctx, s)
+    try:
+        def run(order, kind=ds.DS_KERNEL_REGISTER, waves=4, grid=0):
+            ds.ds_batch_set_order(b, order)
+            ds.ds_batch_set_config(b, kind, waves, grid)
+            out = torch.full((N,), -1.0, device="cuda")
+            pre = torch.full((N,), -1.0, device="cuda")
+            fl = torch.full((N,), 255, dtype=torch.uint8, device="cuda")
+            ds.ds_batch_predict(b, ds.DS_PREC_BF16, pos, s["view"], s["light"], out, pre, fl)
+            return out, pre, fl
+        ref = run(ds.DS_ORDER_INPUT)
+        assert int(ref[2][5]) & ds.DS_FLAG_OUTSIDE and int(ref[2][s["counts"][0] + 7]) & \
+            ds.DS_FLAG_INVALID
+        for kind, waves, grid in [(ds.DS_KERNEL_REGISTER, 4, 0), (ds.DS_KERNEL_REGISTER, 8, 3),
+                                  (ds.DS_KERNEL_PIPELINED, 4, 64), (ds.DS_KERNEL_WIDE, 4, 0)]:
+            got = run(ds.DS_ORDER_SPATIAL, kind, waves, grid)
+            for g, r in zip(got, ref):
+                assert torch.equal(g, r), (kind, waves, grid)
+        # captured with the order inside the graph
+        ds.ds_batch_set_config(b, ds.DS_KERNEL_REGISTER, 4, 0)
+        out = torch.full((N,), -1.0, device="cuda")
+        ds.ds_batch_capture(b, ds.DS_PREC_BF16, pos, s["view"], s["light"], out)
+        for r in range(3):
+            out.fill_(-1.0)
+            ds.ds_batch_replay(b)
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref[0]), r
+            _ = (pos * 2).nan_to_num().sum()  # unrelated eager work between replays
+        # back to the input order: the graph is dropped, results unchanged
+        ds.ds_batch_set_order(b, ds.DS_ORDER_INPUT)
+        with pytest.raises(ds.DSError):
+            ds.ds_batch_replay(b)
+        assert torch.equal(run(ds.DS_ORDER_INPUT)[0], ref[0])
+        with pytest.raises(ds.DSError):
+            ds.ds_batch_set_order(b, 2)
+    finally:
+        ds.ds_batch_destroy(b)
+
+
 def test_batch_argument_checks(ctx, setup):
     s = setup
     with pytest.raises(ds.DSError):
@@ -207,8 +255,10 @@ def paper_width_batch(ctx):
         c.close()
 
 
+@pytest.mark.parametrize("order", [ds.DS_ORDER_INPUT, ds.DS_ORDER_SPATIAL])
 @pytest.mark.parametrize("prec,tol", [(ds.DS_PREC_BF16, 2e-2), (ds.DS_PREC_FP8, 5e-2)])
-def test_paper_width_batch_autotuned_graph_matches_oracle(ctx, paper_width_batch, prec, tol):
+def test_paper_width_batch_autotuned_graph_matches_oracle(ctx, paper_width_batch, prec, tol,
+                                                          order):
     s = paper_width_batch
     N = int(s["offsets"][-1])
     if prec == ds.DS_PREC_FP8:  # calibrated on the largest cloud's points, as the bench does
@@ -218,6 +268,7 @@ def test_paper_width_batch_autotuned_graph_matches_oracle(ctx, paper_width_batch
                            s["light"][a:b].contiguous())
     bt = ds.ds_batch_create(ctx.h, s["net"].h, [c.h for c in s["clouds"]], s["offsets"])
     try:
+        ds.ds_batch_set_order(bt, order)
         out = torch.full((N,), -1.0, device="cuda")
         pre = torch.full((N,), -1.0, device="cuda")
         cfg = ds.ds_batch_autotune(bt, prec, s["pos"], s["view"], s["light"], out, 2)
@@ -237,7 +288,8 @@ def test_paper_width_batch_autotuned_graph_matches_oracle(ctx, paper_width_batch
             gotp.append(pre.cpu().numpy()[a + idx])
         e = rel_l2(np.concatenate(gotp), np.concatenate(wantp))
         eg = rel_l2(np.concatenate(got), np.concatenate(want))
-        print(f"paper-width batch, precision {prec}, {cfg}: relative L2 pre-activation {e:.2e}, "
+        print(f"paper-width batch, precision {prec}, order {order}, {cfg}: relative L2 "
+              f"pre-activation {e:.2e}, "
               f"g {eg:.2e}", flush=True)
         assert e <= tol and eg <= tol
     finally:
