@@ -369,8 +369,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="time the default kernel variant instead of the autotuned one")
     ap.add_argument("--variant", default=None,
-                    help="time this BF16 kernel variant, 'kind,waves,grid' (as ds_batch_set_config), "
-                         "instead of the autotuned one")
+                    help="time this kernel variant, 'kind,waves,grid' (as ds_batch_set_config), "
+                         "instead of the autotuned one (the FP8 form too, where it has one)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 256 MiB elementwise copy kernel (counter calibration)")
     args = ap.parse_args()
@@ -468,7 +468,8 @@ def main():
     mt = (W + 15) // 16
     mt = next(v for v in (1, 2, 4, 8, 13, 16) if v >= mt)
     kname = {ds.DS_KERNEL_REGISTER: "k_fused_reg", ds.DS_KERNEL_PIPELINED: "k_fused",
-             ds.DS_KERNEL_WIDE: "k_fused_wide"}[tuned["kernel"]] + f"<{mt},{tuned['waves']}>"
+             ds.DS_KERNEL_WIDE: "k_fused_wide",
+             ds.DS_KERNEL_TEAMS: "k_fused_teams"}[tuned["kernel"]] + f"<{mt},{tuned['waves']}>"
     traffic, traffic_grid = measured_traffic(kname) if args.workload == "paper" else (None, "")
     roofline = {"bound": "mfma", "achieved": round(achieved, 2), "peak": PEAK_BF16_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_BF16_TFLOPS, 4),
@@ -513,7 +514,10 @@ def main():
                            view[cal].contiguous(), light[cal].contiguous())
         batch8 = ds.ds_batch_create(ctx.h, net.h, [cloud.h], [0, P])
         tuned8 = {"kernel": ds.DS_KERNEL_REGISTER, "waves": 4, "grid": 0, "ms": None}
-        if not args.no_autotune:
+        if args.variant and tuned["kernel"] in (ds.DS_KERNEL_REGISTER, ds.DS_KERNEL_TEAMS):
+            ds.ds_batch_set_config(batch8, tuned["kernel"], tuned["waves"], tuned["grid"])
+            tuned8 = dict(tuned)
+        elif not args.no_autotune:
             tuned8 = ds.ds_batch_autotune(batch8, ds.DS_PREC_FP8, pos, view, light, out8, 3)
         ds.ds_batch_capture(batch8, ds.DS_PREC_FP8, pos, view, light, out8)
         ms8, kms8 = timed(lambda: ds.ds_batch_replay(batch8))

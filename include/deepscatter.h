@@ -233,6 +233,10 @@ ds_status ds_predict_f32_noalloc(ds_ctx *ctx, const ds_cloud *cloud, const ds_ne
 #define DS_KERNEL_REGISTER 0  /* residual stream in registers, one chunk of samples in flight */
 #define DS_KERNEL_PIPELINED 1 /* residual stream in LDS, the next chunk's samples in flight  */
 #define DS_KERNEL_WIDE 2      /* one wave per SIMD with two 16-point tiles (4 waves only)     */
+#define DS_KERNEL_TEAMS 3     /* 8 waves as two teams of 4 on 128-point tiles, one weight copy
+                               * for both, the second team a fixed number of weight chunks
+                               * behind the first (8 waves only, W <= 240, an even number
+                               * of weight chunks per tile)                                    */
 typedef struct ds_batch ds_batch;
 
 /* n_clouds (1..16) clouds; the points of cloud c are rows offsets[c] ..
@@ -245,7 +249,7 @@ ds_status ds_batch_create(ds_ctx *ctx, const ds_net *net, int n_clouds,
 ds_status ds_batch_destroy(ds_batch *batch);
 /* Kernel variant of the plan: kernel DS_KERNEL_*, waves 4 or 8 (8 needs W <= 240 for
  * DS_KERNEL_REGISTER, W <= 192 for DS_KERNEL_PIPELINED and is not available for
- * DS_KERNEL_WIDE),
+ * DS_KERNEL_WIDE; DS_KERNEL_TEAMS takes 8 only),
  * grid 0 (one workgroup per tile) or the number of persistent workgroups.
  * Setting a variant drops a captured graph. */
 ds_status ds_batch_set_config(ds_batch *batch, int32_t kernel, int32_t waves, int32_t grid);
@@ -254,13 +258,15 @@ ds_status ds_batch_get_config(const ds_batch *batch, int32_t *kernel, int32_t *w
                               int32_t *grid, float *ms);
 /* Prediction for all clouds of the plan: as ds_predict per cloud, on the
  * concatenated arrays (device, offsets[n] points).  DS_PREC_BF16 (and DS_PREC_FP8
- * once quantised, register kernel only: DS_ERR_UNSUPPORTED for the other kinds) runs
+ * once quantised, register and two-team kernels only: DS_ERR_UNSUPPORTED for the
+ * others) runs
  * one launch; DS_PREC_F32 runs the plain form per cloud. */
 ds_status ds_batch_predict(ds_batch *batch, ds_precision precision, const float *pos,
                            const float *view_dir, const float *light_dir, float *out,
                            float *pre_out, uint8_t *flags);
 /* Times every available variant (kernel x waves x grid in {one per tile, 1, 2, 4
- * workgroups per compute unit}; for DS_PREC_FP8 the register kernel's) on these arrays, `reps` launches each after one
+ * workgroups per compute unit}; for DS_PREC_FP8 the register and two-team kernels') on
+ * these arrays, `reps` launches each after one
  * warm-up, keeps the fastest and drops a captured graph.  Synchronises; writes
  * out.  Results depend on the arrays' contents only through timing. */
 ds_status ds_batch_autotune(ds_batch *batch, ds_precision precision, const float *pos,

@@ -26,7 +26,7 @@ DS_F32, DS_BF16 = 0, 1
 DS_PREC_F32, DS_PREC_BF16, DS_PREC_FP8 = 0, 1, 2
 DS_FLAG_INVALID, DS_FLAG_OUTSIDE, DS_FLAG_FALLBACK = 1, 2, 4
 DS_LIGHT_DIRECTIONAL, DS_LIGHT_ENVIRONMENT = 0, 1
-DS_KERNEL_REGISTER, DS_KERNEL_PIPELINED, DS_KERNEL_WIDE = 0, 1, 2
+DS_KERNEL_REGISTER, DS_KERNEL_PIPELINED, DS_KERNEL_WIDE, DS_KERNEL_TEAMS = 0, 1, 2, 3
 DS_ORDER_INPUT, DS_ORDER_SPATIAL = 0, 1
 STENCIL_N = 225
 

@@ -1615,7 +1615,7 @@ ds_status ds_batch_autotune(ds_batch *b, ds_precision precision, const float *po
     float best = -1.f;
     FusedVariant bestv = {b->kind, b->waves, b->grid};
     const int grids[4] = {0, cus, 2 * cus, 4 * cus};
-    for (int kind = 0; kind < 3 && !st; ++kind)
+    for (int kind = 0; kind < 4 && !st; ++kind)
         for (int waves = 4; waves <= 8 && !st; waves += 4)
             for (int gi = 0; gi < 4 && !st; ++gi) {
                 FusedVariant v = {kind, waves, grids[gi]};

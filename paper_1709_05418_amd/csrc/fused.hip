@@ -490,6 +490,112 @@ struct WeightStage {
     }
 };
 
+// Weight chunks for two teams of four waves that walk one chunk stream (every tile's
+// chunks in order, tile after tile) D chunks apart: team 0 (waves 0..3) leads, team 1
+// (waves 4..7) follows.  The chunks live in a ring of R slots in LDS; in every period of
+// G chunks the eight waves together copy the group that team 0 needs in the next period,
+// and all of them meet at a barrier every G chunks.  One copy thus serves 128 points, twice a
+// WeightStage's 64, which halves the weight bytes that pass through each compute unit's
+// vector memory path, and the two waves on a SIMD run different phases of the network
+// (the stencil chunks, heavy in vector ALU work, against the dense layers, heavy in
+// matrix work) instead of the same phase in step.  At the barrier that opens period n,
+// team 0 has consumed the chunks before nG and team 1 those before nG - D; during the
+// period the waves copy chunks [nG + G, nG + 2G) into the slots of chunks
+// [nG + G - R, nG + 2G - R), all consumed by team 1 when R >= D + 2G.  The stream
+// wraps at the tile's chunk count nc (even, so a group never straddles two tiles), and
+// a team with no point in a tile still walks its nc chunks (idle steps) so that the
+// barriers of both teams stay paired.
+template <int MT, int R, int D>
+struct TeamRing {
+    static constexpr int G = 2;
+    static constexpr int SLOT = MT * 64;  // LDS entries per chunk
+    static constexpr int ROWS = G * MT;   // 1 KB rows per group
+    static constexpr int RB = ROWS / 8, RX = ROWS % 8;  // rows per wave, all eight copy
+    static_assert(R >= D + 2 * G && R % G == 0 && D % G == 0, "ring too small for the lag");
+    uint4 *ring;
+    const uint4 *frags, *src, *src_end;  // the network's chunks, the next group, the end
+    int slot;   // slot of this team's current chunk
+    int cslot;  // slot of the next group to copy
+    int k;      // steps since the last barrier (both teams alike)
+    int team, r0;
+    bool more, pending;
+
+    __device__ __forceinline__ void init(uint4 *lds, const uint4 *f, int nc, int tid)
+    {
+        ring = lds;
+        frags = src = f;
+        src_end = f + (size_t)nc * SLOT;
+        const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+        team = w >> 2;
+        r0 = w * RB + (w < RX ? w : RX);
+        more = RX > 0 && w < RX;
+        slot = team == 0 ? 0 : R - D;  // team 1 starts D idle steps behind chunk 0
+        cslot = 0;
+        k = 0;
+        pending = false;
+    }
+    __device__ __forceinline__ void copy_group(int tid)
+    {
+        uint4 *dst = ring + cslot * SLOT;
+        const uint4 *g = src + r0 * 64;
+        const uint32_t l = (uint32_t)(uintptr_t)(lvoid *)(dst + r0 * 64);
+        const uint32_t voff = (uint32_t)(tid & 63) * 16u;
+        if (more)
+            dma_run<RB + 1>(g, l, voff);
+        else
+            dma_run<RB>(g, l, voff);
+        src += G * SLOT;
+        if (src == src_end)
+            src = frags;
+        cslot += G;
+        if (cslot == R)
+            cslot = 0;
+    }
+    // the first group; every wave waits for it (and for the tables)
+    __device__ __forceinline__ void prologue(int tid)
+    {
+        copy_group(tid);
+        vm_wait<0>();
+        __syncthreads();
+        pending = true;
+    }
+    __device__ __forceinline__ const uint4 *chunk() const { return ring + slot * SLOT; }
+    __device__ __forceinline__ void begin(const uint4 *, int) {}  // the stream runs on
+    __device__ __forceinline__ void fetch(int tid)
+    {
+        if (pending) {
+            copy_group(tid);
+            pending = false;
+        }
+    }
+    template <int N = 0>
+    __device__ __forceinline__ void next(int tid)
+    {
+        if (++slot == R)
+            slot = 0;
+        if (++k == G) {
+            if (pending) {  // a group whose chunks never fetched: copy now, wait for all
+                fetch(tid);
+                vm_wait<0>();
+            } else {
+                vm_wait<N>();
+            }
+            __syncthreads();
+            k = 0;
+            pending = true;
+        }
+    }
+    // n steps without consuming a chunk (copies and barriers as usual)
+    __device__ __forceinline__ void idle(int tid, int n)
+    {
+#pragma unroll 1
+        for (int i = 0; i < n; ++i) {
+            fetch(tid);
+            next<0>(tid);
+        }
+    }
+};
+
 template <int MT>
 __device__ __forceinline__ void mfma_chunk(const uint4 *w, int lane, const bf16x8 &B, f4 (&acc)[MT])
 {
@@ -564,8 +670,8 @@ __device__ __forceinline__ void mfma8_chunk(const uint4 *w, int lane, const fp8x
 }
 
 // Consume one FP8 chunk (two staging slots) of a W-wide layer.
-template <int MT, int NW, bool CLAMP>
-__device__ __forceinline__ void fp8_layer(WeightStage<MT, NW> &ws, int tid, int lane,
+template <int MT, int NW, bool CLAMP, class Stage>
+__device__ __forceinline__ void fp8_layer(Stage &ws, int tid, int lane,
                                           const f4 (&in)[MT], f4 (&acc)[MT])
 {
 #pragma unroll
@@ -578,8 +684,8 @@ __device__ __forceinline__ void fp8_layer(WeightStage<MT, NW> &ws, int tid, int 
 }
 
 // out = relu(Wmat in + bias) for a W-wide input held in accumulator layout.
-template <int MT, int NW>
-__device__ __forceinline__ void dense(WeightStage<MT, NW> &ws, const float *__restrict__ bias,
+template <int MT, int NW, class Stage>
+__device__ __forceinline__ void dense(Stage &ws, const float *__restrict__ bias,
                                       int tid, int lane, const f4 (&in)[MT], f4 (&out)[MT])
 {
     constexpr int C2 = (MT + 1) / 2;
@@ -604,8 +710,8 @@ __device__ __forceinline__ void dense(WeightStage<MT, NW> &ws, const float *__re
 
 // FP8 form of dense(): the output stays in its scaled units (biases pre-scaled), and the
 // ReLU clamps at 448 so that the next FP8 layer can take it unclamped.
-template <int MT, int NW>
-__device__ __forceinline__ void dense8(WeightStage<MT, NW> &ws, const float *__restrict__ bias,
+template <int MT, int NW, class Stage>
+__device__ __forceinline__ void dense8(Stage &ws, const float *__restrict__ bias,
                                        int tid, int lane, const f4 (&in)[MT], f4 (&out)[MT])
 {
     const int g = lane >> 4;
@@ -856,13 +962,215 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused(FusedArgs a, const uint4 *
 // of the other clouds and recomputes every tile that holds a point outside its grid box; it
 // skips all other tiles after reading their positions.  Launched one after the other, the
 // two passes give every point the clamped kernel's result.
+// One tile's prediction for the calling wave's 16 points p (in: the lane has a point;
+// outside: its usable position lies outside the grid box, which the unclamped pass CL =
+// false treats as invalid).  Shared by the kernels that stage the weight chunks through a
+// WeightStage (one workgroup's waves in step) and a TeamRing (two teams of four waves a
+// fixed number of chunks apart); gslot is the wave's LDS slot of this point's geometry.
+template <int MT, int NW, bool F8, bool CL, class Stage>
+__device__ __forceinline__ void predict_points(const FusedArgs &a, const FusedCloud &cl,
+                                               const float *__restrict__ vec, Stage &ws,
+                                               int tid, PtGeom &gslot, const float4 *plane,
+                                               const float2 *cols, int64_t p, bool in,
+                                               bool outside)
+{
+    constexpr int C2 = (MT + 1) / 2;
+    constexpr int WP = 16 * MT;
+    const int lane = tid & 63;
+    const int g = lane >> 4;
+    float gamma;
+    bool valid;
+    {
+        float x[3];
+        Frame fr;
+        valid = point_frame(a, p, in, x, fr);
+        if (!CL && outside)
+            valid = false;  // no frame: its samples read the zero cell
+        gamma = valid ? fr.gamma : 0.f;
+        // the four lanes of a point write the same slot; each reads its own write
+        gslot = make_geom(x, fr, cl.amin, valid);
+    }
+    const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
+    f4 O[MT], F[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+        O[mt] = z4;
+
+    // Samples are software-pipelined within a level: each stencil chunk finishes
+    // the samples the previous chunk issued and issues the next chunk's.  (Issuing
+    // the next level's first samples before the second layer would keep them live
+    // next to both accumulator sets, which costs more registers than there are.)
+    for (int k = 0; k < a.K; ++k) {
+        const FusedLevel L = cl.lvt[k];
+        gcell_ptr cells = (gcell_ptr)L.cells;
+        PtLevel q;
+        level_from_geom(L, gslot, q);
+        const float *b1 = vec + (size_t)k * 2 * WP;
+        const float *b2 = b1 + WP;
+        // the first layer accumulates onto its bias
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+            F[mt] = *reinterpret_cast<const f4 *>(b1 + 16 * mt + 4 * g);
+        Pending pa, pb;
+        issue_column<CL>(cells, L, q, 0, g, cols, pa, pb);
+#pragma unroll 1
+        for (int c = 0; c < 5; ++c) {  // chunks 0..4: halves 2c, 2c+1 in, 2c+2, 2c+3 out
+            f4 lo, hi;
+            // both halves of the next column share its base
+            const float3 cb = column_base(q, c + 1, g, cols);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                lo[j] = finish_one(pa.v[j], pa.fx[j], pa.t[j]);
+            issue_four<CL>(cells, L, q, cb.x, cb.y, cb.z, pa);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                hi[j] = finish_one(pb.v[j], pb.fx[j], pb.t[j]);
+            // the weight copy goes out after the waits for this chunk's samples (the
+            // empty statement keeps the finished samples from sinking below it)
+            asm volatile("" ::"v"(lo), "v"(hi));
+            ws.fetch(tid);
+            issue_four<CL>(cells, L, q, fmaf(4.f, q.c[0], cb.x), fmaf(4.f, q.c[1], cb.y),
+                       fmaf(4.f, q.c[2], cb.z), pb);
+            mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
+            ws.template next<8>(tid);
+        }
+        {  // chunk 5: issues the table halves of chunk 6
+            f4 lo, hi;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                lo[j] = finish_one(pa.v[j], pa.fx[j], pa.t[j]);
+            issue_table_half<CL>(cells, L, q, 0, g, plane, pa);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                hi[j] = finish_one(pb.v[j], pb.fx[j], pb.t[j]);
+            asm volatile("" ::"v"(lo), "v"(hi));
+            ws.fetch(tid);
+            issue_table_half<CL>(cells, L, q, 1, g, plane, pb);
+            mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
+            ws.template next<8>(tid);
+        }
+        {  // chunk 6: issues chunk 7's stencil sample (4, 4, 8)
+            f4 lo, hi;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                lo[j] = finish_one(pa.v[j], pa.fx[j], pa.t[j]);
+            issue_one<CL>(cells, L, q.u0[0] + 4.f * (q.a[0] + q.b[0]) + 8.f * q.c[0],
+                      q.u0[1] + 4.f * (q.a[1] + q.b[1]) + 8.f * q.c[1],
+                      q.u0[2] + 4.f * (q.a[2] + q.b[2]) + 8.f * q.c[2], pa.v[0], pa.fx[0],
+                      pa.t[0]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                hi[j] = finish_one(pb.v[j], pb.fx[j], pb.t[j]);
+            asm volatile("" ::"v"(lo), "v"(hi));
+            ws.fetch(tid);
+            mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
+            ws.template next<1>(tid);
+        }
+        {  // chunk 7: stencil sample (4, 4, 8), gamma, and the odd tile of o^{k-1}
+            const float sv = finish_one(pa.v[0], pa.fx[0], pa.t[0]);
+            asm volatile("" ::"v"(sv));
+            ws.fetch(tid);
+            const f4 lo = f4{g == 0 ? sv : 0.f, g == 0 ? gamma : 0.f, 0.f, 0.f};
+            mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, (!F8 && (MT & 1)) ? O[MT - 1] : z4),
+                           F);
+            ws.template next<0>(tid);
+        }
+        if (k > 0) {
+            if constexpr (F8) {
+                fp8_layer<MT, NW, true>(ws, tid, lane, O, F);
+            } else {
+#pragma unroll
+                for (int qq = 0; qq < MT / 2; ++qq) {
+                    ws.fetch(tid);
+                    mfma_chunk<MT>(ws.chunk(), lane, pack8(O[2 * qq], O[2 * qq + 1]), F);
+                    ws.template next<0>(tid);
+                }
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            if constexpr (F8) {  // the BF16 form applies this ReLU when packing
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    F[mt][i] = __builtin_amdgcn_fmed3f(F[mt][i], 0.f, 448.f);
+            }
+            O[mt] += *reinterpret_cast<const f4 *>(b2 + 16 * mt + 4 * g);
+        }
+        if constexpr (F8) {
+            fp8_layer<MT, NW, false>(ws, tid, lane, F, O);
+        } else {
+#pragma unroll
+            for (int qq = 0; qq < C2; ++qq) {
+                ws.fetch(tid);
+                mfma_chunk<MT>(ws.chunk(), lane,
+                               pack8_relu(F[2 * qq],
+                                          (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0]
+                                                            : z4),
+                               O);
+                ws.template next<0>(tid);
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                O[mt][i] = fmaxf(O[mt][i], 0.f);
+    }
+    const float *bh = vec + (size_t)a.K * 2 * WP;
+    int h = 0;
+    if constexpr (F8) {
+        for (; h + 1 < a.H - 1; h += 2) {
+            dense8<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+            dense8<MT, NW>(ws, bh + (size_t)(h + 1) * WP, tid, lane, F, O);
+        }
+        if (h < a.H - 1) {
+            dense8<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                O[mt] = F[mt];
+        }
+    } else {
+        for (; h + 1 < a.H - 1; h += 2) {
+            dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+            dense<MT, NW>(ws, bh + (size_t)(h + 1) * WP, tid, lane, F, O);
+        }
+        if (h < a.H - 1) {
+            dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                O[mt] = F[mt];
+        }
+    }
+    const float *wl = bh + (size_t)(a.H - 1) * WP;
+    const float bl = wl[WP];
+    float acc = 0.f;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const f4 w = *reinterpret_cast<const f4 *>(wl + 16 * mt + 4 * g);
+        acc += w[0] * O[mt][0] + w[1] * O[mt][1] + w[2] * O[mt][2] + w[3] * O[mt][3];
+    }
+    acc += __shfl_xor(acc, 16, 64);
+    acc += __shfl_xor(acc, 32, 64);
+    if (g == 0 && in) {
+        const float pre = acc + bl;
+        a.out[p] = valid ? fmaxf(pre, 0.f) : 0.f;
+        if (a.pre)
+            a.pre[p] = valid ? pre : 0.f;
+        if (a.flags) {
+            float x[3];
+            Frame fr;
+            point_frame(a, p, in, x, fr);
+            a.flags[p] = valid ? point_flags(x, fr, cl.amin, cl.amax, cl.inv_mean)
+                               : (uint8_t)DS_FLAG_INVALID;
+        }
+    }
+}
+
 template <int MT, int NW, bool F8, bool CL>
 __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
                                                           const uint4 *__restrict__ frags,
                                                           const float *__restrict__ vec)
 {
-    constexpr int C2 = (MT + 1) / 2;
-    constexpr int WP = 16 * MT;
     __shared__ uint4 wbuf[2 * WeightStage<MT, NW>::BUF];
     __shared__ float4 plane[32];
     __shared__ float2 cols[24];
@@ -896,194 +1204,59 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
         if (CL && cl.fast && !__syncthreads_or(outside))
             continue;  // uniform: the unclamped pass computed this tile
         ws.begin(frags, tid);
-
-        float gamma;
-        bool valid;
-        {
-            float x[3];
-            Frame fr;
-            valid = point_frame(a, p, in, x, fr);
-            if (!CL && outside)
-                valid = false;  // no frame: its samples read the zero cell
-            gamma = valid ? fr.gamma : 0.f;
-            // the four lanes of a point write the same slot; each reads its own write
-            geom[(tid >> 6) * 16 + n] = make_geom(x, fr, cl.amin, valid);
-        }
-        const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
-        f4 O[MT], F[MT];
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt)
-            O[mt] = z4;
-
-        // Samples are software-pipelined within a level: each stencil chunk finishes
-        // the samples the previous chunk issued and issues the next chunk's.  (Issuing
-        // the next level's first samples before the second layer would keep them live
-        // next to both accumulator sets, which costs more registers than there are.)
-        for (int k = 0; k < a.K; ++k) {
-            const FusedLevel L = cl.lvt[k];
-            gcell_ptr cells = (gcell_ptr)L.cells;
-            PtLevel q;
-            level_from_geom(L, geom[(tid >> 6) * 16 + n], q);
-            const float *b1 = vec + (size_t)k * 2 * WP;
-            const float *b2 = b1 + WP;
-            // the first layer accumulates onto its bias
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-                F[mt] = *reinterpret_cast<const f4 *>(b1 + 16 * mt + 4 * g);
-            Pending pa, pb;
-            issue_column<CL>(cells, L, q, 0, g, cols, pa, pb);
-#pragma unroll 1
-            for (int c = 0; c < 5; ++c) {  // chunks 0..4: halves 2c, 2c+1 in, 2c+2, 2c+3 out
-                f4 lo, hi;
-                // both halves of the next column share its base
-                const float3 cb = column_base(q, c + 1, g, cols);
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    lo[j] = finish_one(pa.v[j], pa.fx[j], pa.t[j]);
-                issue_four<CL>(cells, L, q, cb.x, cb.y, cb.z, pa);
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    hi[j] = finish_one(pb.v[j], pb.fx[j], pb.t[j]);
-                // the weight copy goes out after the waits for this chunk's samples (the
-                // empty statement keeps the finished samples from sinking below it)
-                asm volatile("" ::"v"(lo), "v"(hi));
-                ws.fetch(tid);
-                issue_four<CL>(cells, L, q, fmaf(4.f, q.c[0], cb.x), fmaf(4.f, q.c[1], cb.y),
-                           fmaf(4.f, q.c[2], cb.z), pb);
-                mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
-                ws.template next<8>(tid);
-            }
-            {  // chunk 5: issues the table halves of chunk 6
-                f4 lo, hi;
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    lo[j] = finish_one(pa.v[j], pa.fx[j], pa.t[j]);
-                issue_table_half<CL>(cells, L, q, 0, g, plane, pa);
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    hi[j] = finish_one(pb.v[j], pb.fx[j], pb.t[j]);
-                asm volatile("" ::"v"(lo), "v"(hi));
-                ws.fetch(tid);
-                issue_table_half<CL>(cells, L, q, 1, g, plane, pb);
-                mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
-                ws.template next<8>(tid);
-            }
-            {  // chunk 6: issues chunk 7's stencil sample (4, 4, 8)
-                f4 lo, hi;
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    lo[j] = finish_one(pa.v[j], pa.fx[j], pa.t[j]);
-                issue_one<CL>(cells, L, q.u0[0] + 4.f * (q.a[0] + q.b[0]) + 8.f * q.c[0],
-                          q.u0[1] + 4.f * (q.a[1] + q.b[1]) + 8.f * q.c[1],
-                          q.u0[2] + 4.f * (q.a[2] + q.b[2]) + 8.f * q.c[2], pa.v[0], pa.fx[0],
-                          pa.t[0]);
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    hi[j] = finish_one(pb.v[j], pb.fx[j], pb.t[j]);
-                asm volatile("" ::"v"(lo), "v"(hi));
-                ws.fetch(tid);
-                mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, hi), F);
-                ws.template next<1>(tid);
-            }
-            {  // chunk 7: stencil sample (4, 4, 8), gamma, and the odd tile of o^{k-1}
-                const float sv = finish_one(pa.v[0], pa.fx[0], pa.t[0]);
-                asm volatile("" ::"v"(sv));
-                ws.fetch(tid);
-                const f4 lo = f4{g == 0 ? sv : 0.f, g == 0 ? gamma : 0.f, 0.f, 0.f};
-                mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, (!F8 && (MT & 1)) ? O[MT - 1] : z4),
-                               F);
-                ws.template next<0>(tid);
-            }
-            if (k > 0) {
-                if constexpr (F8) {
-                    fp8_layer<MT, NW, true>(ws, tid, lane, O, F);
-                } else {
-#pragma unroll
-                    for (int qq = 0; qq < MT / 2; ++qq) {
-                        ws.fetch(tid);
-                        mfma_chunk<MT>(ws.chunk(), lane, pack8(O[2 * qq], O[2 * qq + 1]), F);
-                        ws.template next<0>(tid);
-                    }
-                }
-            }
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-                if constexpr (F8) {  // the BF16 form applies this ReLU when packing
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-                        F[mt][i] = __builtin_amdgcn_fmed3f(F[mt][i], 0.f, 448.f);
-                }
-                O[mt] += *reinterpret_cast<const f4 *>(b2 + 16 * mt + 4 * g);
-            }
-            if constexpr (F8) {
-                fp8_layer<MT, NW, false>(ws, tid, lane, F, O);
-            } else {
-#pragma unroll
-                for (int qq = 0; qq < C2; ++qq) {
-                    ws.fetch(tid);
-                    mfma_chunk<MT>(ws.chunk(), lane,
-                                   pack8_relu(F[2 * qq],
-                                              (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0]
-                                                                : z4),
-                                   O);
-                    ws.template next<0>(tid);
-                }
-            }
-#pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    O[mt][i] = fmaxf(O[mt][i], 0.f);
-        }
-        const float *bh = vec + (size_t)a.K * 2 * WP;
-        int h = 0;
-        if constexpr (F8) {
-            for (; h + 1 < a.H - 1; h += 2) {
-                dense8<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
-                dense8<MT, NW>(ws, bh + (size_t)(h + 1) * WP, tid, lane, F, O);
-            }
-            if (h < a.H - 1) {
-                dense8<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-                    O[mt] = F[mt];
-            }
-        } else {
-            for (; h + 1 < a.H - 1; h += 2) {
-                dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
-                dense<MT, NW>(ws, bh + (size_t)(h + 1) * WP, tid, lane, F, O);
-            }
-            if (h < a.H - 1) {
-                dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-                    O[mt] = F[mt];
-            }
-        }
-        const float *wl = bh + (size_t)(a.H - 1) * WP;
-        const float bl = wl[WP];
-        float acc = 0.f;
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            const f4 w = *reinterpret_cast<const f4 *>(wl + 16 * mt + 4 * g);
-            acc += w[0] * O[mt][0] + w[1] * O[mt][1] + w[2] * O[mt][2] + w[3] * O[mt][3];
-        }
-        acc += __shfl_xor(acc, 16, 64);
-        acc += __shfl_xor(acc, 32, 64);
-        if (g == 0 && in) {
-            const float pre = acc + bl;
-            a.out[p] = valid ? fmaxf(pre, 0.f) : 0.f;
-            if (a.pre)
-                a.pre[p] = valid ? pre : 0.f;
-            if (a.flags) {
-                float x[3];
-                Frame fr;
-                point_frame(a, p, in, x, fr);
-                a.flags[p] = valid ? point_flags(x, fr, cl.amin, cl.amax, cl.inv_mean)
-                                   : (uint8_t)DS_FLAG_INVALID;
-            }
-        }
+        predict_points<MT, NW, F8, CL>(a, cl, vec, ws, tid, geom[(tid >> 6) * 16 + n], plane,
+                                       cols, p, in, outside);
     }
+}
+
+// Unclamped pass of the register kernel with two teams of four waves sharing one weight
+// ring (TeamRing): tiles of 128 points, team 0 taking points 0..63 and team 1 points
+// 64..127 of each, team 1 kTeamLag chunks behind.  Clouds that need the clamps and tiles
+// with a point outside the grid box are left to the clamped pass of the four-wave kernel,
+// whose 64-point tiles are these tiles' halves.
+constexpr int kTeamRing = 10, kTeamLag = 6;
+
+template <int MT, bool F8>
+__global__ void __launch_bounds__(512, 2) k_fused_teams(FusedArgs a,
+                                                        const uint4 *__restrict__ frags,
+                                                        const float *__restrict__ vec, int nc)
+{
+    __shared__ uint4 ring[kTeamRing * MT * 64];
+    __shared__ float4 plane[32];
+    __shared__ float2 cols[24];
+    __shared__ PtGeom geom[128];
+    const int tid = threadIdx.x;
+    const int n = tid & 15;
+    init_tables(tid, plane, cols);
+    TeamRing<MT, kTeamRing, kTeamLag> ws;
+    ws.init(ring, frags, nc, tid);
+    ws.prologue(tid);  // also publishes the tables
+    if (ws.team == 1)
+        ws.idle(tid, kTeamLag);
+#pragma unroll 1
+    for (int64_t v = blockIdx.x; v < a.n_tiles; v += gridDim.x) {
+        const int64_t t = xcd_tile(v, a.n_tiles);
+        asm volatile("" ::: "memory");
+        const FusedCloud &cl = a.cl[tile_cloud(a, t)];
+        if (!cl.fast) {  // uniform: the clamped pass computes this cloud
+            ws.idle(tid, nc);
+            continue;
+        }
+        const int64_t pl = (t - cl.tile_begin) * 128 + (tid >> 6) * 16 + n;
+        const bool in = pl < cl.P;
+        const int64_t p = point_row(a, cl.p_begin + pl, in);
+        bool outside = false;
+        if (in) {
+            const float x0 = a.pos[3 * p], x1 = a.pos[3 * p + 1], x2 = a.pos[3 * p + 2];
+            outside = isfinite(x0) && isfinite(x1) && isfinite(x2) &&
+                      !(x0 >= cl.amin[0] && x0 <= cl.amax[0] && x1 >= cl.amin[1] &&
+                        x1 <= cl.amax[1] && x2 >= cl.amin[2] && x2 <= cl.amax[2]);
+        }
+        predict_points<MT, 8, F8, false>(a, cl, vec, ws, tid, geom[(tid >> 6) * 16 + n], plane,
+                                         cols, p, in, outside);
+    }
+    if (ws.team == 0)
+        ws.idle(tid, kTeamLag);
 }
 
 // Wide variant: one wave per SIMD holding two 16-point tiles, so every weight
@@ -1415,6 +1588,14 @@ int chunk_count(int MT, int K, int H)
     return (8 + C2) + (K - 1) * (C1 + C2) + (H - 1) * C2;
 }
 
+// staging slots per tile of the FP8 form: 8 stencil slots per block, two slots per FP8
+// chunk of 128 inputs for W1 (blocks 2..K), W2 and the dense trailing layers
+int fp8_slot_count(int MT, int K, int H)
+{
+    const int C8 = (MT + 7) / 8;
+    return (8 + 2 * C8) + (K - 1) * (8 + 4 * C8) + (H - 1) * 2 * C8;
+}
+
 // zeroed entries after the last chunk: the copies run up to two groups (2 x 4 chunks of
 // at most 16 x 64 entries) past the chunk being consumed
 constexpr size_t kFragPad = 8192;
@@ -1455,6 +1636,28 @@ ds_status launch_kind(hipStream_t s, const ds_net *net, FusedArgs a, int grid)
     return DS_OK;
 }
 
+// The two-team kernel's unclamped pass on 128-point tiles, then the clamped pass of the
+// four-wave register kernel on 64-point tiles (the halves of those tiles).
+template <int MT, bool F8>
+ds_status launch_teams(hipStream_t s, const ds_net *net, FusedArgs a, int grid)
+{
+    const int nc = F8 ? fp8_slot_count(MT, a.K, a.H) : chunk_count(MT, a.K, a.H);
+    const uint4 *frags = F8 ? net->frag_fp8 : net->frag_bf16;
+    const float *vec = F8 ? net->vec8 : net->vec;
+    FusedArgs a4 = a;
+    const int64_t tiles = assign_tiles(a, 128), tiles4 = assign_tiles(a4, 64);
+    if (tiles <= 0)
+        return DS_OK;
+    const int64_t g = grid > 0 && grid < tiles ? grid : tiles;
+    const int64_t g4 = grid > 0 && grid < tiles4 ? grid : tiles4;
+    DS_CHECK(g4 < ((int64_t)1 << 31) && nc % 2 == 0, DS_ERR_INVALID_ARG,
+             "two-team launch: %lld tiles, %d chunks per tile", (long long)tiles4, nc);
+    k_fused_teams<MT, F8><<<(unsigned)g, 512, 0, s>>>(a, frags, vec, nc);
+    k_fused_reg<MT, 4, F8, true><<<(unsigned)g4, 256, 0, s>>>(a4, frags, vec);
+    DS_HIP(hipGetLastError());
+    return DS_OK;
+}
+
 // Eight waves need LDS for twice the points: the register kernel fits below 16
 // tiles, the pipelined one (residual stream in LDS) below 13; the wide kernel runs
 // one wave per SIMD, so four waves only.
@@ -1469,6 +1672,13 @@ template <int MT>
 ds_status launch(hipStream_t s, const ds_net *net, const FusedArgs &a, const FusedVariant &v,
                  bool fp8)
 {
+    if (v.kind == DS_KERNEL_TEAMS) {
+        if constexpr (MT < 16)
+            return fp8 ? launch_teams<MT, true>(s, net, a, v.grid)
+                       : launch_teams<MT, false>(s, net, a, v.grid);
+        set_error("the two-team kernel does not fit width %d", net->W);
+        return DS_ERR_UNSUPPORTED;
+    }
     if (fp8) {
         if constexpr (fits(MT, 8, DS_KERNEL_REGISTER)) {
             if (v.waves == 8)
@@ -1846,7 +2056,7 @@ ds_status fused_quantize_fp8(ds_net *net, const float *th, const float *act_amax
         return DS_ERR_STATE;
     }
 
-    const int64_t slots = (8 + 2 * C8) + (int64_t)(K - 1) * (8 + 4 * C8) + (int64_t)(H - 1) * 2 * C8;
+    const int64_t slots = fp8_slot_count(MT, K, H);
     std::vector<uint4> fr((size_t)(slots * MT * 64 + kFragPad), uint4{0, 0, 0, 0});
     auto entry = [&](int64_t slot, int mt, int lane) -> uint8_t * {
         return reinterpret_cast<uint8_t *>(&fr[(size_t)((slot * MT + mt) * 64 + lane)]);
@@ -1953,8 +2163,21 @@ ds_status fused_gather_packed(hipStream_t s, const FusedArgs &a, float *z)
     return DS_OK;
 }
 
+// two-team kernel: eight waves, a ring of ten chunks below 16 tiles, a chunk stream of
+// even length per tile
+static bool teams_ok(const ds_net *net, const FusedVariant &v, bool fp8)
+{
+    const int MT = fused_tiles(net->W);
+    if (v.waves != 8 || v.grid < 0 || MT < 1 || MT >= 16)
+        return false;
+    const int nc = fp8 ? fp8_slot_count(MT, net->K, net->H) : chunk_count(MT, net->K, net->H);
+    return nc % 2 == 0;
+}
+
 bool fused_variant_ok(const ds_net *net, const FusedVariant &v)
 {
+    if (v.kind == DS_KERNEL_TEAMS)
+        return teams_ok(net, v, false);
     if (v.kind != DS_KERNEL_REGISTER && v.kind != DS_KERNEL_PIPELINED && v.kind != DS_KERNEL_WIDE)
         return false;
     if (v.waves != 4 && v.waves != 8)
@@ -1966,6 +2189,8 @@ bool fused_variant_ok(const ds_net *net, const FusedVariant &v)
 
 bool fused_variant_ok_fp8(const ds_net *net, const FusedVariant &v)
 {
+    if (v.kind == DS_KERNEL_TEAMS)
+        return teams_ok(net, v, true);
     return v.kind == DS_KERNEL_REGISTER && fused_variant_ok(net, v);
 }
 

@@ -106,8 +106,9 @@ def test_every_variant_and_grid_agrees(ctx, setup):
     try:
         base = torch.empty(N, dtype=torch.float32, device="cuda")
         ds.ds_batch_predict(b, ds.DS_PREC_BF16, s["pos"], s["view"], s["light"], base)
-        for kind in (ds.DS_KERNEL_REGISTER, ds.DS_KERNEL_PIPELINED, ds.DS_KERNEL_WIDE):
-            for waves in ((4,) if kind == ds.DS_KERNEL_WIDE else (4, 8)):
+        for kind in (ds.DS_KERNEL_REGISTER, ds.DS_KERNEL_PIPELINED, ds.DS_KERNEL_WIDE,
+                     ds.DS_KERNEL_TEAMS):
+            for waves in {ds.DS_KERNEL_WIDE: (4,), ds.DS_KERNEL_TEAMS: (8,)}.get(kind, (4, 8)):
                 for grid in (0, 1, 3, 64):
                     print("variant", kind, waves, grid, flush=True)
                     ds.ds_batch_set_config(b, kind, waves, grid)
@@ -115,9 +116,11 @@ def test_every_variant_and_grid_agrees(ctx, setup):
                     ds.ds_batch_predict(b, ds.DS_PREC_BF16, s["pos"], s["view"], s["light"], out)
                     assert torch.equal(out, base), (kind, waves, grid)
         with pytest.raises(ds.DSError):
-            ds.ds_batch_set_config(b, 3, 4, 0)
+            ds.ds_batch_set_config(b, 4, 4, 0)
         with pytest.raises(ds.DSError):
             ds.ds_batch_set_config(b, ds.DS_KERNEL_WIDE, 8, 0)
+        with pytest.raises(ds.DSError):
+            ds.ds_batch_set_config(b, ds.DS_KERNEL_TEAMS, 4, 0)
         with pytest.raises(ds.DSError):
             ds.ds_batch_set_config(b, 0, 6, 0)
     finally:
@@ -178,7 +181,8 @@ def test_spatial_order_is_bitwise_the_input_order(ctx, setup):
         assert int(ref[2][5]) & ds.DS_FLAG_OUTSIDE and int(ref[2][s["counts"][0] + 7]) & \
             ds.DS_FLAG_INVALID
         for kind, waves, grid in [(ds.DS_KERNEL_REGISTER, 4, 0), (ds.DS_KERNEL_REGISTER, 8, 3),
-                                  (ds.DS_KERNEL_PIPELINED, 4, 64), (ds.DS_KERNEL_WIDE, 4, 0)]:
+                                  (ds.DS_KERNEL_PIPELINED, 4, 64), (ds.DS_KERNEL_WIDE, 4, 0),
+                                  (ds.DS_KERNEL_TEAMS, 8, 0), (ds.DS_KERNEL_TEAMS, 8, 3)]:
             got = run(ds.DS_ORDER_SPATIAL, kind, waves, grid)
             for g, r in zip(got, ref):
                 assert torch.equal(g, r), (kind, waves, grid)
@@ -223,6 +227,18 @@ def test_batch_argument_checks(ctx, setup):
             ds.ds_batch_replay(b)
     finally:
         ds.ds_batch_destroy(b)
+    # the two-team kernel needs an even number of weight chunks per tile: K = 5, W = 16
+    # has 47
+    odd = ds.Net(ctx, K, 16, H)
+    try:
+        b = ds.ds_batch_create(ctx.h, odd.h, [c.h for c in s["clouds"][:2]], [0, 5, 6])
+        try:
+            with pytest.raises(ds.DSError):
+                ds.ds_batch_set_config(b, ds.DS_KERNEL_TEAMS, 8, 0)
+        finally:
+            ds.ds_batch_destroy(b)
+    finally:
+        odd.close()
 
 
 @pytest.fixture(scope="module")
@@ -253,6 +269,31 @@ def paper_width_batch(ctx):
     net.close()
     for c in clouds:
         c.close()
+
+
+@pytest.mark.parametrize("prec", [ds.DS_PREC_BF16, ds.DS_PREC_FP8])
+def test_paper_width_teams_kernel_matches_register_kernel(ctx, paper_width_batch, prec):
+    # the two-team kernel at paper width (ring of ten 13 KB chunks, team lag 6): bitwise the
+    # four-wave register kernel's outputs, on one workgroup per tile and on a persistent grid
+    s = paper_width_batch
+    N = int(s["offsets"][-1])
+    if prec == ds.DS_PREC_FP8:
+        a, b = int(s["offsets"][-2]), int(s["offsets"][-1])
+        ds.ds_net_quantize(ctx.h, s["net"].h, s["clouds"][-1].h, ds.DS_PREC_FP8,
+                           s["pos"][a:b].contiguous(), s["view"][a:b].contiguous(),
+                           s["light"][a:b].contiguous())
+    bt = ds.ds_batch_create(ctx.h, s["net"].h, [c.h for c in s["clouds"]], s["offsets"])
+    try:
+        ref = torch.full((N,), -1.0, device="cuda")
+        ds.ds_batch_predict(bt, prec, s["pos"], s["view"], s["light"], ref)
+        for grid in (0, 7, 256):
+            print("two-team kernel, precision", prec, "grid", grid, flush=True)
+            ds.ds_batch_set_config(bt, ds.DS_KERNEL_TEAMS, 8, grid)
+            out = torch.full((N,), -1.0, device="cuda")
+            ds.ds_batch_predict(bt, prec, s["pos"], s["view"], s["light"], out)
+            assert torch.equal(out, ref), grid
+    finally:
+        ds.ds_batch_destroy(bt)
 
 
 @pytest.mark.parametrize("order", [ds.DS_ORDER_INPUT, ds.DS_ORDER_SPATIAL])

@@ -239,19 +239,20 @@ def test_fp8_batched_variants_and_graph(ctx):
                 per.append(o)
         per = torch.cat(per)
         b = ds.ds_batch_create(ctx.h, net.h, [c.h for c in clouds], offsets)
-        for waves in (4, 8):
+        for kind, waves in ((ds.DS_KERNEL_REGISTER, 4), (ds.DS_KERNEL_REGISTER, 8),
+                            (ds.DS_KERNEL_TEAMS, 8)):
             for grid in (0, 1, 3, 64):
-                print("fp8 variant", waves, grid, flush=True)
-                ds.ds_batch_set_config(b, ds.DS_KERNEL_REGISTER, waves, grid)
+                print("fp8 variant", kind, waves, grid, flush=True)
+                ds.ds_batch_set_config(b, kind, waves, grid)
                 out = torch.full((N,), -1.0, device="cuda")
                 ds.ds_batch_predict(b, ds.DS_PREC_FP8, pos, view, light, out)
-                assert torch.equal(out, per), (waves, grid)
+                assert torch.equal(out, per), (kind, waves, grid)
         ds.ds_batch_set_config(b, ds.DS_KERNEL_PIPELINED, 4, 0)
-        with pytest.raises(ds.DSError) as e:  # the FP8 form has the register kernel only
+        with pytest.raises(ds.DSError) as e:  # the FP8 form: register and two-team kernels
             ds.ds_batch_predict(b, ds.DS_PREC_FP8, pos, view, light, out)
         assert e.value.status == -4
         cfg = ds.ds_batch_autotune(b, ds.DS_PREC_FP8, pos, view, light, out, 2)
-        assert cfg["kernel"] == ds.DS_KERNEL_REGISTER and cfg["ms"] > 0
+        assert cfg["kernel"] in (ds.DS_KERNEL_REGISTER, ds.DS_KERNEL_TEAMS) and cfg["ms"] > 0
         out.fill_(-1.0)
         ds.ds_batch_capture(b, ds.DS_PREC_FP8, pos, view, light, out)
         for r in range(3):
