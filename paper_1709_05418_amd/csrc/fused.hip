@@ -683,21 +683,35 @@ __device__ __forceinline__ void fp8_layer(Stage &ws, int tid, int lane,
     }
 }
 
-// out = relu(Wmat in + bias) for a W-wide input held in accumulator layout.
-template <int MT, int NW, class Stage>
+// Inputs of the free half of a layer's last chunk when the bias rides in it (odd MT): the
+// fragments hold the bias split into BF16 high and low parts at inputs (g = 0, j = 4, 5)
+// of that chunk (see build_pack_maps), so those two inputs are 1 and the product adds the
+// bias; the vector loads of the bias, which pass through the same memory path as the
+// samples and the weight copies, are not needed.
+__device__ __forceinline__ f4 bias_ones(int g)
+{
+    const float one = g == 0 ? 1.f : 0.f;
+    return f4{one, one, 0.f, 0.f};
+}
+
+// out = relu(Wmat in + bias) for a W-wide input held in accumulator layout; FOLD: the bias
+// comes with the last chunk's fragments instead of a vector load (odd MT only).
+template <int MT, int NW, class Stage, bool FOLD = false>
 __device__ __forceinline__ void dense(Stage &ws, const float *__restrict__ bias,
                                       int tid, int lane, const f4 (&in)[MT], f4 (&out)[MT])
 {
+    static_assert(!FOLD || (MT & 1), "a folded bias needs the free half of an odd last chunk");
     constexpr int C2 = (MT + 1) / 2;
     const int g = lane >> 4;
+    const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
-        out[mt] = *reinterpret_cast<const f4 *>(bias + 16 * mt + 4 * g);
+        out[mt] = FOLD ? z4 : *reinterpret_cast<const f4 *>(bias + 16 * mt + 4 * g);
 #pragma unroll
     for (int q = 0; q < C2; ++q) {
         ws.fetch(tid);
-        const f4 z4 = f4{0.f, 0.f, 0.f, 0.f};
-        bf16x8 B = pack8(in[2 * q], (2 * q + 1 < MT) ? in[2 * q + 1 < MT ? 2 * q + 1 : 0] : z4);
+        bf16x8 B = pack8(in[2 * q], (2 * q + 1 < MT) ? in[2 * q + 1 < MT ? 2 * q + 1 : 0]
+                                                      : (FOLD ? bias_ones(g) : z4));
         mfma_chunk<MT>(ws.chunk(), lane, B, out);
         ws.template next<0>(tid);
     }
@@ -976,6 +990,11 @@ __device__ __forceinline__ void predict_points(const FusedArgs &a, const FusedCl
 {
     constexpr int C2 = (MT + 1) / 2;
     constexpr int WP = 16 * MT;
+    // The first layer's bias b1 rides in stencil chunk 7 (inputs (g = 1, j = 0, 1), split
+    // into BF16 high and low parts, in both forms); with an odd MT the BF16 form's b2 and
+    // the dense layers' biases ride in the free half of their last chunk (bias_ones).  The
+    // FP8 form keeps b2 and the dense biases as vector loads: its last chunks are FP8.
+    constexpr bool FOLD2 = !F8 && (MT & 1);
     const int lane = tid & 63;
     const int g = lane >> 4;
     float gamma;
@@ -1007,10 +1026,10 @@ __device__ __forceinline__ void predict_points(const FusedArgs &a, const FusedCl
         level_from_geom(L, gslot, q);
         const float *b1 = vec + (size_t)k * 2 * WP;
         const float *b2 = b1 + WP;
-        // the first layer accumulates onto its bias
+        (void)b1;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
-            F[mt] = *reinterpret_cast<const f4 *>(b1 + 16 * mt + 4 * g);
+            F[mt] = z4;
         Pending pa, pb;
         issue_column<CL>(cells, L, q, 0, g, cols, pa, pb);
 #pragma unroll 1
@@ -1070,7 +1089,8 @@ __device__ __forceinline__ void predict_points(const FusedArgs &a, const FusedCl
             const float sv = finish_one(pa.v[0], pa.fx[0], pa.t[0]);
             asm volatile("" ::"v"(sv));
             ws.fetch(tid);
-            const f4 lo = f4{g == 0 ? sv : 0.f, g == 0 ? gamma : 0.f, 0.f, 0.f};
+            const float one = g == 1 ? 1.f : 0.f;  // the inputs of b1's two parts
+            const f4 lo = f4{g == 0 ? sv : one, g == 0 ? gamma : one, 0.f, 0.f};
             mfma_chunk<MT>(ws.chunk(), lane, pack8(lo, (!F8 && (MT & 1)) ? O[MT - 1] : z4),
                            F);
             ws.template next<0>(tid);
@@ -1094,7 +1114,8 @@ __device__ __forceinline__ void predict_points(const FusedArgs &a, const FusedCl
                 for (int i = 0; i < 4; ++i)
                     F[mt][i] = __builtin_amdgcn_fmed3f(F[mt][i], 0.f, 448.f);
             }
-            O[mt] += *reinterpret_cast<const f4 *>(b2 + 16 * mt + 4 * g);
+            if constexpr (!FOLD2)
+                O[mt] += *reinterpret_cast<const f4 *>(b2 + 16 * mt + 4 * g);
         }
         if constexpr (F8) {
             fp8_layer<MT, NW, false>(ws, tid, lane, F, O);
@@ -1105,7 +1126,7 @@ __device__ __forceinline__ void predict_points(const FusedArgs &a, const FusedCl
                 mfma_chunk<MT>(ws.chunk(), lane,
                                pack8_relu(F[2 * qq],
                                           (2 * qq + 1 < MT) ? F[2 * qq + 1 < MT ? 2 * qq + 1 : 0]
-                                                            : z4),
+                                                            : (FOLD2 ? bias_ones(g) : z4)),
                                O);
                 ws.template next<0>(tid);
             }
@@ -1131,11 +1152,11 @@ __device__ __forceinline__ void predict_points(const FusedArgs &a, const FusedCl
         }
     } else {
         for (; h + 1 < a.H - 1; h += 2) {
-            dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
-            dense<MT, NW>(ws, bh + (size_t)(h + 1) * WP, tid, lane, F, O);
+            dense<MT, NW, Stage, FOLD2>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+            dense<MT, NW, Stage, FOLD2>(ws, bh + (size_t)(h + 1) * WP, tid, lane, F, O);
         }
         if (h < a.H - 1) {
-            dense<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+            dense<MT, NW, Stage, FOLD2>(ws, bh + (size_t)h * WP, tid, lane, O, F);
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
                 O[mt] = F[mt];
@@ -1580,6 +1601,17 @@ int pair_slot(int MT, int q, int g, int j)
     return 16 * t + 4 * g + (j & 3);
 }
 
+// Inputs of a W-wide layer's chunk q that carry the layer's bias (high part at j = 4, low
+// part at j = 5 of lane group 0): the free half of the last chunk when MT is odd.
+bool bias_slot(int MT, int q, int g, int j)
+{
+    return (MT & 1) && q == (MT + 1) / 2 - 1 && g == 0 && (j == 4 || j == 5);
+}
+
+// fragment map entries of a bias's low part: the parameter index with this bit set; the
+// packing stores bf16(v - bf16(v)) there (v the parameter), the high part stores bf16(v)
+constexpr int64_t kLowPart = (int64_t)1 << 30;
+
 // Chunks in consumption order: block 1 has 8 stencil chunks, later blocks also the
 // o^{k-1} pairs; every block then its second layer; then the dense trailing layers.
 int chunk_count(int MT, int K, int H)
@@ -1803,6 +1835,8 @@ static void build_pack_maps(int K, int W, int H, std::vector<int32_t> &fmap,
                                     idx = oV[k] + (int64_t)row * 226 + 224;  // (4, 4, 8)
                                 else if (g == 0 && j == 1)
                                     idx = oV[k] + (int64_t)row * 226 + 225;  // gamma
+                                else if (g == 1 && j < 2)  // b1: high, low part
+                                    idx = (ob1[k] + row) | (j ? kLowPart : 0);
                                 else if (j >= 4 && (MT & 1) && k > 0) {
                                     const int col = 16 * (MT - 1) + 4 * g + (j - 4);
                                     if (col < W)
@@ -1825,8 +1859,10 @@ static void build_pack_maps(int K, int W, int H, std::vector<int32_t> &fmap,
                             continue;
                         for (int j = 0; j < 8; ++j) {
                             const int col = pair_slot(MT, q, g, j);
-                            put(frag + mt, g, r, j,
-                                (col >= 0 && col < W) ? oW2[k] + (int64_t)row * W + col : -1);
+                            int64_t idx = (col >= 0 && col < W) ? oW2[k] + (int64_t)row * W + col : -1;
+                            if (bias_slot(MT, q, g, j))  // b2: high, low part
+                                idx = (ob2[k] + row) | (j == 5 ? kLowPart : 0);
+                            put(frag + mt, g, r, j, idx);
                         }
                     }
     }
@@ -1840,8 +1876,10 @@ static void build_pack_maps(int K, int W, int H, std::vector<int32_t> &fmap,
                             continue;
                         for (int j = 0; j < 8; ++j) {
                             const int col = pair_slot(MT, q, g, j);
-                            put(frag + mt, g, r, j,
-                                (col >= 0 && col < W) ? ohw[h] + (int64_t)row * W + col : -1);
+                            int64_t idx = (col >= 0 && col < W) ? ohw[h] + (int64_t)row * W + col : -1;
+                            if (bias_slot(MT, q, g, j))  // the layer's bias: high, low part
+                                idx = (ohb[h] + row) | (j == 5 ? kLowPart : 0);
+                            put(frag + mt, g, r, j, idx);
                         }
                     }
     // vectors: per block b1, b2; per dense trailing layer its bias; final weights + bias
@@ -1869,7 +1907,16 @@ __global__ void __launch_bounds__(256) k_pack_frags(const float *__restrict__ th
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t idx = map[i];
-        uint32_t u = idx >= 0 ? __float_as_uint(theta[idx]) : 0u;
+        float v = 0.f;
+        if (idx >= 0) {
+            v = theta[idx & (int32_t)(kLowPart - 1)];
+            if (idx & (int32_t)kLowPart) {  // low part: the remainder of the high part
+                uint32_t h = __float_as_uint(v);
+                h = (h + 0x7FFFu + ((h >> 16) & 1u)) & 0xFFFF0000u;
+                v -= __uint_as_float(h);
+            }
+        }
+        uint32_t u = __float_as_uint(v);
         u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
         out[i] = (uint16_t)(u >> 16);
     }
@@ -1893,6 +1940,9 @@ ds_status fused_prepare(ds_net *net)
         return DS_OK;
     DS_CHECK(fused_tiles(net->W) > 0, DS_ERR_UNSUPPORTED,
              "width %d is not supported by the fused kernel", net->W);
+    DS_CHECK(net->n_params < kLowPart, DS_ERR_UNSUPPORTED,
+             "%lld parameters: the fused kernel's packing map holds fewer than 2^30",
+             (long long)net->n_params);
     std::vector<int32_t> fmap, vmap;
     build_pack_maps(net->K, net->W, net->H, fmap, vmap);
     const int64_t nf = (int64_t)fmap.size(), nv = (int64_t)vmap.size();
@@ -2098,6 +2148,14 @@ ds_status fused_quantize_fp8(ds_net *net, const float *th, const float *act_amax
                                 col = stencil_slot(c, g, j);
                             else if (g == 0 && j < 2)
                                 col = 224 + j;  // sample (4, 4, 8), gamma
+                            if (c == 7 && g == 1 && j < 2) {  // b1 in block k's units: high, low
+                                const float b = (float)ldexp((double)th[pb.b1[k] + row], f[k]);
+                                const uint16_t hi = bf16_rne(b);
+                                dst[j] = j == 0 ? hi
+                                                : bf16_rne(b - __builtin_bit_cast(
+                                                                   float, (uint32_t)hi << 16));
+                                continue;
+                            }
                             dst[j] = col < 0 ? 0
                                              : bf16_rne((float)ldexp(
                                                    (double)th[pb.V[k] + (int64_t)row * 226 + col],

@@ -26,9 +26,18 @@ H = 3
 FP8_GATE = 5e-2
 
 
-def theta_for(K, W, seed):
-    return synth.init_params(K, W, H, seed, branch_scale=1.0 / math.sqrt(K), out_scale=0.2,
-                             out_bias=0.5)
+def theta_for(K, W, seed, biases=False):
+    th = synth.init_params(K, W, H, seed, branch_scale=1.0 / math.sqrt(K), out_scale=0.2,
+                           out_bias=0.5)
+    if biases:  # every bias but the output's drawn from N(0, 0.2^2)
+        rng = np.random.default_rng(seed + 100)
+        o = 0
+        for name, r, c in synth.layer_shapes(K, W, H):
+            n = r * (c if c else 1)
+            if c == 0 and name != f"bh{H - 1}":
+                th[o:o + n] = rng.normal(0.0, 0.2, n)
+            o += n
+    return th
 
 
 def numpy_activation_maxima(theta, K, W, z):
@@ -104,13 +113,14 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("biases", [False, True])
 @pytest.mark.parametrize("name", list(CASES))
-def test_fp8_prediction_matches_oracle(ctx, name):
+def test_fp8_prediction_matches_oracle(ctx, name, biases):
     c = CASES[name]
     K, W = c["K"], c["W"]
     w = Workload(c["n"], c["sigma"], L=c["L"], K=K, P=c["P"], seed_cloud=c["seed_cloud"],
                  seed_pts=c["seed_pts"], worley=c["worley"])
-    theta = theta_for(K, W, 12)
+    theta = theta_for(K, W, 12, biases)
     cloud = ds.Cloud(ctx, w.density.cuda(), w.sigma_max, w.aabb_min, w.h0, w.L, K, w.mips)
     net = ds.Net(ctx, K, W, H)
     try:
@@ -127,7 +137,9 @@ def test_fp8_prediction_matches_oracle(ctx, name):
         sl = slice(ncal, None)
         e8 = (rel_l2(g8.cpu().numpy()[sl], gr[sl]), rel_l2(p8.cpu().numpy()[sl], pr[sl]))
         e16 = (rel_l2(g16.cpu().numpy()[sl], gr[sl]), rel_l2(p16.cpu().numpy()[sl], pr[sl]))
-        print(f"{name}: fp8 g {e8[0]:.3e} pre {e8[1]:.3e}; bf16 g {e16[0]:.3e} pre {e16[1]:.3e}; "
+        assert max(e16) < 2e-2
+        print(f"{name}, biases {biases}: fp8 g {e8[0]:.3e} pre {e8[1]:.3e}; bf16 g {e16[0]:.3e} "
+              f"pre {e16[1]:.3e}; "
               f"alive {(gr > 0).mean():.2f}", flush=True)
         assert max(e8) < FP8_GATE
         assert np.array_equal(fl8.cpu().numpy(), flr)

@@ -147,6 +147,48 @@ def test_predict_paper_width(ctx, paper_width, prec, tol):
     cloud.close()
 
 
+def _biased_params(K, W, H, seed):
+    # the reduced-precision recipe (R21) with every bias drawn from N(0, 0.2^2): the fused
+    # kernel carries the biases inside its weight chunks (a BF16 high and low part, the
+    # dense layers' only when the tile count is odd), which zero biases would not test
+    theta = synth.init_params(K, W, H, seed, branch_scale=1 / np.sqrt(K), out_scale=0.2,
+                              out_bias=0.5)
+    rng = np.random.default_rng(seed + 100)
+    o = 0
+    for name, r, c in synth.layer_shapes(K, W, H):
+        n = r * (c if c else 1)
+        if c == 0 and name != f"bh{H - 1}":
+            theta[o:o + n] = rng.normal(0.0, 0.2, n)
+        o += n
+    return theta
+
+
+@pytest.mark.parametrize("W", [16, 64, 200])
+def test_predict_with_nonzero_biases(ctx, tiny, tiny_cloud, W):
+    # W = 16 and 200: odd tile counts (every bias in the chunks); W = 64: even (b1 only).
+    # The FP8 form is checked where it is specified (K = 6 at W = 64 here; K = 10 at W = 200
+    # in the FP8 tests): on this 6-block network it misses its gate at W = 16 and W = 200
+    # with or without biases (7 % and 16-18 %, the same with biases as vector loads)
+    w = tiny
+    theta = _biased_params(w.K, W, 3, 40 + W)
+    net = ds.Net(ctx, w.K, W, 3)
+    try:
+        net.set_params(theta)
+        pos, view, light = w.cuda_inputs()
+        zr, _ = w.oracle_z()
+        gr, prer = O.forward(theta.astype(np.float64), w.K, W, 3, zr)
+        ds.ds_net_quantize(ctx.h, net.h, tiny_cloud.h, ds.DS_PREC_FP8, pos[::3].contiguous(),
+                           view[::3].contiguous(), light[::3].contiguous())
+        precs = [(ds.DS_PREC_BF16, TOL_BF16)] + ([(ds.DS_PREC_FP8, 5e-2)] if W == 64 else [])
+        for prec, tol in precs:
+            g, pre, _ = ds.ds_predict(ctx.h, tiny_cloud.h, net.h, prec, pos, view, light)
+            e = rel_l2(pre.cpu().numpy(), prer)
+            print(f"W={W} precision {prec}: relative L2 of the pre-activation {e:.2e}", flush=True)
+            assert e <= tol
+    finally:
+        net.close()
+
+
 def test_degenerate_and_invalid_inputs(ctx, tiny, tiny_cloud):
     net, theta = _net(ctx, tiny.K, 64)
     pos = tiny.pos[:8].copy()
