@@ -622,14 +622,16 @@ __device__ __forceinline__ void mfma_chunk(const uint4 *w, int lane, const bf16x
 // accumulator layout, dword d holding tile 8Q + d's four features of this lane.  The
 // hardware conversion rounds to nearest even but does not saturate (>= 464 gives
 // NaN), so inputs that may exceed 448 are clamped first.
-template <int MT, bool CLAMP>
-__device__ __forceinline__ fp8x32 pack_fp8(const f4 (&x)[MT], int Q)
+template <int MT, bool CLAMP, bool BIAS = false>
+__device__ __forceinline__ fp8x32 pack_fp8(const f4 (&x)[MT], int Q, int g)
 {
     fp8x32 r;
 #pragma unroll
     for (int d = 0; d < 8; ++d) {
         const int t = 8 * Q + d;
-        if (t < MT) {
+        if (BIAS && t == MT) {  // inputs 0..2 of lane group 0 in the first free tile: E4M3 1.0
+            r[d] = g == 0 ? 0x00383838 : 0;
+        } else if (t < MT) {
             f4 v = x[t < MT ? t : 0];
             if (CLAMP) {  // inputs are ReLU outputs, >= 0
 #pragma unroll
@@ -669,15 +671,18 @@ __device__ __forceinline__ void mfma8_chunk(const uint4 *w, int lane, const fp8x
     __builtin_amdgcn_sched_barrier(0);
 }
 
-// Consume one FP8 chunk (two staging slots) of a W-wide layer.
-template <int MT, int NW, bool CLAMP, class Stage>
+// Consume one FP8 chunk (two staging slots) of a W-wide layer; BIAS: the layer's bias
+// rides in the first free tile of its last chunk (three E4M3 parts, see fused_quantize_fp8),
+// whose inputs pack_fp8 sets to 1.
+template <int MT, int NW, bool CLAMP, class Stage, bool BIAS = false>
 __device__ __forceinline__ void fp8_layer(Stage &ws, int tid, int lane,
                                           const f4 (&in)[MT], f4 (&acc)[MT])
 {
+    static_assert(!BIAS || MT % 8 != 0, "a folded bias needs a free tile in the last chunk");
 #pragma unroll
     for (int Q = 0; Q < (MT + 7) / 8; ++Q) {
         ws.fetch(tid);
-        mfma8_chunk<MT>(ws.chunk(), lane, pack_fp8<MT, CLAMP>(in, Q), acc);
+        mfma8_chunk<MT>(ws.chunk(), lane, pack_fp8<MT, CLAMP, BIAS>(in, Q, lane >> 4), acc);
         ws.template next<0>(tid);
         ws.template next<0>(tid);
     }
@@ -723,16 +728,18 @@ __device__ __forceinline__ void dense(Stage &ws, const float *__restrict__ bias,
 }
 
 // FP8 form of dense(): the output stays in its scaled units (biases pre-scaled), and the
-// ReLU clamps at 448 so that the next FP8 layer can take it unclamped.
-template <int MT, int NW, class Stage>
+// ReLU clamps at 448 so that the next FP8 layer can take it unclamped.  FOLD: the bias
+// comes with the last chunk (MT not a multiple of 8).
+template <int MT, int NW, class Stage, bool FOLD = false>
 __device__ __forceinline__ void dense8(Stage &ws, const float *__restrict__ bias,
                                        int tid, int lane, const f4 (&in)[MT], f4 (&out)[MT])
 {
     const int g = lane >> 4;
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
-        out[mt] = *reinterpret_cast<const f4 *>(bias + 16 * mt + 4 * g);
-    fp8_layer<MT, NW, true>(ws, tid, lane, in, out);
+        out[mt] = FOLD ? f4{0.f, 0.f, 0.f, 0.f}
+                       : *reinterpret_cast<const f4 *>(bias + 16 * mt + 4 * g);
+    fp8_layer<MT, NW, true, Stage, FOLD>(ws, tid, lane, in, out);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -992,9 +999,11 @@ __device__ __forceinline__ void predict_points(const FusedArgs &a, const FusedCl
     constexpr int WP = 16 * MT;
     // The first layer's bias b1 rides in stencil chunk 7 (inputs (g = 1, j = 0, 1), split
     // into BF16 high and low parts, in both forms); with an odd MT the BF16 form's b2 and
-    // the dense layers' biases ride in the free half of their last chunk (bias_ones).  The
-    // FP8 form keeps b2 and the dense biases as vector loads: its last chunks are FP8.
+    // the dense layers' biases ride in the free half of their last chunk (bias_ones); when
+    // MT is not a multiple of 8 the FP8 form's b2 and dense biases ride in the first free
+    // tile of their last FP8 chunk (three E4M3 parts).  Otherwise they are vector loads.
     constexpr bool FOLD2 = !F8 && (MT & 1);
+    constexpr bool FOLD8 = F8 && (MT % 8 != 0);
     const int lane = tid & 63;
     const int g = lane >> 4;
     float gamma;
@@ -1114,11 +1123,11 @@ __device__ __forceinline__ void predict_points(const FusedArgs &a, const FusedCl
                 for (int i = 0; i < 4; ++i)
                     F[mt][i] = __builtin_amdgcn_fmed3f(F[mt][i], 0.f, 448.f);
             }
-            if constexpr (!FOLD2)
+            if constexpr (!FOLD2 && !FOLD8)
                 O[mt] += *reinterpret_cast<const f4 *>(b2 + 16 * mt + 4 * g);
         }
         if constexpr (F8) {
-            fp8_layer<MT, NW, false>(ws, tid, lane, F, O);
+            fp8_layer<MT, NW, false, Stage, FOLD8>(ws, tid, lane, F, O);
         } else {
 #pragma unroll
             for (int qq = 0; qq < C2; ++qq) {
@@ -1141,11 +1150,11 @@ __device__ __forceinline__ void predict_points(const FusedArgs &a, const FusedCl
     int h = 0;
     if constexpr (F8) {
         for (; h + 1 < a.H - 1; h += 2) {
-            dense8<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
-            dense8<MT, NW>(ws, bh + (size_t)(h + 1) * WP, tid, lane, F, O);
+            dense8<MT, NW, Stage, FOLD8>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+            dense8<MT, NW, Stage, FOLD8>(ws, bh + (size_t)(h + 1) * WP, tid, lane, F, O);
         }
         if (h < a.H - 1) {
-            dense8<MT, NW>(ws, bh + (size_t)h * WP, tid, lane, O, F);
+            dense8<MT, NW, Stage, FOLD8>(ws, bh + (size_t)h * WP, tid, lane, O, F);
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
                 O[mt] = F[mt];
@@ -2027,6 +2036,14 @@ uint16_t bf16_rne(float x)
     return (uint16_t)(u >> 16);
 }
 
+// value of an OCP E4M3 code (bias 7, subnormals below 2^-6; 0x7F/0xFF are NaN, never encoded)
+double e4m3_value(uint8_t c)
+{
+    const double sgn = (c & 0x80) ? -1.0 : 1.0;
+    const int e = (c >> 3) & 15, m = c & 7;
+    return sgn * (e == 0 ? ldexp((double)m, -9) : ldexp(1.0 + m / 8.0, e - 7));
+}
+
 double tensor_amax(const float *th, int64_t off, int64_t n)
 {
     double m = 0.0;
@@ -2065,7 +2082,17 @@ ds_status fused_quantize_fp8(ds_net *net, const float *th, const float *act_amax
     // matrix exponent (output unit - input unit) at most its range-filling one (weights
     // fit under 448): f_k - o <= wW1_k, o - f_k <= wW2_k, h_m - in_m <= wH_m.  Lowering
     // o only lowers the bounds, so the loop ends.
+    // A bias that rides in its layer's last FP8 chunk (MT not a multiple of 8) is three
+    // E4M3 parts behind inputs of 1, so it must fit under 448 in its output unit as well.
+    const bool fold = MT % 8 != 0;
     int o = eO;
+    if (fold) {
+        double bm = 0.0;
+        for (int k = 0; k < K; ++k)
+            bm = fmax(bm, tensor_amax(th, pb.b2[k], W));
+        if (bm > 0.0 && log2_scale(bm) < o)
+            o = log2_scale(bm);
+    }
     std::vector<int> f(K);
     for (int it = 0;; ++it) {
         bool again = false;
@@ -2087,6 +2114,9 @@ ds_status fused_quantize_fp8(ds_net *net, const float *th, const float *act_amax
     for (int m = 0; m < H - 1; ++m) {
         const int in = m == 0 ? o : h[m - 1];
         h[m] = in + wH[m] < eH[m] ? in + wH[m] : eH[m];
+        const double bm = fold ? tensor_amax(th, pb.hb[m], W) : 0.0;
+        if (bm > 0.0 && log2_scale(bm) < h[m])
+            h[m] = log2_scale(bm);
     }
     // exported: units, then matrix exponents
     std::vector<int32_t> ex;
@@ -2111,8 +2141,20 @@ ds_status fused_quantize_fp8(ds_net *net, const float *th, const float *act_amax
     auto entry = [&](int64_t slot, int mt, int lane) -> uint8_t * {
         return reinterpret_cast<uint8_t *>(&fr[(size_t)((slot * MT + mt) * 64 + lane)]);
     };
-    // one FP8 matrix [W][W] at offset off, scale 2^e, starting at `slot`
-    auto put_fp8 = [&](int64_t slot, int64_t off, int e) {
+    // One FP8 matrix [W][W] at offset off, scale 2^e, starting at `slot`; with boff >= 0
+    // its bias (offset boff, in units 2^be) goes to the first free tile t = MT of the last
+    // chunk, inputs 0..2 of lane group 0, as three E4M3 parts: each part encodes what the
+    // parts before it left over (about 12 significant bits in all).
+    auto put_fp8 = [&](int64_t slot, int64_t off, int e, int64_t boff = -1, int be = 0) {
+        auto part = [&](int row, int i) -> uint8_t {
+            double r = ldexp((double)th[boff + row], be);
+            uint8_t c = 0;
+            for (int q = 0; q <= i; ++q) {
+                c = e4m3_encode((float)r);
+                r -= e4m3_value(c);
+            }
+            return c;
+        };
         for (int Q = 0; Q < C8; ++Q)
             for (int h = 0; h < 2; ++h)
                 for (int mt = 0; mt < MT; ++mt)
@@ -2129,6 +2171,8 @@ ds_status fused_quantize_fp8(ds_net *net, const float *th, const float *act_amax
                                               ? e4m3_encode((float)ldexp(
                                                     (double)th[off + (int64_t)row * W + col], e))
                                               : 0;
+                                if (boff >= 0 && t == MT && g == 0 && (b & 3) < 3)
+                                    dst[bb] = part(row, b & 3);
                             }
                         }
     };
@@ -2166,11 +2210,11 @@ ds_status fused_quantize_fp8(ds_net *net, const float *th, const float *act_amax
             put_fp8(slot, pb.W1[k], f[k] - o);
             slot += 2 * C8;
         }
-        put_fp8(slot, pb.W2[k], o - f[k]);
+        put_fp8(slot, pb.W2[k], o - f[k], fold ? pb.b2[k] : -1, o);
         slot += 2 * C8;
     }
     for (int m = 0; m < H - 1; ++m) {
-        put_fp8(slot, pb.hw[m], h[m] - (m == 0 ? o : h[m - 1]));
+        put_fp8(slot, pb.hw[m], h[m] - (m == 0 ? o : h[m - 1]), fold ? pb.hb[m] : -1, h[m]);
         slot += 2 * C8;
     }
     if (slot != slots) {
