@@ -529,7 +529,7 @@ struct TeamRing {
         team = w >> 2;
         r0 = w * RB + (w < RX ? w : RX);
         more = RX > 0 && w < RX;
-        slot = team == 0 ? 0 : R - D;  // team 1 starts D idle steps behind chunk 0
+        slot = team == 0 ? 0 : (R - D) % R;  // team 1 starts D idle steps behind chunk 0
         cslot = 0;
         k = 0;
         pending = false;

@@ -193,6 +193,64 @@ def test_render_rpnn_fallback(ctx):
         cloud.close()
 
 
+def test_render_rpnn_fallback_values_match_oracle(ctx):
+    # Sec. 4.4: where the stencil leaves the grid, the pixel takes a path-traced L_i in
+    # place of the network's.  One camera sample per pixel on a cloud that fills its box,
+    # FP32 network: the oracle takes the same first hits, gathers and flags them, evaluates
+    # the network on the rows without the flag and traces the flagged rows on the streams
+    # the renderer derives for camera sample 0
+    w = Workload(32, 32.0, L=5, K=5, P=1, density=0.6 + 0.4 * synth.cloud_density(32, 9))
+    cloud = ds.Cloud(ctx, w.density.cuda(), w.sigma_max, w.aabb_min, w.h0, w.L, w.K, w.mips)
+    net, theta = _net(ctx, w.K, 32)
+    o, dd = _rays(16, 2)
+    ld = synth.table1_lights()["side"]
+    alb, gg, E, seed, fspp = 0.95, 0.85, 1.5, 3, 32
+    prm = ds.TracerParams(alb, gg, E, 0, 0)
+    N = o.shape[0]
+    lt = np.broadcast_to(np.asarray(ld, np.float32), (N, 3)).copy()
+    try:
+        img, _, _, nfb = ds.ds_render_rpnn(ctx.h, cloud.h, net.h, ds.DS_PREC_F32, prm, ld,
+                                           _cuda(o), _cuda(dd), 1, seed, fallback_spp=fspp,
+                                           count_fallback=True)
+        img = img.cpu().numpy()
+        pos, view, _, hit = ds.ds_first_hits(ctx.h, cloud.h, prm, ld, _cuda(o), _cuda(dd),
+                                             seed=seed, sample=0)
+        _, _, fl = ds.ds_predict(ctx.h, cloud.h, net.h, ds.DS_PREC_F32, pos, view, _cuda(lt))
+        pg, hg, flg = pos.cpu().numpy(), hit.cpu().numpy(), fl.cpu().numpy()
+    finally:
+        net.close()
+        cloud.close()
+    po, vo, do, ho = O.first_hits(w.grid, o, dd, ld, albedo=alb, g=gg, irradiance=E, seed=seed,
+                                  sample=0)
+    h = ho == 1
+    pyr, dims, offs = w.pyr
+    z, flo = O.gather(w.grid, pyr, dims, offs, w.mean, w.K, w.mips, po[h], vo[h], lt[h])
+    fb = np.zeros(N, bool)
+    fb[h] = (flo & O.FLAG_FALLBACK) != 0
+    gnet = np.zeros(N)
+    gnet[h], _ = O.forward(theta.astype(np.float64), w.K, 32, 3, z)
+    # streams are keyed by the row, so every row is traced (rows without a hit from a
+    # stand-in position; their estimates are not used)
+    i0 = int(np.argmax(h))
+    pf = np.where(h[:, None], po, po[i0]).astype(np.float32)
+    vf = np.where(h[:, None], vo, vo[i0]).astype(np.float32)
+    mc, mc_var = O.trace_li(w.grid, pf, vf, lt, albedo=alb, g=gg, irradiance=E, spp=fspp,
+                            seed=derived_key(seed, 1))
+    ref = np.where(h, do + alb * np.where(fb, mc, E * gnet), 0.0)
+    # rows where both sides took the same first hit and the same fallback decision
+    lib_fb = (flg & ds.DS_FLAG_FALLBACK) != 0
+    same = (hg == ho) & (np.linalg.norm(pg - po, axis=1) < 1e-4) & (lib_fb == fb)
+    assert same.mean() > 0.9, same.mean()
+    assert nfb == int((lib_fb & (hg == 1)).sum())
+    net_rows, mc_rows = same & h & ~fb, same & h & fb
+    assert net_rows.sum() > 20 and mc_rows.sum() > 20, (net_rows.sum(), mc_rows.sum())
+    assert rel_l2(img[net_rows], ref[net_rows]) < 1e-4
+    # the same paths up to rounding: equal in the median, within 5 sigma everywhere
+    err = np.abs(img[mc_rows] - ref[mc_rows])
+    assert np.all(err <= 5 * alb * np.sqrt(2 * mc_var[mc_rows]) + 1e-6)
+    assert np.median(err / np.maximum(ref[mc_rows], 1e-6)) < 1e-3
+
+
 def test_trained_network_beats_direct_light_only(ctx):
     # training pairs from four seeded clouds, a short run of Adam, and a view of a
     # fifth cloud: the network image must be far closer to the path-traced one than
