@@ -241,6 +241,96 @@ def test_batch_argument_checks(ctx, setup):
         odd.close()
 
 
+def _fast(info, h0):
+    """Whether every level of a cloud gets a zero border wide enough for the unclamped pass:
+    the library's rule (a border of ceil(E + 1/2) + 1 cells, E = sqrt(11) 2^k / mean / h for
+    each stencil level k on that level, kept only while at most 256 cells and not growing
+    the level beyond 1.5 times or 2^21 cells), restated to check that a test builds both
+    kinds of cloud."""
+    mean, mips = info["mean_mu_t"], info["mip_of_level"]
+    for i, (nx, ny, nz) in enumerate(info["dims"]):
+        ext = max([3.3166248 * 2.0 ** k / mean / (h0 * 2.0 ** i)
+                   for k, m in enumerate(mips) if m == i], default=0.0)
+        if ext > 0.0:
+            want = np.ceil(ext + 0.5) + 1.0
+            base = (nx + 2) * (ny + 2) * (nz + 2)
+            grown = (nx + 2 * want) * (ny + 2 * want) * (nz + 2 * want)
+            if not (want <= 256 and (grown <= 1.5 * base or grown <= 1 << 21)):
+                return False
+    return True
+
+
+def test_variants_orders_with_a_clamped_cloud_and_invalid_points(ctx):
+    # The two-pass launches leave clouds whose borders are too narrow, and tiles holding a
+    # point outside the grid box, to the clamped pass; the two-team kernel then walks such
+    # a cloud's chunks idle, and its clamped pass recomputes 64-point halves of its 128-point
+    # tiles.  A batch with a thin cloud between two dense ones and invalid points in ragged
+    # tiles: every variant in both point orders, bitwise the per-cloud default launches
+    # (outputs, pre-activations and flags), BF16 and FP8.
+    specs = [(32, 32.0, 300, 81), (24, 0.5, 150, 82), (40, 40.0, 260, 83)]
+    ws, clouds = [], []
+    try:
+        for n, sig, P, seed in specs:
+            w = Workload(n, sig, L=5, K=K, P=P, seed_cloud=seed, seed_pts=seed + 10)
+            ws.append(w)
+            clouds.append(ds.Cloud(ctx, w.density.cuda(), sig, w.aabb_min, w.h0, w.L, K))
+        assert [_fast(c.info, w.h0) for c, w in zip(clouds, ws)] == [True, False, True]
+        counts = [w.P for w in ws]
+        offsets = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+        pos = np.concatenate([w.pos for w in ws]).astype(np.float32)
+        view = np.concatenate([w.view for w in ws]).astype(np.float32)
+        light = np.concatenate([w.light for w in ws]).astype(np.float32)
+        pos[3] = np.nan                                       # invalid, first tile
+        pos[70] = ws[0].aabb_min - 0.25                       # outside the box, second half
+        view[131] = 0.0                                       # invalid, third half
+        light[300 + 65] = [np.inf, 0.0, 0.0]                  # invalid, in the thin cloud
+        pos[450 + 200] = ws[2].aabb_min + np.float32(2.0)     # outside, last ragged tile
+        view[450 + 7] = light[450 + 7] * 3.0                  # view parallel to the light
+        t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+        pos, view, light = t(pos), t(view), t(light)
+        N = int(offsets[-1])
+        net = ds.Net(ctx, K, W, H)
+        net.set_params(synth.init_params(K, W, H, 19, branch_scale=0.5, out_scale=0.2,
+                                         out_bias=0.5))
+        try:
+            # calibrated on valid points of the first cloud
+            ds.ds_net_quantize(ctx.h, net.h, clouds[0].h, ds.DS_PREC_FP8, pos[140:300],
+                               view[140:300], light[140:300])
+            variants = {ds.DS_PREC_BF16: [(0, 4, 0), (0, 4, 3), (0, 8, 0), (1, 4, 0), (2, 4, 0),
+                                          (3, 8, 0), (3, 8, 5)],
+                        ds.DS_PREC_FP8: [(0, 4, 0), (0, 8, 2), (3, 8, 0), (3, 8, 5)]}
+            for prec, vs in variants.items():
+                ref = [[], [], []]
+                for c, a, b in zip(clouds, offsets[:-1], offsets[1:]):
+                    for r, x in zip(ref, ds.ds_predict(ctx.h, c.h, net.h, prec, pos[a:b],
+                                                       view[a:b], light[a:b])):
+                        r.append(x)
+                ref = [torch.cat(r) for r in ref]
+                fl = ref[2].cpu().numpy()
+                assert fl[3] == fl[131] == fl[365] == ds.DS_FLAG_INVALID
+                assert fl[70] & ds.DS_FLAG_OUTSIDE and fl[650] & ds.DS_FLAG_OUTSIDE
+                for order in (ds.DS_ORDER_INPUT, ds.DS_ORDER_SPATIAL):
+                    bt = ds.ds_batch_create(ctx.h, net.h, [c.h for c in clouds], offsets)
+                    try:
+                        ds.ds_batch_set_order(bt, order)
+                        for v in vs:
+                            print("precision", prec, "order", order, "variant", v, flush=True)
+                            ds.ds_batch_set_config(bt, *v)
+                            got = [torch.full((N,), -1.0, device="cuda"),
+                                   torch.full((N,), -1.0, device="cuda"),
+                                   torch.full((N,), 255, dtype=torch.uint8, device="cuda")]
+                            ds.ds_batch_predict(bt, prec, pos, view, light, *got)
+                            for g, r in zip(got, ref):
+                                assert torch.equal(g, r), (prec, order, v)
+                    finally:
+                        ds.ds_batch_destroy(bt)
+        finally:
+            net.close()
+    finally:
+        for c in clouds:
+            c.close()
+
+
 @pytest.fixture(scope="module")
 def paper_width_batch(ctx):
     # the batched configuration's shape at sizes the oracle handles: five BF16 clouds of
