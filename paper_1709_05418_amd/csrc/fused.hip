@@ -1196,6 +1196,27 @@ __device__ __forceinline__ void predict_points(const FusedArgs &a, const FusedCl
     }
 }
 
+// A usable position of point p outside its cloud's grid box (only the clamped pass
+// computes such a point's tile).
+__device__ __forceinline__ bool point_outside(const FusedArgs &a, const FusedCloud &cl, int64_t p,
+                                              bool in)
+{
+    if (!in)
+        return false;
+    const float x0 = a.pos[3 * p], x1 = a.pos[3 * p + 1], x2 = a.pos[3 * p + 2];
+    return isfinite(x0) && isfinite(x1) && isfinite(x2) &&
+           !(x0 >= cl.amin[0] && x0 <= cl.amax[0] && x1 >= cl.amin[1] && x1 <= cl.amax[1] &&
+             x2 >= cl.amin[2] && x2 <= cl.amax[2]);
+}
+
+// The clamped pass screens this many tiles of a workgroup at once: every lane keeps the
+// position loads of its point in all of them in flight together, and one barrier ORs the
+// tiles' needs over the workgroup.  Its grid is persistent and at most kClampGrid
+// workgroups (two per compute unit): launched one workgroup per tile, the pass spent its
+// time dispatching workgroups that only looked at their positions.
+constexpr int kClampBatch = 32;
+constexpr int kClampGrid = 512;
+
 template <int MT, int NW, bool F8, bool CL>
 __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
                                                           const uint4 *__restrict__ frags,
@@ -1205,37 +1226,78 @@ __global__ void __launch_bounds__(64 * NW, 2) k_fused_reg(FusedArgs a,
     __shared__ float4 plane[32];
     __shared__ float2 cols[24];
     __shared__ PtGeom geom[16 * NW];   // per point of the tile, see make_geom
+    __shared__ uint32_t need[3];        // tiles of a screened batch that need this pass
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int g = lane >> 4, n = lane & 15;
+    const int n = tid & 15;
     init_tables(tid, plane, cols);
     WeightStage<MT, NW> ws;
     ws.init(wbuf, tid);
-    // persistent loop over tiles of 16 NW points; a tile never spans two clouds
+    if constexpr (!CL) {
+        // persistent loop over tiles of 16 NW points; a tile never spans two clouds
 #pragma unroll 1
-    for (int64_t v = blockIdx.x; v < a.n_tiles; v += gridDim.x) {
-        const int64_t t = xcd_tile(v, a.n_tiles);
-        // keeps tile-invariant LDS reads (the tables) inside the loop: hoisted, they
-        // would hold registers across the whole tile and force spills
-        asm volatile("" ::: "memory");
-        const FusedCloud &cl = a.cl[tile_cloud(a, t)];
-        if (!CL && !cl.fast)
-            continue;  // uniform: the clamped pass computes this cloud
-        const int64_t pl = (t - cl.tile_begin) * (16 * NW) + (tid >> 6) * 16 + n;
-        const bool in = pl < cl.P;
-        const int64_t p = point_row(a, cl.p_begin + pl, in);
-        bool outside = false;  // a usable position outside the grid box
-        if (in) {
-            const float x0 = a.pos[3 * p], x1 = a.pos[3 * p + 1], x2 = a.pos[3 * p + 2];
-            outside = isfinite(x0) && isfinite(x1) && isfinite(x2) &&
-                      !(x0 >= cl.amin[0] && x0 <= cl.amax[0] && x1 >= cl.amin[1] &&
-                        x1 <= cl.amax[1] && x2 >= cl.amin[2] && x2 <= cl.amax[2]);
+        for (int64_t v = blockIdx.x; v < a.n_tiles; v += gridDim.x) {
+            const int64_t t = xcd_tile(v, a.n_tiles);
+            // keeps tile-invariant LDS reads (the tables) inside the loop: hoisted, they
+            // would hold registers across the whole tile and force spills
+            asm volatile("" ::: "memory");
+            const FusedCloud &cl = a.cl[tile_cloud(a, t)];
+            if (!cl.fast)
+                continue;  // uniform: the clamped pass computes this cloud
+            const int64_t pl = (t - cl.tile_begin) * (16 * NW) + (tid >> 6) * 16 + n;
+            const bool in = pl < cl.P;
+            const int64_t p = point_row(a, cl.p_begin + pl, in);
+            const bool outside = point_outside(a, cl, p, in);
+            ws.begin(frags, tid);
+            predict_points<MT, NW, F8, false>(a, cl, vec, ws, tid, geom[(tid >> 6) * 16 + n],
+                                              plane, cols, p, in, outside);
         }
-        if (CL && cl.fast && !__syncthreads_or(outside))
-            continue;  // uniform: the unclamped pass computed this tile
-        ws.begin(frags, tid);
-        predict_points<MT, NW, F8, CL>(a, cl, vec, ws, tid, geom[(tid >> 6) * 16 + n], plane,
-                                       cols, p, in, outside);
+    } else {
+        // Batch b of the workgroup's tiles ORs its needs into need[b % 3] and reads it after
+        // the barrier; thread 0 then clears need[(b + 2) % 3], whose last readers (batch
+        // b - 1) and next writers (batch b + 2, after the next barrier) are both on the
+        // other side of a barrier.
+        if (tid < 3)
+            need[tid] = 0;
+        __syncthreads();
+        int slot = 0;
+#pragma unroll 1
+        for (int64_t v0 = blockIdx.x; v0 < a.n_tiles; v0 += (int64_t)kClampBatch * gridDim.x) {
+            uint32_t mine = 0;
+#pragma unroll
+            for (int j = 0; j < kClampBatch; ++j) {
+                const int64_t v = v0 + (int64_t)j * gridDim.x;
+                if (v < a.n_tiles) {  // uniform
+                    const FusedCloud &cl = a.cl[tile_cloud(a, xcd_tile(v, a.n_tiles))];
+                    const int64_t pl = (xcd_tile(v, a.n_tiles) - cl.tile_begin) * (16 * NW) +
+                                       (tid >> 6) * 16 + n;
+                    const bool in = pl < cl.P;
+                    if (!cl.fast || point_outside(a, cl, point_row(a, cl.p_begin + pl, in), in))
+                        mine |= 1u << j;
+                }
+            }
+            if (mine)
+                atomicOr(&need[slot], mine);
+            __syncthreads();
+            const uint32_t m = need[slot];
+            if (tid == 0)
+                need[slot == 0 ? 2 : slot - 1] = 0;  // (slot + 2) % 3
+            slot = slot == 2 ? 0 : slot + 1;
+#pragma unroll 1
+            for (int j = 0; j < kClampBatch; ++j) {
+                if (!((m >> j) & 1u))
+                    continue;  // uniform
+                const int64_t t = xcd_tile(v0 + (int64_t)j * gridDim.x, a.n_tiles);
+                asm volatile("" ::: "memory");
+                const FusedCloud &cl = a.cl[tile_cloud(a, t)];
+                const int64_t pl = (t - cl.tile_begin) * (16 * NW) + (tid >> 6) * 16 + n;
+                const bool in = pl < cl.P;
+                const int64_t p = point_row(a, cl.p_begin + pl, in);
+                const bool outside = point_outside(a, cl, p, in);
+                ws.begin(frags, tid);
+                predict_points<MT, NW, F8, true>(a, cl, vec, ws, tid, geom[(tid >> 6) * 16 + n],
+                                                 plane, cols, p, in, outside);
+            }
+        }
     }
 }
 
@@ -1661,17 +1723,18 @@ ds_status launch_kind(hipStream_t s, const ds_net *net, FusedArgs a, int grid)
         return DS_OK;
     const int64_t g = grid > 0 && grid < tiles ? grid : tiles;
     DS_CHECK(g < ((int64_t)1 << 31), DS_ERR_INVALID_ARG, "too many tiles for one launch");
+    const unsigned gc = (unsigned)std::min<int64_t>(g, kClampGrid);  // the clamped pass
     if constexpr (F8) {
         static_assert(KIND == DS_KERNEL_REGISTER, "the FP8 form has the register kernel only");
         k_fused_reg<MT, NW, true, false><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_fp8, net->vec8);
-        k_fused_reg<MT, NW, true, true><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_fp8, net->vec8);
+        k_fused_reg<MT, NW, true, true><<<gc, 64 * NW, 0, s>>>(a, net->frag_fp8, net->vec8);
     } else if constexpr (KIND == DS_KERNEL_PIPELINED) {
         k_fused<MT, NW><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_bf16, net->vec);
     } else if constexpr (KIND == DS_KERNEL_WIDE) {
         k_fused_wide<MT, NW><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_bf16, net->vec);
     } else {
         k_fused_reg<MT, NW, false, false><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_bf16, net->vec);
-        k_fused_reg<MT, NW, false, true><<<(unsigned)g, 64 * NW, 0, s>>>(a, net->frag_bf16, net->vec);
+        k_fused_reg<MT, NW, false, true><<<gc, 64 * NW, 0, s>>>(a, net->frag_bf16, net->vec);
     }
     DS_HIP(hipGetLastError());
     return DS_OK;
@@ -1694,7 +1757,8 @@ ds_status launch_teams(hipStream_t s, const ds_net *net, FusedArgs a, int grid)
     DS_CHECK(g4 < ((int64_t)1 << 31) && nc % 2 == 0, DS_ERR_INVALID_ARG,
              "two-team launch: %lld tiles, %d chunks per tile", (long long)tiles4, nc);
     k_fused_teams<MT, F8><<<(unsigned)g, 512, 0, s>>>(a, frags, vec, nc);
-    k_fused_reg<MT, 4, F8, true><<<(unsigned)g4, 256, 0, s>>>(a4, frags, vec);
+    k_fused_reg<MT, 4, F8, true><<<(unsigned)std::min<int64_t>(g4, kClampGrid), 256, 0, s>>>(
+        a4, frags, vec);
     DS_HIP(hipGetLastError());
     return DS_OK;
 }
