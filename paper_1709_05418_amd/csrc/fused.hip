@@ -1337,13 +1337,7 @@ __global__ void __launch_bounds__(512, 2) k_fused_teams(FusedArgs a,
         const int64_t pl = (t - cl.tile_begin) * 128 + (tid >> 6) * 16 + n;
         const bool in = pl < cl.P;
         const int64_t p = point_row(a, cl.p_begin + pl, in);
-        bool outside = false;
-        if (in) {
-            const float x0 = a.pos[3 * p], x1 = a.pos[3 * p + 1], x2 = a.pos[3 * p + 2];
-            outside = isfinite(x0) && isfinite(x1) && isfinite(x2) &&
-                      !(x0 >= cl.amin[0] && x0 <= cl.amax[0] && x1 >= cl.amin[1] &&
-                        x1 <= cl.amax[1] && x2 >= cl.amin[2] && x2 <= cl.amax[2]);
-        }
+        const bool outside = point_outside(a, cl, p, in);
         predict_points<MT, 8, F8, false>(a, cl, vec, ws, tid, geom[(tid >> 6) * 16 + n], plane,
                                          cols, p, in, outside);
     }
