@@ -9,6 +9,7 @@ namespace {
 
 constexpr int BM = 64, BN = 64, BK = 32;
 constexpr int NF = BK / 4;  // elements of each operand a thread stages per k step
+typedef float f4v __attribute__((ext_vector_type(4)));
 
 // One operand's share of a k step of the FP32 GEMM: NF values of one row (m of A, n of B)
 // at k = k0 + kq + j with unit k stride (kc), else at k = k0 + kq + 4 j, zero outside.
@@ -55,22 +56,32 @@ __device__ __forceinline__ StageF stage_f(const float *base, int64_t s_row, int6
 }
 
 // C[m][n] (+)= sum_k A(m, k) B(k, n) with A(m, k) = A[m sam + k sak] and
-// B(k, n) = B[k sbk + n sbn], in FP32 on the vector units: a 64 x 64 tile per block,
-// 4 x 4 outputs per thread.  Operands are read along their contiguous index and the
-// next k step is prefetched into registers.  Split s (blockIdx.z) covers k in
+// B(k, n) = B[k sbk + n sbn], in FP32 on the matrix cores (v_mfma_f32_16x16x4_f32): a
+// 64 x 64 tile per block, each wave a 32 x 32 quarter as 2 x 2 products of 16 x 16 (lane
+// l supplies A(row l % 16, k l / 16) and B(k l / 16, column l % 16) and holds C(rows
+// 4 (l / 16) .. + 3, column l % 16)).  Operands are read along their contiguous index and
+// the next k step is prefetched into registers.  Split s (blockIdx.z) covers k in
 // [s kc, (s+1) kc) in order; several splits write partial tiles to P[s][M][N], which
 // k_splitk_sum adds in split order, so every result is reproducible.
 __global__ void __launch_bounds__(256) k_gemm_strided(StridedGemm g, int kc, float *P)
 {
     __shared__ float As[BK][BM + 4];
     __shared__ float Bs[BK][BN + 4];
-    const int t = threadIdx.x, tx = t % 16, ty = t / 16;
+    const int t = threadIdx.x;
+    const int lane = t & 63, w = t >> 6;
+    const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+    const int li = lane & 15, lk = lane >> 4;
     const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
     const int kbeg = blockIdx.z * kc;
     const int kend = min(g.K, kbeg + kc);
     const StageF sa = stage_f(g.A, g.sam, g.sak, m0, g.M, kbeg, t);
     const StageF sb = stage_f(g.B, g.sbn, g.sbk, n0, g.N, kbeg, t);
-    float acc[4][4] = {};
+    f4v acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+            acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
     float va[NF], vb[NF];
     if (kbeg < kend) {
         sa.load(kbeg, kend, va);
@@ -85,39 +96,38 @@ __global__ void __launch_bounds__(256) k_gemm_strided(StridedGemm g, int kc, flo
             sb.load(k0 + BK, kend, vb);
         }
 #pragma unroll
-        for (int kk = 0; kk < BK; ++kk) {
-            float a[4], b[4];
+        for (int ks = 0; ks < BK; ks += 4) {
+            float x[2], y[2];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                a[i] = As[kk][ty * 4 + i];
-                b[i] = Bs[kk][tx * 4 + i];
+            for (int i = 0; i < 2; ++i) {
+                x[i] = As[ks + lk][wm + 16 * i + li];
+                y[i] = Bs[ks + lk][wn + 16 * i + li];
             }
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] += a[i] * b[j];
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[i], y[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int m = m0 + ty * 4 + i;
-        if (m >= g.M)
-            continue;
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int n = n0 + tx * 4 + j;
-            if (n >= g.N)
-                continue;
-            if (P) {
-                P[((int64_t)blockIdx.z * g.M + m) * g.N + n] = acc[i][j];
-            } else {
-                float *c = g.C + (int64_t)m * g.ldc + n;
-                *c = g.accumulate ? *c + acc[i][j] : acc[i][j];
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int m = m0 + wm + 16 * i + 4 * lk + v;
+                const int n = n0 + wn + 16 * j + li;
+                if (m >= g.M || n >= g.N)
+                    continue;
+                if (P) {
+                    P[((int64_t)blockIdx.z * g.M + m) * g.N + n] = acc[i][j][v];
+                } else {
+                    float *c = g.C + (int64_t)m * g.ldc + n;
+                    *c = g.accumulate ? *c + acc[i][j][v] : acc[i][j][v];
+                }
             }
-        }
-    }
 }
 
 // x[r][c] *= (pre[r][c] > 0) for an [R][C] block with row strides.
