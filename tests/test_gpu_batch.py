@@ -266,8 +266,9 @@ def test_variants_orders_with_a_clamped_cloud_and_invalid_points(ctx):
     # a cloud's chunks idle, and its clamped pass recomputes 64-point halves of its 128-point
     # tiles.  A batch with a thin cloud between two dense ones and invalid points in ragged
     # tiles: every variant in both point orders, bitwise the per-cloud default launches
-    # (outputs, pre-activations and flags), BF16 and FP8.
-    specs = [(32, 32.0, 300, 81), (24, 0.5, 150, 82), (40, 40.0, 260, 83)]
+    # (outputs, pre-activations and flags), BF16 and FP8.  With 55 tiles of 64 points and a
+    # grid of one workgroup, the clamped pass screens its tiles in two batches of 32.
+    specs = [(32, 32.0, 1300, 81), (24, 0.5, 900, 82), (40, 40.0, 1260, 83)]
     ws, clouds = [], []
     try:
         for n, sig, P, seed in specs:
@@ -283,9 +284,9 @@ def test_variants_orders_with_a_clamped_cloud_and_invalid_points(ctx):
         pos[3] = np.nan                                       # invalid, first tile
         pos[70] = ws[0].aabb_min - 0.25                       # outside the box, second half
         view[131] = 0.0                                       # invalid, third half
-        light[300 + 65] = [np.inf, 0.0, 0.0]                  # invalid, in the thin cloud
-        pos[450 + 200] = ws[2].aabb_min + np.float32(2.0)     # outside, last ragged tile
-        view[450 + 7] = light[450 + 7] * 3.0                  # view parallel to the light
+        light[1300 + 65] = [np.inf, 0.0, 0.0]                 # invalid, in the thin cloud
+        pos[2200 + 1200] = ws[2].aabb_min + np.float32(2.0)   # outside, second batch of tiles
+        view[2200 + 7] = light[2200 + 7] * 3.0                # view parallel to the light
         t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
         pos, view, light = t(pos), t(view), t(light)
         N = int(offsets[-1])
@@ -296,9 +297,9 @@ def test_variants_orders_with_a_clamped_cloud_and_invalid_points(ctx):
             # calibrated on valid points of the first cloud
             ds.ds_net_quantize(ctx.h, net.h, clouds[0].h, ds.DS_PREC_FP8, pos[140:300],
                                view[140:300], light[140:300])
-            variants = {ds.DS_PREC_BF16: [(0, 4, 0), (0, 4, 3), (0, 8, 0), (1, 4, 0), (2, 4, 0),
-                                          (3, 8, 0), (3, 8, 5)],
-                        ds.DS_PREC_FP8: [(0, 4, 0), (0, 8, 2), (3, 8, 0), (3, 8, 5)]}
+            variants = {ds.DS_PREC_BF16: [(0, 4, 0), (0, 4, 1), (0, 4, 3), (0, 8, 0), (1, 4, 0),
+                                          (2, 4, 0), (3, 8, 0), (3, 8, 1), (3, 8, 5)],
+                        ds.DS_PREC_FP8: [(0, 4, 0), (0, 4, 1), (0, 8, 2), (3, 8, 0), (3, 8, 5)]}
             for prec, vs in variants.items():
                 ref = [[], [], []]
                 for c, a, b in zip(clouds, offsets[:-1], offsets[1:]):
@@ -307,8 +308,8 @@ def test_variants_orders_with_a_clamped_cloud_and_invalid_points(ctx):
                         r.append(x)
                 ref = [torch.cat(r) for r in ref]
                 fl = ref[2].cpu().numpy()
-                assert fl[3] == fl[131] == fl[365] == ds.DS_FLAG_INVALID
-                assert fl[70] & ds.DS_FLAG_OUTSIDE and fl[650] & ds.DS_FLAG_OUTSIDE
+                assert fl[3] == fl[131] == fl[1365] == ds.DS_FLAG_INVALID
+                assert fl[70] & ds.DS_FLAG_OUTSIDE and fl[3400] & ds.DS_FLAG_OUTSIDE
                 for order in (ds.DS_ORDER_INPUT, ds.DS_ORDER_SPATIAL):
                     bt = ds.ds_batch_create(ctx.h, net.h, [c.h for c in clouds], offsets)
                     try:
