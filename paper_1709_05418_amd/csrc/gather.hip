@@ -46,7 +46,7 @@ __device__ __forceinline__ float trilinear_cells(const GatherLevel &L, float ux,
     return fmaf(fz, b1 - b0, b0);
 }
 
-constexpr int kGatherPts = 2;  // shading points per workgroup
+constexpr int kGatherPts = 64;  // shading points per workgroup, one per lane of each wave
 
 // Lattice geometry of one point at one stencil level, in cell coordinates:
 // lattice point (ix, iy, iz) sits at u0 + ix a + iy b + iz c.
@@ -54,115 +54,74 @@ struct LatticeGeom {
     float u0[3], a[3], b[3], c[3];
 };
 
-size_t gather_lds_bytes(int K)
-{
-    return sizeof(float) * (size_t)kGatherPts * (kStencil * K + 1) +
-           sizeof(LatticeGeom) * (size_t)kGatherPts * K;
-}
-
-// kGatherPts points per workgroup.  One thread per (point, level) sets up the lattice
-// geometry; one thread per (point, level, stencil column (ix, iy)) then walks the nine
-// samples iz = 0..8 of that column into the points' rows staged in LDS; the rows leave
-// in coalesced stores (one linear run when the rows are contiguous).
+// kGatherPts points per workgroup, lane l of every wave on point l.  For each stencil level
+// the four waves split the 25 columns (ix, iy) (wave w takes the columns c = w mod 4) and
+// each lane walks the nine samples iz = 0..8 of a column of its point, so the 64 addresses
+// of a load are the same lattice offset of 64 neighbouring points, which share cache lines
+// when the points do (points in camera order); the level's 225 values per point are staged
+// in LDS and leave as one contiguous run per point.
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_gather(GatherArgs a, int64_t p0, int64_t np, T *z,
                                                      int64_t ldz, uint8_t *flags)
 {
-    extern __shared__ float smem[];
-    __shared__ int ok_s[kGatherPts];
+    __shared__ float rows[kGatherPts * kStencil];  // one level: [point][25 iz + column]
     const int K = a.K, D = kStencil * K + 1, tid = threadIdx.x;
-    float *rows = smem;
-    LatticeGeom *geo = reinterpret_cast<LatticeGeom *>(smem + kGatherPts * D);
+    const int lane = tid & 63, w = tid >> 6;
     const int64_t pb = (int64_t)blockIdx.x * kGatherPts;  // first point (chunk-relative)
-    if (tid < kGatherPts * K) {
-        const int i = tid / K, k = tid - i * K;
-        const int64_t pl = pb + i;
+    const int64_t pl = pb + lane;
+    const int n = (int)(np - pb < kGatherPts ? np - pb : kGatherPts);
+    float x[3] = {0.f, 0.f, 0.f};
+    Frame f = {};
+    bool ok = false;
+    if (pl < np) {
+        const int64_t p = p0 + pl;
+        x[0] = a.pos[3 * p];
+        x[1] = a.pos[3 * p + 1];
+        x[2] = a.pos[3 * p + 2];
+        ok = isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) &&
+             light_frame(&a.view[3 * p], &a.light[3 * p], f);
+        if (w == 0) {
+            store<T>(z, pl * ldz + (D - 1), ok ? f.gamma : 0.f);
+            if (flags)
+                flags[p] = ok ? point_flags(x, f, a.amin, a.amax, a.inv_mean)
+                              : (uint8_t)DS_FLAG_INVALID;
+        }
+    }
+    for (int k = 0; k < K; ++k) {
+        const GatherLevel L = a.lv[k];
         LatticeGeom G = {};
-        bool ok = false;
-        float gamma = 0.f;
-        if (pl < np) {
-            const int64_t p = p0 + pl;
-            const float x[3] = {a.pos[3 * p], a.pos[3 * p + 1], a.pos[3 * p + 2]};
-            Frame f;
-            ok = isfinite(x[0]) && isfinite(x[1]) && isfinite(x[2]) &&
-                 light_frame(&a.view[3 * p], &a.light[3 * p], f);
-            if (ok) {
-                const GatherLevel L = a.lv[k];
-                const float hs = 0.5f * L.step * L.inv_h;  // half a lattice unit, in voxels
+        if (ok) {
+            const float hs = 0.5f * L.step * L.inv_h;  // half a lattice unit, in voxels
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    // lattice point (0, 0, 0) has offset (-1, -1, -1) mean free paths
-                    const float q = x[c] - L.step * (f.X[c] + f.Y[c] + f.Z[c]);
-                    G.u0[c] = (q - a.amin[c]) * L.inv_h + 0.5f;
-                    G.a[c] = hs * f.X[c];
-                    G.b[c] = hs * f.Y[c];
-                    G.c[c] = hs * f.Z[c];
-                }
-                gamma = f.gamma;
-            }
-            if (k == 0) {
-                rows[i * D + D - 1] = gamma;
-                if (flags)
-                    flags[p] = ok ? point_flags(x, f, a.amin, a.amax, a.inv_mean)
-                                  : (uint8_t)DS_FLAG_INVALID;
+            for (int c = 0; c < 3; ++c) {
+                // lattice point (0, 0, 0) has offset (-1, -1, -1) mean free paths
+                const float q = x[c] - L.step * (f.X[c] + f.Y[c] + f.Z[c]);
+                G.u0[c] = (q - a.amin[c]) * L.inv_h + 0.5f;
+                G.a[c] = hs * f.X[c];
+                G.b[c] = hs * f.Y[c];
+                G.c[c] = hs * f.Z[c];
             }
         }
-        geo[i * K + k] = G;
-        if (k == 0)
-            ok_s[i] = ok;
-    }
-    __syncthreads();
-    const int items = kGatherPts * K * 25;
-    for (int it = tid; it < items; it += kThreads) {
-        const int i = it / (K * 25), r = it - i * (K * 25);
-        const int k = r / 25, col = r - k * 25;
-        float *out = rows + i * D + k * kStencil + col;
-        if (!ok_s[i]) {
+        float *out = rows + lane * kStencil;
+        for (int col = w; col < 25; col += 4) {
+            const float ix = (float)(col % 5), iy = (float)(col / 5);
+            float ub[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                ub[c] = fmaf(iy, G.b[c], fmaf(ix, G.a[c], G.u0[c]));
 #pragma unroll
             for (int iz = 0; iz < 9; ++iz)
-                out[25 * iz] = 0.f;
-            continue;
+                out[25 * iz + col] = ok ? trilinear_cells(L, fmaf((float)iz, G.c[0], ub[0]),
+                                                          fmaf((float)iz, G.c[1], ub[1]),
+                                                          fmaf((float)iz, G.c[2], ub[2]))
+                                        : 0.f;
         }
-        const LatticeGeom G = geo[i * K + k];
-        const GatherLevel L = a.lv[k];
-        const float ix = (float)(col % 5), iy = (float)(col / 5);
-        float ub[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            ub[c] = fmaf(iy, G.b[c], fmaf(ix, G.a[c], G.u0[c]));
-#pragma unroll
-        for (int iz = 0; iz < 9; ++iz)
-            out[25 * iz] = trilinear_cells(L, fmaf((float)iz, G.c[0], ub[0]),
-                                            fmaf((float)iz, G.c[1], ub[1]),
-                                            fmaf((float)iz, G.c[2], ub[2]));
-    }
-    __syncthreads();
-    const int n = (int)(np - pb < kGatherPts ? np - pb : kGatherPts);
-    if (ldz == D) {
-        T *dst = z + pb * D;
-        const int len = n * D;
-        if constexpr (sizeof(T) == 4) {
-            // 16-byte stores from the first 16-byte boundary on; head and tail singly
-            const int head = (int)((16 - (reinterpret_cast<uintptr_t>(dst) & 15)) & 15) / 4;
-            const int h = head < len ? head : len;
-            if (tid < h)
-                store<T>(dst, tid, rows[tid]);
-            const int nv = (len - h) / 4;
-            float4 *dv = reinterpret_cast<float4 *>(dst + h);
-            for (int j = tid; j < nv; j += kThreads) {
-                const float *r = rows + h + 4 * j;
-                dv[j] = make_float4(r[0], r[1], r[2], r[3]);
-            }
-            for (int j = h + 4 * nv + tid; j < len; j += kThreads)
-                store<T>(dst, j, rows[j]);
-        } else {
-            for (int j = tid; j < len; j += kThreads)
-                store<T>(dst, j, rows[j]);
+        __syncthreads();
+        for (int e = tid; e < n * kStencil; e += kThreads) {
+            const int i = e / kStencil, j = e - i * kStencil;
+            store<T>(z, (pb + i) * ldz + (int64_t)k * kStencil + j, rows[e]);
         }
-    } else {
-        for (int i = 0; i < n; ++i)
-            for (int j = tid; j < D; j += kThreads)
-                store<T>(z + (pb + i) * ldz, j, rows[i * D + j]);
+        __syncthreads();
     }
 }
 
@@ -195,12 +154,11 @@ ds_status gather_plain(hipStream_t s, const GatherArgs &a, int64_t p0, int64_t n
     if (np <= 0)
         return DS_OK;
     const int64_t blocks = (np + kGatherPts - 1) / kGatherPts;
-    const size_t lds = gather_lds_bytes(a.K);
     if (odt == DS_F32)
-        k_gather<float><<<(unsigned)blocks, kThreads, lds, s>>>(a, p0, np, (float *)z, ldz, flags);
+        k_gather<float><<<(unsigned)blocks, kThreads, 0, s>>>(a, p0, np, (float *)z, ldz, flags);
     else
-        k_gather<uint16_t><<<(unsigned)blocks, kThreads, lds, s>>>(a, p0, np, (uint16_t *)z, ldz,
-                                                                   flags);
+        k_gather<uint16_t><<<(unsigned)blocks, kThreads, 0, s>>>(a, p0, np, (uint16_t *)z, ldz,
+                                                                 flags);
     DS_HIP(hipGetLastError());
     return DS_OK;
 }
