@@ -266,9 +266,11 @@ ds_status ds_batch_predict(ds_batch *batch, ds_precision precision, const float 
                            float *pre_out, uint8_t *flags);
 /* Times every available variant (kernel x waves x grid in {one per tile, 1, 2, 4
  * workgroups per compute unit}; for DS_PREC_FP8 the register and two-team kernels') on
- * these arrays, `reps` launches each after one
- * warm-up, keeps the fastest and drops a captured graph.  Synchronises; writes
- * out.  Results depend on the arrays' contents only through timing. */
+ * these arrays: one warm-up launch each, then three rounds that time `reps` launches of
+ * every variant in turn; a variant's time is its fastest round (the rounds interleave, so
+ * a clock that drifts during the sweep favours no variant).  Keeps the fastest variant and
+ * drops a captured graph.  Synchronises; writes out.  Results depend on the arrays'
+ * contents only through timing. */
 ds_status ds_batch_autotune(ds_batch *batch, ds_precision precision, const float *pos,
                             const float *view_dir, const float *light_dir, float *out, int reps);
 /* Records the plan's launch for these arrays into a HIP graph (captured on a

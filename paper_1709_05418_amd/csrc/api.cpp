@@ -1612,8 +1612,13 @@ ds_status ds_batch_autotune(ds_batch *b, ds_precision precision, const float *po
         return hip_fail(hipErrorOutOfMemory, "ds_batch_autotune: event");
     }
     ds_status st = DS_OK;
-    float best = -1.f;
-    FusedVariant bestv = {b->kind, b->waves, b->grid};
+    // the candidates, each warmed up once; then kTuneRounds interleaved rounds of reps
+    // launches per candidate, keeping each candidate's fastest round, so that a clock that
+    // drifts during the sweep does not favour the candidates timed last
+    constexpr int kTuneRounds = 3;
+    FusedVariant cand[32];
+    float tbest[32];
+    int nc = 0;
     const int grids[4] = {0, cus, 2 * cus, 4 * cus};
     for (int kind = 0; kind < 4 && !st; ++kind)
         for (int waves = 4; waves <= 8 && !st; waves += 4)
@@ -1624,30 +1629,38 @@ ds_status ds_batch_autotune(ds_batch *b, ds_precision precision, const float *po
                     continue;
                 st = batch_fused(b, s, precision, pos, view_dir, light_dir, out, nullptr, nullptr,
                                  v);
-                if (st)
-                    break;
-                hipError_t e = hipEventRecord(e0, s);
-                for (int r = 0; r < reps && !st && e == hipSuccess; ++r)
-                    st = batch_fused(b, s, precision, pos, view_dir, light_dir, out, nullptr,
-                                     nullptr, v);
-                if (e == hipSuccess)
-                    e = hipEventRecord(e1, s);
-                if (e == hipSuccess)
-                    e = hipEventSynchronize(e1);
-                float ms = 0.f;
-                if (e == hipSuccess)
-                    e = hipEventElapsedTime(&ms, e0, e1);
-                if (e != hipSuccess && !st)
-                    st = hip_fail(e, "ds_batch_autotune");
-                if (!st && (best < 0.f || ms / reps < best)) {
-                    best = ms / reps;
-                    bestv = v;
-                }
+                cand[nc] = v;
+                tbest[nc++] = -1.f;
             }
+    for (int round = 0; round < kTuneRounds && !st; ++round)
+        for (int c = 0; c < nc && !st; ++c) {
+            hipError_t e = hipEventRecord(e0, s);
+            for (int r = 0; r < reps && !st && e == hipSuccess; ++r)
+                st = batch_fused(b, s, precision, pos, view_dir, light_dir, out, nullptr, nullptr,
+                                 cand[c]);
+            if (e == hipSuccess)
+                e = hipEventRecord(e1, s);
+            if (e == hipSuccess)
+                e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess)
+                e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess && !st)
+                st = hip_fail(e, "ds_batch_autotune");
+            if (!st && (tbest[c] < 0.f || ms / reps < tbest[c]))
+                tbest[c] = ms / reps;
+        }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st)
         return st;
+    float best = -1.f;
+    FusedVariant bestv = {b->kind, b->waves, b->grid};
+    for (int c = 0; c < nc; ++c)
+        if (best < 0.f || tbest[c] < best) {
+            best = tbest[c];
+            bestv = cand[c];
+        }
     b->kind = bestv.kind;
     b->waves = bestv.waves;
     b->grid = bestv.grid;
