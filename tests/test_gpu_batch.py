@@ -135,7 +135,8 @@ def test_autotune_then_graph_replay(ctx, setup):
         eager = torch.empty(N, dtype=torch.float32, device="cuda")
         ds.ds_batch_predict(b, ds.DS_PREC_BF16, s["pos"], s["view"], s["light"], eager)
         cfg = ds.ds_batch_autotune(b, ds.DS_PREC_BF16, s["pos"], s["view"], s["light"], eager, 2)
-        assert cfg["ms"] > 0 and cfg["waves"] in (4, 8) and cfg["kernel"] in (0, 1, 2)
+        # any available variant may win on timing, the two-team kernel (3) included
+        assert cfg["ms"] > 0 and cfg["waves"] in (4, 8) and cfg["kernel"] in (0, 1, 2, 3)
         out = torch.full((N,), -1.0, device="cuda")
         pos = s["pos"].clone()
         ds.ds_batch_capture(b, ds.DS_PREC_BF16, pos, s["view"], s["light"], out)
