@@ -412,9 +412,6 @@ static ds_status mlp_loss_grad(ds_net *net, const float *z, const float *target,
     const bool bf = net->train_prec == DS_PREC_BF16;
     const std::vector<int> &wd = net->mlp_widths;
     const int L = (int)wd.size() - 1, D = wd[0], Wm = net->W;
-    size_t act = 0;
-    for (int l = 1; l <= L; ++l)
-        act += (size_t)B * wd[l];
     size_t split = (size_t)16 * Wm * 226;
     const size_t csum = (size_t)colsum_scratch(Wm);
     split = split > csum ? split : csum;

@@ -86,7 +86,7 @@ __global__ void __launch_bounds__(256) k_scan_block(int32_t *__restrict__ counts
     __syncthreads();
     // inclusive scan of the 256 thread sums (Hillis-Steele)
     for (int d = 1; d < 256; d <<= 1) {
-        const int32_t t = threadIdx.x >= d ? part[threadIdx.x - d] : 0;
+        const int32_t t = (int)threadIdx.x >= d ? part[threadIdx.x - d] : 0;
         __syncthreads();
         part[threadIdx.x] += t;
         __syncthreads();

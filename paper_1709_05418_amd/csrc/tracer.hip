@@ -711,7 +711,7 @@ __global__ void __launch_bounds__(256) k_max(const float *x, int64_t n, float *o
     s[threadIdx.x] = m;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
+        if ((int)threadIdx.x < w)
             s[threadIdx.x] = fmaxf(s[threadIdx.x], s[threadIdx.x + w]);
         __syncthreads();
     }

@@ -211,7 +211,7 @@ __global__ void __launch_bounds__(256) k_loss_mean(const float *sq, int B, float
     s[threadIdx.x] = acc;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w)
+        if ((int)threadIdx.x < w)
             s[threadIdx.x] += s[threadIdx.x + w];
         __syncthreads();
     }
