@@ -11,7 +11,8 @@ What each part follows in the paper and what pins it (tests/test_oracle_*.py):
                                                             fields, impulse response, unit mass
   frame           Sec. 4.2 local frame, gamma               closed form (0, sin g, cos g), det +1
   gather          Sec. 4.2 / Fig. 5 hierarchical stencil    affine-field exactness, constant grid,
-                                                            cube-rotation invariance, axial symmetry
+                                                            cube-rotation invariance, axial symmetry,
+                                                            fall-back flag at known face distances
   forward         Sec. 4.3 / Fig. 6 progressive residual    numpy matmul, bias-only closed form,
                   blocks + trailing layers                  hand-computed K=1, W=2 case
   loss_grad       Sec. 5.2 loss and its gradient            central finite differences
@@ -19,7 +20,9 @@ What each part follows in the paper and what pins it (tests/test_oracle_*.py):
   philox          Salmon et al. 2011                        published known-answer vectors
   trace_li etc.   Sec. 3.2 Eq. 1, Sec. 4, Sec. 4.4, 5.1     slab transmittance, furnace, sphere
                                                             closed form, single-scatter quadrature,
-                                                            HG moments and CDF
+                                                            HG moments and CDF, transmittance
+                                                            across a density profile (interpolated
+                                                            value between voxel centres)
   first_hits      Sec. 4.4 camera sample: first collision   homogeneous box: hit fraction
                   and direct single scattering              1 - exp(-sigma L), direct term against
                                                             albedo p exp(-sigma s) E
@@ -27,7 +30,9 @@ What each part follows in the paper and what pins it (tests/test_oracle_*.py):
   adaptive        95 %), Sec. 7 target L_s = L_d + L_i      path count, rule fails one batch
                                                             earlier; L_s - L_i against the direct
                                                             closed form, L_s furnace = E exactly
-  light_table,    Sec. 4.4 distant emitter as directional   p_j w_j = E_j exactly, all 2^24 draws
+  light_table,    Sec. 4.4 distant emitter as directional   p_j w_j = E_j exactly, thresholds within
+                                                            1/2 of the exact running fraction, all
+                                                            2^24 draws
   *_lights        lights, one drawn per estimate            counted, homogeneous-box closed form,
                                                             one-light set = directional renderer,
                                                             linearity in the lights
@@ -40,9 +45,16 @@ What each part follows in the paper and what pins it (tests/test_oracle_*.py):
                   function at the first collision when      homogeneous box the chopped set-up's
                   rendering                                 first-collision pixel equals the full
                                                             function's single-scattering integral
-                                                            (quadrature), f -> 0 gives the full one
+                                                            (quadrature), f -> 0 gives the full one;
+                                                            coarse tables: linear-in-theta lookup
+                                                            read back exactly, drawn angles invert
+                                                            the piecewise-linear cdf (quadrature)
   e4m3_encode     OCP 8-bit floating point, E4M3 format     torch.float8_e4m3fn cast, hand values,
                   (round to nearest even, saturating)       decode/encode round trip of every code
+
+That the pins can see a mistake is itself tested: tests/test_oracle_mutants.py plants one
+plausible mistake at a time in a copy of this package (46 of them, across every part
+above) and requires a pin to fail for each.
 """
 from __future__ import annotations
 
@@ -109,6 +121,7 @@ def lib():
                                    P, P]),
             "dso_set_phase": (None, [I, P, P, D, I, P, P, D]),
             "dso_tab_sample": (D, [I, P, P, D]),
+            "dso_tab_eval": (D, [I, P, D]),
             "dso_render_pixels_lights": (I, [P, I, I, I, I, D, P, D, D, D, D, I, I, P, P, P, P, P,
                                              I64, I, U64, P, P]),
             "dso_first_hits_lights": (I, [P, I, I, I, I, D, P, D, D, D, D, I, P, P, P, I, P, P,
@@ -484,6 +497,14 @@ def set_phase(table=None, first=None):
         return [a.size, _p(a), _p(b), float(t.get("removed", 0.0))]
 
     L.dso_set_phase(*args(table), *args(first))
+
+
+def tab_eval(p, mu):
+    """p(mu) the tracer reads from the values p at theta_i = i pi / (n - 1)."""
+    a = np.ascontiguousarray(p, np.float64)
+    if a.size < 2:
+        raise ValueError("a table needs at least two values")
+    return lib().dso_tab_eval(a.size, _p(a), float(mu))
 
 
 def tab_sample(table, u):

@@ -983,6 +983,14 @@ static double tab_eval(const phase_tab *t, double mu)
     return t->p[i] + f * (t->p[i + 1] - t->p[i]);
 }
 
+/* The table's p(mu), as the tracer reads it, for a table of n >= 2 values at
+ * theta_i = i pi / (n - 1). */
+double dso_tab_eval(int n, const double *p, double mu)
+{
+    phase_tab t = {n, M_PI / (n - 1), (double *)p, NULL};
+    return tab_eval(&t, mu);
+}
+
 /* cos(theta) drawn from the table: the node interval by the cumulative distribution,
  * then theta inside it from the density linear between the nodes' p sin(theta). */
 double dso_tab_sample(int n, const double *p, const double *cdf, double u)

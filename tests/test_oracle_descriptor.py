@@ -231,3 +231,25 @@ def test_gather_flags_invalid_and_outside():
     assert np.all(z[:3] == 0)
     assert fl[3] & O.FLAG_OUTSIDE and fl[3] & O.FLAG_FALLBACK
     assert fl[4] == O.FLAG_FALLBACK  # inside, but the level-1 box crosses the face x = 0.5
+
+
+def test_fallback_flag_follows_the_level1_box_extents():
+    # light along +z, view along +x: the level-1 stencil box spans one mean free path
+    # (0.1 here) either side of the point across the light and from one behind to three
+    # ahead along it (Sec. 4.2, Fig. 5); the grid box is [-0.5, 0.5]^3.  Points at known
+    # distances from one face each: the flag is set exactly when that face is nearer than
+    # the box's reach towards it.
+    n, L, K = 16, 3, 2
+    g, pyr, dims, offs = _setup_grid(n, L, lambda x, y, z: np.ones_like(x))
+    mips = np.array([0, 1], np.int32)
+    cases = [  # (position, fallback expected)
+        ([0, 0, 0.5 - 0.35], False), ([0, 0, 0.5 - 0.25], True), ([0, 0, 0.5 - 0.05], True),
+        ([0, 0, -0.5 + 0.15], False), ([0, 0, -0.5 + 0.05], True),
+        ([0.5 - 0.15, 0, 0], False), ([0.5 - 0.05, 0, 0], True),
+        ([0, -0.5 + 0.15, 0], False), ([0, -0.5 + 0.05, 0], True), ([0, 0, 0], False),
+    ]
+    pos = np.array([c[0] for c in cases], np.float32)
+    view = np.tile(np.array([1, 0, 0], np.float32), (len(cases), 1))
+    light = np.tile(np.array([0, 0, 1], np.float32), (len(cases), 1))
+    _, fl = O.gather(g, pyr, dims, offs, 10.0, K, mips, pos, view, light)
+    assert fl.tolist() == [O.FLAG_FALLBACK if c[1] else 0 for c in cases]

@@ -5,6 +5,7 @@ and the path-traced pixels against the directional renderer by linearity in the 
 CPU only."""
 import math
 import os
+from fractions import Fraction
 
 import numpy as np
 import pytest
@@ -33,6 +34,17 @@ def test_table_is_an_unbiased_selection(E):
     q = E / E.sum()
     big = q > 4 * E.size / 2.0 ** 24
     assert np.all(np.abs(p[big] - q[big]) <= E.size / 2.0 ** 24)
+    # each threshold is the running fraction times 2^24 rounded to nearest: within 1/2 of
+    # the exact value (rational arithmetic on the FP64 inputs; the FP64 running sum adds at
+    # most a few 1e-6) wherever neither minimum-step clamp can apply
+    S = sum(Fraction(float(e)) for e in E)
+    run, m, prev = Fraction(0), E.size, 0
+    for j in range(m):
+        run += Fraction(float(E[j]))
+        x = run / S * (1 << 24)
+        if prev + 1.5 <= x <= (1 << 24) - (m - 1 - j) - 0.5:
+            assert abs(t[j] - x) <= 0.5 + 1e-5, (j, t[j], float(x))
+        prev = t[j]
 
 
 def test_pick_counts_every_24_bit_value():

@@ -57,6 +57,42 @@ def test_hg_table_moments_and_sampling(g):
     np.testing.assert_allclose(mus[::97], ref, atol=5e-3)
 
 
+def test_table_lookup_is_linear_in_theta_between_nodes():
+    # a table sampled from a function linear in theta is read back exactly between its
+    # nodes, and any table is read back at its nodes (coarse, so that a lookup that does
+    # not interpolate is far off)
+    n = 7
+    theta = np.linspace(0, math.pi, n)
+    rng = np.random.default_rng(5)
+    for th in np.concatenate([rng.uniform(0, math.pi, 60), theta]):
+        assert O.tab_eval(0.3 + 0.5 * theta, math.cos(th)) == pytest.approx(0.3 + 0.5 * th,
+                                                                         rel=1e-7)
+    p = rng.uniform(0.1, 2.0, n)
+    for i, th in enumerate(theta):
+        assert O.tab_eval(p, math.cos(th)) == pytest.approx(p[i], rel=1e-7)
+
+
+def test_table_sampling_inverts_the_piecewise_linear_cdf():
+    # coarse table: the drawn angle follows the density p sin(theta) taken linear in theta
+    # between the nodes (the density that the trapezoid cdf integrates exactly); checked
+    # by quadrature of that density up to the drawn angle
+    n = 6
+    p = np.random.default_rng(8).uniform(0.2, 3.0, n)
+    t = O.phase_table(p)
+    theta = np.linspace(0, math.pi, n)
+    f = t["p"] * np.sin(theta)
+
+    def dens(x):
+        return np.interp(x, theta, f)
+
+    total = integrate.quad(dens, 0, math.pi, points=theta[1:-1], limit=200)[0]
+    for u in (0.03, 0.2, 0.41, 0.5, 0.66, 0.9, 0.99):
+        th = math.acos(O.tab_sample(t, u))
+        inner = [x for x in theta[1:-1] if x < th]
+        F = integrate.quad(dens, 0, th, points=inner or None, limit=200)[0]
+        assert F / total == pytest.approx(u, abs=1e-8)
+
+
 def test_hg_table_in_the_tracer_matches_analytic_hg(clean_phase):
     n = 16
     d = synth.cloud_density(n, seed=7).numpy()

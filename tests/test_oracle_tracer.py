@@ -94,6 +94,39 @@ def test_homogeneous_box_transmittance_along_each_axis():
     assert np.all(np.abs(esc - T) < 5 * sd) and np.all(np.abs(ratio - T) < 5 * sd)
 
 
+@pytest.mark.parametrize("vary,along", [(2, 0), (0, 1), (1, 2)])
+def test_transmittance_across_a_profile_reads_the_interpolated_density(vary, along):
+    # density varies along axis `vary` only and rays run along axis `along`, at heights
+    # that fall at known fractions between two voxel centres: the extinction the ray sees
+    # is the linear interpolation of the two voxel values (closed form), constant along the
+    # ray except for the half-voxel fall-off at the two faces it crosses
+    n = 10
+    h = 1.0 / n
+    rng = np.random.default_rng(21)
+    prof = np.where(np.arange(n) % 2 == 0, 0.2, 0.9) * rng.uniform(0.9, 1.1, n)
+    shape = [1, 1, 1]
+    shape[2 - vary] = n  # arrays are [z][y][x]
+    d = np.broadcast_to(prof.reshape(shape), (n, n, n)).astype(np.float32).copy()
+    v = prof.astype(np.float32).astype(np.float64)
+    sigma = 1.3
+    g = O.Grid(d, sigma, [-0.5] * 3, h)
+    other = 3 - vary - along
+    cells = [(2, 0.2), (3, 0.8), (5, 0.35), (6, 0.9), (1, 0.6), (7, 0.1)]
+    R = len(cells)
+    orig = np.zeros((R, 3))
+    orig[:, along] = -0.9
+    orig[:, other] = rng.uniform(-0.5 + h, 0.5 - h, R)
+    orig[:, vary] = [-0.5 + (i + 0.5 + f) * h for i, f in cells]
+    dirs = np.zeros((R, 3))
+    dirs[:, along] = 1.0
+    c = np.array([(1 - f) * v[i] + f * v[i + 1] for i, f in cells])
+    T = np.exp(-sigma * c * (1.0 - h / 4))
+    spp = 20000
+    ratio, esc = O.transmittance(g, orig, dirs, spp=spp, seed=22)
+    sd = np.sqrt(T * (1 - T) / spp)
+    assert np.all(np.abs(esc - T) < 5 * sd) and np.all(np.abs(ratio - T) < 5 * sd)
+
+
 # ---------------------------------------------------------------- furnace and zero cases
 def test_furnace_every_camera_path_returns_one():
     n = 16
