@@ -461,7 +461,7 @@ ds_status ds_cloud_majorant(const ds_cloud *cloud, float *majorant);
  * of record i uses stream id i * 2^20 + s.  Records with an unusable direction
  * get 0.  In DS_LIGHT_DIRECTIONAL mode light_dir is omega_l per record; in
  * DS_LIGHT_ENVIRONMENT mode it is ignored but must still be a valid pointer.
- * 1 <= spp <= 2^20, P < 2^40.  Library-owned workspace: 16 * P * ceil(spp/256) bytes. */
+ * 1 <= spp <= 2^20, P < 2^40.  Library-owned workspace: 16 * P * ceil(spp/64) bytes. */
 ds_status ds_trace_li(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params *params,
                       const float *pos, const float *view_dir, const float *light_dir, int64_t P,
                       int spp, uint64_t seed, double *mean_out, double *var_out);
@@ -483,7 +483,7 @@ typedef struct ds_adaptive {
  * may be NULL), spp_out (device, P int32, may be NULL) the number of paths used (0
  * for records with an unusable direction).  The estimate of a record that used n
  * paths is the one ds_trace_li gives at spp = n, up to summation order.  Synchronises
- * once per batch.  Library-owned workspace: 16 * P * ceil(batch_spp / 256) + 17 * P
+ * once per batch.  Library-owned workspace: 16 * P * ceil(batch_spp / 64) + 17 * P
  * bytes. */
 ds_status ds_trace_li_adaptive(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params *params,
                                const ds_adaptive *adaptive, const float *pos,
