@@ -118,7 +118,8 @@ def test_trace_li_independent_streams(ctx, small_cloud, small):
 
 
 def test_trace_li_spp_split_over_blocks(ctx, small_cloud, small):
-    # spp above one block's 256 paths: partial sums per block, reduced in order
+    # spp above one block's paths (700: eleven blocks of 64, the last part-filled): partial
+    # sums per block, reduced in block order
     prm = ds.TracerParams(0.9, 0.7, 2.0, 0, 0)
     pos, view, light = small.cuda_inputs()
     idx = np.arange(7)
