@@ -482,9 +482,13 @@ typedef struct ds_adaptive {
 /* ds_trace_li with progressive stopping: mean_out and var_out as ds_trace_li (var_out
  * may be NULL), spp_out (device, P int32, may be NULL) the number of paths used (0
  * for records with an unusable direction).  The estimate of a record that used n
- * paths is the one ds_trace_li gives at spp = n, up to summation order.  Synchronises
- * once per batch.  Library-owned workspace: 16 * P * ceil(batch_spp / 64) + 17 * P
- * bytes. */
+ * paths is the one ds_trace_li gives at spp = n, up to summation order.  When batch_spp
+ * is a multiple of 64, a round traces up to k batches at once for the records still
+ * running (k grows as they thin out, at most 64): the rule is applied after each batch in
+ * order and the paths past a record's stopping batch are discarded, so estimates and path
+ * counts are those of one batch per round.  Synchronises once per round.  Library-owned
+ * workspace: 16 * P * ceil(batch_spp / 64) * k + 17 * P bytes, k the largest round (1 if
+ * batch_spp is not a multiple of 64; its partial sums are kept within 256 MiB). */
 ds_status ds_trace_li_adaptive(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_params *params,
                                const ds_adaptive *adaptive, const float *pos,
                                const float *view_dir, const float *light_dir, int64_t P,

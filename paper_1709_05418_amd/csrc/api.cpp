@@ -2092,15 +2092,18 @@ static ds_status adaptive_li(ds_ctx *ctx, const ds_cloud *cloud, const TracerPar
                              const float *light, int64_t P, uint64_t seed, Carve &cv,
                              double *mean, double *var, int32_t *n_out)
 {
-    ds_status st = ensure_ws(ctx, sizeof(double) * 2 * (size_t)P * tracer_blocks(ad->batch_spp));
+    const int ahead = tracer_adaptive_ahead(P, ad->batch_spp, ad->max_spp);
+    ds_status st = ensure_ws(ctx, sizeof(double) * 2 * (size_t)P * tracer_blocks(ad->batch_spp) *
+                                      (size_t)ahead);
     if (st)
         return st;
     uint8_t *active = cv.take<uint8_t>((size_t)P);
     double *sums = cv.take<double>(2 * (size_t)P);
     unsigned long long *left = cv.take<unsigned long long>(1);
     return tracer_li_adaptive(ctx->stream, cloud, tp, pos, view, light, P, ad->batch_spp,
-                              ad->max_spp, ad->rel, ad->z, seed, static_cast<double *>(ctx->ws),
-                              active, sums, left, mean, var, n_out, nullptr);
+                              ad->max_spp, ahead, ad->rel, ad->z, seed,
+                              static_cast<double *>(ctx->ws), active, sums, left, mean, var, n_out,
+                              nullptr);
 }
 
 static size_t adaptive_ws2(int64_t P) { return (size_t)P * (1 + 2 * sizeof(double)) + 4 * 256; }

@@ -334,15 +334,18 @@ ds_status tracer_li(hipStream_t s, const ds_cloud *c, const TracerParams &tp, co
                     double *partial, double *mean, double *var, const uint8_t *mask = nullptr,
                     uint8_t mask_bits = 0);
 // Progressive estimates: batches of `batch` paths per active record until
-// zq * sqrt(var of mean) <= rel * |mean| or max_spp (a multiple of batch) paths.  Workspace:
-// partial (2 * P * tracer_blocks(batch) doubles), active (P bytes), sums (2 P doubles), left
-// (one counter).  Synchronises once per batch; rounds (may be NULL) gets the batch count.
+// zq * sqrt(var of mean) <= rel * |mean| or max_spp (a multiple of batch) paths; a round
+// traces up to `ahead` batches of the records still running (tracer_adaptive_ahead) and
+// checks the rule after each in order.  Workspace: partial (2 * P * tracer_blocks(batch) *
+// ahead doubles), active (P bytes), sums (2 P doubles), left (one counter).  Synchronises
+// once per round; rounds (may be NULL) gets the round count.
 ds_status tracer_li_adaptive(hipStream_t s, const ds_cloud *c, const TracerParams &tp,
                              const float *pos, const float *view, const float *light, int64_t P,
-                             int batch, int max_spp, double rel, double zq, uint64_t seed,
-                             double *partial, uint8_t *active, double *sums,
+                             int batch, int max_spp, int ahead, double rel, double zq,
+                             uint64_t seed, double *partial, uint8_t *active, double *sums,
                              unsigned long long *left, double *mean, double *var, int32_t *n_out,
                              int *rounds);
+int tracer_adaptive_ahead(int64_t P, int batch, int max_spp);
 ds_status tracer_targets(hipStream_t s, const double *li, int64_t N, int64_t stride, float *t);
 ds_status tracer_accumulate(hipStream_t s, int64_t N, const uint8_t *hit, const float *direct,
                             const float *li_net, const uint8_t *flags, const double *li_mc,

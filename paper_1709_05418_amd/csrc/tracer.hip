@@ -476,34 +476,42 @@ __global__ void __launch_bounds__(256) k_adapt_init(const float *view, const flo
         n_out[i] = 0;
 }
 
-__global__ void __launch_bounds__(256) k_adapt_step(const double *partial, int nblk, int64_t P,
-                                                    int n, int max_spp, double rel, double zq,
-                                                    uint8_t *active, double *sums, double *mean,
-                                                    double *var, int32_t *n_out,
-                                                    unsigned long long *left)
+// Batches j = 0 .. kb - 1 of one round, in order: batch j's nb block partials (blocks
+// j nb .. j nb + nb - 1 of the round's kb nb) join the record's running sums, and the rule
+// is checked after each, so a record stops at the same batch as with one batch per round;
+// later batches of a stopped record are discarded.
+__global__ void __launch_bounds__(256) k_adapt_step(const double *partial, int nb, int kb,
+                                                    int64_t P, int n0, int batch, int max_spp,
+                                                    double rel, double zq, uint8_t *active,
+                                                    double *sums, double *mean, double *var,
+                                                    int32_t *n_out, unsigned long long *left)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P || !active[i])
         return;
     double s1 = sums[2 * i], s2 = sums[2 * i + 1];
-    for (int b = 0; b < nblk; ++b) {
-        s1 += partial[2 * (i * nblk + b)];
-        s2 += partial[2 * (i * nblk + b) + 1];
+    const int64_t nblk = (int64_t)nb * kb;
+    for (int j = 0; j < kb; ++j) {
+        for (int b = j * nb; b < (j + 1) * nb; ++b) {
+            s1 += partial[2 * (i * nblk + b)];
+            s2 += partial[2 * (i * nblk + b) + 1];
+        }
+        const int n = n0 + (j + 1) * batch;
+        const double m = s1 / n;
+        const double vm = fmax(0.0, (s2 - n * m * m) / (n - 1)) / n;
+        if (zq * sqrt(vm) <= rel * fabs(m) || n >= max_spp) {
+            active[i] = 0;
+            mean[i] = m;
+            if (var)
+                var[i] = vm;
+            if (n_out)
+                n_out[i] = n;
+            return;
+        }
     }
     sums[2 * i] = s1;
     sums[2 * i + 1] = s2;
-    const double m = s1 / n;
-    const double vm = fmax(0.0, (s2 - n * m * m) / (n - 1)) / n;
-    if (zq * sqrt(vm) <= rel * fabs(m) || n >= max_spp) {
-        active[i] = 0;
-        mean[i] = m;
-        if (var)
-            var[i] = vm;
-        if (n_out)
-            n_out[i] = n;
-    } else {
-        atomicAdd(left, 1ull);
-    }
+    atomicAdd(left, 1ull);
 }
 
 // Record configurations (Sec. 5.1): direction d uniform on the sphere, origin
@@ -968,37 +976,66 @@ ds_status tracer_li(hipStream_t s, const ds_cloud *c, const TracerParams &tp, co
     return reduce_records(s, partial, P, sp.nblk, spp, mean, var);
 }
 
+// Batches a round of the progressive estimate traces: one while the records still running
+// fill the GPU (kAheadThreads threads), more as they thin out, up to `ahead`.  Tracing
+// several batches at once keeps every block partial and its order (the batch is a whole
+// number of blocks), so estimates and path counts equal those of one batch per round.
+constexpr int64_t kAheadThreads = 1ll << 21;
+
 ds_status tracer_li_adaptive(hipStream_t s, const ds_cloud *c, const TracerParams &tp,
                              const float *pos, const float *view, const float *light, int64_t P,
-                             int batch, int max_spp, double rel, double zq, uint64_t seed,
-                             double *partial, uint8_t *active, double *sums,
+                             int batch, int max_spp, int ahead, double rel, double zq,
+                             uint64_t seed, double *partial, uint8_t *active, double *sums,
                              unsigned long long *left, double *mean, double *var, int32_t *n_out,
                              int *rounds)
 {
-    const Split sp = split(batch);
+    const Split sp1 = split(batch);
+    const bool whole = batch % kPaths == 0;
     const unsigned g256 = (unsigned)((P + 255) / 256);
     DS_TRY_MEDIUM(s, c);
     k_adapt_init<<<g256, 256, 0, s>>>(view, light, P, active, sums, mean, var, n_out);
     DS_HIP(hipGetLastError());
     int r = 0;
-    for (int n = batch; n <= max_spp; n += batch) {
+    int64_t live = P;
+    for (int n = 0; n < max_spp;) {
+        int kb = 1;
+        if (whole && ahead > 1) {
+            const int64_t want = (kAheadThreads + live * batch - 1) / (live * batch);
+            kb = (int)std::max<int64_t>(
+                1, std::min<int64_t>(want, std::min<int64_t>(ahead, (max_spp - n) / batch)));
+        }
         ++r;
-        launch_trace_li(s, c, tp, pos, view, light, P, n - batch, batch, sp, seed, active, 1,
-                        partial);
+        launch_trace_li(s, c, tp, pos, view, light, P, n, kb * batch,
+                        kb == 1 ? sp1 : split(kb * batch), seed, active, 1, partial);
         DS_HIP(hipGetLastError());
         unsigned long long h = 0;
         DS_HIP(hipMemsetAsync(left, 0, sizeof(*left), s));
-        k_adapt_step<<<g256, 256, 0, s>>>(partial, sp.nblk, P, n, max_spp, rel, zq, active, sums,
-                                          mean, var, n_out, left);
+        k_adapt_step<<<g256, 256, 0, s>>>(partial, sp1.nblk, kb, P, n, batch, max_spp, rel, zq,
+                                          active, sums, mean, var, n_out, left);
         DS_HIP(hipGetLastError());
         DS_HIP(hipMemcpyAsync(&h, left, sizeof(h), hipMemcpyDeviceToHost, s));
         DS_HIP(hipStreamSynchronize(s));
+        n += kb * batch;
         if (h == 0)
             break;
+        live = (int64_t)h;
     }
     if (rounds)
         *rounds = r;
     return DS_OK;
+}
+
+// Batches ahead a progressive estimate of P records may trace in one round: 1 unless a
+// batch is a whole number of blocks; else up to 64 (and the cap), within 256 MiB of
+// partial sums.
+int tracer_adaptive_ahead(int64_t P, int batch, int max_spp)
+{
+    if (batch % kPaths != 0 || P <= 0)
+        return 1;
+    const int64_t per = 16 * P * (batch / kPaths);
+    const int64_t k = std::min<int64_t>(std::min<int64_t>(64, max_spp / batch),
+                                        (256ll << 20) / per);
+    return (int)std::max<int64_t>(1, k);
 }
 
 ds_status tracer_records(hipStream_t s, const ds_cloud *c, int64_t N, uint64_t seed, float *pos,

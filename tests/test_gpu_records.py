@@ -54,9 +54,11 @@ def test_ls_records_match_oracle(ctx, small_cloud, small, mode):
     assert m.sum() > mi.cpu().numpy().sum()
 
 
-@pytest.mark.parametrize("include_direct", [0, 1])
-def test_adaptive_matches_oracle(ctx, small_cloud, small, include_direct):
-    batch, top, rel, zq, seed = 32, 1024, 0.3, 1.96, 5
+@pytest.mark.parametrize("include_direct,batch", [(0, 32), (1, 32), (0, 64), (1, 128)])
+def test_adaptive_matches_oracle(ctx, small_cloud, small, include_direct, batch):
+    # batches of 32 paths: one batch per round; 64 and 128 (whole blocks): rounds of several
+    # batches for the records still running, the rule applied after each batch in order
+    top, rel, zq, seed = 1024, 0.3, 1.96, 5
     prm = ds.TracerParams(0.95, 0.85, 1.0, 0, 0, include_direct)
     ad = ds.Adaptive(batch, top, rel, zq)
     pos, view, light = small.cuda_inputs()
