@@ -549,7 +549,8 @@ ds_status ds_make_records(ds_ctx *ctx, const ds_cloud *cloud, const ds_tracer_pa
 
 /* ds_make_records with each target estimated progressively (ds_trace_li_adaptive's
  * rule, same derived key), as Sec. 5.1 does; spp_out (device, N int32, may be NULL)
- * receives the paths each record used.  Synchronises once per batch. */
+ * receives the paths each record used.  Synchronises once per round (rounds and
+ * workspace as ds_trace_li_adaptive). */
 ds_status ds_make_records_adaptive(ds_ctx *ctx, const ds_cloud *cloud,
                                    const ds_tracer_params *params, const ds_adaptive *adaptive,
                                    int64_t N, uint64_t seed, int64_t stride, float *z,
