@@ -131,3 +131,20 @@ def test_render_calls_reject_ls_params(ctx, small_cloud):
     with pytest.raises(ds.DSError):
         ds.ds_trace_li_adaptive(ctx.h, small_cloud.h, ds.TracerParams(), ds.Adaptive(32, 100),
                                 o, d, d, 1)
+
+
+def test_adaptive_rounds_do_not_change_results(ctx, small_cloud):
+    # batches of 64 paths are whole blocks, so a round may trace several batches ahead: 16
+    # at once for 101 records, fewer while 8192 records still run.  Record i keeps its
+    # streams (i * 2^20 + s) either way, so the first 101 records of the large set must give
+    # bitwise the estimates and path counts of the 101 alone.
+    prm = ds.TracerParams(0.95, 0.85, 1.0, 0, 0)
+    ad = ds.Adaptive(64, 1024, 0.2, 1.96)
+    pos, view, light, _ = ds.ds_sample_records(ctx.h, small_cloud.h, 8192, 31)
+    big = ds.ds_trace_li_adaptive(ctx.h, small_cloud.h, prm, ad, pos, view, light, 9)
+    few = ds.ds_trace_li_adaptive(ctx.h, small_cloud.h, prm, ad, pos[:101].contiguous(),
+                                  view[:101].contiguous(), light[:101].contiguous(), 9)
+    for a, b in zip(big, few):
+        assert torch.equal(a[:101], b)
+    n = big[2].cpu().numpy()
+    assert len(set(n.tolist())) > 3 and (n < 1024).any()
